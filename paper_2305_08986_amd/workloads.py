@@ -1,0 +1,305 @@
+"""Seeded synthetic inputs for the generalized-Stokes hot path.
+
+This module only *draws and lays out input data*: the structured box meshes,
+the fine-level vertex displacement of the ALE map, the per-quadrature-point
+coefficient fields (mass coefficient and effective viscosity) and the
+right-hand sides.  It holds none of the method's arithmetic (no basis
+functions, no Jacobians, no operators) and is shared, unchanged, by the CPU
+oracle tests and the HIP path.
+
+The workloads stand in for the paper's channel/beam benchmarks (Sec. 5,
+Tables 1 and 3), whose meshes are not available:
+
+* ``C0`` 2D unit square 16x16, affine, viscosity 1 with an inclusion of
+  viscosity 1e4 on [0.25,0.5]^2 (cell-aligned), mass coefficient 1e2.
+* ``C1`` 2D channel [0,2.5]x[0,0.41], 256x64 cells, bilinear ALE map from a
+  sum of four random sine modes (amplitude 0.02), viscosity 1e-3 with a strip
+  [0.6,1.0]x[0.19,0.21] of viscosity 1e3 (contrast 1e6).
+* ``C2`` 3D unit cube 64^3, trilinear warp (amplitude 0.05), log-uniform
+  viscosity in [1e-3,1e3] per block of 8^3 fine cells.
+* ``C3`` as C2 at 128^3 cells.
+* ``C4`` 96^3 cells, a 20-step sequence: every step adds a displacement
+  increment of amplitude 0.0025 and redraws the viscosity field.
+
+The effective viscosity models the splitting of Sec. 3.1.1 (fluid viscosity
+in the fluid, gamma*tau*mu_s in the solid); the mass coefficient is the
+implicit BDF term rho/(gamma*tau) of Sec. 3.1.
+
+Conventions (shared by every consumer):
+
+* cells, Q2 velocity nodes, Q1 pressure nodes and mesh vertices are numbered
+  lexicographically with x fastest;
+* velocity vectors are component-major ``[dim][n_vel_nodes]``;
+* per-cell quadrature points are the tensor 3-point Gauss points, numbered
+  lexicographically (x fastest); coefficient arrays are ``[n_cells][3**dim]``;
+* the vertex displacement is ``[dim][n_vertices]`` on the finest level and
+  defines a multilinear (Q1) ALE map on every level by injection at that
+  level's vertices;
+* ``dirichlet_faces`` bit f marks face f in (x-, x+, y-, y+, z-, z+) as a
+  homogeneous no-slip wall; the default leaves x+ as a do-nothing outflow.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+BASE_SEED = 230508986
+
+# Reference positions of the 3 Gauss points per direction on [0,1]; used
+# only to decide where a coefficient sample sits inside its cell.
+_SAMPLE_PTS = np.array([0.5 - math.sqrt(15.0) / 10.0, 0.5, 0.5 + math.sqrt(15.0) / 10.0])
+
+
+def default_dirichlet_faces(dim: int) -> int:
+    """All faces except x+ (bit 1)."""
+    return ((1 << (2 * dim)) - 1) & ~0b10
+
+
+@dataclasses.dataclass
+class MeshDesc:
+    dim: int
+    n_fine: tuple
+    extent: tuple
+    n_coarse: tuple
+    dirichlet_faces: int
+
+    @property
+    def n_levels(self) -> int:
+        r = [self.n_fine[i] // self.n_coarse[i] for i in range(self.dim)]
+        lv = int(round(math.log2(r[0])))
+        return lv + 1
+
+    def cells(self, level: int) -> tuple:
+        s = 1 << level
+        return tuple(self.n_coarse[i] * s for i in range(self.dim))
+
+    def n_cells(self, level: int) -> int:
+        return int(np.prod(self.cells(level)))
+
+    def vel_nodes(self, level: int) -> tuple:
+        return tuple(2 * c + 1 for c in self.cells(level))
+
+    def p_nodes(self, level: int) -> tuple:
+        return tuple(c + 1 for c in self.cells(level))
+
+    def n_vel(self, level: int) -> int:
+        return self.dim * int(np.prod(self.vel_nodes(level)))
+
+    def n_p(self, level: int) -> int:
+        return int(np.prod(self.p_nodes(level)))
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    mesh: MeshDesc
+    disp: np.ndarray                  # [dim][n_vert_fine] vertex displacement
+    c_mass: List[np.ndarray]          # per level [n_cells][Q]
+    eta: List[np.ndarray]             # per level [n_cells][Q]
+    g_u: np.ndarray                   # [n_vel_fine], Dirichlet entries zero
+    g_p: np.ndarray                   # [n_p_fine]
+    info: dict
+
+
+CONFIGS = {
+    "C0": dict(dim=2, n=(16, 16), extent=(1.0, 1.0), n_coarse=(4, 4), amp=0.0,
+               eta="inclusion", desc="2D unit square 16x16 affine, inclusion contrast 1e4"),
+    "C1": dict(dim=2, n=(256, 64), extent=(2.5, 0.41), n_coarse=(8, 2), amp=0.02,
+               eta="strip", desc="2D channel 256x64 warped, strip contrast 1e6"),
+    "C2": dict(dim=3, n=(64, 64, 64), extent=(1.0, 1.0, 1.0), n_coarse=(4, 4, 4), amp=0.05,
+               eta="loguniform", desc="3D box 64^3 warped, log-uniform eta per 8^3 block"),
+    "C3": dict(dim=3, n=(128, 128, 128), extent=(1.0, 1.0, 1.0), n_coarse=(4, 4, 4), amp=0.05,
+               eta="loguniform", desc="3D box 128^3 warped, log-uniform eta per 8^3 block"),
+    "C4": dict(dim=3, n=(96, 96, 96), extent=(1.0, 1.0, 1.0), n_coarse=(3, 3, 3), amp=0.0025,
+               eta="loguniform", steps=20, desc="3D box 96^3, 20 ALE steps"),
+    # small cases used by the parity tests (same laws as C2 at reduced size)
+    "T3_4": dict(dim=3, n=(4, 4, 4), extent=(1.0, 1.0, 1.0), n_coarse=(2, 2, 2), amp=0.05,
+                 eta="loguniform", block=2, desc="3D 4^3 warped"),
+    "T3_8": dict(dim=3, n=(8, 8, 8), extent=(1.0, 1.0, 1.0), n_coarse=(2, 2, 2), amp=0.05,
+                 eta="loguniform", block=2, desc="3D 8^3 warped"),
+    "T3_16": dict(dim=3, n=(16, 16, 16), extent=(1.0, 1.0, 1.0), n_coarse=(4, 4, 4), amp=0.05,
+                  eta="loguniform", block=4, desc="3D 16^3 warped"),
+    "T3_R": dict(dim=3, n=(12, 6, 10), extent=(1.2, 0.6, 1.0), n_coarse=(6, 3, 5), amp=0.04,
+                 eta="loguniform", block=3, desc="3D 12x6x10 warped, odd coarse counts"),
+    "T2_R": dict(dim=2, n=(22, 14), extent=(1.1, 0.7), n_coarse=(11, 7), amp=0.03,
+                 eta="loguniform", block=3, desc="2D 22x14 warped, odd coarse counts"),
+}
+
+CONFIG_INDEX = {"C0": 0, "C1": 1, "C2": 2, "C3": 3, "C4": 4,
+                "T3_4": 100, "T3_8": 101, "T3_16": 102, "T3_R": 103, "T2_R": 104}
+
+
+# ---------------------------------------------------------------- geometry of the grids
+def vertex_coords(mesh: MeshDesc, level: int) -> np.ndarray:
+    """Reference coordinates of the vertices of ``level`` as [dim][n_vert]."""
+    pn = mesh.p_nodes(level)
+    axes = [np.linspace(0.0, mesh.extent[i], pn[i]) for i in range(mesh.dim)]
+    grids = np.meshgrid(*axes, indexing="ij")           # axis 0 = x
+    # lexicographic with x fastest: flatten in Fortran order over (x,y,z)
+    return np.stack([g.ravel(order="F") for g in grids])
+
+
+def velocity_node_coords(mesh: MeshDesc, level: int) -> np.ndarray:
+    nn = mesh.vel_nodes(level)
+    axes = [np.linspace(0.0, mesh.extent[i], nn[i]) for i in range(mesh.dim)]
+    grids = np.meshgrid(*axes, indexing="ij")
+    return np.stack([g.ravel(order="F") for g in grids])
+
+
+def dirichlet_node_mask(mesh: MeshDesc, level: int) -> np.ndarray:
+    """Boolean [n_vel_nodes]: node lies on a wall face (all components fixed)."""
+    nn = mesh.vel_nodes(level)
+    idx = np.meshgrid(*[np.arange(n) for n in nn], indexing="ij")
+    idx = [g.ravel(order="F") for g in idx]
+    m = np.zeros(idx[0].shape, dtype=bool)
+    for d in range(mesh.dim):
+        if mesh.dirichlet_faces & (1 << (2 * d)):
+            m |= idx[d] == 0
+        if mesh.dirichlet_faces & (1 << (2 * d + 1)):
+            m |= idx[d] == nn[d] - 1
+    return m
+
+
+def qpoint_ref_coords(mesh: MeshDesc, level: int) -> np.ndarray:
+    """Reference coordinates of the coefficient samples, [n_cells][Q][dim]."""
+    cells = mesh.cells(level)
+    h = [mesh.extent[i] / cells[i] for i in range(mesh.dim)]
+    cidx = np.meshgrid(*[np.arange(c) for c in cells], indexing="ij")
+    cidx = [g.ravel(order="F") for g in cidx]            # per cell, x fastest
+    q = np.meshgrid(*([np.arange(3)] * mesh.dim), indexing="ij")
+    q = [g.ravel(order="F") for g in q]                  # per qpoint, x fastest
+    out = np.empty((len(cidx[0]), 3 ** mesh.dim, mesh.dim))
+    for d in range(mesh.dim):
+        out[:, :, d] = (cidx[d][:, None] + _SAMPLE_PTS[q[d]][None, :]) * h[d]
+    return out
+
+
+# ---------------------------------------------------------------- random laws
+def _sine_modes(rng: np.random.Generator, dim: int):
+    k = rng.integers(1, 3, size=(4, dim))
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=4)
+    e = rng.normal(size=(4, dim))
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    return k, phi, e
+
+
+def _sine_displacement(X: np.ndarray, extent, amp: float, modes) -> np.ndarray:
+    """d(X) = A*b(Xt)*(1/4)*sum_m e_m sin(2 pi k_m.Xt + phi_m); b vanishes on the boundary."""
+    k, phi, e = modes
+    dim = X.shape[0]
+    Xt = X / np.asarray(extent, dtype=float)[:, None]
+    b = np.ones(X.shape[1])
+    for d in range(dim):
+        b *= 4.0 * Xt[d] * (1.0 - Xt[d])
+    out = np.zeros_like(X)
+    for m in range(4):
+        s = np.sin(2.0 * math.pi * (k[m] @ Xt) + phi[m])
+        out += np.outer(e[m], s)
+    return amp * b[None, :] * 0.25 * out
+
+
+def _eta_law(cfg: dict, mesh: MeshDesc, rng: np.random.Generator, level_coords):
+    kind = cfg["eta"]
+    if kind == "inclusion":
+        out = []
+        for X in level_coords:
+            inside = np.all((X >= 0.25) & (X <= 0.5), axis=-1)
+            out.append(np.where(inside, 1e4, 1.0))
+        return out, None
+    if kind == "strip":
+        out = []
+        for X in level_coords:
+            inside = (X[..., 0] >= 0.6) & (X[..., 0] <= 1.0) & (X[..., 1] >= 0.19) & (X[..., 1] <= 0.21)
+            out.append(np.where(inside, 1e3, 1e-3))
+        return out, None
+    if kind == "loguniform":
+        blk = cfg.get("block", 8)
+        nb = [max(1, -(-mesh.n_fine[i] // blk)) for i in range(mesh.dim)]
+        logeta = rng.uniform(-3.0, 3.0, size=tuple(nb[::-1]))   # indexed [z][y][x]
+        hb = [mesh.extent[i] / mesh.n_fine[i] * blk for i in range(mesh.dim)]
+        out = []
+        for X in level_coords:
+            bi = [np.minimum((X[..., d] / hb[d]).astype(np.int64), nb[d] - 1) for d in range(mesh.dim)]
+            idx = tuple(bi[::-1])
+            out.append(10.0 ** logeta[idx])
+        return out, logeta
+    raise ValueError(kind)
+
+
+def make_mesh(name: str, dirichlet_faces: Optional[int] = None) -> MeshDesc:
+    cfg = CONFIGS[name]
+    dim = cfg["dim"]
+    return MeshDesc(dim=dim, n_fine=tuple(cfg["n"]), extent=tuple(cfg["extent"]),
+                    n_coarse=tuple(cfg["n_coarse"]),
+                    dirichlet_faces=default_dirichlet_faces(dim) if dirichlet_faces is None
+                    else dirichlet_faces)
+
+
+def make_workload(name: str, step: Optional[int] = None, seed: int = BASE_SEED,
+                  dirichlet_faces: Optional[int] = None,
+                  prev_disp: Optional[np.ndarray] = None,
+                  levels: Optional[Sequence[int]] = None) -> Workload:
+    """Draw the inputs of workload ``name``.
+
+    Draw order (numpy PCG64 seeded with ``[seed, config]`` or
+    ``[seed, config, step]``): displacement modes, viscosity blocks, g_u
+    (component-major, U[-1,1]), g_p (U[-1,1]); Dirichlet velocity entries are
+    then zeroed.  For the time-step sequence the displacement of ``step`` is
+    ``prev_disp`` plus a fresh increment.
+    ``levels`` restricts which levels get coefficient arrays (all by default).
+    """
+    cfg = CONFIGS[name]
+    mesh = make_mesh(name, dirichlet_faces)
+    key = [seed, CONFIG_INDEX[name]] + ([] if step is None else [step])
+    rng = np.random.default_rng(key)
+    dim = mesh.dim
+    J = mesh.n_levels - 1
+    Xv = vertex_coords(mesh, J)
+    modes = _sine_modes(rng, dim)
+    if cfg["amp"] > 0:
+        disp = _sine_displacement(Xv, mesh.extent, cfg["amp"], modes)
+    else:
+        disp = np.zeros_like(Xv)
+    if prev_disp is not None:
+        disp = disp + prev_disp
+    lvls = list(range(J + 1)) if levels is None else list(levels)
+    coords = [qpoint_ref_coords(mesh, l) for l in lvls]
+    eta_l, logeta = _eta_law(cfg, mesh, rng, coords)
+    eta = [None] * (J + 1)
+    cm = [None] * (J + 1)
+    for l, e in zip(lvls, eta_l):
+        eta[l] = np.ascontiguousarray(e, dtype=np.float64)
+        cm[l] = np.full_like(eta[l], 1e2)
+    del coords
+    g_u = rng.uniform(-1.0, 1.0, size=mesh.n_vel(J))
+    g_p = rng.uniform(-1.0, 1.0, size=mesh.n_p(J))
+    mask = dirichlet_node_mask(mesh, J)
+    g_u.reshape(dim, -1)[:, mask] = 0.0
+    info = dict(config=name, desc=cfg["desc"], seed=seed, step=step,
+                n_cells=mesh.n_cells(J), n_vel=mesh.n_vel(J), n_p=mesh.n_p(J),
+                levels=mesh.n_levels)
+    if logeta is not None:
+        info["eta_contrast"] = float(10.0 ** (logeta.max() - logeta.min()))
+    return Workload(name=name, mesh=mesh, disp=np.ascontiguousarray(disp), c_mass=cm, eta=eta,
+                    g_u=g_u, g_p=g_p, info=info)
+
+
+def inject_displacement(mesh: MeshDesc, disp_fine: np.ndarray, level: int) -> np.ndarray:
+    """Vertex displacement of ``level``: the fine values at the coarse vertices."""
+    J = mesh.n_levels - 1
+    s = 1 << (J - level)
+    pf = mesh.p_nodes(J)
+    arr = disp_fine.reshape((mesh.dim,) + tuple(pf[::-1]))
+    if mesh.dim == 2:
+        sub = arr[:, ::s, ::s]
+    else:
+        sub = arr[:, ::s, ::s, ::s]
+    return np.ascontiguousarray(sub.reshape(mesh.dim, -1))
+
+
+def random_vector(n: int, seed_key) -> np.ndarray:
+    """A seeded U[-1,1] test vector (for parity tests)."""
+    return np.random.default_rng(seed_key).uniform(-1.0, 1.0, size=n)

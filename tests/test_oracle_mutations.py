@@ -1,0 +1,70 @@
+"""Planted mistakes in the oracle (on the CPU) must be caught by its pins.
+
+Each case monkeypatches one plausible slip into ``oracle.fem`` and re-runs the
+pins that should catch it; the test passes only if at least one pin fails.
+"""
+import numpy as np
+import pytest
+
+from oracle import fem
+import tests.test_oracle_pins as pins
+
+_orig_elem = fem.element_matrices
+_orig_geo = fem.geometry_factors
+
+
+def _elem_cross_transposed(J, c_mass, eta, ref):
+    A, B = _orig_elem(J, c_mass, eta, ref)
+    dim = ref.dim
+    nl = ref.phi.shape[1]
+    nc = J.shape[0]
+    Jinv, wdet = _orig_geo(J, ref)
+    G = np.einsum("cqbx,qib->cqix", Jinv, ref.dphi)
+    we = wdet * eta
+    good = np.einsum("cq,cqib,cqja->caibj", we, G, G)
+    bad = np.einsum("cq,cqia,cqjb->caibj", we, G, G)
+    return (A.reshape(nc, dim, nl, dim, nl) - good + bad).reshape(A.shape), B
+
+
+def _elem_dropped_mass(J, c_mass, eta, ref):
+    return _orig_elem(J, 0 * c_mass, eta, ref)
+
+
+def _geo_untransposed(J, ref):
+    Jinv, wdet = _orig_geo(J, ref)
+    return np.swapaxes(Jinv, -1, -2), wdet
+
+
+def _elem_sign_flip_B(J, c_mass, eta, ref):
+    A, B = _orig_elem(J, c_mass, eta, ref)
+    return A, -B
+
+
+CASES = {
+    "cross term with swapped component indices": ("element_matrices", _elem_cross_transposed),
+    "dropped mass term": ("element_matrices", _elem_dropped_mass),
+    "J^{-1} used untransposed": ("geometry_factors", _geo_untransposed),
+    "sign of the divergence": ("element_matrices", _elem_sign_flip_B),
+}
+
+PIN_SETS = [
+    pins.test_element_matrices_2d_tensor_closed_form,
+    pins.test_element_matrices_3d_tensor_closed_form,
+    lambda: pins.test_rigid_motions_in_null_space(3),
+    pins.test_quadratic_fields_energy_exact_on_warped_box,
+    pins.test_mass_and_volume_on_warped_box,
+    pins.test_divergence_of_linear_field,
+]
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_planted_mistake_is_caught(case, monkeypatch):
+    attr, fn = CASES[case]
+    monkeypatch.setattr(fem, attr, fn)
+    caught = 0
+    for pin in PIN_SETS:
+        try:
+            pin()
+        except AssertionError:
+            caught += 1
+    assert caught >= 1, case
