@@ -1,0 +1,199 @@
+/*
+ * fsi.h -- C ABI of the MI355X generalized-Stokes hot path (libfsi.so).
+ *
+ * One stage of the semi-implicit ALE fluid-structure scheme (Algorithm 1,
+ * Sec. 3.1.1) solves the generalized Stokes system of Sec. 4,
+ *
+ *     [ A  B^T ] [u]   [g_u]        a(u,v) = (c_m u, v) + (2 eta eps(u), eps(v)),
+ *     [ B  0   ] [p] = [g_p],       b(v,q) = (div v, q),
+ *
+ * (predictor mode: symmetric A; mass coefficient c_m = rho/(gamma*tau) from the
+ * BDF stencil of Sec. 3.1, effective viscosity eta from the stress splitting of
+ * Sec. 3.1.1), discretised by Taylor-Hood Q2-Q1 elements on the ALE-mapped mesh
+ * (Sec. 3.2, Sec. 5: p1 = 2, p2 = 1) and solved by FGMRES preconditioned with
+ * the monolithic block V-cycle of Sec. 4 (smoother K_j with A-hat^{-1} =
+ * Cheb(A, diag A, k_A) and S-hat^{-1} = ChebMINRES(n_S, k_S)), defaults from
+ * Table 4 (predictor column).
+ *
+ * Conventions
+ *  - Meshes are structured boxes of n_fine cells per direction, obtained from
+ *    n_coarse by uniform refinement (the level hierarchy of Sec. 4); level 0 is
+ *    the coarsest, level L-1 the finest.
+ *  - Cells, Q2 velocity nodes ((2n+1)^dim), Q1 pressure nodes ((n+1)^dim) and
+ *    quadrature points (3 Gauss points per direction, 3^dim per cell) are
+ *    numbered lexicographically with x fastest.
+ *  - Velocity vectors are component-major: u[c * n_vel_nodes + node].
+ *  - Every vector/array argument is DEVICE memory owned by the caller unless
+ *    stated otherwise; the library never frees it.  Calls are asynchronous and
+ *    ordered on the context's stream unless stated otherwise.
+ *  - Dirichlet (no-slip) faces: bit f of dirichlet_faces marks face f in the
+ *    order (x-, x+, y-, y+, z-, z+).  Constrained velocity rows of A act as the
+ *    identity (v_c = u_c), constrained columns of A and B are zero, constrained
+ *    rows of B^T are zero.
+ *  - Not thread safe per context; one context per stream.
+ */
+#ifndef FSI_H
+#define FSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fsi_ctx fsi_ctx;
+typedef int fsi_status;
+
+#define FSI_OK                  0
+#define FSI_NOT_CONVERGED       1   /* solve stopped at max_iter; result still written */
+#define FSI_ERR_ARG            -1   /* bad pointer, size, level or parameter */
+#define FSI_ERR_STATE          -2   /* call needs set_ calls or fsi_setup first */
+#define FSI_ERR_HIP            -3   /* a HIP runtime call failed */
+#define FSI_ERR_OOM            -4   /* device allocation failed */
+#define FSI_ERR_INVERTED_CELL  -5   /* det J <= 0 at some quadrature point */
+#define FSI_ERR_BREAKDOWN      -6   /* Krylov breakdown or singular coarse matrix */
+#define FSI_ERR_NONFINITE      -7   /* NaN/Inf in an input or a residual */
+
+#define FSI_PREC_FP64   0   /* V-cycle in FP64 */
+#define FSI_PREC_MIXED  1   /* V-cycle velocity work in FP32, Schur pressure block FP64 */
+
+typedef struct {
+    int dim;                 /* 2 or 3 */
+    int n_fine[3];           /* cells per direction on the finest level */
+    double extent[3];        /* reference box [0,extent_0] x ... */
+    int n_coarse[3];         /* cells per direction on level 0; n_fine/n_coarse = 2^(L-1) in every direction */
+    uint32_t dirichlet_faces;
+} fsi_mesh_desc;
+
+typedef struct {
+    int64_t n_cells, n_vel_nodes, n_vel, n_p, n_qp, n_vert;
+    int cells[3], vel_nodes[3], p_nodes[3];
+} fsi_sizes;
+
+/* Multigrid parameters (Sec. 4, Table 4).  fsi_default_mg_params fills the
+ * predictor column: k_A=4, m=2, n=1, k_S=1, n_S=1.  The Chebyshev interval of
+ * D^{-1}A on each level is [cheb_upper*lam/cheb_ratio, cheb_upper*lam] with lam
+ * the largest Ritz value of n_eig Lanczos steps on D^{-1/2} A D^{-1/2}.
+ * Only k_S = 1 and n_S = 1 are implemented. */
+typedef struct {
+    int k_A;
+    int m;
+    int n_cycles;
+    int k_S;
+    int n_S;
+    double cheb_upper;
+    double cheb_ratio;
+    int n_eig;
+    int precision;           /* FSI_PREC_FP64 or FSI_PREC_MIXED */
+    int use_graph;           /* capture the V-cycle in a HIP graph */
+} fsi_mg_params;
+
+typedef struct {
+    double lambda_max;       /* Lanczos estimate of lambda_max(D^{-1}A) */
+    double cheb_lo, cheb_hi; /* Chebyshev interval */
+    double diagA_norm2;      /* ||diag(A)||_2 (all velocity dofs) */
+    double diagS_norm2;      /* ||diag(B diag(A)^{-1} B^T)||_2 */
+    int64_t coarse_n;        /* size of the dense coarse system (level 0 only) */
+} fsi_level_info;
+
+typedef struct {
+    double rtol;             /* relative true residual ||g - M x||_2 / ||g||_2 */
+    int max_iter;
+    int restart;
+} fsi_solve_opts;
+
+typedef struct {
+    int iters;
+    double final_rel_res;    /* true FP64 residual, recomputed at exit */
+    double time_ms;          /* wall time of the solve on the stream */
+    int n_hist;              /* entries written to res_history */
+    double* res_history;     /* HOST buffer of >= max_iter+1 doubles, may be NULL */
+} fsi_solve_info;
+
+/* Create a context for the box hierarchy described by *m.  hip_stream is a
+ * hipStream_t (NULL: the library creates and owns one).  Allocates the level
+ * structure (maps, colours) but no geometry.  Errors: FSI_ERR_ARG for an
+ * invalid description (dim, sizes, non power-of-two ratio), FSI_ERR_OOM. */
+fsi_status fsi_create(fsi_ctx** out, const fsi_mesh_desc* m, void* hip_stream);
+void fsi_destroy(fsi_ctx* ctx);
+const char* fsi_last_error(const fsi_ctx* ctx);
+void fsi_default_mg_params(fsi_mg_params* p);
+
+fsi_status fsi_get_num_levels(const fsi_ctx* ctx, int* n_levels);
+fsi_status fsi_get_sizes(const fsi_ctx* ctx, int level, fsi_sizes* s);
+
+/* Geometry (Sec. 3.2, mapped spaces): J[cell][q][a][b] = d x_a / d xi_b of the
+ * ALE map at Gauss point q of the reference cell [0,1]^dim (so an undeformed
+ * cell of size h has J = diag(h)).  FP64 device array of n_cells*Q*dim*dim.
+ * The library stores det(J) w_q J^{-1} per quadrature point (FP64 and FP32).
+ * New geometry invalidates the level's coefficients (set them again).
+ * Errors: FSI_ERR_INVERTED_CELL if det J <= 0 anywhere (synchronises). */
+fsi_status fsi_set_jacobians(fsi_ctx* ctx, int level, const double* J);
+
+/* Convenience: vertex displacement d[c][vertex] (FP64, dim*n_vert of the finest
+ * level) of the multilinear ALE map x = X + d(X); every level receives the
+ * values at its own vertices (injection) and its Jacobians are computed on the
+ * device.  Same errors as fsi_set_jacobians. */
+fsi_status fsi_set_displacement(fsi_ctx* ctx, const double* disp);
+
+/* Coefficients per quadrature point, FP64 [n_cells][Q] each: c_mass is the
+ * implicit BDF mass coefficient rho/(gamma*tau) (Sec. 3.1) and eta the
+ * effective viscosity of the stress splitting (Sec. 3.1.1); the form is
+ * (c_m u, v) + (2 eta eps(u), eps(v)).  Requires the level's geometry.
+ * Errors: FSI_ERR_STATE without geometry, FSI_ERR_NONFINITE if an input is not
+ * finite (synchronises). */
+fsi_status fsi_set_coefficients(fsi_ctx* ctx, int level, const double* c_mass, const double* eta);
+
+fsi_status fsi_set_mg_params(fsi_ctx* ctx, const fsi_mg_params* p);
+
+/* Setup of the preconditioner on every level: diag(A_j), diag(B_j diag(A_j)^{-1}
+ * B_j^T) (Sec. 4), Lanczos bounds, Chebyshev coefficients, the dense inverse of
+ * the coarsest block matrix M_0, FP32 copies and (if enabled) the V-cycle graph.
+ * Synchronises.  Errors: FSI_ERR_STATE if a level lacks geometry or
+ * coefficients, FSI_ERR_BREAKDOWN for a singular coarse matrix. */
+fsi_status fsi_setup(fsi_ctx* ctx);
+fsi_status fsi_get_level_info(const fsi_ctx* ctx, int level, fsi_level_info* info);
+
+/* Matrix-free operators on one level (Sec. 4 block system), FP64:
+ *   apply_A:      v = A u
+ *   apply_B:      q = B u
+ *   apply_BT:     v = B^T p
+ *   apply_stokes: v = A u + B^T p, q = B u
+ * u, v: [n_vel]; p, q: [n_p]; outputs are overwritten; inputs and outputs must
+ * not alias.  Require geometry and coefficients of that level (B and B^T only
+ * geometry).  Errors: FSI_ERR_ARG, FSI_ERR_STATE. */
+fsi_status fsi_apply_A(fsi_ctx* ctx, int level, const double* u, double* v);
+fsi_status fsi_apply_B(fsi_ctx* ctx, int level, const double* u, double* q);
+fsi_status fsi_apply_BT(fsi_ctx* ctx, int level, const double* p, double* v);
+fsi_status fsi_apply_stokes(fsi_ctx* ctx, int level, const double* u, const double* p,
+                            double* v, double* q);
+/* FP32 twins of the same operators, with the FP32 copy of geometry and coefficients. */
+fsi_status fsi_apply_A_f32(fsi_ctx* ctx, int level, const float* u, float* v);
+fsi_status fsi_apply_B_f32(fsi_ctx* ctx, int level, const float* u, float* q);
+fsi_status fsi_apply_BT_f32(fsi_ctx* ctx, int level, const float* p, float* v);
+fsi_status fsi_apply_stokes_f32(fsi_ctx* ctx, int level, const float* u, const float* p,
+                                float* v, float* q);
+
+/* One application of the preconditioner: n V-cycles (Sec. 4) on the finest
+ * level from a zero initial guess, in the configured precision.  FP64 in and
+ * out; casts are internal.  Requires fsi_setup. */
+fsi_status fsi_vcycle(fsi_ctx* ctx, const double* r_u, const double* r_p, double* z_u, double* z_p);
+
+/* Solve the finest-level system with right-preconditioned FGMRES (Sec. 5,
+ * linear solver settings).  u, p hold the initial guess on entry and the
+ * solution on exit.  The stopping test is ||g - M x||_2/||g||_2 <= rtol on the
+ * combined (u,p) vector, confirmed on the true FP64 residual.  Synchronises.
+ * Returns FSI_NOT_CONVERGED (results still written) if max_iter is reached. */
+fsi_status fsi_solve(fsi_ctx* ctx, const double* g_u, const double* g_p, double* u, double* p,
+                     const fsi_solve_opts* opts, fsi_solve_info* info);
+
+/* Autotuner: times the cell-kernel launch variants (cells per workgroup and
+ * scatter strategy) on every level and precision and keeps the fastest.
+ * Synchronises; results are reported through fsi_get_tuning. */
+fsi_status fsi_autotune(fsi_ctx* ctx);
+fsi_status fsi_get_tuning(const fsi_ctx* ctx, int level, int precision, int* variant, double* best_us);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSI_H */

@@ -1,0 +1,1091 @@
+// Host runtime and C ABI of the generalized-Stokes hot path: level hierarchy
+// (Sec. 4: uniformly refined boxes), geometry/coefficient setup, the
+// preconditioner setup, the monolithic block V-cycle with the smoother K_j of
+// Sec. 4, FGMRES (Sec. 5, linear solver settings), HIP-graph capture of the
+// V-cycle and the launch-variant autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fsi_common.h"
+
+struct fsi_ctx {
+    fsi::Context c;
+};
+
+namespace fsi {
+
+fsi_status hip_fail(Context* ctx, hipError_t e, const char* what, const char* file, int line) {
+    char buf[512];
+    snprintf(buf, sizeof buf, "HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e), what, file, line);
+    if (ctx) ctx->err = buf;
+    return e == hipErrorOutOfMemory ? FSI_ERR_OOM : FSI_ERR_HIP;
+}
+fsi_status fail(Context* ctx, fsi_status st, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+template <typename T>
+static fsi_status dalloc(Context* ctx, T** p, int64_t n) {
+    *p = nullptr;
+    if (n <= 0) n = 1;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)n);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_fail(ctx, e, "hipMalloc", __FILE__, __LINE__);
+    }
+    ctx->allocations.push_back((void*)*p);
+    return FSI_OK;
+}
+
+#define TRY(expr)                          \
+    do {                                   \
+        fsi_status st_ = (expr);           \
+        if (st_ != FSI_OK) return st_;     \
+    } while (0)
+
+static int ilog2_exact(int r) {
+    int l = 0;
+    while ((1 << l) < r) ++l;
+    return (1 << l) == r ? l : -1;
+}
+
+// ---------------------------------------------------------------- level construction
+static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3], const fsi_mesh_desc& m) {
+    L.dim = dim;
+    L.Q = dim == 3 ? 27 : 9;
+    L.nc = 1;
+    L.nvn = 1;
+    L.np = 1;
+    for (int d = 0; d < 3; ++d) {
+        L.cells[d] = d < dim ? cells[d] : 1;
+        L.vnodes[d] = d < dim ? 2 * cells[d] + 1 : 1;
+        L.pnodes[d] = d < dim ? cells[d] + 1 : 1;
+        L.nc *= L.cells[d];
+        L.nvn *= L.vnodes[d];
+        L.np *= L.pnodes[d];
+    }
+    L.nv = dim * L.nvn;
+    L.nvert = L.np;
+    L.ncolors = 1 << dim;
+    const int NLOC = dim == 3 ? 27 : 9, NPL = dim == 3 ? 8 : 4;
+    // wall mask of the velocity nodes
+    L.h_dir_node.assign((size_t)L.nvn, 0);
+    std::vector<int> dirn;
+    for (int64_t n = 0; n < L.nvn; ++n) {
+        int64_t r = n;
+        bool w = false;
+        for (int d = 0; d < dim; ++d) {
+            const int i = (int)(r % L.vnodes[d]);
+            r /= L.vnodes[d];
+            if ((m.dirichlet_faces >> (2 * d)) & 1u) w |= (i == 0);
+            if ((m.dirichlet_faces >> (2 * d + 1)) & 1u) w |= (i == L.vnodes[d] - 1);
+        }
+        L.h_dir_node[n] = w ? 1 : 0;
+        if (w) dirn.push_back((int)n);
+    }
+    L.n_dir = (int64_t)dirn.size();
+    // colour ordering: colour = parity bits of the cell index; stable lexicographic inside
+    std::vector<int> col2lex((size_t)L.nc), lex2col((size_t)L.nc);
+    std::vector<int64_t> count(9, 0);
+    for (int64_t c = 0; c < L.nc; ++c) {
+        int64_t r = c;
+        int col = 0;
+        for (int d = 0; d < dim; ++d) {
+            col |= (int)((r % L.cells[d]) & 1) << d;
+            r /= L.cells[d];
+        }
+        count[col]++;
+    }
+    L.color_off[0] = 0;
+    for (int c = 0; c < L.ncolors; ++c) L.color_off[c + 1] = L.color_off[c] + count[c];
+    std::vector<int64_t> pos(L.color_off, L.color_off + 8);
+    for (int64_t c = 0; c < L.nc; ++c) {
+        int64_t r = c;
+        int col = 0;
+        for (int d = 0; d < dim; ++d) {
+            col |= (int)((r % L.cells[d]) & 1) << d;
+            r /= L.cells[d];
+        }
+        const int64_t k = pos[col]++;
+        col2lex[k] = (int)c;
+        lex2col[c] = (int)k;
+    }
+    std::vector<int> vmap((size_t)L.nc * NLOC), pmap((size_t)L.nc * NPL);
+    std::vector<uint32_t> dmask((size_t)L.nc);
+    for (int64_t k = 0; k < L.nc; ++k) {
+        int64_t r = col2lex[k];
+        int ci[3] = {0, 0, 0};
+        for (int d = 0; d < dim; ++d) {
+            ci[d] = (int)(r % L.cells[d]);
+            r /= L.cells[d];
+        }
+        uint32_t dm = 0;
+        for (int n = 0; n < NLOC; ++n) {
+            const int li[3] = {n % 3, (n / 3) % 3, n / 9};
+            int64_t node = 0, st = 1;
+            for (int d = 0; d < dim; ++d) {
+                node += (int64_t)(2 * ci[d] + li[d]) * st;
+                st *= L.vnodes[d];
+            }
+            vmap[k * NLOC + n] = (int)node;
+            if (L.h_dir_node[node]) dm |= 1u << n;
+        }
+        dmask[k] = dm;
+        for (int n = 0; n < NPL; ++n) {
+            const int li[3] = {n & 1, (n >> 1) & 1, (n >> 2) & 1};
+            int64_t node = 0, st = 1;
+            for (int d = 0; d < dim; ++d) {
+                node += (int64_t)(ci[d] + li[d]) * st;
+                st *= L.pnodes[d];
+            }
+            pmap[k * NPL + n] = (int)node;
+        }
+    }
+    TRY(dalloc(ctx, &L.d_col2lex, L.nc));
+    TRY(dalloc(ctx, &L.d_lex2col, L.nc));
+    TRY(dalloc(ctx, &L.d_vmap, L.nc * NLOC));
+    TRY(dalloc(ctx, &L.d_pmap, L.nc * NPL));
+    TRY(dalloc(ctx, &L.d_dmask, L.nc));
+    TRY(dalloc(ctx, &L.d_wall, L.nvn));
+    TRY(dalloc(ctx, &L.d_dir_nodes, std::max<int64_t>(1, L.n_dir)));
+    FSI_HIP_TRY(hipMemcpy(L.d_col2lex, col2lex.data(), sizeof(int) * L.nc, hipMemcpyHostToDevice));
+    FSI_HIP_TRY(hipMemcpy(L.d_lex2col, lex2col.data(), sizeof(int) * L.nc, hipMemcpyHostToDevice));
+    FSI_HIP_TRY(hipMemcpy(L.d_vmap, vmap.data(), sizeof(int) * vmap.size(), hipMemcpyHostToDevice));
+    FSI_HIP_TRY(hipMemcpy(L.d_pmap, pmap.data(), sizeof(int) * pmap.size(), hipMemcpyHostToDevice));
+    FSI_HIP_TRY(hipMemcpy(L.d_dmask, dmask.data(), sizeof(uint32_t) * dmask.size(), hipMemcpyHostToDevice));
+    FSI_HIP_TRY(hipMemcpy(L.d_wall, L.h_dir_node.data(), (size_t)L.nvn, hipMemcpyHostToDevice));
+    if (L.n_dir > 0)
+        FSI_HIP_TRY(hipMemcpy(L.d_dir_nodes, dirn.data(), sizeof(int) * dirn.size(), hipMemcpyHostToDevice));
+    // geometry and coefficient storage
+    const int64_t P = L.plane();
+    TRY(dalloc(ctx, &L.d_K64, (int64_t)dim * dim * P));
+    TRY(dalloc(ctx, &L.d_cw64, P));
+    TRY(dalloc(ctx, &L.d_cv64, 2 * P));
+    TRY(dalloc(ctx, &L.d_K32, (int64_t)dim * dim * P));
+    TRY(dalloc(ctx, &L.d_cv32, 2 * P));
+    TRY(dalloc(ctx, &L.d_dAinv64, L.nv));
+    TRY(dalloc(ctx, &L.d_dAinv32, L.nv));
+    TRY(dalloc(ctx, &L.d_dSinv, L.np));
+    return FSI_OK;
+}
+
+template <typename T> static std::vector<LevelWork<T>>& works(Context* c);
+template <> std::vector<LevelWork<double>>& works<double>(Context* c) { return c->w64; }
+template <> std::vector<LevelWork<float>>& works<float>(Context* c) { return c->w32; }
+template <typename T> static const T* Kp(const Level& L);
+template <> const double* Kp<double>(const Level& L) { return L.d_K64; }
+template <> const float* Kp<float>(const Level& L) { return L.d_K32; }
+template <typename T> static const T* CVp(const Level& L);
+template <> const double* CVp<double>(const Level& L) { return L.d_cv64; }
+template <> const float* CVp<float>(const Level& L) { return L.d_cv32; }
+template <typename T> static const T* DAp(const Level& L);
+template <> const double* DAp<double>(const Level& L) { return L.d_dAinv64; }
+template <> const float* DAp<float>(const Level& L) { return L.d_dAinv32; }
+template <typename T> static constexpr int prec_index();
+template <> constexpr int prec_index<double>() { return 0; }
+template <> constexpr int prec_index<float>() { return 1; }
+
+template <typename T>
+static fsi_status alloc_work(Context* ctx) {
+    auto& W = works<T>(ctx);
+    if (!W.empty()) return FSI_OK;
+    W.resize(ctx->nlev);
+    for (int j = 0; j < ctx->nlev; ++j) {
+        const Level& L = ctx->lv[j];
+        LevelWork<T>& w = W[j];
+        TRY(dalloc(ctx, &w.f_u, L.nv));
+        TRY(dalloc(ctx, &w.x_u, L.nv));
+        TRY(dalloc(ctx, &w.r_u, L.nv));
+        TRY(dalloc(ctx, &w.w_u, L.nv));
+        TRY(dalloc(ctx, &w.v_u, L.nv));
+        TRY(dalloc(ctx, &w.cd_u, L.nv));
+        TRY(dalloc(ctx, &w.cax_u, L.nv));
+        TRY(dalloc(ctx, &w.tu, L.nv));
+        TRY(dalloc(ctx, &w.f_p, L.np));
+        TRY(dalloc(ctx, &w.x_p, L.np));
+        TRY(dalloc(ctx, &w.r_p, L.np));
+        TRY(dalloc(ctx, &w.t_p, L.np));
+        TRY(dalloc(ctx, &w.z_p, L.np));
+        TRY(dalloc(ctx, &w.dots, 2));
+        TRY(dalloc(ctx, &w.partials, 2 * kReduceBlocks));
+    }
+    return FSI_OK;
+}
+
+static int variant_of(const Context* ctx, int prec, int level) {
+    const auto& v = ctx->tune_variant[prec];
+    return level < (int)v.size() ? v[level] : 0;
+}
+
+// ---------------------------------------------------------------- operators
+template <typename T>
+static void op_apply(Context* ctx, int j, int mode, const T* u, const double* p, T* v, double* q, hipStream_t s) {
+    const Level& L = ctx->lv[j];
+    if (mode & (OP_A | OP_BT)) launch_fill<T>(v, T(0), L.nv, s);
+    if (mode & OP_B) launch_fill<double>(q, 0.0, L.np, s);
+    launch_cell_all<T>(L, mode, variant_of(ctx, prec_index<T>(), j), Kp<T>(L), CVp<T>(L), u, p, v, q, s);
+    if (mode & OP_A) launch_dirichlet_copy<T>(L, u, v, s);
+}
+
+// Chebyshev smoother Cheb(A, diag A, k_A) from a zero initial guess: k_A - 1 applications of A
+template <typename T>
+static void cheb(Context* ctx, int j, const T* r, T* x, hipStream_t s) {
+    const Level& L = ctx->lv[j];
+    LevelWork<T>& W = works<T>(ctx)[j];
+    const double theta = 0.5 * (L.hi + L.lo), delta = 0.5 * (L.hi - L.lo);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    launch_cheb_init<T>(DAp<T>(L), r, x, W.cd_u, 1.0 / theta, L.nv, s);
+    for (int i = 1; i < ctx->prm.k_A; ++i) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        op_apply<T>(ctx, j, OP_A, x, nullptr, W.cax_u, nullptr, s);
+        launch_cheb_step<T>(DAp<T>(L), r, W.cax_u, x, W.cd_u, rn * rho, 2.0 * rn / delta, L.nv, s);
+        rho = rn;
+    }
+}
+
+// one step of the block smoother K_j (Sec. 4): w = Ah^{-1} r_u; z = D_S^{-1}(B w - r_p);
+// v = Ah^{-1} B^T z; y = B v; beta = <y,z>/<y,D_S^{-1}y> (one MINRES step, k_S = 1);
+// increment (w - beta v, beta z).  Ah^{-1} is linear, so Ah^{-1} B^T (beta z) = beta v.
+template <typename T>
+static void smoother(Context* ctx, int j, const T* r_u, const double* r_p, T* x_u, double* x_p, bool first,
+                     hipStream_t s) {
+    const Level& L = ctx->lv[j];
+    LevelWork<T>& W = works<T>(ctx)[j];
+    cheb<T>(ctx, j, r_u, W.w_u, s);
+    op_apply<T>(ctx, j, OP_B, W.w_u, nullptr, nullptr, W.t_p, s);
+    launch_schur_z(L.d_dSinv, W.t_p, r_p, W.z_p, L.np, s);
+    op_apply<T>(ctx, j, OP_BT, nullptr, W.z_p, W.tu, nullptr, s);
+    cheb<T>(ctx, j, W.tu, W.v_u, s);
+    op_apply<T>(ctx, j, OP_B, W.v_u, nullptr, nullptr, W.t_p, s);
+    launch_schur_dots(W.t_p, W.z_p, L.d_dSinv, W.partials, W.dots, L.np, s);
+    launch_smoother_update<T>(W.w_u, W.v_u, W.z_p, W.dots, x_u, x_p, L.nv, L.np, first, s);
+}
+
+// r = f - M x on level j (into W.r_u, W.r_p)
+template <typename T>
+static void residual(Context* ctx, int j, hipStream_t s) {
+    const Level& L = ctx->lv[j];
+    LevelWork<T>& W = works<T>(ctx)[j];
+    op_apply<T>(ctx, j, OP_A | OP_BT | OP_B, W.x_u, W.x_p, W.r_u, W.r_p, s);
+    launch_sub<T>(W.f_u, W.r_u, W.r_u, L.nv, s);
+    launch_sub<double>(W.f_p, W.r_p, W.r_p, L.np, s);
+}
+
+// V-cycle on level j from a zero initial guess: W[j].f -> W[j].x
+template <typename T>
+static void vcycle_level(Context* ctx, int j, hipStream_t s) {
+    LevelWork<T>& W = works<T>(ctx)[j];
+    if (j == 0) {
+        launch_coarse_apply<T>(ctx->coarse, ctx->lv[0], W.f_u, W.f_p, W.x_u, W.x_p, s);
+        return;
+    }
+    const int m = ctx->prm.m;
+    for (int st = 0; st < m; ++st) {
+        if (st == 0) {
+            smoother<T>(ctx, j, W.f_u, W.f_p, W.x_u, W.x_p, true, s);
+        } else {
+            residual<T>(ctx, j, s);
+            smoother<T>(ctx, j, W.r_u, W.r_p, W.x_u, W.x_p, false, s);
+        }
+    }
+    if (m == 0) {
+        launch_fill<T>(W.x_u, T(0), ctx->lv[j].nv, s);
+        launch_fill<double>(W.x_p, 0.0, ctx->lv[j].np, s);
+    }
+    residual<T>(ctx, j, s);
+    LevelWork<T>& C = works<T>(ctx)[j - 1];
+    launch_restrict<T>(ctx->lv[j], ctx->lv[j - 1], W.r_u, W.r_p, C.f_u, C.f_p, s);
+    vcycle_level<T>(ctx, j - 1, s);
+    launch_prolongate_add<T>(ctx->lv[j], ctx->lv[j - 1], C.x_u, C.x_p, W.x_u, W.x_p, s);
+    for (int st = 0; st < m; ++st) {
+        residual<T>(ctx, j, s);
+        smoother<T>(ctx, j, W.r_u, W.r_p, W.x_u, W.x_p, false, s);
+    }
+}
+
+// one preconditioner application in precision T: ctx->vc_in -> ctx->vc_out (FP64 buffers)
+template <typename T>
+static void vcycle_body(Context* ctx, hipStream_t s) {
+    const int J = ctx->nlev - 1;
+    const Level& L = ctx->lv[J];
+    LevelWork<T>& W = works<T>(ctx)[J];
+    launch_cast<T, double>(W.f_u, ctx->vc_in_u, L.nv, s);
+    launch_cast<double, double>(W.f_p, ctx->vc_in_p, L.np, s);
+    vcycle_level<T>(ctx, J, s);
+    launch_cast<double, T>(ctx->vc_out_u, W.x_u, L.nv, s);
+    launch_cast<double, double>(ctx->vc_out_p, W.x_p, L.np, s);
+}
+
+static fsi_status run_vcycle(Context* ctx, hipStream_t s) {
+    const int pi = ctx->prm.precision == FSI_PREC_MIXED ? 1 : 0;
+    if (ctx->prm.use_graph && ctx->graph_valid[pi]) {
+        FSI_HIP_TRY(hipGraphLaunch(ctx->graph[pi], s));
+    } else if (pi == 1) {
+        vcycle_body<float>(ctx, s);
+    } else {
+        vcycle_body<double>(ctx, s);
+    }
+    return FSI_OK;
+}
+
+static fsi_status capture_graphs(Context* ctx) {
+    for (int pi = 0; pi < 2; ++pi) {
+        if (ctx->graph_valid[pi]) {
+            hipGraphExecDestroy(ctx->graph[pi]);
+            ctx->graph_valid[pi] = false;
+        }
+    }
+    if (!ctx->prm.use_graph) return FSI_OK;
+    const int pi = ctx->prm.precision == FSI_PREC_MIXED ? 1 : 0;
+    hipStream_t cs;
+    FSI_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g;
+    FSI_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    if (pi == 1) vcycle_body<float>(ctx, cs);
+    else vcycle_body<double>(ctx, cs);
+    FSI_HIP_TRY(hipStreamEndCapture(cs, &g));
+    FSI_HIP_TRY(hipGraphInstantiate(&ctx->graph[pi], g, nullptr, nullptr, 0));
+    hipGraphDestroy(g);
+    hipStreamDestroy(cs);
+    ctx->graph_valid[pi] = true;
+    return FSI_OK;
+}
+
+// ---------------------------------------------------------------- setup pieces
+static fsi_status sync_flag(Context* ctx, fsi_status st, const char* msg) {
+    FSI_HIP_TRY(hipMemcpyAsync(ctx->h_flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    FSI_HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (*ctx->h_flag != 0) return fail(ctx, st, msg);
+    return FSI_OK;
+}
+
+static fsi_status read_scalars(Context* ctx, const double* d, int n, double* h) {
+    FSI_HIP_TRY(hipMemcpyAsync(ctx->h_dbl, d, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+    FSI_HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < n; ++i) h[i] = ctx->h_dbl[i];
+    return FSI_OK;
+}
+
+static fsi_status dot64(Context* ctx, const double* x, const double* y, int64_t n, double* out) {
+    launch_dot<double>(x, y, n, ctx->d_scratch, ctx->d_scratch + 2 * kReduceBlocks, ctx->stream);
+    return read_scalars(ctx, ctx->d_scratch + 2 * kReduceBlocks, 1, out);
+}
+
+// largest eigenvalue of the symmetric tridiagonal (alpha, beta) by Sturm bisection
+static double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+    const int n = (int)a.size();
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < n - 1 ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    auto count_below = [&](double x) {   // number of eigenvalues < x
+        int cnt = 0;
+        double d = 1.0;
+        for (int i = 0; i < n; ++i) {
+            const double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+            d = (a[i] - x) - (i > 0 ? bb / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0) ++cnt;
+        }
+        return cnt;
+    };
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (count_below(mid) >= n) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+static fsi_status lanczos(Context* ctx, int j) {
+    Level& L = ctx->lv[j];
+    hipStream_t s = ctx->stream;
+    LevelWork<double>& W = ctx->w64[j];
+    // reuse work vectors: sA = sqrt(dAinv) in W.w_u, v in W.v_u, vprev in W.cd_u, w in W.cax_u, tmp in W.tu
+    double *sA = W.w_u, *v = W.v_u, *vp = W.cd_u, *w = W.cax_u, *tmp = W.tu;
+    launch_vsqrt(L.d_dAinv64, sA, L.nv, s);
+    launch_lanczos_start(L, v, s);
+    launch_fill<double>(vp, 0.0, L.nv, s);
+    double nrm;
+    TRY(dot64(ctx, v, v, L.nv, &nrm));
+    nrm = std::sqrt(nrm);
+    if (!(nrm > 0)) return fail(ctx, FSI_ERR_BREAKDOWN, "Lanczos start vector vanishes");
+    launch_scale_host(1.0 / nrm, v, v, L.nv, s);
+    std::vector<double> al, be;
+    double beta = 0.0;
+    for (int it = 0; it < ctx->prm.n_eig; ++it) {
+        launch_mul(sA, v, tmp, L.nv, s);
+        op_apply<double>(ctx, j, OP_A, tmp, nullptr, w, nullptr, s);
+        launch_mul(sA, w, w, L.nv, s);
+        double alpha;
+        TRY(dot64(ctx, w, v, L.nv, &alpha));
+        launch_axpy_host(-alpha, v, w, L.nv, s);
+        if (it > 0) launch_axpy_host(-beta, vp, w, L.nv, s);
+        al.push_back(alpha);
+        double bn;
+        TRY(dot64(ctx, w, w, L.nv, &bn));
+        bn = std::sqrt(bn);
+        if (it == ctx->prm.n_eig - 1 || !(bn > 1e-300)) break;
+        be.push_back(bn);
+        std::swap(vp, v);            // vprev <- v
+        launch_scale_host(1.0 / bn, w, v, L.nv, s);   // v <- w / beta
+        beta = bn;
+    }
+    L.lam = tridiag_max_eig(al, be);
+    L.hi = ctx->prm.cheb_upper * L.lam;
+    L.lo = L.hi / ctx->prm.cheb_ratio;
+    return FSI_OK;
+}
+
+static fsi_status setup_coarse(Context* ctx) {
+    Level& L = ctx->lv[0];
+    Coarse& C = ctx->coarse;
+    hipStream_t s = ctx->stream;
+    std::vector<int> vrow((size_t)L.nv, -1), uidx;
+    int64_t nf = 0;
+    for (int a = 0; a < L.dim; ++a)
+        for (int64_t n = 0; n < L.nvn; ++n)
+            if (!L.h_dir_node[n]) {
+                vrow[a * L.nvn + n] = (int)nf++;
+                uidx.push_back((int)(a * L.nvn + n));
+            }
+    const int64_t n = nf + L.np;
+    if (C.n != n) {
+        C.n = n;
+        C.nfree_u = nf;
+        TRY(dalloc(ctx, &C.d_uidx, std::max<int64_t>(1, nf)));
+        TRY(dalloc(ctx, &C.d_inv64, n * n));
+        TRY(dalloc(ctx, &C.d_inv32, n * n));
+        TRY(dalloc(ctx, &C.d_xin64, n));
+        TRY(dalloc(ctx, &C.d_xout64, n));
+        TRY(dalloc(ctx, &C.d_xin32, n));
+        TRY(dalloc(ctx, &C.d_xout32, n));
+    }
+    if (nf > 0)
+        FSI_HIP_TRY(hipMemcpyAsync(C.d_uidx, uidx.data(), sizeof(int) * nf, hipMemcpyHostToDevice, s));
+    int* d_vrow;
+    int* d_piv;
+    double* d_col;
+    FSI_HIP_TRY(hipMalloc((void**)&d_vrow, sizeof(int) * L.nv));
+    FSI_HIP_TRY(hipMalloc((void**)&d_piv, sizeof(int) * n));
+    FSI_HIP_TRY(hipMalloc((void**)&d_col, sizeof(double) * n));
+    FSI_HIP_TRY(hipMemcpyAsync(d_vrow, vrow.data(), sizeof(int) * L.nv, hipMemcpyHostToDevice, s));
+    launch_fill<double>(C.d_inv64, 0.0, n * n, s);
+    launch_coarse_assemble_impl(L, L.d_K64, L.d_cv64, d_vrow, nf, C.d_inv64, n, s);
+    launch_fill<int>(ctx->d_flag, 0, 1, s);
+    launch_gj(C.d_inv64, n, d_piv, d_col, ctx->d_flag, s);
+    launch_cast<float, double>(C.d_inv32, C.d_inv64, n * n, s);
+    fsi_status st = sync_flag(ctx, FSI_ERR_BREAKDOWN, "singular coarse-level matrix");
+    hipFree(d_vrow);
+    hipFree(d_piv);
+    hipFree(d_col);
+    return st;
+}
+
+static fsi_status check_level(Context* ctx, int level) {
+    if (level < 0 || level >= ctx->nlev) return fail(ctx, FSI_ERR_ARG, "level out of range");
+    return FSI_OK;
+}
+
+static fsi_status invalidate(Context* ctx) {
+    ctx->setup_done = false;
+    for (int pi = 0; pi < 2; ++pi)
+        if (ctx->graph_valid[pi]) {
+            hipGraphExecDestroy(ctx->graph[pi]);
+            ctx->graph_valid[pi] = false;
+        }
+    return FSI_OK;
+}
+
+// ---------------------------------------------------------------- FGMRES
+static fsi_status ensure_krylov(Context* ctx, int restart) {
+    Krylov& K = ctx->kr;
+    const Level& L = ctx->lv[ctx->nlev - 1];
+    const int64_t n = L.nv + L.np;
+    if (K.restart >= restart && K.n == n) return FSI_OK;
+    // previous buffers stay in ctx->allocations until destroy
+    K.restart = restart;
+    K.n = n;
+    TRY(dalloc(ctx, &K.V, (int64_t)(restart + 1) * n));
+    TRY(dalloc(ctx, &K.Z, (int64_t)restart * n));
+    TRY(dalloc(ctx, &K.w, n));
+    TRY(dalloc(ctx, &K.r, n));
+    TRY(dalloc(ctx, &K.x, n));
+    TRY(dalloc(ctx, &K.g, n));
+    TRY(dalloc(ctx, &K.h, 2 * (restart + 2)));
+    TRY(dalloc(ctx, &K.partials, std::max<int64_t>(256 * (int64_t)(restart + 2), 2 * kReduceBlocks)));
+    if (K.h_host) hipHostFree(K.h_host);
+    FSI_HIP_TRY(hipHostMalloc((void**)&K.h_host, sizeof(double) * 3 * (restart + 2)));
+    return FSI_OK;
+}
+
+// y = M x on the finest level for combined vectors [u | p]
+static void stokes_combined(Context* ctx, const double* x, double* y, hipStream_t s) {
+    const int J = ctx->nlev - 1;
+    const Level& L = ctx->lv[J];
+    op_apply<double>(ctx, J, OP_A | OP_BT | OP_B, x, x + L.nv, y, y + L.nv, s);
+}
+
+static fsi_status precond_combined(Context* ctx, const double* r, double* z, hipStream_t s) {
+    const Level& L = ctx->lv[ctx->nlev - 1];
+    FSI_HIP_TRY(hipMemcpyAsync(ctx->vc_in_u, r, sizeof(double) * L.nv, hipMemcpyDeviceToDevice, s));
+    FSI_HIP_TRY(hipMemcpyAsync(ctx->vc_in_p, r + L.nv, sizeof(double) * L.np, hipMemcpyDeviceToDevice, s));
+    TRY(run_vcycle(ctx, s));
+    for (int c = 1; c < ctx->prm.n_cycles; ++c) {
+        // z += V(r - M z)
+        FSI_HIP_TRY(hipMemcpyAsync(z, ctx->vc_out_u, sizeof(double) * L.nv, hipMemcpyDeviceToDevice, s));
+        FSI_HIP_TRY(hipMemcpyAsync(z + L.nv, ctx->vc_out_p, sizeof(double) * L.np, hipMemcpyDeviceToDevice, s));
+        stokes_combined(ctx, z, ctx->vc_tmp, s);
+        launch_sub_into(r, ctx->vc_tmp, ctx->vc_in_u, L.nv, s);
+        launch_sub_into(r + L.nv, ctx->vc_tmp + L.nv, ctx->vc_in_p, L.np, s);
+        TRY(run_vcycle(ctx, s));
+        launch_axpy_host(1.0, z, ctx->vc_out_u, L.nv, s);
+        launch_axpy_host(1.0, z + L.nv, ctx->vc_out_p, L.np, s);
+    }
+    FSI_HIP_TRY(hipMemcpyAsync(z, ctx->vc_out_u, sizeof(double) * L.nv, hipMemcpyDeviceToDevice, s));
+    FSI_HIP_TRY(hipMemcpyAsync(z + L.nv, ctx->vc_out_p, sizeof(double) * L.np, hipMemcpyDeviceToDevice, s));
+    return FSI_OK;
+}
+
+}  // namespace fsi
+
+using namespace fsi;
+
+// ================================================================ C ABI
+extern "C" {
+
+void fsi_default_mg_params(fsi_mg_params* p) {
+    if (!p) return;
+    p->k_A = 4;
+    p->m = 2;
+    p->n_cycles = 1;
+    p->k_S = 1;
+    p->n_S = 1;
+    p->cheb_upper = 1.2;
+    p->cheb_ratio = 20.0;
+    p->n_eig = 12;
+    p->precision = FSI_PREC_FP64;
+    p->use_graph = 1;
+}
+
+fsi_status fsi_create(fsi_ctx** out, const fsi_mesh_desc* m, void* hip_stream) {
+    if (!out || !m) return FSI_ERR_ARG;
+    *out = nullptr;
+    if (m->dim != 2 && m->dim != 3) return FSI_ERR_ARG;
+    int lev = -1;
+    for (int d = 0; d < m->dim; ++d) {
+        if (m->n_coarse[d] < 1 || m->n_fine[d] < 1 || m->n_fine[d] % m->n_coarse[d] != 0) return FSI_ERR_ARG;
+        if (!(m->extent[d] > 0)) return FSI_ERR_ARG;
+        const int l = ilog2_exact(m->n_fine[d] / m->n_coarse[d]);
+        if (l < 0 || (lev >= 0 && l != lev)) return FSI_ERR_ARG;
+        lev = l;
+    }
+    int64_t nvn = 1;
+    for (int d = 0; d < m->dim; ++d) nvn *= 2 * (int64_t)m->n_fine[d] + 1;
+    if (nvn * m->dim >= (int64_t)1 << 31) return FSI_ERR_ARG;   // 32-bit node indices
+    fsi_ctx* h = new fsi_ctx();
+    Context* ctx = &h->c;
+    ctx->mesh = *m;
+    ctx->nlev = lev + 1;
+    fsi_default_mg_params(&ctx->prm);
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&ctx->stream) != hipSuccess) {
+            delete h;
+            return FSI_ERR_HIP;
+        }
+        ctx->own_stream = true;
+    }
+    ctx->lv.resize(ctx->nlev);
+    fsi_status st = FSI_OK;
+    for (int j = 0; j < ctx->nlev && st == FSI_OK; ++j) {
+        int cells[3] = {1, 1, 1};
+        for (int d = 0; d < m->dim; ++d) cells[d] = m->n_coarse[d] << j;
+        st = build_level(ctx, ctx->lv[j], m->dim, cells, *m);
+    }
+    if (st == FSI_OK) st = dalloc(ctx, &ctx->d_scratch, 4 * kReduceBlocks + 64);
+    if (st == FSI_OK) st = dalloc(ctx, &ctx->d_flag, 4);
+    if (st == FSI_OK && hipHostMalloc((void**)&ctx->h_flag, sizeof(int) * 4) != hipSuccess) st = FSI_ERR_HIP;
+    if (st == FSI_OK && hipHostMalloc((void**)&ctx->h_dbl, sizeof(double) * 64) != hipSuccess) st = FSI_ERR_HIP;
+    for (int pi = 0; pi < 2; ++pi) {
+        ctx->tune_variant[pi].assign(ctx->nlev, 0);
+        ctx->tune_us[pi].assign(ctx->nlev, 0.0);
+    }
+    if (st != FSI_OK) {
+        fsi_destroy(h);
+        return st;
+    }
+    *out = h;
+    return FSI_OK;
+}
+
+void fsi_destroy(fsi_ctx* h) {
+    if (!h) return;
+    Context* ctx = &h->c;
+    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    for (int pi = 0; pi < 2; ++pi)
+        if (ctx->graph_valid[pi]) hipGraphExecDestroy(ctx->graph[pi]);
+    for (void* p : ctx->allocations) hipFree(p);
+    if (ctx->h_flag) hipHostFree(ctx->h_flag);
+    if (ctx->h_dbl) hipHostFree(ctx->h_dbl);
+    if (ctx->kr.h_host) hipHostFree(ctx->kr.h_host);
+    if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+    delete h;
+}
+
+const char* fsi_last_error(const fsi_ctx* h) { return h ? h->c.err.c_str() : "null context"; }
+
+fsi_status fsi_get_num_levels(const fsi_ctx* h, int* n) {
+    if (!h || !n) return FSI_ERR_ARG;
+    *n = h->c.nlev;
+    return FSI_OK;
+}
+
+fsi_status fsi_get_sizes(const fsi_ctx* h, int level, fsi_sizes* s) {
+    if (!h || !s) return FSI_ERR_ARG;
+    if (level < 0 || level >= h->c.nlev) return FSI_ERR_ARG;
+    const Level& L = h->c.lv[level];
+    s->n_cells = L.nc;
+    s->n_vel_nodes = L.nvn;
+    s->n_vel = L.nv;
+    s->n_p = L.np;
+    s->n_qp = L.Q;
+    s->n_vert = L.nvert;
+    for (int d = 0; d < 3; ++d) {
+        s->cells[d] = L.cells[d];
+        s->vel_nodes[d] = L.vnodes[d];
+        s->p_nodes[d] = L.pnodes[d];
+    }
+    return FSI_OK;
+}
+
+fsi_status fsi_set_jacobians(fsi_ctx* h, int level, const double* J) {
+    if (!h || !J) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    TRY(check_level(ctx, level));
+    Level& L = ctx->lv[level];
+    invalidate(ctx);
+    launch_fill<int>(ctx->d_flag, 0, 1, ctx->stream);
+    launch_geometry(L, J, L.d_K64, L.d_cw64, L.d_K32, ctx->d_flag, ctx->stream);
+    L.geo_set = false;
+    L.coef_set = false;
+    TRY(sync_flag(ctx, FSI_ERR_INVERTED_CELL, "det J <= 0 (or not finite) at a quadrature point"));
+    L.geo_set = true;
+    return FSI_OK;
+}
+
+fsi_status fsi_set_displacement(fsi_ctx* h, const double* disp) {
+    if (!h || !disp) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    invalidate(ctx);
+    const int J = ctx->nlev - 1;
+    const Level& F = ctx->lv[J];
+    launch_fill<int>(ctx->d_flag, 0, 1, ctx->stream);
+    for (int j = 0; j <= J; ++j) {
+        Level& L = ctx->lv[j];
+        double hh[3];
+        for (int d = 0; d < L.dim; ++d) hh[d] = ctx->mesh.extent[d] / L.cells[d];
+        launch_geometry_from_disp_h(L, disp, 1 << (J - j), F.pnodes, hh, L.d_K64, L.d_cw64, L.d_K32, ctx->d_flag,
+                                    ctx->stream);
+        L.geo_set = false;
+        L.coef_set = false;
+    }
+    TRY(sync_flag(ctx, FSI_ERR_INVERTED_CELL, "det J <= 0 (or not finite) at a quadrature point"));
+    for (int j = 0; j <= J; ++j) ctx->lv[j].geo_set = true;
+    return FSI_OK;
+}
+
+fsi_status fsi_set_coefficients(fsi_ctx* h, int level, const double* c_mass, const double* eta) {
+    if (!h || !c_mass || !eta) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    TRY(check_level(ctx, level));
+    Level& L = ctx->lv[level];
+    if (!L.geo_set) return fail(ctx, FSI_ERR_STATE, "set_coefficients before the level's geometry");
+    invalidate(ctx);
+    launch_fill<int>(ctx->d_flag, 0, 1, ctx->stream);
+    launch_coefficients(L, c_mass, eta, L.d_cw64, L.d_cv64, L.d_cv32, ctx->d_flag, ctx->stream);
+    L.coef_set = false;
+    TRY(sync_flag(ctx, FSI_ERR_NONFINITE, "coefficient not finite (or negative viscosity)"));
+    L.coef_set = true;
+    return FSI_OK;
+}
+
+fsi_status fsi_set_mg_params(fsi_ctx* h, const fsi_mg_params* p) {
+    if (!h || !p) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    if (p->k_A < 1 || p->m < 0 || p->n_cycles < 1 || p->k_S != 1 || p->n_S != 1 || !(p->cheb_upper > 0) ||
+        !(p->cheb_ratio > 1) || p->n_eig < 1 || (p->precision != FSI_PREC_FP64 && p->precision != FSI_PREC_MIXED))
+        return fail(ctx, FSI_ERR_ARG, "invalid multigrid parameters (only k_S = n_S = 1 are implemented)");
+    ctx->prm = *p;
+    invalidate(ctx);
+    return FSI_OK;
+}
+
+fsi_status fsi_setup(fsi_ctx* h) {
+    if (!h) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    invalidate(ctx);
+    for (int j = 0; j < ctx->nlev; ++j)
+        if (!ctx->lv[j].geo_set || !ctx->lv[j].coef_set)
+            return fail(ctx, FSI_ERR_STATE, "setup needs geometry and coefficients on every level");
+    TRY(alloc_work<double>(ctx));
+    TRY(alloc_work<float>(ctx));
+    const int J = ctx->nlev - 1;
+    const Level& F = ctx->lv[J];
+    if (!ctx->vc_in_u) {
+        TRY(dalloc(ctx, &ctx->vc_in_u, F.nv));
+        TRY(dalloc(ctx, &ctx->vc_in_p, F.np));
+        TRY(dalloc(ctx, &ctx->vc_out_u, F.nv));
+        TRY(dalloc(ctx, &ctx->vc_out_p, F.np));
+        TRY(dalloc(ctx, &ctx->vc_tmp, F.nv + F.np));
+    }
+    hipStream_t s = ctx->stream;
+    for (int j = 0; j < ctx->nlev; ++j) {
+        Level& L = ctx->lv[j];
+        double* diag = ctx->w64[j].r_u;   // scratch
+        launch_fill<double>(diag, 0.0, L.nv, s);
+        launch_diagA(L, L.d_K64, L.d_cv64, diag, s);
+        launch_diagA_finish(L, diag, L.d_dAinv64, L.d_dAinv32, s);
+        double n2;
+        TRY(dot64(ctx, diag, diag, L.nv, &n2));
+        L.diagA_norm = std::sqrt(n2);
+        launch_diagS_impl(L, L.d_wall, L.d_K64, L.d_dAinv64, L.d_dSinv, s);
+        // ||diag S|| from its inverse
+        double* tmp = ctx->w64[j].t_p;
+        launch_recip(L.d_dSinv, tmp, L.np, s);
+        TRY(dot64(ctx, tmp, tmp, L.np, &n2));
+        L.diagS_norm = std::sqrt(n2);
+        TRY(lanczos(ctx, j));
+    }
+    TRY(setup_coarse(ctx));
+    FSI_HIP_TRY(hipStreamSynchronize(s));
+    TRY(capture_graphs(ctx));
+    ctx->setup_done = true;
+    return FSI_OK;
+}
+
+fsi_status fsi_get_level_info(const fsi_ctx* h, int level, fsi_level_info* info) {
+    if (!h || !info) return FSI_ERR_ARG;
+    const Context* ctx = &h->c;
+    if (level < 0 || level >= ctx->nlev) return FSI_ERR_ARG;
+    if (!ctx->setup_done) return FSI_ERR_STATE;
+    const Level& L = ctx->lv[level];
+    info->lambda_max = L.lam;
+    info->cheb_lo = L.lo;
+    info->cheb_hi = L.hi;
+    info->diagA_norm2 = L.diagA_norm;
+    info->diagS_norm2 = L.diagS_norm;
+    info->coarse_n = level == 0 ? ctx->coarse.n : 0;
+    return FSI_OK;
+}
+
+static fsi_status apply_check(Context* ctx, int level, bool need_coef) {
+    TRY(check_level(ctx, level));
+    const Level& L = ctx->lv[level];
+    if (!L.geo_set) return fail(ctx, FSI_ERR_STATE, "apply before the level's geometry");
+    if (need_coef && !L.coef_set) return fail(ctx, FSI_ERR_STATE, "apply before the level's coefficients");
+    return FSI_OK;
+}
+
+fsi_status fsi_apply_A(fsi_ctx* h, int level, const double* u, double* v) {
+    if (!h || !u || !v) return FSI_ERR_ARG;
+    TRY(apply_check(&h->c, level, true));
+    op_apply<double>(&h->c, level, OP_A, u, nullptr, v, nullptr, h->c.stream);
+    return FSI_OK;
+}
+fsi_status fsi_apply_B(fsi_ctx* h, int level, const double* u, double* q) {
+    if (!h || !u || !q) return FSI_ERR_ARG;
+    TRY(apply_check(&h->c, level, false));
+    op_apply<double>(&h->c, level, OP_B, u, nullptr, nullptr, q, h->c.stream);
+    return FSI_OK;
+}
+fsi_status fsi_apply_BT(fsi_ctx* h, int level, const double* p, double* v) {
+    if (!h || !p || !v) return FSI_ERR_ARG;
+    TRY(apply_check(&h->c, level, false));
+    op_apply<double>(&h->c, level, OP_BT, nullptr, p, v, nullptr, h->c.stream);
+    return FSI_OK;
+}
+fsi_status fsi_apply_stokes(fsi_ctx* h, int level, const double* u, const double* p, double* v, double* q) {
+    if (!h || !u || !p || !v || !q) return FSI_ERR_ARG;
+    TRY(apply_check(&h->c, level, true));
+    op_apply<double>(&h->c, level, OP_A | OP_BT | OP_B, u, p, v, q, h->c.stream);
+    return FSI_OK;
+}
+
+// FP32 twins: pressure is carried in FP64 inside the kernels; cast at the boundary
+static fsi_status p_scratch(Context* ctx, int level, double** a, double** b) {
+    TRY(alloc_work<double>(ctx));
+    *a = ctx->w64[level].z_p;
+    *b = ctx->w64[level].t_p;
+    return FSI_OK;
+}
+fsi_status fsi_apply_A_f32(fsi_ctx* h, int level, const float* u, float* v) {
+    if (!h || !u || !v) return FSI_ERR_ARG;
+    TRY(apply_check(&h->c, level, true));
+    op_apply<float>(&h->c, level, OP_A, u, nullptr, v, nullptr, h->c.stream);
+    return FSI_OK;
+}
+fsi_status fsi_apply_B_f32(fsi_ctx* h, int level, const float* u, float* q) {
+    if (!h || !u || !q) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    TRY(apply_check(ctx, level, false));
+    double *a, *b;
+    TRY(p_scratch(ctx, level, &a, &b));
+    op_apply<float>(ctx, level, OP_B, u, nullptr, nullptr, b, ctx->stream);
+    launch_cast<float, double>(q, b, ctx->lv[level].np, ctx->stream);
+    return FSI_OK;
+}
+fsi_status fsi_apply_BT_f32(fsi_ctx* h, int level, const float* p, float* v) {
+    if (!h || !p || !v) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    TRY(apply_check(ctx, level, false));
+    double *a, *b;
+    TRY(p_scratch(ctx, level, &a, &b));
+    launch_cast<double, float>(a, p, ctx->lv[level].np, ctx->stream);
+    op_apply<float>(ctx, level, OP_BT, nullptr, a, v, nullptr, ctx->stream);
+    return FSI_OK;
+}
+fsi_status fsi_apply_stokes_f32(fsi_ctx* h, int level, const float* u, const float* p, float* v, float* q) {
+    if (!h || !u || !p || !v || !q) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    TRY(apply_check(ctx, level, true));
+    double *a, *b;
+    TRY(p_scratch(ctx, level, &a, &b));
+    launch_cast<double, float>(a, p, ctx->lv[level].np, ctx->stream);
+    op_apply<float>(ctx, level, OP_A | OP_BT | OP_B, u, a, v, b, ctx->stream);
+    launch_cast<float, double>(q, b, ctx->lv[level].np, ctx->stream);
+    return FSI_OK;
+}
+
+fsi_status fsi_vcycle(fsi_ctx* h, const double* r_u, const double* r_p, double* z_u, double* z_p) {
+    if (!h || !r_u || !r_p || !z_u || !z_p) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    if (!ctx->setup_done) return fail(ctx, FSI_ERR_STATE, "vcycle before setup");
+    const Level& L = ctx->lv[ctx->nlev - 1];
+    hipStream_t s = ctx->stream;
+    // combined staging through the Krylov-independent IO buffers
+    FSI_HIP_TRY(hipMemcpyAsync(ctx->vc_in_u, r_u, sizeof(double) * L.nv, hipMemcpyDeviceToDevice, s));
+    FSI_HIP_TRY(hipMemcpyAsync(ctx->vc_in_p, r_p, sizeof(double) * L.np, hipMemcpyDeviceToDevice, s));
+    if (ctx->prm.n_cycles == 1) {
+        TRY(run_vcycle(ctx, s));
+        FSI_HIP_TRY(hipMemcpyAsync(z_u, ctx->vc_out_u, sizeof(double) * L.nv, hipMemcpyDeviceToDevice, s));
+        FSI_HIP_TRY(hipMemcpyAsync(z_p, ctx->vc_out_p, sizeof(double) * L.np, hipMemcpyDeviceToDevice, s));
+        return FSI_OK;
+    }
+    TRY(ensure_krylov(ctx, std::max(ctx->kr.restart, 1)));
+    double* r = ctx->kr.r;
+    double* z = ctx->kr.w;
+    FSI_HIP_TRY(hipMemcpyAsync(r, r_u, sizeof(double) * L.nv, hipMemcpyDeviceToDevice, s));
+    FSI_HIP_TRY(hipMemcpyAsync(r + L.nv, r_p, sizeof(double) * L.np, hipMemcpyDeviceToDevice, s));
+    TRY(precond_combined(ctx, r, z, s));
+    FSI_HIP_TRY(hipMemcpyAsync(z_u, z, sizeof(double) * L.nv, hipMemcpyDeviceToDevice, s));
+    FSI_HIP_TRY(hipMemcpyAsync(z_p, z + L.nv, sizeof(double) * L.np, hipMemcpyDeviceToDevice, s));
+    return FSI_OK;
+}
+
+fsi_status fsi_solve(fsi_ctx* h, const double* g_u, const double* g_p, double* u, double* p,
+                     const fsi_solve_opts* o, fsi_solve_info* info) {
+    if (!h || !g_u || !g_p || !u || !p || !o) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    if (!ctx->setup_done) return fail(ctx, FSI_ERR_STATE, "solve before setup");
+    if (o->restart < 1 || o->max_iter < 0 || !(o->rtol >= 0)) return fail(ctx, FSI_ERR_ARG, "invalid solve options");
+    const auto t0 = std::chrono::steady_clock::now();
+    TRY(ensure_krylov(ctx, o->restart));
+    Krylov& K = ctx->kr;
+    const Level& L = ctx->lv[ctx->nlev - 1];
+    const int64_t n = K.n, nv = L.nv, np = L.np;
+    hipStream_t s = ctx->stream;
+    FSI_HIP_TRY(hipMemcpyAsync(K.g, g_u, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
+    FSI_HIP_TRY(hipMemcpyAsync(K.g + nv, g_p, sizeof(double) * np, hipMemcpyDeviceToDevice, s));
+    FSI_HIP_TRY(hipMemcpyAsync(K.x, u, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
+    FSI_HIP_TRY(hipMemcpyAsync(K.x + nv, p, sizeof(double) * np, hipMemcpyDeviceToDevice, s));
+    launch_fill<int>(ctx->d_flag, 0, 1, s);
+    launch_nonfinite(K.g, n, ctx->d_flag, s);
+    launch_nonfinite(K.x, n, ctx->d_flag, s);
+    TRY(sync_flag(ctx, FSI_ERR_NONFINITE, "right-hand side or initial guess not finite"));
+    double gn2;
+    TRY(dot64(ctx, K.g, K.g, n, &gn2));
+    const double gnorm = std::sqrt(gn2);
+    int hist_n = 0;
+    auto push_hist = [&](double v) {
+        if (info && info->res_history && hist_n < o->max_iter + 1) info->res_history[hist_n] = v;
+        ++hist_n;
+    };
+    if (gnorm == 0.0) {
+        launch_fill<double>(u, 0.0, nv, s);
+        launch_fill<double>(p, 0.0, np, s);
+        FSI_HIP_TRY(hipStreamSynchronize(s));
+        if (info) {
+            info->iters = 0;
+            info->final_rel_res = 0.0;
+            info->n_hist = 0;
+            info->time_ms = 0.0;
+        }
+        return FSI_OK;
+    }
+    stokes_combined(ctx, K.x, K.w, s);
+    launch_sub_into(K.g, K.w, K.r, n, s);
+    double b2;
+    TRY(dot64(ctx, K.r, K.r, n, &b2));
+    double beta = std::sqrt(b2);
+    push_hist(beta / gnorm);
+    int it = 0;
+    const int R = o->restart;
+    std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), sv(R + 1), y(R);
+    fsi_status status = FSI_OK;
+    while (beta / gnorm > o->rtol && it < o->max_iter) {
+        if (!std::isfinite(beta)) {
+            status = fail(ctx, FSI_ERR_NONFINITE, "non-finite residual in FGMRES");
+            break;
+        }
+        launch_scale_host(1.0 / beta, K.r, K.V, n, s);
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(sv.begin(), sv.end(), 0.0);
+        sv[0] = beta;
+        int kused = 0;
+        bool done = false;
+        for (int k = 0; k < R; ++k) {
+            double* Vk = K.V + (int64_t)k * n;
+            double* Zk = K.Z + (int64_t)k * n;
+            TRY(precond_combined(ctx, Vk, Zk, s));
+            stokes_combined(ctx, Zk, K.w, s);
+            // classical Gram-Schmidt with one reorthogonalisation (two batched passes)
+            launch_multi_dot(K.V, n, k + 1, K.w, n, K.partials, K.h, s);
+            launch_multi_axpy(K.V, n, k + 1, K.h, -1.0, K.w, n, s);
+            launch_multi_dot(K.V, n, k + 1, K.w, n, K.partials, K.h + (R + 2), s);
+            launch_multi_axpy(K.V, n, k + 1, K.h + (R + 2), -1.0, K.w, n, s);
+            launch_dot<double>(K.w, K.w, n, K.partials, K.h + (k + 1), s);
+            FSI_HIP_TRY(hipMemcpyAsync(K.h_host, K.h, sizeof(double) * 2 * (R + 2), hipMemcpyDeviceToHost, s));
+            FSI_HIP_TRY(hipStreamSynchronize(s));
+            const double hnext = std::sqrt(K.h_host[k + 1]);
+            for (int i = 0; i <= k; ++i) H[(size_t)i * R + k] = K.h_host[i] + K.h_host[(R + 2) + i];
+            H[(size_t)(k + 1) * R + k] = hnext;
+            for (int i = 0; i < k; ++i) {
+                const double a = H[(size_t)i * R + k], b = H[(size_t)(i + 1) * R + k];
+                H[(size_t)i * R + k] = cs[i] * a + sn[i] * b;
+                H[(size_t)(i + 1) * R + k] = -sn[i] * a + cs[i] * b;
+            }
+            const double a = H[(size_t)k * R + k], b = H[(size_t)(k + 1) * R + k];
+            const double den = std::hypot(a, b);
+            if (!(den > 0) || !std::isfinite(den)) {
+                status = fail(ctx, FSI_ERR_BREAKDOWN, "FGMRES breakdown (zero or non-finite Hessenberg column)");
+                done = true;
+                break;
+            }
+            cs[k] = a / den;
+            sn[k] = b / den;
+            H[(size_t)k * R + k] = den;
+            H[(size_t)(k + 1) * R + k] = 0.0;
+            sv[k + 1] = -sn[k] * sv[k];
+            sv[k] = cs[k] * sv[k];
+            ++it;
+            kused = k + 1;
+            push_hist(std::fabs(sv[k + 1]) / gnorm);
+            if (std::fabs(sv[k + 1]) / gnorm <= o->rtol || it >= o->max_iter || hnext == 0.0) break;
+            launch_scale_host(1.0 / hnext, K.w, K.V + (int64_t)(k + 1) * n, n, s);
+        }
+        if (kused > 0) {
+            for (int i = kused - 1; i >= 0; --i) {
+                double acc = sv[i];
+                for (int jj = i + 1; jj < kused; ++jj) acc -= H[(size_t)i * R + jj] * y[jj];
+                y[i] = acc / H[(size_t)i * R + i];
+            }
+            double* yh = K.h_host + 2 * (R + 2);
+            for (int i = 0; i < kused; ++i) yh[i] = y[i];
+            FSI_HIP_TRY(hipMemcpyAsync(K.h, yh, sizeof(double) * kused, hipMemcpyHostToDevice, s));
+            launch_multi_axpy(K.Z, n, kused, K.h, 1.0, K.x, n, s);
+        }
+        stokes_combined(ctx, K.x, K.w, s);
+        launch_sub_into(K.g, K.w, K.r, n, s);
+        TRY(dot64(ctx, K.r, K.r, n, &b2));
+        beta = std::sqrt(b2);
+        if (done) break;
+    }
+    FSI_HIP_TRY(hipMemcpyAsync(u, K.x, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
+    FSI_HIP_TRY(hipMemcpyAsync(p, K.x + nv, sizeof(double) * np, hipMemcpyDeviceToDevice, s));
+    FSI_HIP_TRY(hipStreamSynchronize(s));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) {
+        info->iters = it;
+        info->final_rel_res = beta / gnorm;
+        info->time_ms = ms;
+        info->n_hist = std::min(hist_n, o->max_iter + 1);
+    }
+    if (status != FSI_OK) return status;
+    if (!std::isfinite(beta)) return fail(ctx, FSI_ERR_NONFINITE, "non-finite final residual");
+    return beta / gnorm <= o->rtol ? FSI_OK : FSI_NOT_CONVERGED;
+}
+
+fsi_status fsi_autotune(fsi_ctx* h) {
+    if (!h) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    for (int j = 0; j < ctx->nlev; ++j)
+        if (!ctx->lv[j].geo_set || !ctx->lv[j].coef_set)
+            return fail(ctx, FSI_ERR_STATE, "autotune needs geometry and coefficients on every level");
+    TRY(alloc_work<double>(ctx));
+    TRY(alloc_work<float>(ctx));
+    hipStream_t s = ctx->stream;
+    hipEvent_t e0, e1;
+    FSI_HIP_TRY(hipEventCreate(&e0));
+    FSI_HIP_TRY(hipEventCreate(&e1));
+    for (int pi = 0; pi < 2; ++pi)
+        for (int j = 0; j < ctx->nlev; ++j) {
+            const Level& L = ctx->lv[j];
+            double best = 1e300;
+            int bestv = 0;
+            for (int var = 0; var < 6; ++var) {
+                ctx->tune_variant[pi][j] = var;
+                const int reps = 3;
+                for (int r = 0; r <= reps; ++r) {
+                    if (r == 1) FSI_HIP_TRY(hipEventRecord(e0, s));
+                    if (pi == 0) {
+                        LevelWork<double>& W = ctx->w64[j];
+                        op_apply<double>(ctx, j, OP_A | OP_BT | OP_B, W.x_u, W.x_p, W.r_u, W.r_p, s);
+                    } else {
+                        LevelWork<float>& W = ctx->w32[j];
+                        op_apply<float>(ctx, j, OP_A | OP_BT | OP_B, W.x_u, W.x_p, W.r_u, W.r_p, s);
+                    }
+                }
+                FSI_HIP_TRY(hipEventRecord(e1, s));
+                FSI_HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0;
+                FSI_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                const double us = 1000.0 * ms / reps;
+                if (us < best) {
+                    best = us;
+                    bestv = var;
+                }
+            }
+            ctx->tune_variant[pi][j] = bestv;
+            ctx->tune_us[pi][j] = best;
+            (void)L;
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    // captured graphs hold the old launch shapes
+    if (ctx->setup_done) TRY(capture_graphs(ctx));
+    return FSI_OK;
+}
+
+fsi_status fsi_get_tuning(const fsi_ctx* h, int level, int precision, int* variant, double* best_us) {
+    if (!h || !variant || !best_us) return FSI_ERR_ARG;
+    const Context* ctx = &h->c;
+    if (level < 0 || level >= ctx->nlev || (precision != 0 && precision != 1)) return FSI_ERR_ARG;
+    *variant = ctx->tune_variant[precision][level];
+    *best_us = ctx->tune_us[precision][level];
+    return FSI_OK;
+}
+
+}  // extern "C"

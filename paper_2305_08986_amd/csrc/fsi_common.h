@@ -1,0 +1,252 @@
+// Shared definitions of the HIP library: 1D reference data, launch helpers,
+// the level/context structures and the kernel-launcher prototypes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fsi.h"
+
+namespace fsi {
+
+// ---------------------------------------------------------------- 1D reference data
+// Q2 Lagrange basis on the nodes {0, 1/2, 1} and Q1 basis on {0, 1}, evaluated at
+// the 3-point Gauss-Legendre points {1/2 - s, 1/2, 1/2 + s}, s = sqrt(15)/10, on [0,1].
+// With g0 = 1/2 - s:  N0(g0) = 3/10 + s, N1(g0) = 2/5, N2(g0) = 3/10 - s,
+// N0'(g0) = -1 - 4s, N1'(g0) = 8s, N2'(g0) = 1 - 4s; the tables at g2 follow by symmetry.
+constexpr double kS15 = 0.38729833462074168852;           // sqrt(15)/10
+constexpr double kG0 = 0.5 - kS15, kG2 = 0.5 + kS15;
+constexpr double kW0 = 5.0 / 18.0, kW1 = 8.0 / 18.0;
+
+struct Tab {
+    // S[q][n] = N_n(g_q), D[q][n] = N_n'(g_q), L[q][a] = Q1 basis a at g_q
+    static constexpr double S[3][3] = {{0.3 + kS15, 0.4, 0.3 - kS15}, {0.0, 1.0, 0.0}, {0.3 - kS15, 0.4, 0.3 + kS15}};
+    static constexpr double D[3][3] = {{-1.0 - 4.0 * kS15, 8.0 * kS15, 1.0 - 4.0 * kS15},
+                                       {-1.0, 0.0, 1.0},
+                                       {-1.0 + 4.0 * kS15, -8.0 * kS15, 1.0 + 4.0 * kS15}};
+    static constexpr double L[3][2] = {{0.5 + kS15, 0.5 - kS15}, {0.5, 0.5}, {0.5 - kS15, 0.5 + kS15}};
+    static constexpr double W[3] = {kW0, kW1, kW0};
+};
+
+// cell-kernel thread shapes: NT threads per cell (one per line of 3 points),
+// CPW cells per 64-wide wavefront
+template <int DIM> struct Shape;
+template <> struct Shape<2> { static constexpr int NT = 3, CPW = 21, NLOC = 9, NPL = 4, Q = 9, NK = 4; };
+template <> struct Shape<3> { static constexpr int NT = 9, CPW = 7, NLOC = 27, NPL = 8, Q = 27, NK = 9; };
+
+// operator mode bits of the cell kernel
+enum : int { OP_A = 1, OP_BT = 2, OP_B = 4 };
+
+// ---------------------------------------------------------------- error helpers
+#define FSI_HIP_TRY(expr)                                                          \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            return ::fsi::hip_fail(ctx, e_, #expr, __FILE__, __LINE__);            \
+        }                                                                          \
+    } while (0)
+
+struct Context;
+fsi_status hip_fail(Context* ctx, hipError_t e, const char* what, const char* file, int line);
+fsi_status fail(Context* ctx, fsi_status st, const std::string& msg);
+
+// ---------------------------------------------------------------- device buffers
+template <typename T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+};
+
+// ---------------------------------------------------------------- level data
+struct Level {
+    int dim = 0;
+    int cells[3] = {1, 1, 1};
+    int vnodes[3] = {1, 1, 1};
+    int pnodes[3] = {1, 1, 1};
+    int64_t nc = 0, nvn = 0, nv = 0, np = 0, nvert = 0;
+    int Q = 0;
+    int ncolors = 0;
+    int64_t color_off[9] = {0};
+
+    // colour-ordered cell structure
+    int* d_col2lex = nullptr;      // [nc]
+    int* d_lex2col = nullptr;      // [nc]
+    int* d_vmap = nullptr;         // [nc][NLOC] Q2 node of local node
+    int* d_pmap = nullptr;         // [nc][NPL]  Q1 node / vertex of local vertex
+    uint32_t* d_dmask = nullptr;   // [nc] bit n set: local Q2 node n is on a wall
+    uint8_t* d_wall = nullptr;     // [nvn] 1: velocity node on a wall
+    int* d_dir_nodes = nullptr;    // wall nodes
+    int64_t n_dir = 0;
+    std::vector<uint8_t> h_dir_node;   // [nvn] host copy of the wall mask
+
+    // geometry and coefficients, internal layout [plane][qx][cell][t]
+    double* d_K64 = nullptr;       // 9 (or 4) planes: det(J) w_q J^{-1}, entry (b,a) in plane b*dim+a
+    double* d_cw64 = nullptr;      // det(J) w_q
+    double* d_cv64 = nullptr;      // 2 planes: 2 eta/(det J w), c_m det J w
+    float* d_K32 = nullptr;
+    float* d_cv32 = nullptr;
+    bool geo_set = false, coef_set = false;
+
+    // preconditioner data
+    double* d_dAinv64 = nullptr;   // 1/diag(A) (1 on wall dofs)
+    float* d_dAinv32 = nullptr;
+    double* d_dSinv = nullptr;     // 1/diag(B diag(A)^{-1} B^T)
+    double lam = 0, lo = 0, hi = 0;
+    double diagA_norm = 0, diagS_norm = 0;
+
+    int64_t plane() const { return (int64_t)Q * nc; }
+};
+
+// per-level work vectors of the V-cycle in one precision (T velocity, double pressure)
+template <typename T>
+struct LevelWork {
+    T *f_u = nullptr, *x_u = nullptr, *r_u = nullptr, *w_u = nullptr, *v_u = nullptr;
+    T *cd_u = nullptr, *cax_u = nullptr, *tu = nullptr;
+    double *f_p = nullptr, *x_p = nullptr, *r_p = nullptr, *t_p = nullptr, *z_p = nullptr;
+    double *dots = nullptr;        // [2] device scalars: <y,z>, <y, D_S^{-1} y>
+    double *partials = nullptr;    // reduction scratch
+};
+
+struct Coarse {
+    int64_t n = 0;                 // free velocity dofs + pressure dofs
+    int64_t nfree_u = 0;
+    int* d_uidx = nullptr;         // [nfree_u] velocity dof index of free dof i
+    double* d_inv64 = nullptr;     // [n][n] row-major inverse of M_0 restricted to free dofs
+    float* d_inv32 = nullptr;
+    double* d_xin64 = nullptr;     // gathered rhs
+    double* d_xout64 = nullptr;
+    float* d_xin32 = nullptr;
+    float* d_xout32 = nullptr;
+};
+
+struct Krylov {
+    int restart = 0;
+    int64_t n = 0;
+    double* V = nullptr;           // [restart+1][n]
+    double* Z = nullptr;           // [restart][n]
+    double* w = nullptr;           // [n]
+    double* r = nullptr;           // [n]
+    double* x = nullptr;           // [n]
+    double* g = nullptr;           // [n]
+    double* h = nullptr;           // device [restart+2]
+    double* partials = nullptr;
+    double* h_host = nullptr;      // pinned host mirror
+};
+
+struct Context {
+    fsi_mesh_desc mesh{};
+    int nlev = 0;
+    std::vector<Level> lv;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    fsi_mg_params prm{};
+    bool setup_done = false;
+
+    std::vector<LevelWork<double>> w64;
+    std::vector<LevelWork<float>> w32;
+    Coarse coarse;
+    Krylov kr;
+    double* d_scratch = nullptr;   // general scratch (partials, flags)
+    int* d_flag = nullptr;
+    int* h_flag = nullptr;         // pinned
+    double* h_dbl = nullptr;       // pinned [64]
+    // top-level V-cycle IO buffers (FP64) for the graph path
+    double *vc_in_u = nullptr, *vc_in_p = nullptr, *vc_out_u = nullptr, *vc_out_p = nullptr;
+    double* vc_tmp = nullptr;      // [nv + np] residual of repeated V-cycles
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    bool graph_valid[2] = {false, false};
+    // tuning: per level and precision, index into the launch-variant table
+    std::vector<int> tune_variant[2];
+    std::vector<double> tune_us[2];
+    std::vector<void*> allocations;
+};
+
+// ---------------------------------------------------------------- launchers (kernels_*.hip)
+// cell operator on one colour range; mode = OP_* bits; variant selects the
+// workgroup size (wavefronts per workgroup) and block->tile mapping.
+template <typename T>
+void launch_cell(const Level& L, int mode, int variant, int color, const T* K, const T* cv,
+                 const T* u, const double* p, T* v, double* q, hipStream_t s);
+template <typename T>
+void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T* cv,
+                     const T* u, const double* p, T* v, double* q, hipStream_t s);
+
+void launch_geometry(const Level& L, const double* J, double* K, double* cw, float* K32, int* flag,
+                     hipStream_t s);
+void launch_geometry_from_disp_h(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
+                                 const double* h, double* K, double* cw, float* K32, int* flag, hipStream_t s);
+void launch_coefficients(const Level& L, const double* cm, const double* eta, const double* cw,
+                         double* cv64, float* cv32, int* flag, hipStream_t s);
+void launch_diagA(const Level& L, const double* K, const double* cv, double* diag, hipStream_t s);
+void launch_diagA_finish(const Level& L, double* diag, double* dinv64, float* dinv32, hipStream_t s);
+void launch_diagS_impl(const Level& L, const uint8_t* d_wall, const double* K, const double* dAinv,
+                       double* dSinv, hipStream_t s);
+inline const uint8_t* level_wall_mask(const Level& L) { return L.d_wall; }
+
+template <typename T>
+void launch_fill(T* x, T val, int64_t n, hipStream_t s);
+template <typename T>
+void launch_dirichlet_copy(const Level& L, const T* u, T* v, hipStream_t s);   // v[wall] = u[wall]
+template <typename T>
+void launch_dirichlet_zero(const Level& L, T* v, hipStream_t s);
+template <typename TD, typename TS>
+void launch_cast(TD* d, const TS* src, int64_t n, hipStream_t s);
+
+// Chebyshev pieces: x = dinv*r*c0, d = x ; d = c1 d + c2 dinv (r - ax), x += d
+template <typename T>
+void launch_cheb_init(const T* dinv, const T* r, T* x, T* d, double c0, int64_t n, hipStream_t s);
+template <typename T>
+void launch_cheb_step(const T* dinv, const T* r, const T* ax, T* x, T* d, double c1, double c2,
+                      int64_t n, hipStream_t s);
+// r = f - a (velocity, type T) ; and pressure (double)
+template <typename T>
+void launch_sub(const T* f, const T* a, T* r, int64_t n, hipStream_t s);
+// z = dsinv * (t - r)
+void launch_schur_z(const double* dsinv, const double* t, const double* r, double* z, int64_t n,
+                    hipStream_t s);
+// dots[0] = <y,z>, dots[1] = <y, dsinv y>
+void launch_schur_dots(const double* y, const double* z, const double* dsinv, double* partials,
+                       double* dots, int64_t n, hipStream_t s);
+// x_u += w - beta v ; x_p += beta z (beta = dots[0]/dots[1]); first: x = instead of +=
+template <typename T>
+void launch_smoother_update(const T* w, const T* vv, const double* z, const double* dots, T* x_u,
+                            double* x_p, int64_t nu, int64_t np, bool first, hipStream_t s);
+
+template <typename T>
+void launch_restrict(const Level& fine, const Level& coarse, const T* rf_u, const double* rf_p,
+                     T* rc_u, double* rc_p, hipStream_t s);
+template <typename T>
+void launch_prolongate_add(const Level& fine, const Level& coarse, const T* ec_u, const double* ec_p,
+                           T* xf_u, double* xf_p, hipStream_t s);
+
+// coarse level
+void launch_coarse_assemble_impl(const Level& L, const double* K, const double* cv, const int* vrow,
+                                 int64_t nfree_u, double* M, int64_t n, hipStream_t s);
+void launch_gj(double* M, int64_t n, int* piv, double* colk, int* flag, hipStream_t s);
+template <typename T>
+void launch_coarse_apply(const Coarse& C, const Level& L, const T* f_u, const double* f_p, T* x_u,
+                         double* x_p, hipStream_t s);
+
+// reductions and BLAS-1 (FP64 accumulation)
+template <typename T>
+void launch_dot(const T* x, const T* y, int64_t n, double* partials, double* out, hipStream_t s);
+void launch_multi_dot(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* partials,
+                      double* out, hipStream_t s);
+void launch_multi_axpy(const double* V, int64_t ldv, int m, const double* coef_dev, double sign,
+                       double* w, int64_t n, hipStream_t s);
+void launch_axpy_host(double a, const double* x, double* y, int64_t n, hipStream_t s);
+void launch_scale_host(double a, const double* x, double* y, int64_t n, hipStream_t s);
+void launch_lanczos_start(const Level& L, double* v, hipStream_t s);
+void launch_mul(const double* a, const double* b, double* c, int64_t n, hipStream_t s);
+void launch_vsqrt(const double* a, double* c, int64_t n, hipStream_t s);
+void launch_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s);
+void launch_sub_into(const double* g, const double* mx, double* r, int64_t n, hipStream_t s);
+void launch_recip(const double* a, double* b, int64_t n, hipStream_t s);
+
+constexpr int kReduceBlocks = 1024;
+
+}  // namespace fsi

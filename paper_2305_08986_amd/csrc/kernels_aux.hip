@@ -1,0 +1,1116 @@
+// Auxiliary kernels of the hot path: geometry and coefficient setup (mapped
+// spaces of Sec. 3.2, BDF mass coefficient of Sec. 3.1, viscosity splitting of
+// Sec. 3.1.1), the diagonals diag(A) and diag(B diag(A)^{-1} B^T) used by the
+// smoother of Sec. 4, the nested-space transfers of the level hierarchy
+// (Sec. 4), the Chebyshev and MINRES vector updates, FP64 reductions and the
+// dense coarsest-level solve.
+#include "fsi_common.h"
+
+namespace fsi {
+
+constexpr int TPB = 256;
+static inline unsigned nblocks(int64_t n, int tpb = TPB) {
+    int64_t b = (n + tpb - 1) / tpb;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+__device__ __forceinline__ double dS(int q, int n) {
+    return n == 1 ? (q == 1 ? 1.0 : 0.4) : (q == 1 ? 0.0 : ((q == 0) == (n == 0) ? 0.3 + kS15 : 0.3 - kS15));
+}
+__device__ __forceinline__ double dD(int q, int n) {
+    if (q == 1) return n == 0 ? -1.0 : (n == 1 ? 0.0 : 1.0);
+    const double sg = (q == 0) ? 1.0 : -1.0;   // D[2][n] = -D[0][2-n]
+    const int m = (q == 0) ? n : 2 - n;
+    const double v = m == 0 ? -1.0 - 4.0 * kS15 : (m == 1 ? 8.0 * kS15 : 1.0 - 4.0 * kS15);
+    return sg * v;
+}
+__device__ __forceinline__ double dL(int q, int a) {
+    if (q == 1) return 0.5;
+    return ((q == 0) == (a == 0)) ? 0.5 + kS15 : 0.5 - kS15;
+}
+__device__ __forceinline__ double dLd(int a) { return a == 0 ? -1.0 : 1.0; }
+__device__ __forceinline__ double dW(int q) { return q == 1 ? kW1 : kW0; }
+
+// ---------------------------------------------------------------- geometry
+struct GeoOut {
+    int dim, NT, Q;
+    int64_t nc, plane;
+    const int* lex2col;
+    double* K;
+    double* cw;
+    float* K32;
+    int* flag;
+};
+
+__device__ __forceinline__ void store_geometry(const GeoOut& g, int64_t cell, int q, const double* J) {
+    const int dim = g.dim;
+    const int qx = q % 3, t = q / 3;
+    const int64_t col = g.lex2col[cell];
+    const int64_t off = ((int64_t)qx * g.nc + col) * g.NT + t;
+    double w = 1.0;
+    int r = q;
+    for (int d = 0; d < dim; ++d) {
+        w *= dW(r % 3);
+        r /= 3;
+    }
+    double inv[9];
+    double det;
+    if (dim == 2) {
+        det = J[0] * J[3] - J[1] * J[2];
+        const double id = 1.0 / det;
+        inv[0] = J[3] * id; inv[1] = -J[1] * id; inv[2] = -J[2] * id; inv[3] = J[0] * id;
+    } else {
+        const double c00 = J[4] * J[8] - J[5] * J[7];
+        const double c01 = J[5] * J[6] - J[3] * J[8];
+        const double c02 = J[3] * J[7] - J[4] * J[6];
+        det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+        const double id = 1.0 / det;
+        inv[0] = c00 * id;
+        inv[1] = (J[2] * J[7] - J[1] * J[8]) * id;
+        inv[2] = (J[1] * J[5] - J[2] * J[4]) * id;
+        inv[3] = c01 * id;
+        inv[4] = (J[0] * J[8] - J[2] * J[6]) * id;
+        inv[5] = (J[2] * J[3] - J[0] * J[5]) * id;
+        inv[6] = c02 * id;
+        inv[7] = (J[1] * J[6] - J[0] * J[7]) * id;
+        inv[8] = (J[0] * J[4] - J[1] * J[3]) * id;
+    }
+    if (!(det > 0.0)) g.flag[0] = 1;
+    const double cw = det * w;
+    g.cw[off] = cw;
+    // plane b*dim + a holds K_{ba} = cw (J^{-1})_{ba}
+    for (int b = 0; b < dim; ++b)
+        for (int a = 0; a < dim; ++a) {
+            const double k = cw * inv[b * dim + a];
+            g.K[(b * dim + a) * g.plane + off] = k;
+            g.K32[(b * dim + a) * g.plane + off] = (float)k;
+        }
+}
+
+__global__ void k_geometry(GeoOut g, const double* __restrict__ J) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.nc * g.Q) return;
+    const int64_t cell = id / g.Q;
+    const int q = (int)(id - cell * g.Q);
+    const int dd = g.dim * g.dim;
+    double Jl[9];
+    for (int i = 0; i < dd; ++i) Jl[i] = J[id * dd + i];
+    store_geometry(g, cell, q, Jl);
+}
+
+void launch_geometry(const Level& L, const double* J, double* K, double* cw, float* K32, int* flag,
+                     hipStream_t s) {
+    GeoOut g{L.dim, L.dim == 3 ? 9 : 3, L.Q, L.nc, L.plane(), L.d_lex2col, K, cw, K32, flag};
+    hipLaunchKernelGGL(k_geometry, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, g, J);
+}
+
+struct DispIn {
+    const double* disp;   // fine vertex displacement [dim][nvert_fine]
+    int stride;           // level vertex -> fine vertex
+    int fp[3];            // fine vertex counts per direction
+    int64_t nvert_fine;
+    int cells[3];
+    double h[3];
+};
+
+__global__ void k_geometry_disp(GeoOut g, DispIn in) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.nc * g.Q) return;
+    const int64_t cell = id / g.Q;
+    const int q = (int)(id - cell * g.Q);
+    const int dim = g.dim;
+    int ci[3] = {0, 0, 0}, qi[3] = {0, 0, 0};
+    int64_t r = cell;
+    for (int d = 0; d < dim; ++d) {
+        ci[d] = (int)(r % in.cells[d]);
+        r /= in.cells[d];
+    }
+    int rq = q;
+    for (int d = 0; d < dim; ++d) {
+        qi[d] = rq % 3;
+        rq /= 3;
+    }
+    double J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int nv = 1 << dim;
+    for (int v = 0; v < nv; ++v) {
+        int vi[3] = {v & 1, (v >> 1) & 1, (v >> 2) & 1};
+        int64_t fidx = 0, st = 1;
+        double X[3];
+        for (int d = 0; d < dim; ++d) {
+            const int lv = ci[d] + vi[d];
+            X[d] = lv * in.h[d];
+            fidx += (int64_t)lv * in.stride * st;
+            st *= in.fp[d];
+        }
+        for (int b = 0; b < dim; ++b) {
+            double dl = 1.0;
+            for (int d = 0; d < dim; ++d) dl *= (d == b) ? dLd(vi[d]) : dL(qi[d], vi[d]);
+            for (int a = 0; a < dim; ++a) {
+                const double xa = X[a] + in.disp[(int64_t)a * in.nvert_fine + fidx];
+                J[a * dim + b] += dl * xa;
+            }
+        }
+    }
+    store_geometry(g, cell, q, J);
+}
+
+void launch_geometry_from_disp(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
+                               double* K, double* cw, float* K32, int* flag, hipStream_t s) {
+    GeoOut g{L.dim, L.dim == 3 ? 9 : 3, L.Q, L.nc, L.plane(), L.d_lex2col, K, cw, K32, flag};
+    DispIn in;
+    in.disp = disp_fine;
+    in.stride = stride;
+    in.nvert_fine = 1;
+    for (int d = 0; d < 3; ++d) {
+        in.fp[d] = d < L.dim ? fine_pnodes[d] : 1;
+        in.cells[d] = L.cells[d];
+        in.h[d] = 0;
+    }
+    for (int d = 0; d < L.dim; ++d) in.nvert_fine *= in.fp[d];
+    hipLaunchKernelGGL(k_geometry_disp, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, g, in);
+}
+
+// h must be set by the caller through a second entry (extent known on the host)
+void launch_geometry_from_disp_h(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
+                                 const double* h, double* K, double* cw, float* K32, int* flag, hipStream_t s) {
+    GeoOut g{L.dim, L.dim == 3 ? 9 : 3, L.Q, L.nc, L.plane(), L.d_lex2col, K, cw, K32, flag};
+    DispIn in;
+    in.disp = disp_fine;
+    in.stride = stride;
+    in.nvert_fine = 1;
+    for (int d = 0; d < 3; ++d) {
+        in.fp[d] = d < L.dim ? fine_pnodes[d] : 1;
+        in.cells[d] = L.cells[d];
+        in.h[d] = d < L.dim ? h[d] : 0.0;
+    }
+    for (int d = 0; d < L.dim; ++d) in.nvert_fine *= in.fp[d];
+    hipLaunchKernelGGL(k_geometry_disp, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, g, in);
+}
+
+// ---------------------------------------------------------------- coefficients
+__global__ void k_coefficients(int64_t nc, int Q, int NT, int64_t plane, const int* __restrict__ lex2col,
+                               const double* __restrict__ cm, const double* __restrict__ eta,
+                               const double* __restrict__ cw, double* __restrict__ cv64, float* __restrict__ cv32,
+                               int* flag) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nc * Q) return;
+    const int64_t cell = id / Q;
+    const int q = (int)(id - cell * Q);
+    const int qx = q % 3, t = q / 3;
+    const int64_t off = ((int64_t)qx * nc + lex2col[cell]) * NT + t;
+    const double m = cm[id], e = eta[id], w = cw[off];
+    if (!isfinite(m) || !isfinite(e) || !(e >= 0.0)) flag[0] = 1;
+    const double cvisc = 2.0 * e / w, cmass = m * w;
+    cv64[off] = cvisc;
+    cv64[plane + off] = cmass;
+    cv32[off] = (float)cvisc;
+    cv32[plane + off] = (float)cmass;
+}
+
+void launch_coefficients(const Level& L, const double* cm, const double* eta, const double* cw, double* cv64,
+                         float* cv32, int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_coefficients, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, L.nc, L.Q,
+                       L.dim == 3 ? 9 : 3, L.plane(), L.d_lex2col, cm, eta, cw, cv64, cv32, flag);
+}
+
+// ---------------------------------------------------------------- diag(A)
+// diag_(a,n) = sum_q cmass phi_n^2 + (cvisc/2)(|G_n|^2 + G_n[a]^2), G_n = K^T grad-hat phi_n
+__global__ void k_diagA(int dim, int64_t cbeg, int64_t cend, int64_t nc, int64_t nvn, int64_t plane,
+                        const int* __restrict__ vmap, const uint32_t* __restrict__ dmask,
+                        const double* __restrict__ K, const double* __restrict__ cv, double* __restrict__ diag) {
+    const int NLOC = dim == 3 ? 27 : 9;
+    const int NT = dim == 3 ? 9 : 3;
+    const int Q = NLOC;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cell = cbeg + id / NLOC;
+    const int n = (int)(id % NLOC);
+    if (cell >= cend) return;
+    if ((dmask[cell] >> n) & 1u) return;
+    int ni[3] = {n % 3, (n / 3) % 3, n / 9};
+    double acc[3] = {0, 0, 0};
+    for (int q = 0; q < Q; ++q) {
+        int qi[3] = {q % 3, (q / 3) % 3, q / 9};
+        const int qx = qi[0], t = q / 3;
+        const int64_t off = ((int64_t)qx * nc + cell) * NT + t;
+        double phi = 1.0, gh[3];
+        for (int d = 0; d < dim; ++d) phi *= dS(qi[d], ni[d]);
+        for (int b = 0; b < dim; ++b) {
+            double v = 1.0;
+            for (int d = 0; d < dim; ++d) v *= (d == b) ? dD(qi[d], ni[d]) : dS(qi[d], ni[d]);
+            gh[b] = v;
+        }
+        double G[3] = {0, 0, 0}, g2 = 0.0;
+        for (int a = 0; a < dim; ++a) {
+            for (int b = 0; b < dim; ++b) G[a] += K[(b * dim + a) * plane + off] * gh[b];
+            g2 += G[a] * G[a];
+        }
+        const double cvisc = cv[off], cmass = cv[plane + off];
+        for (int a = 0; a < dim; ++a) acc[a] += cmass * phi * phi + 0.5 * cvisc * (g2 + G[a] * G[a]);
+    }
+    const int node = vmap[cell * NLOC + n];
+    for (int a = 0; a < dim; ++a) diag[a * nvn + node] += acc[a];
+}
+
+void launch_diagA(const Level& L, const double* K, const double* cv, double* diag, hipStream_t s) {
+    const int nloc = L.dim == 3 ? 27 : 9;
+    for (int c = 0; c < L.ncolors; ++c) {
+        const int64_t n = (L.color_off[c + 1] - L.color_off[c]) * nloc;
+        if (n == 0) continue;
+        hipLaunchKernelGGL(k_diagA, dim3(nblocks(n)), dim3(TPB), 0, s, L.dim, L.color_off[c], L.color_off[c + 1],
+                           L.nc, L.nvn, L.plane(), L.d_vmap, L.d_dmask, K, cv, diag);
+    }
+}
+
+__global__ void k_diag_finish(int64_t nv, double* __restrict__ diag, double* __restrict__ d64,
+                              float* __restrict__ d32) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    const double d = diag[i];
+    const double inv = d > 0.0 ? 1.0 / d : 1.0;   // wall dofs (zero accumulated) act as identity rows
+    if (!(d > 0.0)) diag[i] = 1.0;
+    d64[i] = inv;
+    d32[i] = (float)inv;
+}
+
+void launch_diagA_finish(const Level& L, double* diag, double* dinv64, float* dinv32, hipStream_t s) {
+    hipLaunchKernelGGL(k_diag_finish, dim3(nblocks(L.nv)), dim3(TPB), 0, s, L.nv, diag, dinv64, dinv32);
+}
+
+// ---------------------------------------------------------------- diag(B diag(A)^{-1} B^T)
+// one workgroup per pressure node; thread = node of the 5^dim velocity patch around it.
+// The assembled row entries B_{k,(a,n)} are sums over the cells sharing vertex k and node n.
+__global__ void k_diagS(int dim, int c0, int c1, int c2, int vn0, int vn1, int vn2, int64_t nc, int64_t nvn,
+                        int64_t plane, const int* __restrict__ lex2col, const uint8_t* __restrict__ wall,
+                        const double* __restrict__ K, const double* __restrict__ dAinv,
+                        double* __restrict__ dSinv) {
+    __shared__ double red[128];
+    const int pn0 = c0 + 1, pn1 = c1 + 1;
+    const int64_t k = blockIdx.x;
+    const int kv[3] = {(int)(k % pn0), (int)((k / pn0) % pn1), (int)(k / ((int64_t)pn0 * pn1))};
+    const int tid = threadIdx.x;
+    const int npatch = dim == 3 ? 125 : 25;
+    const int NT = dim == 3 ? 9 : 3;
+    const int cells[3] = {c0, c1, c2};
+    const int vn[3] = {vn0, vn1, vn2};
+    double contrib = 0.0;
+    if (tid < npatch) {
+        const int pi[3] = {tid % 5, (tid / 5) % 5, tid / 25};
+        int g[3] = {0, 0, 0};
+        bool ok = true;
+        for (int d = 0; d < dim; ++d) {
+            g[d] = 2 * kv[d] - 2 + pi[d];
+            if (g[d] < 0 || g[d] >= vn[d]) ok = false;
+        }
+        if (ok) {
+            int64_t node = g[0] + (int64_t)vn[0] * (g[1] + (int64_t)vn[1] * (dim == 3 ? g[2] : 0));
+            if (!wall[node]) {
+                double bs[3] = {0, 0, 0};
+                const int ncell = 1 << dim;
+                for (int cidx = 0; cidx < ncell; ++cidx) {
+                    int ce[3] = {0, 0, 0}, nl[3] = {0, 0, 0}, kl[3] = {0, 0, 0};
+                    bool in = true;
+                    for (int d = 0; d < dim; ++d) {
+                        ce[d] = kv[d] - 1 + ((cidx >> d) & 1);
+                        if (ce[d] < 0 || ce[d] >= cells[d]) in = false;
+                        nl[d] = g[d] - 2 * ce[d];
+                        if (nl[d] < 0 || nl[d] > 2) in = false;
+                        kl[d] = kv[d] - ce[d];
+                    }
+                    if (!in) continue;
+                    const int64_t lex = ce[0] + (int64_t)cells[0] * (ce[1] + (int64_t)cells[1] * (dim == 3 ? ce[2] : 0));
+                    const int64_t col = lex2col[lex];
+                    const int Q = dim == 3 ? 27 : 9;
+                    for (int q = 0; q < Q; ++q) {
+                        const int qi[3] = {q % 3, (q / 3) % 3, q / 9};
+                        const int64_t off = ((int64_t)qi[0] * nc + col) * NT + q / 3;
+                        double psi = 1.0, gh[3];
+                        for (int d = 0; d < dim; ++d) psi *= dL(qi[d], kl[d]);
+                        for (int b = 0; b < dim; ++b) {
+                            double v = 1.0;
+                            for (int d = 0; d < dim; ++d) v *= (d == b) ? dD(qi[d], nl[d]) : dS(qi[d], nl[d]);
+                            gh[b] = v;
+                        }
+                        for (int a = 0; a < dim; ++a) {
+                            double G = 0.0;
+                            for (int b = 0; b < dim; ++b) G += K[(b * dim + a) * plane + off] * gh[b];
+                            bs[a] += psi * G;
+                        }
+                    }
+                }
+                for (int a = 0; a < dim; ++a) contrib += bs[a] * bs[a] * dAinv[a * nvn + node];
+            }
+        }
+    }
+    red[tid] = contrib;
+    __syncthreads();
+    for (int st = 64; st > 0; st >>= 1) {
+        if (tid < st) red[tid] += red[tid + st];
+        __syncthreads();
+    }
+    if (tid == 0) dSinv[k] = red[0] > 0.0 ? 1.0 / red[0] : 1.0;
+}
+
+void launch_diagS_impl(const Level& L, const uint8_t* d_wall, const double* K, const double* dAinv, double* dSinv,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_diagS, dim3((unsigned)L.np), dim3(128), 0, s, L.dim, L.cells[0], L.cells[1], L.cells[2],
+                       L.vnodes[0], L.vnodes[1], L.vnodes[2], L.nc, L.nvn, L.plane(), L.d_lex2col, d_wall, K,
+                       dAinv, dSinv);
+}
+
+// ---------------------------------------------------------------- simple vector kernels
+template <typename T>
+__global__ void k_fill(T* x, T v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+template <typename T>
+void launch_fill(T* x, T val, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_fill<T>, dim3(nblocks(n)), dim3(TPB), 0, s, x, val, n);
+}
+template void launch_fill<double>(double*, double, int64_t, hipStream_t);
+template void launch_fill<float>(float*, float, int64_t, hipStream_t);
+template void launch_fill<int>(int*, int, int64_t, hipStream_t);
+
+template <typename T>
+__global__ void k_dir_copy(const int* __restrict__ nodes, int64_t nd, int dim, int64_t nvn, const T* __restrict__ u,
+                           T* __restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nd) return;
+    const int64_t n = nodes[i];
+    for (int c = 0; c < dim; ++c) v[c * nvn + n] = u[c * nvn + n];
+}
+template <typename T>
+void launch_dirichlet_copy(const Level& L, const T* u, T* v, hipStream_t s) {
+    if (L.n_dir > 0)
+        hipLaunchKernelGGL(k_dir_copy<T>, dim3(nblocks(L.n_dir)), dim3(TPB), 0, s, L.d_dir_nodes, L.n_dir, L.dim,
+                           L.nvn, u, v);
+}
+template void launch_dirichlet_copy<double>(const Level&, const double*, double*, hipStream_t);
+template void launch_dirichlet_copy<float>(const Level&, const float*, float*, hipStream_t);
+
+template <typename T>
+__global__ void k_dir_zero(const int* __restrict__ nodes, int64_t nd, int dim, int64_t nvn, T* __restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nd) return;
+    const int64_t n = nodes[i];
+    for (int c = 0; c < dim; ++c) v[c * nvn + n] = T(0);
+}
+template <typename T>
+void launch_dirichlet_zero(const Level& L, T* v, hipStream_t s) {
+    if (L.n_dir > 0)
+        hipLaunchKernelGGL(k_dir_zero<T>, dim3(nblocks(L.n_dir)), dim3(TPB), 0, s, L.d_dir_nodes, L.n_dir, L.dim,
+                           L.nvn, v);
+}
+template void launch_dirichlet_zero<double>(const Level&, double*, hipStream_t);
+template void launch_dirichlet_zero<float>(const Level&, float*, hipStream_t);
+
+template <typename TD, typename TS>
+__global__ void k_cast(TD* __restrict__ d, const TS* __restrict__ s, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (TD)s[i];
+}
+template <typename TD, typename TS>
+void launch_cast(TD* d, const TS* src, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL((k_cast<TD, TS>), dim3(nblocks(n)), dim3(TPB), 0, s, d, src, n);
+}
+template void launch_cast<float, double>(float*, const double*, int64_t, hipStream_t);
+template void launch_cast<double, float>(double*, const float*, int64_t, hipStream_t);
+template void launch_cast<double, double>(double*, const double*, int64_t, hipStream_t);
+template void launch_cast<float, float>(float*, const float*, int64_t, hipStream_t);
+
+template <typename T>
+__global__ void k_cheb_init(const T* __restrict__ dinv, const T* __restrict__ r, T* __restrict__ x,
+                            T* __restrict__ d, T c0, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T v = dinv[i] * r[i] * c0;
+    x[i] = v;
+    d[i] = v;
+}
+template <typename T>
+void launch_cheb_init(const T* dinv, const T* r, T* x, T* d, double c0, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cheb_init<T>, dim3(nblocks(n)), dim3(TPB), 0, s, dinv, r, x, d, (T)c0, n);
+}
+template void launch_cheb_init<double>(const double*, const double*, double*, double*, double, int64_t, hipStream_t);
+template void launch_cheb_init<float>(const float*, const float*, float*, float*, double, int64_t, hipStream_t);
+
+template <typename T>
+__global__ void k_cheb_step(const T* __restrict__ dinv, const T* __restrict__ r, const T* __restrict__ ax,
+                            T* __restrict__ x, T* __restrict__ d, T c1, T c2, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T dn = c1 * d[i] + c2 * dinv[i] * (r[i] - ax[i]);
+    d[i] = dn;
+    x[i] += dn;
+}
+template <typename T>
+void launch_cheb_step(const T* dinv, const T* r, const T* ax, T* x, T* d, double c1, double c2, int64_t n,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_cheb_step<T>, dim3(nblocks(n)), dim3(TPB), 0, s, dinv, r, ax, x, d, (T)c1, (T)c2, n);
+}
+template void launch_cheb_step<double>(const double*, const double*, const double*, double*, double*, double, double,
+                                       int64_t, hipStream_t);
+template void launch_cheb_step<float>(const float*, const float*, const float*, float*, float*, double, double,
+                                      int64_t, hipStream_t);
+
+template <typename T>
+__global__ void k_sub(const T* __restrict__ f, const T* __restrict__ a, T* __restrict__ r, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) r[i] = f[i] - a[i];
+}
+template <typename T>
+void launch_sub(const T* f, const T* a, T* r, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_sub<T>, dim3(nblocks(n)), dim3(TPB), 0, s, f, a, r, n);
+}
+template void launch_sub<double>(const double*, const double*, double*, int64_t, hipStream_t);
+template void launch_sub<float>(const float*, const float*, float*, int64_t, hipStream_t);
+
+__global__ void k_schur_z(const double* __restrict__ ds, const double* __restrict__ t, const double* __restrict__ r,
+                          double* __restrict__ z, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = ds[i] * (t[i] - r[i]);
+}
+void launch_schur_z(const double* dsinv, const double* t, const double* r, double* z, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_schur_z, dim3(nblocks(n)), dim3(TPB), 0, s, dsinv, t, r, z, n);
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (tid < st) sh[tid] += sh[tid + st];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+template <typename T>
+__global__ void k_dot_partial(const T* __restrict__ x, const T* __restrict__ y, int64_t n, double* __restrict__ part) {
+    __shared__ double sh[TPB];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += (double)x[i] * (double)y[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_sum_partials(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    __shared__ double sh[TPB];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+static unsigned red_blocks(int64_t n) {
+    int64_t b = (n + TPB - 1) / TPB;
+    if (b > kReduceBlocks) b = kReduceBlocks;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+template <typename T>
+void launch_dot(const T* x, const T* y, int64_t n, double* partials, double* out, hipStream_t s) {
+    const unsigned nb = red_blocks(n);
+    hipLaunchKernelGGL(k_dot_partial<T>, dim3(nb), dim3(TPB), 0, s, x, y, n, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(TPB), 0, s, partials, (int)nb, out);
+}
+template void launch_dot<double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
+template void launch_dot<float>(const float*, const float*, int64_t, double*, double*, hipStream_t);
+
+__global__ void k_schur_dots_partial(const double* __restrict__ y, const double* __restrict__ z,
+                                     const double* __restrict__ ds, int64_t n, double* __restrict__ part) {
+    __shared__ double sh[TPB];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double yi = y[i];
+        a += yi * z[i];
+        b += yi * ds[i] * yi;
+    }
+    const double sa = block_sum(a, sh);
+    __syncthreads();
+    const double sb = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sa;
+        part[2 * blockIdx.x + 1] = sb;
+    }
+}
+__global__ void k_schur_dots_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    __shared__ double sh[TPB];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    const double sa = block_sum(a, sh);
+    __syncthreads();
+    const double sb = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        out[0] = sa;
+        out[1] = sb;
+    }
+}
+void launch_schur_dots(const double* y, const double* z, const double* dsinv, double* partials, double* dots,
+                       int64_t n, hipStream_t s) {
+    const unsigned nb = red_blocks(n);
+    hipLaunchKernelGGL(k_schur_dots_partial, dim3(nb), dim3(TPB), 0, s, y, z, dsinv, n, partials);
+    hipLaunchKernelGGL(k_schur_dots_final, dim3(1), dim3(TPB), 0, s, partials, (int)nb, dots);
+}
+
+// x_u (+)= w - beta v ; x_p (+)= beta z with beta = dots[0]/dots[1] (one MINRES step)
+template <typename T>
+__global__ void k_smoother_update(const T* __restrict__ w, const T* __restrict__ vv, const double* __restrict__ z,
+                                  const double* __restrict__ dots, T* __restrict__ xu, double* __restrict__ xp,
+                                  int64_t nu, int64_t np, int first) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double den = dots[1];
+    const double beta = den != 0.0 ? dots[0] / den : 0.0;
+    if (i < nu) {
+        const T inc = w[i] - (T)beta * vv[i];
+        xu[i] = first ? inc : xu[i] + inc;
+    } else if (i < nu + np) {
+        const int64_t j = i - nu;
+        const double inc = beta * z[j];
+        xp[j] = first ? inc : xp[j] + inc;
+    }
+}
+template <typename T>
+void launch_smoother_update(const T* w, const T* vv, const double* z, const double* dots, T* x_u, double* x_p,
+                            int64_t nu, int64_t np, bool first, hipStream_t s) {
+    hipLaunchKernelGGL(k_smoother_update<T>, dim3(nblocks(nu + np)), dim3(TPB), 0, s, w, vv, z, dots, x_u, x_p, nu, np,
+                       first ? 1 : 0);
+}
+template void launch_smoother_update<double>(const double*, const double*, const double*, const double*, double*,
+                                             double*, int64_t, int64_t, bool, hipStream_t);
+template void launch_smoother_update<float>(const float*, const float*, const double*, const double*, float*, double*,
+                                            int64_t, int64_t, bool, hipStream_t);
+
+// ---------------------------------------------------------------- transfers
+// 1D prolongation weights of the nested Q2 space: fine node f, coarse cell e = f/4,
+// r = f - 4e -> weights on coarse nodes 2e..2e+2.
+__device__ __forceinline__ void q2_prol_1d(int f, int ncoarse_cells, int& base, double w[3]) {
+    int e = f >> 2;
+    if (e >= ncoarse_cells) e = ncoarse_cells - 1;
+    const int r = f - 4 * e;
+    base = 2 * e;
+    switch (r) {
+        case 0: w[0] = 1; w[1] = 0; w[2] = 0; break;
+        case 1: w[0] = 0.375; w[1] = 0.75; w[2] = -0.125; break;
+        case 2: w[0] = 0; w[1] = 1; w[2] = 0; break;
+        case 3: w[0] = -0.125; w[1] = 0.75; w[2] = 0.375; break;
+        default: w[0] = 0; w[1] = 0; w[2] = 1; break;
+    }
+}
+__device__ __forceinline__ void q1_prol_1d(int f, int ncoarse_cells, int& base, double w[2]) {
+    int e = f >> 1;
+    if (e >= ncoarse_cells) e = ncoarse_cells - 1;
+    const int r = f - 2 * e;
+    base = e;
+    if (r == 0) { w[0] = 1; w[1] = 0; }
+    else if (r == 1) { w[0] = 0.5; w[1] = 0.5; }
+    else { w[0] = 0; w[1] = 1; }
+}
+// transpose: coarse Q2 node c -> fine nodes and weights (up to 5)
+__device__ __forceinline__ int q2_rest_1d(int c, int nfine_nodes, int f[5], double w[5]) {
+    int m = 0;
+    if ((c & 1) == 0) {
+        const int e = c >> 1;
+        const int fo[5] = {4 * e - 3, 4 * e - 1, 4 * e, 4 * e + 1, 4 * e + 3};
+        const double wo[5] = {-0.125, 0.375, 1.0, 0.375, -0.125};
+        for (int i = 0; i < 5; ++i)
+            if (fo[i] >= 0 && fo[i] < nfine_nodes) { f[m] = fo[i]; w[m] = wo[i]; ++m; }
+    } else {
+        const int e = c >> 1;
+        const int fo[3] = {4 * e + 1, 4 * e + 2, 4 * e + 3};
+        const double wo[3] = {0.75, 1.0, 0.75};
+        for (int i = 0; i < 3; ++i) { f[m] = fo[i]; w[m] = wo[i]; ++m; }
+    }
+    return m;
+}
+__device__ __forceinline__ int q1_rest_1d(int c, int nfine_nodes, int f[3], double w[3]) {
+    int m = 0;
+    const int fo[3] = {2 * c - 1, 2 * c, 2 * c + 1};
+    const double wo[3] = {0.5, 1.0, 0.5};
+    for (int i = 0; i < 3; ++i)
+        if (fo[i] >= 0 && fo[i] < nfine_nodes) { f[m] = fo[i]; w[m] = wo[i]; ++m; }
+    return m;
+}
+
+struct XferDims {
+    int dim;
+    int fv[3], cv[3];     // velocity node counts fine / coarse
+    int fp[3], cp[3];     // pressure node counts
+    int cc[3];            // coarse cells
+    int64_t fnv, cnv, fnp, cnp;
+};
+
+template <typename T>
+__global__ void k_restrict_u(XferDims x, const T* __restrict__ rf, T* __restrict__ rc, const uint8_t* __restrict__ cwall) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= x.cnv) return;
+    int c[3] = {0, 0, 0};
+    int64_t r = id;
+    for (int d = 0; d < x.dim; ++d) { c[d] = (int)(r % x.cv[d]); r /= x.cv[d]; }
+    int fi[3][5];
+    double wi[3][5];
+    int m[3] = {1, 1, 1};
+    fi[1][0] = fi[2][0] = 0;
+    wi[1][0] = wi[2][0] = 1.0;
+    for (int d = 0; d < x.dim; ++d) m[d] = q2_rest_1d(c[d], x.fv[d], fi[d], wi[d]);
+    const bool wall = cwall[id] != 0;
+    for (int comp = 0; comp < x.dim; ++comp) {
+        double acc = 0.0;
+        if (!wall) {
+            for (int k = 0; k < m[2]; ++k)
+                for (int j = 0; j < m[1]; ++j)
+                    for (int i = 0; i < m[0]; ++i) {
+                        const int64_t fn = fi[0][i] + (int64_t)x.fv[0] * (fi[1][j] + (int64_t)x.fv[1] * fi[2][k]);
+                        acc += wi[0][i] * wi[1][j] * wi[2][k] * (double)rf[comp * x.fnv + fn];
+                    }
+        }
+        rc[comp * x.cnv + id] = (T)acc;
+    }
+}
+__global__ void k_restrict_p(XferDims x, const double* __restrict__ rf, double* __restrict__ rc) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= x.cnp) return;
+    int c[3] = {0, 0, 0};
+    int64_t r = id;
+    for (int d = 0; d < x.dim; ++d) { c[d] = (int)(r % x.cp[d]); r /= x.cp[d]; }
+    int fi[3][3];
+    double wi[3][3];
+    int m[3] = {1, 1, 1};
+    fi[1][0] = fi[2][0] = 0;
+    wi[1][0] = wi[2][0] = 1.0;
+    for (int d = 0; d < x.dim; ++d) m[d] = q1_rest_1d(c[d], x.fp[d], fi[d], wi[d]);
+    double acc = 0.0;
+    for (int k = 0; k < m[2]; ++k)
+        for (int j = 0; j < m[1]; ++j)
+            for (int i = 0; i < m[0]; ++i) {
+                const int64_t fn = fi[0][i] + (int64_t)x.fp[0] * (fi[1][j] + (int64_t)x.fp[1] * fi[2][k]);
+                acc += wi[0][i] * wi[1][j] * wi[2][k] * rf[fn];
+            }
+    rc[id] = acc;
+}
+
+template <typename T>
+__global__ void k_prolong_u(XferDims x, const T* __restrict__ ec, T* __restrict__ xf, const uint8_t* __restrict__ fwall) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= x.fnv) return;
+    if (fwall[id]) return;
+    int f[3] = {0, 0, 0};
+    int64_t r = id;
+    for (int d = 0; d < x.dim; ++d) { f[d] = (int)(r % x.fv[d]); r /= x.fv[d]; }
+    int base[3] = {0, 0, 0};
+    double w[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
+    int m[3] = {1, 1, 1};
+    for (int d = 0; d < x.dim; ++d) { q2_prol_1d(f[d], x.cc[d], base[d], w[d]); m[d] = 3; }
+    for (int comp = 0; comp < x.dim; ++comp) {
+        double acc = 0.0;
+        for (int k = 0; k < m[2]; ++k)
+            for (int j = 0; j < m[1]; ++j) {
+                const double wjk = w[1][j] * w[2][k];
+                if (wjk == 0.0) continue;
+                for (int i = 0; i < m[0]; ++i) {
+                    const double ww = w[0][i] * wjk;
+                    if (ww == 0.0) continue;
+                    const int64_t cn = (base[0] + i) + (int64_t)x.cv[0] * ((base[1] + j) + (int64_t)x.cv[1] * (base[2] + k));
+                    acc += ww * (double)ec[comp * x.cnv + cn];
+                }
+            }
+        xf[comp * x.fnv + id] += (T)acc;
+    }
+}
+__global__ void k_prolong_p(XferDims x, const double* __restrict__ ec, double* __restrict__ xf) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= x.fnp) return;
+    int f[3] = {0, 0, 0};
+    int64_t r = id;
+    for (int d = 0; d < x.dim; ++d) { f[d] = (int)(r % x.fp[d]); r /= x.fp[d]; }
+    int base[3] = {0, 0, 0};
+    double w[3][2] = {{1, 0}, {1, 0}, {1, 0}};
+    int m[3] = {1, 1, 1};
+    for (int d = 0; d < x.dim; ++d) { q1_prol_1d(f[d], x.cc[d], base[d], w[d]); m[d] = 2; }
+    double acc = 0.0;
+    for (int k = 0; k < m[2]; ++k)
+        for (int j = 0; j < m[1]; ++j)
+            for (int i = 0; i < m[0]; ++i) {
+                const double ww = w[0][i] * w[1][j] * w[2][k];
+                if (ww == 0.0) continue;
+                const int64_t cn = (base[0] + i) + (int64_t)x.cp[0] * ((base[1] + j) + (int64_t)x.cp[1] * (base[2] + k));
+                acc += ww * ec[cn];
+            }
+    xf[id] += acc;
+}
+
+static XferDims xdims(const Level& fine, const Level& coarse) {
+    XferDims x;
+    x.dim = fine.dim;
+    for (int d = 0; d < 3; ++d) {
+        x.fv[d] = fine.vnodes[d];
+        x.cv[d] = coarse.vnodes[d];
+        x.fp[d] = fine.pnodes[d];
+        x.cp[d] = coarse.pnodes[d];
+        x.cc[d] = coarse.cells[d];
+    }
+    x.fnv = fine.nvn;
+    x.cnv = coarse.nvn;
+    x.fnp = fine.np;
+    x.cnp = coarse.np;
+    return x;
+}
+
+// wall masks live on the device as uint8 per node (set up by the host)
+
+template <typename T>
+void launch_restrict(const Level& fine, const Level& coarse, const T* rf_u, const double* rf_p, T* rc_u, double* rc_p,
+                     hipStream_t s) {
+    const XferDims x = xdims(fine, coarse);
+    hipLaunchKernelGGL(k_restrict_u<T>, dim3(nblocks(x.cnv)), dim3(TPB), 0, s, x, rf_u, rc_u, level_wall_mask(coarse));
+    hipLaunchKernelGGL(k_restrict_p, dim3(nblocks(x.cnp)), dim3(TPB), 0, s, x, rf_p, rc_p);
+}
+template <typename T>
+void launch_prolongate_add(const Level& fine, const Level& coarse, const T* ec_u, const double* ec_p, T* xf_u,
+                           double* xf_p, hipStream_t s) {
+    const XferDims x = xdims(fine, coarse);
+    hipLaunchKernelGGL(k_prolong_u<T>, dim3(nblocks(x.fnv)), dim3(TPB), 0, s, x, ec_u, xf_u, level_wall_mask(fine));
+    hipLaunchKernelGGL(k_prolong_p, dim3(nblocks(x.fnp)), dim3(TPB), 0, s, x, ec_p, xf_p);
+}
+template void launch_restrict<double>(const Level&, const Level&, const double*, const double*, double*, double*,
+                                      hipStream_t);
+template void launch_restrict<float>(const Level&, const Level&, const float*, const double*, float*, double*,
+                                     hipStream_t);
+template void launch_prolongate_add<double>(const Level&, const Level&, const double*, const double*, double*,
+                                            double*, hipStream_t);
+template void launch_prolongate_add<float>(const Level&, const Level&, const float*, const double*, float*, double*,
+                                           hipStream_t);
+
+// ---------------------------------------------------------------- coarse level
+// One thread per (cell of one colour, local velocity dof): the element-matrix row
+// of A (mass + viscous) and the matching column of B^T / row of B are added to the
+// dense matrix restricted to free dofs (dof2row[dof] < 0 for wall dofs).
+__global__ void k_coarse_assemble(int dim, int64_t cbeg, int64_t cend, int64_t nc, int64_t nvn, int64_t plane,
+                                  const int* __restrict__ vmap, const int* __restrict__ pmap,
+                                  const double* __restrict__ K, const double* __restrict__ cv,
+                                  const int* __restrict__ vrow, int64_t nfree_u, double* __restrict__ M, int64_t n) {
+    const int NLOC = dim == 3 ? 27 : 9, NPL = dim == 3 ? 8 : 4, NT = dim == 3 ? 9 : 3;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cell = cbeg + id / (dim * NLOC);
+    if (cell >= cend) return;
+    const int loc = (int)(id % (dim * NLOC));
+    const int a = loc / NLOC, nrow = loc % NLOC;
+    const int row = vrow[a * nvn + vmap[cell * NLOC + nrow]];
+    if (row < 0) return;
+    const int ni[3] = {nrow % 3, (nrow / 3) % 3, nrow / 9};
+    for (int b = 0; b < dim; ++b)
+        for (int m = 0; m < NLOC; ++m) {
+            const int col = vrow[b * nvn + vmap[cell * NLOC + m]];
+            if (col < 0) continue;
+            const int mi[3] = {m % 3, (m / 3) % 3, m / 9};
+            double acc = 0.0;
+            for (int q = 0; q < NLOC; ++q) {
+                const int qi[3] = {q % 3, (q / 3) % 3, q / 9};
+                const int64_t off = ((int64_t)qi[0] * nc + cell) * NT + q / 3;
+                double phin = 1.0, phim = 1.0, gn[3], gm[3];
+                for (int d = 0; d < dim; ++d) {
+                    phin *= dS(qi[d], ni[d]);
+                    phim *= dS(qi[d], mi[d]);
+                }
+                for (int e = 0; e < dim; ++e) {
+                    double vn = 1.0, vm = 1.0;
+                    for (int d = 0; d < dim; ++d) {
+                        vn *= (d == e) ? dD(qi[d], ni[d]) : dS(qi[d], ni[d]);
+                        vm *= (d == e) ? dD(qi[d], mi[d]) : dS(qi[d], mi[d]);
+                    }
+                    gn[e] = vn;
+                    gm[e] = vm;
+                }
+                double Gn[3] = {0, 0, 0}, Gm[3] = {0, 0, 0};
+                for (int c = 0; c < dim; ++c)
+                    for (int e = 0; e < dim; ++e) {
+                        const double k = K[(e * dim + c) * plane + off];
+                        Gn[c] += k * gn[e];
+                        Gm[c] += k * gm[e];
+                    }
+                const double cvisc = cv[off], cmass = cv[plane + off];
+                double v = 0.5 * cvisc * Gn[b] * Gm[a];
+                if (a == b) {
+                    double dot = 0.0;
+                    for (int c = 0; c < dim; ++c) dot += Gn[c] * Gm[c];
+                    v += cmass * phin * phim + 0.5 * cvisc * dot;
+                }
+                acc += v;
+            }
+            M[(int64_t)row * n + col] += acc;
+        }
+    // B^T column / B row entries for the pressure dofs of this cell
+    for (int kk = 0; kk < NPL; ++kk) {
+        const int ki[3] = {kk & 1, (kk >> 1) & 1, (kk >> 2) & 1};
+        double acc = 0.0;
+        for (int q = 0; q < NLOC; ++q) {
+            const int qi[3] = {q % 3, (q / 3) % 3, q / 9};
+            const int64_t off = ((int64_t)qi[0] * nc + cell) * NT + q / 3;
+            double psi = 1.0, gn[3];
+            for (int d = 0; d < dim; ++d) psi *= dL(qi[d], ki[d]);
+            for (int e = 0; e < dim; ++e) {
+                double vn = 1.0;
+                for (int d = 0; d < dim; ++d) vn *= (d == e) ? dD(qi[d], ni[d]) : dS(qi[d], ni[d]);
+                gn[e] = vn;
+            }
+            double G = 0.0;
+            for (int e = 0; e < dim; ++e) G += K[(e * dim + a) * plane + off] * gn[e];
+            acc += psi * G;
+        }
+        const int64_t prow = nfree_u + pmap[cell * NPL + kk];
+        M[(int64_t)row * n + prow] += acc;
+        M[prow * n + row] += acc;
+    }
+}
+
+void launch_coarse_assemble_impl(const Level& L, const double* K, const double* cv, const int* vrow,
+                                 int64_t nfree_u, double* M, int64_t n, hipStream_t s) {
+    const int nloc = L.dim == 3 ? 27 : 9;
+    for (int c = 0; c < L.ncolors; ++c) {
+        const int64_t cnt = (L.color_off[c + 1] - L.color_off[c]) * L.dim * nloc;
+        if (cnt == 0) continue;
+        hipLaunchKernelGGL(k_coarse_assemble, dim3(nblocks(cnt, 64)), dim3(64), 0, s, L.dim, L.color_off[c],
+                           L.color_off[c + 1], L.nc, L.nvn, L.plane(), L.d_vmap, L.d_pmap, K, cv, vrow, nfree_u, M, n);
+    }
+}
+
+// Gauss-Jordan inversion with partial pivoting, one pivot step per three launches.
+__global__ void k_gj_pivot(const double* __restrict__ M, int64_t n, int64_t k, int* __restrict__ piv,
+                           int* __restrict__ flag) {
+    __shared__ double bv[1024];
+    __shared__ int bi[1024];
+    double best = -1.0;
+    int bidx = (int)k;
+    for (int64_t i = k + threadIdx.x; i < n; i += blockDim.x) {
+        const double v = fabs(M[i * n + k]);
+        if (v > best) { best = v; bidx = (int)i; }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = bidx;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            const double o = bv[threadIdx.x + st];
+            const int oi = bi[threadIdx.x + st];
+            if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+                bv[threadIdx.x] = o;
+                bi[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        piv[k] = bi[0];
+        if (!(bv[0] > 0.0)) flag[0] = 1;
+    }
+}
+__global__ void k_gj_swap_scale(double* __restrict__ M, int64_t n, int64_t k, const int* __restrict__ piv,
+                                double* __restrict__ colk) {
+    const int64_t p = piv[k];
+    // swap rows k and p
+    for (int64_t j = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        if (p != k) {
+            const double t = M[k * n + j];
+            M[k * n + j] = M[p * n + j];
+            M[p * n + j] = t;
+        }
+    }
+}
+__global__ void k_gj_save_col(double* __restrict__ M, int64_t n, int64_t k, double* __restrict__ colk) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) colk[i] = M[i * n + k];
+}
+__global__ void k_gj_scale_row(double* __restrict__ M, int64_t n, int64_t k, const double* __restrict__ colk) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double pv = colk[k];
+    if (j == k) M[k * n + k] = 1.0 / pv;
+    else M[k * n + j] = M[k * n + j] / pv;
+}
+__global__ void k_gj_eliminate(double* __restrict__ M, int64_t n, int64_t k, const double* __restrict__ colk) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n * n) return;
+    const int64_t i = id / n, j = id - (id / n) * n;
+    if (i == k) return;
+    const double f = colk[i];
+    if (j == k) M[i * n + k] = -f * M[k * n + k];
+    else M[i * n + j] -= f * M[k * n + j];
+}
+__global__ void k_gj_colswap(double* __restrict__ M, int64_t n, int64_t k, const int* __restrict__ piv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = piv[k];
+    if (i >= n || p == k) return;
+    const double t = M[i * n + k];
+    M[i * n + k] = M[i * n + p];
+    M[i * n + p] = t;
+}
+
+void launch_gj(double* M, int64_t n, int* piv, double* colk, int* flag, hipStream_t s) {
+    for (int64_t k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, M, n, k, piv, flag);
+        hipLaunchKernelGGL(k_gj_swap_scale, dim3(nblocks(n)), dim3(TPB), 0, s, M, n, k, piv, colk);
+        hipLaunchKernelGGL(k_gj_save_col, dim3(nblocks(n)), dim3(TPB), 0, s, M, n, k, colk);
+        hipLaunchKernelGGL(k_gj_scale_row, dim3(nblocks(n)), dim3(TPB), 0, s, M, n, k, colk);
+        hipLaunchKernelGGL(k_gj_eliminate, dim3(nblocks(n * n)), dim3(TPB), 0, s, M, n, k, colk);
+    }
+    for (int64_t k = n - 1; k >= 0; --k)
+        hipLaunchKernelGGL(k_gj_colswap, dim3(nblocks(n)), dim3(TPB), 0, s, M, n, k, piv);
+}
+
+// coarse apply: gather free dofs, dense GEMV with the inverse, scatter
+template <typename T>
+__global__ void k_coarse_gather(const int* __restrict__ uidx, int64_t nfu, int64_t np, const T* __restrict__ fu,
+                                const double* __restrict__ fp, T* __restrict__ xin) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nfu) xin[i] = fu[uidx[i]];
+    else if (i < nfu + np) xin[i] = (T)fp[i - nfu];
+}
+template <typename T>
+__global__ void k_gemv(const T* __restrict__ A, const T* __restrict__ x, T* __restrict__ y, int64_t n) {
+    // one 64-wide wavefront per row
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    double acc = 0.0;
+    for (int64_t j = lane; j < n; j += 64) acc += (double)A[row * n + j] * (double)x[j];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) y[row] = (T)acc;
+}
+template <typename T>
+__global__ void k_coarse_scatter(const int* __restrict__ uidx, int64_t nfu, int64_t np, const T* __restrict__ xout,
+                                 T* __restrict__ xu, double* __restrict__ xp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nfu) xu[uidx[i]] = xout[i];
+    else if (i < nfu + np) xp[i - nfu] = (double)xout[i];
+}
+
+template <typename T>
+void launch_coarse_apply_impl(const Coarse& C, const Level& L, const T* A, T* xin, T* xout, const T* f_u,
+                              const double* f_p, T* x_u, double* x_p, hipStream_t s) {
+    launch_fill<T>(x_u, T(0), L.nv, s);
+    hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblocks(C.n)), dim3(TPB), 0, s, C.d_uidx, C.nfree_u, L.np, f_u, f_p,
+                       xin);
+    hipLaunchKernelGGL(k_gemv<T>, dim3((unsigned)((C.n + 3) / 4)), dim3(256), 0, s, A, xin, xout, C.n);
+    hipLaunchKernelGGL(k_coarse_scatter<T>, dim3(nblocks(C.n)), dim3(TPB), 0, s, C.d_uidx, C.nfree_u, L.np, xout, x_u,
+                       x_p);
+}
+template <typename T>
+void launch_coarse_apply(const Coarse& C, const Level& L, const T* f_u, const double* f_p, T* x_u, double* x_p,
+                         hipStream_t s) {
+    if constexpr (sizeof(T) == 8)
+        launch_coarse_apply_impl<T>(C, L, C.d_inv64, C.d_xin64, C.d_xout64, f_u, f_p, x_u, x_p, s);
+    else
+        launch_coarse_apply_impl<T>(C, L, C.d_inv32, C.d_xin32, C.d_xout32, f_u, f_p, x_u, x_p, s);
+}
+template void launch_coarse_apply<double>(const Coarse&, const Level&, const double*, const double*, double*, double*,
+                                          hipStream_t);
+template void launch_coarse_apply<float>(const Coarse&, const Level&, const float*, const double*, float*, double*,
+                                         hipStream_t);
+
+// ---------------------------------------------------------------- Krylov helpers (FP64)
+__global__ void k_multi_dot_partial(const double* __restrict__ V, int64_t ldv, const double* __restrict__ w, int64_t n,
+                                    double* __restrict__ part) {
+    __shared__ double sh[TPB];
+    const int j = blockIdx.y;
+    const double* vj = V + (int64_t)j * ldv;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += vj[i] * w[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = s;
+}
+__global__ void k_multi_dot_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    __shared__ double sh[TPB];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[(int64_t)j * nb + i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[j] = s;
+}
+void launch_multi_dot(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* partials, double* out,
+                      hipStream_t s) {
+    const unsigned nb = 256;
+    hipLaunchKernelGGL(k_multi_dot_partial, dim3(nb, m), dim3(TPB), 0, s, V, ldv, w, n, partials);
+    hipLaunchKernelGGL(k_multi_dot_final, dim3(m), dim3(TPB), 0, s, partials, (int)nb, out);
+}
+__global__ void k_multi_axpy(const double* __restrict__ V, int64_t ldv, int m, const double* __restrict__ coef,
+                             double sign, double* __restrict__ w, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int j = 0; j < m; ++j) acc += coef[j] * V[(int64_t)j * ldv + i];
+    w[i] += sign * acc;
+}
+void launch_multi_axpy(const double* V, int64_t ldv, int m, const double* coef_dev, double sign, double* w, int64_t n,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_multi_axpy, dim3(nblocks(n)), dim3(TPB), 0, s, V, ldv, m, coef_dev, sign, w, n);
+}
+__global__ void k_axpy(double a, const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += a * x[i];
+}
+void launch_axpy_host(double a, const double* x, double* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(TPB), 0, s, a, x, y, n);
+}
+__global__ void k_scale(double a, const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i];
+}
+void launch_scale_host(double a, const double* x, double* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale, dim3(nblocks(n)), dim3(TPB), 0, s, a, x, y, n);
+}
+__global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ c, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = a[i] * b[i];
+}
+void launch_mul(const double* a, const double* b, double* c, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_mul, dim3(nblocks(n)), dim3(TPB), 0, s, a, b, c, n);
+}
+__global__ void k_vsqrt(const double* __restrict__ a, double* __restrict__ c, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = sqrt(a[i]);
+}
+void launch_vsqrt(const double* a, double* c, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_vsqrt, dim3(nblocks(n)), dim3(TPB), 0, s, a, c, n);
+}
+// v_i = ((7919 i) mod 1021)/1021 - 1/2 on free dofs, 0 on wall dofs
+__global__ void k_lanczos_start(int64_t nv, int64_t nvn, const uint8_t* __restrict__ wall, double* __restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    const int64_t node = i % nvn;
+    v[i] = wall[node] ? 0.0 : (double)((7919 * i) % 1021) / 1021.0 - 0.5;
+}
+void launch_lanczos_start(const Level& L, double* v, hipStream_t s) {
+    hipLaunchKernelGGL(k_lanczos_start, dim3(nblocks(L.nv)), dim3(TPB), 0, s, L.nv, L.nvn, level_wall_mask(L), v);
+}
+__global__ void k_nonfinite(const double* __restrict__ x, int64_t n, int* flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(x[i])) flag[0] = 1;
+}
+void launch_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_nonfinite, dim3(nblocks(n)), dim3(TPB), 0, s, x, n, flag);
+}
+__global__ void k_sub_into(const double* __restrict__ g, const double* __restrict__ mx, double* __restrict__ r,
+                           int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) r[i] = g[i] - mx[i];
+}
+void launch_sub_into(const double* g, const double* mx, double* r, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub_into, dim3(nblocks(n)), dim3(TPB), 0, s, g, mx, r, n);
+}
+__global__ void k_recip(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = 1.0 / a[i];
+}
+void launch_recip(const double* a, double* b, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_recip, dim3(nblocks(n)), dim3(TPB), 0, s, a, b, n);
+}
+
+}  // namespace fsi
