@@ -1,0 +1,254 @@
+"""Benchmark of the generalized-Stokes hot path on one MI355X.
+
+Workload (default): the 128^3 warped box with log-uniform viscosity per 8^3
+block (contrast up to 1e6), Q2-Q1, 6 levels down to 4^3, 50.9M velocity +
+2.1M pressure dofs.
+
+One timed step = one pass of the whole hot path on that workload:
+  * R applications of the FP64 matrix-free operator A (the dominant kernel;
+    every colour launch timed with HIP events on the library stream);
+  * geometry + coefficient upload and preconditioner setup (ALE Jacobians,
+    coefficient packing, diag(A), diag(B diag(A)^-1 B^T), Lanczos bounds,
+    dense coarse inverse, V-cycle graphs);
+  * a plain FP64 solve (FP64 V-cycle, per-launch) and the mixed-precision
+    graph-captured solve (FP32 V-cycle, FP64 FGMRES / residuals / Schur block),
+    both from a zero guess to relative residual 1e-8.
+Inputs are resident in HBM before the timed region.  `value` is the FP64
+vmult throughput N_vel / t_apply in GDoF/s; the solve times, their ratio
+and the mixed-vs-FP64 velocity difference are reported beside it.
+
+Prints one JSON line (rank 0, N = 1 only: this build targets one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cell_kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_2305_08986_amd", "csrc", "kernels_cell.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes_per_cell(dim: int, elem: int) -> int:
+    """Bytes one cell of the A-apply must move: per quadrature point 9 (4) values of
+    det(J) w J^-1 plus 2 coefficients, the unique velocity dofs of the cell read
+    and written once (2^dim nodes x dim components), and the int32 cell->node map."""
+    q = 3 ** dim
+    geo = (dim * dim + 2) * q * elem
+    vec = 2 * (2 ** dim) * dim * elem
+    cmap = 4 * q
+    return geo + vec + cmap
+
+
+def load_counter_profile(workload: str):
+    """HBM traffic per colour launch from the committed rocprofv3 counter summary."""
+    path = os.path.join(ROOT, "profiles", f"counters_cell3d_A_fp64_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha256_16") != cell_kernel_source_hash():
+        return None
+    return d
+
+
+def cpu_baseline(seconds: float = 12.0):
+    """The CPU oracle's A-apply (CSR SpMV, scipy) timed on a bounded sample."""
+    import numpy as np
+    from oracle import fem
+    from paper_2305_08986_amd import workloads as W
+
+    wl = W.make_workload("T3_16", levels=[2])
+    box = fem.level_box(wl.mesh, 2)
+    ref = fem.Reference(3)
+    t0 = time.perf_counter()
+    J = fem.jacobians_q1(box, wl.disp, ref)
+    op = fem.assemble(box, J, wl.c_mass[2], wl.eta[2], ref)
+    t_asm = time.perf_counter() - t0
+    u = np.random.default_rng(0).uniform(-1, 1, box.n_vel)
+    reps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        op.A @ u
+        reps += 1
+    dt = time.perf_counter() - t0
+    gdofs = box.n_vel * reps / dt / 1e9
+    return {
+        "value": gdofs, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+        "sample": (f"FP64 CSR SpMV y = A u (scipy, single thread) of the oracle-assembled Q2 velocity block on a "
+                   f"16^3 warped box with the same viscosity law (n_vel={box.n_vel}, nnz={op.A.nnz}); "
+                   f"{reps} products in {dt:.1f} s; assembly {t_asm:.1f} s not included"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C3")
+    ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs the hot path on one GPU only (no multi-GPU path); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2305_08986_amd import fsi
+    from paper_2305_08986_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    name = args.workload
+    _log(f"[bench] generating workload {name}")
+    wl = W.make_workload(name)
+    mesh = wl.mesh
+    ctx = fsi.Context.from_mesh(mesh)
+    J = ctx.n_levels - 1
+    sz = ctx.sizes(J)
+    nv, npr, nc = sz["n_vel"], sz["n_p"], sz["n_cells"]
+    # inputs resident in HBM before timing
+    d_disp = torch.from_numpy(wl.disp).cuda()
+    d_cm = [torch.from_numpy(a).cuda() for a in wl.c_mass]
+    d_eta = [torch.from_numpy(a).cuda() for a in wl.eta]
+    gu = torch.from_numpy(wl.g_u).cuda()
+    gp = torch.from_numpy(wl.g_p).cuda()
+    del wl
+    torch.cuda.synchronize()
+
+    def do_setup():
+        ctx.set_displacement(d_disp)
+        for j in range(ctx.n_levels):
+            ctx.set_coefficients(j, d_cm[j], d_eta[j])
+        ctx.setup()
+
+    _log("[bench] setup + autotune")
+    do_setup()
+    ctx.autotune()
+    tuning = {f"L{j}": [ctx.tuning(j, 0)[0], ctx.tuning(j, 1)[0]] for j in range(ctx.n_levels)}
+
+    def one_step(record):
+        t0 = time.perf_counter()
+        k_us, op_us = ctx.time_operator(J, precision=0, mode=1, reps=args.apply_reps)
+        k32_us, op32_us = ctx.time_operator(J, precision=1, mode=1, reps=max(4, args.apply_reps // 2))
+        ks_us, ops_us = ctx.time_operator(J, precision=0, mode=7, reps=max(4, args.apply_reps // 2))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        do_setup()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ctx.set_mg_params(precision=0, use_graph=0)
+        u64, p64, i64 = ctx.solve(gu, gp, rtol=args.rtol, max_iter=300, restart=100)
+        ctx.set_mg_params(precision=1, use_graph=1)
+        umx, pmx, imx = ctx.solve(gu, gp, rtol=args.rtol, max_iter=300, restart=100)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        du = float(torch.linalg.vector_norm(umx - u64) / torch.linalg.vector_norm(u64))
+        rec = dict(k_us=k_us, op_us=op_us, k32_us=k32_us, op32_us=op32_us, ks_us=ks_us, ops_us=ops_us,
+                   apply_s=t1 - t0, setup_s=t2 - t1, solve_s=t3 - t2, fp64=i64, mixed=imx, du=du,
+                   step_s=t3 - t0)
+        record.append(rec)
+        _log(f"[bench] step: A-apply {op_us:.0f} us (colour launch {k_us:.1f} us), setup {1e3*(t2-t1):.0f} ms, "
+             f"fp64 solve {i64['time_ms']:.0f} ms/{i64['iters']} it ({i64['status']}), "
+             f"mixed {imx['time_ms']:.0f} ms/{imx['iters']} it ({imx['status']}), du {du:.2e}")
+
+    warm = []
+    for _ in range(args.warmup):
+        one_step(warm)
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step(recs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    def mean(key, sub=None):
+        vals = [r[key][sub] if sub else r[key] for r in recs]
+        return float(np.mean(vals))
+
+    op_us = mean("op_us")
+    k_us = mean("k_us")
+    gdofs = nv / (op_us * 1e-6) / 1e9
+    ncol = 8 if mesh.dim == 3 else 4
+    cells_per_launch = nc / ncol
+    bpc = algorithmic_bytes_per_cell(mesh.dim, 8)
+    achieved = bpc * cells_per_launch / (k_us * 1e-6) / 1e9
+    prof = load_counter_profile(name)
+    traffic = None
+    if prof is not None:
+        traffic = prof["hbm_bytes_per_launch"]
+    fp64_ms = mean("fp64", "time_ms")
+    mx_ms = mean("mixed", "time_ms")
+    out = {
+        "metric": "Q2 matrix-free vmult GDoF/s; Stokes solve time to rel.res 1e-8, FP64 vs mixed",
+        "value": round(gdofs, 4),
+        "unit": "GDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{name}: {W.CONFIGS[name]['desc']}, Q2-Q1, {ctx.n_levels} levels",
+            "cells": nc, "n_vel": nv, "n_p": npr, "rtol": args.rtol,
+            "mg": "FGMRES(100) + 1 V-cycle, k_A=4, m=2, k_S=n_S=1",
+        },
+        "apply": {
+            "fp64_A_gdofs": round(gdofs, 4),
+            "fp64_A_us": round(op_us, 1),
+            "fp64_A_colour_launch_us": round(k_us, 2),
+            "fp32_A_gdofs": round(nv / (mean("op32_us") * 1e-6) / 1e9, 4),
+            "fp64_stokes_gdofs": round((nv + npr) / (mean("ops_us") * 1e-6) / 1e9, 4),
+            "algorithmic_bytes_per_cell": bpc,
+        },
+        "solve": {
+            "fp64_ms": round(fp64_ms, 1), "fp64_iters": recs[-1]["fp64"]["iters"],
+            "fp64_rel_res": recs[-1]["fp64"]["rel_res"], "fp64_status": recs[-1]["fp64"]["status"],
+            "mixed_graph_ms": round(mx_ms, 1), "mixed_iters": recs[-1]["mixed"]["iters"],
+            "mixed_rel_res": recs[-1]["mixed"]["rel_res"], "mixed_status": recs[-1]["mixed"]["status"],
+            "speedup_mixed_vs_fp64": round(fp64_ms / mx_ms, 3),
+            "velocity_rel_diff_mixed_vs_fp64": recs[-1]["du"],
+            "setup_ms": round(1e3 * mean("setup_s"), 1),
+        },
+        "tuning_variant": tuning,
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "cell3d<double, A> (one colour launch)" if mesh.dim == 3 else "cell2d<double, A>",
+        },
+    }
+    if not args.no_cpu_baseline:
+        _log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -84,8 +84,8 @@ typedef struct {
     double cheb_upper;
     double cheb_ratio;
     int n_eig;
-    int precision;           /* FSI_PREC_FP64 or FSI_PREC_MIXED */
-    int use_graph;           /* capture the V-cycle in a HIP graph */
+    int precision;           /* FSI_PREC_FP64 or FSI_PREC_MIXED (switching needs no new setup) */
+    int use_graph;           /* launch the V-cycle as a captured HIP graph (switching needs no new setup) */
 } fsi_mg_params;
 
 typedef struct {
@@ -144,11 +144,14 @@ fsi_status fsi_set_displacement(fsi_ctx* ctx, const double* disp);
  * finite (synchronises). */
 fsi_status fsi_set_coefficients(fsi_ctx* ctx, int level, const double* c_mass, const double* eta);
 
+/* Changing k_A, m, n_cycles or the Chebyshev/Lanczos settings requires a new
+ * fsi_setup; precision and use_graph may change at any time.  Errors:
+ * FSI_ERR_ARG (only k_S = n_S = 1 are implemented). */
 fsi_status fsi_set_mg_params(fsi_ctx* ctx, const fsi_mg_params* p);
 
 /* Setup of the preconditioner on every level: diag(A_j), diag(B_j diag(A_j)^{-1}
  * B_j^T) (Sec. 4), Lanczos bounds, Chebyshev coefficients, the dense inverse of
- * the coarsest block matrix M_0, FP32 copies and (if enabled) the V-cycle graph.
+ * the coarsest block matrix M_0, FP32 copies and the V-cycle graphs of both precisions.
  * Synchronises.  Errors: FSI_ERR_STATE if a level lacks geometry or
  * coefficients, FSI_ERR_BREAKDOWN for a singular coarse matrix. */
 fsi_status fsi_setup(fsi_ctx* ctx);
@@ -192,6 +195,15 @@ fsi_status fsi_solve(fsi_ctx* ctx, const double* g_u, const double* g_p, double*
  * Synchronises; results are reported through fsi_get_tuning. */
 fsi_status fsi_autotune(fsi_ctx* ctx);
 fsi_status fsi_get_tuning(const fsi_ctx* ctx, int level, int precision, int* variant, double* best_us);
+
+/* Measurement support: runs `reps` applications of the level operator
+ * (mode bits 1 = A, 2 = B^T, 4 = B; 7 = fused Stokes) in the given precision on
+ * internal work vectors, timing every colour launch of the cell kernel with
+ * HIP events on the context's stream.  kernel_us = mean duration of one
+ * colour launch, op_us = mean duration of the whole operator (output clear,
+ * all colours, wall rows).  Synchronises.  Errors: FSI_ERR_ARG, FSI_ERR_STATE. */
+fsi_status fsi_time_operator(fsi_ctx* ctx, int level, int precision, int mode, int reps,
+                             double* kernel_us, double* op_us);
 
 #ifdef __cplusplus
 }

@@ -344,19 +344,20 @@ static fsi_status capture_graphs(Context* ctx) {
             ctx->graph_valid[pi] = false;
         }
     }
-    if (!ctx->prm.use_graph) return FSI_OK;
-    const int pi = ctx->prm.precision == FSI_PREC_MIXED ? 1 : 0;
+    // one graph per precision, so switching precision needs no new setup
     hipStream_t cs;
     FSI_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipGraph_t g;
-    FSI_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    if (pi == 1) vcycle_body<float>(ctx, cs);
-    else vcycle_body<double>(ctx, cs);
-    FSI_HIP_TRY(hipStreamEndCapture(cs, &g));
-    FSI_HIP_TRY(hipGraphInstantiate(&ctx->graph[pi], g, nullptr, nullptr, 0));
-    hipGraphDestroy(g);
+    for (int pi = 0; pi < 2; ++pi) {
+        hipGraph_t g;
+        FSI_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        if (pi == 1) vcycle_body<float>(ctx, cs);
+        else vcycle_body<double>(ctx, cs);
+        FSI_HIP_TRY(hipStreamEndCapture(cs, &g));
+        FSI_HIP_TRY(hipGraphInstantiate(&ctx->graph[pi], g, nullptr, nullptr, 0));
+        hipGraphDestroy(g);
+        ctx->graph_valid[pi] = true;
+    }
     hipStreamDestroy(cs);
-    ctx->graph_valid[pi] = true;
     return FSI_OK;
 }
 
@@ -728,8 +729,12 @@ fsi_status fsi_set_mg_params(fsi_ctx* h, const fsi_mg_params* p) {
     if (p->k_A < 1 || p->m < 0 || p->n_cycles < 1 || p->k_S != 1 || p->n_S != 1 || !(p->cheb_upper > 0) ||
         !(p->cheb_ratio > 1) || p->n_eig < 1 || (p->precision != FSI_PREC_FP64 && p->precision != FSI_PREC_MIXED))
         return fail(ctx, FSI_ERR_ARG, "invalid multigrid parameters (only k_S = n_S = 1 are implemented)");
+    const fsi_mg_params& o = ctx->prm;
+    // precision and graph use select among already prepared paths; the rest changes the setup
+    const bool same = o.k_A == p->k_A && o.m == p->m && o.n_cycles == p->n_cycles && o.cheb_upper == p->cheb_upper &&
+                      o.cheb_ratio == p->cheb_ratio && o.n_eig == p->n_eig;
     ctx->prm = *p;
-    invalidate(ctx);
+    if (!same) invalidate(ctx);
     return FSI_OK;
 }
 
@@ -1076,6 +1081,60 @@ fsi_status fsi_autotune(fsi_ctx* h) {
     hipEventDestroy(e1);
     // captured graphs hold the old launch shapes
     if (ctx->setup_done) TRY(capture_graphs(ctx));
+    return FSI_OK;
+}
+
+fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int reps, double* kernel_us,
+                             double* op_us) {
+    if (!h || !kernel_us || !op_us || reps < 1 || (precision != 0 && precision != 1) || mode < 1 || mode > 7)
+        return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    TRY(apply_check(ctx, level, (mode & OP_A) != 0));
+    TRY(alloc_work<double>(ctx));
+    TRY(alloc_work<float>(ctx));
+    const Level& L = ctx->lv[level];
+    hipStream_t s = ctx->stream;
+    const int ncol = L.ncolors;
+    std::vector<hipEvent_t> ev((size_t)2 * ncol + 2);
+    for (auto& e : ev) FSI_HIP_TRY(hipEventCreate(&e));
+    const int var = variant_of(ctx, precision, level);
+    double ksum = 0.0, osum = 0.0;
+    for (int r = 0; r < reps; ++r) {
+        FSI_HIP_TRY(hipEventRecord(ev[0], s));
+        if (precision == 0) {
+            LevelWork<double>& W = ctx->w64[level];
+            if (mode & (OP_A | OP_BT)) launch_fill<double>(W.r_u, 0.0, L.nv, s);
+            if (mode & OP_B) launch_fill<double>(W.r_p, 0.0, L.np, s);
+            for (int c = 0; c < ncol; ++c) {
+                FSI_HIP_TRY(hipEventRecord(ev[1 + 2 * c], s));
+                launch_cell<double>(L, mode, var, c, L.d_K64, L.d_cv64, W.x_u, W.x_p, W.r_u, W.r_p, s);
+                FSI_HIP_TRY(hipEventRecord(ev[2 + 2 * c], s));
+            }
+            if (mode & OP_A) launch_dirichlet_copy<double>(L, W.x_u, W.r_u, s);
+        } else {
+            LevelWork<float>& W = ctx->w32[level];
+            if (mode & (OP_A | OP_BT)) launch_fill<float>(W.r_u, 0.0f, L.nv, s);
+            if (mode & OP_B) launch_fill<double>(W.r_p, 0.0, L.np, s);
+            for (int c = 0; c < ncol; ++c) {
+                FSI_HIP_TRY(hipEventRecord(ev[1 + 2 * c], s));
+                launch_cell<float>(L, mode, var, c, L.d_K32, L.d_cv32, W.x_u, W.x_p, W.r_u, W.r_p, s);
+                FSI_HIP_TRY(hipEventRecord(ev[2 + 2 * c], s));
+            }
+            if (mode & OP_A) launch_dirichlet_copy<float>(L, W.x_u, W.r_u, s);
+        }
+        FSI_HIP_TRY(hipEventRecord(ev[2 * ncol + 1], s));
+        FSI_HIP_TRY(hipEventSynchronize(ev[2 * ncol + 1]));
+        float ms;
+        for (int c = 0; c < ncol; ++c) {
+            FSI_HIP_TRY(hipEventElapsedTime(&ms, ev[1 + 2 * c], ev[2 + 2 * c]));
+            ksum += ms;
+        }
+        FSI_HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[2 * ncol + 1]));
+        osum += ms;
+    }
+    for (auto& e : ev) hipEventDestroy(e);
+    *kernel_us = 1000.0 * ksum / ((double)reps * ncol);
+    *op_us = 1000.0 * osum / reps;
     return FSI_OK;
 }
 
