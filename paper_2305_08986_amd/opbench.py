@@ -1,0 +1,68 @@
+"""Micro-benchmark of the matrix-free level operators (one workload, one level).
+
+    python -m paper_2305_08986_amd.opbench --workload C3 --mode A --prec fp64 --reps 20
+
+Times the fused cell kernel with HIP events (fsi_time_operator) and prints one
+JSON line.  With --copy-calibration it also runs a plain device copy of a
+known size first, which profiler counter runs use to scale HBM byte counters.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+MODES = {"A": 1, "BT": 2, "B": 4, "stokes": 7}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="C3")
+    ap.add_argument("--mode", default="A", choices=sorted(MODES))
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--level", type=int, default=-1)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch variant")
+    ap.add_argument("--copy-calibration", action="store_true")
+    a = ap.parse_args(argv)
+
+    import torch
+
+    from . import fsi
+    from . import workloads as W
+
+    torch.cuda.set_device(0)
+    out = {}
+    if a.copy_calibration:
+        n = 1 << 28                     # 2 GiB of doubles
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out["copy_bytes_read"] = 8 * n
+        out["copy_bytes_written"] = 8 * n
+        out["copy_GBps"] = 16 * n / (ms * 1e-3) / 1e9
+        del x, y
+    wl = W.make_workload(a.workload)
+    ctx = fsi.Context.from_mesh(wl.mesh)
+    fsi.setup_workload(ctx, wl)
+    lev = ctx.n_levels - 1 if a.level < 0 else a.level
+    p = 0 if a.prec == "fp64" else 1
+    if not a.no_autotune:
+        ctx.autotune()
+    k_us, op_us = ctx.time_operator(lev, precision=p, mode=MODES[a.mode], reps=a.reps)
+    s = ctx.sizes(lev)
+    out.update(dict(workload=a.workload, level=lev, mode=a.mode, prec=a.prec, reps=a.reps,
+                    variant=ctx.tuning(lev, p)[0], n_cells=s["n_cells"], n_vel=s["n_vel"],
+                    colour_launch_us=k_us, operator_us=op_us,
+                    gdofs=s["n_vel"] / (op_us * 1e-6) / 1e9))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
