@@ -198,12 +198,13 @@ fsi_status fsi_get_tuning(const fsi_ctx* ctx, int level, int precision, int* var
 
 /* Measurement support: runs `reps` applications of the level operator
  * (mode bits 1 = A, 2 = B^T, 4 = B; 7 = fused Stokes) in the given precision on
- * internal work vectors, timing every colour launch of the cell kernel with
- * HIP events on the context's stream.  kernel_us = mean duration of one
- * colour launch, op_us = mean duration of the whole operator (output clear,
- * all colours, wall rows).  Synchronises.  Errors: FSI_ERR_ARG, FSI_ERR_STATE. */
+ * internal work vectors, timing every launch of the cell kernel with HIP events
+ * on the context's stream.  kernel_us = cell-kernel time of one application
+ * (sum over its n_launches launches: processing phases = slabs x colours),
+ * op_us = duration of the whole application (including the wall rows).
+ * Synchronises.  Errors: FSI_ERR_ARG, FSI_ERR_STATE. */
 fsi_status fsi_time_operator(fsi_ctx* ctx, int level, int precision, int mode, int reps,
-                             double* kernel_us, double* op_us);
+                             double* kernel_us, double* op_us, int* n_launches);
 
 #ifdef __cplusplus
 }

@@ -74,7 +74,6 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
     }
     L.nv = dim * L.nvn;
     L.nvert = L.np;
-    L.ncolors = 1 << dim;
     const int NLOC = dim == 3 ? 27 : 9, NPL = dim == 3 ? 8 : 4;
     // wall mask of the velocity nodes
     L.h_dir_node.assign((size_t)L.nvn, 0);
@@ -92,42 +91,77 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
         if (w) dirn.push_back((int)n);
     }
     L.n_dir = (int64_t)dirn.size();
-    // colour ordering: colour = parity bits of the cell index; stable lexicographic inside
-    std::vector<int> col2lex((size_t)L.nc), lex2col((size_t)L.nc);
-    std::vector<int64_t> count(9, 0);
-    for (int64_t c = 0; c < L.nc; ++c) {
+    // processing order: phases are the parity colours of (iy, iz); a phase holds
+    // whole rows of cells along x (lexicographic), so one wavefront can own a row
+    L.ncolors = 1 << (dim - 1);
+    auto cell_coords = [&](int64_t c, int ci[3]) {
         int64_t r = c;
-        int col = 0;
-        for (int d = 0; d < dim; ++d) {
-            col |= (int)((r % L.cells[d]) & 1) << d;
-            r /= L.cells[d];
-        }
-        count[col]++;
-    }
-    L.color_off[0] = 0;
-    for (int c = 0; c < L.ncolors; ++c) L.color_off[c + 1] = L.color_off[c] + count[c];
-    std::vector<int64_t> pos(L.color_off, L.color_off + 8);
-    for (int64_t c = 0; c < L.nc; ++c) {
-        int64_t r = c;
-        int col = 0;
-        for (int d = 0; d < dim; ++d) {
-            col |= (int)((r % L.cells[d]) & 1) << d;
-            r /= L.cells[d];
-        }
-        const int64_t k = pos[col]++;
-        col2lex[k] = (int)c;
-        lex2col[c] = (int)k;
-    }
-    std::vector<int> vmap((size_t)L.nc * NLOC), pmap((size_t)L.nc * NPL);
-    std::vector<uint32_t> dmask((size_t)L.nc);
-    for (int64_t k = 0; k < L.nc; ++k) {
-        int64_t r = col2lex[k];
-        int ci[3] = {0, 0, 0};
+        ci[0] = ci[1] = ci[2] = 0;
         for (int d = 0; d < dim; ++d) {
             ci[d] = (int)(r % L.cells[d]);
             r /= L.cells[d];
         }
-        uint32_t dm = 0;
+    };
+    auto phase_of = [&](const int ci[3]) {
+        int col = 0;
+        for (int d = 1; d < dim; ++d) col |= (ci[d] & 1) << (d - 1);
+        return col;
+    };
+    const int nph = L.nphases();
+    const int cpw = dim == 3 ? Shape<3>::CPW : Shape<2>::CPW;
+    const int nx = L.cells[0];
+    const int nchunk = (nx + cpw - 1) / cpw;
+    std::vector<int> col2lex((size_t)L.nc), lex2col((size_t)L.nc);
+    // rows of each phase (lexicographic in the row index)
+    std::vector<std::vector<int64_t>> rows((size_t)nph);
+    for (int64_t c = 0; c < L.nc; c += nx) {
+        int ci[3];
+        cell_coords(c, ci);
+        rows[phase_of(ci)].push_back(c);      // lex index of the row's first cell
+    }
+    // inside a phase, cells are numbered row by row (x fastest)
+    L.phase_off.assign((size_t)nph + 1, 0);
+    int64_t k = 0;
+    for (int p = 0; p < nph; ++p) {
+        L.phase_off[p] = k;
+        for (int64_t r : rows[p])
+            for (int ix = 0; ix < nx; ++ix) {
+                col2lex[k] = (int)(r + ix);
+                lex2col[r + ix] = (int)k;
+                ++k;
+            }
+    }
+    (void)nchunk;
+    L.phase_off[nph] = k;
+    std::vector<int> vmap((size_t)L.nc * NLOC), pmap((size_t)L.nc * NPL);
+    std::vector<uint4> info((size_t)L.nc);
+    // first/last touch of a shared node: compare the phase of every other cell containing it
+    // x-neighbours belong to the same row: their contributions are summed in the
+    // wavefront before the write, so only y/z neighbours decide first/last touch
+    auto touch_bits = [&](const int ci[3], const int li[3], int hi_index, bool& first, bool& last) {
+        int dirs[3], nd = 0;
+        for (int d = 1; d < dim; ++d) {
+            if (li[d] == 0 && ci[d] > 0) dirs[nd++] = -(d + 1);
+            else if (li[d] == hi_index && ci[d] < L.cells[d] - 1) dirs[nd++] = d + 1;
+        }
+        const int me = phase_of(ci);
+        first = last = true;
+        for (int m = 1; m < (1 << nd); ++m) {
+            int nb[3] = {ci[0], ci[1], ci[2]};
+            for (int b = 0; b < nd; ++b)
+                if (m & (1 << b)) {
+                    const int d = dirs[b] < 0 ? -dirs[b] - 1 : dirs[b] - 1;
+                    nb[d] += dirs[b] < 0 ? -1 : 1;
+                }
+            const int ph = phase_of(nb);
+            if (ph < me) first = false;
+            if (ph > me) last = false;
+        }
+    };
+    for (int64_t k = 0; k < L.nc; ++k) {
+        int ci[3];
+        cell_coords(col2lex[k], ci);
+        uint4 inf = {0u, 0u, 0u, 0u};
         for (int n = 0; n < NLOC; ++n) {
             const int li[3] = {n % 3, (n / 3) % 3, n / 9};
             int64_t node = 0, st = 1;
@@ -136,9 +170,12 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
                 st *= L.vnodes[d];
             }
             vmap[k * NLOC + n] = (int)node;
-            if (L.h_dir_node[node]) dm |= 1u << n;
+            if (L.h_dir_node[node]) inf.x |= 1u << n;
+            bool f, l;
+            touch_bits(ci, li, 2, f, l);
+            if (f) inf.y |= 1u << n;
+            if (l) inf.w |= 1u << n;
         }
-        dmask[k] = dm;
         for (int n = 0; n < NPL; ++n) {
             const int li[3] = {n & 1, (n >> 1) & 1, (n >> 2) & 1};
             int64_t node = 0, st = 1;
@@ -147,20 +184,24 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
                 st *= L.pnodes[d];
             }
             pmap[k * NPL + n] = (int)node;
+            bool f, l;
+            touch_bits(ci, li, 1, f, l);
+            if (f) inf.z |= 1u << n;
         }
+        info[k] = inf;
     }
     TRY(dalloc(ctx, &L.d_col2lex, L.nc));
     TRY(dalloc(ctx, &L.d_lex2col, L.nc));
     TRY(dalloc(ctx, &L.d_vmap, L.nc * NLOC));
     TRY(dalloc(ctx, &L.d_pmap, L.nc * NPL));
-    TRY(dalloc(ctx, &L.d_dmask, L.nc));
+    TRY(dalloc(ctx, &L.d_info, L.nc));
     TRY(dalloc(ctx, &L.d_wall, L.nvn));
     TRY(dalloc(ctx, &L.d_dir_nodes, std::max<int64_t>(1, L.n_dir)));
     FSI_HIP_TRY(hipMemcpy(L.d_col2lex, col2lex.data(), sizeof(int) * L.nc, hipMemcpyHostToDevice));
     FSI_HIP_TRY(hipMemcpy(L.d_lex2col, lex2col.data(), sizeof(int) * L.nc, hipMemcpyHostToDevice));
     FSI_HIP_TRY(hipMemcpy(L.d_vmap, vmap.data(), sizeof(int) * vmap.size(), hipMemcpyHostToDevice));
     FSI_HIP_TRY(hipMemcpy(L.d_pmap, pmap.data(), sizeof(int) * pmap.size(), hipMemcpyHostToDevice));
-    FSI_HIP_TRY(hipMemcpy(L.d_dmask, dmask.data(), sizeof(uint32_t) * dmask.size(), hipMemcpyHostToDevice));
+    FSI_HIP_TRY(hipMemcpy(L.d_info, info.data(), sizeof(uint4) * info.size(), hipMemcpyHostToDevice));
     FSI_HIP_TRY(hipMemcpy(L.d_wall, L.h_dir_node.data(), (size_t)L.nvn, hipMemcpyHostToDevice));
     if (L.n_dir > 0)
         FSI_HIP_TRY(hipMemcpy(L.d_dir_nodes, dirn.data(), sizeof(int) * dirn.size(), hipMemcpyHostToDevice));
@@ -228,11 +269,12 @@ static int variant_of(const Context* ctx, int prec, int level) {
 // ---------------------------------------------------------------- operators
 template <typename T>
 static void op_apply(Context* ctx, int j, int mode, const T* u, const double* p, T* v, double* q, hipStream_t s) {
+    // every output entry is written by its first touching cell (no clearing pass);
+    // wall rows: identity for A, zero for B^T alone
     const Level& L = ctx->lv[j];
-    if (mode & (OP_A | OP_BT)) launch_fill<T>(v, T(0), L.nv, s);
-    if (mode & OP_B) launch_fill<double>(q, 0.0, L.np, s);
     launch_cell_all<T>(L, mode, variant_of(ctx, prec_index<T>(), j), Kp<T>(L), CVp<T>(L), u, p, v, q, s);
     if (mode & OP_A) launch_dirichlet_copy<T>(L, u, v, s);
+    else if (mode & OP_BT) launch_dirichlet_zero<T>(L, v, s);
 }
 
 // Chebyshev smoother Cheb(A, diag A, k_A) from a zero initial guess: k_A - 1 applications of A
@@ -1050,7 +1092,7 @@ fsi_status fsi_autotune(fsi_ctx* h) {
             const Level& L = ctx->lv[j];
             double best = 1e300;
             int bestv = 0;
-            for (int var = 0; var < 6; ++var) {
+            for (int var = 0; var < kNumVariants; ++var) {
                 ctx->tune_variant[pi][j] = var;
                 const int reps = 3;
                 for (int r = 0; r <= reps; ++r) {
@@ -1068,6 +1110,8 @@ fsi_status fsi_autotune(fsi_ctx* h) {
                 float ms = 0;
                 FSI_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
                 const double us = 1000.0 * ms / reps;
+                if (getenv("FSI_TUNE_VERBOSE"))
+                    fprintf(stderr, "[fsi autotune] precision %d level %d variant %d: %.1f us\n", pi, j, var, us);
                 if (us < best) {
                     best = us;
                     bestv = var;
@@ -1085,8 +1129,9 @@ fsi_status fsi_autotune(fsi_ctx* h) {
 }
 
 fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int reps, double* kernel_us,
-                             double* op_us) {
-    if (!h || !kernel_us || !op_us || reps < 1 || (precision != 0 && precision != 1) || mode < 1 || mode > 7)
+                             double* op_us, int* n_launches) {
+    if (!h || !kernel_us || !op_us || !n_launches || reps < 1 || (precision != 0 && precision != 1) || mode < 1 ||
+        mode > 7)
         return FSI_ERR_ARG;
     Context* ctx = &h->c;
     TRY(apply_check(ctx, level, (mode & OP_A) != 0));
@@ -1094,47 +1139,51 @@ fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int
     TRY(alloc_work<float>(ctx));
     const Level& L = ctx->lv[level];
     hipStream_t s = ctx->stream;
-    const int ncol = L.ncolors;
-    std::vector<hipEvent_t> ev((size_t)2 * ncol + 2);
+    const int nph = L.nphases();
+    std::vector<hipEvent_t> ev((size_t)2 * nph + 2);
     for (auto& e : ev) FSI_HIP_TRY(hipEventCreate(&e));
     const int var = variant_of(ctx, precision, level);
     double ksum = 0.0, osum = 0.0;
+    int launched = 0;
     for (int r = 0; r < reps; ++r) {
         FSI_HIP_TRY(hipEventRecord(ev[0], s));
+        launched = 0;
+        for (int ph = 0; ph < nph; ++ph) {
+            FSI_HIP_TRY(hipEventRecord(ev[1 + 2 * ph], s));
+            if (L.phase_off[ph + 1] > L.phase_off[ph]) ++launched;
+            if (precision == 0) {
+                LevelWork<double>& W = ctx->w64[level];
+                launch_cell<double>(L, mode, var, ph, L.d_K64, L.d_cv64, W.x_u, W.x_p, W.r_u, W.r_p, s);
+            } else {
+                LevelWork<float>& W = ctx->w32[level];
+                launch_cell<float>(L, mode, var, ph, L.d_K32, L.d_cv32, W.x_u, W.x_p, W.r_u, W.r_p, s);
+            }
+            FSI_HIP_TRY(hipEventRecord(ev[2 + 2 * ph], s));
+        }
         if (precision == 0) {
             LevelWork<double>& W = ctx->w64[level];
-            if (mode & (OP_A | OP_BT)) launch_fill<double>(W.r_u, 0.0, L.nv, s);
-            if (mode & OP_B) launch_fill<double>(W.r_p, 0.0, L.np, s);
-            for (int c = 0; c < ncol; ++c) {
-                FSI_HIP_TRY(hipEventRecord(ev[1 + 2 * c], s));
-                launch_cell<double>(L, mode, var, c, L.d_K64, L.d_cv64, W.x_u, W.x_p, W.r_u, W.r_p, s);
-                FSI_HIP_TRY(hipEventRecord(ev[2 + 2 * c], s));
-            }
             if (mode & OP_A) launch_dirichlet_copy<double>(L, W.x_u, W.r_u, s);
+            else if (mode & OP_BT) launch_dirichlet_zero<double>(L, W.r_u, s);
         } else {
             LevelWork<float>& W = ctx->w32[level];
-            if (mode & (OP_A | OP_BT)) launch_fill<float>(W.r_u, 0.0f, L.nv, s);
-            if (mode & OP_B) launch_fill<double>(W.r_p, 0.0, L.np, s);
-            for (int c = 0; c < ncol; ++c) {
-                FSI_HIP_TRY(hipEventRecord(ev[1 + 2 * c], s));
-                launch_cell<float>(L, mode, var, c, L.d_K32, L.d_cv32, W.x_u, W.x_p, W.r_u, W.r_p, s);
-                FSI_HIP_TRY(hipEventRecord(ev[2 + 2 * c], s));
-            }
             if (mode & OP_A) launch_dirichlet_copy<float>(L, W.x_u, W.r_u, s);
+            else if (mode & OP_BT) launch_dirichlet_zero<float>(L, W.r_u, s);
         }
-        FSI_HIP_TRY(hipEventRecord(ev[2 * ncol + 1], s));
-        FSI_HIP_TRY(hipEventSynchronize(ev[2 * ncol + 1]));
+        FSI_HIP_TRY(hipEventRecord(ev[2 * nph + 1], s));
+        FSI_HIP_TRY(hipEventSynchronize(ev[2 * nph + 1]));
         float ms;
-        for (int c = 0; c < ncol; ++c) {
-            FSI_HIP_TRY(hipEventElapsedTime(&ms, ev[1 + 2 * c], ev[2 + 2 * c]));
+        for (int ph = 0; ph < nph; ++ph) {
+            if (L.phase_off[ph + 1] == L.phase_off[ph]) continue;
+            FSI_HIP_TRY(hipEventElapsedTime(&ms, ev[1 + 2 * ph], ev[2 + 2 * ph]));
             ksum += ms;
         }
-        FSI_HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[2 * ncol + 1]));
+        FSI_HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[2 * nph + 1]));
         osum += ms;
     }
     for (auto& e : ev) hipEventDestroy(e);
-    *kernel_us = 1000.0 * ksum / ((double)reps * ncol);
+    *kernel_us = 1000.0 * ksum / reps;
     *op_us = 1000.0 * osum / reps;
+    *n_launches = launched;
     return FSI_OK;
 }
 

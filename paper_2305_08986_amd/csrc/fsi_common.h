@@ -69,14 +69,21 @@ struct Level {
     int64_t nc = 0, nvn = 0, nv = 0, np = 0, nvert = 0;
     int Q = 0;
     int ncolors = 0;
-    int64_t color_off[9] = {0};
+    // processing phases: the parity colours of the row index (iy[, iz]); cells
+    // are stored phase-major as whole rows along x, phase p owning cells
+    // [phase_off[p], phase_off[p+1])
+    std::vector<int64_t> phase_off;
+    int nphases() const { return ncolors; }
 
     // colour-ordered cell structure
     int* d_col2lex = nullptr;      // [nc]
     int* d_lex2col = nullptr;      // [nc]
     int* d_vmap = nullptr;         // [nc][NLOC] Q2 node of local node
     int* d_pmap = nullptr;         // [nc][NPL]  Q1 node / vertex of local vertex
-    uint32_t* d_dmask = nullptr;   // [nc] bit n set: local Q2 node n is on a wall
+    // per cell: x = wall bits of the local Q2 nodes, y = first-touch bits of the
+    // local Q2 nodes, z = first-touch bits of the local vertices, w = last-touch
+    // bits of the local Q2 nodes (first/last in phase order)
+    uint4* d_info = nullptr;
     uint8_t* d_wall = nullptr;     // [nvn] 1: velocity node on a wall
     int* d_dir_nodes = nullptr;    // wall nodes
     int64_t n_dir = 0;
@@ -168,8 +175,9 @@ struct Context {
 // ---------------------------------------------------------------- launchers (kernels_*.hip)
 // cell operator on one colour range; mode = OP_* bits; variant selects the
 // workgroup size (wavefronts per workgroup) and block->tile mapping.
+constexpr int kNumVariants = 8;
 template <typename T>
-void launch_cell(const Level& L, int mode, int variant, int color, const T* K, const T* cv,
+void launch_cell(const Level& L, int mode, int variant, int phase, const T* K, const T* cv,
                  const T* u, const double* p, T* v, double* q, hipStream_t s);
 template <typename T>
 void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T* cv,

@@ -216,8 +216,9 @@ void launch_coefficients(const Level& L, const double* cm, const double* eta, co
 
 // ---------------------------------------------------------------- diag(A)
 // diag_(a,n) = sum_q cmass phi_n^2 + (cvisc/2)(|G_n|^2 + G_n[a]^2), G_n = K^T grad-hat phi_n
-__global__ void k_diagA(int dim, int64_t cbeg, int64_t cend, int64_t nc, int64_t nvn, int64_t plane,
-                        const int* __restrict__ vmap, const uint32_t* __restrict__ dmask,
+__global__ void k_diagA(int dim, int64_t cbeg, int64_t cend, const int* __restrict__ col2lex, int nx, int xpar,
+                        int64_t nc, int64_t nvn, int64_t plane,
+                        const int* __restrict__ vmap, const uint4* __restrict__ info,
                         const double* __restrict__ K, const double* __restrict__ cv, double* __restrict__ diag) {
     const int NLOC = dim == 3 ? 27 : 9;
     const int NT = dim == 3 ? 9 : 3;
@@ -226,7 +227,8 @@ __global__ void k_diagA(int dim, int64_t cbeg, int64_t cend, int64_t nc, int64_t
     const int64_t cell = cbeg + id / NLOC;
     const int n = (int)(id % NLOC);
     if (cell >= cend) return;
-    if ((dmask[cell] >> n) & 1u) return;
+    if ((col2lex[cell] % nx) % 2 != xpar) return;   // cells of a row share x-faces
+    if ((info[cell].x >> n) & 1u) return;
     int ni[3] = {n % 3, (n / 3) % 3, n / 9};
     double acc[3] = {0, 0, 0};
     for (int q = 0; q < Q; ++q) {
@@ -254,12 +256,14 @@ __global__ void k_diagA(int dim, int64_t cbeg, int64_t cend, int64_t nc, int64_t
 
 void launch_diagA(const Level& L, const double* K, const double* cv, double* diag, hipStream_t s) {
     const int nloc = L.dim == 3 ? 27 : 9;
-    for (int c = 0; c < L.ncolors; ++c) {
-        const int64_t n = (L.color_off[c + 1] - L.color_off[c]) * nloc;
-        if (n == 0) continue;
-        hipLaunchKernelGGL(k_diagA, dim3(nblocks(n)), dim3(TPB), 0, s, L.dim, L.color_off[c], L.color_off[c + 1],
-                           L.nc, L.nvn, L.plane(), L.d_vmap, L.d_dmask, K, cv, diag);
-    }
+    for (int ph = 0; ph < L.nphases(); ++ph)
+        for (int xpar = 0; xpar < 2; ++xpar) {
+            const int64_t n = (L.phase_off[ph + 1] - L.phase_off[ph]) * nloc;
+            if (n == 0) continue;
+            hipLaunchKernelGGL(k_diagA, dim3(nblocks(n)), dim3(TPB), 0, s, L.dim, L.phase_off[ph],
+                               L.phase_off[ph + 1], L.d_col2lex, L.cells[0], xpar, L.nc, L.nvn, L.plane(), L.d_vmap,
+                               L.d_info, K, cv, diag);
+        }
 }
 
 __global__ void k_diag_finish(int64_t nv, double* __restrict__ diag, double* __restrict__ d64,
@@ -792,7 +796,8 @@ template void launch_prolongate_add<float>(const Level&, const Level&, const flo
 // One thread per (cell of one colour, local velocity dof): the element-matrix row
 // of A (mass + viscous) and the matching column of B^T / row of B are added to the
 // dense matrix restricted to free dofs (dof2row[dof] < 0 for wall dofs).
-__global__ void k_coarse_assemble(int dim, int64_t cbeg, int64_t cend, int64_t nc, int64_t nvn, int64_t plane,
+__global__ void k_coarse_assemble(int dim, int64_t cbeg, int64_t cend, const int* __restrict__ col2lex, int nx,
+                                  int xpar, int64_t nc, int64_t nvn, int64_t plane,
                                   const int* __restrict__ vmap, const int* __restrict__ pmap,
                                   const double* __restrict__ K, const double* __restrict__ cv,
                                   const int* __restrict__ vrow, int64_t nfree_u, double* __restrict__ M, int64_t n) {
@@ -800,6 +805,7 @@ __global__ void k_coarse_assemble(int dim, int64_t cbeg, int64_t cend, int64_t n
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cell = cbeg + id / (dim * NLOC);
     if (cell >= cend) return;
+    if ((col2lex[cell] % nx) % 2 != xpar) return;   // cells of a row share x-faces
     const int loc = (int)(id % (dim * NLOC));
     const int a = loc / NLOC, nrow = loc % NLOC;
     const int row = vrow[a * nvn + vmap[cell * NLOC + nrow]];
@@ -873,12 +879,14 @@ __global__ void k_coarse_assemble(int dim, int64_t cbeg, int64_t cend, int64_t n
 void launch_coarse_assemble_impl(const Level& L, const double* K, const double* cv, const int* vrow,
                                  int64_t nfree_u, double* M, int64_t n, hipStream_t s) {
     const int nloc = L.dim == 3 ? 27 : 9;
-    for (int c = 0; c < L.ncolors; ++c) {
-        const int64_t cnt = (L.color_off[c + 1] - L.color_off[c]) * L.dim * nloc;
-        if (cnt == 0) continue;
-        hipLaunchKernelGGL(k_coarse_assemble, dim3(nblocks(cnt, 64)), dim3(64), 0, s, L.dim, L.color_off[c],
-                           L.color_off[c + 1], L.nc, L.nvn, L.plane(), L.d_vmap, L.d_pmap, K, cv, vrow, nfree_u, M, n);
-    }
+    for (int ph = 0; ph < L.nphases(); ++ph)
+        for (int xpar = 0; xpar < 2; ++xpar) {
+            const int64_t cnt = (L.phase_off[ph + 1] - L.phase_off[ph]) * L.dim * nloc;
+            if (cnt == 0) continue;
+            hipLaunchKernelGGL(k_coarse_assemble, dim3(nblocks(cnt, 64)), dim3(64), 0, s, L.dim, L.phase_off[ph],
+                               L.phase_off[ph + 1], L.d_col2lex, L.cells[0], xpar, L.nc, L.nvn, L.plane(), L.d_vmap,
+                               L.d_pmap, K, cv, vrow, nfree_u, M, n);
+        }
 }
 
 // Gauss-Jordan inversion with partial pivoting, one pivot step per three launches.

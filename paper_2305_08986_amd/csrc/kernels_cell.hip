@@ -15,8 +15,10 @@
 // cell, NT = 3^(dim-1) threads per cell, CPW cells per wavefront.  The three
 // 1D contraction sweeps run in registers; between sweep directions the lines
 // are transposed through LDS (wavefront-private).  Cells of one colour share
-// no node, so the scatter is a plain read-modify-write (no atomics); the host
-// launches the 2^dim colours one after another.
+// no node, so the scatter is a plain store (first touch of a node in phase
+// order) or read-modify-write (later touches), with no atomics; the host
+// launches the phases (slab x colour) one after another, so that the vector
+// data of a slab stays cache-resident across its colours.
 #include "fsi_common.h"
 
 namespace fsi {
@@ -31,6 +33,13 @@ template <typename T> __device__ __forceinline__ T rL(int q, int a) {
     return ((q == 0) == (a == 0)) ? hi : lo;
 }
 
+// geometry is read exactly once per application: optionally stream it past the caches
+template <bool NT, typename T>
+__device__ __forceinline__ T gload(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
     const int64_t x = b & 7, qd = nb >> 3, r = nb & 7;
     const int64_t base = (x < r) ? x * (qd + 1) : r * (qd + 1) + (x - r) * qd;
@@ -40,8 +49,11 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
 template <typename T>
 struct CellArgs {
     int64_t cbeg, cend, nc, nvn, plane;
+    int64_t nrows;      // rows of cells (along x) in this phase
+    int nx, nchunks;    // cells per row, chunks of CPW cells per row
+    int wlast;          // cells in the last (ragged) chunk of a row
     const int* __restrict__ vmap;
-    const uint32_t* __restrict__ dmask;
+    const uint4* __restrict__ info;
     const int* __restrict__ pmap;
     const T* __restrict__ K;
     const T* __restrict__ cv;
@@ -52,329 +64,458 @@ struct CellArgs {
 };
 
 // ============================================================== 3D
-template <typename T, int MODE, int WPB, bool REMAP>
-__global__ __launch_bounds__(64 * WPB) void cell3d(CellArgs<T> a) {
+// One wavefront owns a row of cells along x and walks it in chunks of CPW = 7
+// cells (9 threads per cell: one per line of 3 points).
+template <typename T, int MODE, int WPB, bool REMAP, bool NTL, int WPE>
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE))) void cell3d(CellArgs<T> a) {
     constexpr int NT = 9, CPW = 7, NLOC = 27, BUF = 243;
     constexpr bool FWD = (MODE & (OP_A | OP_B)) != 0;
     constexpr bool BWD = (MODE & (OP_A | OP_BT)) != 0;
+    constexpr bool HAS_B = (MODE & OP_B) != 0;
+    constexpr bool HAS_BT = (MODE & OP_BT) != 0;
+    constexpr bool HAS_A = (MODE & OP_A) != 0;
     __shared__ T sbuf[WPB][CPW][BUF];
-    __shared__ double pbuf[(MODE & OP_B) ? WPB : 1][CPW][NT][8];
+    __shared__ double pbuf[HAS_B ? WPB : 1][CPW][NT][8];
+    // x-face hand-over between neighbouring cells of the row: [slot][j][comp][k],
+    // carry from the last slot of a chunk to the first slot of the next one
+    __shared__ T xb[WPB][CPW][27];
+    __shared__ T xcarry[WPB][2][27];
+    __shared__ double pxb[HAS_B ? WPB : 1][CPW][4];
+    __shared__ double pcarry[HAS_B ? WPB : 1][2][4];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane / NT, t = lane - slot * NT;
     const bool inwave = slot < CPW;
     const int64_t lb = REMAP ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    const int64_t cell = a.cbeg + (lb * WPB + wave) * CPW + slot;
-    const bool act = inwave && cell < a.cend;
+    const int64_t row = lb * WPB + wave;
+    const bool rowact = row < a.nrows;
     T* B = sbuf[wave][inwave ? slot : 0];
     const int64_t P = a.plane;
-
-    // ---------------- forward: values and reference gradients at the 27 points
-    T val[3][3], g0[3][3], g1[3][3], g2[3][3];   // [comp][qx] at this thread's (qy,qz)
-    if constexpr (FWD) {
-        T uu[3][3];
-        if (act) {
-            const uint32_t dm = a.dmask[cell];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int ln = t + 9 * k;
-                const int node = a.vmap[cell * NLOC + ln];
-                const bool wall = (dm >> ln) & 1u;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) uu[c][k] = wall ? T(0) : a.u[c * a.nvn + node];
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int k = 0; k < 3; ++k) uu[c][k] = T(0);
-        }
-        // stage A (t = i + 3j): z-sweep
-        if (inwave) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int qz = 0; qz < 3; ++qz) {
-                    T s = T(0), d = T(0);
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        s += cS<T>(qz, k) * uu[c][k];
-                        d += cD<T>(qz, k) * uu[c][k];
-                    }
-                    B[((c * 2 + 0) * 3 + qz) * 9 + t] = s;
-                    B[((c * 2 + 1) * 3 + qz) * 9 + t] = d;
-                }
-        }
-        __syncthreads();
-        // stage B (t = i + 3 qz): y-sweep
-        const int ib = t % 3, qzb = t / 3;
-        T ya[3][3], yb[3][3], yc[3][3];
-        if (inwave) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                T zs[3], zd[3];
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    zs[j] = B[((c * 2 + 0) * 3 + qzb) * 9 + ib + 3 * j];
-                    zd[j] = B[((c * 2 + 1) * 3 + qzb) * 9 + ib + 3 * j];
-                }
-#pragma unroll
-                for (int qy = 0; qy < 3; ++qy) {
-                    T s = T(0), d = T(0), e = T(0);
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        s += cS<T>(qy, j) * zs[j];
-                        d += cD<T>(qy, j) * zs[j];
-                        e += cS<T>(qy, j) * zd[j];
-                    }
-                    ya[c][qy] = s;
-                    yb[c][qy] = d;
-                    yc[c][qy] = e;
-                }
-            }
-        }
-        __syncthreads();
-        if (inwave) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int qy = 0; qy < 3; ++qy) {
-                    B[((c * 3 + 0) * 9 + qy + 3 * qzb) * 3 + ib] = ya[c][qy];
-                    B[((c * 3 + 1) * 9 + qy + 3 * qzb) * 3 + ib] = yb[c][qy];
-                    B[((c * 3 + 2) * 9 + qy + 3 * qzb) * 3 + ib] = yc[c][qy];
-                }
-        }
-        __syncthreads();
-        // stage C (t = qy + 3 qz): x-sweep
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            T ga[3], gb[3], gc[3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                ga[i] = inwave ? B[((c * 3 + 0) * 9 + t) * 3 + i] : T(0);
-                gb[i] = inwave ? B[((c * 3 + 1) * 9 + t) * 3 + i] : T(0);
-                gc[i] = inwave ? B[((c * 3 + 2) * 9 + t) * 3 + i] : T(0);
-            }
-#pragma unroll
-            for (int qx = 0; qx < 3; ++qx) {
-                T s = T(0), d = T(0), e = T(0), f = T(0);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    s += cS<T>(qx, i) * ga[i];
-                    d += cD<T>(qx, i) * ga[i];
-                    e += cS<T>(qx, i) * gb[i];
-                    f += cS<T>(qx, i) * gc[i];
-                }
-                val[c][qx] = s;
-                g0[c][qx] = d;
-                g1[c][qx] = e;
-                g2[c][qx] = f;
-            }
-        }
-    }
-
+    // thread roles: stage A / scatter column (ic, jc) = (t % 3, t / 3); stage B line (ib, qzb)
+    // = (t % 3, t / 3); stage C line (qy, qz) = (t % 3, t / 3)
+    const int ic = t % 3, jc = t / 3;
     const int qy = t % 3, qz = t / 3;
-    // ---------------- pressure at the quadrature points (B^T)
-    T pq[3] = {T(0), T(0), T(0)};
-    if constexpr ((MODE & OP_BT) != 0) {
-        if (act) {
-            double pv[8];
-#pragma unroll
-            for (int n = 0; n < 8; ++n) pv[n] = a.p[a.pmap[cell * 8 + n]];
-            const T ly0 = rL<T>(qy, 0), ly1 = rL<T>(qy, 1), lz0 = rL<T>(qz, 0), lz1 = rL<T>(qz, 1);
-            T tx[2];
-#pragma unroll
-            for (int ax = 0; ax < 2; ++ax)
-                tx[ax] = ly0 * lz0 * T(pv[ax]) + ly1 * lz0 * T(pv[ax + 2]) + ly0 * lz1 * T(pv[ax + 4]) +
-                         ly1 * lz1 * T(pv[ax + 6]);
-#pragma unroll
-            for (int qx = 0; qx < 3; ++qx) pq[qx] = cL<T>(qx, 0) * tx[0] + cL<T>(qx, 1) * tx[1];
-        }
-    }
+    const int pax = t & 1, pyz = t >> 1;
 
-    // ---------------- quadrature-point operation
-    T F0[3][3], F1[3][3], F2[3][3], Fv[3][3];   // [comp][qx]
-    T divq[3];
+    for (int ch = 0; ch < a.nchunks; ++ch) {
+        const int ix = ch * CPW + slot;
+        const bool act = rowact && inwave && ix < a.nx;
+        const int64_t cell = a.cbeg + row * a.nx + ix;   // phase cells are stored row by row
+        const uint4 inf = act ? a.info[cell] : make_uint4(0u, 0u, 0u, 0u);
+        // does this thread write its column (x-face columns go to the right neighbour)?
+        const bool vwriter = act && (ic != 2 || ix == a.nx - 1);
+        const bool pwriter = act && t < 8 && (pax == 0 || ix == a.nx - 1);
+
+        // ---------------- loads
+        int node[3] = {0, 0, 0};
+        T uu[3][3];     // [comp][k] velocity of the column nodes
 #pragma unroll
-    for (int qx = 0; qx < 3; ++qx) {
-        T Km[3][3];
-        const int64_t off = ((int64_t)qx * a.nc + cell) * NT + t;
+        for (int k = 0; k < 3; ++k) {
+            const int ln = t + 9 * k;
+            node[k] = act ? a.vmap[cell * NLOC + ln] : 0;
+            const bool wall = (inf.x >> ln) & 1u;
 #pragma unroll
-        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c) uu[c][k] = (FWD && act && !wall) ? a.u[c * a.nvn + node[k]] : T(0);
+        }
+        int pnode = 0;
+        double qold = 0.0;
+        if constexpr (HAS_B) {
+            if (pwriter) {
+                pnode = a.pmap[cell * 8 + t];
+                if (!((inf.z >> t) & 1u)) qold = a.q[pnode];
+            }
+        }
+        T pv[8];
+        if constexpr (HAS_BT) {
 #pragma unroll
-            for (int aa = 0; aa < 3; ++aa) Km[b][aa] = act ? a.K[(b * 3 + aa) * P + off] : T(0);
-        T Tm[3][3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int aa = 0; aa < 3; ++aa) Tm[c][aa] = T(0);
-        divq[qx] = T(0);
+            for (int n = 0; n < 8; ++n) pv[n] = act ? T(a.p[a.pmap[cell * 8 + n]]) : T(0);
+        }
+
+        // ---------------- forward sweeps z (A), y (B); x happens per point in stage C
+        T ga[3][3], gb[3][3], gc[3][3];   // [comp][i] at this thread's (qy, qz)
         if constexpr (FWD) {
-            T H[3][3];
+            if (inwave) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
+                for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int aa = 0; aa < 3; ++aa)
-                    H[c][aa] = g0[c][qx] * Km[0][aa] + g1[c][qx] * Km[1][aa] + g2[c][qx] * Km[2][aa];
-            if constexpr ((MODE & OP_B) != 0) divq[qx] = H[0][0] + H[1][1] + H[2][2];
-            if constexpr ((MODE & OP_A) != 0) {
-                const T cvisc = act ? a.cv[off] : T(0);
-                const T cmass = act ? a.cv[P + off] : T(0);
+                    for (int q3 = 0; q3 < 3; ++q3) {
+                        T sv = T(0), dv = T(0);
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            sv += cS<T>(q3, k) * uu[c][k];
+                            dv += cD<T>(q3, k) * uu[c][k];
+                        }
+                        B[((c * 2 + 0) * 3 + q3) * 9 + t] = sv;
+                        B[((c * 2 + 1) * 3 + q3) * 9 + t] = dv;
+                    }
+            }
+            __syncthreads();
+            const int ib = t % 3, qzb = t / 3;
+            T ya[3][3], yb[3][3], yc[3][3];
+            if (inwave) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    Tm[c][c] = cvisc * H[c][c];
-                    Fv[c][qx] = cmass * val[c][qx];
+                    T zs[3], zd[3];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        zs[j] = B[((c * 2 + 0) * 3 + qzb) * 9 + ib + 3 * j];
+                        zd[j] = B[((c * 2 + 1) * 3 + qzb) * 9 + ib + 3 * j];
+                    }
+#pragma unroll
+                    for (int q2 = 0; q2 < 3; ++q2) {
+                        T sv = T(0), dv = T(0), ev = T(0);
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            sv += cS<T>(q2, j) * zs[j];
+                            dv += cD<T>(q2, j) * zs[j];
+                            ev += cS<T>(q2, j) * zd[j];
+                        }
+                        ya[c][q2] = sv;
+                        yb[c][q2] = dv;
+                        yc[c][q2] = ev;
+                    }
                 }
-                const T e01 = T(0.5) * cvisc * (H[0][1] + H[1][0]);
-                const T e02 = T(0.5) * cvisc * (H[0][2] + H[2][0]);
-                const T e12 = T(0.5) * cvisc * (H[1][2] + H[2][1]);
-                Tm[0][1] = e01; Tm[1][0] = e01;
-                Tm[0][2] = e02; Tm[2][0] = e02;
-                Tm[1][2] = e12; Tm[2][1] = e12;
             }
-        }
-        if constexpr ((MODE & OP_A) == 0) {
+            __syncthreads();
+            if (inwave) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Fv[c][qx] = T(0);
-        }
-        if constexpr ((MODE & OP_BT) != 0) {
+                for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Tm[c][c] += pq[qx];
-        }
-        if constexpr (BWD) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                F0[c][qx] = Tm[c][0] * Km[0][0] + Tm[c][1] * Km[0][1] + Tm[c][2] * Km[0][2];
-                F1[c][qx] = Tm[c][0] * Km[1][0] + Tm[c][1] * Km[1][1] + Tm[c][2] * Km[1][2];
-                F2[c][qx] = Tm[c][0] * Km[2][0] + Tm[c][1] * Km[2][1] + Tm[c][2] * Km[2][2];
+                    for (int q2 = 0; q2 < 3; ++q2) {
+                        B[((c * 3 + 0) * 9 + q2 + 3 * qzb) * 3 + ib] = ya[c][q2];
+                        B[((c * 3 + 1) * 9 + q2 + 3 * qzb) * 3 + ib] = yb[c][q2];
+                        B[((c * 3 + 2) * 9 + q2 + 3 * qzb) * 3 + ib] = yc[c][q2];
+                    }
             }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    ga[c][i] = inwave ? B[((c * 3 + 0) * 9 + t) * 3 + i] : T(0);
+                    gb[c][i] = inwave ? B[((c * 3 + 1) * 9 + t) * 3 + i] : T(0);
+                    gc[c][i] = inwave ? B[((c * 3 + 2) * 9 + t) * 3 + i] : T(0);
+                }
         }
-    }
 
-    // ---------------- divergence tested with the Q1 basis (B)
-    if constexpr ((MODE & OP_B) != 0) {
-        T r[2];
-#pragma unroll
-        for (int ax = 0; ax < 2; ++ax)
-            r[ax] = cL<T>(0, ax) * divq[0] + cL<T>(1, ax) * divq[1] + cL<T>(2, ax) * divq[2];
-        if (inwave) {
-            const T ly[2] = {rL<T>(qy, 0), rL<T>(qy, 1)};
-            const T lz[2] = {rL<T>(qz, 0), rL<T>(qz, 1)};
-#pragma unroll
-            for (int cz = 0; cz < 2; ++cz)
-#pragma unroll
-                for (int by = 0; by < 2; ++by)
-#pragma unroll
-                    for (int ax = 0; ax < 2; ++ax)
-                        pbuf[wave][slot][t][ax + 2 * by + 4 * cz] = double(ly[by] * lz[cz] * r[ax]);
-        }
-        __syncthreads();
-        if (act && t < 8) {
-            double s = 0.0;
-#pragma unroll
-            for (int tt = 0; tt < NT; ++tt) s += pbuf[wave][slot][tt][t];
-            const int node = a.pmap[cell * 8 + t];
-            a.q[node] += s;
-        }
-    }
-
-    // ---------------- backward: test with the gradients / values of the Q2 basis
-    if constexpr (BWD) {
+        // ---------------- stage C: per quadrature point (qx, qy, qz); the backward
+        // x-sweep is accumulated on the fly into wa/wb/wc
         T wa[3][3], wb[3][3], wc[3][3];   // [comp][i]
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                T s = T(0), d = T(0), e = T(0);
+            for (int i = 0; i < 3; ++i) wa[c][i] = wb[c][i] = wc[c][i] = T(0);
+        T r0 = T(0), r1 = T(0);           // divergence tested with the two Q1 x-factors
+        T tx0 = T(0), tx1 = T(0);         // pressure contracted in y and z
+        if constexpr (HAS_BT) {
+            const T ly0 = rL<T>(qy, 0), ly1 = rL<T>(qy, 1), lz0 = rL<T>(qz, 0), lz1 = rL<T>(qz, 1);
+            tx0 = ly0 * lz0 * pv[0] + ly1 * lz0 * pv[2] + ly0 * lz1 * pv[4] + ly1 * lz1 * pv[6];
+            tx1 = ly0 * lz0 * pv[1] + ly1 * lz0 * pv[3] + ly0 * lz1 * pv[5] + ly1 * lz1 * pv[7];
+        }
+        if constexpr (sizeof(T) == 8) {
+        // FP64: accumulate the backward x-sweep point by point (fewer live registers)
 #pragma unroll
-                for (int qx = 0; qx < 3; ++qx) {
-                    s += cS<T>(qx, i) * Fv[c][qx] + cD<T>(qx, i) * F0[c][qx];
-                    d += cS<T>(qx, i) * F1[c][qx];
-                    e += cS<T>(qx, i) * F2[c][qx];
+        for (int qx = 0; qx < 3; ++qx) {
+            // keep one point's geometry in flight at a time (register budget)
+            __builtin_amdgcn_sched_barrier(0);
+            // geometry of the point: K = det(J) w J^{-1} (row-major 3x3), cvisc, cmass
+            T Kq[9];
+            const int64_t off = ((int64_t)qx * a.nc + cell) * NT + t;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) Kq[e] = act ? gload<NTL>(a.K + e * P + off) : T(0);
+            const T cvq = (HAS_A && act) ? gload<NTL>(a.cv + off) : T(0);
+            const T cmq = (HAS_A && act) ? gload<NTL>(a.cv + P + off) : T(0);
+            T Tm[3][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int e = 0; e < 3; ++e) Tm[c][e] = T(0);
+            T Fv[3] = {T(0), T(0), T(0)};
+            if constexpr (FWD) {
+                T H[3][3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    T vv = T(0), d0 = T(0), d1 = T(0), d2 = T(0);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        vv += cS<T>(qx, i) * ga[c][i];
+                        d0 += cD<T>(qx, i) * ga[c][i];
+                        d1 += cS<T>(qx, i) * gb[c][i];
+                        d2 += cS<T>(qx, i) * gc[c][i];
+                    }
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) H[c][e] = d0 * Kq[e] + d1 * Kq[3 + e] + d2 * Kq[6 + e];
+                    if constexpr (HAS_A) Fv[c] = cmq * vv;
                 }
-                wa[c][i] = s;
-                wb[c][i] = d;
-                wc[c][i] = e;
+                if constexpr (HAS_B) {
+                    const T dv = H[0][0] + H[1][1] + H[2][2];
+                    r0 += cL<T>(qx, 0) * dv;
+                    r1 += cL<T>(qx, 1) * dv;
+                }
+                if constexpr (HAS_A) {
+                    const T cv = cvq;
+                    Tm[0][0] = cv * H[0][0];
+                    Tm[1][1] = cv * H[1][1];
+                    Tm[2][2] = cv * H[2][2];
+                    const T e01 = T(0.5) * cv * (H[0][1] + H[1][0]);
+                    const T e02 = T(0.5) * cv * (H[0][2] + H[2][0]);
+                    const T e12 = T(0.5) * cv * (H[1][2] + H[2][1]);
+                    Tm[0][1] = e01; Tm[1][0] = e01;
+                    Tm[0][2] = e02; Tm[2][0] = e02;
+                    Tm[1][2] = e12; Tm[2][1] = e12;
+                }
             }
-        __syncthreads();
-        if (inwave) {
+            if constexpr (HAS_BT) {
+                const T pq = cL<T>(qx, 0) * tx0 + cL<T>(qx, 1) * tx1;
+                Tm[0][0] += pq;
+                Tm[1][1] += pq;
+                Tm[2][2] += pq;
+            }
+            if constexpr (BWD) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    // F[c][b] = sum_e Tm[c][e] K[b][e]
+                    const T F0 = Tm[c][0] * Kq[0] + Tm[c][1] * Kq[1] + Tm[c][2] * Kq[2];
+                    const T F1 = Tm[c][0] * Kq[3] + Tm[c][1] * Kq[4] + Tm[c][2] * Kq[5];
+                    const T F2 = Tm[c][0] * Kq[6] + Tm[c][1] * Kq[7] + Tm[c][2] * Kq[8];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        wa[c][i] += cS<T>(qx, i) * Fv[c] + cD<T>(qx, i) * F0;
+                        wb[c][i] += cS<T>(qx, i) * F1;
+                        wc[c][i] += cS<T>(qx, i) * F2;
+                    }
+                }
+            }
+        }
+
+        } else {
+        // FP32: registers are plentiful; all points first, then the backward x-sweep
+        T Fva[3][3], F0a[3][3], F1a[3][3], F2a[3][3];   // [comp][qx]
+#pragma unroll
+        for (int qx = 0; qx < 3; ++qx) {
+            // geometry of the point: K = det(J) w J^{-1} (row-major 3x3), cvisc, cmass
+            T Kq[9];
+            const int64_t off = ((int64_t)qx * a.nc + cell) * NT + t;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) Kq[e] = act ? gload<NTL>(a.K + e * P + off) : T(0);
+            const T cvq = (HAS_A && act) ? gload<NTL>(a.cv + off) : T(0);
+            const T cmq = (HAS_A && act) ? gload<NTL>(a.cv + P + off) : T(0);
+            T Tm[3][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int e = 0; e < 3; ++e) Tm[c][e] = T(0);
+            T Fv[3] = {T(0), T(0), T(0)};
+            if constexpr (FWD) {
+                T H[3][3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    T vv = T(0), d0 = T(0), d1 = T(0), d2 = T(0);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        vv += cS<T>(qx, i) * ga[c][i];
+                        d0 += cD<T>(qx, i) * ga[c][i];
+                        d1 += cS<T>(qx, i) * gb[c][i];
+                        d2 += cS<T>(qx, i) * gc[c][i];
+                    }
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) H[c][e] = d0 * Kq[e] + d1 * Kq[3 + e] + d2 * Kq[6 + e];
+                    if constexpr (HAS_A) Fv[c] = cmq * vv;
+                }
+                if constexpr (HAS_B) {
+                    const T dv = H[0][0] + H[1][1] + H[2][2];
+                    r0 += cL<T>(qx, 0) * dv;
+                    r1 += cL<T>(qx, 1) * dv;
+                }
+                if constexpr (HAS_A) {
+                    const T cv = cvq;
+                    Tm[0][0] = cv * H[0][0];
+                    Tm[1][1] = cv * H[1][1];
+                    Tm[2][2] = cv * H[2][2];
+                    const T e01 = T(0.5) * cv * (H[0][1] + H[1][0]);
+                    const T e02 = T(0.5) * cv * (H[0][2] + H[2][0]);
+                    const T e12 = T(0.5) * cv * (H[1][2] + H[2][1]);
+                    Tm[0][1] = e01; Tm[1][0] = e01;
+                    Tm[0][2] = e02; Tm[2][0] = e02;
+                    Tm[1][2] = e12; Tm[2][1] = e12;
+                }
+            }
+            if constexpr (HAS_BT) {
+                const T pq = cL<T>(qx, 0) * tx0 + cL<T>(qx, 1) * tx1;
+                Tm[0][0] += pq;
+                Tm[1][1] += pq;
+                Tm[2][2] += pq;
+            }
+            if constexpr (BWD) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    // F[c][b] = sum_e Tm[c][e] K[b][e]
+                    const T F0 = Tm[c][0] * Kq[0] + Tm[c][1] * Kq[1] + Tm[c][2] * Kq[2];
+                    const T F1 = Tm[c][0] * Kq[3] + Tm[c][1] * Kq[4] + Tm[c][2] * Kq[5];
+                    const T F2 = Tm[c][0] * Kq[6] + Tm[c][1] * Kq[7] + Tm[c][2] * Kq[8];
+                    Fva[c][qx] = Fv[c];
+                    F0a[c][qx] = F0;
+                    F1a[c][qx] = F1;
+                    F2a[c][qx] = F2;
+                }
+            }
+        }
+
+        if constexpr (BWD) {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    B[((c * 3 + 0) * 9 + t) * 3 + i] = wa[c][i];
-                    B[((c * 3 + 1) * 9 + t) * 3 + i] = wb[c][i];
-                    B[((c * 3 + 2) * 9 + t) * 3 + i] = wc[c][i];
+                    T sv = T(0), dv = T(0), ev = T(0);
+#pragma unroll
+                    for (int qx = 0; qx < 3; ++qx) {
+                        sv += cS<T>(qx, i) * Fva[c][qx] + cD<T>(qx, i) * F0a[c][qx];
+                        dv += cS<T>(qx, i) * F1a[c][qx];
+                        ev += cS<T>(qx, i) * F2a[c][qx];
+                    }
+                    wa[c][i] = sv;
+                    wb[c][i] = dv;
+                    wc[c][i] = ev;
                 }
         }
-        __syncthreads();
-        const int ib = t % 3, qzb = t / 3;
-        T vs[3][3], vd[3][3];   // [comp][j]
+        }
+        // ---------------- divergence tested with the Q1 basis (B); x-shared vertices
+        // are summed along the row before the write
+        if constexpr (HAS_B) {
+            if (inwave) {
+                const T ly[2] = {rL<T>(qy, 0), rL<T>(qy, 1)};
+                const T lz[2] = {rL<T>(qz, 0), rL<T>(qz, 1)};
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            T WA[3], WB[3], WC[3];
+                for (int cz = 0; cz < 2; ++cz)
 #pragma unroll
-            for (int q2 = 0; q2 < 3; ++q2) {
-                WA[q2] = inwave ? B[((c * 3 + 0) * 9 + q2 + 3 * qzb) * 3 + ib] : T(0);
-                WB[q2] = inwave ? B[((c * 3 + 1) * 9 + q2 + 3 * qzb) * 3 + ib] : T(0);
-                WC[q2] = inwave ? B[((c * 3 + 2) * 9 + q2 + 3 * qzb) * 3 + ib] : T(0);
+                    for (int by = 0; by < 2; ++by) {
+                        pbuf[wave][slot][t][0 + 2 * by + 4 * cz] = double(ly[by] * lz[cz] * r0);
+                        pbuf[wave][slot][t][1 + 2 * by + 4 * cz] = double(ly[by] * lz[cz] * r1);
+                    }
             }
+            __syncthreads();
+            double sq = 0.0;
+            if (inwave && t < 8) {
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                T s = T(0), d = T(0);
+                for (int tt = 0; tt < NT; ++tt) sq += pbuf[wave][slot][tt][t];
+                if (pax == 1) pxb[wave][slot][pyz] = sq;
+            }
+            __syncthreads();
+            if (act && t < 8) {
+                if (pax == 0 && ix > 0) sq += slot > 0 ? pxb[wave][slot - 1][pyz] : pcarry[wave][(ch + 1) & 1][pyz];
+                if (pwriter) a.q[pnode] = qold + sq;
+                else if (slot == CPW - 1) pcarry[wave][ch & 1][pyz] = sq;
+            }
+        }
+
+        // ---------------- backward sweeps y (B) and z (A), x-face hand-over, stores
+        if constexpr (BWD) {
+            __syncthreads();
+            if (inwave) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        B[((c * 3 + 0) * 9 + t) * 3 + i] = wa[c][i];
+                        B[((c * 3 + 1) * 9 + t) * 3 + i] = wb[c][i];
+                        B[((c * 3 + 2) * 9 + t) * 3 + i] = wc[c][i];
+                    }
+            }
+            __syncthreads();
+            const int ib = t % 3, qzb = t / 3;
+            T vs[3][3], vd[3][3];   // [comp][j]
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                T WA[3], WB[3], WC[3];
 #pragma unroll
                 for (int q2 = 0; q2 < 3; ++q2) {
-                    s += cS<T>(q2, j) * WA[q2] + cD<T>(q2, j) * WB[q2];
-                    d += cS<T>(q2, j) * WC[q2];
+                    WA[q2] = inwave ? B[((c * 3 + 0) * 9 + q2 + 3 * qzb) * 3 + ib] : T(0);
+                    WB[q2] = inwave ? B[((c * 3 + 1) * 9 + q2 + 3 * qzb) * 3 + ib] : T(0);
+                    WC[q2] = inwave ? B[((c * 3 + 2) * 9 + q2 + 3 * qzb) * 3 + ib] : T(0);
                 }
-                vs[c][j] = s;
-                vd[c][j] = d;
-            }
-        }
-        __syncthreads();
-        if (inwave) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    B[((c * 2 + 0) * 3 + qzb) * 9 + ib + 3 * j] = vs[c][j];
-                    B[((c * 2 + 1) * 3 + qzb) * 9 + ib + 3 * j] = vd[c][j];
+                    T sv = T(0), dv = T(0);
+#pragma unroll
+                    for (int q2 = 0; q2 < 3; ++q2) {
+                        sv += cS<T>(q2, j) * WA[q2] + cD<T>(q2, j) * WB[q2];
+                        dv += cS<T>(q2, j) * WC[q2];
+                    }
+                    vs[c][j] = sv;
+                    vd[c][j] = dv;
                 }
-        }
-        __syncthreads();
-        if (act) {
-            const uint32_t dm = a.dmask[cell];
-            T out[3][3];   // [comp][k]
+            }
+            __syncthreads();
+            if (inwave) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        B[((c * 2 + 0) * 3 + qzb) * 9 + ib + 3 * j] = vs[c][j];
+                        B[((c * 2 + 1) * 3 + qzb) * 9 + ib + 3 * j] = vd[c][j];
+                    }
+            }
+            __syncthreads();
+            T out[3][3];   // [comp][k] for the nodes (ic, jc, k) of this thread's column
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 T VS[3], VD[3];
 #pragma unroll
                 for (int q3 = 0; q3 < 3; ++q3) {
-                    VS[q3] = B[((c * 2 + 0) * 3 + q3) * 9 + t];
-                    VD[q3] = B[((c * 2 + 1) * 3 + q3) * 9 + t];
+                    VS[q3] = inwave ? B[((c * 2 + 0) * 3 + q3) * 9 + t] : T(0);
+                    VD[q3] = inwave ? B[((c * 2 + 1) * 3 + q3) * 9 + t] : T(0);
                 }
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    T s = T(0);
+                    T sv = T(0);
 #pragma unroll
-                    for (int q3 = 0; q3 < 3; ++q3) s += cS<T>(q3, k) * VS[q3] + cD<T>(q3, k) * VD[q3];
-                    out[c][k] = s;
+                    for (int q3 = 0; q3 < 3; ++q3) sv += cS<T>(q3, k) * VS[q3] + cD<T>(q3, k) * VD[q3];
+                    out[c][k] = sv;
                 }
             }
+            if (inwave && ic == 2) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int ln = t + 9 * k;
-                if ((dm >> ln) & 1u) continue;
-                const int node = a.vmap[cell * NLOC + ln];
+                for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node] += out[c][k];
+                    for (int k = 0; k < 3; ++k) xb[wave][slot][jc * 9 + c * 3 + k] = out[c][k];
+            }
+            __syncthreads();
+            if (act) {
+                if (ic == 0 && ix > 0) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+                            out[c][k] += slot > 0 ? xb[wave][slot - 1][jc * 9 + c * 3 + k]
+                                                  : xcarry[wave][(ch + 1) & 1][jc * 9 + c * 3 + k];
+                }
+                if (vwriter) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const int ln = t + 9 * k;
+                        if ((inf.x >> ln) & 1u) continue;
+                        if ((inf.y >> ln) & 1u) {   // first touch of the node in phase order
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node[k]] = out[c][k];
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node[k]] += out[c][k];
+                        }
+                    }
+                } else if (slot == CPW - 1) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) xcarry[wave][ch & 1][jc * 9 + c * 3 + k] = out[c][k];
+                }
             }
         }
-    }
+        __syncthreads();
+    }   // chunk loop
 }
 
 // ============================================================== 2D
-template <typename T, int MODE, int WPB, bool REMAP>
+template <typename T, int MODE, int WPB, bool REMAP, bool NTL>
 __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
     constexpr int NT = 3, CPW = 21, NLOC = 9, BUF = 36;
     constexpr bool FWD = (MODE & (OP_A | OP_B)) != 0;
@@ -382,20 +523,30 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
     __shared__ T sbuf[WPB][CPW][BUF];
     __shared__ double pbuf[(MODE & OP_B) ? WPB : 1][CPW][NT][4];
 
+    __shared__ T xb[WPB][CPW][6];
+    __shared__ T xcarry[WPB][2][6];
+    __shared__ double pxb[(MODE & OP_B) ? WPB : 1][CPW][2];
+    __shared__ double pcarry[(MODE & OP_B) ? WPB : 1][2][2];
+
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane / NT, t = lane - slot * NT;
     const bool inwave = slot < CPW;
     const int64_t lb = REMAP ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    const int64_t cell = a.cbeg + (lb * WPB + wave) * CPW + slot;
-    const bool act = inwave && cell < a.cend;
+    const int64_t row = lb * WPB + wave;
+    const bool rowact = row < a.nrows;
     T* B = sbuf[wave][inwave ? slot : 0];
     const int64_t P = a.plane;
+
+    for (int ch = 0; ch < a.nchunks; ++ch) {
+    const int ix = ch * CPW + slot;
+    const bool act = rowact && inwave && ix < a.nx;
+    const int64_t cell = a.cbeg + row * a.nx + ix;   // phase cells are stored row by row
 
     T val[2][3], g0[2][3], g1[2][3];
     if constexpr (FWD) {
         T uu[2][3];
         if (act) {
-            const uint32_t dm = a.dmask[cell];
+            const uint32_t dm = a.info[cell].x;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const int ln = t + 3 * j;
@@ -474,7 +625,7 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int aa = 0; aa < 2; ++aa) Km[b][aa] = act ? a.K[(b * 2 + aa) * P + off] : T(0);
+            for (int aa = 0; aa < 2; ++aa) Km[b][aa] = act ? gload<NTL>(a.K + (b * 2 + aa) * P + off) : T(0);
         T Tm[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
         divq[qx] = T(0);
         if constexpr (FWD) {
@@ -485,8 +636,8 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
                 for (int aa = 0; aa < 2; ++aa) H[c][aa] = g0[c][qx] * Km[0][aa] + g1[c][qx] * Km[1][aa];
             if constexpr ((MODE & OP_B) != 0) divq[qx] = H[0][0] + H[1][1];
             if constexpr ((MODE & OP_A) != 0) {
-                const T cvisc = act ? a.cv[off] : T(0);
-                const T cmass = act ? a.cv[P + off] : T(0);
+                const T cvisc = act ? gload<NTL>(a.cv + off) : T(0);
+                const T cmass = act ? gload<NTL>(a.cv + P + off) : T(0);
                 Tm[0][0] = cvisc * H[0][0];
                 Tm[1][1] = cvisc * H[1][1];
                 const T e01 = T(0.5) * cvisc * (H[0][1] + H[1][0]);
@@ -526,14 +677,26 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
                 for (int ax = 0; ax < 2; ++ax) pbuf[wave][slot][t][ax + 2 * by] = double(ly[by] * r[ax]);
         }
         __syncthreads();
-        if (act) {
-            // 3 threads per cell, 4 vertices: thread t sums vertex t (and t = 0 also vertex 3)
-#pragma unroll
-            for (int rep = 0; rep < 2; ++rep) {
-                const int vtx = rep == 0 ? t : 3;
-                if (rep == 1 && t != 0) break;
-                double s = pbuf[wave][slot][0][vtx] + pbuf[wave][slot][1][vtx] + pbuf[wave][slot][2][vtx];
-                a.q[a.pmap[cell * 4 + vtx]] += s;
+        // thread t < 2 sums the vertices (0, t) and (1, t); the x-shared vertex (1, t)
+        // is added into the right neighbour's (0, t) along the row
+        double s0 = 0.0, s1 = 0.0;
+        if (inwave && t < 2) {
+            s0 = pbuf[wave][slot][0][2 * t] + pbuf[wave][slot][1][2 * t] + pbuf[wave][slot][2][2 * t];
+            s1 = pbuf[wave][slot][0][2 * t + 1] + pbuf[wave][slot][1][2 * t + 1] + pbuf[wave][slot][2][2 * t + 1];
+            pxb[wave][slot][t] = s1;
+        }
+        __syncthreads();
+        if (act && t < 2) {
+            if (ix > 0) s0 += slot > 0 ? pxb[wave][slot - 1][t] : pcarry[wave][(ch + 1) & 1][t];
+            const uint32_t pf = a.info[cell].z;
+            const int n0 = a.pmap[cell * 4 + 2 * t], n1 = a.pmap[cell * 4 + 2 * t + 1];
+            if ((pf >> (2 * t)) & 1u) a.q[n0] = s0;
+            else a.q[n0] += s0;
+            if (ix == a.nx - 1) {
+                if ((pf >> (2 * t + 1)) & 1u) a.q[n1] = s1;
+                else a.q[n1] += s1;
+            } else if (slot == CPW - 1) {
+                pcarry[wave][ch & 1][t] = s1;
             }
         }
     }
@@ -564,70 +727,110 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
                 }
         }
         __syncthreads();
+        T out[2][3];   // [comp][j] for the nodes (i, j) of this thread's column
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            T WS[3], WD[3];
+#pragma unroll
+            for (int q2 = 0; q2 < 3; ++q2) {
+                WS[q2] = inwave ? B[((c * 2 + 0) * 3 + q2) * 3 + t] : T(0);
+                WD[q2] = inwave ? B[((c * 2 + 1) * 3 + q2) * 3 + t] : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                T s = T(0);
+#pragma unroll
+                for (int q2 = 0; q2 < 3; ++q2) s += cS<T>(q2, j) * WS[q2] + cD<T>(q2, j) * WD[q2];
+                out[c][j] = s;
+            }
+        }
+        if (inwave && t == 2) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) xb[wave][slot][c * 3 + j] = out[c][j];
+        }
+        __syncthreads();
         if (act) {
-            const uint32_t dm = a.dmask[cell];
+            if (t == 0 && ix > 0) {
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                T WS[3], WD[3];
+                for (int c = 0; c < 2; ++c)
 #pragma unroll
-                for (int q2 = 0; q2 < 3; ++q2) {
-                    WS[q2] = B[((c * 2 + 0) * 3 + q2) * 3 + t];
-                    WD[q2] = B[((c * 2 + 1) * 3 + q2) * 3 + t];
-                }
+                    for (int j = 0; j < 3; ++j)
+                        out[c][j] += slot > 0 ? xb[wave][slot - 1][c * 3 + j] : xcarry[wave][(ch + 1) & 1][c * 3 + j];
+            }
+            if (t != 2 || ix == a.nx - 1) {
+                const uint4 inf = a.info[cell];
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    T s = T(0);
-#pragma unroll
-                    for (int q2 = 0; q2 < 3; ++q2) s += cS<T>(q2, j) * WS[q2] + cD<T>(q2, j) * WD[q2];
                     const int ln = t + 3 * j;
-                    if ((dm >> ln) & 1u) continue;
+                    if ((inf.x >> ln) & 1u) continue;
                     const int node = a.vmap[cell * NLOC + ln];
-                    a.v[c * a.nvn + node] += s;
+                    if ((inf.y >> ln) & 1u) {
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) a.v[c * a.nvn + node] = out[c][j];
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) a.v[c * a.nvn + node] += out[c][j];
+                    }
                 }
+            } else if (slot == CPW - 1) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) xcarry[wave][ch & 1][c * 3 + j] = out[c][j];
             }
         }
     }
+    __syncthreads();
+    }   // chunk loop
 }
 
 // ============================================================== launchers
-// variant: bits 0-1 waves per block (0:1, 1:2, 2:4), bit 2: disable XCD remap
-constexpr int kNumVariants = 6;
-
-template <typename T, int MODE, int WPB, bool REMAP>
-static void launch_one(const Level& L, const CellArgs<T>& args, int64_t ncell, hipStream_t s) {
-    const int cpw = L.dim == 3 ? Shape<3>::CPW : Shape<2>::CPW;
-    const int64_t per_block = (int64_t)cpw * WPB;
-    const int64_t grid = (ncell + per_block - 1) / per_block;
+// Phase p holds whole rows of cells (cells[0] each); one wavefront walks a row.
+template <typename T, int MODE, int WPB, bool NTL, int WPE>
+static void launch_one(const Level& L, const CellArgs<T>& args, hipStream_t s) {
+    const int64_t grid = (args.nrows + WPB - 1) / WPB;   // one wavefront per row of cells
     if (grid <= 0) return;
     if (L.dim == 3)
-        hipLaunchKernelGGL((cell3d<T, MODE, WPB, REMAP>), dim3((unsigned)grid), dim3(64 * WPB), 0, s, args);
+        hipLaunchKernelGGL((cell3d<T, MODE, WPB, false, NTL, WPE>), dim3((unsigned)grid), dim3(64 * WPB), 0, s, args);
     else
-        hipLaunchKernelGGL((cell2d<T, MODE, WPB, REMAP>), dim3((unsigned)grid), dim3(64 * WPB), 0, s, args);
+        hipLaunchKernelGGL((cell2d<T, MODE, WPB, false, NTL>), dim3((unsigned)grid), dim3(64 * WPB), 0, s, args);
 }
 
+// variant bit 0: two wavefronts per workgroup (else one); bit 1: ask the compiler
+// for two wavefronts per SIMD (register cap) instead of one; bit 2: plain
+// (cached) geometry loads instead of non-temporal ones.
 template <typename T, int MODE>
-static void launch_mode(const Level& L, int variant, const CellArgs<T>& args, int64_t ncell, hipStream_t s) {
-    switch (variant) {
-        case 0: launch_one<T, MODE, 1, true>(L, args, ncell, s); break;
-        case 1: launch_one<T, MODE, 2, true>(L, args, ncell, s); break;
-        case 2: launch_one<T, MODE, 4, true>(L, args, ncell, s); break;
-        case 3: launch_one<T, MODE, 1, false>(L, args, ncell, s); break;
-        case 4: launch_one<T, MODE, 2, false>(L, args, ncell, s); break;
-        default: launch_one<T, MODE, 4, false>(L, args, ncell, s); break;
+static void launch_mode(const Level& L, int variant, const CellArgs<T>& args, hipStream_t s) {
+    switch (variant & 7) {
+        case 0: launch_one<T, MODE, 1, true, 1>(L, args, s); break;
+        case 1: launch_one<T, MODE, 2, true, 1>(L, args, s); break;
+        case 2: launch_one<T, MODE, 1, true, 2>(L, args, s); break;
+        case 3: launch_one<T, MODE, 2, true, 2>(L, args, s); break;
+        case 4: launch_one<T, MODE, 1, false, 1>(L, args, s); break;
+        case 5: launch_one<T, MODE, 2, false, 1>(L, args, s); break;
+        case 6: launch_one<T, MODE, 1, false, 2>(L, args, s); break;
+        default: launch_one<T, MODE, 2, false, 2>(L, args, s); break;
     }
 }
 
 template <typename T>
-void launch_cell(const Level& L, int mode, int variant, int color, const T* K, const T* cv, const T* u,
+void launch_cell(const Level& L, int mode, int variant, int phase, const T* K, const T* cv, const T* u,
                  const double* p, T* v, double* q, hipStream_t s) {
     CellArgs<T> args;
-    args.cbeg = L.color_off[color];
-    args.cend = L.color_off[color + 1];
+    args.cbeg = L.phase_off[phase];
+    args.cend = L.phase_off[phase + 1];
+    args.nx = L.cells[0];
+    args.nrows = (args.cend - args.cbeg) / L.cells[0];
+    const int cpw = L.dim == 3 ? Shape<3>::CPW : Shape<2>::CPW;
+    args.nchunks = (L.cells[0] + cpw - 1) / cpw;
+    args.wlast = L.cells[0] - (args.nchunks - 1) * cpw;
     args.nc = L.nc;
     args.nvn = L.nvn;
     args.plane = L.plane();
     args.vmap = L.d_vmap;
-    args.dmask = L.d_dmask;
+    args.info = L.d_info;
     args.pmap = L.d_pmap;
     args.K = K;
     args.cv = cv;
@@ -635,20 +838,19 @@ void launch_cell(const Level& L, int mode, int variant, int color, const T* K, c
     args.p = p;
     args.v = v;
     args.q = q;
-    const int64_t ncell = args.cend - args.cbeg;
     switch (mode) {
-        case OP_A: launch_mode<T, OP_A>(L, variant, args, ncell, s); break;
-        case OP_B: launch_mode<T, OP_B>(L, variant, args, ncell, s); break;
-        case OP_BT: launch_mode<T, OP_BT>(L, variant, args, ncell, s); break;
-        case OP_A | OP_BT: launch_mode<T, OP_A | OP_BT>(L, variant, args, ncell, s); break;
-        default: launch_mode<T, OP_A | OP_BT | OP_B>(L, variant, args, ncell, s); break;
+        case OP_A: launch_mode<T, OP_A>(L, variant, args, s); break;
+        case OP_B: launch_mode<T, OP_B>(L, variant, args, s); break;
+        case OP_BT: launch_mode<T, OP_BT>(L, variant, args, s); break;
+        case OP_A | OP_BT: launch_mode<T, OP_A | OP_BT>(L, variant, args, s); break;
+        default: launch_mode<T, OP_A | OP_BT | OP_B>(L, variant, args, s); break;
     }
 }
 
 template <typename T>
 void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T* cv, const T* u,
                      const double* p, T* v, double* q, hipStream_t s) {
-    for (int c = 0; c < L.ncolors; ++c) launch_cell<T>(L, mode, variant, c, K, cv, u, p, v, q, s);
+    for (int ph = 0; ph < L.nphases(); ++ph) launch_cell<T>(L, mode, variant, ph, K, cv, u, p, v, q, s);
 }
 
 template void launch_cell<double>(const Level&, int, int, int, const double*, const double*, const double*,

@@ -99,7 +99,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fsi_solve": (i, [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
         "fsi_autotune": (i, [vp]),
         "fsi_get_tuning": (i, [vp, i, i, C.POINTER(i), C.POINTER(d)]),
-        "fsi_time_operator": (i, [vp, i, i, i, i, C.POINTER(d), C.POINTER(d)]),
+        "fsi_time_operator": (i, [vp, i, i, i, i, C.POINTER(d), C.POINTER(d), C.POINTER(i)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -223,11 +223,13 @@ class Context:
         return v.value, us.value
 
     def time_operator(self, level: int, precision: int = 0, mode: int = 1, reps: int = 10):
-        """(mean colour-launch microseconds, mean operator microseconds) from HIP events."""
+        """(cell-kernel us per application, operator us per application, launches per application)."""
         k = C.c_double()
         o = C.c_double()
-        self._check(self.lib.fsi_time_operator(self.h, level, precision, mode, reps, C.byref(k), C.byref(o)))
-        return k.value, o.value
+        n = C.c_int()
+        self._check(self.lib.fsi_time_operator(self.h, level, precision, mode, reps, C.byref(k), C.byref(o),
+                                               C.byref(n)))
+        return k.value, o.value, n.value
 
     # ---------------------------------------------------------------- operators
     def _out(self, n, dtype):

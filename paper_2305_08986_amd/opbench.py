@@ -55,11 +55,11 @@ def main(argv=None):
     p = 0 if a.prec == "fp64" else 1
     if not a.no_autotune:
         ctx.autotune()
-    k_us, op_us = ctx.time_operator(lev, precision=p, mode=MODES[a.mode], reps=a.reps)
+    k_us, op_us, nl = ctx.time_operator(lev, precision=p, mode=MODES[a.mode], reps=a.reps)
     s = ctx.sizes(lev)
     out.update(dict(workload=a.workload, level=lev, mode=a.mode, prec=a.prec, reps=a.reps,
                     variant=ctx.tuning(lev, p)[0], n_cells=s["n_cells"], n_vel=s["n_vel"],
-                    colour_launch_us=k_us, operator_us=op_us,
+                    kernel_us=k_us, launches=nl, mean_launch_us=k_us / nl, operator_us=op_us,
                     gdofs=s["n_vel"] / (op_us * 1e-6) / 1e9))
     print(json.dumps(out), flush=True)
 
