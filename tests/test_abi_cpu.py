@@ -1,0 +1,93 @@
+"""The C-ABI library loads without a GPU and exports every function declared in
+include/fsi.h; the ctypes structures of the binding have the sizes and field
+offsets of a C compilation of the header."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fsi.h")
+
+
+def _lib_path():
+    from paper_2305_08986_amd import fsi
+    if not os.path.exists(fsi.LIB_PATH):
+        from paper_2305_08986_amd import build
+        build.build(verbose=False)
+    return fsi.LIB_PATH
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fsi_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib_path())
+    names = _declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_2305_08986_amd import fsi
+    lib = fsi.load_library(_lib_path())
+    for n in _declared_functions():
+        assert getattr(lib, n).argtypes is not None or n in ("fsi_destroy",), n
+
+
+def test_struct_layouts_match_c_header():
+    from paper_2305_08986_amd import fsi
+    structs = {"fsi_mesh_desc": fsi.MeshDesc, "fsi_sizes": fsi.Sizes, "fsi_mg_params": fsi.MGParams,
+               "fsi_level_info": fsi.LevelInfo, "fsi_solve_opts": fsi.SolveOpts, "fsi_solve_info": fsi.SolveInfo}
+    src = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        src.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            src.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    src.append("return 0; }")
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write("\n".join(src))
+        subprocess.run(["gcc", "-std=c99", "-o", exe, c], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
+    ref = dict(line.split() for line in out if line.strip())
+    for cname, py in structs.items():
+        assert int(ref[cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(ref[f"{cname}.{fname}"]) == getattr(py, fname).offset, (cname, fname)
+
+
+def test_default_parameters_are_the_predictor_column():
+    """Table 4, predictor column: k_A = 4, m = 2, n = 1, k_S = 1, n_S = 1."""
+    from paper_2305_08986_amd import fsi
+    lib = fsi.load_library(_lib_path())
+    p = fsi.MGParams()
+    lib.fsi_default_mg_params(ctypes.byref(p))
+    assert (p.k_A, p.m, p.n_cycles, p.k_S, p.n_S) == (4, 2, 1, 1, 1)
+
+
+def test_invalid_mesh_is_rejected_without_gpu_work():
+    """Argument checks run before any device call."""
+    from paper_2305_08986_amd import fsi
+    lib = fsi.load_library(_lib_path())
+    h = ctypes.c_void_p()
+    md = fsi.MeshDesc()
+    md.dim = 4
+    assert lib.fsi_create(ctypes.byref(h), ctypes.byref(md), None) == fsi.FSI_ERR_ARG
+    md.dim = 3
+    for k in range(3):
+        md.n_fine[k] = 12
+        md.n_coarse[k] = 5          # 12/5 is not a power of two
+        md.extent[k] = 1.0
+    assert lib.fsi_create(ctypes.byref(h), ctypes.byref(md), None) == fsi.FSI_ERR_ARG
+    for k in range(3):
+        md.n_coarse[k] = 3 if k < 2 else 6   # ratios 4, 4, 2 differ
+    assert lib.fsi_create(ctypes.byref(h), ctypes.byref(md), None) == fsi.FSI_ERR_ARG
