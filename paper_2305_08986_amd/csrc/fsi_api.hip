@@ -988,7 +988,7 @@ fsi_status fsi_solve(fsi_ctx* h, const double* g_u, const double* g_p, double* u
     TRY(dot64(ctx, K.r, K.r, n, &b2));
     double beta = std::sqrt(b2);
     push_hist(beta / gnorm);
-    int it = 0;
+    int it = 0, reorth = 0;
     const int R = o->restart;
     std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), sv(R + 1), y(R);
     fsi_status status = FSI_OK;
@@ -1008,16 +1008,28 @@ fsi_status fsi_solve(fsi_ctx* h, const double* g_u, const double* g_p, double* u
             double* Zk = K.Z + (int64_t)k * n;
             TRY(precond_combined(ctx, Vk, Zk, s));
             stokes_combined(ctx, Zk, K.w, s);
-            // classical Gram-Schmidt with one reorthogonalisation (two batched passes)
+            // classical Gram-Schmidt as batched passes over the basis; a second
+            // (reorthogonalising) pass only when the first cancelled most of w:
+            // ||w_after|| < ||w_before|| / sqrt(2)  (Daniel-Gragg-Kaufman-Stewart)
+            launch_dot<double>(K.w, K.w, n, K.partials, K.h + (R + 1), s);
             launch_multi_dot(K.V, n, k + 1, K.w, n, K.partials, K.h, s);
             launch_multi_axpy(K.V, n, k + 1, K.h, -1.0, K.w, n, s);
-            launch_multi_dot(K.V, n, k + 1, K.w, n, K.partials, K.h + (R + 2), s);
-            launch_multi_axpy(K.V, n, k + 1, K.h + (R + 2), -1.0, K.w, n, s);
             launch_dot<double>(K.w, K.w, n, K.partials, K.h + (k + 1), s);
-            FSI_HIP_TRY(hipMemcpyAsync(K.h_host, K.h, sizeof(double) * 2 * (R + 2), hipMemcpyDeviceToHost, s));
+            FSI_HIP_TRY(hipMemcpyAsync(K.h_host, K.h, sizeof(double) * (R + 2), hipMemcpyDeviceToHost, s));
             FSI_HIP_TRY(hipStreamSynchronize(s));
-            const double hnext = std::sqrt(K.h_host[k + 1]);
-            for (int i = 0; i <= k; ++i) H[(size_t)i * R + k] = K.h_host[i] + K.h_host[(R + 2) + i];
+            for (int i = 0; i <= k; ++i) H[(size_t)i * R + k] = K.h_host[i];
+            double after = K.h_host[k + 1];
+            if (after < 0.5 * K.h_host[R + 1]) {
+                launch_multi_dot(K.V, n, k + 1, K.w, n, K.partials, K.h + (R + 2), s);
+                launch_multi_axpy(K.V, n, k + 1, K.h + (R + 2), -1.0, K.w, n, s);
+                launch_dot<double>(K.w, K.w, n, K.partials, K.h + (k + 1), s);
+                FSI_HIP_TRY(hipMemcpyAsync(K.h_host, K.h, sizeof(double) * 2 * (R + 2), hipMemcpyDeviceToHost, s));
+                FSI_HIP_TRY(hipStreamSynchronize(s));
+                for (int i = 0; i <= k; ++i) H[(size_t)i * R + k] += K.h_host[(R + 2) + i];
+                after = K.h_host[k + 1];
+                ++reorth;
+            }
+            const double hnext = std::sqrt(after);
             H[(size_t)(k + 1) * R + k] = hnext;
             for (int i = 0; i < k; ++i) {
                 const double a = H[(size_t)i * R + k], b = H[(size_t)(i + 1) * R + k];
@@ -1064,6 +1076,8 @@ fsi_status fsi_solve(fsi_ctx* h, const double* g_u, const double* g_p, double* u
     FSI_HIP_TRY(hipMemcpyAsync(p, K.x + nv, sizeof(double) * np, hipMemcpyDeviceToDevice, s));
     FSI_HIP_TRY(hipStreamSynchronize(s));
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (getenv("FSI_SOLVE_VERBOSE"))
+        fprintf(stderr, "[fsi solve] %d iterations, %d reorthogonalisations, %.1f ms\n", it, reorth, ms);
     if (info) {
         info->iters = it;
         info->final_rel_res = beta / gnorm;
