@@ -86,6 +86,12 @@ typedef struct {
     int n_eig;
     int precision;           /* FSI_PREC_FP64 or FSI_PREC_MIXED (switching needs no new setup) */
     int use_graph;           /* launch the V-cycle as a captured HIP graph (switching needs no new setup) */
+    int fused;               /* 1: Chebyshev steps and residuals fused into the cell kernel's
+                                last-touch epilogue; 0: separate vector kernels (same results
+                                up to rounding; switching needs no new setup) */
+    int tuned;               /* 1: autotuned launch variant per level and, with fused = 1, the
+                                fused or separate form per level, whichever fsi_autotune
+                                measured faster; 0: the default variant, fused everywhere */
 } fsi_mg_params;
 
 typedef struct {
@@ -145,7 +151,8 @@ fsi_status fsi_set_displacement(fsi_ctx* ctx, const double* disp);
 fsi_status fsi_set_coefficients(fsi_ctx* ctx, int level, const double* c_mass, const double* eta);
 
 /* Changing k_A, m, n_cycles or the Chebyshev/Lanczos settings requires a new
- * fsi_setup; precision and use_graph may change at any time.  Errors:
+ * fsi_setup; precision, use_graph, fused and tuned may change at any time
+ * (fused = tuned = use_graph = 0 with FP64 is the plain per-launch path).  Errors:
  * FSI_ERR_ARG (only k_S = n_S = 1 are implemented). */
 fsi_status fsi_set_mg_params(fsi_ctx* ctx, const fsi_mg_params* p);
 
@@ -190,14 +197,18 @@ fsi_status fsi_vcycle(fsi_ctx* ctx, const double* r_u, const double* r_p, double
 fsi_status fsi_solve(fsi_ctx* ctx, const double* g_u, const double* g_p, double* u, double* p,
                      const fsi_solve_opts* opts, fsi_solve_info* info);
 
-/* Autotuner: times the cell-kernel launch variants (cells per workgroup and
- * scatter strategy) on every level and precision and keeps the fastest.
- * Synchronises; results are reported through fsi_get_tuning. */
+/* Autotuner: times the cell-kernel launch variants (wavefronts per workgroup,
+ * register cap, cached or streaming geometry loads) for every operator class
+ * (A, A with the fused Chebyshev step, Stokes, Stokes with the fused residual,
+ * B, B^T), level and precision, and keeps the fastest of each.  Synchronises;
+ * fsi_get_tuning reports the choice for A. */
 fsi_status fsi_autotune(fsi_ctx* ctx);
 fsi_status fsi_get_tuning(const fsi_ctx* ctx, int level, int precision, int* variant, double* best_us);
 
 /* Measurement support: runs `reps` applications of the level operator
- * (mode bits 1 = A, 2 = B^T, 4 = B; 7 = fused Stokes) in the given precision on
+ * (mode bits 1 = A, 2 = B^T, 4 = B; 7 = fused Stokes; 9 = A with the fused
+ * Chebyshev epilogue, run with zero coefficients; 23 = Stokes with the fused
+ * residual epilogue) in the given precision on
  * internal work vectors, timing every launch of the cell kernel with HIP events
  * on the context's stream.  kernel_us = cell-kernel time of one application
  * (sum over its n_launches launches: processing phases = slabs x colours),

@@ -187,6 +187,7 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
             bool f, l;
             touch_bits(ci, li, 1, f, l);
             if (f) inf.z |= 1u << n;
+            if (l) inf.z |= 1u << (16 + n);
         }
         info[k] = inf;
     }
@@ -261,9 +262,11 @@ static fsi_status alloc_work(Context* ctx) {
     return FSI_OK;
 }
 
-static int variant_of(const Context* ctx, int prec, int level) {
+static int variant_of(const Context* ctx, int prec, int level, int mode) {
+    if (!ctx->prm.tuned) return 0;
     const auto& v = ctx->tune_variant[prec];
-    return level < (int)v.size() ? v[level] : 0;
+    const size_t k = (size_t)level * kTuneClasses + tune_class(mode);
+    return k < v.size() ? v[k] : 0;
 }
 
 // ---------------------------------------------------------------- operators
@@ -272,7 +275,7 @@ static void op_apply(Context* ctx, int j, int mode, const T* u, const double* p,
     // every output entry is written by its first touching cell (no clearing pass);
     // wall rows: identity for A, zero for B^T alone
     const Level& L = ctx->lv[j];
-    launch_cell_all<T>(L, mode, variant_of(ctx, prec_index<T>(), j), Kp<T>(L), CVp<T>(L), u, p, v, q, s);
+    launch_cell_all<T>(L, mode, variant_of(ctx, prec_index<T>(), j, mode), Kp<T>(L), CVp<T>(L), u, p, v, q, s);
     if (mode & OP_A) launch_dirichlet_copy<T>(L, u, v, s);
     else if (mode & OP_BT) launch_dirichlet_zero<T>(L, v, s);
 }
@@ -288,8 +291,18 @@ static void cheb(Context* ctx, int j, const T* r, T* x, hipStream_t s) {
     launch_cheb_init<T>(DAp<T>(L), r, x, W.cd_u, 1.0 / theta, L.nv, s);
     for (int i = 1; i < ctx->prm.k_A; ++i) {
         const double rn = 1.0 / (2.0 * sigma - rho);
-        op_apply<T>(ctx, j, OP_A, x, nullptr, W.cax_u, nullptr, s);
-        launch_cheb_step<T>(DAp<T>(L), r, W.cax_u, x, W.cd_u, rn * rho, 2.0 * rn / delta, L.nv, s);
+        const double c1 = rn * rho, c2 = 2.0 * rn / delta;
+        if (ctx->prm.fused && (!ctx->prm.tuned || ctx->fuse_cheb[prec_index<T>()][j])) {
+            // the update happens at each node's last touch; the last step needs no direction
+            const bool store_d = i + 1 < ctx->prm.k_A;
+            launch_cell_cheb_all<T>(L, variant_of(ctx, prec_index<T>(), j, OP_A | OP_CHEB), Kp<T>(L), CVp<T>(L), x,
+                                    W.cd_u, r,
+                                    DAp<T>(L), W.cax_u, c1, c2, store_d, s);
+            launch_dirichlet_cheb<T>(L, x, W.cd_u, r, DAp<T>(L), c1, c2, store_d, s);
+        } else {
+            op_apply<T>(ctx, j, OP_A, x, nullptr, W.cax_u, nullptr, s);
+            launch_cheb_step<T>(DAp<T>(L), r, W.cax_u, x, W.cd_u, c1, c2, L.nv, s);
+        }
         rho = rn;
     }
 }
@@ -317,6 +330,13 @@ template <typename T>
 static void residual(Context* ctx, int j, hipStream_t s) {
     const Level& L = ctx->lv[j];
     LevelWork<T>& W = works<T>(ctx)[j];
+    if (ctx->prm.fused && (!ctx->prm.tuned || ctx->fuse_res[prec_index<T>()][j])) {
+        launch_cell_res_all<T>(L, variant_of(ctx, prec_index<T>(), j, OP_A | OP_BT | OP_B | OP_RES), Kp<T>(L),
+                               CVp<T>(L), W.x_u, W.x_p, W.f_u,
+                               W.f_p, W.r_u, W.r_p, s);
+        launch_dirichlet_res<T>(L, W.f_u, W.x_u, W.r_u, s);
+        return;
+    }
     op_apply<T>(ctx, j, OP_A | OP_BT | OP_B, W.x_u, W.x_p, W.r_u, W.r_p, s);
     launch_sub<T>(W.f_u, W.r_u, W.r_u, L.nv, s);
     launch_sub<double>(W.f_p, W.r_p, W.r_p, L.np, s);
@@ -367,8 +387,12 @@ static void vcycle_body(Context* ctx, hipStream_t s) {
     launch_cast<double, double>(ctx->vc_out_p, W.x_p, L.np, s);
 }
 
+static fsi_status capture_graphs(Context* ctx);
+
 static fsi_status run_vcycle(Context* ctx, hipStream_t s) {
     const int pi = ctx->prm.precision == FSI_PREC_MIXED ? 1 : 0;
+    const int key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0);
+    if (ctx->prm.use_graph && ctx->graph_valid[pi] && ctx->graph_key != key) TRY(capture_graphs(ctx));
     if (ctx->prm.use_graph && ctx->graph_valid[pi]) {
         FSI_HIP_TRY(hipGraphLaunch(ctx->graph[pi], s));
     } else if (pi == 1) {
@@ -400,6 +424,7 @@ static fsi_status capture_graphs(Context* ctx) {
         ctx->graph_valid[pi] = true;
     }
     hipStreamDestroy(cs);
+    ctx->graph_key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0);
     return FSI_OK;
 }
 
@@ -620,6 +645,8 @@ void fsi_default_mg_params(fsi_mg_params* p) {
     p->n_eig = 12;
     p->precision = FSI_PREC_FP64;
     p->use_graph = 1;
+    p->fused = 1;
+    p->tuned = 1;
 }
 
 fsi_status fsi_create(fsi_ctx** out, const fsi_mesh_desc* m, void* hip_stream) {
@@ -663,8 +690,10 @@ fsi_status fsi_create(fsi_ctx** out, const fsi_mesh_desc* m, void* hip_stream) {
     if (st == FSI_OK && hipHostMalloc((void**)&ctx->h_flag, sizeof(int) * 4) != hipSuccess) st = FSI_ERR_HIP;
     if (st == FSI_OK && hipHostMalloc((void**)&ctx->h_dbl, sizeof(double) * 64) != hipSuccess) st = FSI_ERR_HIP;
     for (int pi = 0; pi < 2; ++pi) {
-        ctx->tune_variant[pi].assign(ctx->nlev, 0);
-        ctx->tune_us[pi].assign(ctx->nlev, 0.0);
+        ctx->tune_variant[pi].assign((size_t)ctx->nlev * kTuneClasses, 0);
+        ctx->tune_us[pi].assign((size_t)ctx->nlev * kTuneClasses, 0.0);
+        ctx->fuse_cheb[pi].assign(ctx->nlev, 1);
+        ctx->fuse_res[pi].assign(ctx->nlev, 1);
     }
     if (st != FSI_OK) {
         fsi_destroy(h);
@@ -1089,6 +1118,31 @@ fsi_status fsi_solve(fsi_ctx* h, const double* g_u, const double* g_p, double* u
     return beta / gnorm <= o->rtol ? FSI_OK : FSI_NOT_CONVERGED;
 }
 
+// one processing phase of a level operator on the level's work vectors (timing and
+// tuning only: the fused Chebyshev mode runs with c1 = c2 = 0, so it leaves x as is)
+static void launch_phase_on_work(Context* ctx, int prec, int j, int mode, int var, int ph, hipStream_t s) {
+    const Level& L = ctx->lv[j];
+    if (prec == 0) {
+        LevelWork<double>& W = ctx->w64[j];
+        if (mode == (OP_A | OP_CHEB))
+            launch_cell_cheb<double>(L, var, ph, L.d_K64, L.d_cv64, W.w_u, W.cd_u, W.f_u, L.d_dAinv64, W.cax_u, 0.0,
+                                     0.0, true, s);
+        else if (mode == (OP_A | OP_BT | OP_B | OP_RES))
+            launch_cell_res<double>(L, var, ph, L.d_K64, L.d_cv64, W.x_u, W.x_p, W.f_u, W.f_p, W.r_u, W.r_p, s);
+        else
+            launch_cell<double>(L, mode, var, ph, L.d_K64, L.d_cv64, W.x_u, W.x_p, W.r_u, W.r_p, s);
+    } else {
+        LevelWork<float>& W = ctx->w32[j];
+        if (mode == (OP_A | OP_CHEB))
+            launch_cell_cheb<float>(L, var, ph, L.d_K32, L.d_cv32, W.w_u, W.cd_u, W.f_u, L.d_dAinv32, W.cax_u, 0.0,
+                                    0.0, true, s);
+        else if (mode == (OP_A | OP_BT | OP_B | OP_RES))
+            launch_cell_res<float>(L, var, ph, L.d_K32, L.d_cv32, W.x_u, W.x_p, W.f_u, W.f_p, W.r_u, W.r_p, s);
+        else
+            launch_cell<float>(L, mode, var, ph, L.d_K32, L.d_cv32, W.x_u, W.x_p, W.r_u, W.r_p, s);
+    }
+}
+
 fsi_status fsi_autotune(fsi_ctx* h) {
     if (!h) return FSI_ERR_ARG;
     Context* ctx = &h->c;
@@ -1102,38 +1156,74 @@ fsi_status fsi_autotune(fsi_ctx* h) {
     FSI_HIP_TRY(hipEventCreate(&e0));
     FSI_HIP_TRY(hipEventCreate(&e1));
     for (int pi = 0; pi < 2; ++pi)
-        for (int j = 0; j < ctx->nlev; ++j) {
-            const Level& L = ctx->lv[j];
-            double best = 1e300;
-            int bestv = 0;
-            for (int var = 0; var < kNumVariants; ++var) {
-                ctx->tune_variant[pi][j] = var;
-                const int reps = 3;
-                for (int r = 0; r <= reps; ++r) {
-                    if (r == 1) FSI_HIP_TRY(hipEventRecord(e0, s));
-                    if (pi == 0) {
-                        LevelWork<double>& W = ctx->w64[j];
-                        op_apply<double>(ctx, j, OP_A | OP_BT | OP_B, W.x_u, W.x_p, W.r_u, W.r_p, s);
-                    } else {
-                        LevelWork<float>& W = ctx->w32[j];
-                        op_apply<float>(ctx, j, OP_A | OP_BT | OP_B, W.x_u, W.x_p, W.r_u, W.r_p, s);
+        for (int j = 0; j < ctx->nlev; ++j)
+            for (int cls = 0; cls < kTuneClasses; ++cls) {
+                const int mode = kTuneModes[cls];
+                double best = 1e300;
+                int bestv = 0;
+                for (int var = 0; var < kNumVariants; ++var) {
+                    const int reps = 3;
+                    for (int r = 0; r <= reps; ++r) {
+                        if (r == 1) FSI_HIP_TRY(hipEventRecord(e0, s));
+                        for (int ph = 0; ph < ctx->lv[j].nphases(); ++ph)
+                            launch_phase_on_work(ctx, pi, j, mode, var, ph, s);
+                    }
+                    FSI_HIP_TRY(hipEventRecord(e1, s));
+                    FSI_HIP_TRY(hipEventSynchronize(e1));
+                    float ms = 0;
+                    FSI_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    const double us = 1000.0 * ms / reps;
+                    if (getenv("FSI_TUNE_VERBOSE"))
+                        fprintf(stderr, "[fsi autotune] precision %d level %d mode %d variant %d: %.1f us\n", pi, j,
+                                mode, var, us);
+                    if (us < best) {
+                        best = us;
+                        bestv = var;
                     }
                 }
-                FSI_HIP_TRY(hipEventRecord(e1, s));
-                FSI_HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0;
-                FSI_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                const double us = 1000.0 * ms / reps;
-                if (getenv("FSI_TUNE_VERBOSE"))
-                    fprintf(stderr, "[fsi autotune] precision %d level %d variant %d: %.1f us\n", pi, j, var, us);
-                if (us < best) {
-                    best = us;
-                    bestv = var;
-                }
+                ctx->tune_variant[pi][(size_t)j * kTuneClasses + cls] = bestv;
+                ctx->tune_us[pi][(size_t)j * kTuneClasses + cls] = best;
             }
-            ctx->tune_variant[pi][j] = bestv;
-            ctx->tune_us[pi][j] = best;
-            (void)L;
+    // fused epilogues against operator + separate vector kernel, each with its tuned variant
+    auto timed = [&](auto&& body, double* us) -> fsi_status {
+        body();
+        FSI_HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r) body();
+        FSI_HIP_TRY(hipEventRecord(e1, s));
+        FSI_HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        FSI_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        *us = 1000.0 * ms / 3;
+        return FSI_OK;
+    };
+    for (int pi = 0; pi < 2; ++pi)
+        for (int j = 0; j < ctx->nlev; ++j) {
+            const Level& L = ctx->lv[j];
+            auto var = [&](int mode) { return ctx->tune_variant[pi][(size_t)j * kTuneClasses + tune_class(mode)]; };
+            auto all = [&](int mode) {
+                for (int ph = 0; ph < L.nphases(); ++ph) launch_phase_on_work(ctx, pi, j, mode, var(mode), ph, s);
+            };
+            double sep_c = 0, fus_c = 0, sep_r = 0, fus_r = 0;
+            if (pi == 0) {
+                LevelWork<double>& W = ctx->w64[j];
+                TRY(timed([&] { all(OP_A); launch_cheb_step<double>(L.d_dAinv64, W.f_u, W.cax_u, W.w_u, W.cd_u, 0.0, 0.0, L.nv, s); }, &sep_c));
+                TRY(timed([&] { all(OP_A | OP_CHEB); launch_dirichlet_cheb<double>(L, W.w_u, W.cd_u, W.f_u, L.d_dAinv64, 0.0, 0.0, true, s); }, &fus_c));
+                TRY(timed([&] { all(OP_A | OP_BT | OP_B); launch_dirichlet_copy<double>(L, W.x_u, W.r_u, s);
+                                launch_sub<double>(W.f_u, W.r_u, W.r_u, L.nv, s); launch_sub<double>(W.f_p, W.r_p, W.r_p, L.np, s); }, &sep_r));
+                TRY(timed([&] { all(OP_A | OP_BT | OP_B | OP_RES); launch_dirichlet_res<double>(L, W.f_u, W.x_u, W.r_u, s); }, &fus_r));
+            } else {
+                LevelWork<float>& W = ctx->w32[j];
+                TRY(timed([&] { all(OP_A); launch_cheb_step<float>(L.d_dAinv32, W.f_u, W.cax_u, W.w_u, W.cd_u, 0.0, 0.0, L.nv, s); }, &sep_c));
+                TRY(timed([&] { all(OP_A | OP_CHEB); launch_dirichlet_cheb<float>(L, W.w_u, W.cd_u, W.f_u, L.d_dAinv32, 0.0, 0.0, true, s); }, &fus_c));
+                TRY(timed([&] { all(OP_A | OP_BT | OP_B); launch_dirichlet_copy<float>(L, W.x_u, W.r_u, s);
+                                launch_sub<float>(W.f_u, W.r_u, W.r_u, L.nv, s); launch_sub<double>(W.f_p, W.r_p, W.r_p, L.np, s); }, &sep_r));
+                TRY(timed([&] { all(OP_A | OP_BT | OP_B | OP_RES); launch_dirichlet_res<float>(L, W.f_u, W.x_u, W.r_u, s); }, &fus_r));
+            }
+            ctx->fuse_cheb[pi][j] = fus_c < sep_c ? 1 : 0;
+            ctx->fuse_res[pi][j] = fus_r < sep_r ? 1 : 0;
+            if (getenv("FSI_TUNE_VERBOSE"))
+                fprintf(stderr, "[fsi autotune] precision %d level %d chebyshev step %.1f us separate / %.1f us fused; "
+                        "residual %.1f us separate / %.1f us fused\n", pi, j, sep_c, fus_c, sep_r, fus_r);
         }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -1144,8 +1234,9 @@ fsi_status fsi_autotune(fsi_ctx* h) {
 
 fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int reps, double* kernel_us,
                              double* op_us, int* n_launches) {
-    if (!h || !kernel_us || !op_us || !n_launches || reps < 1 || (precision != 0 && precision != 1) || mode < 1 ||
-        mode > 7)
+    const bool fused_mode = mode == (OP_A | OP_CHEB) || mode == (OP_A | OP_BT | OP_B | OP_RES);
+    if (!h || !kernel_us || !op_us || !n_launches || reps < 1 || (precision != 0 && precision != 1) ||
+        ((mode < 1 || mode > 7) && !fused_mode))
         return FSI_ERR_ARG;
     Context* ctx = &h->c;
     TRY(apply_check(ctx, level, (mode & OP_A) != 0));
@@ -1156,7 +1247,7 @@ fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int
     const int nph = L.nphases();
     std::vector<hipEvent_t> ev((size_t)2 * nph + 2);
     for (auto& e : ev) FSI_HIP_TRY(hipEventCreate(&e));
-    const int var = variant_of(ctx, precision, level);
+    const int var = variant_of(ctx, precision, level, mode);
     double ksum = 0.0, osum = 0.0;
     int launched = 0;
     for (int r = 0; r < reps; ++r) {
@@ -1165,13 +1256,7 @@ fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int
         for (int ph = 0; ph < nph; ++ph) {
             FSI_HIP_TRY(hipEventRecord(ev[1 + 2 * ph], s));
             if (L.phase_off[ph + 1] > L.phase_off[ph]) ++launched;
-            if (precision == 0) {
-                LevelWork<double>& W = ctx->w64[level];
-                launch_cell<double>(L, mode, var, ph, L.d_K64, L.d_cv64, W.x_u, W.x_p, W.r_u, W.r_p, s);
-            } else {
-                LevelWork<float>& W = ctx->w32[level];
-                launch_cell<float>(L, mode, var, ph, L.d_K32, L.d_cv32, W.x_u, W.x_p, W.r_u, W.r_p, s);
-            }
+            launch_phase_on_work(ctx, precision, level, mode, var, ph, s);
             FSI_HIP_TRY(hipEventRecord(ev[2 + 2 * ph], s));
         }
         if (precision == 0) {
@@ -1205,8 +1290,8 @@ fsi_status fsi_get_tuning(const fsi_ctx* h, int level, int precision, int* varia
     if (!h || !variant || !best_us) return FSI_ERR_ARG;
     const Context* ctx = &h->c;
     if (level < 0 || level >= ctx->nlev || (precision != 0 && precision != 1)) return FSI_ERR_ARG;
-    *variant = ctx->tune_variant[precision][level];
-    *best_us = ctx->tune_us[precision][level];
+    *variant = ctx->tune_variant[precision][(size_t)level * kTuneClasses];       // class A
+    *best_us = ctx->tune_us[precision][(size_t)level * kTuneClasses];
     return FSI_OK;
 }
 

@@ -37,8 +37,10 @@ template <int DIM> struct Shape;
 template <> struct Shape<2> { static constexpr int NT = 3, CPW = 21, NLOC = 9, NPL = 4, Q = 9, NK = 4; };
 template <> struct Shape<3> { static constexpr int NT = 9, CPW = 7, NLOC = 27, NPL = 8, Q = 27, NK = 9; };
 
-// operator mode bits of the cell kernel
-enum : int { OP_A = 1, OP_BT = 2, OP_B = 4 };
+// operator mode bits of the cell kernel; OP_CHEB (with OP_A) and OP_RES (with
+// OP_A | OP_BT | OP_B) replace the plain store at a node's last touch by a
+// Chebyshev update of the iterate or by the residual f - M u
+enum : int { OP_A = 1, OP_BT = 2, OP_B = 4, OP_CHEB = 8, OP_RES = 16 };
 
 // ---------------------------------------------------------------- error helpers
 #define FSI_HIP_TRY(expr)                                                          \
@@ -81,8 +83,9 @@ struct Level {
     int* d_vmap = nullptr;         // [nc][NLOC] Q2 node of local node
     int* d_pmap = nullptr;         // [nc][NPL]  Q1 node / vertex of local vertex
     // per cell: x = wall bits of the local Q2 nodes, y = first-touch bits of the
-    // local Q2 nodes, z = first-touch bits of the local vertices, w = last-touch
-    // bits of the local Q2 nodes (first/last in phase order)
+    // local Q2 nodes, z = first-touch bits of the local vertices (bits 0..7) and
+    // last-touch bits of the local vertices (bits 16..23), w = last-touch bits of
+    // the local Q2 nodes (first/last in phase order)
     uint4* d_info = nullptr;
     uint8_t* d_wall = nullptr;     // [nvn] 1: velocity node on a wall
     int* d_dir_nodes = nullptr;    // wall nodes
@@ -166,22 +169,53 @@ struct Context {
     double* vc_tmp = nullptr;      // [nv + np] residual of repeated V-cycles
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     bool graph_valid[2] = {false, false};
+    int graph_key = -1;            // (fused, tuned) the graphs were captured with
     // tuning: per level and precision, index into the launch-variant table
     std::vector<int> tune_variant[2];
     std::vector<double> tune_us[2];
+    // per level and precision: use the fused Chebyshev / residual epilogue (when the
+    // fused path is enabled); the autotuner keeps whichever it measured faster
+    std::vector<uint8_t> fuse_cheb[2], fuse_res[2];
     std::vector<void*> allocations;
 };
 
 // ---------------------------------------------------------------- launchers (kernels_*.hip)
 // cell operator on one colour range; mode = OP_* bits; variant selects the
 // workgroup size (wavefronts per workgroup) and block->tile mapping.
-constexpr int kNumVariants = 8;
+constexpr int kNumVariants = 12;
+// launch variants are tuned per operator class: A, A with the Chebyshev epilogue,
+// Stokes, Stokes with the residual epilogue, B, B^T
+constexpr int kTuneClasses = 6;
+constexpr int kTuneModes[kTuneClasses] = {OP_A, OP_A | OP_CHEB, OP_A | OP_BT | OP_B, OP_A | OP_BT | OP_B | OP_RES,
+                                          OP_B, OP_BT};
+inline int tune_class(int mode) {
+    for (int c = 0; c < kTuneClasses; ++c)
+        if (kTuneModes[c] == mode) return c;
+    return 2;   // A + B^T is timed as the Stokes class
+}
 template <typename T>
 void launch_cell(const Level& L, int mode, int variant, int phase, const T* K, const T* cv,
                  const T* u, const double* p, T* v, double* q, hipStream_t s);
 template <typename T>
 void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T* cv,
                      const T* u, const double* p, T* v, double* q, hipStream_t s);
+template <typename T>
+void launch_cell_cheb(const Level& L, int variant, int phase, const T* K, const T* cv, T* x, T* d, const T* r,
+                      const T* dinv, T* v, double c1, double c2, bool store_d, hipStream_t s);
+template <typename T>
+void launch_cell_res(const Level& L, int variant, int phase, const T* K, const T* cv, const T* u, const double* p,
+                     const T* f_u, const double* f_p, T* r_u, double* r_p, hipStream_t s);
+// one Chebyshev step fused into A x: at each node's last touch
+// d = c1 d + c2 dinv (r - A x), x += d (d is stored only if store_d); v holds the
+// partial sums of nodes touched by several phases.  Wall nodes are left alone.
+template <typename T>
+void launch_cell_cheb_all(const Level& L, int variant, const T* K, const T* cv, T* x, T* d, const T* r,
+                          const T* dinv, T* v, double c1, double c2, bool store_d, hipStream_t s);
+// residual fused into the Stokes apply: r_u = f_u - (A u + B^T p), r_p = f_p - B u,
+// written at each node's last touch.  Wall nodes are left alone.
+template <typename T>
+void launch_cell_res_all(const Level& L, int variant, const T* K, const T* cv, const T* u, const double* p,
+                         const T* f_u, const double* f_p, T* r_u, double* r_p, hipStream_t s);
 
 void launch_geometry(const Level& L, const double* J, double* K, double* cw, float* K32, int* flag,
                      hipStream_t s);
@@ -201,6 +235,13 @@ template <typename T>
 void launch_dirichlet_copy(const Level& L, const T* u, T* v, hipStream_t s);   // v[wall] = u[wall]
 template <typename T>
 void launch_dirichlet_zero(const Level& L, T* v, hipStream_t s);
+// wall rows of the fused epilogues (identity rows of A): the Chebyshev step with
+// A x = x, and r = f - u
+template <typename T>
+void launch_dirichlet_cheb(const Level& L, T* x, T* d, const T* r, const T* dinv, double c1, double c2,
+                           bool store_d, hipStream_t s);
+template <typename T>
+void launch_dirichlet_res(const Level& L, const T* f, const T* u, T* r, hipStream_t s);
 template <typename TD, typename TS>
 void launch_cast(TD* d, const TS* src, int64_t n, hipStream_t s);
 

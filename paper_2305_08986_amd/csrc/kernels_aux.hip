@@ -409,6 +409,49 @@ void launch_dirichlet_zero(const Level& L, T* v, hipStream_t s) {
 template void launch_dirichlet_zero<double>(const Level&, double*, hipStream_t);
 template void launch_dirichlet_zero<float>(const Level&, float*, hipStream_t);
 
+template <typename T>
+__global__ void k_dir_cheb(const int* __restrict__ nodes, int64_t nd, int dim, int64_t nvn, T* __restrict__ x,
+                           T* __restrict__ d, const T* __restrict__ r, const T* __restrict__ dinv, T c1, T c2,
+                           int store_d) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nd) return;
+    const int64_t n = nodes[i];
+    for (int c = 0; c < dim; ++c) {
+        const int64_t k = c * nvn + n;
+        const T dn = c1 * d[k] + c2 * dinv[k] * (r[k] - x[k]);   // wall row of A: identity
+        if (store_d) d[k] = dn;
+        x[k] += dn;
+    }
+}
+template <typename T>
+void launch_dirichlet_cheb(const Level& L, T* x, T* d, const T* r, const T* dinv, double c1, double c2,
+                           bool store_d, hipStream_t s) {
+    if (L.n_dir > 0)
+        hipLaunchKernelGGL(k_dir_cheb<T>, dim3(nblocks(L.n_dir)), dim3(TPB), 0, s, L.d_dir_nodes, L.n_dir, L.dim,
+                           L.nvn, x, d, r, dinv, (T)c1, (T)c2, store_d ? 1 : 0);
+}
+template void launch_dirichlet_cheb<double>(const Level&, double*, double*, const double*, const double*, double,
+                                            double, bool, hipStream_t);
+template void launch_dirichlet_cheb<float>(const Level&, float*, float*, const float*, const float*, double, double,
+                                           bool, hipStream_t);
+
+template <typename T>
+__global__ void k_dir_res(const int* __restrict__ nodes, int64_t nd, int dim, int64_t nvn, const T* __restrict__ f,
+                          const T* __restrict__ u, T* __restrict__ r) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nd) return;
+    const int64_t n = nodes[i];
+    for (int c = 0; c < dim; ++c) r[c * nvn + n] = f[c * nvn + n] - u[c * nvn + n];
+}
+template <typename T>
+void launch_dirichlet_res(const Level& L, const T* f, const T* u, T* r, hipStream_t s) {
+    if (L.n_dir > 0)
+        hipLaunchKernelGGL(k_dir_res<T>, dim3(nblocks(L.n_dir)), dim3(TPB), 0, s, L.d_dir_nodes, L.n_dir, L.dim,
+                           L.nvn, f, u, r);
+}
+template void launch_dirichlet_res<double>(const Level&, const double*, const double*, double*, hipStream_t);
+template void launch_dirichlet_res<float>(const Level&, const float*, const float*, float*, hipStream_t);
+
 template <typename TD, typename TS>
 __global__ void k_cast(TD* __restrict__ d, const TS* __restrict__ s, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

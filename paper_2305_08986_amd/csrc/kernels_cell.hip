@@ -61,6 +61,15 @@ struct CellArgs {
     const double* __restrict__ p;
     T* __restrict__ v;
     double* __restrict__ q;
+    // fused epilogues (OP_CHEB: iterate x, direction d, right-hand side r, 1/diag A;
+    // OP_RES: right-hand sides r (velocity) and fp (pressure))
+    T* __restrict__ x;
+    T* __restrict__ d;
+    const T* __restrict__ r;
+    const T* __restrict__ dinv;
+    const double* __restrict__ fp;
+    T c1, c2;
+    int store_d;
 };
 
 // ============================================================== 3D
@@ -74,6 +83,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     constexpr bool HAS_B = (MODE & OP_B) != 0;
     constexpr bool HAS_BT = (MODE & OP_BT) != 0;
     constexpr bool HAS_A = (MODE & OP_A) != 0;
+    constexpr bool CHEB = (MODE & OP_CHEB) != 0;
+    constexpr bool RES = (MODE & OP_RES) != 0;
+    static_assert(!CHEB || MODE == (OP_A | OP_CHEB), "the Chebyshev epilogue goes with A alone");
+    static_assert(!RES || MODE == (OP_A | OP_BT | OP_B | OP_RES), "the residual epilogue goes with the Stokes apply");
     __shared__ T sbuf[WPB][CPW][BUF];
     __shared__ double pbuf[HAS_B ? WPB : 1][CPW][NT][8];
     // x-face hand-over between neighbouring cells of the row: [slot][j][comp][k],
@@ -115,14 +128,20 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             node[k] = act ? a.vmap[cell * NLOC + ln] : 0;
             const bool wall = (inf.x >> ln) & 1u;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) uu[c][k] = (FWD && act && !wall) ? a.u[c * a.nvn + node[k]] : T(0);
+            for (int c = 0; c < 3; ++c)
+                uu[c][k] = (FWD && act && !wall) ? (CHEB ? a.x : a.u)[c * a.nvn + node[k]] : T(0);
         }
         int pnode = 0;
-        double qold = 0.0;
+        double qold = 0.0;       // partial sum of earlier phases (RES at the last touch: f_p - partial)
+        bool plast = false;
         if constexpr (HAS_B) {
             if (pwriter) {
                 pnode = a.pmap[cell * 8 + t];
                 if (!((inf.z >> t) & 1u)) qold = a.q[pnode];
+                if constexpr (RES) {
+                    plast = (inf.z >> (16 + t)) & 1u;
+                    if (plast) qold = a.fp[pnode] - qold;
+                }
             }
         }
         T pv[8];
@@ -403,12 +422,18 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             __syncthreads();
             if (act && t < 8) {
                 if (pax == 0 && ix > 0) sq += slot > 0 ? pxb[wave][slot - 1][pyz] : pcarry[wave][(ch + 1) & 1][pyz];
-                if (pwriter) a.q[pnode] = qold + sq;
-                else if (slot == CPW - 1) pcarry[wave][ch & 1][pyz] = sq;
+                if (pwriter) {
+                    a.q[pnode] = plast ? qold - sq : qold + sq;
+                } else if (slot == CPW - 1) {
+                    pcarry[wave][ch & 1][pyz] = sq;
+                }
             }
         }
 
         // ---------------- backward sweeps y (B) and z (A), x-face hand-over, stores
+        // fused epilogue operands [comp][k]: partial sum of earlier phases, right-hand
+        // side, and for the Chebyshev step the iterate, direction and 1/diag A
+        T ep[3][3], er[3][3], ex[3][3], ed[3][3], eg[3][3];
         if constexpr (BWD) {
             __syncthreads();
             if (inwave) {
@@ -422,6 +447,28 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                     }
             }
             __syncthreads();
+            // ---------------- fused epilogue operands, fetched behind the barrier that
+            // ends stage C (so they do not add to its register peak) and combined only
+            // at the store, after the backward sweeps whose work hides their latency
+            if constexpr (CHEB || RES) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int ln = t + 9 * k;
+                    const bool last = vwriter && !((inf.x >> ln) & 1u) && ((inf.w >> ln) & 1u);
+                    const bool part = last && !((inf.y >> ln) & 1u);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int64_t i = c * a.nvn + node[k];
+                        ep[c][k] = part ? a.v[i] : T(0);
+                        er[c][k] = last ? a.r[i] : T(0);
+                        if constexpr (CHEB) {
+                            ex[c][k] = last ? a.x[i] : T(0);
+                            ed[c][k] = last ? a.d[i] : T(0);
+                            eg[c][k] = last ? a.dinv[i] : T(0);
+                        }
+                    }
+                }
+            }
             const int ib = t % 3, qzb = t / 3;
             T vs[3][3], vd[3][3];   // [comp][j]
 #pragma unroll
@@ -494,7 +541,22 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                     for (int k = 0; k < 3; ++k) {
                         const int ln = t + 9 * k;
                         if ((inf.x >> ln) & 1u) continue;
-                        if ((inf.y >> ln) & 1u) {   // first touch of the node in phase order
+                        const bool first = (inf.y >> ln) & 1u;   // first touch of the node in phase order
+                        if ((CHEB || RES) && ((inf.w >> ln) & 1u)) {
+                            // last touch: the row of A x (M u) is complete here
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) {
+                                const int64_t i = c * a.nvn + node[k];
+                                const T tot = ep[c][k] + out[c][k];
+                                if constexpr (CHEB) {
+                                    const T dn = a.c1 * ed[c][k] + a.c2 * eg[c][k] * (er[c][k] - tot);
+                                    if (a.store_d) a.d[i] = dn;
+                                    a.x[i] = ex[c][k] + dn;
+                                } else {
+                                    a.v[i] = er[c][k] - tot;
+                                }
+                            }
+                        } else if (first) {
 #pragma unroll
                             for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node[k]] = out[c][k];
                         } else {
@@ -520,6 +582,10 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
     constexpr int NT = 3, CPW = 21, NLOC = 9, BUF = 36;
     constexpr bool FWD = (MODE & (OP_A | OP_B)) != 0;
     constexpr bool BWD = (MODE & (OP_A | OP_BT)) != 0;
+    constexpr bool CHEB = (MODE & OP_CHEB) != 0;
+    constexpr bool RES = (MODE & OP_RES) != 0;
+    static_assert(!CHEB || MODE == (OP_A | OP_CHEB), "the Chebyshev epilogue goes with A alone");
+    static_assert(!RES || MODE == (OP_A | OP_BT | OP_B | OP_RES), "the residual epilogue goes with the Stokes apply");
     __shared__ T sbuf[WPB][CPW][BUF];
     __shared__ double pbuf[(MODE & OP_B) ? WPB : 1][CPW][NT][4];
 
@@ -553,7 +619,7 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
                 const int node = a.vmap[cell * NLOC + ln];
                 const bool wall = (dm >> ln) & 1u;
 #pragma unroll
-                for (int c = 0; c < 2; ++c) uu[c][j] = wall ? T(0) : a.u[c * a.nvn + node];
+                for (int c = 0; c < 2; ++c) uu[c][j] = wall ? T(0) : (CHEB ? a.x : a.u)[c * a.nvn + node];
             }
         } else {
 #pragma unroll
@@ -690,11 +756,13 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
             if (ix > 0) s0 += slot > 0 ? pxb[wave][slot - 1][t] : pcarry[wave][(ch + 1) & 1][t];
             const uint32_t pf = a.info[cell].z;
             const int n0 = a.pmap[cell * 4 + 2 * t], n1 = a.pmap[cell * 4 + 2 * t + 1];
-            if ((pf >> (2 * t)) & 1u) a.q[n0] = s0;
-            else a.q[n0] += s0;
+            {
+                const double tot = ((pf >> (2 * t)) & 1u) ? s0 : a.q[n0] + s0;
+                a.q[n0] = (RES && ((pf >> (16 + 2 * t)) & 1u)) ? a.fp[n0] - tot : tot;
+            }
             if (ix == a.nx - 1) {
-                if ((pf >> (2 * t + 1)) & 1u) a.q[n1] = s1;
-                else a.q[n1] += s1;
+                const double tot = ((pf >> (2 * t + 1)) & 1u) ? s1 : a.q[n1] + s1;
+                a.q[n1] = (RES && ((pf >> (16 + 2 * t + 1)) & 1u)) ? a.fp[n1] - tot : tot;
             } else if (slot == CPW - 1) {
                 pcarry[wave][ch & 1][t] = s1;
             }
@@ -766,7 +834,21 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
                     const int ln = t + 3 * j;
                     if ((inf.x >> ln) & 1u) continue;
                     const int node = a.vmap[cell * NLOC + ln];
-                    if ((inf.y >> ln) & 1u) {
+                    const bool first = (inf.y >> ln) & 1u;
+                    if ((CHEB || RES) && ((inf.w >> ln) & 1u)) {
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const int64_t i = c * a.nvn + node;
+                            const T tot = first ? out[c][j] : a.v[i] + out[c][j];
+                            if constexpr (CHEB) {
+                                const T dn = a.c1 * a.d[i] + a.c2 * a.dinv[i] * (a.r[i] - tot);
+                                if (a.store_d) a.d[i] = dn;
+                                a.x[i] += dn;
+                            } else {
+                                a.v[i] = a.r[i] - tot;
+                            }
+                        }
+                    } else if (first) {
 #pragma unroll
                         for (int c = 0; c < 2; ++c) a.v[c * a.nvn + node] = out[c][j];
                     } else {
@@ -798,27 +880,37 @@ static void launch_one(const Level& L, const CellArgs<T>& args, hipStream_t s) {
         hipLaunchKernelGGL((cell2d<T, MODE, WPB, false, NTL>), dim3((unsigned)grid), dim3(64 * WPB), 0, s, args);
 }
 
-// variant bit 0: two wavefronts per workgroup (else one); bit 1: ask the compiler
-// for two wavefronts per SIMD (register cap) instead of one; bit 2: plain
-// (cached) geometry loads instead of non-temporal ones.
+// launch variant v: v & 1 two wavefronts per workgroup (else one); v & 2 plain
+// (cached) geometry loads instead of non-temporal ones; v / 4 register cap: none,
+// or one or two wavefronts per SIMD more than the class reaches unconstrained
+// (spills allowed).  Unconstrained occupancy (3D): FP64 2 (A, B classes) or 1
+// (Stokes classes); FP32 3-4 (A, B classes) or 2 (Stokes classes).
+template <typename T, int MODE, int WPB, bool NTL>
+static void launch_capped(const Level& L, int cap, const CellArgs<T>& args, hipStream_t s) {
+    constexpr bool STOKES = (MODE & OP_A) && (MODE & OP_BT);
+    constexpr int W1 = sizeof(T) == 8 ? (STOKES ? 2 : 3) : (STOKES ? 3 : 4);
+    constexpr int W2 = sizeof(T) == 8 ? W1 : W1 + 1;   // FP64: a second step only spills more
+    switch (cap) {
+        case 0: launch_one<T, MODE, WPB, NTL, 1>(L, args, s); break;
+        case 1: launch_one<T, MODE, WPB, NTL, W1>(L, args, s); break;
+        default: launch_one<T, MODE, WPB, NTL, W2>(L, args, s); break;
+    }
+}
+
 template <typename T, int MODE>
 static void launch_mode(const Level& L, int variant, const CellArgs<T>& args, hipStream_t s) {
-    switch (variant & 7) {
-        case 0: launch_one<T, MODE, 1, true, 1>(L, args, s); break;
-        case 1: launch_one<T, MODE, 2, true, 1>(L, args, s); break;
-        case 2: launch_one<T, MODE, 1, true, 2>(L, args, s); break;
-        case 3: launch_one<T, MODE, 2, true, 2>(L, args, s); break;
-        case 4: launch_one<T, MODE, 1, false, 1>(L, args, s); break;
-        case 5: launch_one<T, MODE, 2, false, 1>(L, args, s); break;
-        case 6: launch_one<T, MODE, 1, false, 2>(L, args, s); break;
-        default: launch_one<T, MODE, 2, false, 2>(L, args, s); break;
+    const int cap = (variant >> 2) % 3;
+    switch (variant & 3) {
+        case 0: launch_capped<T, MODE, 1, true>(L, cap, args, s); break;
+        case 1: launch_capped<T, MODE, 2, true>(L, cap, args, s); break;
+        case 2: launch_capped<T, MODE, 1, false>(L, cap, args, s); break;
+        default: launch_capped<T, MODE, 2, false>(L, cap, args, s); break;
     }
 }
 
 template <typename T>
-void launch_cell(const Level& L, int mode, int variant, int phase, const T* K, const T* cv, const T* u,
-                 const double* p, T* v, double* q, hipStream_t s) {
-    CellArgs<T> args;
+static CellArgs<T> phase_args(const Level& L, int phase, const T* K, const T* cv) {
+    CellArgs<T> args{};
     args.cbeg = L.phase_off[phase];
     args.cend = L.phase_off[phase + 1];
     args.nx = L.cells[0];
@@ -834,6 +926,13 @@ void launch_cell(const Level& L, int mode, int variant, int phase, const T* K, c
     args.pmap = L.d_pmap;
     args.K = K;
     args.cv = cv;
+    return args;
+}
+
+template <typename T>
+void launch_cell(const Level& L, int mode, int variant, int phase, const T* K, const T* cv, const T* u,
+                 const double* p, T* v, double* q, hipStream_t s) {
+    CellArgs<T> args = phase_args<T>(L, phase, K, cv);
     args.u = u;
     args.p = p;
     args.v = v;
@@ -853,6 +952,47 @@ void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T*
     for (int ph = 0; ph < L.nphases(); ++ph) launch_cell<T>(L, mode, variant, ph, K, cv, u, p, v, q, s);
 }
 
+template <typename T>
+void launch_cell_cheb(const Level& L, int variant, int phase, const T* K, const T* cv, T* x, T* d, const T* r,
+                      const T* dinv, T* v, double c1, double c2, bool store_d, hipStream_t s) {
+    CellArgs<T> args = phase_args<T>(L, phase, K, cv);
+    args.v = v;
+    args.x = x;
+    args.d = d;
+    args.r = r;
+    args.dinv = dinv;
+    args.c1 = (T)c1;
+    args.c2 = (T)c2;
+    args.store_d = store_d ? 1 : 0;
+    launch_mode<T, OP_A | OP_CHEB>(L, variant, args, s);
+}
+
+template <typename T>
+void launch_cell_cheb_all(const Level& L, int variant, const T* K, const T* cv, T* x, T* d, const T* r,
+                          const T* dinv, T* v, double c1, double c2, bool store_d, hipStream_t s) {
+    for (int ph = 0; ph < L.nphases(); ++ph)
+        launch_cell_cheb<T>(L, variant, ph, K, cv, x, d, r, dinv, v, c1, c2, store_d, s);
+}
+
+template <typename T>
+void launch_cell_res(const Level& L, int variant, int phase, const T* K, const T* cv, const T* u, const double* p,
+                     const T* f_u, const double* f_p, T* r_u, double* r_p, hipStream_t s) {
+    CellArgs<T> args = phase_args<T>(L, phase, K, cv);
+    args.u = u;
+    args.p = p;
+    args.v = r_u;
+    args.q = r_p;
+    args.r = f_u;
+    args.fp = f_p;
+    launch_mode<T, OP_A | OP_BT | OP_B | OP_RES>(L, variant, args, s);
+}
+
+template <typename T>
+void launch_cell_res_all(const Level& L, int variant, const T* K, const T* cv, const T* u, const double* p,
+                         const T* f_u, const double* f_p, T* r_u, double* r_p, hipStream_t s) {
+    for (int ph = 0; ph < L.nphases(); ++ph) launch_cell_res<T>(L, variant, ph, K, cv, u, p, f_u, f_p, r_u, r_p, s);
+}
+
 template void launch_cell<double>(const Level&, int, int, int, const double*, const double*, const double*,
                                   const double*, double*, double*, hipStream_t);
 template void launch_cell<float>(const Level&, int, int, int, const float*, const float*, const float*,
@@ -861,5 +1001,22 @@ template void launch_cell_all<double>(const Level&, int, int, const double*, con
                                       const double*, double*, double*, hipStream_t);
 template void launch_cell_all<float>(const Level&, int, int, const float*, const float*, const float*,
                                      const double*, float*, double*, hipStream_t);
+template void launch_cell_cheb_all<double>(const Level&, int, const double*, const double*, double*, double*,
+                                           const double*, const double*, double*, double, double, bool, hipStream_t);
+template void launch_cell_cheb_all<float>(const Level&, int, const float*, const float*, float*, float*,
+                                          const float*, const float*, float*, double, double, bool, hipStream_t);
+template void launch_cell_cheb<double>(const Level&, int, int, const double*, const double*, double*, double*,
+                                       const double*, const double*, double*, double, double, bool, hipStream_t);
+template void launch_cell_cheb<float>(const Level&, int, int, const float*, const float*, float*, float*,
+                                      const float*, const float*, float*, double, double, bool, hipStream_t);
+template void launch_cell_res<double>(const Level&, int, int, const double*, const double*, const double*,
+                                      const double*, const double*, const double*, double*, double*, hipStream_t);
+template void launch_cell_res<float>(const Level&, int, int, const float*, const float*, const float*,
+                                     const double*, const float*, const double*, float*, double*, hipStream_t);
+template void launch_cell_res_all<double>(const Level&, int, const double*, const double*, const double*,
+                                          const double*, const double*, const double*, double*, double*,
+                                          hipStream_t);
+template void launch_cell_res_all<float>(const Level&, int, const float*, const float*, const float*,
+                                         const double*, const float*, const double*, float*, double*, hipStream_t);
 
 }  // namespace fsi

@@ -28,9 +28,10 @@ def _setup(name, **prm):
     return wl, ctx, ops
 
 
+@pytest.mark.parametrize("fused", [0, 1])
 @pytest.mark.parametrize("name", ["C0", "T2_R", "T3_4", "T3_R"])
-def test_vcycle_fp64_matches_oracle(name):
-    wl, ctx, ops = _setup(name, precision=0)
+def test_vcycle_fp64_matches_oracle(name, fused):
+    wl, ctx, ops = _setup(name, precision=0, fused=fused)
     h = solvers.Hierarchy(ops)
     for j in range(ctx.n_levels):
         li = ctx.level_info(j)
@@ -68,3 +69,48 @@ def test_fgmres_solution_matches_direct(name, prec):
     eu = np.linalg.norm(u - uo) / np.linalg.norm(uo)
     print("velocity error vs direct", eu)
     assert eu <= 1e3 * rtol
+
+
+def _vc(ctx, ru, rp, **prm):
+    ctx.set_mg_params(**prm)
+    zu, zp = ctx.vcycle(ru, rp)
+    torch.cuda.synchronize()
+    return zu.double().cpu().numpy(), zp.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["T2_R", "T3_R", "T3_8"])
+def test_fused_epilogues_equal_separate_kernels(name):
+    """The last-touch Chebyshev and residual epilogues compute the same V-cycle as
+    the separate vector kernels (identical arithmetic, so agreement to rounding),
+    eager and graph-launched, in both precisions, with default and tuned launches."""
+    wl, ctx, ops = _setup(name)
+    ctx.autotune()
+    rng = np.random.default_rng(11)
+    op = ops[-1]
+    ru = torch.from_numpy(rng.uniform(-1, 1, op.box.n_vel)).cuda()   # wall entries too
+    rp = torch.from_numpy(rng.uniform(-1, 1, op.box.n_p)).cuda()
+    for prec, tol in ((0, 1e-13), (1, 2e-5)):
+        ref_u, ref_p = _vc(ctx, ru, rp, precision=prec, fused=0, use_graph=0, tuned=0)
+        for fused, graph, tuned in ((1, 0, 0), (1, 0, 1), (1, 1, 1), (0, 1, 1)):
+            zu, zp = _vc(ctx, ru, rp, precision=prec, fused=fused, use_graph=graph, tuned=tuned)
+            eu = np.linalg.norm(zu - ref_u) / np.linalg.norm(ref_u)
+            ep = np.linalg.norm(zp - ref_p) / np.linalg.norm(ref_p)
+            print(name, prec, fused, graph, tuned, eu, ep)
+            assert eu <= tol and ep <= tol, (prec, fused, graph, tuned, eu, ep)
+
+
+def test_graph_replays_match_eager():
+    """Replays of the captured V-cycle, with eager work and synchronisations in
+    between, all reproduce the eager result."""
+    wl, ctx, ops = _setup("T3_R")
+    rng = np.random.default_rng(5)
+    op = ops[-1]
+    ru = torch.from_numpy(rng.uniform(-1, 1, op.box.n_vel) * ~op.dir_mask).cuda()
+    rp = torch.from_numpy(rng.uniform(-1, 1, op.box.n_p)).cuda()
+    for prec, tol in ((0, 1e-13), (1, 1e-6)):
+        eu, ep = _vc(ctx, ru, rp, precision=prec, use_graph=0)
+        for rep in range(4):
+            gu, gp = _vc(ctx, ru, rp, precision=prec, use_graph=1)
+            assert np.linalg.norm(gu - eu) <= tol * np.linalg.norm(eu), (prec, rep)
+            assert np.linalg.norm(gp - ep) <= tol * np.linalg.norm(ep), (prec, rep)
+            _vc(ctx, 2 * ru, rp, precision=prec, use_graph=0)     # eager work between replays
