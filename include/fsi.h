@@ -106,6 +106,9 @@ typedef struct {
     double rtol;             /* relative true residual ||g - M x||_2 / ||g||_2 */
     int max_iter;
     int restart;
+    int reorth;              /* Arnoldi by classical Gram-Schmidt: 0 one pass; 1 a second pass
+                                when the first cancelled most of the vector (norm drop
+                                below 1/sqrt(2), Daniel-Gragg-Kaufman-Stewart); 2 always two */
 } fsi_solve_opts;
 
 typedef struct {

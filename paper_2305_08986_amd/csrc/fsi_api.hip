@@ -131,8 +131,12 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
                 ++k;
             }
     }
-    (void)nchunk;
     L.phase_off[nph] = k;
+    L.geo.nx = nx;
+    L.geo.nchunks = nchunk;
+    L.geo.cpw = cpw;
+    L.geo.nt = dim == 3 ? Shape<3>::NT : Shape<2>::NT;
+    L.geo.nchk = (L.nc / nx) * nchunk;
     std::vector<int> vmap((size_t)L.nc * NLOC), pmap((size_t)L.nc * NPL);
     std::vector<uint4> info((size_t)L.nc);
     // first/last touch of a shared node: compare the phase of every other cell containing it
@@ -592,7 +596,8 @@ static fsi_status ensure_krylov(Context* ctx, int restart) {
     TRY(dalloc(ctx, &K.x, n));
     TRY(dalloc(ctx, &K.g, n));
     TRY(dalloc(ctx, &K.h, 2 * (restart + 2)));
-    TRY(dalloc(ctx, &K.partials, std::max<int64_t>(256 * (int64_t)(restart + 2), 2 * kReduceBlocks)));
+    TRY(dalloc(ctx, &K.partials, std::max<int64_t>(std::max<int64_t>(1024 * (int64_t)(restart + 2), 4096),
+                                                   2 * kReduceBlocks)));
     if (K.h_host) hipHostFree(K.h_host);
     FSI_HIP_TRY(hipHostMalloc((void**)&K.h_host, sizeof(double) * 3 * (restart + 2)));
     return FSI_OK;
@@ -976,7 +981,8 @@ fsi_status fsi_solve(fsi_ctx* h, const double* g_u, const double* g_p, double* u
     if (!h || !g_u || !g_p || !u || !p || !o) return FSI_ERR_ARG;
     Context* ctx = &h->c;
     if (!ctx->setup_done) return fail(ctx, FSI_ERR_STATE, "solve before setup");
-    if (o->restart < 1 || o->max_iter < 0 || !(o->rtol >= 0)) return fail(ctx, FSI_ERR_ARG, "invalid solve options");
+    if (o->restart < 1 || o->max_iter < 0 || !(o->rtol >= 0) || o->reorth < 0 || o->reorth > 2)
+        return fail(ctx, FSI_ERR_ARG, "invalid solve options");
     const auto t0 = std::chrono::steady_clock::now();
     TRY(ensure_krylov(ctx, o->restart));
     Krylov& K = ctx->kr;
@@ -1037,25 +1043,24 @@ fsi_status fsi_solve(fsi_ctx* h, const double* g_u, const double* g_p, double* u
             double* Zk = K.Z + (int64_t)k * n;
             TRY(precond_combined(ctx, Vk, Zk, s));
             stokes_combined(ctx, Zk, K.w, s);
-            // classical Gram-Schmidt as batched passes over the basis; a second
-            // (reorthogonalising) pass only when the first cancelled most of w:
-            // ||w_after|| < ||w_before|| / sqrt(2)  (Daniel-Gragg-Kaufman-Stewart)
-            launch_dot<double>(K.w, K.w, n, K.partials, K.h + (R + 1), s);
-            launch_multi_dot(K.V, n, k + 1, K.w, n, K.partials, K.h, s);
-            launch_multi_axpy(K.V, n, k + 1, K.h, -1.0, K.w, n, s);
-            launch_dot<double>(K.w, K.w, n, K.partials, K.h + (k + 1), s);
+            // classical Gram-Schmidt as batched passes over the basis
+            // h[0..k] = V^T w and h[k+1] = ||w||^2 in one sweep; the projection
+            // returns ||w||^2 after it in h[R+1]
+            launch_multi_dot(K.V, n, k + 1, K.w, n, K.partials, K.h, s, true);
+            launch_multi_axpy_norm(K.V, n, k + 1, K.h, -1.0, K.w, n, K.partials, K.h + (R + 1), s);
             FSI_HIP_TRY(hipMemcpyAsync(K.h_host, K.h, sizeof(double) * (R + 2), hipMemcpyDeviceToHost, s));
             FSI_HIP_TRY(hipStreamSynchronize(s));
             for (int i = 0; i <= k; ++i) H[(size_t)i * R + k] = K.h_host[i];
-            double after = K.h_host[k + 1];
-            if (after < 0.5 * K.h_host[R + 1]) {
+            double after = K.h_host[R + 1];
+            // second pass: never (reorth 0), when the DGKS test flags cancellation
+            // (reorth 1), or always (reorth 2)
+            if (o->reorth == 2 || (o->reorth == 1 && after < 0.5 * K.h_host[k + 1])) {
                 launch_multi_dot(K.V, n, k + 1, K.w, n, K.partials, K.h + (R + 2), s);
-                launch_multi_axpy(K.V, n, k + 1, K.h + (R + 2), -1.0, K.w, n, s);
-                launch_dot<double>(K.w, K.w, n, K.partials, K.h + (k + 1), s);
+                launch_multi_axpy_norm(K.V, n, k + 1, K.h + (R + 2), -1.0, K.w, n, K.partials, K.h + (R + 1), s);
                 FSI_HIP_TRY(hipMemcpyAsync(K.h_host, K.h, sizeof(double) * 2 * (R + 2), hipMemcpyDeviceToHost, s));
                 FSI_HIP_TRY(hipStreamSynchronize(s));
                 for (int i = 0; i <= k; ++i) H[(size_t)i * R + k] += K.h_host[(R + 2) + i];
-                after = K.h_host[k + 1];
+                after = K.h_host[R + 1];
                 ++reorth;
             }
             const double hnext = std::sqrt(after);

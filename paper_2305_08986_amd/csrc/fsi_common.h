@@ -37,6 +37,23 @@ template <int DIM> struct Shape;
 template <> struct Shape<2> { static constexpr int NT = 3, CPW = 21, NLOC = 9, NPL = 4, Q = 9, NK = 4; };
 template <> struct Shape<3> { static constexpr int NT = 9, CPW = 7, NLOC = 27, NPL = 8, Q = 27, NK = 9; };
 
+// Geometry/coefficient layout: the cell kernels read, per wavefront chunk of CPW
+// cells and per quadrature abscissa qx, the CPW * NT values (NT points (qy[, qz])
+// per cell) of every plane as one aligned block of 64 slots (63 used), so that
+// consecutive chunks never share a cache line.  Chunks are numbered row by row in
+// processing order; col is the cell's processing-order index.
+struct GeoLayout {
+    int64_t nchk = 0;              // chunks on the level
+    int nx = 1, nchunks = 1, cpw = 1, nt = 1;   // cells per row, chunks per row, CPW, NT
+};
+constexpr int kGeoSlots = 64;
+__host__ __device__ inline int64_t geo_off(const GeoLayout& g, int qx, int64_t col, int t) {
+    const int64_t row = col / g.nx;
+    const int ix = (int)(col - row * g.nx);
+    const int ch = ix / g.cpw, slot = ix - ch * g.cpw;
+    return ((int64_t)qx * g.nchk + row * g.nchunks + ch) * kGeoSlots + slot * g.nt + t;
+}
+
 // operator mode bits of the cell kernel; OP_CHEB (with OP_A) and OP_RES (with
 // OP_A | OP_BT | OP_B) replace the plain store at a node's last touch by a
 // Chebyshev update of the iterate or by the residual f - M u
@@ -92,7 +109,7 @@ struct Level {
     int64_t n_dir = 0;
     std::vector<uint8_t> h_dir_node;   // [nvn] host copy of the wall mask
 
-    // geometry and coefficients, internal layout [plane][qx][cell][t]
+    // geometry and coefficients, internal layout [plane][qx][chunk][slot] (GeoLayout)
     double* d_K64 = nullptr;       // 9 (or 4) planes: det(J) w_q J^{-1}, entry (b,a) in plane b*dim+a
     double* d_cw64 = nullptr;      // det(J) w_q
     double* d_cv64 = nullptr;      // 2 planes: 2 eta/(det J w), c_m det J w
@@ -107,7 +124,8 @@ struct Level {
     double lam = 0, lo = 0, hi = 0;
     double diagA_norm = 0, diagS_norm = 0;
 
-    int64_t plane() const { return (int64_t)Q * nc; }
+    GeoLayout geo;
+    int64_t plane() const { return 3 * geo.nchk * kGeoSlots; }
 };
 
 // per-level work vectors of the V-cycle in one precision (T velocity, double pressure)
@@ -283,8 +301,12 @@ void launch_coarse_apply(const Coarse& C, const Level& L, const T* f_u, const do
 // reductions and BLAS-1 (FP64 accumulation)
 template <typename T>
 void launch_dot(const T* x, const T* y, int64_t n, double* partials, double* out, hipStream_t s);
+// out[j] = <V_j, w> for j < m (and out[m] = ||w||^2 with with_norm), V_j = V + j ldv
 void launch_multi_dot(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* partials,
-                      double* out, hipStream_t s);
+                      double* out, hipStream_t s, bool with_norm = false);
+// w += sign sum_j coef_j V_j; *out_norm2 = ||w||^2 afterwards (partials: >= kReduceBlocks)
+void launch_multi_axpy_norm(const double* V, int64_t ldv, int m, const double* coef_dev, double sign, double* w,
+                            int64_t n, double* partials, double* out_norm2, hipStream_t s);
 void launch_multi_axpy(const double* V, int64_t ldv, int m, const double* coef_dev, double sign,
                        double* w, int64_t n, hipStream_t s);
 void launch_axpy_host(double a, const double* x, double* y, int64_t n, hipStream_t s);

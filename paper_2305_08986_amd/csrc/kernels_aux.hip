@@ -36,6 +36,7 @@ __device__ __forceinline__ double dW(int q) { return q == 1 ? kW1 : kW0; }
 struct GeoOut {
     int dim, NT, Q;
     int64_t nc, plane;
+    GeoLayout geo;
     const int* lex2col;
     double* K;
     double* cw;
@@ -47,7 +48,7 @@ __device__ __forceinline__ void store_geometry(const GeoOut& g, int64_t cell, in
     const int dim = g.dim;
     const int qx = q % 3, t = q / 3;
     const int64_t col = g.lex2col[cell];
-    const int64_t off = ((int64_t)qx * g.nc + col) * g.NT + t;
+    const int64_t off = geo_off(g.geo, qx, col, t);
     double w = 1.0;
     int r = q;
     for (int d = 0; d < dim; ++d) {
@@ -101,7 +102,7 @@ __global__ void k_geometry(GeoOut g, const double* __restrict__ J) {
 
 void launch_geometry(const Level& L, const double* J, double* K, double* cw, float* K32, int* flag,
                      hipStream_t s) {
-    GeoOut g{L.dim, L.dim == 3 ? 9 : 3, L.Q, L.nc, L.plane(), L.d_lex2col, K, cw, K32, flag};
+    GeoOut g{L.dim, L.dim == 3 ? 9 : 3, L.Q, L.nc, L.plane(), L.geo, L.d_lex2col, K, cw, K32, flag};
     hipLaunchKernelGGL(k_geometry, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, g, J);
 }
 
@@ -157,7 +158,7 @@ __global__ void k_geometry_disp(GeoOut g, DispIn in) {
 
 void launch_geometry_from_disp(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
                                double* K, double* cw, float* K32, int* flag, hipStream_t s) {
-    GeoOut g{L.dim, L.dim == 3 ? 9 : 3, L.Q, L.nc, L.plane(), L.d_lex2col, K, cw, K32, flag};
+    GeoOut g{L.dim, L.dim == 3 ? 9 : 3, L.Q, L.nc, L.plane(), L.geo, L.d_lex2col, K, cw, K32, flag};
     DispIn in;
     in.disp = disp_fine;
     in.stride = stride;
@@ -174,7 +175,7 @@ void launch_geometry_from_disp(const Level& L, const double* disp_fine, int stri
 // h must be set by the caller through a second entry (extent known on the host)
 void launch_geometry_from_disp_h(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
                                  const double* h, double* K, double* cw, float* K32, int* flag, hipStream_t s) {
-    GeoOut g{L.dim, L.dim == 3 ? 9 : 3, L.Q, L.nc, L.plane(), L.d_lex2col, K, cw, K32, flag};
+    GeoOut g{L.dim, L.dim == 3 ? 9 : 3, L.Q, L.nc, L.plane(), L.geo, L.d_lex2col, K, cw, K32, flag};
     DispIn in;
     in.disp = disp_fine;
     in.stride = stride;
@@ -189,7 +190,7 @@ void launch_geometry_from_disp_h(const Level& L, const double* disp_fine, int st
 }
 
 // ---------------------------------------------------------------- coefficients
-__global__ void k_coefficients(int64_t nc, int Q, int NT, int64_t plane, const int* __restrict__ lex2col,
+__global__ void k_coefficients(int64_t nc, int Q, GeoLayout geo, int64_t plane, const int* __restrict__ lex2col,
                                const double* __restrict__ cm, const double* __restrict__ eta,
                                const double* __restrict__ cw, double* __restrict__ cv64, float* __restrict__ cv32,
                                int* flag) {
@@ -198,7 +199,7 @@ __global__ void k_coefficients(int64_t nc, int Q, int NT, int64_t plane, const i
     const int64_t cell = id / Q;
     const int q = (int)(id - cell * Q);
     const int qx = q % 3, t = q / 3;
-    const int64_t off = ((int64_t)qx * nc + lex2col[cell]) * NT + t;
+    const int64_t off = geo_off(geo, qx, lex2col[cell], t);
     const double m = cm[id], e = eta[id], w = cw[off];
     if (!isfinite(m) || !isfinite(e) || !(e >= 0.0)) flag[0] = 1;
     const double cvisc = 2.0 * e / w, cmass = m * w;
@@ -210,14 +211,14 @@ __global__ void k_coefficients(int64_t nc, int Q, int NT, int64_t plane, const i
 
 void launch_coefficients(const Level& L, const double* cm, const double* eta, const double* cw, double* cv64,
                          float* cv32, int* flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_coefficients, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, L.nc, L.Q,
-                       L.dim == 3 ? 9 : 3, L.plane(), L.d_lex2col, cm, eta, cw, cv64, cv32, flag);
+    hipLaunchKernelGGL(k_coefficients, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, L.nc, L.Q, L.geo, L.plane(),
+                       L.d_lex2col, cm, eta, cw, cv64, cv32, flag);
 }
 
 // ---------------------------------------------------------------- diag(A)
 // diag_(a,n) = sum_q cmass phi_n^2 + (cvisc/2)(|G_n|^2 + G_n[a]^2), G_n = K^T grad-hat phi_n
 __global__ void k_diagA(int dim, int64_t cbeg, int64_t cend, const int* __restrict__ col2lex, int nx, int xpar,
-                        int64_t nc, int64_t nvn, int64_t plane,
+                        GeoLayout geo, int64_t nvn, int64_t plane,
                         const int* __restrict__ vmap, const uint4* __restrict__ info,
                         const double* __restrict__ K, const double* __restrict__ cv, double* __restrict__ diag) {
     const int NLOC = dim == 3 ? 27 : 9;
@@ -234,7 +235,7 @@ __global__ void k_diagA(int dim, int64_t cbeg, int64_t cend, const int* __restri
     for (int q = 0; q < Q; ++q) {
         int qi[3] = {q % 3, (q / 3) % 3, q / 9};
         const int qx = qi[0], t = q / 3;
-        const int64_t off = ((int64_t)qx * nc + cell) * NT + t;
+        const int64_t off = geo_off(geo, qx, cell, t);
         double phi = 1.0, gh[3];
         for (int d = 0; d < dim; ++d) phi *= dS(qi[d], ni[d]);
         for (int b = 0; b < dim; ++b) {
@@ -261,7 +262,7 @@ void launch_diagA(const Level& L, const double* K, const double* cv, double* dia
             const int64_t n = (L.phase_off[ph + 1] - L.phase_off[ph]) * nloc;
             if (n == 0) continue;
             hipLaunchKernelGGL(k_diagA, dim3(nblocks(n)), dim3(TPB), 0, s, L.dim, L.phase_off[ph],
-                               L.phase_off[ph + 1], L.d_col2lex, L.cells[0], xpar, L.nc, L.nvn, L.plane(), L.d_vmap,
+                               L.phase_off[ph + 1], L.d_col2lex, L.cells[0], xpar, L.geo, L.nvn, L.plane(), L.d_vmap,
                                L.d_info, K, cv, diag);
         }
 }
@@ -284,7 +285,7 @@ void launch_diagA_finish(const Level& L, double* diag, double* dinv64, float* di
 // ---------------------------------------------------------------- diag(B diag(A)^{-1} B^T)
 // one workgroup per pressure node; thread = node of the 5^dim velocity patch around it.
 // The assembled row entries B_{k,(a,n)} are sums over the cells sharing vertex k and node n.
-__global__ void k_diagS(int dim, int c0, int c1, int c2, int vn0, int vn1, int vn2, int64_t nc, int64_t nvn,
+__global__ void k_diagS(int dim, int c0, int c1, int c2, int vn0, int vn1, int vn2, GeoLayout geo, int64_t nvn,
                         int64_t plane, const int* __restrict__ lex2col, const uint8_t* __restrict__ wall,
                         const double* __restrict__ K, const double* __restrict__ dAinv,
                         double* __restrict__ dSinv) {
@@ -327,7 +328,7 @@ __global__ void k_diagS(int dim, int c0, int c1, int c2, int vn0, int vn1, int v
                     const int Q = dim == 3 ? 27 : 9;
                     for (int q = 0; q < Q; ++q) {
                         const int qi[3] = {q % 3, (q / 3) % 3, q / 9};
-                        const int64_t off = ((int64_t)qi[0] * nc + col) * NT + q / 3;
+                        const int64_t off = geo_off(geo, qi[0], col, q / 3);
                         double psi = 1.0, gh[3];
                         for (int d = 0; d < dim; ++d) psi *= dL(qi[d], kl[d]);
                         for (int b = 0; b < dim; ++b) {
@@ -358,7 +359,7 @@ __global__ void k_diagS(int dim, int c0, int c1, int c2, int vn0, int vn1, int v
 void launch_diagS_impl(const Level& L, const uint8_t* d_wall, const double* K, const double* dAinv, double* dSinv,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_diagS, dim3((unsigned)L.np), dim3(128), 0, s, L.dim, L.cells[0], L.cells[1], L.cells[2],
-                       L.vnodes[0], L.vnodes[1], L.vnodes[2], L.nc, L.nvn, L.plane(), L.d_lex2col, d_wall, K,
+                       L.vnodes[0], L.vnodes[1], L.vnodes[2], L.geo, L.nvn, L.plane(), L.d_lex2col, d_wall, K,
                        dAinv, dSinv);
 }
 
@@ -840,7 +841,7 @@ template void launch_prolongate_add<float>(const Level&, const Level&, const flo
 // of A (mass + viscous) and the matching column of B^T / row of B are added to the
 // dense matrix restricted to free dofs (dof2row[dof] < 0 for wall dofs).
 __global__ void k_coarse_assemble(int dim, int64_t cbeg, int64_t cend, const int* __restrict__ col2lex, int nx,
-                                  int xpar, int64_t nc, int64_t nvn, int64_t plane,
+                                  int xpar, GeoLayout geo, int64_t nvn, int64_t plane,
                                   const int* __restrict__ vmap, const int* __restrict__ pmap,
                                   const double* __restrict__ K, const double* __restrict__ cv,
                                   const int* __restrict__ vrow, int64_t nfree_u, double* __restrict__ M, int64_t n) {
@@ -862,7 +863,7 @@ __global__ void k_coarse_assemble(int dim, int64_t cbeg, int64_t cend, const int
             double acc = 0.0;
             for (int q = 0; q < NLOC; ++q) {
                 const int qi[3] = {q % 3, (q / 3) % 3, q / 9};
-                const int64_t off = ((int64_t)qi[0] * nc + cell) * NT + q / 3;
+                const int64_t off = geo_off(geo, qi[0], cell, q / 3);
                 double phin = 1.0, phim = 1.0, gn[3], gm[3];
                 for (int d = 0; d < dim; ++d) {
                     phin *= dS(qi[d], ni[d]);
@@ -901,7 +902,7 @@ __global__ void k_coarse_assemble(int dim, int64_t cbeg, int64_t cend, const int
         double acc = 0.0;
         for (int q = 0; q < NLOC; ++q) {
             const int qi[3] = {q % 3, (q / 3) % 3, q / 9};
-            const int64_t off = ((int64_t)qi[0] * nc + cell) * NT + q / 3;
+            const int64_t off = geo_off(geo, qi[0], cell, q / 3);
             double psi = 1.0, gn[3];
             for (int d = 0; d < dim; ++d) psi *= dL(qi[d], ki[d]);
             for (int e = 0; e < dim; ++e) {
@@ -927,7 +928,7 @@ void launch_coarse_assemble_impl(const Level& L, const double* K, const double* 
             const int64_t cnt = (L.phase_off[ph + 1] - L.phase_off[ph]) * L.dim * nloc;
             if (cnt == 0) continue;
             hipLaunchKernelGGL(k_coarse_assemble, dim3(nblocks(cnt, 64)), dim3(64), 0, s, L.dim, L.phase_off[ph],
-                               L.phase_off[ph + 1], L.d_col2lex, L.cells[0], xpar, L.nc, L.nvn, L.plane(), L.d_vmap,
+                               L.phase_off[ph + 1], L.d_col2lex, L.cells[0], xpar, L.geo, L.nvn, L.plane(), L.d_vmap,
                                L.d_pmap, K, cv, vrow, nfree_u, M, n);
         }
 }
@@ -1066,16 +1067,38 @@ template void launch_coarse_apply<float>(const Coarse&, const Level&, const floa
                                          hipStream_t);
 
 // ---------------------------------------------------------------- Krylov helpers (FP64)
-__global__ void k_multi_dot_partial(const double* __restrict__ V, int64_t ldv, const double* __restrict__ w, int64_t n,
-                                    double* __restrict__ part) {
-    __shared__ double sh[TPB];
-    const int j = blockIdx.y;
-    const double* vj = V + (int64_t)j * ldv;
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        acc += vj[i] * w[i];
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = s;
+// partial dots <V_j, w> for a group of kDotGroup basis vectors per block row, so that
+// w is streamed once per group rather than once per vector
+constexpr int kDotGroup = 8;
+// Vector index mb (== number of basis vectors) stands for w itself when the total
+// count m exceeds mb, which yields ||w||^2 in the same sweep.
+__global__ void k_multi_dot_partial(const double* __restrict__ V, int64_t ldv, int mb, int m,
+                                    const double* __restrict__ w, int64_t n, double* __restrict__ part) {
+    __shared__ double sh[kDotGroup][TPB / 64];
+    const int j0 = blockIdx.y * kDotGroup;
+    const int ng = min(kDotGroup, m - j0);
+    double acc[kDotGroup];
+#pragma unroll
+    for (int g = 0; g < kDotGroup; ++g) acc[g] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double wi = w[i];
+#pragma unroll
+        for (int g = 0; g < kDotGroup; ++g)
+            if (g < ng) acc[g] += (j0 + g < mb ? V[(int64_t)(j0 + g) * ldv + i] : wi) * wi;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int g = 0; g < kDotGroup; ++g) {
+        double v = acc[g];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+        if (lane == 0) sh[g][wave] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ng) {
+        double sum = 0.0;
+        for (int k = 0; k < TPB / 64; ++k) sum += sh[threadIdx.x][k];
+        part[(int64_t)(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = sum;
+    }
 }
 __global__ void k_multi_dot_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
     __shared__ double sh[TPB];
@@ -1086,22 +1109,63 @@ __global__ void k_multi_dot_final(const double* __restrict__ part, int nb, doubl
     if (threadIdx.x == 0) out[j] = s;
 }
 void launch_multi_dot(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* partials, double* out,
-                      hipStream_t s) {
-    const unsigned nb = 256;
-    hipLaunchKernelGGL(k_multi_dot_partial, dim3(nb, m), dim3(TPB), 0, s, V, ldv, w, n, partials);
-    hipLaunchKernelGGL(k_multi_dot_final, dim3(m), dim3(TPB), 0, s, partials, (int)nb, out);
+                      hipStream_t s, bool with_norm) {
+    const unsigned nb = 1024;
+    const int mt = m + (with_norm ? 1 : 0);
+    const unsigned groups = (unsigned)((mt + kDotGroup - 1) / kDotGroup);
+    hipLaunchKernelGGL(k_multi_dot_partial, dim3(nb, groups), dim3(TPB), 0, s, V, ldv, m, mt, w, n, partials);
+    hipLaunchKernelGGL(k_multi_dot_final, dim3(mt), dim3(TPB), 0, s, partials, (int)nb, out);
 }
 __global__ void k_multi_axpy(const double* __restrict__ V, int64_t ldv, int m, const double* __restrict__ coef,
                              double sign, double* __restrict__ w, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double acc = 0.0;
-    for (int j = 0; j < m; ++j) acc += coef[j] * V[(int64_t)j * ldv + i];
+    int j = 0;
+    for (; j + 8 <= m; j += 8) {
+        double v[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) v[g] = V[(int64_t)(j + g) * ldv + i];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) acc += coef[j + g] * v[g];
+    }
+    for (; j < m; ++j) acc += coef[j] * V[(int64_t)j * ldv + i];
     w[i] += sign * acc;
 }
 void launch_multi_axpy(const double* V, int64_t ldv, int m, const double* coef_dev, double sign, double* w, int64_t n,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_multi_axpy, dim3(nblocks(n)), dim3(TPB), 0, s, V, ldv, m, coef_dev, sign, w, n);
+}
+constexpr int kAxpyBlocks = 4096;
+// w += sign * sum_j coef[j] V_j, and ||w||^2 of the result in the same sweep; the
+// basis loads are issued eight at a time so that each thread keeps several in flight
+__global__ void k_multi_axpy_norm(const double* __restrict__ V, int64_t ldv, int m, const double* __restrict__ coef,
+                                  double sign, double* __restrict__ w, int64_t n, double* __restrict__ part) {
+    __shared__ double sh[TPB];
+    double nrm = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        int j = 0;
+        for (; j + 8 <= m; j += 8) {
+            double v[8];
+#pragma unroll
+            for (int g = 0; g < 8; ++g) v[g] = V[(int64_t)(j + g) * ldv + i];
+#pragma unroll
+            for (int g = 0; g < 8; ++g) acc += coef[j + g] * v[g];
+        }
+        for (; j < m; ++j) acc += coef[j] * V[(int64_t)j * ldv + i];
+        const double wn = w[i] + sign * acc;
+        w[i] = wn;
+        nrm += wn * wn;
+    }
+    const double t = block_sum(nrm, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+void launch_multi_axpy_norm(const double* V, int64_t ldv, int m, const double* coef_dev, double sign, double* w,
+                            int64_t n, double* partials, double* out_norm2, hipStream_t s) {
+    hipLaunchKernelGGL(k_multi_axpy_norm, dim3(kAxpyBlocks), dim3(TPB), 0, s, V, ldv, m, coef_dev, sign, w, n,
+                       partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(TPB), 0, s, partials, kAxpyBlocks, out_norm2);
 }
 __global__ void k_axpy(double a, const double* __restrict__ x, double* __restrict__ y, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -52,6 +52,8 @@ struct CellArgs {
     int64_t nrows;      // rows of cells (along x) in this phase
     int nx, nchunks;    // cells per row, chunks of CPW cells per row
     int wlast;          // cells in the last (ragged) chunk of a row
+    int64_t chunk0;     // geometry chunk index of the phase's first chunk
+    int64_t nchk;       // geometry chunks on the level (stride of the qx blocks)
     const int* __restrict__ vmap;
     const uint4* __restrict__ info;
     const int* __restrict__ pmap;
@@ -114,6 +116,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         const int ix = ch * CPW + slot;
         const bool act = rowact && inwave && ix < a.nx;
         const int64_t cell = a.cbeg + row * a.nx + ix;   // phase cells are stored row by row
+        // the chunk is wavefront-uniform: keep it scalar so that every geometry load is
+        // a scalar base plus the lane's fixed offset (no per-plane vector addresses)
+        const int64_t chunk = __builtin_amdgcn_readfirstlane((int)(a.chunk0 + row * a.nchunks + ch));
         const uint4 inf = act ? a.info[cell] : make_uint4(0u, 0u, 0u, 0u);
         // does this thread write its column (x-face columns go to the right neighbour)?
         const bool vwriter = act && (ic != 2 || ix == a.nx - 1);
@@ -239,7 +244,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             __builtin_amdgcn_sched_barrier(0);
             // geometry of the point: K = det(J) w J^{-1} (row-major 3x3), cvisc, cmass
             T Kq[9];
-            const int64_t off = ((int64_t)qx * a.nc + cell) * NT + t;
+            const int64_t off = ((int64_t)qx * a.nchk + chunk) * kGeoSlots + (slot * NT + t);
 #pragma unroll
             for (int e = 0; e < 9; ++e) Kq[e] = act ? gload<NTL>(a.K + e * P + off) : T(0);
             const T cvq = (HAS_A && act) ? gload<NTL>(a.cv + off) : T(0);
@@ -314,7 +319,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         for (int qx = 0; qx < 3; ++qx) {
             // geometry of the point: K = det(J) w J^{-1} (row-major 3x3), cvisc, cmass
             T Kq[9];
-            const int64_t off = ((int64_t)qx * a.nc + cell) * NT + t;
+            const int64_t off = ((int64_t)qx * a.nchk + chunk) * kGeoSlots + (slot * NT + t);
 #pragma unroll
             for (int e = 0; e < 9; ++e) Kq[e] = act ? gload<NTL>(a.K + e * P + off) : T(0);
             const T cvq = (HAS_A && act) ? gload<NTL>(a.cv + off) : T(0);
@@ -607,6 +612,7 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
     const int ix = ch * CPW + slot;
     const bool act = rowact && inwave && ix < a.nx;
     const int64_t cell = a.cbeg + row * a.nx + ix;   // phase cells are stored row by row
+    const int64_t chunk = __builtin_amdgcn_readfirstlane((int)(a.chunk0 + row * a.nchunks + ch));
 
     T val[2][3], g0[2][3], g1[2][3];
     if constexpr (FWD) {
@@ -687,7 +693,7 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
 #pragma unroll
     for (int qx = 0; qx < 3; ++qx) {
         T Km[2][2];
-        const int64_t off = ((int64_t)qx * a.nc + cell) * NT + t;
+        const int64_t off = ((int64_t)qx * a.nchk + chunk) * kGeoSlots + (slot * NT + t);
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -918,6 +924,8 @@ static CellArgs<T> phase_args(const Level& L, int phase, const T* K, const T* cv
     const int cpw = L.dim == 3 ? Shape<3>::CPW : Shape<2>::CPW;
     args.nchunks = (L.cells[0] + cpw - 1) / cpw;
     args.wlast = L.cells[0] - (args.nchunks - 1) * cpw;
+    args.chunk0 = (args.cbeg / L.cells[0]) * args.nchunks;
+    args.nchk = L.geo.nchk;
     args.nc = L.nc;
     args.nvn = L.nvn;
     args.plane = L.plane();

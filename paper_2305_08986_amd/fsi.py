@@ -55,7 +55,7 @@ class LevelInfo(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int)]
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int), ("reorth", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -277,12 +277,14 @@ class Context:
                                         C.c_void_p(_ptr(z_u)), C.c_void_p(_ptr(z_p))))
         return z_u, z_p
 
-    def solve(self, g_u, g_p, u=None, p=None, rtol: float = 1e-8, max_iter: int = 500, restart: int = 100):
-        """FGMRES solve; returns (u, p, info).  u/p (if given) are the initial guess, updated in place."""
+    def solve(self, g_u, g_p, u=None, p=None, rtol: float = 1e-8, max_iter: int = 500, restart: int = 100,
+              reorth: int = 1):
+        """FGMRES solve; returns (u, p, info).  u/p (if given) are the initial guess, updated in place.
+        reorth: 0 one classical Gram-Schmidt pass, 1 second pass when needed, 2 always two."""
         t = self.torch
         u = t.zeros_like(g_u) if u is None else u
         p = t.zeros_like(g_p) if p is None else p
-        o = SolveOpts(rtol=rtol, max_iter=max_iter, restart=restart)
+        o = SolveOpts(rtol=rtol, max_iter=max_iter, restart=restart, reorth=reorth)
         hist = (C.c_double * (max_iter + 1))()
         info = SolveInfo()
         info.res_history = C.cast(hist, C.POINTER(C.c_double))
