@@ -278,7 +278,7 @@ class Context:
         return z_u, z_p
 
     def solve(self, g_u, g_p, u=None, p=None, rtol: float = 1e-8, max_iter: int = 500, restart: int = 100,
-              reorth: int = 1):
+              reorth: int = 0):
         """FGMRES solve; returns (u, p, info).  u/p (if given) are the initial guess, updated in place.
         reorth: 0 one classical Gram-Schmidt pass, 1 second pass when needed, 2 always two."""
         t = self.torch

@@ -126,10 +126,12 @@ CONFIGS = {
                  eta="loguniform", block=3, desc="3D 12x6x10 warped, odd coarse counts"),
     "T2_R": dict(dim=2, n=(22, 14), extent=(1.1, 0.7), n_coarse=(11, 7), amp=0.03,
                  eta="loguniform", block=3, desc="2D 22x14 warped, odd coarse counts"),
+    "T4_S": dict(dim=3, n=(16, 16, 16), extent=(1.0, 1.0, 1.0), n_coarse=(4, 4, 4), amp=0.0025,
+                 eta="loguniform", block=4, steps=3, desc="3D 16^3 step sequence (C4 law, small)"),
 }
 
 CONFIG_INDEX = {"C0": 0, "C1": 1, "C2": 2, "C3": 3, "C4": 4,
-                "T3_4": 100, "T3_8": 101, "T3_16": 102, "T3_R": 103, "T2_R": 104}
+                "T3_4": 100, "T3_8": 101, "T3_16": 102, "T3_R": 103, "T2_R": 104, "T4_S": 105}
 
 
 # ---------------------------------------------------------------- geometry of the grids
