@@ -92,6 +92,12 @@ typedef struct {
     int tuned;               /* 1: autotuned launch variant per level and, with fused = 1, the
                                 fused or separate form per level, whichever fsi_autotune
                                 measured faster; 0: the default variant, fused everywhere */
+    int vertex_geometry;     /* 1: FP32 cell kernels on 3D levels form det(J) w J^{-1} at each
+                                quadrature point from the vertex displacements given to
+                                fsi_set_displacement (multilinear map, Sec. 3.2) instead of
+                                reading the stored values; 0: stored values (default).  FP64
+                                kernels always read the stored values.  Switching needs no new
+                                setup. */
 } fsi_mg_params;
 
 typedef struct {

@@ -217,6 +217,9 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
     TRY(dalloc(ctx, &L.d_cv64, 2 * P));
     TRY(dalloc(ctx, &L.d_K32, (int64_t)dim * dim * P));
     TRY(dalloc(ctx, &L.d_cv32, 2 * P));
+    TRY(dalloc(ctx, &L.d_cq32, 2 * P));
+    TRY(dalloc(ctx, &L.d_vd32, L.np));
+    for (int d = 0; d < dim; ++d) L.h[d] = m.extent[d] / L.cells[d];
     TRY(dalloc(ctx, &L.d_dAinv64, L.nv));
     TRY(dalloc(ctx, &L.d_dAinv32, L.nv));
     TRY(dalloc(ctx, &L.d_dSinv, L.np));
@@ -395,7 +398,7 @@ static fsi_status capture_graphs(Context* ctx);
 
 static fsi_status run_vcycle(Context* ctx, hipStream_t s) {
     const int pi = ctx->prm.precision == FSI_PREC_MIXED ? 1 : 0;
-    const int key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0);
+    const int key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0);
     if (ctx->prm.use_graph && ctx->graph_valid[pi] && ctx->graph_key != key) TRY(capture_graphs(ctx));
     if (ctx->prm.use_graph && ctx->graph_valid[pi]) {
         FSI_HIP_TRY(hipGraphLaunch(ctx->graph[pi], s));
@@ -428,7 +431,7 @@ static fsi_status capture_graphs(Context* ctx) {
         ctx->graph_valid[pi] = true;
     }
     hipStreamDestroy(cs);
-    ctx->graph_key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0);
+    ctx->graph_key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0);
     return FSI_OK;
 }
 
@@ -652,6 +655,7 @@ void fsi_default_mg_params(fsi_mg_params* p) {
     p->use_graph = 1;
     p->fused = 1;
     p->tuned = 1;
+    p->vertex_geometry = 0;   // measured slower than the stored values on MI355X
 }
 
 fsi_status fsi_create(fsi_ctx** out, const fsi_mesh_desc* m, void* hip_stream) {
@@ -758,6 +762,7 @@ fsi_status fsi_set_jacobians(fsi_ctx* h, int level, const double* J) {
     launch_geometry(L, J, L.d_K64, L.d_cw64, L.d_K32, ctx->d_flag, ctx->stream);
     L.geo_set = false;
     L.coef_set = false;
+    L.vgeo_avail = L.vgeo = false;   // arbitrary per-point Jacobians: stored geometry only
     TRY(sync_flag(ctx, FSI_ERR_INVERTED_CELL, "det J <= 0 (or not finite) at a quadrature point"));
     L.geo_set = true;
     return FSI_OK;
@@ -776,8 +781,11 @@ fsi_status fsi_set_displacement(fsi_ctx* h, const double* disp) {
         for (int d = 0; d < L.dim; ++d) hh[d] = ctx->mesh.extent[d] / L.cells[d];
         launch_geometry_from_disp_h(L, disp, 1 << (J - j), F.pnodes, hh, L.d_K64, L.d_cw64, L.d_K32, ctx->d_flag,
                                     ctx->stream);
+        launch_vertex_disp32(L, disp, 1 << (J - j), F.pnodes, L.d_vd32, ctx->stream);
         L.geo_set = false;
         L.coef_set = false;
+        L.vgeo_avail = L.dim == 3;
+        L.vgeo = L.vgeo_avail && ctx->prm.vertex_geometry;
     }
     TRY(sync_flag(ctx, FSI_ERR_INVERTED_CELL, "det J <= 0 (or not finite) at a quadrature point"));
     for (int j = 0; j <= J; ++j) ctx->lv[j].geo_set = true;
@@ -792,7 +800,7 @@ fsi_status fsi_set_coefficients(fsi_ctx* h, int level, const double* c_mass, con
     if (!L.geo_set) return fail(ctx, FSI_ERR_STATE, "set_coefficients before the level's geometry");
     invalidate(ctx);
     launch_fill<int>(ctx->d_flag, 0, 1, ctx->stream);
-    launch_coefficients(L, c_mass, eta, L.d_cw64, L.d_cv64, L.d_cv32, ctx->d_flag, ctx->stream);
+    launch_coefficients(L, c_mass, eta, L.d_cw64, L.d_cv64, L.d_cv32, L.d_cq32, ctx->d_flag, ctx->stream);
     L.coef_set = false;
     TRY(sync_flag(ctx, FSI_ERR_NONFINITE, "coefficient not finite (or negative viscosity)"));
     L.coef_set = true;
@@ -810,6 +818,7 @@ fsi_status fsi_set_mg_params(fsi_ctx* h, const fsi_mg_params* p) {
     const bool same = o.k_A == p->k_A && o.m == p->m && o.n_cycles == p->n_cycles && o.cheb_upper == p->cheb_upper &&
                       o.cheb_ratio == p->cheb_ratio && o.n_eig == p->n_eig;
     ctx->prm = *p;
+    for (Level& L : ctx->lv) L.vgeo = L.vgeo_avail && p->vertex_geometry;
     if (!same) invalidate(ctx);
     return FSI_OK;
 }

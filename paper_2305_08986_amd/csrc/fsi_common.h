@@ -115,6 +115,13 @@ struct Level {
     double* d_cv64 = nullptr;      // 2 planes: 2 eta/(det J w), c_m det J w
     float* d_K32 = nullptr;
     float* d_cv32 = nullptr;
+    // FP32 geometry from vertices: level vertex displacement (x, y, z, 0) and per
+    // point (2 eta, c_m) in the geometry layout; valid after fsi_set_displacement
+    float4* d_vd32 = nullptr;
+    float* d_cq32 = nullptr;
+    bool vgeo_avail = false;          // geometry came from vertex displacements (3D)
+    bool vgeo = false;                // ... and the FP32 kernels use it
+    double h[3] = {1.0, 1.0, 1.0};    // reference cell sizes
     bool geo_set = false, coef_set = false;
 
     // preconditioner data
@@ -187,7 +194,7 @@ struct Context {
     double* vc_tmp = nullptr;      // [nv + np] residual of repeated V-cycles
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     bool graph_valid[2] = {false, false};
-    int graph_key = -1;            // (fused, tuned) the graphs were captured with
+    int graph_key = -1;            // (fused, tuned, vertex_geometry) the graphs were captured with
     // tuning: per level and precision, index into the launch-variant table
     std::vector<int> tune_variant[2];
     std::vector<double> tune_us[2];
@@ -240,7 +247,10 @@ void launch_geometry(const Level& L, const double* J, double* K, double* cw, flo
 void launch_geometry_from_disp_h(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
                                  const double* h, double* K, double* cw, float* K32, int* flag, hipStream_t s);
 void launch_coefficients(const Level& L, const double* cm, const double* eta, const double* cw,
-                         double* cv64, float* cv32, int* flag, hipStream_t s);
+                         double* cv64, float* cv32, float* cq32, int* flag, hipStream_t s);
+// level vertex displacement (FP32 float4) from the fine-level displacement by injection
+void launch_vertex_disp32(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
+                          float4* out, hipStream_t s);
 void launch_diagA(const Level& L, const double* K, const double* cv, double* diag, hipStream_t s);
 void launch_diagA_finish(const Level& L, double* diag, double* dinv64, float* dinv32, hipStream_t s);
 void launch_diagS_impl(const Level& L, const uint8_t* d_wall, const double* K, const double* dAinv,

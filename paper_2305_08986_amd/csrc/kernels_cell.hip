@@ -10,6 +10,10 @@
 // cvisc = 2 eta / (det J w_q), cmass = c_m det J w_q; with H = (grad-hat u) K
 // (= det J w_q grad u) the viscous flux is F = cvisc sym(H) K^T and the
 // divergence is tr(H), so A, B and B^T share the same 9(+2) stored values.
+// In FP32 on 3D levels whose geometry comes from vertex displacements (the
+// multilinear ALE map), the kernel can instead form det(J) w_q J^{-1} = w_q adj(J)
+// at each point from the cell's 8 vertex displacements and read only
+// (2 eta, c_m) per point.
 //
 // Thread layout (64-wide wavefronts): one thread per line of 3 points of a
 // cell, NT = 3^(dim-1) threads per cell, CPW cells per wavefront.  The three
@@ -17,8 +21,7 @@
 // are transposed through LDS (wavefront-private).  Cells of one colour share
 // no node, so the scatter is a plain store (first touch of a node in phase
 // order) or read-modify-write (later touches), with no atomics; the host
-// launches the phases (slab x colour) one after another, so that the vector
-// data of a slab stays cache-resident across its colours.
+// launches the processing phases one after another.
 #include "fsi_common.h"
 
 namespace fsi {
@@ -32,6 +35,9 @@ template <typename T> __device__ __forceinline__ T rL(int q, int a) {
     if (q == 1) return T(0.5);
     return ((q == 0) == (a == 0)) ? hi : lo;
 }
+
+// 1D Gauss weight at a runtime index
+template <typename T> __device__ __forceinline__ T rW(int q) { return q == 1 ? T(kW1) : T(kW0); }
 
 // geometry is read exactly once per application: optionally stream it past the caches
 template <bool NT, typename T>
@@ -72,12 +78,18 @@ struct CellArgs {
     const double* __restrict__ fp;
     T c1, c2;
     int store_d;
+    // geometry from vertices (FP32, 3D): per-vertex displacement of the level's
+    // multilinear ALE map, reference cell sizes, and per point (2 eta, c_m) in the
+    // geometry layout (2 planes)
+    const float4* __restrict__ vd;
+    const T* __restrict__ cq;
+    T hx, hy, hz;
 };
 
 // ============================================================== 3D
 // One wavefront owns a row of cells along x and walks it in chunks of CPW = 7
 // cells (9 threads per cell: one per line of 3 points).
-template <typename T, int MODE, int WPB, bool REMAP, bool NTL, int WPE>
+template <typename T, int MODE, int WPB, bool REMAP, bool NTL, int WPE, bool VG>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE))) void cell3d(CellArgs<T> a) {
     constexpr int NT = 9, CPW = 7, NLOC = 27, BUF = 243;
     constexpr bool FWD = (MODE & (OP_A | OP_B)) != 0;
@@ -89,6 +101,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     constexpr bool RES = (MODE & OP_RES) != 0;
     static_assert(!CHEB || MODE == (OP_A | OP_CHEB), "the Chebyshev epilogue goes with A alone");
     static_assert(!RES || MODE == (OP_A | OP_BT | OP_B | OP_RES), "the residual epilogue goes with the Stokes apply");
+    static_assert(!VG || sizeof(T) == 4, "geometry from vertices is the FP32 path");
     __shared__ T sbuf[WPB][CPW][BUF];
     __shared__ double pbuf[HAS_B ? WPB : 1][CPW][NT][8];
     // x-face hand-over between neighbouring cells of the row: [slot][j][comp][k],
@@ -153,6 +166,29 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         if constexpr (HAS_BT) {
 #pragma unroll
             for (int n = 0; n < 8; ++n) pv[n] = act ? T(a.p[a.pmap[cell * 8 + n]]) : T(0);
+        }
+        // geometry from vertices: at this thread's (qy, qz) the Jacobian columns of the
+        // multilinear map x = X + sum_v N_v d_v are dx/dxi_0 = g0 (constant in qx) and
+        // dx/dxi_1 = L0(qx) b0 + L1(qx) b1, dx/dxi_2 = L0(qx) f0 + L1(qx) f1, where the
+        // reference cell sizes are folded in (L0 + L1 = 1); vertex v = i + 2j + 4k
+        T vg0[3], vb0[3], vb1[3], vf0[3], vf1[3];
+        if constexpr (VG) {
+            float4 dv[8];
+#pragma unroll
+            for (int n = 0; n < 8; ++n) dv[n] = act ? a.vd[a.pmap[cell * 8 + n]] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const T ly0 = rL<T>(qy, 0), ly1 = rL<T>(qy, 1), lz0 = rL<T>(qz, 0), lz1 = rL<T>(qz, 1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                T d[8];
+#pragma unroll
+                for (int n = 0; n < 8; ++n) d[n] = c == 0 ? dv[n].x : (c == 1 ? dv[n].y : dv[n].z);
+                vg0[c] = (c == 0 ? a.hx : T(0)) + ly0 * lz0 * (d[1] - d[0]) + ly1 * lz0 * (d[3] - d[2]) +
+                         ly0 * lz1 * (d[5] - d[4]) + ly1 * lz1 * (d[7] - d[6]);
+                vb0[c] = (c == 1 ? a.hy : T(0)) + lz0 * (d[2] - d[0]) + lz1 * (d[6] - d[4]);
+                vb1[c] = (c == 1 ? a.hy : T(0)) + lz0 * (d[3] - d[1]) + lz1 * (d[7] - d[5]);
+                vf0[c] = (c == 2 ? a.hz : T(0)) + ly0 * (d[4] - d[0]) + ly1 * (d[6] - d[2]);
+                vf1[c] = (c == 2 ? a.hz : T(0)) + ly0 * (d[5] - d[1]) + ly1 * (d[7] - d[3]);
+            }
         }
 
         // ---------------- forward sweeps z (A), y (B); x happens per point in stage C
@@ -318,12 +354,46 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
 #pragma unroll
         for (int qx = 0; qx < 3; ++qx) {
             // geometry of the point: K = det(J) w J^{-1} (row-major 3x3), cvisc, cmass
-            T Kq[9];
+            T Kq[9], cvq = T(0), cmq = T(0);
             const int64_t off = ((int64_t)qx * a.nchk + chunk) * kGeoSlots + (slot * NT + t);
+            if constexpr (VG) {
+                // det(J) w J^{-1} = w adj(J): no division; J[r][a] = dx_r/dxi_a
+                const T lx0 = rL<T>(qx, 0), lx1 = rL<T>(qx, 1);
+                T Jm[9];
 #pragma unroll
-            for (int e = 0; e < 9; ++e) Kq[e] = act ? gload<NTL>(a.K + e * P + off) : T(0);
-            const T cvq = (HAS_A && act) ? gload<NTL>(a.cv + off) : T(0);
-            const T cmq = (HAS_A && act) ? gload<NTL>(a.cv + P + off) : T(0);
+                for (int r = 0; r < 3; ++r) {
+                    Jm[r * 3 + 0] = vg0[r];
+                    Jm[r * 3 + 1] = lx0 * vb0[r] + lx1 * vb1[r];
+                    Jm[r * 3 + 2] = lx0 * vf0[r] + lx1 * vf1[r];
+                }
+                const T wq = rW<T>(qx) * rW<T>(qy) * rW<T>(qz);
+                const T c00 = Jm[4] * Jm[8] - Jm[5] * Jm[7];
+                const T c01 = Jm[5] * Jm[6] - Jm[3] * Jm[8];
+                const T c02 = Jm[3] * Jm[7] - Jm[4] * Jm[6];
+                const T det = Jm[0] * c00 + Jm[1] * c01 + Jm[2] * c02;
+                Kq[0] = wq * c00;
+                Kq[1] = wq * (Jm[2] * Jm[7] - Jm[1] * Jm[8]);
+                Kq[2] = wq * (Jm[1] * Jm[5] - Jm[2] * Jm[4]);
+                Kq[3] = wq * c01;
+                Kq[4] = wq * (Jm[0] * Jm[8] - Jm[2] * Jm[6]);
+                Kq[5] = wq * (Jm[2] * Jm[3] - Jm[0] * Jm[5]);
+                Kq[6] = wq * c02;
+                Kq[7] = wq * (Jm[1] * Jm[6] - Jm[0] * Jm[7]);
+                Kq[8] = wq * (Jm[0] * Jm[4] - Jm[1] * Jm[3]);
+                if constexpr (HAS_A) {
+                    if (act) {
+                        const T cw = det * wq;
+                        // hardware reciprocal (about 1 ulp): this is the FP32 preconditioner path
+                        cvq = gload<NTL>(a.cq + off) * __builtin_amdgcn_rcpf(cw);   // 2 eta / (det J w)
+                        cmq = gload<NTL>(a.cq + P + off) * cw;                       // c_m det J w
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 9; ++e) Kq[e] = act ? gload<NTL>(a.K + e * P + off) : T(0);
+                cvq = (HAS_A && act) ? gload<NTL>(a.cv + off) : T(0);
+                cmq = (HAS_A && act) ? gload<NTL>(a.cv + P + off) : T(0);
+            }
             T Tm[3][3];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
@@ -880,10 +950,19 @@ template <typename T, int MODE, int WPB, bool NTL, int WPE>
 static void launch_one(const Level& L, const CellArgs<T>& args, hipStream_t s) {
     const int64_t grid = (args.nrows + WPB - 1) / WPB;   // one wavefront per row of cells
     if (grid <= 0) return;
-    if (L.dim == 3)
-        hipLaunchKernelGGL((cell3d<T, MODE, WPB, false, NTL, WPE>), dim3((unsigned)grid), dim3(64 * WPB), 0, s, args);
-    else
+    if (L.dim == 3) {
+        if constexpr (sizeof(T) == 4) {
+            if (args.vd) {
+                hipLaunchKernelGGL((cell3d<T, MODE, WPB, false, NTL, WPE, true>), dim3((unsigned)grid),
+                                   dim3(64 * WPB), 0, s, args);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((cell3d<T, MODE, WPB, false, NTL, WPE, false>), dim3((unsigned)grid), dim3(64 * WPB), 0,
+                           s, args);
+    } else {
         hipLaunchKernelGGL((cell2d<T, MODE, WPB, false, NTL>), dim3((unsigned)grid), dim3(64 * WPB), 0, s, args);
+    }
 }
 
 // launch variant v: v & 1 two wavefronts per workgroup (else one); v & 2 plain
@@ -934,6 +1013,15 @@ static CellArgs<T> phase_args(const Level& L, int phase, const T* K, const T* cv
     args.pmap = L.d_pmap;
     args.K = K;
     args.cv = cv;
+    if constexpr (sizeof(T) == 4) {
+        if (L.vgeo && L.dim == 3) {
+            args.vd = L.d_vd32;
+            args.cq = L.d_cq32;
+            args.hx = (T)L.h[0];
+            args.hy = (T)L.h[1];
+            args.hz = (T)L.h[2];
+        }
+    }
     return args;
 }
 

@@ -58,9 +58,13 @@ def test_fp64_operators_match_oracle(name):
         _cmp(q, rq, 1e-12, f"{name} L{j} stokes-q")
 
 
-@pytest.mark.parametrize("name", ["C0", "T3_R", "T3_8"])
-def test_fp32_operators_match_oracle(name):
+@pytest.mark.parametrize("vertex_geometry", [0, 1])
+@pytest.mark.parametrize("name", ["C0", "T3_R", "T3_8", "T3_16"])
+def test_fp32_operators_match_oracle(name, vertex_geometry):
+    """FP32 applies, with stored geometry and (3D) with det(J) w J^-1 formed from the
+    vertex displacements inside the kernel; both against the FP64 oracle."""
     wl, ctx, ops = _ctx_and_ops(name)
+    ctx.set_mg_params(vertex_geometry=vertex_geometry)
     rng = np.random.default_rng(11)
     j = ctx.n_levels - 1
     op = ops[j]

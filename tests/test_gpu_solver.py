@@ -90,9 +90,9 @@ def test_fused_epilogues_equal_separate_kernels(name):
     ru = torch.from_numpy(rng.uniform(-1, 1, op.box.n_vel)).cuda()   # wall entries too
     rp = torch.from_numpy(rng.uniform(-1, 1, op.box.n_p)).cuda()
     for prec, tol in ((0, 1e-13), (1, 2e-5)):
-        ref_u, ref_p = _vc(ctx, ru, rp, precision=prec, fused=0, use_graph=0, tuned=0)
+        ref_u, ref_p = _vc(ctx, ru, rp, precision=prec, fused=0, use_graph=0, tuned=0, vertex_geometry=0)
         for fused, graph, tuned in ((1, 0, 0), (1, 0, 1), (1, 1, 1), (0, 1, 1)):
-            zu, zp = _vc(ctx, ru, rp, precision=prec, fused=fused, use_graph=graph, tuned=tuned)
+            zu, zp = _vc(ctx, ru, rp, precision=prec, fused=fused, use_graph=graph, tuned=tuned, vertex_geometry=0)
             eu = np.linalg.norm(zu - ref_u) / np.linalg.norm(ref_u)
             ep = np.linalg.norm(zp - ref_p) / np.linalg.norm(ref_p)
             print(name, prec, fused, graph, tuned, eu, ep)
@@ -114,3 +114,21 @@ def test_graph_replays_match_eager():
             assert np.linalg.norm(gu - eu) <= tol * np.linalg.norm(eu), (prec, rep)
             assert np.linalg.norm(gp - ep) <= tol * np.linalg.norm(ep), (prec, rep)
             _vc(ctx, 2 * ru, rp, precision=prec, use_graph=0)     # eager work between replays
+
+
+@pytest.mark.parametrize("name", ["T3_R", "T3_8"])
+def test_mixed_vcycle_with_vertex_geometry_close_to_stored(name):
+    """The FP32 V-cycle with geometry formed from vertices equals the one with stored
+    FP32 geometry up to FP32 rounding of J (graph and eager)."""
+    wl, ctx, ops = _setup(name)
+    rng = np.random.default_rng(13)
+    op = ops[-1]
+    ru = torch.from_numpy(rng.uniform(-1, 1, op.box.n_vel) * ~op.dir_mask).cuda()
+    rp = torch.from_numpy(rng.uniform(-1, 1, op.box.n_p)).cuda()
+    su, sp = _vc(ctx, ru, rp, precision=1, vertex_geometry=0, use_graph=0)
+    for graph in (0, 1):
+        vu, vp = _vc(ctx, ru, rp, precision=1, vertex_geometry=1, use_graph=graph)
+        eu = np.linalg.norm(vu - su) / np.linalg.norm(su)
+        ep = np.linalg.norm(vp - sp) / np.linalg.norm(sp)
+        print(name, graph, eu, ep)
+        assert eu <= 1e-4 and ep <= 1e-4, (graph, eu, ep)
