@@ -241,42 +241,56 @@ void launch_vertex_disp32(const Level& L, const double* disp_fine, int stride, c
 
 // ---------------------------------------------------------------- diag(A)
 // diag_(a,n) = sum_q cmass phi_n^2 + (cvisc/2)(|G_n|^2 + G_n[a]^2), G_n = K^T grad-hat phi_n
-__global__ void k_diagA(int dim, int64_t cbeg, int64_t cend, const int* __restrict__ col2lex, int nx, int xpar,
+template <int DIM>
+__global__ __launch_bounds__(TPB) void k_diagA(int64_t cbeg, int64_t cend, const int* __restrict__ col2lex, int nx, int xpar,
                         GeoLayout geo, int64_t nvn, int64_t plane,
                         const int* __restrict__ vmap, const uint4* __restrict__ info,
                         const double* __restrict__ K, const double* __restrict__ cv, double* __restrict__ diag) {
-    const int NLOC = dim == 3 ? 27 : 9;
-    const int NT = dim == 3 ? 9 : 3;
-    const int Q = NLOC;
+    constexpr int NLOC = DIM == 3 ? 27 : 9, NQZ = DIM == 3 ? 3 : 1;
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cell = cbeg + id / NLOC;
     const int n = (int)(id % NLOC);
     if (cell >= cend) return;
     if ((col2lex[cell] % nx) % 2 != xpar) return;   // cells of a row share x-faces
     if ((info[cell].x >> n) & 1u) return;
-    int ni[3] = {n % 3, (n / 3) % 3, n / 9};
-    double acc[3] = {0, 0, 0};
-    for (int q = 0; q < Q; ++q) {
-        int qi[3] = {q % 3, (q / 3) % 3, q / 9};
-        const int qx = qi[0], t = q / 3;
-        const int64_t off = geo_off(geo, qx, cell, t);
-        double phi = 1.0, gh[3];
-        for (int d = 0; d < dim; ++d) phi *= dS(qi[d], ni[d]);
-        for (int b = 0; b < dim; ++b) {
-            double v = 1.0;
-            for (int d = 0; d < dim; ++d) v *= (d == b) ? dD(qi[d], ni[d]) : dS(qi[d], ni[d]);
-            gh[b] = v;
-        }
-        double G[3] = {0, 0, 0}, g2 = 0.0;
-        for (int a = 0; a < dim; ++a) {
-            for (int b = 0; b < dim; ++b) G[a] += K[(b * dim + a) * plane + off] * gh[b];
-            g2 += G[a] * G[a];
-        }
-        const double cvisc = cv[off], cmass = cv[plane + off];
-        for (int a = 0; a < dim; ++a) acc[a] += cmass * phi * phi + 0.5 * cvisc * (g2 + G[a] * G[a]);
+    const int ni[3] = {n % 3, (n / 3) % 3, n / 9};
+    double S1[1][3], D1[1][3];   // 1D value and derivative tables of the node along x
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        S1[0][q] = dS(q, ni[0]);
+        D1[0][q] = dD(q, ni[0]);
     }
+    double acc[3] = {0, 0, 0};
+    // outer points in loops (tables re-evaluated there), the x points unrolled: a full
+    // unroll hoists all 27 points' loads and runs out of registers
+#pragma unroll 1
+    for (int q2 = 0; q2 < NQZ; ++q2)
+#pragma unroll 1
+        for (int q1 = 0; q1 < 3; ++q1) {
+            const double s2 = DIM == 3 ? dS(q2, ni[2]) : 1.0, d2 = DIM == 3 ? dD(q2, ni[2]) : 0.0;
+            const double s1 = dS(q1, ni[1]), d1 = dD(q1, ni[1]);
+#pragma unroll
+            for (int q0 = 0; q0 < 3; ++q0) {
+                const int64_t off = geo_off(geo, q0, cell, q1 + 3 * q2);
+                const double phi = S1[0][q0] * s1 * s2;
+                double gh[3];
+                gh[0] = D1[0][q0] * s1 * s2;
+                gh[1] = S1[0][q0] * d1 * s2;
+                gh[2] = S1[0][q0] * s1 * d2;
+                double G[3] = {0, 0, 0}, g2 = 0.0;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+#pragma unroll
+                    for (int b = 0; b < DIM; ++b) G[a] += K[(b * DIM + a) * plane + off] * gh[b];
+                    g2 += G[a] * G[a];
+                }
+                const double cvisc = cv[off], cmass = cv[plane + off];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) acc[a] += cmass * phi * phi + 0.5 * cvisc * (g2 + G[a] * G[a]);
+            }
+        }
     const int node = vmap[cell * NLOC + n];
-    for (int a = 0; a < dim; ++a) diag[a * nvn + node] += acc[a];
+    for (int a = 0; a < DIM; ++a) diag[a * nvn + node] += acc[a];
 }
 
 void launch_diagA(const Level& L, const double* K, const double* cv, double* diag, hipStream_t s) {
@@ -285,9 +299,14 @@ void launch_diagA(const Level& L, const double* K, const double* cv, double* dia
         for (int xpar = 0; xpar < 2; ++xpar) {
             const int64_t n = (L.phase_off[ph + 1] - L.phase_off[ph]) * nloc;
             if (n == 0) continue;
-            hipLaunchKernelGGL(k_diagA, dim3(nblocks(n)), dim3(TPB), 0, s, L.dim, L.phase_off[ph],
-                               L.phase_off[ph + 1], L.d_col2lex, L.cells[0], xpar, L.geo, L.nvn, L.plane(), L.d_vmap,
-                               L.d_info, K, cv, diag);
+            if (L.dim == 3)
+                hipLaunchKernelGGL(k_diagA<3>, dim3(nblocks(n)), dim3(TPB), 0, s, L.phase_off[ph], L.phase_off[ph + 1],
+                                   L.d_col2lex, L.cells[0], xpar, L.geo, L.nvn, L.plane(), L.d_vmap, L.d_info, K, cv,
+                                   diag);
+            else
+                hipLaunchKernelGGL(k_diagA<2>, dim3(nblocks(n)), dim3(TPB), 0, s, L.phase_off[ph], L.phase_off[ph + 1],
+                                   L.d_col2lex, L.cells[0], xpar, L.geo, L.nvn, L.plane(), L.d_vmap, L.d_info, K, cv,
+                                   diag);
         }
 }
 
@@ -307,73 +326,130 @@ void launch_diagA_finish(const Level& L, double* diag, double* dinv64, float* di
 }
 
 // ---------------------------------------------------------------- diag(B diag(A)^{-1} B^T)
-// one workgroup per pressure node; thread = node of the 5^dim velocity patch around it.
-// The assembled row entries B_{k,(a,n)} are sums over the cells sharing vertex k and node n.
-__global__ void k_diagS(int dim, int c0, int c1, int c2, int vn0, int vn1, int vn2, GeoLayout geo, int64_t nvn,
+// s_k = sum_i (B_{k,i})^2 / A_ii over the velocity dofs i of the 5^dim node patch around
+// vertex k.  One workgroup per pressure node: thread (c, n) evaluates, for cell c of the
+// 2^dim cells around the vertex and its local node n, the three element-row entries
+// B^K_{k,(a,n)} = sum_q psi_k(q) (K^T grad-hat phi_n)_a(q); thread p then sums the
+// entries of patch node p over the cells containing it (fixed order, no atomics).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_diagS(int c0, int c1, int c2, int vn0, int vn1, int vn2, GeoLayout geo, int64_t nvn,
                         int64_t plane, const int* __restrict__ lex2col, const uint8_t* __restrict__ wall,
                         const double* __restrict__ K, const double* __restrict__ dAinv,
                         double* __restrict__ dSinv) {
-    __shared__ double red[128];
+    constexpr int NLOC = DIM == 3 ? 27 : 9, NCELL = 1 << DIM, Q = NLOC, DD = DIM * DIM;
+    constexpr int NQZ = DIM == 3 ? 3 : 1;
+    __shared__ double be[NCELL][NLOC][DIM];   // [cell][local node][component]
+    __shared__ double kg[NCELL][Q][DD];       // K of the cells around the vertex
+    __shared__ double red[256];
     const int pn0 = c0 + 1, pn1 = c1 + 1;
     const int64_t k = blockIdx.x;
-    const int kv[3] = {(int)(k % pn0), (int)((k / pn0) % pn1), (int)(k / ((int64_t)pn0 * pn1))};
+    const int kv[3] = {(int)(k % pn0), (int)((k / pn0) % pn1), DIM == 3 ? (int)(k / ((int64_t)pn0 * pn1)) : 0};
     const int tid = threadIdx.x;
-    const int npatch = dim == 3 ? 125 : 25;
-    const int NT = dim == 3 ? 9 : 3;
     const int cells[3] = {c0, c1, c2};
     const int vn[3] = {vn0, vn1, vn2};
+    // stage the geometry of the cells around the vertex once (each value is used by
+    // every local node of its cell)
+    for (int e = tid; e < NCELL * Q * DD; e += blockDim.x) {
+        const int c = e / (Q * DD), r = e - c * (Q * DD), q = r / DD, pl = r - q * DD;
+        int ce[3] = {0, 0, 0};
+        bool in = true;
+        for (int d = 0; d < DIM; ++d) {
+            ce[d] = kv[d] - 1 + ((c >> d) & 1);
+            if (ce[d] < 0 || ce[d] >= cells[d]) in = false;
+        }
+        double v = 0.0;
+        if (in) {
+            const int64_t lex = ce[0] + (int64_t)cells[0] * (ce[1] + (int64_t)cells[1] * ce[2]);
+            v = K[pl * plane + geo_off(geo, q % 3, lex2col[lex], q / 3)];
+        }
+        kg[c][q][pl] = v;
+    }
+    __syncthreads();
+    // element-row entries of the cells around the vertex: 1D tables of this thread's
+    // node (values, derivatives) and of the vertex's Q1 function, then tensor products
+    if (tid < NCELL * NLOC) {
+        const int c = tid / NLOC, n = tid % NLOC;
+        const int ni[3] = {n % 3, (n / 3) % 3, n / 9};
+        bool in = true;
+        int kl[3] = {0, 0, 0};
+        for (int d = 0; d < DIM; ++d) {
+            const int ce = kv[d] - 1 + ((c >> d) & 1);
+            if (ce < 0 || ce >= cells[d]) in = false;
+            kl[d] = kv[d] - ce;
+        }
+        double S1[3][3], D1[3][3], P1[3][3];   // [direction][point]
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                S1[d][q] = d < DIM ? dS(q, ni[d]) : 1.0;
+                D1[d][q] = d < DIM ? dD(q, ni[d]) : 0.0;
+                P1[d][q] = d < DIM ? dL(q, kl[d]) : 1.0;
+            }
+        double bs[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) bs[a] = 0.0;
+        if (in) {
+#pragma unroll
+            for (int q2 = 0; q2 < NQZ; ++q2)
+#pragma unroll
+                for (int q1 = 0; q1 < 3; ++q1)
+#pragma unroll
+                    for (int q0 = 0; q0 < 3; ++q0) {
+                        const int q = q0 + 3 * q1 + 9 * q2;
+                        const double psi = P1[0][q0] * P1[1][q1] * P1[2][q2];
+                        double gh[3];
+                        gh[0] = D1[0][q0] * S1[1][q1] * S1[2][q2];
+                        gh[1] = S1[0][q0] * D1[1][q1] * S1[2][q2];
+                        gh[2] = S1[0][q0] * S1[1][q1] * D1[2][q2];
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) {
+                            double G = 0.0;
+#pragma unroll
+                            for (int b = 0; b < DIM; ++b) G += kg[c][q][b * DIM + a] * gh[b];
+                            bs[a] += psi * G;
+                        }
+                    }
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) be[c][n][a] = bs[a];
+    }
+    __syncthreads();
+    // patch node p: sum its entries over the cells containing it
     double contrib = 0.0;
+    const int npatch = DIM == 3 ? 125 : 25;
     if (tid < npatch) {
-        const int pi[3] = {tid % 5, (tid / 5) % 5, tid / 25};
+        const int pi[3] = {tid % 5, (tid / 5) % 5, DIM == 3 ? tid / 25 : 0};
         int g[3] = {0, 0, 0};
         bool ok = true;
-        for (int d = 0; d < dim; ++d) {
+        for (int d = 0; d < DIM; ++d) {
             g[d] = 2 * kv[d] - 2 + pi[d];
             if (g[d] < 0 || g[d] >= vn[d]) ok = false;
         }
         if (ok) {
-            int64_t node = g[0] + (int64_t)vn[0] * (g[1] + (int64_t)vn[1] * (dim == 3 ? g[2] : 0));
+            const int64_t node = g[0] + (int64_t)vn[0] * (g[1] + (int64_t)vn[1] * g[2]);
             if (!wall[node]) {
-                double bs[3] = {0, 0, 0};
-                const int ncell = 1 << dim;
-                for (int cidx = 0; cidx < ncell; ++cidx) {
-                    int ce[3] = {0, 0, 0}, nl[3] = {0, 0, 0}, kl[3] = {0, 0, 0};
-                    bool in = true;
-                    for (int d = 0; d < dim; ++d) {
-                        ce[d] = kv[d] - 1 + ((cidx >> d) & 1);
-                        if (ce[d] < 0 || ce[d] >= cells[d]) in = false;
-                        nl[d] = g[d] - 2 * ce[d];
-                        if (nl[d] < 0 || nl[d] > 2) in = false;
-                        kl[d] = kv[d] - ce[d];
+                double bsum[DIM];
+                for (int a = 0; a < DIM; ++a) bsum[a] = 0.0;
+                for (int c = 0; c < NCELL; ++c) {
+                    int n = 0, st = 1;
+                    bool inside = true;
+                    for (int d = 0; d < DIM; ++d) {
+                        const int l = pi[d] - 2 * ((c >> d) & 1);   // local index in cell c
+                        if (l < 0 || l > 2) inside = false;
+                        n += l * st;
+                        st *= 3;
                     }
-                    if (!in) continue;
-                    const int64_t lex = ce[0] + (int64_t)cells[0] * (ce[1] + (int64_t)cells[1] * (dim == 3 ? ce[2] : 0));
-                    const int64_t col = lex2col[lex];
-                    const int Q = dim == 3 ? 27 : 9;
-                    for (int q = 0; q < Q; ++q) {
-                        const int qi[3] = {q % 3, (q / 3) % 3, q / 9};
-                        const int64_t off = geo_off(geo, qi[0], col, q / 3);
-                        double psi = 1.0, gh[3];
-                        for (int d = 0; d < dim; ++d) psi *= dL(qi[d], kl[d]);
-                        for (int b = 0; b < dim; ++b) {
-                            double v = 1.0;
-                            for (int d = 0; d < dim; ++d) v *= (d == b) ? dD(qi[d], nl[d]) : dS(qi[d], nl[d]);
-                            gh[b] = v;
-                        }
-                        for (int a = 0; a < dim; ++a) {
-                            double G = 0.0;
-                            for (int b = 0; b < dim; ++b) G += K[(b * dim + a) * plane + off] * gh[b];
-                            bs[a] += psi * G;
-                        }
-                    }
+                    if (!inside) continue;                      // cells outside the mesh hold zeros
+                    for (int a = 0; a < DIM; ++a) bsum[a] += be[c][n][a];
                 }
-                for (int a = 0; a < dim; ++a) contrib += bs[a] * bs[a] * dAinv[a * nvn + node];
+                for (int a = 0; a < DIM; ++a) contrib += bsum[a] * bsum[a] * dAinv[a * nvn + node];
             }
         }
     }
     red[tid] = contrib;
     __syncthreads();
-    for (int st = 64; st > 0; st >>= 1) {
+    for (int st = 128; st > 0; st >>= 1) {
         if (tid < st) red[tid] += red[tid + st];
         __syncthreads();
     }
@@ -382,9 +458,14 @@ __global__ void k_diagS(int dim, int c0, int c1, int c2, int vn0, int vn1, int v
 
 void launch_diagS_impl(const Level& L, const uint8_t* d_wall, const double* K, const double* dAinv, double* dSinv,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_diagS, dim3((unsigned)L.np), dim3(128), 0, s, L.dim, L.cells[0], L.cells[1], L.cells[2],
-                       L.vnodes[0], L.vnodes[1], L.vnodes[2], L.geo, L.nvn, L.plane(), L.d_lex2col, d_wall, K,
-                       dAinv, dSinv);
+    if (L.dim == 3)
+        hipLaunchKernelGGL(k_diagS<3>, dim3((unsigned)L.np), dim3(256), 0, s, L.cells[0], L.cells[1], L.cells[2],
+                           L.vnodes[0], L.vnodes[1], L.vnodes[2], L.geo, L.nvn, L.plane(), L.d_lex2col, d_wall, K,
+                           dAinv, dSinv);
+    else
+        hipLaunchKernelGGL(k_diagS<2>, dim3((unsigned)L.np), dim3(256), 0, s, L.cells[0], L.cells[1], L.cells[2],
+                           L.vnodes[0], L.vnodes[1], L.vnodes[2], L.geo, L.nvn, L.plane(), L.d_lex2col, d_wall, K,
+                           dAinv, dSinv);
 }
 
 // ---------------------------------------------------------------- simple vector kernels
@@ -861,83 +942,112 @@ template void launch_prolongate_add<float>(const Level&, const Level&, const flo
                                            hipStream_t);
 
 // ---------------------------------------------------------------- coarse level
-// One thread per (cell of one colour, local velocity dof): the element-matrix row
-// of A (mass + viscous) and the matching column of B^T / row of B are added to the
-// dense matrix restricted to free dofs (dof2row[dof] < 0 for wall dofs).
-__global__ void k_coarse_assemble(int dim, int64_t cbeg, int64_t cend, const int* __restrict__ col2lex, int nx,
-                                  int xpar, GeoLayout geo, int64_t nvn, int64_t plane,
-                                  const int* __restrict__ vmap, const int* __restrict__ pmap,
-                                  const double* __restrict__ K, const double* __restrict__ cv,
-                                  const int* __restrict__ vrow, int64_t nfree_u, double* __restrict__ M, int64_t n) {
-    const int NLOC = dim == 3 ? 27 : 9, NPL = dim == 3 ? 8 : 4, NT = dim == 3 ? 9 : 3;
+// One thread per (cell of one colour, test dof (a, n), column node m): the element
+// matrix entries of A (mass + viscous) for the trial dofs (b, m), b = 0..dim-1, or
+// (m >= NLOC) the B^T column / B row entries of pressure vertex m - NLOC, are added
+// to the dense matrix restricted to free dofs (dof2row[dof] < 0 for wall dofs).
+// Cells of one launch share no node, so every entry has one writer.
+template <int DIM>
+__global__ __launch_bounds__(64) void k_coarse_assemble(int64_t cbeg, int64_t cend, const int* __restrict__ col2lex, int nx, int xpar,
+                                  GeoLayout geo, int64_t nvn, int64_t plane, const int* __restrict__ vmap,
+                                  const int* __restrict__ pmap, const double* __restrict__ K,
+                                  const double* __restrict__ cv, const int* __restrict__ vrow, int64_t nfree_u,
+                                  double* __restrict__ M, int64_t n) {
+    constexpr int NLOC = DIM == 3 ? 27 : 9, NPL = DIM == 3 ? 8 : 4, NQZ = DIM == 3 ? 3 : 1;
+    constexpr int NCOL = NLOC + NPL, PER_CELL = DIM * NLOC * NCOL;
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t cell = cbeg + id / (dim * NLOC);
+    const int64_t cell = cbeg + id / PER_CELL;
     if (cell >= cend) return;
     if ((col2lex[cell] % nx) % 2 != xpar) return;   // cells of a row share x-faces
-    const int loc = (int)(id % (dim * NLOC));
-    const int a = loc / NLOC, nrow = loc % NLOC;
+    const int loc = (int)(id % PER_CELL);
+    const int a = loc / (NLOC * NCOL), nrow = (loc / NCOL) % NLOC, m = loc % NCOL;
     const int row = vrow[a * nvn + vmap[cell * NLOC + nrow]];
     if (row < 0) return;
     const int ni[3] = {nrow % 3, (nrow / 3) % 3, nrow / 9};
-    for (int b = 0; b < dim; ++b)
-        for (int m = 0; m < NLOC; ++m) {
-            const int col = vrow[b * nvn + vmap[cell * NLOC + m]];
-            if (col < 0) continue;
-            const int mi[3] = {m % 3, (m / 3) % 3, m / 9};
-            double acc = 0.0;
-            for (int q = 0; q < NLOC; ++q) {
-                const int qi[3] = {q % 3, (q / 3) % 3, q / 9};
-                const int64_t off = geo_off(geo, qi[0], cell, q / 3);
-                double phin = 1.0, phim = 1.0, gn[3], gm[3];
-                for (int d = 0; d < dim; ++d) {
-                    phin *= dS(qi[d], ni[d]);
-                    phim *= dS(qi[d], mi[d]);
-                }
-                for (int e = 0; e < dim; ++e) {
-                    double vn = 1.0, vm = 1.0;
-                    for (int d = 0; d < dim; ++d) {
-                        vn *= (d == e) ? dD(qi[d], ni[d]) : dS(qi[d], ni[d]);
-                        vm *= (d == e) ? dD(qi[d], mi[d]) : dS(qi[d], mi[d]);
-                    }
-                    gn[e] = vn;
-                    gm[e] = vm;
-                }
-                double Gn[3] = {0, 0, 0}, Gm[3] = {0, 0, 0};
-                for (int c = 0; c < dim; ++c)
-                    for (int e = 0; e < dim; ++e) {
-                        const double k = K[(e * dim + c) * plane + off];
-                        Gn[c] += k * gn[e];
-                        Gm[c] += k * gm[e];
-                    }
-                const double cvisc = cv[off], cmass = cv[plane + off];
-                double v = 0.5 * cvisc * Gn[b] * Gm[a];
-                if (a == b) {
+    double Sn[3][3], Dn[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            Sn[d][q] = d < DIM ? dS(q, ni[d]) : 1.0;
+            Dn[d][q] = d < DIM ? dD(q, ni[d]) : 0.0;
+        }
+    if (m < NLOC) {
+        const int mi[3] = {m % 3, (m / 3) % 3, m / 9};
+        double Sm[3][3], Dm[3][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                Sm[d][q] = d < DIM ? dS(q, mi[d]) : 1.0;
+                Dm[d][q] = d < DIM ? dD(q, mi[d]) : 0.0;
+            }
+        double acc[DIM];
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) acc[b] = 0.0;
+#pragma unroll 1
+        for (int q2 = 0; q2 < NQZ; ++q2)
+#pragma unroll 1
+            for (int q1 = 0; q1 < 3; ++q1)
+#pragma unroll
+                for (int q0 = 0; q0 < 3; ++q0) {
+                    const int64_t off = geo_off(geo, q0, cell, q1 + 3 * q2);
+                    const double phin = Sn[0][q0] * Sn[1][q1] * Sn[2][q2];
+                    const double phim = Sm[0][q0] * Sm[1][q1] * Sm[2][q2];
+                    const double gn[3] = {Dn[0][q0] * Sn[1][q1] * Sn[2][q2], Sn[0][q0] * Dn[1][q1] * Sn[2][q2],
+                                          Sn[0][q0] * Sn[1][q1] * Dn[2][q2]};
+                    const double gm[3] = {Dm[0][q0] * Sm[1][q1] * Sm[2][q2], Sm[0][q0] * Dm[1][q1] * Sm[2][q2],
+                                          Sm[0][q0] * Sm[1][q1] * Dm[2][q2]};
+                    double Gn[3] = {0, 0, 0}, Gm[3] = {0, 0, 0};
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                        for (int e = 0; e < DIM; ++e) {
+                            const double kk = K[(e * DIM + c) * plane + off];
+                            Gn[c] += kk * gn[e];
+                            Gm[c] += kk * gm[e];
+                        }
+                    const double cvisc = cv[off], cmass = cv[plane + off];
                     double dot = 0.0;
-                    for (int c = 0; c < dim; ++c) dot += Gn[c] * Gm[c];
-                    v += cmass * phin * phim + 0.5 * cvisc * dot;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) dot += Gn[c] * Gm[c];
+#pragma unroll
+                    for (int b = 0; b < DIM; ++b) {
+                        double v = 0.5 * cvisc * Gn[b] * Gm[a];
+                        if (a == b) v += cmass * phin * phim + 0.5 * cvisc * dot;
+                        acc[b] += v;
+                    }
                 }
-                acc += v;
-            }
-            M[(int64_t)row * n + col] += acc;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            const int col = vrow[b * nvn + vmap[cell * NLOC + m]];
+            if (col >= 0) M[(int64_t)row * n + col] += acc[b];
         }
-    // B^T column / B row entries for the pressure dofs of this cell
-    for (int kk = 0; kk < NPL; ++kk) {
+    } else {
+        // B^T column / B row entries of pressure vertex kk of this cell
+        const int kk = m - NLOC;
         const int ki[3] = {kk & 1, (kk >> 1) & 1, (kk >> 2) & 1};
+        double P1[3][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) P1[d][q] = d < DIM ? dL(q, ki[d]) : 1.0;
         double acc = 0.0;
-        for (int q = 0; q < NLOC; ++q) {
-            const int qi[3] = {q % 3, (q / 3) % 3, q / 9};
-            const int64_t off = geo_off(geo, qi[0], cell, q / 3);
-            double psi = 1.0, gn[3];
-            for (int d = 0; d < dim; ++d) psi *= dL(qi[d], ki[d]);
-            for (int e = 0; e < dim; ++e) {
-                double vn = 1.0;
-                for (int d = 0; d < dim; ++d) vn *= (d == e) ? dD(qi[d], ni[d]) : dS(qi[d], ni[d]);
-                gn[e] = vn;
-            }
-            double G = 0.0;
-            for (int e = 0; e < dim; ++e) G += K[(e * dim + a) * plane + off] * gn[e];
-            acc += psi * G;
-        }
+#pragma unroll 1
+        for (int q2 = 0; q2 < NQZ; ++q2)
+#pragma unroll 1
+            for (int q1 = 0; q1 < 3; ++q1)
+#pragma unroll
+                for (int q0 = 0; q0 < 3; ++q0) {
+                    const int64_t off = geo_off(geo, q0, cell, q1 + 3 * q2);
+                    const double psi = P1[0][q0] * P1[1][q1] * P1[2][q2];
+                    const double gn[3] = {Dn[0][q0] * Sn[1][q1] * Sn[2][q2], Sn[0][q0] * Dn[1][q1] * Sn[2][q2],
+                                          Sn[0][q0] * Sn[1][q1] * Dn[2][q2]};
+                    double G = 0.0;
+#pragma unroll
+                    for (int e = 0; e < DIM; ++e) G += K[(e * DIM + a) * plane + off] * gn[e];
+                    acc += psi * G;
+                }
         const int64_t prow = nfree_u + pmap[cell * NPL + kk];
         M[(int64_t)row * n + prow] += acc;
         M[prow * n + row] += acc;
@@ -946,14 +1056,19 @@ __global__ void k_coarse_assemble(int dim, int64_t cbeg, int64_t cend, const int
 
 void launch_coarse_assemble_impl(const Level& L, const double* K, const double* cv, const int* vrow,
                                  int64_t nfree_u, double* M, int64_t n, hipStream_t s) {
-    const int nloc = L.dim == 3 ? 27 : 9;
+    const int nloc = L.dim == 3 ? 27 : 9, npl = L.dim == 3 ? 8 : 4;
     for (int ph = 0; ph < L.nphases(); ++ph)
         for (int xpar = 0; xpar < 2; ++xpar) {
-            const int64_t cnt = (L.phase_off[ph + 1] - L.phase_off[ph]) * L.dim * nloc;
+            const int64_t cnt = (L.phase_off[ph + 1] - L.phase_off[ph]) * L.dim * nloc * (nloc + npl);
             if (cnt == 0) continue;
-            hipLaunchKernelGGL(k_coarse_assemble, dim3(nblocks(cnt, 64)), dim3(64), 0, s, L.dim, L.phase_off[ph],
-                               L.phase_off[ph + 1], L.d_col2lex, L.cells[0], xpar, L.geo, L.nvn, L.plane(), L.d_vmap,
-                               L.d_pmap, K, cv, vrow, nfree_u, M, n);
+            if (L.dim == 3)
+                hipLaunchKernelGGL(k_coarse_assemble<3>, dim3(nblocks(cnt, 64)), dim3(64), 0, s, L.phase_off[ph],
+                                   L.phase_off[ph + 1], L.d_col2lex, L.cells[0], xpar, L.geo, L.nvn, L.plane(),
+                                   L.d_vmap, L.d_pmap, K, cv, vrow, nfree_u, M, n);
+            else
+                hipLaunchKernelGGL(k_coarse_assemble<2>, dim3(nblocks(cnt, 64)), dim3(64), 0, s, L.phase_off[ph],
+                                   L.phase_off[ph + 1], L.d_col2lex, L.cells[0], xpar, L.geo, L.nvn, L.plane(),
+                                   L.d_vmap, L.d_pmap, K, cv, vrow, nfree_u, M, n);
         }
 }
 
