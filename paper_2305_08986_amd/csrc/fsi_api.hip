@@ -218,6 +218,8 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
     TRY(dalloc(ctx, &L.d_K32, (int64_t)dim * dim * P));
     TRY(dalloc(ctx, &L.d_cv32, 2 * P));
     TRY(dalloc(ctx, &L.d_cq32, 2 * P));
+    TRY(dalloc(ctx, &L.d_Ks64, (int64_t)dim * dim * P));
+    TRY(dalloc(ctx, &L.d_Ks32, (int64_t)dim * dim * P));
     TRY(dalloc(ctx, &L.d_vd32, L.np));
     for (int d = 0; d < dim; ++d) L.h[d] = m.extent[d] / L.cells[d];
     TRY(dalloc(ctx, &L.d_dAinv64, L.nv));
@@ -232,6 +234,12 @@ template <> std::vector<LevelWork<float>>& works<float>(Context* c) { return c->
 template <typename T> static const T* Kp(const Level& L);
 template <> const double* Kp<double>(const Level& L) { return L.d_K64; }
 template <> const float* Kp<float>(const Level& L) { return L.d_K32; }
+// geometry planes a cell-kernel mode reads: A alone (and with the Chebyshev epilogue)
+// reads sqrt(cvisc) K, the other modes K
+static bool scaled_mode(int mode) { return mode == OP_A || mode == (OP_A | OP_CHEB); }
+template <typename T> static const T* Kmode(const Level& L, int mode);
+template <> const double* Kmode<double>(const Level& L, int mode) { return scaled_mode(mode) ? L.d_Ks64 : L.d_K64; }
+template <> const float* Kmode<float>(const Level& L, int mode) { return scaled_mode(mode) ? L.d_Ks32 : L.d_K32; }
 template <typename T> static const T* CVp(const Level& L);
 template <> const double* CVp<double>(const Level& L) { return L.d_cv64; }
 template <> const float* CVp<float>(const Level& L) { return L.d_cv32; }
@@ -282,7 +290,8 @@ static void op_apply(Context* ctx, int j, int mode, const T* u, const double* p,
     // every output entry is written by its first touching cell (no clearing pass);
     // wall rows: identity for A, zero for B^T alone
     const Level& L = ctx->lv[j];
-    launch_cell_all<T>(L, mode, variant_of(ctx, prec_index<T>(), j, mode), Kp<T>(L), CVp<T>(L), u, p, v, q, s);
+    launch_cell_all<T>(L, mode, variant_of(ctx, prec_index<T>(), j, mode), Kmode<T>(L, mode), CVp<T>(L), u, p, v, q,
+                       s);
     if (mode & OP_A) launch_dirichlet_copy<T>(L, u, v, s);
     else if (mode & OP_BT) launch_dirichlet_zero<T>(L, v, s);
 }
@@ -302,7 +311,8 @@ static void cheb(Context* ctx, int j, const T* r, T* x, hipStream_t s) {
         if (ctx->prm.fused && (!ctx->prm.tuned || ctx->fuse_cheb[prec_index<T>()][j])) {
             // the update happens at each node's last touch; the last step needs no direction
             const bool store_d = i + 1 < ctx->prm.k_A;
-            launch_cell_cheb_all<T>(L, variant_of(ctx, prec_index<T>(), j, OP_A | OP_CHEB), Kp<T>(L), CVp<T>(L), x,
+            launch_cell_cheb_all<T>(L, variant_of(ctx, prec_index<T>(), j, OP_A | OP_CHEB), Kmode<T>(L, OP_A | OP_CHEB),
+                                    CVp<T>(L), x,
                                     W.cd_u, r,
                                     DAp<T>(L), W.cax_u, c1, c2, store_d, s);
             launch_dirichlet_cheb<T>(L, x, W.cd_u, r, DAp<T>(L), c1, c2, store_d, s);
@@ -800,7 +810,8 @@ fsi_status fsi_set_coefficients(fsi_ctx* h, int level, const double* c_mass, con
     if (!L.geo_set) return fail(ctx, FSI_ERR_STATE, "set_coefficients before the level's geometry");
     invalidate(ctx);
     launch_fill<int>(ctx->d_flag, 0, 1, ctx->stream);
-    launch_coefficients(L, c_mass, eta, L.d_cw64, L.d_cv64, L.d_cv32, L.d_cq32, ctx->d_flag, ctx->stream);
+    launch_coefficients(L, c_mass, eta, L.d_cw64, L.d_cv64, L.d_cv32, L.d_cq32, L.d_K64, L.d_Ks64, L.d_Ks32,
+                        ctx->d_flag, ctx->stream);
     L.coef_set = false;
     TRY(sync_flag(ctx, FSI_ERR_NONFINITE, "coefficient not finite (or negative viscosity)"));
     L.coef_set = true;
@@ -1139,21 +1150,21 @@ static void launch_phase_on_work(Context* ctx, int prec, int j, int mode, int va
     if (prec == 0) {
         LevelWork<double>& W = ctx->w64[j];
         if (mode == (OP_A | OP_CHEB))
-            launch_cell_cheb<double>(L, var, ph, L.d_K64, L.d_cv64, W.w_u, W.cd_u, W.f_u, L.d_dAinv64, W.cax_u, 0.0,
+            launch_cell_cheb<double>(L, var, ph, L.d_Ks64, L.d_cv64, W.w_u, W.cd_u, W.f_u, L.d_dAinv64, W.cax_u, 0.0,
                                      0.0, true, s);
         else if (mode == (OP_A | OP_BT | OP_B | OP_RES))
             launch_cell_res<double>(L, var, ph, L.d_K64, L.d_cv64, W.x_u, W.x_p, W.f_u, W.f_p, W.r_u, W.r_p, s);
         else
-            launch_cell<double>(L, mode, var, ph, L.d_K64, L.d_cv64, W.x_u, W.x_p, W.r_u, W.r_p, s);
+            launch_cell<double>(L, mode, var, ph, Kmode<double>(L, mode), L.d_cv64, W.x_u, W.x_p, W.r_u, W.r_p, s);
     } else {
         LevelWork<float>& W = ctx->w32[j];
         if (mode == (OP_A | OP_CHEB))
-            launch_cell_cheb<float>(L, var, ph, L.d_K32, L.d_cv32, W.w_u, W.cd_u, W.f_u, L.d_dAinv32, W.cax_u, 0.0,
+            launch_cell_cheb<float>(L, var, ph, L.d_Ks32, L.d_cv32, W.w_u, W.cd_u, W.f_u, L.d_dAinv32, W.cax_u, 0.0,
                                     0.0, true, s);
         else if (mode == (OP_A | OP_BT | OP_B | OP_RES))
             launch_cell_res<float>(L, var, ph, L.d_K32, L.d_cv32, W.x_u, W.x_p, W.f_u, W.f_p, W.r_u, W.r_p, s);
         else
-            launch_cell<float>(L, mode, var, ph, L.d_K32, L.d_cv32, W.x_u, W.x_p, W.r_u, W.r_p, s);
+            launch_cell<float>(L, mode, var, ph, Kmode<float>(L, mode), L.d_cv32, W.x_u, W.x_p, W.r_u, W.r_p, s);
     }
 }
 

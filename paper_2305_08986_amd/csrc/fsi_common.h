@@ -115,6 +115,10 @@ struct Level {
     double* d_cv64 = nullptr;      // 2 planes: 2 eta/(det J w), c_m det J w
     float* d_K32 = nullptr;
     float* d_cv32 = nullptr;
+    // sqrt(cvisc) K: with it the viscous flux of A alone is sym(grad-hat u K') K'^T,
+    // so A reads 9 + 1 values per point instead of 9 + 2
+    double* d_Ks64 = nullptr;
+    float* d_Ks32 = nullptr;
     // FP32 geometry from vertices: level vertex displacement (x, y, z, 0) and per
     // point (2 eta, c_m) in the geometry layout; valid after fsi_set_displacement
     float4* d_vd32 = nullptr;
@@ -247,7 +251,8 @@ void launch_geometry(const Level& L, const double* J, double* K, double* cw, flo
 void launch_geometry_from_disp_h(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
                                  const double* h, double* K, double* cw, float* K32, int* flag, hipStream_t s);
 void launch_coefficients(const Level& L, const double* cm, const double* eta, const double* cw,
-                         double* cv64, float* cv32, float* cq32, int* flag, hipStream_t s);
+                         double* cv64, float* cv32, float* cq32, const double* K64, double* Ks64, float* Ks32,
+                         int* flag, hipStream_t s);
 // level vertex displacement (FP32 float4) from the fine-level displacement by injection
 void launch_vertex_disp32(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
                           float4* out, hipStream_t s);

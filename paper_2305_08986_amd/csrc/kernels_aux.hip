@@ -190,10 +190,12 @@ void launch_geometry_from_disp_h(const Level& L, const double* disp_fine, int st
 }
 
 // ---------------------------------------------------------------- coefficients
-__global__ void k_coefficients(int64_t nc, int Q, GeoLayout geo, int64_t plane, const int* __restrict__ lex2col,
-                               const double* __restrict__ cm, const double* __restrict__ eta,
-                               const double* __restrict__ cw, double* __restrict__ cv64, float* __restrict__ cv32,
-                               float* __restrict__ cq32, int* flag) {
+__global__ void k_coefficients(int dim, int64_t nc, int Q, GeoLayout geo, int64_t plane,
+                               const int* __restrict__ lex2col, const double* __restrict__ cm,
+                               const double* __restrict__ eta, const double* __restrict__ cw,
+                               double* __restrict__ cv64, float* __restrict__ cv32, float* __restrict__ cq32,
+                               const double* __restrict__ K64, double* __restrict__ Ks64, float* __restrict__ Ks32,
+                               int* flag) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nc * Q) return;
     const int64_t cell = id / Q;
@@ -211,12 +213,19 @@ __global__ void k_coefficients(int64_t nc, int Q, GeoLayout geo, int64_t plane, 
         cq32[off] = (float)(2.0 * e);
         cq32[plane + off] = (float)m;
     }
+    const double sv = sqrt(cvisc);
+    for (int pl = 0; pl < dim * dim; ++pl) {
+        const double k = sv * K64[pl * plane + off];
+        Ks64[pl * plane + off] = k;
+        Ks32[pl * plane + off] = (float)k;
+    }
 }
 
 void launch_coefficients(const Level& L, const double* cm, const double* eta, const double* cw, double* cv64,
-                         float* cv32, float* cq32, int* flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_coefficients, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, L.nc, L.Q, L.geo, L.plane(),
-                       L.d_lex2col, cm, eta, cw, cv64, cv32, cq32, flag);
+                         float* cv32, float* cq32, const double* K64, double* Ks64, float* Ks32, int* flag,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_coefficients, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, L.dim, L.nc, L.Q, L.geo,
+                       L.plane(), L.d_lex2col, cm, eta, cw, cv64, cv32, cq32, K64, Ks64, Ks32, flag);
 }
 
 // level vertex v (lexicographic) takes the fine displacement at fine vertex stride * v

@@ -102,6 +102,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     static_assert(!CHEB || MODE == (OP_A | OP_CHEB), "the Chebyshev epilogue goes with A alone");
     static_assert(!RES || MODE == (OP_A | OP_BT | OP_B | OP_RES), "the residual epilogue goes with the Stokes apply");
     static_assert(!VG || sizeof(T) == 4, "geometry from vertices is the FP32 path");
+    // A alone reads K' = sqrt(cvisc) K (no cvisc plane): sym(grad-hat u K') K'^T = cvisc sym(H) K^T
+    constexpr bool SCALED = !VG && (MODE == OP_A || MODE == (OP_A | OP_CHEB));
     __shared__ T sbuf[WPB][CPW][BUF];
     __shared__ double pbuf[HAS_B ? WPB : 1][CPW][NT][8];
     // x-face hand-over between neighbouring cells of the row: [slot][j][comp][k],
@@ -283,7 +285,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             const int64_t off = ((int64_t)qx * a.nchk + chunk) * kGeoSlots + (slot * NT + t);
 #pragma unroll
             for (int e = 0; e < 9; ++e) Kq[e] = act ? gload<NTL>(a.K + e * P + off) : T(0);
-            const T cvq = (HAS_A && act) ? gload<NTL>(a.cv + off) : T(0);
+            const T cvq = SCALED ? T(1) : ((HAS_A && act) ? gload<NTL>(a.cv + off) : T(0));
             const T cmq = (HAS_A && act) ? gload<NTL>(a.cv + P + off) : T(0);
             T Tm[3][3];
 #pragma unroll
@@ -391,7 +393,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             } else {
 #pragma unroll
                 for (int e = 0; e < 9; ++e) Kq[e] = act ? gload<NTL>(a.K + e * P + off) : T(0);
-                cvq = (HAS_A && act) ? gload<NTL>(a.cv + off) : T(0);
+                cvq = SCALED ? T(1) : ((HAS_A && act) ? gload<NTL>(a.cv + off) : T(0));
                 cmq = (HAS_A && act) ? gload<NTL>(a.cv + P + off) : T(0);
             }
             T Tm[3][3];
@@ -661,6 +663,7 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
     constexpr bool RES = (MODE & OP_RES) != 0;
     static_assert(!CHEB || MODE == (OP_A | OP_CHEB), "the Chebyshev epilogue goes with A alone");
     static_assert(!RES || MODE == (OP_A | OP_BT | OP_B | OP_RES), "the residual epilogue goes with the Stokes apply");
+    constexpr bool SCALED = MODE == OP_A || MODE == (OP_A | OP_CHEB);   // K' = sqrt(cvisc) K, no cvisc plane
     __shared__ T sbuf[WPB][CPW][BUF];
     __shared__ double pbuf[(MODE & OP_B) ? WPB : 1][CPW][NT][4];
 
@@ -778,7 +781,7 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
                 for (int aa = 0; aa < 2; ++aa) H[c][aa] = g0[c][qx] * Km[0][aa] + g1[c][qx] * Km[1][aa];
             if constexpr ((MODE & OP_B) != 0) divq[qx] = H[0][0] + H[1][1];
             if constexpr ((MODE & OP_A) != 0) {
-                const T cvisc = act ? gload<NTL>(a.cv + off) : T(0);
+                const T cvisc = SCALED ? T(1) : (act ? gload<NTL>(a.cv + off) : T(0));
                 const T cmass = act ? gload<NTL>(a.cv + P + off) : T(0);
                 Tm[0][0] = cvisc * H[0][0];
                 Tm[1][1] = cvisc * H[1][1];
