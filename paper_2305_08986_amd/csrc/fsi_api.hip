@@ -1311,6 +1311,17 @@ fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int
     return FSI_OK;
 }
 
+fsi_status fsi_set_tuning(fsi_ctx* h, int level, int precision, int variant) {
+    if (!h) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    if (level < 0 || level >= ctx->nlev || (precision != 0 && precision != 1) || variant < 0 ||
+        variant >= kNumVariants)
+        return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: level, precision or variant out of range");
+    for (int c = 0; c < kTuneClasses; ++c) ctx->tune_variant[precision][(size_t)level * kTuneClasses + c] = variant;
+    if (ctx->setup_done) TRY(capture_graphs(ctx));   // captured graphs hold the old launch shapes
+    return FSI_OK;
+}
+
 fsi_status fsi_get_tuning(const fsi_ctx* h, int level, int precision, int* variant, double* best_us) {
     if (!h || !variant || !best_us) return FSI_ERR_ARG;
     const Context* ctx = &h->c;

@@ -87,9 +87,13 @@ struct CellArgs {
 };
 
 // ============================================================== 3D
-// One wavefront owns a row of cells along x and walks it in chunks of CPW = 7
-// cells (9 threads per cell: one per line of 3 points).
-template <typename T, int MODE, int WPB, bool REMAP, bool NTL, int WPE, bool VG>
+// A row of cells along x is walked in chunks of CPW = 7 cells (9 threads per cell:
+// one per line of 3 points), one chunk per wavefront.  RS = false: each wavefront
+// of the workgroup owns its own row.  RS = true: the WPB wavefronts share one row
+// and take WPB consecutive chunks per step, so a step covers 14 WPB nodes of every
+// node line (fewer cache lines shared with the next step) and the row has WPB
+// times more wavefronts in flight; the x-face hand-over then crosses wavefronts.
+template <typename T, int MODE, int WPB, bool RS, bool NTL, int WPE, bool VG>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE))) void cell3d(CellArgs<T> a) {
     constexpr int NT = 9, CPW = 7, NLOC = 27, BUF = 243;
     constexpr bool FWD = (MODE & (OP_A | OP_B)) != 0;
@@ -116,9 +120,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane / NT, t = lane - slot * NT;
     const bool inwave = slot < CPW;
-    const int64_t lb = REMAP ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    const int64_t row = lb * WPB + wave;
+    const int64_t row = RS ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * WPB + wave;
     const bool rowact = row < a.nrows;
+    const int nsteps = RS ? (a.nchunks + WPB - 1) / WPB : a.nchunks;
+    const int cw = RS ? 0 : wave;                  // owner of the chunk-to-chunk carry
+    const bool carry_out = !RS || wave == WPB - 1; // this wavefront's last cell feeds the next step
     T* B = sbuf[wave][inwave ? slot : 0];
     const int64_t P = a.plane;
     // thread roles: stage A / scatter column (ic, jc) = (t % 3, t / 3); stage B line (ib, qzb)
@@ -127,7 +133,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     const int qy = t % 3, qz = t / 3;
     const int pax = t & 1, pyz = t >> 1;
 
-    for (int ch = 0; ch < a.nchunks; ++ch) {
+    for (int st = 0; st < nsteps; ++st) {
+        const int ch = RS ? st * WPB + wave : st;
         const int ix = ch * CPW + slot;
         const bool act = rowact && inwave && ix < a.nx;
         const int64_t cell = a.cbeg + row * a.nx + ix;   // phase cells are stored row by row
@@ -498,11 +505,13 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             }
             __syncthreads();
             if (act && t < 8) {
-                if (pax == 0 && ix > 0) sq += slot > 0 ? pxb[wave][slot - 1][pyz] : pcarry[wave][(ch + 1) & 1][pyz];
+                if (pax == 0 && ix > 0)
+                    sq += slot > 0 ? pxb[wave][slot - 1][pyz]
+                                   : ((RS && wave > 0) ? pxb[wave - 1][CPW - 1][pyz] : pcarry[cw][(st + 1) & 1][pyz]);
                 if (pwriter) {
                     a.q[pnode] = plast ? qold - sq : qold + sq;
-                } else if (slot == CPW - 1) {
-                    pcarry[wave][ch & 1][pyz] = sq;
+                } else if (slot == CPW - 1 && carry_out) {
+                    pcarry[cw][st & 1][pyz] = sq;
                 }
             }
         }
@@ -611,7 +620,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
 #pragma unroll
                         for (int k = 0; k < 3; ++k)
                             out[c][k] += slot > 0 ? xb[wave][slot - 1][jc * 9 + c * 3 + k]
-                                                  : xcarry[wave][(ch + 1) & 1][jc * 9 + c * 3 + k];
+                                                  : ((RS && wave > 0) ? xb[wave - 1][CPW - 1][jc * 9 + c * 3 + k]
+                                                                      : xcarry[cw][(st + 1) & 1][jc * 9 + c * 3 + k]);
                 }
                 if (vwriter) {
 #pragma unroll
@@ -641,11 +651,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                             for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node[k]] += out[c][k];
                         }
                     }
-                } else if (slot == CPW - 1) {
+                } else if (slot == CPW - 1 && carry_out) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) xcarry[wave][ch & 1][jc * 9 + c * 3 + k] = out[c][k];
+                        for (int k = 0; k < 3; ++k) xcarry[cw][st & 1][jc * 9 + c * 3 + k] = out[c][k];
                 }
             }
         }
@@ -949,26 +959,32 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
 
 // ============================================================== launchers
 // Phase p holds whole rows of cells (cells[0] each); one wavefront walks a row.
+// WPB > 1: in 3D the wavefronts of a workgroup share a row (one row per workgroup);
+// in 2D each wavefront keeps its own row (two per workgroup)
 template <typename T, int MODE, int WPB, bool NTL, int WPE>
 static void launch_one(const Level& L, const CellArgs<T>& args, hipStream_t s) {
-    const int64_t grid = (args.nrows + WPB - 1) / WPB;   // one wavefront per row of cells
-    if (grid <= 0) return;
+    if (args.nrows <= 0) return;
     if (L.dim == 3) {
+        constexpr bool RS = WPB > 1;
+        const int64_t grid = args.nrows;   // one workgroup per row
         if constexpr (sizeof(T) == 4) {
             if (args.vd) {
-                hipLaunchKernelGGL((cell3d<T, MODE, WPB, false, NTL, WPE, true>), dim3((unsigned)grid),
-                                   dim3(64 * WPB), 0, s, args);
+                hipLaunchKernelGGL((cell3d<T, MODE, WPB, RS, NTL, WPE, true>), dim3((unsigned)grid), dim3(64 * WPB), 0,
+                                   s, args);
                 return;
             }
         }
-        hipLaunchKernelGGL((cell3d<T, MODE, WPB, false, NTL, WPE, false>), dim3((unsigned)grid), dim3(64 * WPB), 0,
-                           s, args);
+        hipLaunchKernelGGL((cell3d<T, MODE, WPB, RS, NTL, WPE, false>), dim3((unsigned)grid), dim3(64 * WPB), 0, s,
+                           args);
     } else {
-        hipLaunchKernelGGL((cell2d<T, MODE, WPB, false, NTL>), dim3((unsigned)grid), dim3(64 * WPB), 0, s, args);
+        constexpr int W2 = WPB > 1 ? 2 : 1;
+        const int64_t grid = (args.nrows + W2 - 1) / W2;   // one wavefront per row of cells
+        hipLaunchKernelGGL((cell2d<T, MODE, W2, false, NTL>), dim3((unsigned)grid), dim3(64 * W2), 0, s, args);
     }
 }
 
-// launch variant v: v & 1 two wavefronts per workgroup (else one); v & 2 plain
+// launch variant v: v & 1 four wavefronts per workgroup sharing a row (3D; two
+// rows per workgroup in 2D), else one wavefront per row; v & 2 plain
 // (cached) geometry loads instead of non-temporal ones; v / 4 register cap: none,
 // or one or two wavefronts per SIMD more than the class reaches unconstrained
 // (spills allowed).  Unconstrained occupancy (3D): FP64 2 (A, B classes) or 1
@@ -990,9 +1006,9 @@ static void launch_mode(const Level& L, int variant, const CellArgs<T>& args, hi
     const int cap = (variant >> 2) % 3;
     switch (variant & 3) {
         case 0: launch_capped<T, MODE, 1, true>(L, cap, args, s); break;
-        case 1: launch_capped<T, MODE, 2, true>(L, cap, args, s); break;
+        case 1: launch_capped<T, MODE, 4, true>(L, cap, args, s); break;
         case 2: launch_capped<T, MODE, 1, false>(L, cap, args, s); break;
-        default: launch_capped<T, MODE, 2, false>(L, cap, args, s); break;
+        default: launch_capped<T, MODE, 4, false>(L, cap, args, s); break;
     }
 }
 

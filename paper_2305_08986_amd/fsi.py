@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fsi_solve": (i, [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
         "fsi_autotune": (i, [vp]),
         "fsi_get_tuning": (i, [vp, i, i, C.POINTER(i), C.POINTER(d)]),
+        "fsi_set_tuning": (i, [vp, i, i, i]),
         "fsi_time_operator": (i, [vp, i, i, i, i, C.POINTER(d), C.POINTER(d), C.POINTER(i)]),
     }
     for name, (res, args) in sig.items():
@@ -223,6 +224,10 @@ class Context:
         self._check(self.lib.fsi_get_tuning(self.h, level, precision, C.byref(v), C.byref(us)))
         return v.value, us.value
 
+
+    def set_tuning(self, level: int, precision: int, variant: int):
+        """Pin the launch variant of every operator class on a level (overrides autotune)."""
+        self._check(self.lib.fsi_set_tuning(self.h, level, precision, variant))
     def time_operator(self, level: int, precision: int = 0, mode: int = 1, reps: int = 10):
         """(cell-kernel us per application, operator us per application, launches per application)."""
         k = C.c_double()
