@@ -214,10 +214,10 @@ fsi_status fsi_solve(fsi_ctx* ctx, const double* g_u, const double* g_p, double*
 fsi_status fsi_autotune(fsi_ctx* ctx);
 fsi_status fsi_get_tuning(const fsi_ctx* ctx, int level, int precision, int* variant, double* best_us);
 /* Pin the launch variant (0 .. 11) of every operator class on one level and
- * precision, overriding the autotuner (used with tuned = 1).  Variant v: v & 1 four
- * wavefronts per workgroup sharing a row of cells (3D); v & 2 cached instead of
- * streaming geometry loads; v / 4 register cap (none, +1, +2 wavefronts per SIMD).
- * Errors: FSI_ERR_ARG. */
+ * precision, overriding the autotuner (used with tuned = 1).  Variant v: v % 3
+ * selects 1, 2 or 4 wavefronts per workgroup sharing a row of cells (3D; 2D: one row
+ * per wavefront, at most two); (v / 3) % 2 cached instead of streaming geometry
+ * loads; v / 6 a register cap of one more wavefront per SIMD.  Errors: FSI_ERR_ARG. */
 fsi_status fsi_set_tuning(fsi_ctx* ctx, int level, int precision, int variant);
 
 /* Measurement support: runs `reps` applications of the level operator

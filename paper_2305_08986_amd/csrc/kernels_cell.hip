@@ -977,38 +977,34 @@ static void launch_one(const Level& L, const CellArgs<T>& args, hipStream_t s) {
         hipLaunchKernelGGL((cell3d<T, MODE, WPB, RS, NTL, WPE, false>), dim3((unsigned)grid), dim3(64 * WPB), 0, s,
                            args);
     } else {
-        constexpr int W2 = WPB > 1 ? 2 : 1;
+        constexpr int W2 = WPB > 1 ? 2 : 1;   // 2D: one row per wavefront, at most two
         const int64_t grid = (args.nrows + W2 - 1) / W2;   // one wavefront per row of cells
         hipLaunchKernelGGL((cell2d<T, MODE, W2, false, NTL>), dim3((unsigned)grid), dim3(64 * W2), 0, s, args);
     }
 }
 
-// launch variant v: v & 1 four wavefronts per workgroup sharing a row (3D; two
-// rows per workgroup in 2D), else one wavefront per row; v & 2 plain
-// (cached) geometry loads instead of non-temporal ones; v / 4 register cap: none,
-// or one or two wavefronts per SIMD more than the class reaches unconstrained
-// (spills allowed).  Unconstrained occupancy (3D): FP64 2 (A, B classes) or 1
-// (Stokes classes); FP32 3-4 (A, B classes) or 2 (Stokes classes).
+// launch variant v (0 .. 11): v % 3 selects 1, 2 or 4 wavefronts per workgroup (in 3D
+// the wavefronts share one row; in 2D they own a row each, at most two); (v / 3) % 2
+// selects cached instead of streaming geometry loads; v / 6 caps the registers for
+// one wavefront per SIMD more than the class reaches unconstrained (spills allowed).
+// Unconstrained occupancy (3D): FP64 2 (A, B classes) or 1 (Stokes classes); FP32
+// 3-4 (A, B classes) or 2 (Stokes classes).
 template <typename T, int MODE, int WPB, bool NTL>
 static void launch_capped(const Level& L, int cap, const CellArgs<T>& args, hipStream_t s) {
     constexpr bool STOKES = (MODE & OP_A) && (MODE & OP_BT);
     constexpr int W1 = sizeof(T) == 8 ? (STOKES ? 2 : 3) : (STOKES ? 3 : 4);
-    constexpr int W2 = sizeof(T) == 8 ? W1 : W1 + 1;   // FP64: a second step only spills more
-    switch (cap) {
-        case 0: launch_one<T, MODE, WPB, NTL, 1>(L, args, s); break;
-        case 1: launch_one<T, MODE, WPB, NTL, W1>(L, args, s); break;
-        default: launch_one<T, MODE, WPB, NTL, W2>(L, args, s); break;
-    }
+    if (cap == 0) launch_one<T, MODE, WPB, NTL, 1>(L, args, s);
+    else launch_one<T, MODE, WPB, NTL, W1>(L, args, s);
 }
 
 template <typename T, int MODE>
 static void launch_mode(const Level& L, int variant, const CellArgs<T>& args, hipStream_t s) {
-    const int cap = (variant >> 2) % 3;
-    switch (variant & 3) {
-        case 0: launch_capped<T, MODE, 1, true>(L, cap, args, s); break;
-        case 1: launch_capped<T, MODE, 4, true>(L, cap, args, s); break;
-        case 2: launch_capped<T, MODE, 1, false>(L, cap, args, s); break;
-        default: launch_capped<T, MODE, 4, false>(L, cap, args, s); break;
+    const int cap = (variant / 6) & 1;
+    const bool plain = ((variant / 3) & 1) != 0;
+    switch (variant % 3) {
+        case 0: plain ? launch_capped<T, MODE, 1, false>(L, cap, args, s) : launch_capped<T, MODE, 1, true>(L, cap, args, s); break;
+        case 1: plain ? launch_capped<T, MODE, 2, false>(L, cap, args, s) : launch_capped<T, MODE, 2, true>(L, cap, args, s); break;
+        default: plain ? launch_capped<T, MODE, 4, false>(L, cap, args, s) : launch_capped<T, MODE, 4, true>(L, cap, args, s); break;
     }
 }
 
