@@ -59,6 +59,13 @@ def algorithmic_bytes_per_cell(dim: int, elem: int) -> int:
     return geo + vec + cmap
 
 
+def kernel_bytes_per_cell(dim: int, elem: int) -> int:
+    """Bytes the A-only kernel itself must move per cell: it reads K' = sqrt(cvisc) K
+    and cmass, (dim^2 + 1) values per point instead of (dim^2 + 2)."""
+    q = 3 ** dim
+    return (dim * dim + 1) * q * elem + 2 * (2 ** dim) * dim * elem + 4 * q
+
+
 def load_counter_profile(workload: str):
     """HBM traffic per colour launch from the committed rocprofv3 counter summary."""
     path = os.path.join(ROOT, "profiles", f"counters_cell3d_A_fp64_{workload}.json")
@@ -157,6 +164,10 @@ def main():
         k_us, op_us, nl = ctx.time_operator(J, precision=0, mode=1, reps=args.apply_reps)
         k32_us, op32_us, _ = ctx.time_operator(J, precision=1, mode=1, reps=max(4, args.apply_reps // 2))
         ks_us, ops_us, _ = ctx.time_operator(J, precision=0, mode=7, reps=max(4, args.apply_reps // 2))
+        # FP32 A with the geometry formed from the vertex displacements in the kernel
+        ctx.set_mg_params(vertex_geometry=1)
+        kv_us, opv_us, _ = ctx.time_operator(J, precision=1, mode=1, reps=max(4, args.apply_reps // 2))
+        ctx.set_mg_params(vertex_geometry=0)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         do_setup()
@@ -174,6 +185,7 @@ def main():
         t3 = time.perf_counter()
         du = float(torch.linalg.vector_norm(umx - u64) / torch.linalg.vector_norm(u64))
         rec = dict(k_us=k_us, op_us=op_us, n_launch=nl, k32_us=k32_us, op32_us=op32_us, ks_us=ks_us, ops_us=ops_us,
+                   opv_us=opv_us,
                    apply_s=t1 - t0, setup_s=t2 - t1, solve_s=t3 - t2, fp64=i64, fp64_opt=ift, mixed=imx, du=du,
                    step_s=t3 - t0)
         record.append(rec)
@@ -205,10 +217,16 @@ def main():
     bpc = algorithmic_bytes_per_cell(mesh.dim, 8)
     # algorithmic bytes per launch / mean launch duration (k_us = all launches of one apply)
     achieved = bpc * nc / (k_us * 1e-6) / 1e9
+    kbpc = kernel_bytes_per_cell(mesh.dim, 8)
     prof = load_counter_profile(name)
     traffic = None
+    flops = None
     if prof is not None:
         traffic = prof["hbm_bytes_per_launch"]
+        if prof.get("fp64_flops_per_launch"):
+            tf = prof["fp64_flops_per_launch"] / (k_us / n_launch * 1e-6) / 1e12
+            flops = {"fp64_tflops": round(tf, 2), "peak": FP64_PEAK_TFLOPS, "frac": round(tf / FP64_PEAK_TFLOPS, 4),
+                     "source": "rocprofv3 SQ_INSTS_VALU_FMA/ADD/MUL_F64 per launch (profiles/)"}
     fp64_ms = mean("fp64", "time_ms")
     ft_ms = mean("fp64_opt", "time_ms")
     mx_ms = mean("mixed", "time_ms")
@@ -238,7 +256,9 @@ def main():
             "fp64_A_mean_launch_us": round(k_us / n_launch, 2),
             "fp32_A_gdofs": round(nv / (mean("op32_us") * 1e-6) / 1e9, 4),
             "fp64_stokes_gdofs": round((nv + npr) / (mean("ops_us") * 1e-6) / 1e9, 4),
+            "fp32_A_vertex_geometry_gdofs": round(nv / (mean("opv_us") * 1e-6) / 1e9, 4),
             "algorithmic_bytes_per_cell": bpc,
+            "kernel_bytes_per_cell": kbpc,
         },
         "solve": {
             "fp64_plain_ms": round(fp64_ms, 1), "fp64_plain_iters": recs[-1]["fp64"]["iters"],
@@ -255,9 +275,11 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "achieved_kernel_bytes": round(kbpc * nc / (k_us * 1e-6) / 1e9, 1),
             "kernel": ("cell3d<double, A>" if mesh.dim == 3 else "cell2d<double, A>")
-                      + f", {n_launch} launches (slab x colour) per apply, mean {k_us / n_launch:.1f} us",
+                      + f", {n_launch} launches (processing phases) per apply, mean {k_us / n_launch:.1f} us",
         },
+        "flops": flops,
     }
     if not args.no_cpu_baseline:
         _log("[bench] CPU oracle baseline")

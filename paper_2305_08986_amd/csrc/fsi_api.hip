@@ -304,21 +304,20 @@ static void cheb(Context* ctx, int j, const T* r, T* x, hipStream_t s) {
     const double theta = 0.5 * (L.hi + L.lo), delta = 0.5 * (L.hi - L.lo);
     const double sigma = theta / delta;
     double rho = 1.0 / sigma;
-    launch_cheb_init<T>(DAp<T>(L), r, x, W.cd_u, 1.0 / theta, L.nv, s);
+    launch_cheb_init<T>(DAp<T>(L), r, x, 1.0 / theta, L.nv, s);
     for (int i = 1; i < ctx->prm.k_A; ++i) {
         const double rn = 1.0 / (2.0 * sigma - rho);
         const double c1 = rn * rho, c2 = 2.0 * rn / delta;
+        // the first direction is the first iterate; the last step needs no direction
+        const bool first = i == 1, store_d = i + 1 < ctx->prm.k_A;
         if (ctx->prm.fused && (!ctx->prm.tuned || ctx->fuse_cheb[prec_index<T>()][j])) {
-            // the update happens at each node's last touch; the last step needs no direction
-            const bool store_d = i + 1 < ctx->prm.k_A;
+            // the update happens at each node's last touch
             launch_cell_cheb_all<T>(L, variant_of(ctx, prec_index<T>(), j, OP_A | OP_CHEB), Kmode<T>(L, OP_A | OP_CHEB),
-                                    CVp<T>(L), x,
-                                    W.cd_u, r,
-                                    DAp<T>(L), W.cax_u, c1, c2, store_d, s);
-            launch_dirichlet_cheb<T>(L, x, W.cd_u, r, DAp<T>(L), c1, c2, store_d, s);
+                                    CVp<T>(L), x, W.cd_u, r, DAp<T>(L), W.cax_u, c1, c2, first, store_d, s);
+            launch_dirichlet_cheb<T>(L, x, W.cd_u, r, DAp<T>(L), c1, c2, first, store_d, s);
         } else {
             op_apply<T>(ctx, j, OP_A, x, nullptr, W.cax_u, nullptr, s);
-            launch_cheb_step<T>(DAp<T>(L), r, W.cax_u, x, W.cd_u, c1, c2, L.nv, s);
+            launch_cheb_step<T>(DAp<T>(L), r, W.cax_u, x, W.cd_u, c1, c2, first, store_d, L.nv, s);
         }
         rho = rn;
     }
@@ -1151,7 +1150,7 @@ static void launch_phase_on_work(Context* ctx, int prec, int j, int mode, int va
         LevelWork<double>& W = ctx->w64[j];
         if (mode == (OP_A | OP_CHEB))
             launch_cell_cheb<double>(L, var, ph, L.d_Ks64, L.d_cv64, W.w_u, W.cd_u, W.f_u, L.d_dAinv64, W.cax_u, 0.0,
-                                     0.0, true, s);
+                                     0.0, false, true, s);
         else if (mode == (OP_A | OP_BT | OP_B | OP_RES))
             launch_cell_res<double>(L, var, ph, L.d_K64, L.d_cv64, W.x_u, W.x_p, W.f_u, W.f_p, W.r_u, W.r_p, s);
         else
@@ -1160,7 +1159,7 @@ static void launch_phase_on_work(Context* ctx, int prec, int j, int mode, int va
         LevelWork<float>& W = ctx->w32[j];
         if (mode == (OP_A | OP_CHEB))
             launch_cell_cheb<float>(L, var, ph, L.d_Ks32, L.d_cv32, W.w_u, W.cd_u, W.f_u, L.d_dAinv32, W.cax_u, 0.0,
-                                    0.0, true, s);
+                                    0.0, false, true, s);
         else if (mode == (OP_A | OP_BT | OP_B | OP_RES))
             launch_cell_res<float>(L, var, ph, L.d_K32, L.d_cv32, W.x_u, W.x_p, W.f_u, W.f_p, W.r_u, W.r_p, s);
         else
@@ -1231,15 +1230,15 @@ fsi_status fsi_autotune(fsi_ctx* h) {
             double sep_c = 0, fus_c = 0, sep_r = 0, fus_r = 0;
             if (pi == 0) {
                 LevelWork<double>& W = ctx->w64[j];
-                TRY(timed([&] { all(OP_A); launch_cheb_step<double>(L.d_dAinv64, W.f_u, W.cax_u, W.w_u, W.cd_u, 0.0, 0.0, L.nv, s); }, &sep_c));
-                TRY(timed([&] { all(OP_A | OP_CHEB); launch_dirichlet_cheb<double>(L, W.w_u, W.cd_u, W.f_u, L.d_dAinv64, 0.0, 0.0, true, s); }, &fus_c));
+                TRY(timed([&] { all(OP_A); launch_cheb_step<double>(L.d_dAinv64, W.f_u, W.cax_u, W.w_u, W.cd_u, 0.0, 0.0, false, true, L.nv, s); }, &sep_c));
+                TRY(timed([&] { all(OP_A | OP_CHEB); launch_dirichlet_cheb<double>(L, W.w_u, W.cd_u, W.f_u, L.d_dAinv64, 0.0, 0.0, false, true, s); }, &fus_c));
                 TRY(timed([&] { all(OP_A | OP_BT | OP_B); launch_dirichlet_copy<double>(L, W.x_u, W.r_u, s);
                                 launch_sub<double>(W.f_u, W.r_u, W.r_u, L.nv, s); launch_sub<double>(W.f_p, W.r_p, W.r_p, L.np, s); }, &sep_r));
                 TRY(timed([&] { all(OP_A | OP_BT | OP_B | OP_RES); launch_dirichlet_res<double>(L, W.f_u, W.x_u, W.r_u, s); }, &fus_r));
             } else {
                 LevelWork<float>& W = ctx->w32[j];
-                TRY(timed([&] { all(OP_A); launch_cheb_step<float>(L.d_dAinv32, W.f_u, W.cax_u, W.w_u, W.cd_u, 0.0, 0.0, L.nv, s); }, &sep_c));
-                TRY(timed([&] { all(OP_A | OP_CHEB); launch_dirichlet_cheb<float>(L, W.w_u, W.cd_u, W.f_u, L.d_dAinv32, 0.0, 0.0, true, s); }, &fus_c));
+                TRY(timed([&] { all(OP_A); launch_cheb_step<float>(L.d_dAinv32, W.f_u, W.cax_u, W.w_u, W.cd_u, 0.0, 0.0, false, true, L.nv, s); }, &sep_c));
+                TRY(timed([&] { all(OP_A | OP_CHEB); launch_dirichlet_cheb<float>(L, W.w_u, W.cd_u, W.f_u, L.d_dAinv32, 0.0, 0.0, false, true, s); }, &fus_c));
                 TRY(timed([&] { all(OP_A | OP_BT | OP_B); launch_dirichlet_copy<float>(L, W.x_u, W.r_u, s);
                                 launch_sub<float>(W.f_u, W.r_u, W.r_u, L.nv, s); launch_sub<double>(W.f_p, W.r_p, W.r_p, L.np, s); }, &sep_r));
                 TRY(timed([&] { all(OP_A | OP_BT | OP_B | OP_RES); launch_dirichlet_res<float>(L, W.f_u, W.x_u, W.r_u, s); }, &fus_r));

@@ -230,16 +230,17 @@ void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T*
                      const T* u, const double* p, T* v, double* q, hipStream_t s);
 template <typename T>
 void launch_cell_cheb(const Level& L, int variant, int phase, const T* K, const T* cv, T* x, T* d, const T* r,
-                      const T* dinv, T* v, double c1, double c2, bool store_d, hipStream_t s);
+                      const T* dinv, T* v, double c1, double c2, bool first, bool store_d, hipStream_t s);
 template <typename T>
 void launch_cell_res(const Level& L, int variant, int phase, const T* K, const T* cv, const T* u, const double* p,
                      const T* f_u, const double* f_p, T* r_u, double* r_p, hipStream_t s);
 // one Chebyshev step fused into A x: at each node's last touch
-// d = c1 d + c2 dinv (r - A x), x += d (d is stored only if store_d); v holds the
+// d = c1 d + c2 dinv (r - A x), x += d (first: d taken as x; d is stored only if
+// store_d); v holds the
 // partial sums of nodes touched by several phases.  Wall nodes are left alone.
 template <typename T>
 void launch_cell_cheb_all(const Level& L, int variant, const T* K, const T* cv, T* x, T* d, const T* r,
-                          const T* dinv, T* v, double c1, double c2, bool store_d, hipStream_t s);
+                          const T* dinv, T* v, double c1, double c2, bool first, bool store_d, hipStream_t s);
 // residual fused into the Stokes apply: r_u = f_u - (A u + B^T p), r_p = f_p - B u,
 // written at each node's last touch.  Wall nodes are left alone.
 template <typename T>
@@ -271,19 +272,20 @@ void launch_dirichlet_zero(const Level& L, T* v, hipStream_t s);
 // wall rows of the fused epilogues (identity rows of A): the Chebyshev step with
 // A x = x, and r = f - u
 template <typename T>
-void launch_dirichlet_cheb(const Level& L, T* x, T* d, const T* r, const T* dinv, double c1, double c2,
+void launch_dirichlet_cheb(const Level& L, T* x, T* d, const T* r, const T* dinv, double c1, double c2, bool first,
                            bool store_d, hipStream_t s);
 template <typename T>
 void launch_dirichlet_res(const Level& L, const T* f, const T* u, T* r, hipStream_t s);
 template <typename TD, typename TS>
 void launch_cast(TD* d, const TS* src, int64_t n, hipStream_t s);
 
-// Chebyshev pieces: x = dinv*r*c0, d = x ; d = c1 d + c2 dinv (r - ax), x += d
+// Chebyshev pieces: x = dinv*r*c0 (the first direction equals x and is not stored);
+// d' = c1 d + c2 dinv (r - ax), x += d' (first: d taken as x; store_d: keep d')
 template <typename T>
-void launch_cheb_init(const T* dinv, const T* r, T* x, T* d, double c0, int64_t n, hipStream_t s);
+void launch_cheb_init(const T* dinv, const T* r, T* x, double c0, int64_t n, hipStream_t s);
 template <typename T>
-void launch_cheb_step(const T* dinv, const T* r, const T* ax, T* x, T* d, double c1, double c2,
-                      int64_t n, hipStream_t s);
+void launch_cheb_step(const T* dinv, const T* r, const T* ax, T* x, T* d, double c1, double c2, bool first,
+                      bool store_d, int64_t n, hipStream_t s);
 // r = f - a (velocity, type T) ; and pressure (double)
 template <typename T>
 void launch_sub(const T* f, const T* a, T* r, int64_t n, hipStream_t s);

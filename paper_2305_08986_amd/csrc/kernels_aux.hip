@@ -527,28 +527,29 @@ template void launch_dirichlet_zero<float>(const Level&, float*, hipStream_t);
 template <typename T>
 __global__ void k_dir_cheb(const int* __restrict__ nodes, int64_t nd, int dim, int64_t nvn, T* __restrict__ x,
                            T* __restrict__ d, const T* __restrict__ r, const T* __restrict__ dinv, T c1, T c2,
-                           int store_d) {
+                           int first, int store_d) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nd) return;
     const int64_t n = nodes[i];
     for (int c = 0; c < dim; ++c) {
         const int64_t k = c * nvn + n;
-        const T dn = c1 * d[k] + c2 * dinv[k] * (r[k] - x[k]);   // wall row of A: identity
+        const T xk = x[k];
+        const T dn = c1 * (first ? xk : d[k]) + c2 * dinv[k] * (r[k] - xk);   // wall row of A: identity
         if (store_d) d[k] = dn;
-        x[k] += dn;
+        x[k] = xk + dn;
     }
 }
 template <typename T>
-void launch_dirichlet_cheb(const Level& L, T* x, T* d, const T* r, const T* dinv, double c1, double c2,
+void launch_dirichlet_cheb(const Level& L, T* x, T* d, const T* r, const T* dinv, double c1, double c2, bool first,
                            bool store_d, hipStream_t s) {
     if (L.n_dir > 0)
         hipLaunchKernelGGL(k_dir_cheb<T>, dim3(nblocks(L.n_dir)), dim3(TPB), 0, s, L.d_dir_nodes, L.n_dir, L.dim,
-                           L.nvn, x, d, r, dinv, (T)c1, (T)c2, store_d ? 1 : 0);
+                           L.nvn, x, d, r, dinv, (T)c1, (T)c2, first ? 1 : 0, store_d ? 1 : 0);
 }
 template void launch_dirichlet_cheb<double>(const Level&, double*, double*, const double*, const double*, double,
-                                            double, bool, hipStream_t);
+                                            double, bool, bool, hipStream_t);
 template void launch_dirichlet_cheb<float>(const Level&, float*, float*, const float*, const float*, double, double,
-                                           bool, hipStream_t);
+                                           bool, bool, hipStream_t);
 
 template <typename T>
 __global__ void k_dir_res(const int* __restrict__ nodes, int64_t nd, int dim, int64_t nvn, const T* __restrict__ f,
@@ -581,40 +582,43 @@ template void launch_cast<double, float>(double*, const float*, int64_t, hipStre
 template void launch_cast<double, double>(double*, const double*, int64_t, hipStream_t);
 template void launch_cast<float, float>(float*, const float*, int64_t, hipStream_t);
 
+// first Chebyshev iterate x = c0 D^{-1} r; the first direction equals it, so it is not stored
 template <typename T>
-__global__ void k_cheb_init(const T* __restrict__ dinv, const T* __restrict__ r, T* __restrict__ x,
-                            T* __restrict__ d, T c0, int64_t n) {
+__global__ void k_cheb_init(const T* __restrict__ dinv, const T* __restrict__ r, T* __restrict__ x, T c0,
+                            int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const T v = dinv[i] * r[i] * c0;
-    x[i] = v;
-    d[i] = v;
+    x[i] = dinv[i] * r[i] * c0;
 }
 template <typename T>
-void launch_cheb_init(const T* dinv, const T* r, T* x, T* d, double c0, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_cheb_init<T>, dim3(nblocks(n)), dim3(TPB), 0, s, dinv, r, x, d, (T)c0, n);
+void launch_cheb_init(const T* dinv, const T* r, T* x, double c0, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cheb_init<T>, dim3(nblocks(n)), dim3(TPB), 0, s, dinv, r, x, (T)c0, n);
 }
-template void launch_cheb_init<double>(const double*, const double*, double*, double*, double, int64_t, hipStream_t);
-template void launch_cheb_init<float>(const float*, const float*, float*, float*, double, int64_t, hipStream_t);
+template void launch_cheb_init<double>(const double*, const double*, double*, double, int64_t, hipStream_t);
+template void launch_cheb_init<float>(const float*, const float*, float*, double, int64_t, hipStream_t);
 
+// d' = c1 d + c2 D^{-1}(r - A x), x += d'; the first step takes d = x (nothing stored
+// yet), the last one does not store d'
 template <typename T>
 __global__ void k_cheb_step(const T* __restrict__ dinv, const T* __restrict__ r, const T* __restrict__ ax,
-                            T* __restrict__ x, T* __restrict__ d, T c1, T c2, int64_t n) {
+                            T* __restrict__ x, T* __restrict__ d, T c1, T c2, int first, int store_d, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const T dn = c1 * d[i] + c2 * dinv[i] * (r[i] - ax[i]);
-    d[i] = dn;
-    x[i] += dn;
+    const T xi = x[i];
+    const T dn = c1 * (first ? xi : d[i]) + c2 * dinv[i] * (r[i] - ax[i]);
+    if (store_d) d[i] = dn;
+    x[i] = xi + dn;
 }
 template <typename T>
-void launch_cheb_step(const T* dinv, const T* r, const T* ax, T* x, T* d, double c1, double c2, int64_t n,
-                      hipStream_t s) {
-    hipLaunchKernelGGL(k_cheb_step<T>, dim3(nblocks(n)), dim3(TPB), 0, s, dinv, r, ax, x, d, (T)c1, (T)c2, n);
+void launch_cheb_step(const T* dinv, const T* r, const T* ax, T* x, T* d, double c1, double c2, bool first,
+                      bool store_d, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cheb_step<T>, dim3(nblocks(n)), dim3(TPB), 0, s, dinv, r, ax, x, d, (T)c1, (T)c2,
+                       first ? 1 : 0, store_d ? 1 : 0, n);
 }
 template void launch_cheb_step<double>(const double*, const double*, const double*, double*, double*, double, double,
-                                       int64_t, hipStream_t);
-template void launch_cheb_step<float>(const float*, const float*, const float*, float*, float*, double, double,
-                                      int64_t, hipStream_t);
+                                       bool, bool, int64_t, hipStream_t);
+template void launch_cheb_step<float>(const float*, const float*, const float*, float*, float*, double, double, bool,
+                                      bool, int64_t, hipStream_t);
 
 template <typename T>
 __global__ void k_sub(const T* __restrict__ f, const T* __restrict__ a, T* __restrict__ r, int64_t n) {

@@ -77,6 +77,7 @@ struct CellArgs {
     const T* __restrict__ dinv;
     const double* __restrict__ fp;
     T c1, c2;
+    int first;          // OP_CHEB: first step, the direction is the iterate itself
     int store_d;
     // geometry from vertices (FP32, 3D): per-vertex displacement of the level's
     // multilinear ALE map, reference cell sizes, and per point (2 eta, c_m) in the
@@ -549,7 +550,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                         er[c][k] = last ? a.r[i] : T(0);
                         if constexpr (CHEB) {
                             ex[c][k] = last ? a.x[i] : T(0);
-                            ed[c][k] = last ? a.d[i] : T(0);
+                            ed[c][k] = (last && !a.first) ? a.d[i] : T(0);
                             eg[c][k] = last ? a.dinv[i] : T(0);
                         }
                     }
@@ -636,7 +637,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                                 const int64_t i = c * a.nvn + node[k];
                                 const T tot = ep[c][k] + out[c][k];
                                 if constexpr (CHEB) {
-                                    const T dn = a.c1 * ed[c][k] + a.c2 * eg[c][k] * (er[c][k] - tot);
+                                    const T dprev = a.first ? ex[c][k] : ed[c][k];
+                                    const T dn = a.c1 * dprev + a.c2 * eg[c][k] * (er[c][k] - tot);
                                     if (a.store_d) a.d[i] = dn;
                                     a.x[i] = ex[c][k] + dn;
                                 } else {
@@ -930,9 +932,10 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
                             const int64_t i = c * a.nvn + node;
                             const T tot = first ? out[c][j] : a.v[i] + out[c][j];
                             if constexpr (CHEB) {
-                                const T dn = a.c1 * a.d[i] + a.c2 * a.dinv[i] * (a.r[i] - tot);
+                                const T xi = a.x[i];
+                                const T dn = a.c1 * (a.first ? xi : a.d[i]) + a.c2 * a.dinv[i] * (a.r[i] - tot);
                                 if (a.store_d) a.d[i] = dn;
-                                a.x[i] += dn;
+                                a.x[i] = xi + dn;
                             } else {
                                 a.v[i] = a.r[i] - tot;
                             }
@@ -1065,7 +1068,7 @@ void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T*
 
 template <typename T>
 void launch_cell_cheb(const Level& L, int variant, int phase, const T* K, const T* cv, T* x, T* d, const T* r,
-                      const T* dinv, T* v, double c1, double c2, bool store_d, hipStream_t s) {
+                      const T* dinv, T* v, double c1, double c2, bool first, bool store_d, hipStream_t s) {
     CellArgs<T> args = phase_args<T>(L, phase, K, cv);
     args.v = v;
     args.x = x;
@@ -1074,15 +1077,16 @@ void launch_cell_cheb(const Level& L, int variant, int phase, const T* K, const 
     args.dinv = dinv;
     args.c1 = (T)c1;
     args.c2 = (T)c2;
+    args.first = first ? 1 : 0;
     args.store_d = store_d ? 1 : 0;
     launch_mode<T, OP_A | OP_CHEB>(L, variant, args, s);
 }
 
 template <typename T>
 void launch_cell_cheb_all(const Level& L, int variant, const T* K, const T* cv, T* x, T* d, const T* r,
-                          const T* dinv, T* v, double c1, double c2, bool store_d, hipStream_t s) {
+                          const T* dinv, T* v, double c1, double c2, bool first, bool store_d, hipStream_t s) {
     for (int ph = 0; ph < L.nphases(); ++ph)
-        launch_cell_cheb<T>(L, variant, ph, K, cv, x, d, r, dinv, v, c1, c2, store_d, s);
+        launch_cell_cheb<T>(L, variant, ph, K, cv, x, d, r, dinv, v, c1, c2, first, store_d, s);
 }
 
 template <typename T>
@@ -1113,13 +1117,14 @@ template void launch_cell_all<double>(const Level&, int, int, const double*, con
 template void launch_cell_all<float>(const Level&, int, int, const float*, const float*, const float*,
                                      const double*, float*, double*, hipStream_t);
 template void launch_cell_cheb_all<double>(const Level&, int, const double*, const double*, double*, double*,
-                                           const double*, const double*, double*, double, double, bool, hipStream_t);
+                                           const double*, const double*, double*, double, double, bool, bool,
+                                           hipStream_t);
 template void launch_cell_cheb_all<float>(const Level&, int, const float*, const float*, float*, float*,
-                                          const float*, const float*, float*, double, double, bool, hipStream_t);
+                                          const float*, const float*, float*, double, double, bool, bool, hipStream_t);
 template void launch_cell_cheb<double>(const Level&, int, int, const double*, const double*, double*, double*,
-                                       const double*, const double*, double*, double, double, bool, hipStream_t);
+                                       const double*, const double*, double*, double, double, bool, bool, hipStream_t);
 template void launch_cell_cheb<float>(const Level&, int, int, const float*, const float*, float*, float*,
-                                      const float*, const float*, float*, double, double, bool, hipStream_t);
+                                      const float*, const float*, float*, double, double, bool, bool, hipStream_t);
 template void launch_cell_res<double>(const Level&, int, int, const double*, const double*, const double*,
                                       const double*, const double*, const double*, double*, double*, hipStream_t);
 template void launch_cell_res<float>(const Level&, int, int, const float*, const float*, const float*,
