@@ -141,3 +141,35 @@ def test_every_launch_variant_gives_the_same_operator(name):
             base = (got, got32)
         for g, b in zip(got + got32, base[0] + base[1]):
             assert np.array_equal(g, b), (name, var)
+
+
+def test_jacobian_input_path_matches_oracle_and_keeps_stored_fp32_geometry():
+    """Per-point Jacobians through fsi_set_jacobians (the general ALE input) give the
+    oracle's operator in FP64; FP32 applies use the stored geometry even when the
+    vertex-geometry path is requested, since arbitrary Jacobians carry no vertex data."""
+    from paper_2305_08986_amd import fsi
+    wl = W.make_workload("T3_R")
+    ctx = fsi.Context.from_mesh(wl.mesh)
+    ops = solvers.build_levels(wl.mesh, wl.disp, wl.c_mass, wl.eta)
+    ref = fem.Reference(3)
+    for j in range(ctx.n_levels):
+        box = fem.level_box(wl.mesh, j)
+        Jq = fem.jacobians_q1(box, W.inject_displacement(wl.mesh, wl.disp, j), ref)
+        ctx.set_jacobians(j, np.ascontiguousarray(Jq))
+        ctx.set_coefficients(j, wl.c_mass[j], wl.eta[j])
+    ctx.set_mg_params(vertex_geometry=1)
+    j = ctx.n_levels - 1
+    op = ops[j]
+    rng = np.random.default_rng(23)
+    u = rng.uniform(-1, 1, op.box.n_vel)
+    p = rng.uniform(-1, 1, op.box.n_p)
+    rv, rq = op.apply_stokes(u, p)
+    v, q = ctx.apply_stokes(j, torch.from_numpy(u).cuda(), torch.from_numpy(p).cuda())
+    _cmp(v, rv, 1e-12, "jacobian path stokes-v")
+    _cmp(q, rq, 1e-12, "jacobian path stokes-q")
+    ut = torch.from_numpy(u).float().cuda()
+    pt = torch.from_numpy(p).float().cuda()
+    v32, q32 = ctx.apply_stokes(j, ut, pt)
+    rv32, rq32 = op.apply_stokes(ut.double().cpu().numpy(), pt.double().cpu().numpy())
+    _cmp(v32, rv32, 1e-5, "jacobian path stokes-v f32")
+    _cmp(q32, rq32, 1e-5, "jacobian path stokes-q f32")

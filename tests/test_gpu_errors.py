@@ -58,6 +58,17 @@ def test_argument_errors():
     assert e.value.status == fsi.FSI_ERR_ARG
     s = fsi.Sizes()
     assert ctx.lib.fsi_get_sizes(ctx.h, ctx.n_levels, ctypes.byref(s)) == fsi.FSI_ERR_ARG
+    # launch variants and solve options out of range
+    for lev, prec, var in ((ctx.n_levels, 0, 0), (0, 2, 0), (0, 0, 12), (0, 1, -1)):
+        assert ctx.lib.fsi_set_tuning(ctx.h, lev, prec, var) == fsi.FSI_ERR_ARG
+    fsi.setup_workload(ctx, wl)
+    ctx.setup()
+    gu = torch.from_numpy(wl.g_u).cuda()
+    gp = torch.from_numpy(wl.g_p).cuda()
+    for bad in (dict(reorth=3), dict(reorth=-1), dict(restart=0)):
+        with pytest.raises(fsi.FSIError) as e:
+            ctx.solve(gu, gp, **bad)
+        assert e.value.status == fsi.FSI_ERR_ARG
 
 
 def test_nonfinite_inputs_are_rejected():
