@@ -160,17 +160,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                 uu[c][k] = (FWD && act && !wall) ? (CHEB ? a.x : a.u)[c * a.nvn + node[k]] : T(0);
         }
         int pnode = 0;
-        double qold = 0.0;       // partial sum of earlier phases (RES at the last touch: f_p - partial)
-        bool plast = false;
         if constexpr (HAS_B) {
-            if (pwriter) {
-                pnode = a.pmap[cell * 8 + t];
-                if (!((inf.z >> t) & 1u)) qold = a.q[pnode];
-                if constexpr (RES) {
-                    plast = (inf.z >> (16 + t)) & 1u;
-                    if (plast) qold = a.fp[pnode] - qold;
-                }
-            }
+            if (pwriter) pnode = a.pmap[cell * 8 + t];
         }
         T pv[8];
         if constexpr (HAS_BT) {
@@ -282,8 +273,12 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             tx0 = ly0 * lz0 * pv[0] + ly1 * lz0 * pv[2] + ly0 * lz1 * pv[4] + ly1 * lz1 * pv[6];
             tx1 = ly0 * lz0 * pv[1] + ly1 * lz0 * pv[3] + ly0 * lz1 * pv[5] + ly1 * lz1 * pv[7];
         }
-        if constexpr (sizeof(T) == 8) {
-        // FP64: accumulate the backward x-sweep point by point (fewer live registers)
+        // point-by-point accumulation of the backward x-sweep needs fewer live registers;
+        // FP64 always uses it, FP32 for the Stokes modes (A + B^T [+ B]), whose extra
+        // pressure state would otherwise halve the wavefronts per SIMD
+        constexpr bool PERQX = sizeof(T) == 8 || (HAS_A && HAS_BT && !VG);
+        if constexpr (PERQX) {
+        // accumulate the backward x-sweep point by point (fewer live registers)
 #pragma unroll
         for (int qx = 0; qx < 3; ++qx) {
             // keep one point's geometry in flight at a time (register budget)
@@ -486,6 +481,17 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         // ---------------- divergence tested with the Q1 basis (B); x-shared vertices
         // are summed along the row before the write
         if constexpr (HAS_B) {
+            // partial sum of earlier phases (RES at the last touch: f_p - partial), fetched
+            // here so that it is not live through stage C; the reduction below hides it
+            double qold = 0.0;
+            bool plast = false;
+            if (pwriter) {
+                if (!((inf.z >> t) & 1u)) qold = a.q[pnode];
+                if constexpr (RES) {
+                    plast = (inf.z >> (16 + t)) & 1u;
+                    if (plast) qold = a.fp[pnode] - qold;
+                }
+            }
             if (inwave) {
                 const T ly[2] = {rL<T>(qy, 0), rL<T>(qy, 1)};
                 const T lz[2] = {rL<T>(qz, 0), rL<T>(qz, 1)};
