@@ -165,8 +165,13 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         }
         T pv[8];
         if constexpr (HAS_BT) {
+            // threads t < 8 of a cell fetch one vertex value each; the cell's other
+            // threads read them across lanes (one memory round trip instead of
+            // eight index + eight value loads per thread)
+            const T mine = (act && t < 8) ? T(a.p[a.pmap[cell * 8 + t]]) : T(0);
+            const int base = lane - t;   // lane of the cell's first thread
 #pragma unroll
-            for (int n = 0; n < 8; ++n) pv[n] = act ? T(a.p[a.pmap[cell * 8 + n]]) : T(0);
+            for (int n = 0; n < 8; ++n) pv[n] = __shfl(mine, base + n, 64);
         }
         // geometry from vertices: at this thread's (qy, qz) the Jacobian columns of the
         // multilinear map x = X + sum_v N_v d_v are dx/dxi_0 = g0 (constant in qx) and
