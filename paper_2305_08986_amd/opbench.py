@@ -3,7 +3,8 @@
     python -m paper_2305_08986_amd.opbench --workload C3 --mode A --prec fp64 --reps 20
 
 Times the fused cell kernel with HIP events (fsi_time_operator) and prints one
-JSON line.  With --copy-calibration it also runs a plain elementwise copy kernel
+JSON line per (precision, launch variant) pair: --prec and --variant take
+comma-separated lists, and a pinned --variant overrides the autotuner.  With --copy-calibration it also runs a plain elementwise copy kernel
 (y = 1.0 * x, 2 GiB each way) first, which profiler counter runs use to scale
 HBM byte counters.
 """
@@ -20,7 +21,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--mode", default="A", choices=sorted(MODES))
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--prec", default="fp64", help="fp64, fp32 or a comma-separated list")
+    ap.add_argument("--variant", default="", help="launch variant(s) 0..11 to pin, comma-separated")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--level", type=int, default=-1)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch variant")
@@ -53,16 +55,21 @@ def main(argv=None):
     ctx = fsi.Context.from_mesh(wl.mesh)
     fsi.setup_workload(ctx, wl)
     lev = ctx.n_levels - 1 if a.level < 0 else a.level
-    p = 0 if a.prec == "fp64" else 1
-    if not a.no_autotune:
+    precs = [{"fp64": 0, "fp32": 1}[x] for x in a.prec.split(",")]
+    variants = [int(v) for v in a.variant.split(",")] if a.variant else [None]
+    if not a.no_autotune and variants == [None]:
         ctx.autotune()
-    k_us, op_us, nl = ctx.time_operator(lev, precision=p, mode=MODES[a.mode], reps=a.reps)
     s = ctx.sizes(lev)
-    out.update(dict(workload=a.workload, level=lev, mode=a.mode, prec=a.prec, reps=a.reps,
-                    variant=ctx.tuning(lev, p)[0], n_cells=s["n_cells"], n_vel=s["n_vel"],
-                    kernel_us=k_us, launches=nl, mean_launch_us=k_us / nl, operator_us=op_us,
-                    gdofs=s["n_vel"] / (op_us * 1e-6) / 1e9))
-    print(json.dumps(out), flush=True)
+    for p in precs:
+        for var in variants:
+            if var is not None:
+                ctx.set_tuning(lev, p, var)
+            k_us, op_us, nl = ctx.time_operator(lev, precision=p, mode=MODES[a.mode], reps=a.reps)
+            out.update(dict(workload=a.workload, level=lev, mode=a.mode, prec=["fp64", "fp32"][p], reps=a.reps,
+                            variant=ctx.tuning(lev, p)[0], n_cells=s["n_cells"], n_vel=s["n_vel"],
+                            kernel_us=k_us, launches=nl, mean_launch_us=k_us / nl, operator_us=op_us,
+                            gdofs=s["n_vel"] / (op_us * 1e-6) / 1e9))
+            print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -111,6 +111,64 @@ def test_fp64_operator_full_size_sampled_rows():
     assert np.array_equal(v[dm], u[dm])
 
 
+def _sampled_rows(box, rng, n_vel_rows, n_p_rows):
+    """Random rows plus the rows of the first and last cells of the box (the ragged
+    ends of rows, walls and the last processing phase)."""
+    nn = box.n_vel_nodes
+    last = box.n_cells - 1
+    edge = np.concatenate([box.cell_vel_nodes(np.array([0, last])).ravel() + c * nn for c in range(3)])
+    rows = np.unique(np.concatenate([rng.choice(box.n_vel, n_vel_rows, replace=False), edge]))
+    prow = np.unique(np.concatenate([rng.choice(box.n_p, n_p_rows, replace=False),
+                                     box.cell_p_nodes(np.array([0, last])).ravel()]))
+    return rows, prow
+
+
+@pytest.mark.parametrize("name", ["C4", "C3"])
+def test_full_size_operators_in_the_tuned_launch_shapes(name):
+    """96^3 and 128^3 warped boxes (the time-step sequence and the mixed-precision
+    solve workloads) with the autotuned launch variants that the benchmark times:
+    sampled rows of A, B^T and B against the oracle's cell-by-cell evaluation, FP64
+    within 1e-12 and FP32 within 1e-5 of the largest sampled entry."""
+    from paper_2305_08986_amd import fsi
+    wl = W.make_workload(name)
+    ctx = fsi.Context.from_mesh(wl.mesh)
+    fsi.setup_workload(ctx, wl)
+    ctx.setup()
+    ctx.autotune()
+    J = ctx.n_levels - 1
+    box = fem.level_box(wl.mesh, J)
+    rng = np.random.default_rng([29, box.n_cells])
+    u = rng.uniform(-1, 1, box.n_vel)
+    p = rng.uniform(-1, 1, box.n_p)
+    rows, prow = _sampled_rows(box, rng, 120, 30)
+    ref = fem.Reference(3)
+    rv, rq = fem.apply_rows(box, wl.disp, wl.c_mass[J], wl.eta[J], ref, u, p, rows, prow)
+    ra, _ = fem.apply_rows(box, wl.disp, wl.c_mass[J], wl.eta[J], ref, u, None, rows, prow)
+    ut, pt = torch.from_numpy(u).cuda(), torch.from_numpy(p).cuda()
+    v, q = ctx.apply_stokes(J, ut, pt)
+    a = ctx.apply_A(J, ut)
+    b = ctx.apply_B(J, ut)
+    for got, want, what in ((v, rv, "stokes-v"), (a, ra, "A"), (q, rq, "stokes-q"), (b, rq, "B")):
+        sel = rows if what in ("stokes-v", "A") else prow
+        err = np.abs(got.cpu().numpy()[sel] - want).max() / np.abs(want).max()
+        print(f"{name} fp64 {what}: {err:.2e}")
+        assert err <= 1e-12, (name, what, err)
+    del v, q, a, b
+    # FP32 twins on the rounded inputs
+    u32, p32 = ut.float(), pt.float()
+    uf = u32.double().cpu().numpy()
+    pf = p32.double().cpu().numpy()
+    rv, rq = fem.apply_rows(box, wl.disp, wl.c_mass[J], wl.eta[J], ref, uf, pf, rows, prow)
+    ra, _ = fem.apply_rows(box, wl.disp, wl.c_mass[J], wl.eta[J], ref, uf, None, rows, prow)
+    v, q = ctx.apply_stokes(J, u32, p32)
+    a = ctx.apply_A(J, u32)
+    for got, want, what in ((v, rv, "stokes-v"), (a, ra, "A"), (q, rq, "stokes-q")):
+        sel = rows if what != "stokes-q" else prow
+        err = np.abs(got.cpu().double().numpy()[sel] - want).max() / np.abs(want).max()
+        print(f"{name} fp32 {what}: {err:.2e}")
+        assert err <= 1e-5, (name, what, err)
+
+
 @pytest.mark.parametrize("name", ["T3_R", "T3_16", "T3_4"])
 def test_every_launch_variant_gives_the_same_operator(name):
     """Each of the 12 launch variants (one or four wavefronts per row, streaming or
