@@ -46,6 +46,15 @@ __device__ __forceinline__ T gload(const T* p) {
     else return *p;
 }
 
+// ordering of LDS traffic among the lanes of one wavefront: a wavefront's LDS
+// instructions execute in issue order, so only compiler code motion has to be
+// stopped (no s_barrier, no wait for outstanding memory operations)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
     const int64_t x = b & 7, qd = nb >> 3, r = nb & 7;
     const int64_t base = (x < r) ? x * (qd + 1) : r * (qd + 1) + (x - r) * qd;
@@ -94,6 +103,8 @@ struct CellArgs {
 // and take WPB consecutive chunks per step, so a step covers 14 WPB nodes of every
 // node line (fewer cache lines shared with the next step) and the row has WPB
 // times more wavefronts in flight; the x-face hand-over then crosses wavefronts.
+// Only the two hand-overs (x-face values and pressure partial sums) synchronise the
+// workgroup; the LDS transposes between sweep directions are wavefront-private.
 template <typename T, int MODE, int WPB, bool RS, bool NTL, int WPE, bool VG>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE))) void cell3d(CellArgs<T> a) {
     constexpr int NT = 9, CPW = 7, NLOC = 27, BUF = 243;
@@ -113,9 +124,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     __shared__ double pbuf[HAS_B ? WPB : 1][CPW][NT][8];
     // x-face hand-over between neighbouring cells of the row: [slot][j][comp][k],
     // carry from the last slot of a chunk to the first slot of the next one
-    __shared__ T xb[WPB][CPW][27];
+    // (double-buffered by step parity, so that a wavefront may start the next step
+    // while its right neighbour still reads the previous step's values)
+    __shared__ T xb[2][WPB][CPW][27];
     __shared__ T xcarry[WPB][2][27];
-    __shared__ double pxb[HAS_B ? WPB : 1][CPW][4];
+    __shared__ double pxb[2][HAS_B ? WPB : 1][CPW][4];
     __shared__ double pcarry[HAS_B ? WPB : 1][2][4];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -215,7 +228,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                         B[((c * 2 + 1) * 3 + q3) * 9 + t] = dv;
                     }
             }
-            __syncthreads();
+            wave_sync();
             const int ib = t % 3, qzb = t / 3;
             T ya[3][3], yb[3][3], yc[3][3];
             if (inwave) {
@@ -242,7 +255,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                     }
                 }
             }
-            __syncthreads();
+            wave_sync();
             if (inwave) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
@@ -253,7 +266,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                         B[((c * 3 + 2) * 9 + q2 + 3 * qzb) * 3 + ib] = yc[c][q2];
                     }
             }
-            __syncthreads();
+            wave_sync();
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -508,18 +521,19 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                         pbuf[wave][slot][t][1 + 2 * by + 4 * cz] = double(ly[by] * lz[cz] * r1);
                     }
             }
-            __syncthreads();
+            wave_sync();
             double sq = 0.0;
             if (inwave && t < 8) {
 #pragma unroll
                 for (int tt = 0; tt < NT; ++tt) sq += pbuf[wave][slot][tt][t];
-                if (pax == 1) pxb[wave][slot][pyz] = sq;
+                if (pax == 1) pxb[st & 1][wave][slot][pyz] = sq;
             }
-            __syncthreads();
+            __syncthreads();   // pxb crosses wavefronts (row sharing)
             if (act && t < 8) {
                 if (pax == 0 && ix > 0)
-                    sq += slot > 0 ? pxb[wave][slot - 1][pyz]
-                                   : ((RS && wave > 0) ? pxb[wave - 1][CPW - 1][pyz] : pcarry[cw][(st + 1) & 1][pyz]);
+                    sq += slot > 0 ? pxb[st & 1][wave][slot - 1][pyz]
+                                   : ((RS && wave > 0) ? pxb[st & 1][wave - 1][CPW - 1][pyz]
+                                                       : pcarry[cw][(st + 1) & 1][pyz]);
                 if (pwriter) {
                     a.q[pnode] = plast ? qold - sq : qold + sq;
                 } else if (slot == CPW - 1 && carry_out) {
@@ -533,7 +547,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         // side, and for the Chebyshev step the iterate, direction and 1/diag A
         T ep[3][3], er[3][3], ex[3][3], ed[3][3], eg[3][3];
         if constexpr (BWD) {
-            __syncthreads();
+            wave_sync();
             if (inwave) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
@@ -544,7 +558,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                         B[((c * 3 + 2) * 9 + t) * 3 + i] = wc[c][i];
                     }
             }
-            __syncthreads();
+            wave_sync();
             // ---------------- fused epilogue operands, fetched behind the barrier that
             // ends stage C (so they do not add to its register peak) and combined only
             // at the store, after the backward sweeps whose work hides their latency
@@ -590,7 +604,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                     vd[c][j] = dv;
                 }
             }
-            __syncthreads();
+            wave_sync();
             if (inwave) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
@@ -600,7 +614,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                         B[((c * 2 + 1) * 3 + qzb) * 9 + ib + 3 * j] = vd[c][j];
                     }
             }
-            __syncthreads();
+            wave_sync();
             T out[3][3];   // [comp][k] for the nodes (ic, jc, k) of this thread's column
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -622,17 +636,17 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) xb[wave][slot][jc * 9 + c * 3 + k] = out[c][k];
+                    for (int k = 0; k < 3; ++k) xb[st & 1][wave][slot][jc * 9 + c * 3 + k] = out[c][k];
             }
-            __syncthreads();
+            __syncthreads();   // xb crosses wavefronts (row sharing)
             if (act) {
                 if (ic == 0 && ix > 0) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
 #pragma unroll
                         for (int k = 0; k < 3; ++k)
-                            out[c][k] += slot > 0 ? xb[wave][slot - 1][jc * 9 + c * 3 + k]
-                                                  : ((RS && wave > 0) ? xb[wave - 1][CPW - 1][jc * 9 + c * 3 + k]
+                            out[c][k] += slot > 0 ? xb[st & 1][wave][slot - 1][jc * 9 + c * 3 + k]
+                                                  : ((RS && wave > 0) ? xb[st & 1][wave - 1][CPW - 1][jc * 9 + c * 3 + k]
                                                                       : xcarry[cw][(st + 1) & 1][jc * 9 + c * 3 + k]);
                 }
                 if (vwriter) {
@@ -672,7 +686,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
     }   // chunk loop
 }
 
@@ -744,7 +758,7 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
                     B[((c * 2 + 1) * 3 + qy) * 3 + t] = d;
                 }
         }
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             T sa[3], da[3];
@@ -844,7 +858,7 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
 #pragma unroll
                 for (int ax = 0; ax < 2; ++ax) pbuf[wave][slot][t][ax + 2 * by] = double(ly[by] * r[ax]);
         }
-        __syncthreads();
+        wave_sync();
         // thread t < 2 sums the vertices (0, t) and (1, t); the x-shared vertex (1, t)
         // is added into the right neighbour's (0, t) along the row
         double s0 = 0.0, s1 = 0.0;
@@ -853,7 +867,7 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
             s1 = pbuf[wave][slot][0][2 * t + 1] + pbuf[wave][slot][1][2 * t + 1] + pbuf[wave][slot][2][2 * t + 1];
             pxb[wave][slot][t] = s1;
         }
-        __syncthreads();
+        wave_sync();
         if (act && t < 2) {
             if (ix > 0) s0 += slot > 0 ? pxb[wave][slot - 1][t] : pcarry[wave][(ch + 1) & 1][t];
             const uint32_t pf = a.info[cell].z;
@@ -886,7 +900,7 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
                 ws[c][i] = s;
                 wd[c][i] = d;
             }
-        __syncthreads();
+        wave_sync();
         if (inwave) {
 #pragma unroll
             for (int c = 0; c < 2; ++c)
@@ -896,7 +910,7 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
                     B[((c * 2 + 1) * 3 + t) * 3 + i] = wd[c][i];
                 }
         }
-        __syncthreads();
+        wave_sync();
         T out[2][3];   // [comp][j] for the nodes (i, j) of this thread's column
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -920,7 +934,7 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
 #pragma unroll
                 for (int j = 0; j < 3; ++j) xb[wave][slot][c * 3 + j] = out[c][j];
         }
-        __syncthreads();
+        wave_sync();
         if (act) {
             if (t == 0 && ix > 0) {
 #pragma unroll
@@ -967,7 +981,7 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
             }
         }
     }
-    __syncthreads();
+    wave_sync();
     }   // chunk loop
 }
 
@@ -1007,7 +1021,10 @@ template <typename T, int MODE, int WPB, bool NTL>
 static void launch_capped(const Level& L, int cap, const CellArgs<T>& args, hipStream_t s) {
     constexpr bool STOKES = (MODE & OP_A) && (MODE & OP_BT);
     constexpr int W1 = sizeof(T) == 8 ? (STOKES ? 2 : 3) : (STOKES ? 3 : 4);
-    if (cap == 0) launch_one<T, MODE, WPB, NTL, 1>(L, args, s);
+    // uncapped: FP64 A and B classes fit two wavefronts per SIMD (the row-shared
+    // launches would otherwise take a few registers more and drop to one)
+    constexpr int W0 = (sizeof(T) == 8 && !STOKES) ? 2 : 1;
+    if (cap == 0) launch_one<T, MODE, WPB, NTL, W0>(L, args, s);
     else launch_one<T, MODE, WPB, NTL, W1>(L, args, s);
 }
 
