@@ -561,19 +561,22 @@ static fsi_status setup_coarse(Context* ctx) {
     int* d_vrow;
     int* d_piv;
     double* d_col;
+    double* d_tmp;
     FSI_HIP_TRY(hipMalloc((void**)&d_vrow, sizeof(int) * L.nv));
-    FSI_HIP_TRY(hipMalloc((void**)&d_piv, sizeof(int) * n));
+    FSI_HIP_TRY(hipMalloc((void**)&d_piv, sizeof(int) * 2 * n));
     FSI_HIP_TRY(hipMalloc((void**)&d_col, sizeof(double) * n));
+    FSI_HIP_TRY(hipMalloc((void**)&d_tmp, sizeof(double) * n * n));
     FSI_HIP_TRY(hipMemcpyAsync(d_vrow, vrow.data(), sizeof(int) * L.nv, hipMemcpyHostToDevice, s));
     launch_fill<double>(C.d_inv64, 0.0, n * n, s);
     launch_coarse_assemble_impl(L, L.d_K64, L.d_cv64, d_vrow, nf, C.d_inv64, n, s);
     launch_fill<int>(ctx->d_flag, 0, 1, s);
-    launch_gj(C.d_inv64, n, d_piv, d_col, ctx->d_flag, s);
+    launch_gj(C.d_inv64, n, d_piv, d_piv + n, d_col, d_tmp, ctx->d_flag, s);
     launch_cast<float, double>(C.d_inv32, C.d_inv64, n * n, s);
     fsi_status st = sync_flag(ctx, FSI_ERR_BREAKDOWN, "singular coarse-level matrix");
     hipFree(d_vrow);
     hipFree(d_piv);
     hipFree(d_col);
+    hipFree(d_tmp);
     return st;
 }
 

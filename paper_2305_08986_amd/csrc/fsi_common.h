@@ -310,7 +310,7 @@ void launch_prolongate_add(const Level& fine, const Level& coarse, const T* ec_u
 // coarse level
 void launch_coarse_assemble_impl(const Level& L, const double* K, const double* cv, const int* vrow,
                                  int64_t nfree_u, double* M, int64_t n, hipStream_t s);
-void launch_gj(double* M, int64_t n, int* piv, double* colk, int* flag, hipStream_t s);
+void launch_gj(double* M, int64_t n, int* piv, int* sigma, double* colk, double* tmp, int* flag, hipStream_t s);
 template <typename T>
 void launch_coarse_apply(const Coarse& C, const Level& L, const T* f_u, const double* f_p, T* x_u,
                          double* x_p, hipStream_t s);

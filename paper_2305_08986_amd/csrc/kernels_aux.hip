@@ -1085,11 +1085,16 @@ void launch_coarse_assemble_impl(const Level& L, const double* K, const double* 
         }
 }
 
-// Gauss-Jordan inversion with partial pivoting, one pivot step per three launches.
-__global__ void k_gj_pivot(const double* __restrict__ M, int64_t n, int64_t k, int* __restrict__ piv,
-                           int* __restrict__ flag) {
-    __shared__ double bv[1024];
-    __shared__ int bi[1024];
+// Gauss-Jordan inversion with partial pivoting: per pivot step one single-workgroup
+// launch (pivot search, row swap, copy of the pivot column, scaling of the pivot
+// row) and one elimination launch over the whole matrix; the column swaps of the
+// row pivoting are applied at the end as one permutation.
+constexpr int kGjThreads = 1024;
+__global__ __launch_bounds__(kGjThreads) void k_gj_prep(double* __restrict__ M, int64_t n, int64_t k,
+                                                        int* __restrict__ piv, double* __restrict__ colk,
+                                                        int* __restrict__ flag) {
+    __shared__ double bv[kGjThreads];
+    __shared__ int bi[kGjThreads];
     double best = -1.0;
     int bidx = (int)k;
     for (int64_t i = k + threadIdx.x; i < n; i += blockDim.x) {
@@ -1110,33 +1115,25 @@ __global__ void k_gj_pivot(const double* __restrict__ M, int64_t n, int64_t k, i
         }
         __syncthreads();
     }
+    const int64_t p = bi[0];
     if (threadIdx.x == 0) {
-        piv[k] = bi[0];
+        piv[k] = (int)p;
         if (!(bv[0] > 0.0)) flag[0] = 1;
     }
-}
-__global__ void k_gj_swap_scale(double* __restrict__ M, int64_t n, int64_t k, const int* __restrict__ piv,
-                                double* __restrict__ colk) {
-    const int64_t p = piv[k];
     // swap rows k and p
-    for (int64_t j = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-        if (p != k) {
+    if (p != k)
+        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
             const double t = M[k * n + j];
             M[k * n + j] = M[p * n + j];
             M[p * n + j] = t;
         }
-    }
-}
-__global__ void k_gj_save_col(double* __restrict__ M, int64_t n, int64_t k, double* __restrict__ colk) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) colk[i] = M[i * n + k];
-}
-__global__ void k_gj_scale_row(double* __restrict__ M, int64_t n, int64_t k, const double* __restrict__ colk) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const double pv = colk[k];
-    if (j == k) M[k * n + k] = 1.0 / pv;
-    else M[k * n + j] = M[k * n + j] / pv;
+    __syncthreads();
+    // pivot column (after the swap), then the scaled pivot row
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) colk[i] = M[i * n + k];
+    __syncthreads();
+    const double pv = M[k * n + k];
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) M[k * n + j] = (j == k) ? 1.0 / pv : M[k * n + j] / pv;
 }
 __global__ void k_gj_eliminate(double* __restrict__ M, int64_t n, int64_t k, const double* __restrict__ colk) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1147,25 +1144,37 @@ __global__ void k_gj_eliminate(double* __restrict__ M, int64_t n, int64_t k, con
     if (j == k) M[i * n + k] = -f * M[k * n + k];
     else M[i * n + j] -= f * M[k * n + j];
 }
-__global__ void k_gj_colswap(double* __restrict__ M, int64_t n, int64_t k, const int* __restrict__ piv) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t p = piv[k];
-    if (i >= n || p == k) return;
-    const double t = M[i * n + k];
-    M[i * n + k] = M[i * n + p];
-    M[i * n + p] = t;
+// the column swaps (k, piv[k]) for k = n-1 .. 0 compose to one permutation:
+// column j of the result is column sigma[j] of the eliminated matrix
+__global__ void k_gj_sigma(const int* __restrict__ piv, int64_t n, int* __restrict__ sigma) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int64_t j = 0; j < n; ++j) sigma[j] = (int)j;
+    for (int64_t k = n - 1; k >= 0; --k) {
+        const int64_t p = piv[k];
+        const int t = sigma[k];
+        sigma[k] = sigma[p];
+        sigma[p] = t;
+    }
+}
+__global__ void k_gj_permute(const double* __restrict__ M, int64_t n, const int* __restrict__ sigma,
+                             double* __restrict__ out) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n * n) return;
+    const int64_t i = id / n, j = id - (id / n) * n;
+    out[id] = M[i * n + sigma[j]];
 }
 
-void launch_gj(double* M, int64_t n, int* piv, double* colk, int* flag, hipStream_t s) {
+// inverts M (n x n, row-major) in place; piv and sigma: n ints, colk: n doubles,
+// tmp: n * n doubles of scratch
+void launch_gj(double* M, int64_t n, int* piv, int* sigma, double* colk, double* tmp, int* flag, hipStream_t s) {
+    if (n <= 0) return;
     for (int64_t k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, M, n, k, piv, flag);
-        hipLaunchKernelGGL(k_gj_swap_scale, dim3(nblocks(n)), dim3(TPB), 0, s, M, n, k, piv, colk);
-        hipLaunchKernelGGL(k_gj_save_col, dim3(nblocks(n)), dim3(TPB), 0, s, M, n, k, colk);
-        hipLaunchKernelGGL(k_gj_scale_row, dim3(nblocks(n)), dim3(TPB), 0, s, M, n, k, colk);
+        hipLaunchKernelGGL(k_gj_prep, dim3(1), dim3(kGjThreads), 0, s, M, n, k, piv, colk, flag);
         hipLaunchKernelGGL(k_gj_eliminate, dim3(nblocks(n * n)), dim3(TPB), 0, s, M, n, k, colk);
     }
-    for (int64_t k = n - 1; k >= 0; --k)
-        hipLaunchKernelGGL(k_gj_colswap, dim3(nblocks(n)), dim3(TPB), 0, s, M, n, k, piv);
+    hipLaunchKernelGGL(k_gj_sigma, dim3(1), dim3(64), 0, s, piv, n, sigma);
+    hipLaunchKernelGGL(k_gj_permute, dim3(nblocks(n * n)), dim3(TPB), 0, s, M, n, sigma, tmp);
+    hipMemcpyAsync(M, tmp, sizeof(double) * n * n, hipMemcpyDeviceToDevice, s);
 }
 
 // coarse apply: gather free dofs, dense GEMV with the inverse, scatter
