@@ -779,23 +779,6 @@ __device__ __forceinline__ void q1_prol_1d(int f, int ncoarse_cells, int& base, 
     else if (r == 1) { w[0] = 0.5; w[1] = 0.5; }
     else { w[0] = 0; w[1] = 1; }
 }
-// transpose: coarse Q2 node c -> fine nodes and weights (up to 5)
-__device__ __forceinline__ int q2_rest_1d(int c, int nfine_nodes, int f[5], double w[5]) {
-    int m = 0;
-    if ((c & 1) == 0) {
-        const int e = c >> 1;
-        const int fo[5] = {4 * e - 3, 4 * e - 1, 4 * e, 4 * e + 1, 4 * e + 3};
-        const double wo[5] = {-0.125, 0.375, 1.0, 0.375, -0.125};
-        for (int i = 0; i < 5; ++i)
-            if (fo[i] >= 0 && fo[i] < nfine_nodes) { f[m] = fo[i]; w[m] = wo[i]; ++m; }
-    } else {
-        const int e = c >> 1;
-        const int fo[3] = {4 * e + 1, 4 * e + 2, 4 * e + 3};
-        const double wo[3] = {0.75, 1.0, 0.75};
-        for (int i = 0; i < 3; ++i) { f[m] = fo[i]; w[m] = wo[i]; ++m; }
-    }
-    return m;
-}
 __device__ __forceinline__ int q1_rest_1d(int c, int nfine_nodes, int f[3], double w[3]) {
     int m = 0;
     const int fo[3] = {2 * c - 1, 2 * c, 2 * c + 1};
@@ -813,33 +796,6 @@ struct XferDims {
     int64_t fnv, cnv, fnp, cnp;
 };
 
-template <typename T>
-__global__ void k_restrict_u(XferDims x, const T* __restrict__ rf, T* __restrict__ rc, const uint8_t* __restrict__ cwall) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= x.cnv) return;
-    int c[3] = {0, 0, 0};
-    int64_t r = id;
-    for (int d = 0; d < x.dim; ++d) { c[d] = (int)(r % x.cv[d]); r /= x.cv[d]; }
-    int fi[3][5];
-    double wi[3][5];
-    int m[3] = {1, 1, 1};
-    fi[1][0] = fi[2][0] = 0;
-    wi[1][0] = wi[2][0] = 1.0;
-    for (int d = 0; d < x.dim; ++d) m[d] = q2_rest_1d(c[d], x.fv[d], fi[d], wi[d]);
-    const bool wall = cwall[id] != 0;
-    for (int comp = 0; comp < x.dim; ++comp) {
-        double acc = 0.0;
-        if (!wall) {
-            for (int k = 0; k < m[2]; ++k)
-                for (int j = 0; j < m[1]; ++j)
-                    for (int i = 0; i < m[0]; ++i) {
-                        const int64_t fn = fi[0][i] + (int64_t)x.fv[0] * (fi[1][j] + (int64_t)x.fv[1] * fi[2][k]);
-                        acc += wi[0][i] * wi[1][j] * wi[2][k] * (double)rf[comp * x.fnv + fn];
-                    }
-        }
-        rc[comp * x.cnv + id] = (T)acc;
-    }
-}
 __global__ void k_restrict_p(XferDims x, const double* __restrict__ rf, double* __restrict__ rc) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= x.cnp) return;
@@ -862,33 +818,57 @@ __global__ void k_restrict_p(XferDims x, const double* __restrict__ rf, double* 
     rc[id] = acc;
 }
 
+// The velocity transfers are tensor products of the 1D Q2 stencils, so they run as
+// one 1D pass per direction over a tensor viewed as [outer][n][inner] (inner = the
+// faster directions, contiguous): each pass reads its input once, coalesced along
+// the inner index.  Restriction contracts x, then y, then z (the last pass zeroes
+// the coarse wall rows); prolongation expands z, then y, then x (the last pass adds
+// into the fine vector, skipping its wall rows).
 template <typename T>
-__global__ void k_prolong_u(XferDims x, const T* __restrict__ ec, T* __restrict__ xf, const uint8_t* __restrict__ fwall) {
+__global__ void k_restrict_axis(const T* __restrict__ in, T* __restrict__ out, int64_t outer, int nf, int nc,
+                                int64_t inner, const uint8_t* __restrict__ cwall, int64_t cnv) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= x.fnv) return;
-    if (fwall[id]) return;
-    int f[3] = {0, 0, 0};
-    int64_t r = id;
-    for (int d = 0; d < x.dim; ++d) { f[d] = (int)(r % x.fv[d]); r /= x.fv[d]; }
-    int base[3] = {0, 0, 0};
-    double w[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
-    int m[3] = {1, 1, 1};
-    for (int d = 0; d < x.dim; ++d) { q2_prol_1d(f[d], x.cc[d], base[d], w[d]); m[d] = 3; }
-    for (int comp = 0; comp < x.dim; ++comp) {
-        double acc = 0.0;
-        for (int k = 0; k < m[2]; ++k)
-            for (int j = 0; j < m[1]; ++j) {
-                const double wjk = w[1][j] * w[2][k];
-                if (wjk == 0.0) continue;
-                for (int i = 0; i < m[0]; ++i) {
-                    const double ww = w[0][i] * wjk;
-                    if (ww == 0.0) continue;
-                    const int64_t cn = (base[0] + i) + (int64_t)x.cv[0] * ((base[1] + j) + (int64_t)x.cv[1] * (base[2] + k));
-                    acc += ww * (double)ec[comp * x.cnv + cn];
-                }
-            }
-        xf[comp * x.fnv + id] += (T)acc;
+    if (id >= outer * nc * inner) return;
+    const int64_t b = id % inner, r = id / inner;
+    const int c = (int)(r % nc);
+    const int64_t a = r / nc;
+    const T* src = in + a * nf * inner + b;
+    const int e = c >> 1;
+    T acc = T(0);
+    if ((c & 1) == 0) {
+        const int f0 = 4 * e;
+        acc = src[(int64_t)f0 * inner];
+        if (f0 - 1 >= 0) acc += T(0.375) * src[(int64_t)(f0 - 1) * inner];
+        if (f0 + 1 < nf) acc += T(0.375) * src[(int64_t)(f0 + 1) * inner];
+        if (f0 - 3 >= 0) acc -= T(0.125) * src[(int64_t)(f0 - 3) * inner];
+        if (f0 + 3 < nf) acc -= T(0.125) * src[(int64_t)(f0 + 3) * inner];
+    } else {
+        const int f1 = 4 * e + 1;
+        acc = T(0.75) * (src[(int64_t)f1 * inner] + src[(int64_t)(f1 + 2) * inner]) + src[(int64_t)(f1 + 1) * inner];
     }
+    if (cwall && cwall[id % cnv]) acc = T(0);
+    out[id] = acc;
+}
+template <typename T>
+__global__ void k_prolong_axis(const T* __restrict__ in, T* __restrict__ out, int64_t outer, int ncells, int nf,
+                               int64_t inner, const uint8_t* __restrict__ fwall, int64_t fnv) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= outer * nf * inner) return;
+    if (fwall && fwall[id % fnv]) return;   // last pass: wall rows keep their value
+    const int64_t b = id % inner, r = id / inner;
+    const int f = (int)(r % nf);
+    const int64_t a = r / nf;
+    const int nc = 2 * ncells + 1;
+    int base;
+    double w[3];
+    q2_prol_1d(f, ncells, base, w);
+    const T* src = in + (a * nc + base) * inner + b;
+    T acc = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (w[i] != 0.0) acc += T(w[i]) * src[(int64_t)i * inner];
+    if (fwall) out[id] += acc;
+    else out[id] = acc;
 }
 __global__ void k_prolong_p(XferDims x, const double* __restrict__ ec, double* __restrict__ xf) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -933,26 +913,57 @@ static XferDims xdims(const Level& fine, const Level& coarse) {
 
 template <typename T>
 void launch_restrict(const Level& fine, const Level& coarse, const T* rf_u, const double* rf_p, T* rc_u, double* rc_p,
-                     hipStream_t s) {
+                     T* s1, T* s2, hipStream_t s) {
     const XferDims x = xdims(fine, coarse);
-    hipLaunchKernelGGL(k_restrict_u<T>, dim3(nblocks(x.cnv)), dim3(TPB), 0, s, x, rf_u, rc_u, level_wall_mask(coarse));
+    const int D = x.dim;
+    // extents of the tensor [comp][z][y][x] as the passes shrink it
+    int64_t ext[3] = {x.fv[0], x.fv[1], D == 3 ? x.fv[2] : 1};
+    const T* in = rf_u;
+    for (int d = 0; d < D; ++d) {
+        const bool last = d == D - 1;
+        T* out = last ? rc_u : (d == 0 ? s1 : s2);
+        int64_t inner = 1, outer = D;
+        for (int e = 0; e < d; ++e) inner *= ext[e];
+        for (int e = d + 1; e < 3; ++e) outer *= ext[e];
+        const int nf = (int)ext[d], nc = x.cv[d];
+        const int64_t n = outer * nc * inner;
+        hipLaunchKernelGGL(k_restrict_axis<T>, dim3(nblocks(n)), dim3(TPB), 0, s, in, out, outer, nf, nc, inner,
+                           last ? level_wall_mask(coarse) : nullptr, x.cnv);
+        ext[d] = nc;
+        in = out;
+    }
     hipLaunchKernelGGL(k_restrict_p, dim3(nblocks(x.cnp)), dim3(TPB), 0, s, x, rf_p, rc_p);
 }
 template <typename T>
 void launch_prolongate_add(const Level& fine, const Level& coarse, const T* ec_u, const double* ec_p, T* xf_u,
-                           double* xf_p, hipStream_t s) {
+                           double* xf_p, T* s1, T* s2, hipStream_t s) {
     const XferDims x = xdims(fine, coarse);
-    hipLaunchKernelGGL(k_prolong_u<T>, dim3(nblocks(x.fnv)), dim3(TPB), 0, s, x, ec_u, xf_u, level_wall_mask(fine));
+    const int D = x.dim;
+    int64_t ext[3] = {x.cv[0], x.cv[1], D == 3 ? x.cv[2] : 1};
+    const T* in = ec_u;
+    for (int d = D - 1; d >= 0; --d) {
+        const bool last = d == 0;
+        T* out = last ? xf_u : (d == D - 1 ? s1 : s2);
+        int64_t inner = 1, outer = D;
+        for (int e = 0; e < d; ++e) inner *= ext[e];
+        for (int e = d + 1; e < 3; ++e) outer *= ext[e];
+        const int nf = x.fv[d];
+        const int64_t n = outer * nf * inner;
+        hipLaunchKernelGGL(k_prolong_axis<T>, dim3(nblocks(n)), dim3(TPB), 0, s, in, out, outer, x.cc[d], nf, inner,
+                           last ? level_wall_mask(fine) : nullptr, x.fnv);
+        ext[d] = nf;
+        in = out;
+    }
     hipLaunchKernelGGL(k_prolong_p, dim3(nblocks(x.fnp)), dim3(TPB), 0, s, x, ec_p, xf_p);
 }
 template void launch_restrict<double>(const Level&, const Level&, const double*, const double*, double*, double*,
-                                      hipStream_t);
+                                      double*, double*, hipStream_t);
 template void launch_restrict<float>(const Level&, const Level&, const float*, const double*, float*, double*,
-                                     hipStream_t);
+                                     float*, float*, hipStream_t);
 template void launch_prolongate_add<double>(const Level&, const Level&, const double*, const double*, double*,
-                                            double*, hipStream_t);
+                                            double*, double*, double*, hipStream_t);
 template void launch_prolongate_add<float>(const Level&, const Level&, const float*, const double*, float*, double*,
-                                           hipStream_t);
+                                           float*, float*, hipStream_t);
 
 // ---------------------------------------------------------------- coarse level
 // One thread per (cell of one colour, test dof (a, n), column node m): the element

@@ -229,7 +229,8 @@ class Context:
         """Pin the launch variant of every operator class on a level (overrides autotune)."""
         self._check(self.lib.fsi_set_tuning(self.h, level, precision, variant))
     def time_operator(self, level: int, precision: int = 0, mode: int = 1, reps: int = 10):
-        """(cell-kernel us per application, operator us per application, launches per application)."""
+        """(cell-kernel us, operator us, launches) of one application: medians over `reps`
+        timed applications after three warm-ups."""
         k = C.c_double()
         o = C.c_double()
         n = C.c_int()
