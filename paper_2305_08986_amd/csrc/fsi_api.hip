@@ -381,10 +381,12 @@ static void vcycle_level(Context* ctx, int j, hipStream_t s) {
     }
     residual<T>(ctx, j, s);
     LevelWork<T>& C = works<T>(ctx)[j - 1];
-    // the smoother's work vectors are free here and serve as transfer scratch
-    launch_restrict<T>(ctx->lv[j], ctx->lv[j - 1], W.r_u, W.r_p, C.f_u, C.f_p, W.w_u, W.v_u, s);
+    // FP64 transfer scratch: the level's FP64 smoother work vectors, free here in
+    // either precision (one V-cycle runs at a time on the context's stream)
+    LevelWork<double>& S = ctx->w64[j];
+    launch_restrict<T>(ctx->lv[j], ctx->lv[j - 1], W.r_u, W.r_p, C.f_u, C.f_p, S.w_u, S.v_u, s);
     vcycle_level<T>(ctx, j - 1, s);
-    launch_prolongate_add<T>(ctx->lv[j], ctx->lv[j - 1], C.x_u, C.x_p, W.x_u, W.x_p, W.w_u, W.v_u, s);
+    launch_prolongate_add<T>(ctx->lv[j], ctx->lv[j - 1], C.x_u, C.x_p, W.x_u, W.x_p, S.w_u, S.v_u, s);
     for (int st = 0; st < m; ++st) {
         residual<T>(ctx, j, s);
         smoother<T>(ctx, j, W.r_u, W.r_p, W.x_u, W.x_p, false, s);

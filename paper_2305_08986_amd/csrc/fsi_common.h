@@ -300,13 +300,13 @@ template <typename T>
 void launch_smoother_update(const T* w, const T* vv, const double* z, const double* dots, T* x_u,
                             double* x_p, int64_t nu, int64_t np, bool first, hipStream_t s);
 
-// s1, s2: fine-level scratch vectors (velocity length) for the intermediate passes
+// s1, s2: FP64 fine-level scratch vectors (velocity length) for the intermediate passes
 template <typename T>
 void launch_restrict(const Level& fine, const Level& coarse, const T* rf_u, const double* rf_p,
-                     T* rc_u, double* rc_p, T* s1, T* s2, hipStream_t s);
+                     T* rc_u, double* rc_p, double* s1, double* s2, hipStream_t s);
 template <typename T>
 void launch_prolongate_add(const Level& fine, const Level& coarse, const T* ec_u, const double* ec_p,
-                           T* xf_u, double* xf_p, T* s1, T* s2, hipStream_t s);
+                           T* xf_u, double* xf_p, double* s1, double* s2, hipStream_t s);
 
 // coarse level
 void launch_coarse_assemble_impl(const Level& L, const double* K, const double* cv, const int* vrow,

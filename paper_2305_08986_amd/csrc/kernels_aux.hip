@@ -823,34 +823,36 @@ __global__ void k_restrict_p(XferDims x, const double* __restrict__ rf, double* 
 // faster directions, contiguous): each pass reads its input once, coalesced along
 // the inner index.  Restriction contracts x, then y, then z (the last pass zeroes
 // the coarse wall rows); prolongation expands z, then y, then x (the last pass adds
-// into the fine vector, skipping its wall rows).
-template <typename T>
-__global__ void k_restrict_axis(const T* __restrict__ in, T* __restrict__ out, int64_t outer, int nf, int nc,
+// into the fine vector, skipping its wall rows).  Sums are formed in FP64 and the
+// intermediate tensors are FP64, so an FP32 transfer rounds once, at its output.
+template <typename Tin, typename Tout>
+__global__ void k_restrict_axis(const Tin* __restrict__ in, Tout* __restrict__ out, int64_t outer, int nf, int nc,
                                 int64_t inner, const uint8_t* __restrict__ cwall, int64_t cnv) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= outer * nc * inner) return;
     const int64_t b = id % inner, r = id / inner;
     const int c = (int)(r % nc);
     const int64_t a = r / nc;
-    const T* src = in + a * nf * inner + b;
+    const Tin* src = in + a * nf * inner + b;
     const int e = c >> 1;
-    T acc = T(0);
+    double acc;
     if ((c & 1) == 0) {
         const int f0 = 4 * e;
-        acc = src[(int64_t)f0 * inner];
-        if (f0 - 1 >= 0) acc += T(0.375) * src[(int64_t)(f0 - 1) * inner];
-        if (f0 + 1 < nf) acc += T(0.375) * src[(int64_t)(f0 + 1) * inner];
-        if (f0 - 3 >= 0) acc -= T(0.125) * src[(int64_t)(f0 - 3) * inner];
-        if (f0 + 3 < nf) acc -= T(0.125) * src[(int64_t)(f0 + 3) * inner];
+        acc = double(src[(int64_t)f0 * inner]);
+        if (f0 - 1 >= 0) acc += 0.375 * double(src[(int64_t)(f0 - 1) * inner]);
+        if (f0 + 1 < nf) acc += 0.375 * double(src[(int64_t)(f0 + 1) * inner]);
+        if (f0 - 3 >= 0) acc -= 0.125 * double(src[(int64_t)(f0 - 3) * inner]);
+        if (f0 + 3 < nf) acc -= 0.125 * double(src[(int64_t)(f0 + 3) * inner]);
     } else {
         const int f1 = 4 * e + 1;
-        acc = T(0.75) * (src[(int64_t)f1 * inner] + src[(int64_t)(f1 + 2) * inner]) + src[(int64_t)(f1 + 1) * inner];
+        acc = 0.75 * (double(src[(int64_t)f1 * inner]) + double(src[(int64_t)(f1 + 2) * inner])) +
+              double(src[(int64_t)(f1 + 1) * inner]);
     }
-    if (cwall && cwall[id % cnv]) acc = T(0);
-    out[id] = acc;
+    if (cwall && cwall[id % cnv]) acc = 0.0;
+    out[id] = Tout(acc);
 }
-template <typename T>
-__global__ void k_prolong_axis(const T* __restrict__ in, T* __restrict__ out, int64_t outer, int ncells, int nf,
+template <typename Tin, typename Tout>
+__global__ void k_prolong_axis(const Tin* __restrict__ in, Tout* __restrict__ out, int64_t outer, int ncells, int nf,
                                int64_t inner, const uint8_t* __restrict__ fwall, int64_t fnv) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= outer * nf * inner) return;
@@ -862,13 +864,13 @@ __global__ void k_prolong_axis(const T* __restrict__ in, T* __restrict__ out, in
     int base;
     double w[3];
     q2_prol_1d(f, ncells, base, w);
-    const T* src = in + (a * nc + base) * inner + b;
-    T acc = T(0);
+    const Tin* src = in + (a * nc + base) * inner + b;
+    double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-        if (w[i] != 0.0) acc += T(w[i]) * src[(int64_t)i * inner];
-    if (fwall) out[id] += acc;
-    else out[id] = acc;
+        if (w[i] != 0.0) acc += w[i] * double(src[(int64_t)i * inner]);
+    if (fwall) out[id] += Tout(acc);
+    else out[id] = Tout(acc);
 }
 __global__ void k_prolong_p(XferDims x, const double* __restrict__ ec, double* __restrict__ xf) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -911,59 +913,93 @@ static XferDims xdims(const Level& fine, const Level& coarse) {
 
 // wall masks live on the device as uint8 per node (set up by the host)
 
+namespace {
+// one 1D pass of a transfer: tensor extents before the pass, the direction d, and
+// the input / output types of the pass
+struct AxisPass {
+    int64_t outer, inner;
+    int nin, nout;
+};
+AxisPass axis_pass(const int64_t ext[3], int d, int D, int nout) {
+    AxisPass p;
+    p.inner = 1;
+    p.outer = D;
+    for (int e = 0; e < d; ++e) p.inner *= ext[e];
+    for (int e = d + 1; e < 3; ++e) p.outer *= ext[e];
+    p.nin = (int)ext[d];
+    p.nout = nout;
+    return p;
+}
+template <typename Tin, typename Tout>
+void restrict_pass(const Tin* in, Tout* out, const AxisPass& p, const uint8_t* cwall, int64_t cnv, hipStream_t s) {
+    const int64_t n = p.outer * p.nout * p.inner;
+    hipLaunchKernelGGL((k_restrict_axis<Tin, Tout>), dim3(nblocks(n)), dim3(TPB), 0, s, in, out, p.outer, p.nin, p.nout,
+                       p.inner, cwall, cnv);
+}
+template <typename Tin, typename Tout>
+void prolong_pass(const Tin* in, Tout* out, const AxisPass& p, int ncells, const uint8_t* fwall, int64_t fnv,
+                  hipStream_t s) {
+    const int64_t n = p.outer * p.nout * p.inner;
+    hipLaunchKernelGGL((k_prolong_axis<Tin, Tout>), dim3(nblocks(n)), dim3(TPB), 0, s, in, out, p.outer, ncells,
+                       p.nout, p.inner, fwall, fnv);
+}
+}  // namespace
+
 template <typename T>
 void launch_restrict(const Level& fine, const Level& coarse, const T* rf_u, const double* rf_p, T* rc_u, double* rc_p,
-                     T* s1, T* s2, hipStream_t s) {
+                     double* s1, double* s2, hipStream_t s) {
     const XferDims x = xdims(fine, coarse);
     const int D = x.dim;
     // extents of the tensor [comp][z][y][x] as the passes shrink it
     int64_t ext[3] = {x.fv[0], x.fv[1], D == 3 ? x.fv[2] : 1};
-    const T* in = rf_u;
-    for (int d = 0; d < D; ++d) {
-        const bool last = d == D - 1;
-        T* out = last ? rc_u : (d == 0 ? s1 : s2);
-        int64_t inner = 1, outer = D;
-        for (int e = 0; e < d; ++e) inner *= ext[e];
-        for (int e = d + 1; e < 3; ++e) outer *= ext[e];
-        const int nf = (int)ext[d], nc = x.cv[d];
-        const int64_t n = outer * nc * inner;
-        hipLaunchKernelGGL(k_restrict_axis<T>, dim3(nblocks(n)), dim3(TPB), 0, s, in, out, outer, nf, nc, inner,
-                           last ? level_wall_mask(coarse) : nullptr, x.cnv);
-        ext[d] = nc;
-        in = out;
+    const uint8_t* cw = level_wall_mask(coarse);
+    AxisPass p = axis_pass(ext, 0, D, x.cv[0]);
+    restrict_pass<T, double>(rf_u, s1, p, nullptr, x.cnv, s);
+    ext[0] = x.cv[0];
+    p = axis_pass(ext, 1, D, x.cv[1]);
+    if (D == 2) {
+        restrict_pass<double, T>(s1, rc_u, p, cw, x.cnv, s);
+    } else {
+        restrict_pass<double, double>(s1, s2, p, nullptr, x.cnv, s);
+        ext[1] = x.cv[1];
+        p = axis_pass(ext, 2, D, x.cv[2]);
+        restrict_pass<double, T>(s2, rc_u, p, cw, x.cnv, s);
     }
     hipLaunchKernelGGL(k_restrict_p, dim3(nblocks(x.cnp)), dim3(TPB), 0, s, x, rf_p, rc_p);
 }
 template <typename T>
 void launch_prolongate_add(const Level& fine, const Level& coarse, const T* ec_u, const double* ec_p, T* xf_u,
-                           double* xf_p, T* s1, T* s2, hipStream_t s) {
+                           double* xf_p, double* s1, double* s2, hipStream_t s) {
     const XferDims x = xdims(fine, coarse);
     const int D = x.dim;
     int64_t ext[3] = {x.cv[0], x.cv[1], D == 3 ? x.cv[2] : 1};
-    const T* in = ec_u;
-    for (int d = D - 1; d >= 0; --d) {
-        const bool last = d == 0;
-        T* out = last ? xf_u : (d == D - 1 ? s1 : s2);
-        int64_t inner = 1, outer = D;
-        for (int e = 0; e < d; ++e) inner *= ext[e];
-        for (int e = d + 1; e < 3; ++e) outer *= ext[e];
-        const int nf = x.fv[d];
-        const int64_t n = outer * nf * inner;
-        hipLaunchKernelGGL(k_prolong_axis<T>, dim3(nblocks(n)), dim3(TPB), 0, s, in, out, outer, x.cc[d], nf, inner,
-                           last ? level_wall_mask(fine) : nullptr, x.fnv);
-        ext[d] = nf;
-        in = out;
+    const uint8_t* fw = level_wall_mask(fine);
+    const double* in = nullptr;
+    if (D == 3) {
+        AxisPass p = axis_pass(ext, 2, D, x.fv[2]);
+        prolong_pass<T, double>(ec_u, s1, p, x.cc[2], nullptr, x.fnv, s);
+        ext[2] = x.fv[2];
+        p = axis_pass(ext, 1, D, x.fv[1]);
+        prolong_pass<double, double>(s1, s2, p, x.cc[1], nullptr, x.fnv, s);
+        in = s2;
+    } else {
+        AxisPass p = axis_pass(ext, 1, D, x.fv[1]);
+        prolong_pass<T, double>(ec_u, s2, p, x.cc[1], nullptr, x.fnv, s);
+        in = s2;
     }
+    ext[1] = x.fv[1];
+    AxisPass p = axis_pass(ext, 0, D, x.fv[0]);
+    prolong_pass<double, T>(in, xf_u, p, x.cc[0], fw, x.fnv, s);
     hipLaunchKernelGGL(k_prolong_p, dim3(nblocks(x.fnp)), dim3(TPB), 0, s, x, ec_p, xf_p);
 }
 template void launch_restrict<double>(const Level&, const Level&, const double*, const double*, double*, double*,
                                       double*, double*, hipStream_t);
 template void launch_restrict<float>(const Level&, const Level&, const float*, const double*, float*, double*,
-                                     float*, float*, hipStream_t);
+                                     double*, double*, hipStream_t);
 template void launch_prolongate_add<double>(const Level&, const Level&, const double*, const double*, double*,
                                             double*, double*, double*, hipStream_t);
 template void launch_prolongate_add<float>(const Level&, const Level&, const float*, const double*, float*, double*,
-                                           float*, float*, hipStream_t);
+                                           double*, double*, hipStream_t);
 
 // ---------------------------------------------------------------- coarse level
 // One thread per (cell of one colour, test dof (a, n), column node m): the element
