@@ -225,10 +225,11 @@ fsi_status fsi_set_tuning(fsi_ctx* ctx, int level, int precision, int variant);
  * Chebyshev epilogue, run with zero coefficients; 23 = Stokes with the fused
  * residual epilogue) in the given precision on
  * internal work vectors, timing every launch of the cell kernel with HIP events
- * on the context's stream.  kernel_us = cell-kernel time of one application
- * (sum over its n_launches launches: processing phases = slabs x colours),
- * op_us = duration of the whole application (including the wall rows).
- * Synchronises.  Errors: FSI_ERR_ARG, FSI_ERR_STATE. */
+ * on the context's stream, after three untimed warm-up applications.
+ * kernel_us = cell-kernel time of one application (sum over its n_launches
+ * launches, one per processing phase), op_us = duration of the whole
+ * application (including the wall rows); both are medians over the `reps`
+ * timed applications.  Synchronises.  Errors: FSI_ERR_ARG, FSI_ERR_STATE. */
 fsi_status fsi_time_operator(fsi_ctx* ctx, int level, int precision, int mode, int reps,
                              double* kernel_us, double* op_us, int* n_launches);
 
