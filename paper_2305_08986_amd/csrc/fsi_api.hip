@@ -558,29 +558,21 @@ static fsi_status setup_coarse(Context* ctx) {
         TRY(dalloc(ctx, &C.d_xout64, n));
         TRY(dalloc(ctx, &C.d_xin32, n));
         TRY(dalloc(ctx, &C.d_xout32, n));
+        TRY(dalloc(ctx, &C.d_vrow, L.nv));
+        TRY(dalloc(ctx, &C.d_piv, 2 * n));
+        TRY(dalloc(ctx, &C.d_col, n));
+        TRY(dalloc(ctx, &C.d_tmp, n * n));
     }
     if (nf > 0)
         FSI_HIP_TRY(hipMemcpyAsync(C.d_uidx, uidx.data(), sizeof(int) * nf, hipMemcpyHostToDevice, s));
-    int* d_vrow;
-    int* d_piv;
-    double* d_col;
-    double* d_tmp;
-    FSI_HIP_TRY(hipMalloc((void**)&d_vrow, sizeof(int) * L.nv));
-    FSI_HIP_TRY(hipMalloc((void**)&d_piv, sizeof(int) * 2 * n));
-    FSI_HIP_TRY(hipMalloc((void**)&d_col, sizeof(double) * n));
-    FSI_HIP_TRY(hipMalloc((void**)&d_tmp, sizeof(double) * n * n));
-    FSI_HIP_TRY(hipMemcpyAsync(d_vrow, vrow.data(), sizeof(int) * L.nv, hipMemcpyHostToDevice, s));
+    FSI_HIP_TRY(hipMemcpyAsync(C.d_vrow, vrow.data(), sizeof(int) * L.nv, hipMemcpyHostToDevice, s));
     launch_fill<double>(C.d_inv64, 0.0, n * n, s);
-    launch_coarse_assemble_impl(L, L.d_K64, L.d_cv64, d_vrow, nf, C.d_inv64, n, s);
+    launch_coarse_assemble_impl(L, L.d_K64, L.d_cv64, C.d_vrow, nf, C.d_inv64, n, s);
     launch_fill<int>(ctx->d_flag, 0, 1, s);
-    launch_gj(C.d_inv64, n, d_piv, d_piv + n, d_col, d_tmp, ctx->d_flag, s);
+    launch_gj(C.d_inv64, n, C.d_piv, C.d_piv + n, C.d_col, C.d_tmp, ctx->d_flag, s);
     launch_cast<float, double>(C.d_inv32, C.d_inv64, n * n, s);
-    fsi_status st = sync_flag(ctx, FSI_ERR_BREAKDOWN, "singular coarse-level matrix");
-    hipFree(d_vrow);
-    hipFree(d_piv);
-    hipFree(d_col);
-    hipFree(d_tmp);
-    return st;
+    // synchronises the stream, so the host vectors above outlive their copies
+    return sync_flag(ctx, FSI_ERR_BREAKDOWN, "singular coarse-level matrix");
 }
 
 static fsi_status check_level(Context* ctx, int level) {

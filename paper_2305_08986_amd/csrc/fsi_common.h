@@ -159,6 +159,12 @@ struct Coarse {
     double* d_xout64 = nullptr;
     float* d_xin32 = nullptr;
     float* d_xout32 = nullptr;
+    // set-up scratch, kept for the next set-up: velocity dof -> free row, pivot rows and
+    // column permutation (2n), pivot column, and the n x n permutation target
+    int* d_vrow = nullptr;
+    int* d_piv = nullptr;
+    double* d_col = nullptr;
+    double* d_tmp = nullptr;
 };
 
 struct Krylov {
