@@ -16,7 +16,9 @@ level matrices:
 * n V-cycles with m pre- and m post-smoothing steps (Sec. 4), dense LU on the
   coarsest level;
 * right-preconditioned flexible GMRES (Sec. 5, linear solver settings);
-* Lanczos estimate of lambda_max(D^{-1}A) for the Chebyshev interval.
+* Lanczos estimate of lambda_max(D^{-1}A) for the Chebyshev interval;
+* the pseudo-elastic extension Ext of Sec. 2 (its defining boundary-value
+  problem, solved directly).
 Defaults follow Table 4 (predictor column): k_A=4, m=2, n=1, k_S=1, n_S=1.
 
 Readings where the paper is silent (interval, eigenvalue estimate, start
@@ -371,6 +373,34 @@ def fgmres(apply_M: Callable, precond: Callable, g: np.ndarray, x0: Optional[np.
         r = g - apply_M(x)
         beta = float(np.linalg.norm(r))
     return SolveResult(x=x, iters=it, rel_res=beta / gnorm, history=hist, converged=beta / gnorm <= rtol)
+
+
+# ---------------------------------------------------------------- extension (Sec. 2)
+def extension_solve(box: fem.Box, J: np.ndarray, mu: np.ndarray, ref: fem.Reference, g: np.ndarray):
+    """Ext of Sec. 2: the displacement u with u = g on the Dirichlet dofs of ``box`` and
+    (mu eps(u), eps(v)) = 0 for every v that vanishes there.
+
+    The bilinear form is the operator's a(u, v) = (c_m u, v) + (2 eta eps(u), eps(v)) with
+    c_m = 0 and eta = mu / 2.  Interior dofs I, Dirichlet dofs W of the unconstrained
+    matrix: A_II u_I = -A_IW g_W, solved by SuperLU.  Reading: the Dirichlet set is the box
+    walls (the paper's fixed outer boundary, with data allowed to be nonzero); the
+    interface with the solid would be a further Dirichlet set of the same kind.
+    """
+    zero = np.zeros_like(mu)
+    A = fem.assemble_unconstrained(box, J, zero, 0.5 * mu, ref).A.tocsr()
+    dm = box.dirichlet_vel_dofs()
+    I = np.nonzero(~dm)[0]
+    W = np.nonzero(dm)[0]
+    u = np.where(dm, g, 0.0)
+    rhs = -(A[I][:, W] @ g[W])
+    u[I] = spla.splu(A[I][:, I].tocsc()).solve(rhs)
+    return u
+
+
+def extension_energy(box: fem.Box, J: np.ndarray, mu: np.ndarray, ref: fem.Reference, u: np.ndarray) -> float:
+    """(mu eps(u), eps(u)) / 2 of the whole box (the extension minimises it)."""
+    A = fem.assemble_unconstrained(box, J, np.zeros_like(mu), 0.5 * mu, ref).A
+    return 0.5 * float(u @ (A @ u))
 
 
 # ---------------------------------------------------------------- glue

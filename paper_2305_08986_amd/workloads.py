@@ -289,6 +289,60 @@ def make_workload(name: str, step: Optional[int] = None, seed: int = BASE_SEED,
                     g_u=g_u, g_p=g_p, info=info)
 
 
+# ---------------------------------------------------------------- extension problem inputs
+# The pseudo-elastic extension of Sec. 2 (the problem that defines Ext) with the
+# mesh-quality coefficient law of Sec. 5: mu_A = 1 + 50 exp(-800 ((x - A_x)^2 +
+# (y - A_y)^2)), evaluated at the reference quadrature-point coordinates, with A the
+# control point (0.6, 0.2) of the channel benchmarks.  The boundary data is a smooth
+# seeded field on the Dirichlet nodes (zero elsewhere).
+EXT_STREAM = 7
+EXT_POINT = (0.6, 0.2)
+
+
+@dataclasses.dataclass
+class ExtensionInputs:
+    mu: list               # per level [n_cells][Q] mu_A
+    g: np.ndarray          # fine-level [dim][n_vel_nodes] flattened; Dirichlet data, zero inside
+
+
+def mu_law(X: np.ndarray) -> np.ndarray:
+    """mu_A at reference points X[..., dim]."""
+    r2 = (X[..., 0] - EXT_POINT[0]) ** 2 + (X[..., 1] - EXT_POINT[1]) ** 2
+    return 1.0 + 50.0 * np.exp(-800.0 * r2)
+
+
+def make_extension_inputs(name: str, mesh: MeshDesc, seed: int = BASE_SEED, amp: float = 0.01,
+                          levels: Optional[Sequence[int]] = None, constant_mu: Optional[float] = None,
+                          boundary_field=None) -> ExtensionInputs:
+    """Coefficients and boundary data of the extension problem on ``mesh``.
+
+    Draw order (PCG64 seeded with ``[seed, config, EXT_STREAM]``): the four sine modes of
+    g(X) = amp * (1/4) sum_m e_m sin(2 pi k_m . X/extent + phi_m) on the Dirichlet nodes.
+    ``constant_mu`` replaces the law by a constant; ``boundary_field(X)`` (X: [dim][n])
+    replaces the drawn boundary data.
+    """
+    J = mesh.n_levels - 1
+    rng = np.random.default_rng([seed, CONFIG_INDEX[name], EXT_STREAM])
+    k, phi, e = _sine_modes(rng, mesh.dim)
+    X = velocity_node_coords(mesh, J)
+    if boundary_field is None:
+        Xt = X / np.asarray(mesh.extent, dtype=float)[:, None]
+        g = np.zeros_like(X)
+        for m in range(4):
+            g += np.outer(e[m], np.sin(2.0 * math.pi * (k[m] @ Xt) + phi[m]))
+        g *= 0.25 * amp
+    else:
+        g = np.asarray(boundary_field(X), dtype=np.float64)
+    g[:, ~dirichlet_node_mask(mesh, J)] = 0.0
+    lvls = list(range(J + 1)) if levels is None else list(levels)
+    mu = [None] * (J + 1)
+    for l in lvls:
+        Xq = qpoint_ref_coords(mesh, l)
+        m = mu_law(Xq) if constant_mu is None else np.full(Xq.shape[:2], float(constant_mu))
+        mu[l] = np.ascontiguousarray(m, dtype=np.float64)
+    return ExtensionInputs(mu=mu, g=np.ascontiguousarray(g.ravel()))
+
+
 def inject_displacement(mesh: MeshDesc, disp_fine: np.ndarray, level: int) -> np.ndarray:
     """Vertex displacement of ``level``: the fine values at the coarse vertices."""
     J = mesh.n_levels - 1

@@ -68,3 +68,38 @@ def test_planted_mistake_is_caught(case, monkeypatch):
         except AssertionError:
             caught += 1
     assert caught >= 1, case
+
+
+# ---------------------------------------------------------------- extension solve
+def _make_bad_extension(kind):
+    import scipy.sparse.linalg as spla
+    from oracle import solvers
+
+    def bad(box, J, mu, ref, g):
+        A = fem.assemble_unconstrained(box, J, np.zeros_like(mu), 0.5 * mu, ref).A.tocsr()
+        dm = box.dirichlet_vel_dofs()
+        I = np.nonzero(~dm)[0]
+        W = np.nonzero(dm)[0]
+        u = np.where(dm, g, 0.0)
+        rhs = -(A[I][:, W] @ g[W])
+        if kind == "sign":
+            rhs = -rhs
+        elif kind == "half":         # the boundary coupling counted once per pair of dofs, halved
+            rhs = 0.5 * rhs
+        u[I] = spla.splu(A[I][:, I].tocsc()).solve(rhs)
+        return u
+    return bad
+
+
+@pytest.mark.parametrize("kind", ["sign", "half"])
+def test_planted_extension_mistake_is_caught(kind, monkeypatch):
+    from oracle import solvers
+    monkeypatch.setattr(solvers, "extension_solve", _make_bad_extension(kind))
+    caught = 0
+    for pin in (lambda: pins.test_extension_reproduces_affine_fields_on_warped_mesh("T3_4", 63),
+                pins.test_extension_minimises_the_energy_with_variable_mu):
+        try:
+            pin()
+        except AssertionError:
+            caught += 1
+    assert caught >= 1, kind

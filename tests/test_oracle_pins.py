@@ -541,3 +541,92 @@ def test_workload_generator_contract():
     sizes = {n: (W.make_mesh(n).n_vel(W.make_mesh(n).n_levels - 1), W.make_mesh(n).n_p(W.make_mesh(n).n_levels - 1))
              for n in ("C2", "C3", "C4")}
     assert sizes == {"C2": (6440067, 274625), "C3": (50923779, 2146689), "C4": (21567171, 912673)}
+
+
+# ---------------------------------------------------------------- extension solve (Sec. 2)
+def _q2_node_displacement(mesh, disp):
+    """Displacement of the multilinear ALE map at the Q2 nodes: vertex values at even
+    node indices, averages of the two neighbours at odd ones (per direction)."""
+    pn = mesh.p_nodes(mesh.n_levels - 1)
+    a = disp.reshape((mesh.dim,) + tuple(pn[::-1]))
+    for ax in range(1, mesh.dim + 1):
+        n = a.shape[ax]
+        shape = list(a.shape)
+        shape[ax] = 2 * n - 1
+        b = np.empty(shape)
+        sl_even = [slice(None)] * a.ndim
+        sl_even[ax] = slice(0, None, 2)
+        b[tuple(sl_even)] = a
+        lo = [slice(None)] * a.ndim
+        hi = [slice(None)] * a.ndim
+        lo[ax] = slice(0, n - 1)
+        hi[ax] = slice(1, n)
+        odd = [slice(None)] * a.ndim
+        odd[ax] = slice(1, None, 2)
+        b[tuple(odd)] = 0.5 * (a[tuple(lo)] + a[tuple(hi)])
+        a = b
+    return a.reshape(mesh.dim, -1)
+
+
+def _extension_case(name, faces, constant_mu=None, boundary_field=None):
+    from oracle import solvers
+    wl = W.make_workload(name, dirichlet_faces=faces, levels=[])
+    mesh = wl.mesh
+    J = mesh.n_levels - 1
+    ext = W.make_extension_inputs(name, mesh, levels=[J], constant_mu=constant_mu, boundary_field=boundary_field)
+    box = fem.level_box(mesh, J)
+    ref = fem.Reference(mesh.dim)
+    Jq = fem.jacobians_q1(box, wl.disp, ref)
+    u = solvers.extension_solve(box, Jq, ext.mu[J], ref, ext.g)
+    return wl, box, ref, Jq, ext, u
+
+
+@pytest.mark.parametrize("name,faces", [("T3_4", 63), ("T2_R", 15)])
+def test_extension_reproduces_affine_fields_on_warped_mesh(name, faces):
+    """Constant mu, every wall Dirichlet, boundary data of a physical affine field f(x) =
+    Bx + c: f composed with the multilinear map lies in the mapped Q2 space and
+    div(mu eps(f)) = 0, so the discrete extension is f itself at every node."""
+    rng = np.random.default_rng(41)
+    dim = 3 if name.startswith("T3") else 2
+    Bm = rng.uniform(-0.02, 0.02, (dim, dim))
+    c = rng.uniform(-0.01, 0.01, dim)
+    holder = {}
+
+    def field(X):
+        mesh = holder["mesh"]
+        x = X + _q2_node_displacement(mesh, holder["disp"])
+        return Bm @ x + c[:, None]
+
+    wl0 = W.make_workload(name, dirichlet_faces=faces, levels=[])
+    holder["mesh"], holder["disp"] = wl0.mesh, wl0.disp
+    wl, box, ref, Jq, ext, u = _extension_case(name, faces, constant_mu=3.7, boundary_field=field)
+    want = field(W.velocity_node_coords(wl.mesh, wl.mesh.n_levels - 1)).ravel()
+    assert np.abs(wl.disp).max() > 1e-3          # the mesh really is warped
+    err = np.abs(u - want).max() / np.abs(want).max()
+    assert err <= 1e-11, err
+
+
+def test_extension_minimises_the_energy_with_variable_mu():
+    """With the mu_A law and the default walls (do-nothing outflow face), the solution is
+    the minimiser of (mu eps(u), eps(u))/2 over fields with the boundary data: the first
+    variation along random interior perturbations vanishes and the energy grows."""
+    from oracle import solvers
+    wl, box, ref, Jq, ext, u = _extension_case("T3_R", None)
+    J = wl.mesh.n_levels - 1
+    mu = ext.mu[J]
+    assert mu.max() > 10 and mu.min() < 1.01      # the law's peak lies inside the box
+    E = lambda v: solvers.extension_energy(box, Jq, mu, ref, v)
+    e0 = E(u)
+    dm = box.dirichlet_vel_dofs()
+    assert np.array_equal(u[dm], ext.g[dm])
+    rng = np.random.default_rng(43)
+    for _ in range(3):
+        d = rng.uniform(-1, 1, u.size) * 1e-3
+        d[dm] = 0.0
+        ep, em = E(u + d), E(u - d)
+        first = 0.5 * (ep - em)                   # a(u, d)
+        second = 0.5 * (ep + em) - e0             # a(d, d) / 2
+        assert second > 0
+        assert abs(first) <= 1e-9 * np.sqrt(e0 * second), (first, e0, second)
+    # the zero extension of the boundary data has more energy
+    assert E(np.where(dm, ext.g, 0.0)) > e0
