@@ -206,6 +206,27 @@ fsi_status fsi_vcycle(fsi_ctx* ctx, const double* r_u, const double* r_p, double
 fsi_status fsi_solve(fsi_ctx* ctx, const double* g_u, const double* g_p, double* u, double* p,
                      const fsi_solve_opts* opts, fsi_solve_info* info);
 
+/* Extension solve: the pseudo-elastic extension Ext of Sec. 2 (its defining
+ * boundary-value problem) on the finest level.  Finds u with u = g on the
+ * Dirichlet (wall) nodes and a(u, v) = 0 for every v that vanishes there, where
+ * a is the context's A form, (c_m u, v) + (2 eta eps(u), eps(v)): set c_m = 0
+ * and eta = mu_A / 2 on every level to get (mu_A eps(u), eps(v)).  Solver (Sec. 5,
+ * settings of the extension): flexible CG preconditioned by one multigrid V-cycle
+ * on A alone (Chebyshev(A, diag A, k_A) pre- and post-smoothing, the nested-space
+ * transfers, a direct solve of the free velocity block of A_0), in the configured
+ * precision (FSI_PREC_MIXED: FP32 V-cycle, FP64 CG).
+ *   g: device [n_vel] (component-major), only the wall entries are read.
+ *   u: device [n_vel]; interior entries are the initial guess on entry; on exit
+ *      the extension (wall entries = g).
+ *   opts: rtol = ||b - A u_I||_2 / ||b||_2 with b = -A_IW g_W (the residual of the
+ *      zero interior guess), confirmed on the true FP64 residual; max_iter;
+ *      restart and reorth are not used.
+ * The first call after fsi_setup builds the velocity-only coarse inverse.
+ * Synchronises.  Errors: FSI_ERR_ARG, FSI_ERR_STATE, FSI_ERR_NONFINITE,
+ * FSI_ERR_BREAKDOWN; FSI_NOT_CONVERGED (result still written) at max_iter. */
+fsi_status fsi_solve_extension(fsi_ctx* ctx, const double* g, double* u, const fsi_solve_opts* opts,
+                               fsi_solve_info* info);
+
 /* Autotuner: times the cell-kernel launch variants (wavefronts per workgroup,
  * register cap, cached or streaming geometry loads) for every operator class
  * (A, A with the fused Chebyshev step, Stokes, Stokes with the fused residual,

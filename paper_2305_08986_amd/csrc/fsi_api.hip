@@ -582,6 +582,7 @@ static fsi_status check_level(Context* ctx, int level) {
 
 static fsi_status invalidate(Context* ctx) {
     ctx->setup_done = false;
+    ctx->ext_ready = false;
     for (int pi = 0; pi < 2; ++pi)
         if (ctx->graph_valid[pi]) {
             hipGraphExecDestroy(ctx->graph[pi]);
@@ -639,6 +640,85 @@ static fsi_status precond_combined(Context* ctx, const double* r, double* z, hip
     FSI_HIP_TRY(hipMemcpyAsync(z, ctx->vc_out_u, sizeof(double) * L.nv, hipMemcpyDeviceToDevice, s));
     FSI_HIP_TRY(hipMemcpyAsync(z + L.nv, ctx->vc_out_p, sizeof(double) * L.np, hipMemcpyDeviceToDevice, s));
     return FSI_OK;
+}
+
+
+// ---------------------------------------------------------------- extension solve
+// The pseudo-elastic extension of Sec. 2: u = g on the Dirichlet nodes and a(u, v) = 0
+// for every v vanishing there, with a the context's A form (c_m = 0 and eta = mu_A / 2
+// give (mu_A eps(u), eps(v))).  Classical matrix-free multigrid on A alone (Sec. 5,
+// extension solver settings): Chebyshev(A, diag A, k_A) pre- and post-smoothing, the
+// same transfers and a direct solve of the free velocity block on the coarsest level,
+// inside flexible CG.
+
+// velocity-only coarse inverse: the level-0 block matrix assembled once more into the
+// set-up scratch, its free velocity block copied out and inverted
+static fsi_status setup_coarse_u(Context* ctx) {
+    Level& L = ctx->lv[0];
+    Coarse& C = ctx->coarse;
+    Coarse& U = ctx->coarse_u;
+    hipStream_t s = ctx->stream;
+    const int64_t n = C.n, nf = C.nfree_u;
+    if (U.n != nf) {
+        U.n = nf;
+        U.nfree_u = nf;
+        TRY(dalloc(ctx, &U.d_inv64, nf * nf));
+        TRY(dalloc(ctx, &U.d_inv32, nf * nf));
+        TRY(dalloc(ctx, &U.d_xin64, nf));
+        TRY(dalloc(ctx, &U.d_xout64, nf));
+        TRY(dalloc(ctx, &U.d_xin32, nf));
+        TRY(dalloc(ctx, &U.d_xout32, nf));
+    }
+    U.d_uidx = C.d_uidx;
+    if (nf == 0) return FSI_OK;
+    launch_fill<double>(C.d_tmp, 0.0, n * n, s);
+    launch_coarse_assemble_impl(L, L.d_K64, L.d_cv64, C.d_vrow, nf, C.d_tmp, n, s);
+    FSI_HIP_TRY(hipMemcpy2DAsync(U.d_inv64, sizeof(double) * nf, C.d_tmp, sizeof(double) * n, sizeof(double) * nf,
+                                 nf, hipMemcpyDeviceToDevice, s));
+    launch_fill<int>(ctx->d_flag, 0, 1, s);
+    launch_gj(U.d_inv64, nf, C.d_piv, C.d_piv + nf, C.d_col, C.d_tmp, ctx->d_flag, s);
+    launch_cast<float, double>(U.d_inv32, U.d_inv64, nf * nf, s);
+    return sync_flag(ctx, FSI_ERR_BREAKDOWN, "singular coarse-level velocity block");
+}
+
+// W.r_u = W.f_u - A W.x_u
+template <typename T>
+static void ext_residual(Context* ctx, int j, hipStream_t s) {
+    LevelWork<T>& W = works<T>(ctx)[j];
+    op_apply<T>(ctx, j, OP_A, W.x_u, nullptr, W.tu, nullptr, s);
+    launch_sub<T>(W.f_u, W.tu, W.r_u, ctx->lv[j].nv, s);
+}
+
+// one V-cycle from a zero guess on level j: W.f_u -> W.x_u (velocity only)
+template <typename T>
+static void ext_vcycle_level(Context* ctx, int j, hipStream_t s) {
+    LevelWork<T>& W = works<T>(ctx)[j];
+    const Level& L = ctx->lv[j];
+    if (j == 0) {
+        launch_coarse_apply_u<T>(ctx->coarse_u, L, W.f_u, W.x_u, s);
+        return;
+    }
+    cheb<T>(ctx, j, W.f_u, W.x_u, s);          // pre-smoothing from zero
+    ext_residual<T>(ctx, j, s);
+    LevelWork<T>& C = works<T>(ctx)[j - 1];
+    LevelWork<double>& S = ctx->w64[j];         // FP64 transfer scratch, free here
+    launch_restrict<T>(L, ctx->lv[j - 1], W.r_u, nullptr, C.f_u, nullptr, S.w_u, S.v_u, s);
+    ext_vcycle_level<T>(ctx, j - 1, s);
+    launch_prolongate_add<T>(L, ctx->lv[j - 1], C.x_u, nullptr, W.x_u, nullptr, S.w_u, S.v_u, s);
+    ext_residual<T>(ctx, j, s);                 // post-smoothing
+    cheb<T>(ctx, j, W.r_u, W.w_u, s);
+    launch_add<T>(W.x_u, W.w_u, L.nv, s);
+}
+
+// z = V(r) on the finest level, FP64 in and out
+template <typename T>
+static void ext_precondition(Context* ctx, const double* r, double* z, hipStream_t s) {
+    const int J = ctx->nlev - 1;
+    LevelWork<T>& W = works<T>(ctx)[J];
+    const int64_t nv = ctx->lv[J].nv;
+    launch_cast<T, double>(W.f_u, r, nv, s);
+    ext_vcycle_level<T>(ctx, J, s);
+    launch_cast<double, T>(z, W.x_u, nv, s);
 }
 
 }  // namespace fsi
@@ -1163,6 +1243,132 @@ static void launch_phase_on_work(Context* ctx, int prec, int j, int mode, int va
         else
             launch_cell<float>(L, mode, var, ph, Kmode<float>(L, mode), L.d_cv32, W.x_u, W.x_p, W.r_u, W.r_p, s);
     }
+}
+
+fsi_status fsi_solve_extension(fsi_ctx* h, const double* g, double* u, const fsi_solve_opts* o,
+                               fsi_solve_info* info) {
+    if (!h || !g || !u || !o) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    if (!ctx->setup_done) return fail(ctx, FSI_ERR_STATE, "extension solve before setup");
+    if (o->max_iter < 0 || !(o->rtol >= 0)) return fail(ctx, FSI_ERR_ARG, "invalid solve options");
+    const int J = ctx->nlev - 1;
+    Level& L = ctx->lv[J];
+    const int64_t nv = L.nv;
+    hipStream_t s = ctx->stream;
+    if (!ctx->ext_ready) {
+        TRY(setup_coarse_u(ctx));
+        if (!ctx->d_info_free) TRY(dalloc(ctx, &ctx->d_info_free, L.nc));
+        launch_clear_wall_bits(L.d_info, ctx->d_info_free, L.nc, s);
+        if (!ctx->ext_buf) TRY(dalloc(ctx, &ctx->ext_buf, 8 * nv));
+        ctx->ext_ready = true;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    double* b = ctx->ext_buf;
+    double* x = b + nv;
+    double* r = x + nv;
+    double* z = r + nv;
+    double* zo = z + nv;
+    double* pd = zo + nv;
+    double* q = pd + nv;
+    double* gw = q + nv;
+    const bool mixed = ctx->prm.precision == FSI_PREC_MIXED;
+    auto precond = [&](const double* rr, double* zz) {
+        if (mixed) ext_precondition<float>(ctx, rr, zz, s);
+        else ext_precondition<double>(ctx, rr, zz, s);
+    };
+    // boundary data on the walls (gw) and the interior initial guess (x, walls zero)
+    launch_fill<double>(gw, 0.0, nv, s);
+    launch_dirichlet_copy<double>(L, g, gw, s);
+    FSI_HIP_TRY(hipMemcpyAsync(x, u, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
+    launch_dirichlet_zero<double>(L, x, s);
+    launch_fill<int>(ctx->d_flag, 0, 1, s);
+    launch_nonfinite(gw, nv, ctx->d_flag, s);
+    launch_nonfinite(x, nv, ctx->d_flag, s);
+    TRY(sync_flag(ctx, FSI_ERR_NONFINITE, "boundary data or initial guess not finite"));
+    // lifting: b = -(A gw) on the interior rows, with the unconstrained operator (wall
+    // columns kept); the cell info without wall bits stands in for the level's own
+    {
+        uint4* own = L.d_info;
+        L.d_info = ctx->d_info_free;
+        op_apply<double>(ctx, J, OP_A, gw, nullptr, q, nullptr, s);
+        L.d_info = own;
+    }
+    launch_scale_host(-1.0, q, b, nv, s);
+    launch_dirichlet_zero<double>(L, b, s);
+    double bn2;
+    TRY(dot64(ctx, b, b, nv, &bn2));
+    const double bnorm = std::sqrt(bn2);
+    int hist_n = 0;
+    auto push_hist = [&](double v) {
+        if (info && info->res_history && hist_n < o->max_iter + 1) info->res_history[hist_n] = v;
+        ++hist_n;
+    };
+    auto finish = [&](int it, double rel, fsi_status st) -> fsi_status {
+        // u = x on the interior, g on the walls
+        FSI_HIP_TRY(hipMemcpyAsync(u, x, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
+        launch_dirichlet_copy<double>(L, gw, u, s);
+        FSI_HIP_TRY(hipStreamSynchronize(s));
+        if (info) {
+            info->iters = it;
+            info->final_rel_res = rel;
+            info->n_hist = std::min(hist_n, o->max_iter + 1);
+            info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        return st;
+    };
+    if (bnorm == 0.0) {   // zero boundary data: the extension vanishes
+        launch_fill<double>(x, 0.0, nv, s);
+        return finish(0, 0.0, FSI_OK);
+    }
+    op_apply<double>(ctx, J, OP_A, x, nullptr, q, nullptr, s);
+    launch_sub<double>(b, q, r, nv, s);
+    launch_dirichlet_zero<double>(L, r, s);
+    double rr;
+    TRY(dot64(ctx, r, r, nv, &rr));
+    double rel = std::sqrt(rr) / bnorm;
+    push_hist(rel);
+    int it = 0;
+    fsi_status status = FSI_OK;
+    if (rel > o->rtol && o->max_iter > 0) {
+        precond(r, z);
+        double rz;
+        TRY(dot64(ctx, r, z, nv, &rz));
+        FSI_HIP_TRY(hipMemcpyAsync(pd, z, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
+        while (rel > o->rtol && it < o->max_iter) {
+            op_apply<double>(ctx, J, OP_A, pd, nullptr, q, nullptr, s);
+            double pq;
+            TRY(dot64(ctx, pd, q, nv, &pq));
+            if (!(pq > 0.0) || !std::isfinite(pq)) {
+                status = fail(ctx, FSI_ERR_BREAKDOWN, "CG breakdown in the extension solve");
+                break;
+            }
+            const double alpha = rz / pq;
+            launch_axpy_host(alpha, pd, x, nv, s);
+            launch_axpy_host(-alpha, q, r, nv, s);
+            TRY(dot64(ctx, r, r, nv, &rr));
+            rel = std::sqrt(rr) / bnorm;
+            ++it;
+            push_hist(rel);
+            if (rel <= o->rtol) break;
+            // flexible (Polak-Ribiere) beta: the preconditioner may vary between calls
+            std::swap(z, zo);
+            precond(r, z);
+            double rz_new, rzo;
+            TRY(dot64(ctx, r, z, nv, &rz_new));
+            TRY(dot64(ctx, r, zo, nv, &rzo));
+            const double beta = (rz_new - rzo) / rz;
+            rz = rz_new;
+            launch_xpby_host(z, beta, pd, nv, s);
+        }
+    }
+    if (status != FSI_OK) return status;
+    // true residual at exit
+    op_apply<double>(ctx, J, OP_A, x, nullptr, q, nullptr, s);
+    launch_sub<double>(b, q, r, nv, s);
+    launch_dirichlet_zero<double>(L, r, s);
+    TRY(dot64(ctx, r, r, nv, &rr));
+    rel = std::sqrt(rr) / bnorm;
+    return finish(it, rel, rel <= o->rtol ? FSI_OK : FSI_NOT_CONVERGED);
 }
 
 fsi_status fsi_autotune(fsi_ctx* h) {

@@ -195,6 +195,14 @@ struct Context {
     std::vector<LevelWork<float>> w32;
     Coarse coarse;
     Krylov kr;
+    // extension solve: velocity-only coarse inverse (shares the free-dof list of
+    // `coarse`), finest-level cell info without wall bits (the unconstrained operator
+    // for the boundary lifting) and the CG vectors; built at the first extension solve
+    // after a set-up
+    Coarse coarse_u;
+    bool ext_ready = false;
+    uint4* d_info_free = nullptr;
+    double* ext_buf = nullptr;     // 8 finest-level velocity vectors
     double* d_scratch = nullptr;   // general scratch (partials, flags)
     int* d_flag = nullptr;
     int* h_flag = nullptr;         // pinned
@@ -334,6 +342,12 @@ void launch_multi_axpy_norm(const double* V, int64_t ldv, int m, const double* c
 void launch_multi_axpy(const double* V, int64_t ldv, int m, const double* coef_dev, double sign,
                        double* w, int64_t n, hipStream_t s);
 void launch_axpy_host(double a, const double* x, double* y, int64_t n, hipStream_t s);
+void launch_xpby_host(const double* x, double b, double* y, int64_t n, hipStream_t s);   // y = x + b y
+template <typename T>
+void launch_add(T* x, const T* y, int64_t n, hipStream_t s);                              // x += y
+void launch_clear_wall_bits(const uint4* in, uint4* out, int64_t n, hipStream_t s);
+template <typename T>
+void launch_coarse_apply_u(const Coarse& U, const Level& L, const T* f_u, T* x_u, hipStream_t s);
 void launch_scale_host(double a, const double* x, double* y, int64_t n, hipStream_t s);
 void launch_lanczos_start(const Level& L, double* v, hipStream_t s);
 void launch_mul(const double* a, const double* b, double* c, int64_t n, hipStream_t s);

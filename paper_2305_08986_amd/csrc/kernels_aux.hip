@@ -965,7 +965,7 @@ void launch_restrict(const Level& fine, const Level& coarse, const T* rf_u, cons
         p = axis_pass(ext, 2, D, x.cv[2]);
         restrict_pass<double, T>(s2, rc_u, p, cw, x.cnv, s);
     }
-    hipLaunchKernelGGL(k_restrict_p, dim3(nblocks(x.cnp)), dim3(TPB), 0, s, x, rf_p, rc_p);
+    if (rf_p) hipLaunchKernelGGL(k_restrict_p, dim3(nblocks(x.cnp)), dim3(TPB), 0, s, x, rf_p, rc_p);
 }
 template <typename T>
 void launch_prolongate_add(const Level& fine, const Level& coarse, const T* ec_u, const double* ec_p, T* xf_u,
@@ -990,7 +990,7 @@ void launch_prolongate_add(const Level& fine, const Level& coarse, const T* ec_u
     ext[1] = x.fv[1];
     AxisPass p = axis_pass(ext, 0, D, x.fv[0]);
     prolong_pass<double, T>(in, xf_u, p, x.cc[0], fw, x.fnv, s);
-    hipLaunchKernelGGL(k_prolong_p, dim3(nblocks(x.fnp)), dim3(TPB), 0, s, x, ec_p, xf_p);
+    if (ec_p) hipLaunchKernelGGL(k_prolong_p, dim3(nblocks(x.fnp)), dim3(TPB), 0, s, x, ec_p, xf_p);
 }
 template void launch_restrict<double>(const Level&, const Level&, const double*, const double*, double*, double*,
                                       double*, double*, hipStream_t);
@@ -1271,6 +1271,30 @@ void launch_coarse_apply(const Coarse& C, const Level& L, const T* f_u, const do
 }
 template void launch_coarse_apply<double>(const Coarse&, const Level&, const double*, const double*, double*, double*,
                                           hipStream_t);
+// velocity-only coarse solve (the extension problem): U holds the inverse of the free
+// velocity block of A_0
+template <typename T>
+void launch_coarse_apply_u(const Coarse& U, const Level& L, const T* f_u, T* x_u, hipStream_t s) {
+    const T* A = nullptr;
+    T *xin = nullptr, *xout = nullptr;
+    if constexpr (sizeof(T) == 8) {
+        A = U.d_inv64;
+        xin = U.d_xin64;
+        xout = U.d_xout64;
+    } else {
+        A = U.d_inv32;
+        xin = U.d_xin32;
+        xout = U.d_xout32;
+    }
+    launch_fill<T>(x_u, T(0), L.nv, s);
+    hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblocks(U.n)), dim3(TPB), 0, s, U.d_uidx, U.nfree_u, (int64_t)0, f_u,
+                       (const double*)nullptr, xin);
+    hipLaunchKernelGGL(k_gemv<T>, dim3((unsigned)((U.n + 3) / 4)), dim3(256), 0, s, A, xin, xout, U.n);
+    hipLaunchKernelGGL(k_coarse_scatter<T>, dim3(nblocks(U.n)), dim3(TPB), 0, s, U.d_uidx, U.nfree_u, (int64_t)0, xout,
+                       x_u, (double*)nullptr);
+}
+template void launch_coarse_apply_u<double>(const Coarse&, const Level&, const double*, double*, hipStream_t);
+template void launch_coarse_apply_u<float>(const Coarse&, const Level&, const float*, float*, hipStream_t);
 template void launch_coarse_apply<float>(const Coarse&, const Level&, const float*, const double*, float*, double*,
                                          hipStream_t);
 
@@ -1378,6 +1402,35 @@ void launch_multi_axpy_norm(const double* V, int64_t ldv, int m, const double* c
 __global__ void k_axpy(double a, const double* __restrict__ x, double* __restrict__ y, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] += a * x[i];
+}
+__global__ void k_xpby(const double* __restrict__ x, double b, double* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i] + b * y[i];
+}
+void launch_xpby_host(const double* x, double b, double* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_xpby, dim3(nblocks(n)), dim3(TPB), 0, s, x, b, y, n);
+}
+template <typename T>
+__global__ void k_add(T* __restrict__ x, const T* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += y[i];
+}
+template <typename T>
+void launch_add(T* x, const T* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_add<T>, dim3(nblocks(n)), dim3(TPB), 0, s, x, y, n);
+}
+template void launch_add<double>(double*, const double*, int64_t, hipStream_t);
+template void launch_add<float>(float*, const float*, int64_t, hipStream_t);
+__global__ void k_clear_wall_bits(const uint4* __restrict__ in, uint4* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        uint4 v = in[i];
+        v.x = 0u;
+        out[i] = v;
+    }
+}
+void launch_clear_wall_bits(const uint4* in, uint4* out, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_wall_bits, dim3(nblocks(n)), dim3(TPB), 0, s, in, out, n);
 }
 void launch_axpy_host(double a, const double* x, double* y, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(TPB), 0, s, a, x, y, n);

@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fsi_apply_stokes_f32": (i, [vp, i, vp, vp, vp, vp]),
         "fsi_vcycle": (i, [vp, vp, vp, vp, vp]),
         "fsi_solve": (i, [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
+        "fsi_solve_extension": (i, [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
         "fsi_autotune": (i, [vp]),
         "fsi_get_tuning": (i, [vp, i, i, C.POINTER(i), C.POINTER(d)]),
         "fsi_set_tuning": (i, [vp, i, i, i]),
@@ -300,6 +301,22 @@ class Context:
         out = dict(status=STATUS_NAMES[st], iters=info.iters, rel_res=info.final_rel_res, time_ms=info.time_ms,
                    history=[hist[k] for k in range(info.n_hist)])
         return u, p, out
+
+    def solve_extension(self, g, u=None, rtol: float = 1e-6, max_iter: int = 200):
+        """Extension solve (fsi_solve_extension); returns (u, info).  g holds the wall
+        data; u (if given) the interior initial guess, updated in place."""
+        t = self.torch
+        u = t.zeros_like(g) if u is None else u
+        o = SolveOpts(rtol=rtol, max_iter=max_iter, restart=1, reorth=0)
+        hist = (C.c_double * (max_iter + 1))()
+        info = SolveInfo()
+        info.res_history = C.cast(hist, C.POINTER(C.c_double))
+        st = self._check(self.lib.fsi_solve_extension(self.h, C.c_void_p(_ptr(g)), C.c_void_p(_ptr(u)), C.byref(o),
+                                                      C.byref(info)),
+                         allow=(FSI_OK, FSI_NOT_CONVERGED))
+        out = dict(status=STATUS_NAMES[st], iters=info.iters, rel_res=info.final_rel_res, time_ms=info.time_ms,
+                   history=[hist[k] for k in range(info.n_hist)])
+        return u, out
 
     def raw_status(self, name: str, *args) -> int:
         """Call a C entry point and return its status without raising (error-path tests)."""
