@@ -20,6 +20,10 @@ Inputs are resident in HBM before the timed region.  `value` is the FP64
 vmult throughput N_vel / t_apply in GDoF/s; the solve times, their ratio
 and the mixed-vs-FP64 velocity difference are reported beside it.
 
+After the timed steps (not part of them): the pseudo-elastic extension solve
+on the same mesh (flexible CG + multigrid on A with c_m = 0, eta = mu_A / 2,
+to 1e-6), FP64 and FP32 V-cycle, reported under "extension".
+
 Prints one JSON line (rank 0, N = 1 only: this build targets one GPU).
 """
 from __future__ import annotations
@@ -78,6 +82,41 @@ def load_counter_profile(workload: str):
     return d
 
 
+def extension_measure(name, mesh, d_disp, fsi, W, np, torch, rtol: float = 1e-6, reps: int = 3):
+    """The pseudo-elastic extension on the same warped mesh (mu_A law, seeded wall data):
+    flexible CG + multigrid to rtol 1e-6 (the paper's extension criterion), FP64 and FP32
+    V-cycle, each after one untimed solve; median of ``reps`` timed solves."""
+    ext = W.make_extension_inputs(name, mesh)
+    ectx = fsi.Context.from_mesh(mesh)
+    ectx.set_displacement(d_disp)
+    for j in range(ectx.n_levels):
+        mu = torch.from_numpy(ext.mu[j]).cuda()
+        ectx.set_coefficients(j, torch.zeros_like(mu), 0.5 * mu)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ectx.setup()
+    torch.cuda.synchronize()
+    setup_ms = 1e3 * (time.perf_counter() - t0)
+    g = torch.from_numpy(ext.g).cuda()
+    res = {}
+    sol = {}
+    for label, prec in (("fp64", 0), ("mixed", 1)):
+        ectx.set_mg_params(precision=prec)
+        ectx.solve_extension(g, rtol=rtol, max_iter=200)
+        times = []
+        for _ in range(reps):
+            u, info = ectx.solve_extension(g, rtol=rtol, max_iter=200)
+            times.append(info["time_ms"])
+        sol[label] = u
+        res[label] = dict(ms=round(float(np.median(times)), 2), iters=info["iters"], rel_res=info["rel_res"],
+                          status=info["status"])
+    diff = float(torch.linalg.vector_norm(sol["mixed"] - sol["fp64"]) / torch.linalg.vector_norm(sol["fp64"]))
+    return {"rtol": rtol, "setup_ms": round(setup_ms, 1), "fp64": res["fp64"], "mixed": res["mixed"],
+            "speedup_mixed_vs_fp64": round(res["fp64"]["ms"] / res["mixed"]["ms"], 3),
+            "rel_diff_mixed_vs_fp64": diff,
+            "first_solve_builds_coarse_inverse": True}
+
+
 def cpu_baseline(seconds: float = 12.0):
     """The CPU oracle's A-apply (CSR SpMV, scipy) timed on a bounded sample."""
     import numpy as np
@@ -116,6 +155,7 @@ def main():
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extension", action="store_true", help="skip the extension-solve measurement")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
 
@@ -286,6 +326,9 @@ def main():
         },
         "flops": flops,
     }
+    if not args.no_extension:
+        _log("[bench] extension solve")
+        out["extension"] = extension_measure(name, mesh, d_disp, fsi, W, np, torch)
     if not args.no_cpu_baseline:
         _log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
