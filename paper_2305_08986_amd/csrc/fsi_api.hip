@@ -424,6 +424,11 @@ static fsi_status run_vcycle(Context* ctx, hipStream_t s) {
 
 static fsi_status capture_graphs(Context* ctx) {
     for (int pi = 0; pi < 2; ++pi) {
+        // the extension graphs hold launch shapes too: recaptured at their next use
+        if (ctx->ext_graph_valid[pi]) {
+            hipGraphExecDestroy(ctx->ext_graph[pi]);
+            ctx->ext_graph_valid[pi] = false;
+        }
         if (ctx->graph_valid[pi]) {
             hipGraphExecDestroy(ctx->graph[pi]);
             ctx->graph_valid[pi] = false;
@@ -583,11 +588,16 @@ static fsi_status check_level(Context* ctx, int level) {
 static fsi_status invalidate(Context* ctx) {
     ctx->setup_done = false;
     ctx->ext_ready = false;
-    for (int pi = 0; pi < 2; ++pi)
+    for (int pi = 0; pi < 2; ++pi) {
         if (ctx->graph_valid[pi]) {
             hipGraphExecDestroy(ctx->graph[pi]);
             ctx->graph_valid[pi] = false;
         }
+        if (ctx->ext_graph_valid[pi]) {
+            hipGraphExecDestroy(ctx->ext_graph[pi]);
+            ctx->ext_graph_valid[pi] = false;
+        }
+    }
     return FSI_OK;
 }
 
@@ -721,6 +731,38 @@ static void ext_precondition(Context* ctx, const double* r, double* z, hipStream
     launch_cast<double, T>(z, W.x_u, nv, s);
 }
 
+// the extension preconditioner on the fixed CG buffers r -> z: captured once per
+// precision and launch configuration (fused, tuned, vertex geometry), then replayed
+static fsi_status ext_run_precond(Context* ctx, const double* r, double* z, hipStream_t s) {
+    const int pi = ctx->prm.precision == FSI_PREC_MIXED ? 1 : 0;
+    if (!ctx->prm.use_graph) {
+        if (pi) ext_precondition<float>(ctx, r, z, s);
+        else ext_precondition<double>(ctx, r, z, s);
+        return FSI_OK;
+    }
+    const int key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0);
+    if (!ctx->ext_graph_valid[pi] || ctx->ext_graph_key[pi] != key) {
+        if (ctx->ext_graph_valid[pi]) {
+            hipGraphExecDestroy(ctx->ext_graph[pi]);
+            ctx->ext_graph_valid[pi] = false;
+        }
+        hipStream_t cs;
+        FSI_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t g;
+        FSI_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        if (pi) ext_precondition<float>(ctx, r, z, cs);
+        else ext_precondition<double>(ctx, r, z, cs);
+        FSI_HIP_TRY(hipStreamEndCapture(cs, &g));
+        FSI_HIP_TRY(hipGraphInstantiate(&ctx->ext_graph[pi], g, nullptr, nullptr, 0));
+        hipGraphDestroy(g);
+        hipStreamDestroy(cs);
+        ctx->ext_graph_valid[pi] = true;
+        ctx->ext_graph_key[pi] = key;
+    }
+    FSI_HIP_TRY(hipGraphLaunch(ctx->ext_graph[pi], s));
+    return FSI_OK;
+}
+
 }  // namespace fsi
 
 using namespace fsi;
@@ -803,8 +845,10 @@ void fsi_destroy(fsi_ctx* h) {
     if (!h) return;
     Context* ctx = &h->c;
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
-    for (int pi = 0; pi < 2; ++pi)
+    for (int pi = 0; pi < 2; ++pi) {
         if (ctx->graph_valid[pi]) hipGraphExecDestroy(ctx->graph[pi]);
+        if (ctx->ext_graph_valid[pi]) hipGraphExecDestroy(ctx->ext_graph[pi]);
+    }
     for (void* p : ctx->allocations) hipFree(p);
     if (ctx->h_flag) hipHostFree(ctx->h_flag);
     if (ctx->h_dbl) hipHostFree(ctx->h_dbl);
@@ -1271,11 +1315,6 @@ fsi_status fsi_solve_extension(fsi_ctx* h, const double* g, double* u, const fsi
     double* pd = zo + nv;
     double* q = pd + nv;
     double* gw = q + nv;
-    const bool mixed = ctx->prm.precision == FSI_PREC_MIXED;
-    auto precond = [&](const double* rr, double* zz) {
-        if (mixed) ext_precondition<float>(ctx, rr, zz, s);
-        else ext_precondition<double>(ctx, rr, zz, s);
-    };
     // boundary data on the walls (gw) and the interior initial guess (x, walls zero)
     launch_fill<double>(gw, 0.0, nv, s);
     launch_dirichlet_copy<double>(L, g, gw, s);
@@ -1330,7 +1369,7 @@ fsi_status fsi_solve_extension(fsi_ctx* h, const double* g, double* u, const fsi
     int it = 0;
     fsi_status status = FSI_OK;
     if (rel > o->rtol && o->max_iter > 0) {
-        precond(r, z);
+        TRY(ext_run_precond(ctx, r, z, s));
         double rz;
         TRY(dot64(ctx, r, z, nv, &rz));
         FSI_HIP_TRY(hipMemcpyAsync(pd, z, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
@@ -1350,9 +1389,10 @@ fsi_status fsi_solve_extension(fsi_ctx* h, const double* g, double* u, const fsi
             ++it;
             push_hist(rel);
             if (rel <= o->rtol) break;
-            // flexible (Polak-Ribiere) beta: the preconditioner may vary between calls
-            std::swap(z, zo);
-            precond(r, z);
+            // flexible (Polak-Ribiere) beta: the preconditioner may vary between calls;
+            // the preconditioner always writes the same buffer (the captured graph's)
+            FSI_HIP_TRY(hipMemcpyAsync(zo, z, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
+            TRY(ext_run_precond(ctx, r, z, s));
             double rz_new, rzo;
             TRY(dot64(ctx, r, z, nv, &rz_new));
             TRY(dot64(ctx, r, zo, nv, &rzo));

@@ -203,6 +203,10 @@ struct Context {
     bool ext_ready = false;
     uint4* d_info_free = nullptr;
     double* ext_buf = nullptr;     // 8 finest-level velocity vectors
+    // the extension preconditioner (r -> z on fixed CG buffers) as a graph per precision
+    hipGraphExec_t ext_graph[2] = {nullptr, nullptr};
+    bool ext_graph_valid[2] = {false, false};
+    int ext_graph_key[2] = {-1, -1};
     double* d_scratch = nullptr;   // general scratch (partials, flags)
     int* d_flag = nullptr;
     int* h_flag = nullptr;         // pinned

@@ -134,3 +134,20 @@ def test_extension_degenerate_and_error_cases():
     st = ctx2.raw_status("fsi_solve_extension", C.c_void_p(g.data_ptr()), C.c_void_p(g.clone().data_ptr()),
                          C.byref(o), None)
     assert st == fsi.FSI_ERR_STATE
+
+
+def test_extension_graph_replays_equal_eager():
+    """The captured extension preconditioner replayed over several solves, with eager
+    work in between, gives the eager solve's result in both precisions."""
+    wl, ext, ctx = _ext_ctx("T3_R")
+    g = torch.from_numpy(ext.g).cuda()
+    for prec in (0, 1):
+        ctx.set_mg_params(precision=prec, use_graph=0)
+        ue, ie = ctx.solve_extension(g, rtol=1e-10)
+        ctx.set_mg_params(use_graph=1)
+        for rep in range(3):
+            ug, ig = ctx.solve_extension(g, rtol=1e-10)
+            ctx.apply_A(ctx.n_levels - 1, ug)          # eager work between the replays
+            torch.cuda.synchronize()
+            assert ig["iters"] == ie["iters"], (prec, rep)
+            assert float((ug - ue).abs().max()) <= 1e-14 * float(ue.abs().max()), (prec, rep)
