@@ -300,6 +300,55 @@ def element_matrices(J: np.ndarray, c_mass: np.ndarray, eta: np.ndarray, ref: Re
     return A, B
 
 
+def convection_matrices(J: np.ndarray, vconv: np.ndarray, rho: float, r: np.ndarray, ref: Reference):
+    """Element matrices of the corrector-mode terms on every cell of the batch.
+
+    With the semi-implicit advection of the corrector mode (Sec. 3.1.1: v* is the
+    unknown, v° the known convective velocity) the form a_j gains
+    (rho (grad v) v°, w), and the streamline term of Sec. 3.2 adds
+    sum_K int_K r (v° . grad v)(v° . grad w):
+
+      N_K[(a,i),(b,j)] = d_ab sum_q w_q det J_q rho phi_i (v° . grad phi_j)
+      S_K[(a,i),(b,j)] = d_ab sum_q w_q det J_q r_q (v° . grad phi_i)(v° . grad phi_j)
+
+    vconv [nc][Q][dim]: v° at the points; r [nc][Q]: the stabilisation parameter.
+    Returns N_K + S_K, component-major like ``element_matrices``.
+    """
+    dim = ref.dim
+    Jinv, wdet = geometry_factors(J, ref)
+    G = np.einsum("cqbx,qib->cqix", Jinv, ref.dphi)
+    vg = np.einsum("cqx,cqix->cqi", vconv, G)                 # v° . grad phi_i
+    conv = rho * np.einsum("cq,qi,cqj->cij", wdet, ref.phi, vg)
+    stab = np.einsum("cq,cqi,cqj->cij", wdet * r, vg, vg)
+    nc, nl = J.shape[0], ref.phi.shape[1]
+    C = np.zeros((nc, dim, nl, dim, nl))
+    for a in range(dim):
+        C[:, a, :, a, :] = conv + stab
+    return C.reshape(nc, dim * nl, dim * nl)
+
+
+def assemble_convection(box: "Box", J: np.ndarray, vconv: np.ndarray, rho: float, r: np.ndarray,
+                        ref: "Reference", chunk: int = 2048) -> sp.csr_matrix:
+    """Global velocity-block matrix of the corrector-mode terms; Dirichlet rows and
+    columns are zero, so A + C keeps the identity rows of ``assemble``."""
+    rows, cols, vals = [], [], []
+    nc = box.n_cells
+    for s0 in range(0, nc, chunk):
+        cs = np.arange(s0, min(nc, s0 + chunk))
+        CK = convection_matrices(J[cs], vconv[cs], rho, r[cs], ref)
+        gd = _global_vel_dofs(box, box.cell_vel_nodes(cs))
+        n = gd.shape[1]
+        rows.append(np.repeat(gd, n, axis=1).ravel())
+        cols.append(np.tile(gd, (1, n)).ravel())
+        vals.append(CK.ravel())
+    nv = box.n_vel
+    Cm = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(nv, nv)).tocsr()
+    free = sp.diags((~box.dirichlet_vel_dofs()).astype(float))
+    Cm = (free @ Cm @ free).tocsr()
+    Cm.eliminate_zeros()
+    return Cm
+
+
 # ---------------------------------------------------------------- assembly
 @dataclass
 class Operator:
@@ -372,11 +421,12 @@ def assemble_unconstrained(box: Box, J, c_mass, eta, ref: Reference) -> Operator
 # ---------------------------------------------------------------- sampled rows (large meshes)
 def apply_rows(box: Box, disp: np.ndarray, c_mass: np.ndarray, eta: np.ndarray,
                ref: Reference, u: np.ndarray, p: Optional[np.ndarray],
-               vel_dofs: Sequence[int], p_dofs: Sequence[int]):
+               vel_dofs: Sequence[int], p_dofs: Sequence[int], conv=None):
     """Selected entries of (A u + B^T p, B u) evaluated cell by cell.
 
     Only the cells touching the requested rows are integrated, so this works at
-    any mesh size.  Dirichlet handling matches ``assemble``.
+    any mesh size.  Dirichlet handling matches ``assemble``.  ``conv`` =
+    (vconv, rho, r) adds the corrector-mode terms of ``convection_matrices`` to A.
     """
     dm = box.dirichlet_vel_dofs()
     uf = np.where(dm, 0.0, u)
@@ -396,6 +446,9 @@ def apply_rows(box: Box, disp: np.ndarray, c_mass: np.ndarray, eta: np.ndarray,
     pos = {c: i for i, c in enumerate(cells)}
     J = jacobians_q1(box, disp, ref, cells)
     AK, BK = element_matrices(J, c_mass[cells], eta[cells], ref)
+    if conv is not None:
+        vconv, rho, r = conv
+        AK = AK + convection_matrices(J, vconv[cells], rho, r[cells], ref)
     gd = _global_vel_dofs(box, box.cell_vel_nodes(cells))
     gp = box.cell_p_nodes(cells)
     ov = np.zeros(len(vel_dofs))

@@ -343,6 +343,50 @@ def make_extension_inputs(name: str, mesh: MeshDesc, seed: int = BASE_SEED, amp:
     return ExtensionInputs(mu=mu, g=np.ascontiguousarray(g.ravel()))
 
 
+# ---------------------------------------------------------------- corrector-mode inputs
+# The corrector mode of Sec. 3.1.1 adds rho (grad v) v° (v° the known convective
+# velocity) and the streamline term r (v° . grad v)(v° . grad w) of Sec. 3.2.  Inputs:
+# v° per point, a smooth seeded field; rho of the fluid; r per cell from the Peclet
+# law of Sec. 3.2 with the cell's reference diameter h_K, max |v°| over its points,
+# its mean eta and p1 = 2, and r = 0 where Pe_K < 1.
+CONV_STREAM = 9
+RHO_FLUID = 1.0e3
+
+
+@dataclasses.dataclass
+class ConvectionInputs:
+    vconv: np.ndarray      # [n_cells][Q][dim]
+    r: np.ndarray          # [n_cells][Q]
+    rho: float
+
+
+def make_convection_inputs(name: str, mesh: MeshDesc, level: int, eta: np.ndarray, seed: int = BASE_SEED,
+                           speed: float = 1.0, rho: float = RHO_FLUID) -> ConvectionInputs:
+    """v° = speed * (1/4) sum_m e_m sin(2 pi k_m . X/extent + phi_m) at the reference
+    points (draw order: the four sine modes from PCG64 ``[seed, config, CONV_STREAM]``),
+    and the streamline parameter per cell (Pe_K = |v°| h_K / (2 eta p1),
+    r = h_K / (2 |v°| p1) (coth Pe_K - 1 / Pe_K), zero where Pe_K < 1)."""
+    rng = np.random.default_rng([seed, CONFIG_INDEX[name], CONV_STREAM])
+    k, phi, e = _sine_modes(rng, mesh.dim)
+    X = qpoint_ref_coords(mesh, level)                       # [nc][Q][dim]
+    Xt = X / np.asarray(mesh.extent, dtype=float)
+    v = np.zeros_like(X)
+    for m in range(4):
+        v += np.sin(2.0 * math.pi * (Xt @ k[m]) + phi[m])[..., None] * e[m]
+    v *= 0.25 * speed
+    cells = mesh.cells(level)
+    hK = math.sqrt(sum((mesh.extent[d] / cells[d]) ** 2 for d in range(mesh.dim)))
+    vmax = np.sqrt((v ** 2).sum(axis=-1)).max(axis=1)        # per cell
+    mu = eta.mean(axis=1)
+    p1 = 2.0
+    pe = vmax * hK / (2.0 * mu * p1)
+    r = np.zeros_like(pe)
+    on = pe >= 1.0
+    r[on] = hK / (2.0 * vmax[on] * p1) * (1.0 / np.tanh(pe[on]) - 1.0 / pe[on])
+    return ConvectionInputs(vconv=np.ascontiguousarray(v), r=np.ascontiguousarray(np.repeat(r[:, None], X.shape[1], 1)),
+                            rho=float(rho))
+
+
 def inject_displacement(mesh: MeshDesc, disp_fine: np.ndarray, level: int) -> np.ndarray:
     """Vertex displacement of ``level``: the fine values at the coarse vertices."""
     J = mesh.n_levels - 1

@@ -103,3 +103,33 @@ def test_planted_extension_mistake_is_caught(kind, monkeypatch):
         except AssertionError:
             caught += 1
     assert caught >= 1, kind
+
+
+# ---------------------------------------------------------------- corrector-mode terms
+_orig_conv = fem.convection_matrices
+
+
+def _conv_transposed(J, vconv, rho, r, ref):
+    """the convection term with trial and test functions swapped"""
+    C = _orig_conv(J, vconv, rho, 0.0 * r, ref)
+    S = _orig_conv(J, vconv, 0.0, r, ref)
+    return np.swapaxes(C, 1, 2) + S
+
+
+def _conv_stab_dropped_cross(J, vconv, rho, r, ref):
+    """the streamline term built from the squared components only"""
+    C = _orig_conv(J, vconv, rho, 0.0 * r, ref)
+    S = sum(_orig_conv(J, vconv * (np.arange(3) == d), 0.0, r, ref) for d in range(3))
+    return C + S
+
+
+@pytest.mark.parametrize("fn", [_conv_transposed, _conv_stab_dropped_cross])
+def test_planted_convection_mistake_is_caught(fn, monkeypatch):
+    monkeypatch.setattr(fem, "convection_matrices", fn)
+    caught = 0
+    for pin in (pins.test_convection_matrices_closed_form, pins.test_convection_skew_and_streamline_psd_on_closed_box):
+        try:
+            pin()
+        except AssertionError:
+            caught += 1
+    assert caught >= 1, fn.__doc__

@@ -630,3 +630,50 @@ def test_extension_minimises_the_energy_with_variable_mu():
         assert abs(first) <= 1e-9 * np.sqrt(e0 * second), (first, e0, second)
     # the zero extension of the boundary data has more energy
     assert E(np.where(dm, ext.g, 0.0)) > e0
+
+
+# ---------------------------------------------------------------- corrector-mode terms
+def test_convection_matrices_closed_form():
+    """One affine cell, constant v° in the x-y plane and constant r: the convection and
+    streamline matrices are sums of Kronecker products of the 1D closed forms."""
+    h = (0.5, 0.3, 0.7)
+    rho, r = 1.7, 0.4
+    ref = fem.Reference(3)
+    box = fem.Box(3, (1, 1, 1), h, 0)
+    J = fem.jacobians_q1(box, np.zeros((3, box.n_p)), ref)
+    M = [M1(t) for t in h]
+    K = [K1(t) for t in h]
+    k3 = lambda a, b, c: np.kron(c, np.kron(b, a))       # x fastest
+    n = 27
+    for vx, vy in ((0.8, 0.0), (0.0, -0.6), (0.8, -0.5)):
+        vconv = np.tile(np.array([vx, vy, 0.0]), (1, 27, 1))
+        C = fem.convection_matrices(J, vconv, rho, np.full((1, 27), r), ref)[0]
+        conv = rho * (vx * k3(C1.T, M[1], M[2]) + vy * k3(M[0], C1.T, M[2]))
+        stab = r * (vx * vx * k3(K[0], M[1], M[2]) + vy * vy * k3(M[0], K[1], M[2])
+                    + vx * vy * (k3(C1, C1.T, M[2]) + k3(C1.T, C1, M[2])))
+        want = conv + stab
+        for a in range(3):
+            for b in range(3):
+                blk = C[a * n:(a + 1) * n, b * n:(b + 1) * n]
+                ref_blk = want if a == b else np.zeros_like(want)
+                assert np.allclose(blk, ref_blk, rtol=0, atol=1e-14 * np.abs(want).max()), (vx, vy, a, b)
+
+
+def test_convection_skew_and_streamline_psd_on_closed_box():
+    """Constant (divergence-free) v° on an affinely mapped box with every wall Dirichlet:
+    (v° . grad u, w) + (v° . grad w, u) is a boundary integral, so the interior block of
+    the convection matrix is skew-symmetric; the streamline matrix is symmetric positive
+    semi-definite."""
+    box = fem.Box(3, (3, 2, 4), (1.2, 0.6, 1.0), 63)
+    ref = fem.Reference(3)
+    J = fem.jacobians_q1(box, np.zeros((3, box.n_p)), ref)
+    v = np.array([0.3, -0.7, 0.5])
+    vconv = np.tile(v, (box.n_cells, 27, 1))
+    zero = np.zeros((box.n_cells, 27))
+    I = np.nonzero(~box.dirichlet_vel_dofs())[0]
+    N = fem.assemble_convection(box, J, vconv, 2.0, zero, ref)[I][:, I].toarray()
+    assert np.abs(N).max() > 1e-3
+    assert np.abs(N + N.T).max() <= 1e-13 * np.abs(N).max()
+    S = fem.assemble_convection(box, J, vconv, 0.0, np.full_like(zero, 0.3), ref)[I][:, I].toarray()
+    assert np.abs(S - S.T).max() <= 1e-13 * np.abs(S).max()
+    assert np.linalg.eigvalsh(0.5 * (S + S.T)).min() >= -1e-12 * np.abs(S).max()
