@@ -193,6 +193,29 @@ fsi_status fsi_apply_BT_f32(fsi_ctx* ctx, int level, const float* p, float* v);
 fsi_status fsi_apply_stokes_f32(fsi_ctx* ctx, int level, const float* u, const float* p,
                                 float* v, float* q);
 
+/* Corrector-mode terms (3D): with the semi-implicit advection of the corrector
+ * mode (Sec. 3.1.1: the form a_j with v* the unknown and v° known) and the
+ * streamline term of Sec. 3.2, the velocity block becomes
+ *   a(u, w) + (rho (grad u) v°, w) + sum_K (r (v° . grad u), (v° . grad w))_K.
+ * vconv: device [N_c][Q][3] FP64, v° at the quadrature points (physical
+ * components); r: device [N_c][Q] FP64, the streamline parameter (>= 0, e.g. the
+ * Peclet law of Sec. 3.2, constant per cell); rho >= 0 the density.  Cells and
+ * points as for fsi_set_coefficients.  Needs the level's geometry; a later
+ * geometry change clears the terms (set them again).  Copies on the stream and
+ * synchronises.  Errors: FSI_ERR_ARG (2D mesh, bad level or rho), FSI_ERR_STATE
+ * (no geometry), FSI_ERR_NONFINITE (non-finite input or r < 0). */
+fsi_status fsi_set_convection(fsi_ctx* ctx, int level, const double* vconv, const double* r, double rho);
+/* Corrector-mode Stokes apply on one level: v = (A + N + S) u + B^T p, q = B u,
+ * with N the convection and S the streamline term set by fsi_set_convection
+ * (Dirichlet rows act as identity, Dirichlet columns are zero, as for
+ * fsi_apply_stokes).  FP64 and FP32 twin; layouts and errors as fsi_apply_stokes,
+ * FSI_ERR_STATE without fsi_set_convection.  The V-cycle and the solve stay in
+ * predictor mode. */
+fsi_status fsi_apply_corrector(fsi_ctx* ctx, int level, const double* u, const double* p,
+                               double* v, double* q);
+fsi_status fsi_apply_corrector_f32(fsi_ctx* ctx, int level, const float* u, const float* p,
+                                   float* v, float* q);
+
 /* One application of the preconditioner: n V-cycles (Sec. 4) on the finest
  * level from a zero initial guess, in the configured precision.  FP64 in and
  * out; casts are internal.  Requires fsi_setup. */
@@ -244,7 +267,8 @@ fsi_status fsi_set_tuning(fsi_ctx* ctx, int level, int precision, int variant);
 /* Measurement support: runs `reps` applications of the level operator
  * (mode bits 1 = A, 2 = B^T, 4 = B; 7 = fused Stokes; 9 = A with the fused
  * Chebyshev epilogue, run with zero coefficients; 23 = Stokes with the fused
- * residual epilogue) in the given precision on
+ * residual epilogue; 33 = A and 39 = Stokes with the corrector terms, after
+ * fsi_set_convection) in the given precision on
  * internal work vectors, timing every launch of the cell kernel with HIP events
  * on the context's stream, after three untimed warm-up applications.
  * kernel_us = cell-kernel time of one application (sum over its n_launches

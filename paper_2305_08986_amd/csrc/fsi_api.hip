@@ -896,6 +896,7 @@ fsi_status fsi_set_jacobians(fsi_ctx* h, int level, const double* J) {
     L.vgeo_avail = L.vgeo = false;   // arbitrary per-point Jacobians: stored geometry only
     TRY(sync_flag(ctx, FSI_ERR_INVERTED_CELL, "det J <= 0 (or not finite) at a quadrature point"));
     L.geo_set = true;
+    L.conv_set = false;   // beta = K v° follows the geometry
     return FSI_OK;
 }
 
@@ -919,7 +920,10 @@ fsi_status fsi_set_displacement(fsi_ctx* h, const double* disp) {
         L.vgeo = L.vgeo_avail && ctx->prm.vertex_geometry;
     }
     TRY(sync_flag(ctx, FSI_ERR_INVERTED_CELL, "det J <= 0 (or not finite) at a quadrature point"));
-    for (int j = 0; j <= J; ++j) ctx->lv[j].geo_set = true;
+    for (int j = 0; j <= J; ++j) {
+        ctx->lv[j].geo_set = true;
+        ctx->lv[j].conv_set = false;   // beta = K v° follows the geometry
+    }
     return FSI_OK;
 }
 
@@ -1087,6 +1091,56 @@ fsi_status fsi_apply_stokes_f32(fsi_ctx* h, int level, const float* u, const flo
     TRY(p_scratch(ctx, level, &a, &b));
     launch_cast<double, float>(a, p, ctx->lv[level].np, ctx->stream);
     op_apply<float>(ctx, level, OP_A | OP_BT | OP_B, u, a, v, b, ctx->stream);
+    launch_cast<float, double>(q, b, ctx->lv[level].np, ctx->stream);
+    return FSI_OK;
+}
+
+fsi_status fsi_set_convection(fsi_ctx* h, int level, const double* vconv, const double* r, double rho) {
+    if (!h || !vconv || !r) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    TRY(check_level(ctx, level));
+    Level& L = ctx->lv[level];
+    if (L.dim != 3) return fail(ctx, FSI_ERR_ARG, "fsi_set_convection: the corrector terms are 3D only");
+    if (!(rho >= 0.0) || !std::isfinite(rho)) return fail(ctx, FSI_ERR_ARG, "fsi_set_convection: rho must be >= 0");
+    if (!L.geo_set) return fail(ctx, FSI_ERR_STATE, "fsi_set_convection before the level's geometry");
+    const int64_t P = L.plane();
+    if (!L.d_cb64) {
+        TRY(dalloc(ctx, &L.d_cb64, 3 * P));
+        TRY(dalloc(ctx, &L.d_cs64, P));
+        TRY(dalloc(ctx, &L.d_cb32, 3 * P));
+        TRY(dalloc(ctx, &L.d_cs32, P));
+    }
+    launch_fill<int>(ctx->d_flag, 0, 1, ctx->stream);
+    launch_convection(L, vconv, r, L.d_cb64, L.d_cs64, L.d_cb32, L.d_cs32, ctx->d_flag, ctx->stream);
+    L.conv_set = false;
+    TRY(sync_flag(ctx, FSI_ERR_NONFINITE, "convective velocity or streamline parameter not finite, or r < 0"));
+    L.rho = rho;
+    L.conv_set = true;
+    return FSI_OK;
+}
+
+static fsi_status conv_check(Context* ctx, int level) {
+    TRY(apply_check(ctx, level, true));
+    if (!ctx->lv[level].conv_set) return fail(ctx, FSI_ERR_STATE, "corrector apply before fsi_set_convection");
+    return FSI_OK;
+}
+
+fsi_status fsi_apply_corrector(fsi_ctx* h, int level, const double* u, const double* p, double* v, double* q) {
+    if (!h || !u || !p || !v || !q) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    TRY(conv_check(ctx, level));
+    op_apply<double>(ctx, level, OP_A | OP_BT | OP_B | OP_CONV, u, p, v, q, ctx->stream);
+    return FSI_OK;
+}
+
+fsi_status fsi_apply_corrector_f32(fsi_ctx* h, int level, const float* u, const float* p, float* v, float* q) {
+    if (!h || !u || !p || !v || !q) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    TRY(conv_check(ctx, level));
+    double *a, *b;
+    TRY(p_scratch(ctx, level, &a, &b));
+    launch_cast<double, float>(a, p, ctx->lv[level].np, ctx->stream);
+    op_apply<float>(ctx, level, OP_A | OP_BT | OP_B | OP_CONV, u, a, v, b, ctx->stream);
     launch_cast<float, double>(q, b, ctx->lv[level].np, ctx->stream);
     return FSI_OK;
 }
@@ -1503,11 +1557,13 @@ fsi_status fsi_autotune(fsi_ctx* h) {
 fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int reps, double* kernel_us,
                              double* op_us, int* n_launches) {
     const bool fused_mode = mode == (OP_A | OP_CHEB) || mode == (OP_A | OP_BT | OP_B | OP_RES);
+    const bool conv_mode = mode == (OP_A | OP_CONV) || mode == (OP_A | OP_BT | OP_B | OP_CONV);
     if (!h || !kernel_us || !op_us || !n_launches || reps < 1 || (precision != 0 && precision != 1) ||
-        ((mode < 1 || mode > 7) && !fused_mode))
+        ((mode < 1 || mode > 7) && !fused_mode && !conv_mode))
         return FSI_ERR_ARG;
     Context* ctx = &h->c;
     TRY(apply_check(ctx, level, (mode & OP_A) != 0));
+    if (conv_mode) TRY(conv_check(ctx, level));
     TRY(alloc_work<double>(ctx));
     TRY(alloc_work<float>(ctx));
     const Level& L = ctx->lv[level];

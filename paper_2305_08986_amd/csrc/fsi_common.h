@@ -57,7 +57,9 @@ __host__ __device__ inline int64_t geo_off(const GeoLayout& g, int qx, int64_t c
 // operator mode bits of the cell kernel; OP_CHEB (with OP_A) and OP_RES (with
 // OP_A | OP_BT | OP_B) replace the plain store at a node's last touch by a
 // Chebyshev update of the iterate or by the residual f - M u
-enum : int { OP_A = 1, OP_BT = 2, OP_B = 4, OP_CHEB = 8, OP_RES = 16 };
+// OP_CONV (with OP_A, 3D) adds the corrector-mode terms: convection rho (grad u) v° and
+// the streamline term r (v° . grad u)(v° . grad w)
+enum : int { OP_A = 1, OP_BT = 2, OP_B = 4, OP_CHEB = 8, OP_RES = 16, OP_CONV = 32 };
 
 // ---------------------------------------------------------------- error helpers
 #define FSI_HIP_TRY(expr)                                                          \
@@ -123,6 +125,14 @@ struct Level {
     // point (2 eta, c_m) in the geometry layout; valid after fsi_set_displacement
     float4* d_vd32 = nullptr;
     float* d_cq32 = nullptr;
+    // corrector-mode terms per point in the geometry layout: beta = K v° (3 planes,
+    // K = det(J) w J^{-1}) and sigma = r / (det J w) (1 plane); rho is the density
+    double* d_cb64 = nullptr;
+    double* d_cs64 = nullptr;
+    float* d_cb32 = nullptr;
+    float* d_cs32 = nullptr;
+    bool conv_set = false;
+    double rho = 0.0;
     bool vgeo_avail = false;          // geometry came from vertex displacements (3D)
     bool vgeo = false;                // ... and the FP32 kernels use it
     double h[3] = {1.0, 1.0, 1.0};    // reference cell sizes
@@ -350,6 +360,8 @@ void launch_xpby_host(const double* x, double b, double* y, int64_t n, hipStream
 template <typename T>
 void launch_add(T* x, const T* y, int64_t n, hipStream_t s);                              // x += y
 void launch_clear_wall_bits(const uint4* in, uint4* out, int64_t n, hipStream_t s);
+void launch_convection(const Level& L, const double* vconv, const double* r, double* cb64, double* cs64, float* cb32,
+                       float* cs32, int* flag, hipStream_t s);
 template <typename T>
 void launch_coarse_apply_u(const Coarse& U, const Level& L, const T* f_u, T* x_u, hipStream_t s);
 void launch_scale_host(double a, const double* x, double* y, int64_t n, hipStream_t s);

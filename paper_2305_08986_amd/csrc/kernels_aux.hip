@@ -221,6 +221,36 @@ __global__ void k_coefficients(int dim, int64_t nc, int Q, GeoLayout geo, int64_
     }
 }
 
+// corrector-mode terms: per point (lexicographic cell, point) beta_b = sum_e K[b][e] v°_e
+// and sigma = r / (det J w), written into the geometry layout in FP64 and FP32
+__global__ void k_convection(int64_t nc, int Q, GeoLayout geo, int64_t plane, const int* __restrict__ lex2col,
+                             const double* __restrict__ vconv, const double* __restrict__ r,
+                             const double* __restrict__ K64, const double* __restrict__ cw,
+                             double* __restrict__ cb64, double* __restrict__ cs64, float* __restrict__ cb32,
+                             float* __restrict__ cs32, int* flag) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nc * Q) return;
+    const int64_t cell = id / Q;
+    const int q = (int)(id - cell * Q);
+    const int64_t off = geo_off(geo, q % 3, lex2col[cell], q / 3);
+    const double v0 = vconv[3 * id], v1 = vconv[3 * id + 1], v2 = vconv[3 * id + 2], rr = r[id];
+    if (!isfinite(v0) || !isfinite(v1) || !isfinite(v2) || !isfinite(rr) || !(rr >= 0.0)) flag[0] = 1;
+    for (int b = 0; b < 3; ++b) {
+        const double be = K64[(3 * b) * plane + off] * v0 + K64[(3 * b + 1) * plane + off] * v1 +
+                          K64[(3 * b + 2) * plane + off] * v2;
+        cb64[b * plane + off] = be;
+        cb32[b * plane + off] = (float)be;
+    }
+    const double sg = rr / cw[off];
+    cs64[off] = sg;
+    cs32[off] = (float)sg;
+}
+void launch_convection(const Level& L, const double* vconv, const double* r, double* cb64, double* cs64, float* cb32,
+                       float* cs32, int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_convection, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, L.nc, L.Q, L.geo, L.plane(),
+                       L.d_lex2col, vconv, r, L.d_K64, L.d_cw64, cb64, cs64, cb32, cs32, flag);
+}
+
 void launch_coefficients(const Level& L, const double* cm, const double* eta, const double* cw, double* cv64,
                          float* cv32, float* cq32, const double* K64, double* Ks64, float* Ks32, int* flag,
                          hipStream_t s) {

@@ -94,6 +94,11 @@ struct CellArgs {
     const float4* __restrict__ vd;
     const T* __restrict__ cq;
     T hx, hy, hz;
+    // corrector-mode terms (OP_CONV): beta = K v° (3 planes) and sigma = r / (det J w)
+    // in the geometry layout, and the density
+    const T* __restrict__ cb;
+    const T* __restrict__ cs;
+    T rho;
 };
 
 // ============================================================== 3D
@@ -115,7 +120,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     constexpr bool HAS_A = (MODE & OP_A) != 0;
     constexpr bool CHEB = (MODE & OP_CHEB) != 0;
     constexpr bool RES = (MODE & OP_RES) != 0;
+    constexpr bool CONV = (MODE & OP_CONV) != 0;
     static_assert(!CHEB || MODE == (OP_A | OP_CHEB), "the Chebyshev epilogue goes with A alone");
+    static_assert(!CONV || (MODE == (OP_A | OP_CONV) || MODE == (OP_A | OP_BT | OP_B | OP_CONV)),
+                  "the corrector terms go with A or the Stokes apply");
+    static_assert(!CONV || !VG, "the corrector terms use the stored geometry");
     static_assert(!RES || MODE == (OP_A | OP_BT | OP_B | OP_RES), "the residual epilogue goes with the Stokes apply");
     static_assert(!VG || sizeof(T) == 4, "geometry from vertices is the FP32 path");
     // A alone reads K' = sqrt(cvisc) K (no cvisc plane): sym(grad-hat u K') K'^T = cvisc sym(H) K^T
@@ -294,7 +303,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         // point-by-point accumulation of the backward x-sweep needs fewer live registers;
         // FP64 always uses it, FP32 for the Stokes modes (A + B^T [+ B]), whose extra
         // pressure state would otherwise halve the wavefronts per SIMD
-        constexpr bool PERQX = sizeof(T) == 8 || (HAS_A && HAS_BT && !VG);
+        constexpr bool PERQX = sizeof(T) == 8 || (HAS_A && HAS_BT && !VG) || CONV;
         if constexpr (PERQX) {
         // accumulate the backward x-sweep point by point (fewer live registers)
 #pragma unroll
@@ -308,6 +317,13 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             for (int e = 0; e < 9; ++e) Kq[e] = act ? gload<NTL>(a.K + e * P + off) : T(0);
             const T cvq = SCALED ? T(1) : ((HAS_A && act) ? gload<NTL>(a.cv + off) : T(0));
             const T cmq = (HAS_A && act) ? gload<NTL>(a.cv + P + off) : T(0);
+            // corrector terms: with beta = K v°, (grad-hat u_c) . beta = det(J) w (v° . grad u_c)
+            T be[3] = {T(0), T(0), T(0)}, sg = T(0), cvc[3] = {T(0), T(0), T(0)};
+            if constexpr (CONV) {
+#pragma unroll
+                for (int b = 0; b < 3; ++b) be[b] = act ? gload<NTL>(a.cb + b * P + off) : T(0);
+                sg = act ? gload<NTL>(a.cs + off) : T(0);
+            }
             T Tm[3][3];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
@@ -329,6 +345,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
 #pragma unroll
                     for (int e = 0; e < 3; ++e) H[c][e] = d0 * Kq[e] + d1 * Kq[3 + e] + d2 * Kq[6 + e];
                     if constexpr (HAS_A) Fv[c] = cmq * vv;
+                    if constexpr (CONV) {
+                        cvc[c] = d0 * be[0] + d1 * be[1] + d2 * be[2];
+                        Fv[c] += a.rho * cvc[c];      // rho (v° . grad u_c) det(J) w, tested with phi
+                    }
                 }
                 if constexpr (HAS_B) {
                     const T dv = H[0][0] + H[1][1] + H[2][2];
@@ -358,9 +378,16 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     // F[c][b] = sum_e Tm[c][e] K[b][e]
-                    const T F0 = Tm[c][0] * Kq[0] + Tm[c][1] * Kq[1] + Tm[c][2] * Kq[2];
-                    const T F1 = Tm[c][0] * Kq[3] + Tm[c][1] * Kq[4] + Tm[c][2] * Kq[5];
-                    const T F2 = Tm[c][0] * Kq[6] + Tm[c][1] * Kq[7] + Tm[c][2] * Kq[8];
+                    T F0 = Tm[c][0] * Kq[0] + Tm[c][1] * Kq[1] + Tm[c][2] * Kq[2];
+                    T F1 = Tm[c][0] * Kq[3] + Tm[c][1] * Kq[4] + Tm[c][2] * Kq[5];
+                    T F2 = Tm[c][0] * Kq[6] + Tm[c][1] * Kq[7] + Tm[c][2] * Kq[8];
+                    if constexpr (CONV) {
+                        // streamline term, tested with (grad-hat w_c) . beta / (det J w)
+                        const T st = sg * cvc[c];
+                        F0 += st * be[0];
+                        F1 += st * be[1];
+                        F2 += st * be[2];
+                    }
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
                         wa[c][i] += cS<T>(qx, i) * Fv[c] + cD<T>(qx, i) * F0;
@@ -995,7 +1022,9 @@ static void launch_one(const Level& L, const CellArgs<T>& args, hipStream_t s) {
     if (L.dim == 3) {
         constexpr bool RS = WPB > 1;
         const int64_t grid = args.nrows;   // one workgroup per row
-        if constexpr (sizeof(T) == 4) {
+        // the corrector terms use the stored geometry, also where the FP32 applies form it
+        // from the vertices
+        if constexpr (sizeof(T) == 4 && (MODE & OP_CONV) == 0) {
             if (args.vd) {
                 hipLaunchKernelGGL((cell3d<T, MODE, WPB, RS, NTL, WPE, true>), dim3((unsigned)grid), dim3(64 * WPB), 0,
                                    s, args);
@@ -1004,7 +1033,7 @@ static void launch_one(const Level& L, const CellArgs<T>& args, hipStream_t s) {
         }
         hipLaunchKernelGGL((cell3d<T, MODE, WPB, RS, NTL, WPE, false>), dim3((unsigned)grid), dim3(64 * WPB), 0, s,
                            args);
-    } else {
+    } else if constexpr ((MODE & OP_CONV) == 0) {   // the corrector terms are 3D only
         constexpr int W2 = WPB > 1 ? 2 : 1;   // 2D: one row per wavefront, at most two
         const int64_t grid = (args.nrows + W2 - 1) / W2;   // one wavefront per row of cells
         hipLaunchKernelGGL((cell2d<T, MODE, W2, false, NTL>), dim3((unsigned)grid), dim3(64 * W2), 0, s, args);
@@ -1059,6 +1088,14 @@ static CellArgs<T> phase_args(const Level& L, int phase, const T* K, const T* cv
     args.pmap = L.d_pmap;
     args.K = K;
     args.cv = cv;
+    if constexpr (sizeof(T) == 8) {
+        args.cb = L.d_cb64;
+        args.cs = L.d_cs64;
+    } else {
+        args.cb = L.d_cb32;
+        args.cs = L.d_cs32;
+    }
+    args.rho = (T)L.rho;
     if constexpr (sizeof(T) == 4) {
         if (L.vgeo && L.dim == 3) {
             args.vd = L.d_vd32;
@@ -1084,6 +1121,8 @@ void launch_cell(const Level& L, int mode, int variant, int phase, const T* K, c
         case OP_B: launch_mode<T, OP_B>(L, variant, args, s); break;
         case OP_BT: launch_mode<T, OP_BT>(L, variant, args, s); break;
         case OP_A | OP_BT: launch_mode<T, OP_A | OP_BT>(L, variant, args, s); break;
+        case OP_A | OP_CONV: launch_mode<T, OP_A | OP_CONV>(L, variant, args, s); break;
+        case OP_A | OP_BT | OP_B | OP_CONV: launch_mode<T, OP_A | OP_BT | OP_B | OP_CONV>(L, variant, args, s); break;
         default: launch_mode<T, OP_A | OP_BT | OP_B>(L, variant, args, s); break;
     }
 }

@@ -96,6 +96,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fsi_apply_B_f32": (i, [vp, i, vp, vp]),
         "fsi_apply_BT_f32": (i, [vp, i, vp, vp]),
         "fsi_apply_stokes_f32": (i, [vp, i, vp, vp, vp, vp]),
+        "fsi_set_convection": (i, [vp, i, vp, vp, C.c_double]),
+        "fsi_apply_corrector": (i, [vp, i, vp, vp, vp, vp]),
+        "fsi_apply_corrector_f32": (i, [vp, i, vp, vp, vp, vp]),
         "fsi_vcycle": (i, [vp, vp, vp, vp, vp]),
         "fsi_solve": (i, [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
         "fsi_solve_extension": (i, [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
@@ -204,6 +207,14 @@ class Context:
         self._check(self.lib.fsi_set_coefficients(self.h, level, C.c_void_p(_ptr(cm)), C.c_void_p(_ptr(et))))
         self.stream.synchronize()
 
+    def set_convection(self, level: int, vconv, r, rho: float):
+        """Corrector-mode terms on a level (fsi_set_convection): v° [n_cells][Q][3], r [n_cells][Q]."""
+        vc = self._dev64(vconv)
+        rr = self._dev64(r)
+        self._check(self.lib.fsi_set_convection(self.h, level, C.c_void_p(_ptr(vc)), C.c_void_p(_ptr(rr)),
+                                                float(rho)))
+        self.stream.synchronize()
+
     def set_mg_params(self, **kw):
         p = MGParams()
         self.lib.fsi_default_mg_params(C.byref(p))
@@ -273,6 +284,17 @@ class Context:
         v = out_v if out_v is not None else self._out(s["n_vel"], u.dtype)
         q = out_q if out_q is not None else self._out(s["n_p"], u.dtype)
         fn = self.lib.fsi_apply_stokes_f32 if f32 else self.lib.fsi_apply_stokes
+        self._check(fn(self.h, level, C.c_void_p(_ptr(u)), C.c_void_p(_ptr(p)), C.c_void_p(_ptr(v)),
+                       C.c_void_p(_ptr(q))))
+        return v, q
+
+    def apply_corrector(self, level, u, p, out_v=None, out_q=None):
+        """Stokes apply with the corrector-mode terms (fsi_apply_corrector[_f32])."""
+        s = self.sizes(level)
+        f32 = u.dtype == self.torch.float32
+        v = out_v if out_v is not None else self._out(s["n_vel"], u.dtype)
+        q = out_q if out_q is not None else self._out(s["n_p"], u.dtype)
+        fn = self.lib.fsi_apply_corrector_f32 if f32 else self.lib.fsi_apply_corrector
         self._check(fn(self.h, level, C.c_void_p(_ptr(u)), C.c_void_p(_ptr(p)), C.c_void_p(_ptr(v)),
                        C.c_void_p(_ptr(q))))
         return v, q

@@ -14,7 +14,7 @@ import argparse
 import json
 import sys
 
-MODES = {"A": 1, "BT": 2, "B": 4, "stokes": 7, "cheb": 9, "res": 23}
+MODES = {"A": 1, "BT": 2, "B": 4, "stokes": 7, "cheb": 9, "res": 23, "convA": 33, "conv": 39}
 
 
 def main(argv=None):
@@ -55,6 +55,9 @@ def main(argv=None):
     ctx = fsi.Context.from_mesh(wl.mesh)
     fsi.setup_workload(ctx, wl)
     lev = ctx.n_levels - 1 if a.level < 0 else a.level
+    if MODES[a.mode] & 32:
+        c = W.make_convection_inputs(a.workload, wl.mesh, lev, wl.eta[lev])
+        ctx.set_convection(lev, c.vconv, c.r, c.rho)
     precs = [{"fp64": 0, "fp32": 1}[x] for x in a.prec.split(",")]
     variants = [int(v) for v in a.variant.split(",")] if a.variant else [None]
     if not a.no_autotune and variants == [None]:

@@ -1,0 +1,151 @@
+"""GPU parity of the corrector-mode Stokes apply (convection and streamline terms,
+Sec. 3.1.1 and 3.2) against the assembled oracle, through the C ABI.
+
+FP64 within 1e-12 (normwise and entrywise against the largest entry), FP32 within
+1e-5; every launch variant gives bitwise the same result; 128^3 sampled rows in the
+autotuned launch shapes; error cases.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from oracle import fem
+from paper_2305_08986_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _setup(name):
+    from paper_2305_08986_amd import fsi
+    wl = W.make_workload(name)
+    ctx = fsi.Context.from_mesh(wl.mesh)
+    fsi.setup_workload(ctx, wl)
+    conv = {}
+    for j in range(ctx.n_levels):
+        c = W.make_convection_inputs(name, wl.mesh, j, wl.eta[j])
+        ctx.set_convection(j, c.vconv, c.r, c.rho)
+        conv[j] = c
+    return wl, ctx, conv
+
+
+def _oracle(wl, j, c, u, p):
+    box = fem.level_box(wl.mesh, j)
+    ref = fem.Reference(3)
+    Jq = fem.jacobians_q1(box, W.inject_displacement(wl.mesh, wl.disp, j), ref)
+    op = fem.assemble(box, Jq, wl.c_mass[j], wl.eta[j], ref)
+    Cm = fem.assemble_convection(box, Jq, c.vconv, c.rho, c.r, ref)
+    return (op.A + Cm) @ u + op.B.T @ p, op.B @ u, op
+
+
+def _cmp(got, want, tol, what):
+    got = got.cpu().double().numpy()
+    nrm = np.linalg.norm(got - want) / np.linalg.norm(want)
+    ent = np.abs(got - want).max() / np.abs(want).max()
+    print(f"{what}: normwise {nrm:.2e} entrywise {ent:.2e}")
+    assert nrm <= tol and ent <= tol, (what, nrm, ent)
+
+
+@pytest.mark.parametrize("name", ["T3_R", "T3_8", "T3_4"])
+def test_corrector_apply_matches_oracle(name):
+    wl, ctx, conv = _setup(name)
+    rng = np.random.default_rng([61, len(name)])
+    for j in sorted({ctx.n_levels - 1, ctx.n_levels - 2}):
+        box = fem.level_box(wl.mesh, j)
+        u = rng.uniform(-1, 1, box.n_vel)
+        p = rng.uniform(-1, 1, box.n_p)
+        rv, rq, op = _oracle(wl, j, conv[j], u, p)
+        # the corrector terms change the result (streamline term active somewhere)
+        assert np.abs(rv - op.apply_stokes(u, p)[0]).max() > 1e-6 * np.abs(rv).max()
+        v, q = ctx.apply_corrector(j, torch.from_numpy(u).cuda(), torch.from_numpy(p).cuda())
+        _cmp(v, rv, 1e-12, f"{name} L{j} v")
+        _cmp(q, rq, 1e-12, f"{name} L{j} q")
+        u32 = torch.from_numpy(u).float().cuda()
+        p32 = torch.from_numpy(p).float().cuda()
+        rv32, rq32, _ = _oracle(wl, j, conv[j], u32.double().cpu().numpy(), p32.double().cpu().numpy())
+        v, q = ctx.apply_corrector(j, u32, p32)
+        _cmp(v, rv32, 1e-5, f"{name} L{j} v f32")
+        _cmp(q, rq32, 1e-5, f"{name} L{j} q f32")
+
+
+def test_corrector_every_launch_variant_same_result():
+    wl, ctx, conv = _setup("T3_R")
+    ctx.set_mg_params(tuned=1)
+    j = ctx.n_levels - 1
+    box = fem.level_box(wl.mesh, j)
+    rng = np.random.default_rng(67)
+    u = torch.from_numpy(rng.uniform(-1, 1, box.n_vel)).cuda()
+    p = torch.from_numpy(rng.uniform(-1, 1, box.n_p)).cuda()
+    base = None
+    for var in range(12):
+        for prec in (0, 1):
+            ctx.set_tuning(j, prec, var)
+        got = [t.cpu().numpy() for t in ctx.apply_corrector(j, u, p)]
+        got += [t.cpu().numpy() for t in ctx.apply_corrector(j, u.float(), p.float())]
+        if base is None:
+            base = got
+        for g, b in zip(got, base):
+            assert np.array_equal(g, b), var
+
+
+def test_corrector_full_size_sampled_rows():
+    """128^3 warped box: sampled rows of the corrector apply (tuned launches) against the
+    oracle's cell-by-cell evaluation with the same terms."""
+    from paper_2305_08986_amd import fsi
+    wl = W.make_workload("C3")
+    ctx = fsi.Context.from_mesh(wl.mesh)
+    fsi.setup_workload(ctx, wl)
+    ctx.setup()
+    ctx.autotune()
+    J = ctx.n_levels - 1
+    c = W.make_convection_inputs("C3", wl.mesh, J, wl.eta[J])
+    assert (c.r > 0).any()
+    ctx.set_convection(J, c.vconv, c.r, c.rho)
+    box = fem.level_box(wl.mesh, J)
+    rng = np.random.default_rng(71)
+    u = rng.uniform(-1, 1, box.n_vel)
+    p = rng.uniform(-1, 1, box.n_p)
+    # rows of cells with an active streamline term, and random rows
+    act = np.nonzero(c.r[:, 0] > 0)[0]
+    cells = rng.choice(act, 20, replace=False)
+    rows = np.unique(np.concatenate([box.cell_vel_nodes(cells)[:, 13] + k * box.n_vel_nodes for k in range(3)]
+                                    + [rng.choice(box.n_vel, 60, replace=False)]))
+    prow = rng.choice(box.n_p, 30, replace=False)
+    rv, rq = fem.apply_rows(box, wl.disp, wl.c_mass[J], wl.eta[J], fem.Reference(3), u, p, rows, prow,
+                            conv=(c.vconv, c.rho, c.r))
+    v, q = ctx.apply_corrector(J, torch.from_numpy(u).cuda(), torch.from_numpy(p).cuda())
+    ev = np.abs(v.cpu().numpy()[rows] - rv).max() / np.abs(rv).max()
+    eq = np.abs(q.cpu().numpy()[prow] - rq).max() / np.abs(rq).max()
+    assert ev <= 1e-12 and eq <= 1e-12, (ev, eq)
+
+
+def test_corrector_error_cases():
+    from paper_2305_08986_amd import fsi
+    wl = W.make_workload("T3_4")
+    ctx = fsi.Context.from_mesh(wl.mesh)
+    fsi.setup_workload(ctx, wl)
+    J = ctx.n_levels - 1
+    box = fem.level_box(wl.mesh, J)
+    u = torch.zeros(box.n_vel, dtype=torch.float64, device="cuda")
+    p = torch.zeros(box.n_p, dtype=torch.float64, device="cuda")
+    with pytest.raises(fsi.FSIError):
+        ctx.apply_corrector(J, u, p)                      # no convection set
+    c = W.make_convection_inputs("T3_4", wl.mesh, J, wl.eta[J])
+    with pytest.raises(fsi.FSIError):
+        ctx.set_convection(J, c.vconv, c.r, -1.0)          # rho < 0
+    bad = c.r.copy()
+    bad[0, 0] = -1.0
+    with pytest.raises(fsi.FSIError):
+        ctx.set_convection(J, c.vconv, bad, c.rho)         # r < 0
+    ctx.set_convection(J, c.vconv, c.r, c.rho)
+    ctx.apply_corrector(J, u, p)
+    ctx.set_displacement(wl.disp)                          # new geometry clears the terms
+    with pytest.raises(fsi.FSIError):
+        ctx.apply_corrector(J, u, p)
+    wl2 = W.make_workload("T2_R")
+    ctx2 = fsi.Context.from_mesh(wl2.mesh)
+    fsi.setup_workload(ctx2, wl2)
+    n2 = wl2.eta[-1].shape[0]
+    with pytest.raises(fsi.FSIError):
+        ctx2.set_convection(ctx2.n_levels - 1, np.zeros((n2, 9, 3)), np.zeros((n2, 9)), 1.0)
