@@ -139,6 +139,27 @@ def minres1(apply_S: Callable, ds_inv: np.ndarray, r: np.ndarray):
     return beta * z, y, beta
 
 
+def bicgstab1(apply_S: Callable, ds_inv: np.ndarray, r: np.ndarray):
+    """One right-preconditioned BiCGStab iteration from zero with P = D_S^{-1} (the
+    corrector mode's ChebBiCGStab(1, 1) of Sec. 4: one Chebyshev step on the diagonal is
+    a scaled Jacobi step, and BiCGStab is invariant to that scale).
+
+    r_0 = r, shadow residual r_0; p = P r_0, v = S p, alpha = <r_0, r_0>/<r_0, v>;
+    s = r_0 - alpha v, q = P s, t = S q, omega = <t, s>/<t, t> (0 if t = 0);
+    x = alpha p + omega q.
+    Returns (x, p, q, alpha, omega) so callers can reuse A^{-1} B^T p and A^{-1} B^T q.
+    """
+    p = ds_inv * r
+    v = apply_S(p)
+    alpha = float(r @ r) / float(r @ v)
+    s_ = r - alpha * v
+    q = ds_inv * s_
+    t = apply_S(q)
+    tt = float(t @ t)
+    omega = float(t @ s_) / tt if tt > 0.0 else 0.0     # s = 0: the first half-step solved it
+    return alpha * p + omega * q, p, q, alpha, omega
+
+
 # ---------------------------------------------------------------- block smoother
 def block_smoother(ainv: Callable, sinv: Callable, B, r_u: np.ndarray, r_p: np.ndarray):
     """K_j = [[Ah, B^T], [B, B Ah^{-1} B^T - Sh]]^{-1} applied to (r_u, r_p).
@@ -211,6 +232,7 @@ class MGParams:
     cheb_upper: float = 1.2
     cheb_ratio: float = 20.0
     n_eig: int = 12
+    schur: str = "minres"      # "bicgstab" in the corrector mode (Sec. 4)
 
 
 class Hierarchy:
@@ -245,7 +267,10 @@ class Hierarchy:
         lv = self.levels[j]
         B = lv.op.B
         ainv = lambda r: self.cheb(j, r)
-        sinv = lambda t: minres1(lambda z: B @ ainv(B.T @ z), lv.dS_inv, t)[0]
+        if self.params.schur == "bicgstab":
+            sinv = lambda t: bicgstab1(lambda z: B @ ainv(B.T @ z), lv.dS_inv, t)[0]
+        else:
+            sinv = lambda t: minres1(lambda z: B @ ainv(B.T @ z), lv.dS_inv, t)[0]
         return block_smoother(ainv, sinv, B, r_u, r_p)
 
     def restrict(self, j: int, r_u: np.ndarray, r_p: np.ndarray):
@@ -414,6 +439,23 @@ def build_levels(mesh, disp_fine: np.ndarray, c_mass: list, eta: list, ref: Opti
         dj = inject_displacement(mesh, disp_fine, j)
         J = fem.jacobians_q1(box, dj, ref)
         ops.append(fem.assemble(box, J, c_mass[j], eta[j], ref))
+    return ops
+
+
+def build_levels_corrector(mesh, disp_fine: np.ndarray, c_mass: list, eta: list, conv: list,
+                           ref: Optional[fem.Reference] = None):
+    """Levels of the corrector mode: A + N + S with the convection and streamline terms
+    of ``fem.convection_matrices``; conv[j] = (vconv, rho, r) of level j."""
+    from paper_2305_08986_amd.workloads import inject_displacement   # input layout only
+    ref = ref or fem.Reference(mesh.dim)
+    ops = []
+    for j in range(mesh.n_levels):
+        box = fem.level_box(mesh, j)
+        Jq = fem.jacobians_q1(box, inject_displacement(mesh, disp_fine, j), ref)
+        op = fem.assemble(box, Jq, c_mass[j], eta[j], ref)
+        vconv, rho, r = conv[j]
+        op.A = (op.A + fem.assemble_convection(box, Jq, vconv, rho, r, ref)).tocsr()
+        ops.append(op)
     return ops
 
 

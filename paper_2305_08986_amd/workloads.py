@@ -346,11 +346,13 @@ def make_extension_inputs(name: str, mesh: MeshDesc, seed: int = BASE_SEED, amp:
 # ---------------------------------------------------------------- corrector-mode inputs
 # The corrector mode of Sec. 3.1.1 adds rho (grad v) v° (v° the known convective
 # velocity) and the streamline term r (v° . grad v)(v° . grad w) of Sec. 3.2.  Inputs:
-# v° per point, a smooth seeded field; rho of the fluid; r per cell from the Peclet
-# law of Sec. 3.2 with the cell's reference diameter h_K, max |v°| over its points,
-# its mean eta and p1 = 2, and r = 0 where Pe_K < 1.
+# v° per point, a smooth seeded field; rho consistent with the workloads' mass
+# coefficient c_m = rho / (gamma tau) = 1e2 (second-order BDF, gamma = 2/3, and the time
+# step tau = 0.005 of the 3D test); r per cell from the Peclet law of Sec. 3.2 with the
+# cell's reference diameter h_K, max |v°| over its points, its mean eta and p1 = 2, and
+# r = 0 where Pe_K < 1.
 CONV_STREAM = 9
-RHO_FLUID = 1.0e3
+RHO_FLUID = 1.0e2 * (2.0 / 3.0) * 0.005
 
 
 @dataclasses.dataclass

@@ -677,3 +677,51 @@ def test_convection_skew_and_streamline_psd_on_closed_box():
     S = fem.assemble_convection(box, J, vconv, 0.0, np.full_like(zero, 0.3), ref)[I][:, I].toarray()
     assert np.abs(S - S.T).max() <= 1e-13 * np.abs(S).max()
     assert np.linalg.eigvalsh(0.5 * (S + S.T)).min() >= -1e-12 * np.abs(S).max()
+
+
+# ---------------------------------------------------------------- BiCGStab Schur step
+def test_bicgstab1_properties():
+    """One BiCGStab step: the final residual is orthogonal to t = S P s (omega minimises
+    ||s - omega t||), the half-step residual is orthogonal to the shadow residual r_0,
+    the result does not depend on the scale of the Jacobi preconditioner, and an exact
+    (scaled) preconditioner solves in the first half-step."""
+    from oracle import solvers
+    rng = np.random.default_rng(73)
+    n = 12
+    S = np.eye(n) * 4 + rng.uniform(-1, 1, (n, n))          # nonsymmetric, well conditioned
+    d = rng.uniform(1, 3, n)
+    r = rng.uniform(-1, 1, n)
+    x, p, q, alpha, omega = solvers.bicgstab1(lambda z: S @ z, 1.0 / d, r)
+    v = S @ p
+    s_ = r - alpha * v
+    assert abs(r @ s_) <= 1e-12 * np.linalg.norm(r) * np.linalg.norm(s_)
+    t = S @ q
+    res = r - S @ x
+    assert np.allclose(res, s_ - omega * t, atol=1e-13)
+    assert abs(t @ res) <= 1e-12 * np.linalg.norm(t) * np.linalg.norm(res)
+    assert np.linalg.norm(res) < np.linalg.norm(r)
+    x3 = solvers.bicgstab1(lambda z: S @ z, 3.0 / d, r)[0]
+    assert np.allclose(x3, x, rtol=1e-12, atol=1e-14)
+    c = 2.5
+    xe = solvers.bicgstab1(lambda z: c * d * z, 1.0 / d, r)[0]
+    assert np.allclose(xe, r / (c * d), rtol=1e-13)
+
+
+def test_corrector_hierarchy_solves_the_nonsymmetric_system():
+    """Corrector mode (A + N + S on every level, k_A = 6, BiCGStab Schur step) as the
+    FGMRES preconditioner reaches the direct solution of the nonsymmetric system."""
+    from oracle import solvers
+    wl = W.make_workload("T3_4")
+    conv = []
+    for j in range(wl.mesh.n_levels):
+        c = W.make_convection_inputs("T3_4", wl.mesh, j, wl.eta[j])
+        conv.append((c.vconv, c.rho, c.r))
+    ops = solvers.build_levels_corrector(wl.mesh, wl.disp, wl.c_mass, wl.eta, conv)
+    A = ops[-1].A
+    assert abs(A - A.T).max() > 1e-8 * abs(A).max()          # really nonsymmetric
+    h = solvers.Hierarchy(ops, solvers.MGParams(k_A=6, schur="bicgstab"))
+    res = solvers.solve_stokes(h, wl.g_u, wl.g_p, rtol=1e-10)
+    u, p = solvers.direct_solve(ops[-1], wl.g_u, wl.g_p)
+    nv = ops[-1].box.n_vel
+    assert res.converged and res.iters < 40
+    assert np.linalg.norm(res.x[:nv] - u) / np.linalg.norm(u) <= 1e-8
