@@ -98,6 +98,13 @@ typedef struct {
                                 reading the stored values; 0: stored values (default).  FP64
                                 kernels always read the stored values.  Switching needs no new
                                 setup. */
+    int corrector;           /* 1: corrector mode (Sec. 3.1.1, Sec. 4; 3D): every level's velocity
+                                block is A + N + S with the terms of fsi_set_convection (needed on
+                                every level before fsi_setup), the Schur step is one BiCGStab
+                                iteration (ChebBiCGStab(1, 1)) instead of MINRES, the fused
+                                epilogues are not used; set k_A = 6 for Table 4's corrector
+                                column.  0: predictor mode (default).  Changing it needs a new
+                                setup. */
 } fsi_mg_params;
 
 typedef struct {

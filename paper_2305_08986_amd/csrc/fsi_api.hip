@@ -271,7 +271,9 @@ static fsi_status alloc_work(Context* ctx) {
         TRY(dalloc(ctx, &w.r_p, L.np));
         TRY(dalloc(ctx, &w.t_p, L.np));
         TRY(dalloc(ctx, &w.z_p, L.np));
-        TRY(dalloc(ctx, &w.dots, 2));
+        TRY(dalloc(ctx, &w.b_p, L.np));
+        TRY(dalloc(ctx, &w.s_p, L.np));
+        TRY(dalloc(ctx, &w.dots, 4));
         TRY(dalloc(ctx, &w.partials, 2 * kReduceBlocks));
     }
     return FSI_OK;
@@ -282,6 +284,11 @@ static int variant_of(const Context* ctx, int prec, int level, int mode) {
     const auto& v = ctx->tune_variant[prec];
     const size_t k = (size_t)level * kTuneClasses + tune_class(mode);
     return k < v.size() ? v[k] : 0;
+}
+
+// the solver's velocity block: A, or in the corrector mode A + N + S
+static int solver_mode(const Context* ctx, int mode) {
+    return (ctx->prm.corrector && (mode & OP_A)) ? (mode | OP_CONV) : mode;
 }
 
 // ---------------------------------------------------------------- operators
@@ -310,13 +317,13 @@ static void cheb(Context* ctx, int j, const T* r, T* x, hipStream_t s) {
         const double c1 = rn * rho, c2 = 2.0 * rn / delta;
         // the first direction is the first iterate; the last step needs no direction
         const bool first = i == 1, store_d = i + 1 < ctx->prm.k_A;
-        if (ctx->prm.fused && (!ctx->prm.tuned || ctx->fuse_cheb[prec_index<T>()][j])) {
+        if (ctx->prm.fused && !ctx->prm.corrector && (!ctx->prm.tuned || ctx->fuse_cheb[prec_index<T>()][j])) {
             // the update happens at each node's last touch
             launch_cell_cheb_all<T>(L, variant_of(ctx, prec_index<T>(), j, OP_A | OP_CHEB), Kmode<T>(L, OP_A | OP_CHEB),
                                     CVp<T>(L), x, W.cd_u, r, DAp<T>(L), W.cax_u, c1, c2, first, store_d, s);
             launch_dirichlet_cheb<T>(L, x, W.cd_u, r, DAp<T>(L), c1, c2, first, store_d, s);
         } else {
-            op_apply<T>(ctx, j, OP_A, x, nullptr, W.cax_u, nullptr, s);
+            op_apply<T>(ctx, j, solver_mode(ctx, OP_A), x, nullptr, W.cax_u, nullptr, s);
             launch_cheb_step<T>(DAp<T>(L), r, W.cax_u, x, W.cd_u, c1, c2, first, store_d, L.nv, s);
         }
         rho = rn;
@@ -333,6 +340,27 @@ static void smoother(Context* ctx, int j, const T* r_u, const double* r_p, T* x_
     LevelWork<T>& W = works<T>(ctx)[j];
     cheb<T>(ctx, j, r_u, W.w_u, s);
     op_apply<T>(ctx, j, OP_B, W.w_u, nullptr, nullptr, W.t_p, s);
+    if (ctx->prm.corrector) {
+        // ChebBiCGStab(1, 1): one right-preconditioned BiCGStab iteration from zero on
+        // S y = b, b = B w - r_p, P = D_S^{-1}; Ah^{-1} B^T y = alpha t1 + omega t2 by
+        // linearity.  t2 lives in W.r_u, free once w is formed.
+        T* t1 = W.v_u;
+        T* t2 = W.r_u;
+        launch_bicg_start(L.d_dSinv, W.t_p, r_p, W.b_p, W.z_p, L.np, s);           // b, p
+        op_apply<T>(ctx, j, OP_BT, nullptr, W.z_p, W.tu, nullptr, s);
+        cheb<T>(ctx, j, W.tu, t1, s);
+        op_apply<T>(ctx, j, OP_B, t1, nullptr, nullptr, W.t_p, s);                  // v = S p
+        launch_dot<double>(W.b_p, W.b_p, L.np, W.partials, W.dots, s);
+        launch_dot<double>(W.b_p, W.t_p, L.np, W.partials, W.dots + 1, s);
+        launch_bicg_mid(L.d_dSinv, W.dots, W.t_p, W.b_p, W.s_p, L.np, s);          // s, q
+        op_apply<T>(ctx, j, OP_BT, nullptr, W.s_p, W.tu, nullptr, s);
+        cheb<T>(ctx, j, W.tu, t2, s);
+        op_apply<T>(ctx, j, OP_B, t2, nullptr, nullptr, W.t_p, s);                  // t = S q
+        launch_dot<double>(W.t_p, W.b_p, L.np, W.partials, W.dots + 2, s);
+        launch_dot<double>(W.t_p, W.t_p, L.np, W.partials, W.dots + 3, s);
+        launch_bicg_update<T>(W.w_u, t1, t2, W.z_p, W.s_p, W.dots, x_u, x_p, L.nv, L.np, first, s);
+        return;
+    }
     launch_schur_z(L.d_dSinv, W.t_p, r_p, W.z_p, L.np, s);
     op_apply<T>(ctx, j, OP_BT, nullptr, W.z_p, W.tu, nullptr, s);
     cheb<T>(ctx, j, W.tu, W.v_u, s);
@@ -346,14 +374,14 @@ template <typename T>
 static void residual(Context* ctx, int j, hipStream_t s) {
     const Level& L = ctx->lv[j];
     LevelWork<T>& W = works<T>(ctx)[j];
-    if (ctx->prm.fused && (!ctx->prm.tuned || ctx->fuse_res[prec_index<T>()][j])) {
+    if (ctx->prm.fused && !ctx->prm.corrector && (!ctx->prm.tuned || ctx->fuse_res[prec_index<T>()][j])) {
         launch_cell_res_all<T>(L, variant_of(ctx, prec_index<T>(), j, OP_A | OP_BT | OP_B | OP_RES), Kp<T>(L),
                                CVp<T>(L), W.x_u, W.x_p, W.f_u,
                                W.f_p, W.r_u, W.r_p, s);
         launch_dirichlet_res<T>(L, W.f_u, W.x_u, W.r_u, s);
         return;
     }
-    op_apply<T>(ctx, j, OP_A | OP_BT | OP_B, W.x_u, W.x_p, W.r_u, W.r_p, s);
+    op_apply<T>(ctx, j, solver_mode(ctx, OP_A | OP_BT | OP_B), W.x_u, W.x_p, W.r_u, W.r_p, s);
     launch_sub<T>(W.f_u, W.r_u, W.r_u, L.nv, s);
     launch_sub<double>(W.f_p, W.r_p, W.r_p, L.np, s);
 }
@@ -410,7 +438,7 @@ static fsi_status capture_graphs(Context* ctx);
 
 static fsi_status run_vcycle(Context* ctx, hipStream_t s) {
     const int pi = ctx->prm.precision == FSI_PREC_MIXED ? 1 : 0;
-    const int key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0);
+    const int key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0) | (ctx->prm.corrector ? 8 : 0);
     if (ctx->prm.use_graph && ctx->graph_valid[pi] && ctx->graph_key != key) TRY(capture_graphs(ctx));
     if (ctx->prm.use_graph && ctx->graph_valid[pi]) {
         FSI_HIP_TRY(hipGraphLaunch(ctx->graph[pi], s));
@@ -448,7 +476,7 @@ static fsi_status capture_graphs(Context* ctx) {
         ctx->graph_valid[pi] = true;
     }
     hipStreamDestroy(cs);
-    ctx->graph_key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0);
+    ctx->graph_key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0) | (ctx->prm.corrector ? 8 : 0);
     return FSI_OK;
 }
 
@@ -518,7 +546,7 @@ static fsi_status lanczos(Context* ctx, int j) {
     double beta = 0.0;
     for (int it = 0; it < ctx->prm.n_eig; ++it) {
         launch_mul(sA, v, tmp, L.nv, s);
-        op_apply<double>(ctx, j, OP_A, tmp, nullptr, w, nullptr, s);
+        op_apply<double>(ctx, j, solver_mode(ctx, OP_A), tmp, nullptr, w, nullptr, s);
         launch_mul(sA, w, w, L.nv, s);
         double alpha;
         TRY(dot64(ctx, w, v, L.nv, &alpha));
@@ -572,7 +600,7 @@ static fsi_status setup_coarse(Context* ctx) {
         FSI_HIP_TRY(hipMemcpyAsync(C.d_uidx, uidx.data(), sizeof(int) * nf, hipMemcpyHostToDevice, s));
     FSI_HIP_TRY(hipMemcpyAsync(C.d_vrow, vrow.data(), sizeof(int) * L.nv, hipMemcpyHostToDevice, s));
     launch_fill<double>(C.d_inv64, 0.0, n * n, s);
-    launch_coarse_assemble_impl(L, L.d_K64, L.d_cv64, C.d_vrow, nf, C.d_inv64, n, s);
+    launch_coarse_assemble_impl(L, L.d_K64, L.d_cv64, C.d_vrow, nf, C.d_inv64, n, s, ctx->prm.corrector != 0);
     launch_fill<int>(ctx->d_flag, 0, 1, s);
     launch_gj(C.d_inv64, n, C.d_piv, C.d_piv + n, C.d_col, C.d_tmp, ctx->d_flag, s);
     launch_cast<float, double>(C.d_inv32, C.d_inv64, n * n, s);
@@ -628,7 +656,7 @@ static fsi_status ensure_krylov(Context* ctx, int restart) {
 static void stokes_combined(Context* ctx, const double* x, double* y, hipStream_t s) {
     const int J = ctx->nlev - 1;
     const Level& L = ctx->lv[J];
-    op_apply<double>(ctx, J, OP_A | OP_BT | OP_B, x, x + L.nv, y, y + L.nv, s);
+    op_apply<double>(ctx, J, solver_mode(ctx, OP_A | OP_BT | OP_B), x, x + L.nv, y, y + L.nv, s);
 }
 
 static fsi_status precond_combined(Context* ctx, const double* r, double* z, hipStream_t s) {
@@ -740,7 +768,7 @@ static fsi_status ext_run_precond(Context* ctx, const double* r, double* z, hipS
         else ext_precondition<double>(ctx, r, z, s);
         return FSI_OK;
     }
-    const int key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0);
+    const int key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0) | (ctx->prm.corrector ? 8 : 0);
     if (!ctx->ext_graph_valid[pi] || ctx->ext_graph_key[pi] != key) {
         if (ctx->ext_graph_valid[pi]) {
             hipGraphExecDestroy(ctx->ext_graph[pi]);
@@ -785,6 +813,7 @@ void fsi_default_mg_params(fsi_mg_params* p) {
     p->fused = 1;
     p->tuned = 1;
     p->vertex_geometry = 0;   // measured slower than the stored values on MI355X
+    p->corrector = 0;
 }
 
 fsi_status fsi_create(fsi_ctx** out, const fsi_mesh_desc* m, void* hip_stream) {
@@ -947,12 +976,13 @@ fsi_status fsi_set_mg_params(fsi_ctx* h, const fsi_mg_params* p) {
     if (!h || !p) return FSI_ERR_ARG;
     Context* ctx = &h->c;
     if (p->k_A < 1 || p->m < 0 || p->n_cycles < 1 || p->k_S != 1 || p->n_S != 1 || !(p->cheb_upper > 0) ||
-        !(p->cheb_ratio > 1) || p->n_eig < 1 || (p->precision != FSI_PREC_FP64 && p->precision != FSI_PREC_MIXED))
+        !(p->cheb_ratio > 1) || p->n_eig < 1 || (p->precision != FSI_PREC_FP64 && p->precision != FSI_PREC_MIXED) ||
+        (p->corrector != 0 && p->corrector != 1))
         return fail(ctx, FSI_ERR_ARG, "invalid multigrid parameters (only k_S = n_S = 1 are implemented)");
     const fsi_mg_params& o = ctx->prm;
     // precision and graph use select among already prepared paths; the rest changes the setup
     const bool same = o.k_A == p->k_A && o.m == p->m && o.n_cycles == p->n_cycles && o.cheb_upper == p->cheb_upper &&
-                      o.cheb_ratio == p->cheb_ratio && o.n_eig == p->n_eig;
+                      o.cheb_ratio == p->cheb_ratio && o.n_eig == p->n_eig && o.corrector == p->corrector;
     ctx->prm = *p;
     for (Level& L : ctx->lv) L.vgeo = L.vgeo_avail && p->vertex_geometry;
     if (!same) invalidate(ctx);
@@ -966,6 +996,10 @@ fsi_status fsi_setup(fsi_ctx* h) {
     for (int j = 0; j < ctx->nlev; ++j)
         if (!ctx->lv[j].geo_set || !ctx->lv[j].coef_set)
             return fail(ctx, FSI_ERR_STATE, "setup needs geometry and coefficients on every level");
+    if (ctx->prm.corrector)
+        for (int j = 0; j < ctx->nlev; ++j)
+            if (!ctx->lv[j].conv_set)
+                return fail(ctx, FSI_ERR_STATE, "corrector mode needs fsi_set_convection on every level");
     TRY(alloc_work<double>(ctx));
     TRY(alloc_work<float>(ctx));
     const int J = ctx->nlev - 1;
@@ -982,7 +1016,7 @@ fsi_status fsi_setup(fsi_ctx* h) {
         Level& L = ctx->lv[j];
         double* diag = ctx->w64[j].r_u;   // scratch
         launch_fill<double>(diag, 0.0, L.nv, s);
-        launch_diagA(L, L.d_K64, L.d_cv64, diag, s);
+        launch_diagA(L, L.d_K64, L.d_cv64, diag, s, ctx->prm.corrector != 0);
         launch_diagA_finish(L, diag, L.d_dAinv64, L.d_dAinv32, s);
         double n2;
         TRY(dot64(ctx, diag, diag, L.nv, &n2));
@@ -1349,6 +1383,7 @@ fsi_status fsi_solve_extension(fsi_ctx* h, const double* g, double* u, const fsi
     Context* ctx = &h->c;
     if (!ctx->setup_done) return fail(ctx, FSI_ERR_STATE, "extension solve before setup");
     if (o->max_iter < 0 || !(o->rtol >= 0)) return fail(ctx, FSI_ERR_ARG, "invalid solve options");
+    if (ctx->prm.corrector) return fail(ctx, FSI_ERR_ARG, "the extension solve is not a corrector-mode problem");
     const int J = ctx->nlev - 1;
     Level& L = ctx->lv[J];
     const int64_t nv = L.nv;

@@ -155,7 +155,9 @@ struct LevelWork {
     T *f_u = nullptr, *x_u = nullptr, *r_u = nullptr, *w_u = nullptr, *v_u = nullptr;
     T *cd_u = nullptr, *cax_u = nullptr, *tu = nullptr;
     double *f_p = nullptr, *x_p = nullptr, *r_p = nullptr, *t_p = nullptr, *z_p = nullptr;
-    double *dots = nullptr;        // [2] device scalars: <y,z>, <y, D_S^{-1} y>
+    double *b_p = nullptr, *s_p = nullptr;   // BiCGStab Schur step (corrector mode)
+    double *dots = nullptr;        // [4] device scalars: <y,z>, <y, D_S^{-1} y> (MINRES) or
+                                   // <b,b>, <b,v>, <t,s>, <t,t> (BiCGStab)
     double *partials = nullptr;    // reduction scratch
 };
 
@@ -285,7 +287,8 @@ void launch_coefficients(const Level& L, const double* cm, const double* eta, co
 // level vertex displacement (FP32 float4) from the fine-level displacement by injection
 void launch_vertex_disp32(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
                           float4* out, hipStream_t s);
-void launch_diagA(const Level& L, const double* K, const double* cv, double* diag, hipStream_t s);
+// conv: add the corrector-mode terms of the level (fsi_set_convection)
+void launch_diagA(const Level& L, const double* K, const double* cv, double* diag, hipStream_t s, bool conv = false);
 void launch_diagA_finish(const Level& L, double* diag, double* dinv64, float* dinv32, hipStream_t s);
 void launch_diagS_impl(const Level& L, const uint8_t* d_wall, const double* K, const double* dAinv,
                        double* dSinv, hipStream_t s);
@@ -329,6 +332,16 @@ void launch_smoother_update(const T* w, const T* vv, const double* z, const doub
                             double* x_p, int64_t nu, int64_t np, bool first, hipStream_t s);
 
 // s1, s2: FP64 fine-level scratch vectors (velocity length) for the intermediate passes
+// BiCGStab(1) Schur step: b = t - r, p = D_S^{-1} b; s = b - alpha v (in place of b),
+// q = D_S^{-1} s; x_u (+)= w - alpha t1 - omega t2, x_p (+)= alpha p + omega q with
+// alpha = dots[0]/dots[1], omega = dots[2]/dots[3] (0 if dots[3] = 0)
+void launch_bicg_start(const double* dsinv, const double* t, const double* r, double* b, double* p, int64_t n,
+                       hipStream_t s);
+void launch_bicg_mid(const double* dsinv, const double* dots, const double* v, double* b, double* q, int64_t n,
+                     hipStream_t s);
+template <typename T>
+void launch_bicg_update(const T* w, const T* t1, const T* t2, const double* p, const double* q, const double* dots,
+                        T* x_u, double* x_p, int64_t nu, int64_t np, bool first, hipStream_t s);
 template <typename T>
 void launch_restrict(const Level& fine, const Level& coarse, const T* rf_u, const double* rf_p,
                      T* rc_u, double* rc_p, double* s1, double* s2, hipStream_t s);
@@ -338,7 +351,7 @@ void launch_prolongate_add(const Level& fine, const Level& coarse, const T* ec_u
 
 // coarse level
 void launch_coarse_assemble_impl(const Level& L, const double* K, const double* cv, const int* vrow,
-                                 int64_t nfree_u, double* M, int64_t n, hipStream_t s);
+                                 int64_t nfree_u, double* M, int64_t n, hipStream_t s, bool conv = false);
 void launch_gj(double* M, int64_t n, int* piv, int* sigma, double* colk, double* tmp, int* flag, hipStream_t s);
 template <typename T>
 void launch_coarse_apply(const Coarse& C, const Level& L, const T* f_u, const double* f_p, T* x_u,

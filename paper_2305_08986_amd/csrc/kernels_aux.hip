@@ -284,7 +284,10 @@ template <int DIM>
 __global__ __launch_bounds__(TPB) void k_diagA(int64_t cbeg, int64_t cend, const int* __restrict__ col2lex, int nx, int xpar,
                         GeoLayout geo, int64_t nvn, int64_t plane,
                         const int* __restrict__ vmap, const uint4* __restrict__ info,
-                        const double* __restrict__ K, const double* __restrict__ cv, double* __restrict__ diag) {
+                        const double* __restrict__ K, const double* __restrict__ cv,
+                        const double* __restrict__ cb, const double* __restrict__ cs, double rho,
+                        double* __restrict__ diag) {
+    // cb, cs (corrector mode, else null): beta = K v° planes and sigma = r / (det J w)
     constexpr int NLOC = DIM == 3 ? 27 : 9, NQZ = DIM == 3 ? 3 : 1;
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cell = cbeg + id / NLOC;
@@ -324,15 +327,24 @@ __global__ __launch_bounds__(TPB) void k_diagA(int64_t cbeg, int64_t cend, const
                     g2 += G[a] * G[a];
                 }
                 const double cvisc = cv[off], cmass = cv[plane + off];
+                double extra = 0.0;
+                if (cb) {   // rho phi (v° . grad phi) + r (v° . grad phi)^2, times det(J) w
+                    double cg = 0.0;
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) acc[a] += cmass * phi * phi + 0.5 * cvisc * (g2 + G[a] * G[a]);
+                    for (int b = 0; b < DIM; ++b) cg += gh[b] * cb[b * plane + off];
+                    extra = rho * phi * cg + cs[off] * cg * cg;
+                }
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) acc[a] += cmass * phi * phi + 0.5 * cvisc * (g2 + G[a] * G[a]) + extra;
             }
         }
     const int node = vmap[cell * NLOC + n];
     for (int a = 0; a < DIM; ++a) diag[a * nvn + node] += acc[a];
 }
 
-void launch_diagA(const Level& L, const double* K, const double* cv, double* diag, hipStream_t s) {
+void launch_diagA(const Level& L, const double* K, const double* cv, double* diag, hipStream_t s, bool conv) {
+    const double* cb = conv ? L.d_cb64 : nullptr;
+    const double* cs = conv ? L.d_cs64 : nullptr;
     const int nloc = L.dim == 3 ? 27 : 9;
     for (int ph = 0; ph < L.nphases(); ++ph)
         for (int xpar = 0; xpar < 2; ++xpar) {
@@ -341,11 +353,11 @@ void launch_diagA(const Level& L, const double* K, const double* cv, double* dia
             if (L.dim == 3)
                 hipLaunchKernelGGL(k_diagA<3>, dim3(nblocks(n)), dim3(TPB), 0, s, L.phase_off[ph], L.phase_off[ph + 1],
                                    L.d_col2lex, L.cells[0], xpar, L.geo, L.nvn, L.plane(), L.d_vmap, L.d_info, K, cv,
-                                   diag);
+                                   cb, cs, L.rho, diag);
             else
                 hipLaunchKernelGGL(k_diagA<2>, dim3(nblocks(n)), dim3(TPB), 0, s, L.phase_off[ph], L.phase_off[ph + 1],
                                    L.d_col2lex, L.cells[0], xpar, L.geo, L.nvn, L.plane(), L.d_vmap, L.d_info, K, cv,
-                                   diag);
+                                   cb, cs, L.rho, diag);
         }
 }
 
@@ -779,6 +791,61 @@ void launch_smoother_update(const T* w, const T* vv, const double* z, const doub
     hipLaunchKernelGGL(k_smoother_update<T>, dim3(nblocks(nu + np)), dim3(TPB), 0, s, w, vv, z, dots, x_u, x_p, nu, np,
                        first ? 1 : 0);
 }
+__global__ void k_bicg_start(const double* __restrict__ ds, const double* __restrict__ t,
+                             const double* __restrict__ r, double* __restrict__ b, double* __restrict__ p,
+                             int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const double bi = t[i] - r[i];
+        b[i] = bi;
+        p[i] = ds[i] * bi;
+    }
+}
+void launch_bicg_start(const double* dsinv, const double* t, const double* r, double* b, double* p, int64_t n,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_bicg_start, dim3(nblocks(n)), dim3(TPB), 0, s, dsinv, t, r, b, p, n);
+}
+__global__ void k_bicg_mid(const double* __restrict__ ds, const double* __restrict__ dots,
+                           const double* __restrict__ v, double* __restrict__ b, double* __restrict__ q, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double alpha = dots[1] != 0.0 ? dots[0] / dots[1] : 0.0;
+    if (i < n) {
+        const double si = b[i] - alpha * v[i];
+        b[i] = si;
+        q[i] = ds[i] * si;
+    }
+}
+void launch_bicg_mid(const double* dsinv, const double* dots, const double* v, double* b, double* q, int64_t n,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_bicg_mid, dim3(nblocks(n)), dim3(TPB), 0, s, dsinv, dots, v, b, q, n);
+}
+template <typename T>
+__global__ void k_bicg_update(const T* __restrict__ w, const T* __restrict__ t1, const T* __restrict__ t2,
+                              const double* __restrict__ p, const double* __restrict__ q,
+                              const double* __restrict__ dots, T* __restrict__ xu, double* __restrict__ xp,
+                              int64_t nu, int64_t np, int first) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double alpha = dots[1] != 0.0 ? dots[0] / dots[1] : 0.0;
+    const double omega = dots[3] > 0.0 ? dots[2] / dots[3] : 0.0;
+    if (i < nu) {
+        const T inc = w[i] - (T)alpha * t1[i] - (T)omega * t2[i];
+        xu[i] = first ? inc : xu[i] + inc;
+    } else if (i < nu + np) {
+        const int64_t j = i - nu;
+        const double inc = alpha * p[j] + omega * q[j];
+        xp[j] = first ? inc : xp[j] + inc;
+    }
+}
+template <typename T>
+void launch_bicg_update(const T* w, const T* t1, const T* t2, const double* p, const double* q, const double* dots,
+                        T* x_u, double* x_p, int64_t nu, int64_t np, bool first, hipStream_t s) {
+    hipLaunchKernelGGL(k_bicg_update<T>, dim3(nblocks(nu + np)), dim3(TPB), 0, s, w, t1, t2, p, q, dots, x_u, x_p,
+                       nu, np, first ? 1 : 0);
+}
+template void launch_bicg_update<double>(const double*, const double*, const double*, const double*, const double*,
+                                         const double*, double*, double*, int64_t, int64_t, bool, hipStream_t);
+template void launch_bicg_update<float>(const float*, const float*, const float*, const double*, const double*,
+                                        const double*, float*, double*, int64_t, int64_t, bool, hipStream_t);
 template void launch_smoother_update<double>(const double*, const double*, const double*, const double*, double*,
                                              double*, int64_t, int64_t, bool, hipStream_t);
 template void launch_smoother_update<float>(const float*, const float*, const double*, const double*, float*, double*,
@@ -1041,8 +1108,9 @@ template <int DIM>
 __global__ __launch_bounds__(64) void k_coarse_assemble(int64_t cbeg, int64_t cend, const int* __restrict__ col2lex, int nx, int xpar,
                                   GeoLayout geo, int64_t nvn, int64_t plane, const int* __restrict__ vmap,
                                   const int* __restrict__ pmap, const double* __restrict__ K,
-                                  const double* __restrict__ cv, const int* __restrict__ vrow, int64_t nfree_u,
-                                  double* __restrict__ M, int64_t n) {
+                                  const double* __restrict__ cv, const double* __restrict__ cb,
+                                  const double* __restrict__ cs, double rho, const int* __restrict__ vrow,
+                                  int64_t nfree_u, double* __restrict__ M, int64_t n) {
     constexpr int NLOC = DIM == 3 ? 27 : 9, NPL = DIM == 3 ? 8 : 4, NQZ = DIM == 3 ? 3 : 1;
     constexpr int NCOL = NLOC + NPL, PER_CELL = DIM * NLOC * NCOL;
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1101,10 +1169,22 @@ __global__ __launch_bounds__(64) void k_coarse_assemble(int64_t cbeg, int64_t ce
                     double dot = 0.0;
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) dot += Gn[c] * Gm[c];
+                    // corrector mode: rho phi_n (v° . grad phi_m) + r (v° . grad phi_n)(v° . grad phi_m)
+                    double extra = 0.0;
+                    if (cb) {
+                        double cn = 0.0, cmv = 0.0;
+#pragma unroll
+                        for (int e = 0; e < DIM; ++e) {
+                            const double be = cb[e * plane + off];
+                            cn += gn[e] * be;
+                            cmv += gm[e] * be;
+                        }
+                        extra = rho * phin * cmv + cs[off] * cn * cmv;
+                    }
 #pragma unroll
                     for (int b = 0; b < DIM; ++b) {
                         double v = 0.5 * cvisc * Gn[b] * Gm[a];
-                        if (a == b) v += cmass * phin * phim + 0.5 * cvisc * dot;
+                        if (a == b) v += cmass * phin * phim + 0.5 * cvisc * dot + extra;
                         acc[b] += v;
                     }
                 }
@@ -1145,8 +1225,10 @@ __global__ __launch_bounds__(64) void k_coarse_assemble(int64_t cbeg, int64_t ce
 }
 
 void launch_coarse_assemble_impl(const Level& L, const double* K, const double* cv, const int* vrow,
-                                 int64_t nfree_u, double* M, int64_t n, hipStream_t s) {
+                                 int64_t nfree_u, double* M, int64_t n, hipStream_t s, bool conv) {
     const int nloc = L.dim == 3 ? 27 : 9, npl = L.dim == 3 ? 8 : 4;
+    const double* cb = conv ? L.d_cb64 : nullptr;
+    const double* cs = conv ? L.d_cs64 : nullptr;
     for (int ph = 0; ph < L.nphases(); ++ph)
         for (int xpar = 0; xpar < 2; ++xpar) {
             const int64_t cnt = (L.phase_off[ph + 1] - L.phase_off[ph]) * L.dim * nloc * (nloc + npl);
@@ -1154,11 +1236,11 @@ void launch_coarse_assemble_impl(const Level& L, const double* K, const double* 
             if (L.dim == 3)
                 hipLaunchKernelGGL(k_coarse_assemble<3>, dim3(nblocks(cnt, 64)), dim3(64), 0, s, L.phase_off[ph],
                                    L.phase_off[ph + 1], L.d_col2lex, L.cells[0], xpar, L.geo, L.nvn, L.plane(),
-                                   L.d_vmap, L.d_pmap, K, cv, vrow, nfree_u, M, n);
+                                   L.d_vmap, L.d_pmap, K, cv, cb, cs, L.rho, vrow, nfree_u, M, n);
             else
                 hipLaunchKernelGGL(k_coarse_assemble<2>, dim3(nblocks(cnt, 64)), dim3(64), 0, s, L.phase_off[ph],
                                    L.phase_off[ph + 1], L.d_col2lex, L.cells[0], xpar, L.geo, L.nvn, L.plane(),
-                                   L.d_vmap, L.d_pmap, K, cv, vrow, nfree_u, M, n);
+                                   L.d_vmap, L.d_pmap, K, cv, cb, cs, L.rho, vrow, nfree_u, M, n);
         }
 }
 

@@ -149,3 +149,63 @@ def test_corrector_error_cases():
     n2 = wl2.eta[-1].shape[0]
     with pytest.raises(fsi.FSIError):
         ctx2.set_convection(ctx2.n_levels - 1, np.zeros((n2, 9, 3)), np.zeros((n2, 9)), 1.0)
+
+
+def _corrector_ctx(name, precision=0, fused=1):
+    from oracle import solvers
+    wl, ctx, conv = _setup(name)
+    ctx.set_mg_params(corrector=1, k_A=6, precision=precision, fused=fused)
+    ctx.setup()
+    ops = solvers.build_levels_corrector(wl.mesh, wl.disp, wl.c_mass, wl.eta,
+                                         [(conv[j].vconv, conv[j].rho, conv[j].r) for j in range(ctx.n_levels)])
+    h = solvers.Hierarchy(ops, solvers.MGParams(k_A=6, schur="bicgstab"))
+    return wl, ctx, ops, h
+
+
+@pytest.mark.parametrize("name", ["T3_4", "T3_R"])
+def test_corrector_vcycle_matches_oracle(name):
+    """Corrector mode (A + N + S on every level, k_A = 6, BiCGStab Schur step): Lanczos
+    bounds within 1e-10 and one FP64 V-cycle within 1e-9 of the oracle's."""
+    wl, ctx, ops, h = _corrector_ctx(name)
+    for j in range(ctx.n_levels):
+        li = ctx.level_info(j)
+        assert abs(li["lambda_max"] - h.levels[j].lam) <= 1e-10 * h.levels[j].lam, (j, li, h.levels[j].lam)
+    rng = np.random.default_rng(79)
+    op = ops[-1]
+    ru = rng.uniform(-1, 1, op.box.n_vel) * ~op.dir_mask
+    rp = rng.uniform(-1, 1, op.box.n_p)
+    for use_graph in (0, 1):
+        ctx.set_mg_params(corrector=1, k_A=6, use_graph=use_graph)
+        zu, zp = ctx.vcycle(torch.from_numpy(ru).cuda(), torch.from_numpy(rp).cuda())
+        ou, opp = h.precondition(ru, rp)
+        eu = np.linalg.norm(zu.cpu().numpy() - ou) / np.linalg.norm(ou)
+        ep = np.linalg.norm(zp.cpu().numpy() - opp) / np.linalg.norm(opp)
+        print(name, use_graph, "corrector vcycle err", eu, ep)
+        assert eu <= 1e-9 and ep <= 1e-9
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_corrector_solve_matches_direct(prec):
+    from oracle import solvers
+    wl, ctx, ops, h = _corrector_ctx("T3_4", precision=prec)
+    gu = torch.from_numpy(wl.g_u).cuda()
+    gp = torch.from_numpy(wl.g_p).cuda()
+    u, p, info = ctx.solve(gu, gp, rtol=1e-10, max_iter=200)
+    print("corrector solve", prec, info["iters"], info["rel_res"])
+    assert info["status"] == "OK" and info["rel_res"] <= 1e-10
+    du, dp = solvers.direct_solve(ops[-1], wl.g_u, wl.g_p)
+    err = np.linalg.norm(u.cpu().numpy() - du) / np.linalg.norm(du)
+    assert err <= 1e-7, err
+
+
+def test_corrector_setup_needs_convection_everywhere():
+    from paper_2305_08986_amd import fsi
+    wl = W.make_workload("T3_4")
+    ctx = fsi.Context.from_mesh(wl.mesh)
+    fsi.setup_workload(ctx, wl)
+    J = ctx.n_levels - 1
+    c = W.make_convection_inputs("T3_4", wl.mesh, J, wl.eta[J])
+    ctx.set_convection(J, c.vconv, c.r, c.rho)         # finest level only
+    ctx.set_mg_params(corrector=1, k_A=6)
+    with pytest.raises(fsi.FSIError):
+        ctx.setup()
