@@ -22,7 +22,9 @@ and the mixed-vs-FP64 velocity difference are reported beside it.
 
 After the timed steps (not part of them): the pseudo-elastic extension solve
 on the same mesh (flexible CG + multigrid on A with c_m = 0, eta = mu_A / 2,
-to 1e-6), FP64 and FP32 V-cycle, reported under "extension".
+to 1e-6), FP64 and FP32 V-cycle, reported under "extension"; the corrector
+mode (convection and streamline terms): its Stokes apply on the same mesh and
+its solve on the 64^3 box, reported under "corrector".
 
 Prints one JSON line (rank 0, N = 1 only: this build targets one GPU).
 """
@@ -117,6 +119,57 @@ def extension_measure(name, mesh, d_disp, fsi, W, np, torch, rtol: float = 1e-6,
             "first_solve_builds_coarse_inverse": True}
 
 
+def corrector_measure(name, ctx, W, np, torch, fsi, solve_workload: str = "C2", rtol: float = 1e-8):
+    """Corrector mode (convection and streamline terms, Sec. 3.1.1 and 3.2): the Stokes
+    apply with the terms on the bench workload's finest level (FP64 and FP32, median of
+    timed applications), and the corrector solve (k_A = 6, BiCGStab Schur step) on the
+    64^3 box to rtol 1e-8: plain FP64 path, optimised FP64 and mixed precision."""
+    J = ctx.n_levels - 1
+    sz = ctx.sizes(J)
+    wl = W.make_workload(name, levels=[J])
+    c = W.make_convection_inputs(name, wl.mesh, J, wl.eta[J])
+    ctx.set_convection(J, c.vconv, c.r, c.rho)
+    del wl
+    n = sz["n_vel"] + sz["n_p"]
+    _, o64, _ = ctx.time_operator(J, precision=0, mode=39, reps=10)
+    _, o32, _ = ctx.time_operator(J, precision=1, mode=39, reps=10)
+    _, op7, _ = ctx.time_operator(J, precision=0, mode=7, reps=10)
+    out = {"apply": {"workload": name, "fp64_us": round(o64, 1), "fp64_gdofs": round(n / (o64 * 1e-6) / 1e9, 3),
+                     "fp32_us": round(o32, 1), "fp32_gdofs": round(n / (o32 * 1e-6) / 1e9, 3),
+                     "predictor_fp64_us": round(op7, 1),
+                     "streamline_active_cells": float((c.r[:, 0] > 0).mean())}}
+    wl = W.make_workload(solve_workload)
+    cctx = fsi.Context.from_mesh(wl.mesh)
+    fsi.setup_workload(cctx, wl)
+    for j in range(cctx.n_levels):
+        cj = W.make_convection_inputs(solve_workload, wl.mesh, j, wl.eta[j])
+        cctx.set_convection(j, cj.vconv, cj.r, cj.rho)
+    cctx.setup()
+    cctx.autotune()
+    cctx.set_mg_params(corrector=1, k_A=6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cctx.setup()
+    torch.cuda.synchronize()
+    setup_ms = 1e3 * (time.perf_counter() - t0)
+    gu = torch.from_numpy(wl.g_u).cuda()
+    gp = torch.from_numpy(wl.g_p).cuda()
+    res = {}
+    sol = {}
+    for label, prm in (("plain_fp64", dict(precision=0, use_graph=0, fused=0, tuned=0)),
+                       ("fp64", dict(precision=0)), ("mixed", dict(precision=1))):
+        cctx.set_mg_params(corrector=1, k_A=6, **prm)
+        u, p, info = cctx.solve(gu, gp, rtol=rtol, max_iter=300)
+        sol[label] = u
+        res[label] = dict(ms=round(info["time_ms"], 1), iters=info["iters"], rel_res=info["rel_res"],
+                          status=info["status"])
+    du = float(torch.linalg.vector_norm(sol["mixed"] - sol["fp64"]) / torch.linalg.vector_norm(sol["fp64"]))
+    out["solve"] = {"workload": solve_workload, "rtol": rtol, "k_A": 6, "setup_ms": round(setup_ms, 1), **res,
+                    "speedup_mixed_vs_plain_fp64": round(res["plain_fp64"]["ms"] / res["mixed"]["ms"], 3),
+                    "velocity_rel_diff_mixed_vs_fp64": du}
+    return out
+
+
 def cpu_baseline(seconds: float = 12.0):
     """The CPU oracle's A-apply (CSR SpMV, scipy) timed on a bounded sample."""
     import numpy as np
@@ -156,6 +209,7 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extension", action="store_true", help="skip the extension-solve measurement")
+    ap.add_argument("--no-corrector", action="store_true", help="skip the corrector-mode measurement")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
 
@@ -329,6 +383,9 @@ def main():
     if not args.no_extension:
         _log("[bench] extension solve")
         out["extension"] = extension_measure(name, mesh, d_disp, fsi, W, np, torch)
+    if not args.no_corrector:
+        _log("[bench] corrector mode")
+        out["corrector"] = corrector_measure(name, ctx, W, np, torch, fsi)
     if not args.no_cpu_baseline:
         _log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
