@@ -216,8 +216,8 @@ fsi_status fsi_set_convection(fsi_ctx* ctx, int level, const double* vconv, cons
  * with N the convection and S the streamline term set by fsi_set_convection
  * (Dirichlet rows act as identity, Dirichlet columns are zero, as for
  * fsi_apply_stokes).  FP64 and FP32 twin; layouts and errors as fsi_apply_stokes,
- * FSI_ERR_STATE without fsi_set_convection.  The V-cycle and the solve stay in
- * predictor mode. */
+ * FSI_ERR_STATE without fsi_set_convection.  The V-cycle and the solve use these
+ * terms when fsi_mg_params.corrector = 1. */
 fsi_status fsi_apply_corrector(fsi_ctx* ctx, int level, const double* u, const double* p,
                                double* v, double* q);
 fsi_status fsi_apply_corrector_f32(fsi_ctx* ctx, int level, const float* u, const float* p,
