@@ -156,7 +156,26 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     const int qy = t % 3, qz = t / 3;
     const int pax = t & 1, pyz = t >> 1;
 
+    // cell info and node indices of a step: the Stokes modes (one or two wavefronts per
+    // SIMD) fetch the next step's while their own gathers are in flight, which takes one
+    // dependent round trip out of the step; the other modes fetch them in the step
+    // itself (measured faster there: 7 more live registers cost them more than the
+    // round trip)
+    constexpr bool PREF = HAS_A && HAS_BT;
+    uint4 inf_nx;
+    int node_nx[3];
+    auto fetch_idx = [&](int stp) {
+        const int chp = RS ? stp * WPB + wave : stp;
+        const int ixp = chp * CPW + slot;
+        const bool actp = rowact && inwave && stp < nsteps && ixp < a.nx;
+        const int64_t cellp = a.cbeg + row * a.nx + ixp;
+        inf_nx = actp ? a.info[cellp] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) node_nx[k] = actp ? a.vmap[cellp * NLOC + t + 9 * k] : 0;
+    };
+    if constexpr (PREF) fetch_idx(0);
     for (int st = 0; st < nsteps; ++st) {
+        if constexpr (!PREF) fetch_idx(st);
         const int ch = RS ? st * WPB + wave : st;
         const int ix = ch * CPW + slot;
         const bool act = rowact && inwave && ix < a.nx;
@@ -164,23 +183,23 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         // the chunk is wavefront-uniform: keep it scalar so that every geometry load is
         // a scalar base plus the lane's fixed offset (no per-plane vector addresses)
         const int64_t chunk = __builtin_amdgcn_readfirstlane((int)(a.chunk0 + row * a.nchunks + ch));
-        const uint4 inf = act ? a.info[cell] : make_uint4(0u, 0u, 0u, 0u);
+        const uint4 inf = inf_nx;
         // does this thread write its column (x-face columns go to the right neighbour)?
         const bool vwriter = act && (ic != 2 || ix == a.nx - 1);
         const bool pwriter = act && t < 8 && (pax == 0 || ix == a.nx - 1);
 
         // ---------------- loads
-        int node[3] = {0, 0, 0};
+        const int node[3] = {node_nx[0], node_nx[1], node_nx[2]};
         T uu[3][3];     // [comp][k] velocity of the column nodes
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int ln = t + 9 * k;
-            node[k] = act ? a.vmap[cell * NLOC + ln] : 0;
             const bool wall = (inf.x >> ln) & 1u;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 uu[c][k] = (FWD && act && !wall) ? (CHEB ? a.x : a.u)[c * a.nvn + node[k]] : T(0);
         }
+        if constexpr (PREF) fetch_idx(st + 1);
         int pnode = 0;
         if constexpr (HAS_B) {
             if (pwriter) pnode = a.pmap[cell * 8 + t];
