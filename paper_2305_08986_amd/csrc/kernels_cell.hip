@@ -613,7 +613,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                 for (int k = 0; k < 3; ++k) {
                     const int ln = t + 9 * k;
                     const bool last = vwriter && !((inf.x >> ln) & 1u) && ((inf.w >> ln) & 1u);
-                    const bool part = last && !((inf.y >> ln) & 1u);
+                    // every node this step adds to: earlier phases' partial sum
+                    const bool part = vwriter && !((inf.x >> ln) & 1u) && !((inf.y >> ln) & 1u);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         const int64_t i = c * a.nvn + node[k];
@@ -625,6 +626,16 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                             eg[c][k] = last ? a.dinv[i] : T(0);
                         }
                     }
+                }
+            } else {
+                // the earlier phases' partial sums of the nodes this step adds to (plain
+                // modes), fetched here so that their latency hides behind the backward sweeps
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int ln = t + 9 * k;
+                    const bool part = vwriter && !((inf.x >> ln) & 1u) && !((inf.y >> ln) & 1u);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) ep[c][k] = part ? a.v[c * a.nvn + node[k]] : T(0);
                 }
             }
             const int ib = t % 3, qzb = t / 3;
@@ -721,7 +732,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                             for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node[k]] = out[c][k];
                         } else {
 #pragma unroll
-                            for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node[k]] += out[c][k];
+                            for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node[k]] = ep[c][k] + out[c][k];
                         }
                     }
                 } else if (slot == CPW - 1 && carry_out) {
