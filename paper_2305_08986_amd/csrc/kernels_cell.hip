@@ -200,6 +200,18 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                 uu[c][k] = (FWD && act && !wall) ? (CHEB ? a.x : a.u)[c * a.nvn + node[k]] : T(0);
         }
         if constexpr (PREF) fetch_idx(st + 1);
+        // the first point's geometry (per-point path): issued before the forward sweeps,
+        // whose work hides its latency
+        constexpr bool PERQX0 = sizeof(T) == 8 || (HAS_A && HAS_BT && !VG) || CONV;
+        T g0[11];
+        if constexpr (PERQX0) {
+            const int64_t off0 = chunk * kGeoSlots + (slot * NT + t);
+#pragma unroll
+            for (int e = 0; e < 9; ++e) g0[e] = act ? gload<NTL>(a.K + e * P + off0) : T(0);
+            g0[9] = (SCALED || !HAS_A || !act) ? T(1) : gload<NTL>(a.cv + off0);
+            g0[10] = (HAS_A && act) ? gload<NTL>(a.cv + P + off0) : T(0);
+            __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the sweeps
+        }
         int pnode = 0;
         if constexpr (HAS_B) {
             if (pwriter) pnode = a.pmap[cell * 8 + t];
@@ -332,10 +344,18 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             // geometry of the point: K = det(J) w J^{-1} (row-major 3x3), cvisc, cmass
             T Kq[9];
             const int64_t off = ((int64_t)qx * a.nchk + chunk) * kGeoSlots + (slot * NT + t);
+            T cvq, cmq;
+            if (qx == 0) {
 #pragma unroll
-            for (int e = 0; e < 9; ++e) Kq[e] = act ? gload<NTL>(a.K + e * P + off) : T(0);
-            const T cvq = SCALED ? T(1) : ((HAS_A && act) ? gload<NTL>(a.cv + off) : T(0));
-            const T cmq = (HAS_A && act) ? gload<NTL>(a.cv + P + off) : T(0);
+                for (int e = 0; e < 9; ++e) Kq[e] = g0[e];
+                cvq = SCALED ? T(1) : ((HAS_A && act) ? g0[9] : T(0));
+                cmq = g0[10];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 9; ++e) Kq[e] = act ? gload<NTL>(a.K + e * P + off) : T(0);
+                cvq = SCALED ? T(1) : ((HAS_A && act) ? gload<NTL>(a.cv + off) : T(0));
+                cmq = (HAS_A && act) ? gload<NTL>(a.cv + P + off) : T(0);
+            }
             // corrector terms: with beta = K v°, (grad-hat u_c) . beta = det(J) w (v° . grad u_c)
             T be[3] = {T(0), T(0), T(0)}, sg = T(0), cvc[3] = {T(0), T(0), T(0)};
             if constexpr (CONV) {
