@@ -264,11 +264,18 @@ fsi_status fsi_solve_extension(fsi_ctx* ctx, const double* g, double* u, const f
  * fsi_get_tuning reports the choice for A. */
 fsi_status fsi_autotune(fsi_ctx* ctx);
 fsi_status fsi_get_tuning(const fsi_ctx* ctx, int level, int precision, int* variant, double* best_us);
-/* Pin the launch variant (0 .. 11) of every operator class on one level and
- * precision, overriding the autotuner (used with tuned = 1).  Variant v: v % 3
+/* Pin the launch variant (0 .. 15) of every operator class on one level and
+ * precision, overriding the autotuner (used with tuned = 1).  Variant v < 12: v % 3
  * selects 1, 2 or 4 wavefronts per workgroup sharing a row of cells (3D; 2D: one row
  * per wavefront, at most two); (v / 3) % 2 cached instead of streaming geometry
- * loads; v / 6 a register cap of one more wavefront per SIMD.  Errors: FSI_ERR_ARG. */
+ * loads; v / 6 a register cap of one more wavefront per SIMD.  v = 12 .. 15: three
+ * wavefronts share a row (2D: two rows), (v - 12) % 2 cached loads, (v - 12) / 2 the
+ * register cap.  v = 16, 17 (3D levels): the unfused applies (A, B, B^T, Stokes) run
+ * as one launch over all processing phases that adds into zeroed outputs with
+ * atomics, one (16) or four (17) wavefronts per row; results then vary in the last
+ * bits from run to run; the fused epilogues keep variant 0.  fsi_autotune picks this
+ * form for a level where it measures it faster (latency-bound small levels).
+ * Errors: FSI_ERR_ARG. */
 fsi_status fsi_set_tuning(fsi_ctx* ctx, int level, int precision, int variant);
 
 /* Measurement support: runs `reps` applications of the level operator

@@ -297,8 +297,12 @@ static void op_apply(Context* ctx, int j, int mode, const T* u, const double* p,
     // every output entry is written by its first touching cell (no clearing pass);
     // wall rows: identity for A, zero for B^T alone
     const Level& L = ctx->lv[j];
-    launch_cell_all<T>(L, mode, variant_of(ctx, prec_index<T>(), j, mode), Kmode<T>(L, mode), CVp<T>(L), u, p, v, q,
-                       s);
+    const int am = ctx->prm.tuned ? ctx->atom[prec_index<T>()][j] : -1;
+    if (am >= 0 && L.dim == 3 && !(mode & OP_CONV))
+        launch_cell_atomic<T>(L, mode, am, Kmode<T>(L, mode), CVp<T>(L), u, p, v, q, s);
+    else
+        launch_cell_all<T>(L, mode, variant_of(ctx, prec_index<T>(), j, mode), Kmode<T>(L, mode), CVp<T>(L), u, p,
+                           v, q, s);
     if (mode & OP_A) launch_dirichlet_copy<T>(L, u, v, s);
     else if (mode & OP_BT) launch_dirichlet_zero<T>(L, v, s);
 }
@@ -861,6 +865,7 @@ fsi_status fsi_create(fsi_ctx** out, const fsi_mesh_desc* m, void* hip_stream) {
         ctx->tune_us[pi].assign((size_t)ctx->nlev * kTuneClasses, 0.0);
         ctx->fuse_cheb[pi].assign(ctx->nlev, 1);
         ctx->fuse_res[pi].assign(ctx->nlev, 1);
+        ctx->atom[pi].assign(ctx->nlev, -1);
     }
     if (st != FSI_OK) {
         fsi_destroy(h);
@@ -1377,6 +1382,19 @@ static void launch_phase_on_work(Context* ctx, int prec, int j, int mode, int va
     }
 }
 
+// the single atomic launch of an unfused level operator on the level's work vectors
+// (timing and tuning only)
+static void launch_atomic_on_work(Context* ctx, int prec, int j, int mode, int shape, hipStream_t s) {
+    const Level& L = ctx->lv[j];
+    if (prec == 0) {
+        LevelWork<double>& W = ctx->w64[j];
+        launch_cell_atomic<double>(L, mode, shape, Kmode<double>(L, mode), L.d_cv64, W.x_u, W.x_p, W.r_u, W.r_p, s);
+    } else {
+        LevelWork<float>& W = ctx->w32[j];
+        launch_cell_atomic<float>(L, mode, shape, Kmode<float>(L, mode), CVp<float>(L), W.x_u, W.x_p, W.r_u, W.r_p, s);
+    }
+}
+
 fsi_status fsi_solve_extension(fsi_ctx* h, const double* g, double* u, const fsi_solve_opts* o,
                                fsi_solve_info* info) {
     if (!h || !g || !u || !o) return FSI_ERR_ARG;
@@ -1541,6 +1559,39 @@ fsi_status fsi_autotune(fsi_ctx* h) {
                 ctx->tune_variant[pi][(size_t)j * kTuneClasses + cls] = bestv;
                 ctx->tune_us[pi][(size_t)j * kTuneClasses + cls] = best;
             }
+    // phased launches (tuned) against the single atomic launch, over the unfused
+    // classes A, Stokes, B, B^T together
+    const int unfused[4] = {OP_A, OP_A | OP_BT | OP_B, OP_B, OP_BT};
+    for (int pi = 0; pi < 2; ++pi)
+        for (int j = 0; j < ctx->nlev; ++j) {
+            ctx->atom[pi][j] = -1;
+            if (ctx->lv[j].dim != 3) continue;
+            double phased = 0;
+            for (int m : unfused) phased += ctx->tune_us[pi][(size_t)j * kTuneClasses + tune_class(m)];
+            double best = phased;
+            for (int shape = 0; shape < 2; ++shape) {
+                double tot = 0;
+                for (int m : unfused) {
+                    const int reps = 3;
+                    for (int r = 0; r <= reps; ++r) {
+                        if (r == 1) FSI_HIP_TRY(hipEventRecord(e0, s));
+                        launch_atomic_on_work(ctx, pi, j, m, shape, s);
+                    }
+                    FSI_HIP_TRY(hipEventRecord(e1, s));
+                    FSI_HIP_TRY(hipEventSynchronize(e1));
+                    float ms = 0;
+                    FSI_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    tot += 1000.0 * ms / reps;
+                }
+                if (getenv("FSI_TUNE_VERBOSE"))
+                    fprintf(stderr, "[fsi autotune] precision %d level %d unfused applies %.1f us phased / %.1f us atomic "
+                            "(shape %d)\n", pi, j, phased, tot, shape);
+                if (tot < best) {
+                    best = tot;
+                    ctx->atom[pi][j] = (int8_t)shape;
+                }
+            }
+        }
     // fused epilogues against operator + separate vector kernel, each with its tuned variant
     auto timed = [&](auto&& body, double* us) -> fsi_status {
         body();
@@ -1558,6 +1609,11 @@ fsi_status fsi_autotune(fsi_ctx* h) {
             const Level& L = ctx->lv[j];
             auto var = [&](int mode) { return ctx->tune_variant[pi][(size_t)j * kTuneClasses + tune_class(mode)]; };
             auto all = [&](int mode) {
+                const bool epilogue = (mode & (OP_CHEB | OP_RES)) != 0;
+                if (!epilogue && ctx->atom[pi][j] >= 0) {
+                    launch_atomic_on_work(ctx, pi, j, mode, ctx->atom[pi][j], s);
+                    return;
+                }
                 for (int ph = 0; ph < L.nphases(); ++ph) launch_phase_on_work(ctx, pi, j, mode, var(mode), ph, s);
             };
             double sep_c = 0, fus_c = 0, sep_r = 0, fus_r = 0;
@@ -1658,9 +1714,14 @@ fsi_status fsi_set_tuning(fsi_ctx* h, int level, int precision, int variant) {
     if (!h) return FSI_ERR_ARG;
     Context* ctx = &h->c;
     if (level < 0 || level >= ctx->nlev || (precision != 0 && precision != 1) || variant < 0 ||
-        variant >= kNumVariants)
+        variant >= kNumVariants + 2)
         return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: level, precision or variant out of range");
-    for (int c = 0; c < kTuneClasses; ++c) ctx->tune_variant[precision][(size_t)level * kTuneClasses + c] = variant;
+    const bool atomic = variant >= kNumVariants;
+    if (atomic && ctx->lv[level].dim != 3)
+        return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: the single atomic launch is 3D only");
+    for (int c = 0; c < kTuneClasses; ++c)
+        ctx->tune_variant[precision][(size_t)level * kTuneClasses + c] = atomic ? 0 : variant;
+    ctx->atom[precision][level] = atomic ? (int8_t)(variant - kNumVariants) : (int8_t)-1;
     if (ctx->setup_done) TRY(capture_graphs(ctx));   // captured graphs hold the old launch shapes
     return FSI_OK;
 }

@@ -59,7 +59,9 @@ __host__ __device__ inline int64_t geo_off(const GeoLayout& g, int qx, int64_t c
 // Chebyshev update of the iterate or by the residual f - M u
 // OP_CONV (with OP_A, 3D) adds the corrector-mode terms: convection rho (grad u) v° and
 // the streamline term r (v° . grad u)(v° . grad w)
-enum : int { OP_A = 1, OP_BT = 2, OP_B = 4, OP_CHEB = 8, OP_RES = 16, OP_CONV = 32 };
+// OP_ATOM: one launch over every phase, adding into zeroed outputs with atomics
+// (small levels, where the four phase launches are latency-bound)
+enum : int { OP_A = 1, OP_BT = 2, OP_B = 4, OP_CHEB = 8, OP_RES = 16, OP_CONV = 32, OP_ATOM = 64 };
 
 // ---------------------------------------------------------------- error helpers
 #define FSI_HIP_TRY(expr)                                                          \
@@ -235,13 +237,17 @@ struct Context {
     // per level and precision: use the fused Chebyshev / residual epilogue (when the
     // fused path is enabled); the autotuner keeps whichever it measured faster
     std::vector<uint8_t> fuse_cheb[2], fuse_res[2];
+    // per level and precision: -1 phased launches; 0 or 1 the single atomic launch
+    // (one or four wavefronts per row) for the unfused applies, where the autotuner
+    // measured it faster (results then vary in the last bits from run to run)
+    std::vector<int8_t> atom[2];
     std::vector<void*> allocations;
 };
 
 // ---------------------------------------------------------------- launchers (kernels_*.hip)
 // cell operator on one colour range; mode = OP_* bits; variant selects the
 // workgroup size (wavefronts per workgroup) and block->tile mapping.
-constexpr int kNumVariants = 12;
+constexpr int kNumVariants = 16;
 // launch variants are tuned per operator class: A, A with the Chebyshev epilogue,
 // Stokes, Stokes with the residual epilogue, B, B^T
 constexpr int kTuneClasses = 6;
@@ -258,6 +264,11 @@ void launch_cell(const Level& L, int mode, int variant, int phase, const T* K, c
 template <typename T>
 void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T* cv,
                      const T* u, const double* p, T* v, double* q, hipStream_t s);
+// the same apply in one launch over all phases with atomic adds (3D; modes A, B, B^T
+// and A + B^T + B; shape 0 or 1: one or four wavefronts per row)
+template <typename T>
+void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T* cv,
+                        const T* u, const double* p, T* v, double* q, hipStream_t s);
 template <typename T>
 void launch_cell_cheb(const Level& L, int variant, int phase, const T* K, const T* cv, T* x, T* d, const T* r,
                       const T* dinv, T* v, double c1, double c2, bool first, bool store_d, hipStream_t s);

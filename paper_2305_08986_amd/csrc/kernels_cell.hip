@@ -22,6 +22,8 @@
 // no node, so the scatter is a plain store (first touch of a node in phase
 // order) or read-modify-write (later touches), with no atomics; the host
 // launches the processing phases one after another.
+#include <type_traits>
+
 #include "fsi_common.h"
 
 namespace fsi {
@@ -121,6 +123,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     constexpr bool CHEB = (MODE & OP_CHEB) != 0;
     constexpr bool RES = (MODE & OP_RES) != 0;
     constexpr bool CONV = (MODE & OP_CONV) != 0;
+    // every phase in one launch: each touch adds atomically (outputs zeroed beforehand)
+    constexpr bool ATOM = (MODE & OP_ATOM) != 0;
+    static_assert(!ATOM || !(CHEB || RES || CONV), "the atomic form has no epilogue and no corrector terms");
     static_assert(!CHEB || MODE == (OP_A | OP_CHEB), "the Chebyshev epilogue goes with A alone");
     static_assert(!CONV || (MODE == (OP_A | OP_CONV) || MODE == (OP_A | OP_BT | OP_B | OP_CONV)),
                   "the corrector terms go with A or the Stokes apply");
@@ -128,7 +133,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     static_assert(!RES || MODE == (OP_A | OP_BT | OP_B | OP_RES), "the residual epilogue goes with the Stokes apply");
     static_assert(!VG || sizeof(T) == 4, "geometry from vertices is the FP32 path");
     // A alone reads K' = sqrt(cvisc) K (no cvisc plane): sym(grad-hat u K') K'^T = cvisc sym(H) K^T
-    constexpr bool SCALED = !VG && (MODE == OP_A || MODE == (OP_A | OP_CHEB));
+    constexpr bool SCALED = !VG && ((MODE & ~OP_ATOM) == OP_A || MODE == (OP_A | OP_CHEB));
     __shared__ T sbuf[WPB][CPW][BUF];
     __shared__ double pbuf[HAS_B ? WPB : 1][CPW][NT][8];
     // x-face hand-over between neighbouring cells of the row: [slot][j][comp][k],
@@ -570,7 +575,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             double qold = 0.0;
             bool plast = false;
             if (pwriter) {
-                if (!((inf.z >> t) & 1u)) qold = a.q[pnode];
+                if (!ATOM && !((inf.z >> t) & 1u)) qold = a.q[pnode];
                 if constexpr (RES) {
                     plast = (inf.z >> (16 + t)) & 1u;
                     if (plast) qold = a.fp[pnode] - qold;
@@ -601,7 +606,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                                    : ((RS && wave > 0) ? pxb[st & 1][wave - 1][CPW - 1][pyz]
                                                        : pcarry[cw][(st + 1) & 1][pyz]);
                 if (pwriter) {
-                    a.q[pnode] = plast ? qold - sq : qold + sq;
+                    if constexpr (ATOM) unsafeAtomicAdd(&a.q[pnode], sq);
+                    else a.q[pnode] = plast ? qold - sq : qold + sq;
                 } else if (slot == CPW - 1 && carry_out) {
                     pcarry[cw][st & 1][pyz] = sq;
                 }
@@ -653,7 +659,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const int ln = t + 9 * k;
-                    const bool part = vwriter && !((inf.x >> ln) & 1u) && !((inf.y >> ln) & 1u);
+                    const bool part = !ATOM && vwriter && !((inf.x >> ln) & 1u) && !((inf.y >> ln) & 1u);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) ep[c][k] = part ? a.v[c * a.nvn + node[k]] : T(0);
                 }
@@ -747,6 +753,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                                     a.v[i] = er[c][k] - tot;
                                 }
                             }
+                        } else if (ATOM) {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) unsafeAtomicAdd(&a.v[c * a.nvn + node[k]], out[c][k]);
                         } else if (first) {
 #pragma unroll
                             for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node[k]] = out[c][k];
@@ -1083,17 +1092,21 @@ static void launch_one(const Level& L, const CellArgs<T>& args, hipStream_t s) {
         }
         hipLaunchKernelGGL((cell3d<T, MODE, WPB, RS, NTL, WPE, false>), dim3((unsigned)grid), dim3(64 * WPB), 0, s,
                            args);
-    } else if constexpr ((MODE & OP_CONV) == 0) {   // the corrector terms are 3D only
+    } else if constexpr ((MODE & (OP_CONV | OP_ATOM)) == 0) {   // the corrector terms and the atomic form are 3D only
         constexpr int W2 = WPB > 1 ? 2 : 1;   // 2D: one row per wavefront, at most two
         const int64_t grid = (args.nrows + W2 - 1) / W2;   // one wavefront per row of cells
         hipLaunchKernelGGL((cell2d<T, MODE, W2, false, NTL>), dim3((unsigned)grid), dim3(64 * W2), 0, s, args);
     }
 }
 
-// launch variant v (0 .. 11): v % 3 selects 1, 2 or 4 wavefronts per workgroup (in 3D
-// the wavefronts share one row; in 2D they own a row each, at most two); (v / 3) % 2
-// selects cached instead of streaming geometry loads; v / 6 caps the registers for
-// one wavefront per SIMD more than the class reaches unconstrained (spills allowed).
+// launch variant v (0 .. 15): for v < 12, v % 3 selects 1, 2 or 4 wavefronts per
+// workgroup (in 3D the wavefronts share one row; in 2D they own a row each, at most
+// two); (v / 3) % 2 selects cached instead of streaming geometry loads; v / 6 caps the
+// registers for one wavefront per SIMD more than the class reaches unconstrained
+// (spills allowed).  v = 12 .. 15: three wavefronts share a row, (v - 12) % 2 cached
+// loads, (v - 12) / 2 the register cap.  Three wavefronts fit five workgroups where
+// four fit four (FP32 A, B classes), which fills the chip better when the rows of a
+// phase are not a multiple of the four-wavefront slots (96^3: 2304 rows per phase).
 // Unconstrained occupancy (3D): FP64 2 (A, B classes) or 1 (Stokes classes); FP32
 // 3-4 (A, B classes) or 2 (Stokes classes).
 template <typename T, int MODE, int WPB, bool NTL>
@@ -1109,6 +1122,13 @@ static void launch_capped(const Level& L, int cap, const CellArgs<T>& args, hipS
 
 template <typename T, int MODE>
 static void launch_mode(const Level& L, int variant, const CellArgs<T>& args, hipStream_t s) {
+    if (variant >= 12) {
+        const int w = variant - 12;
+        const int cap = (w >> 1) & 1;
+        if (w & 1) launch_capped<T, MODE, 3, false>(L, cap, args, s);
+        else launch_capped<T, MODE, 3, true>(L, cap, args, s);
+        return;
+    }
     const int cap = (variant / 6) & 1;
     const bool plain = ((variant / 3) & 1) != 0;
     switch (variant % 3) {
@@ -1183,6 +1203,37 @@ void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T*
     for (int ph = 0; ph < L.nphases(); ++ph) launch_cell<T>(L, mode, variant, ph, K, cv, u, p, v, q, s);
 }
 
+// every phase in one launch (3D, modes A, B, B^T, A + B^T + B): the outputs are
+// zeroed, then each cell adds its contributions atomically.  shape 0: one wavefront
+// per row; 1: four wavefronts share a row.  Wall rows are left at zero (the callers'
+// Dirichlet kernels follow as for the phased launches).
+template <typename T>
+void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T* cv, const T* u, const double* p,
+                        T* v, double* q, hipStream_t s) {
+    CellArgs<T> args = phase_args<T>(L, 0, K, cv);
+    args.cend = L.phase_off[L.nphases()];
+    args.nrows = (args.cend - args.cbeg) / L.cells[0];
+    args.u = u;
+    args.p = p;
+    args.v = v;
+    args.q = q;
+    if (mode & (OP_A | OP_BT)) launch_fill<T>(v, T(0), L.nv, s);
+    if (mode & OP_B) launch_fill<double>(q, 0.0, L.np, s);
+    auto go = [&](auto mc) {
+        constexpr int M = decltype(mc)::value | OP_ATOM;
+        constexpr int W0 = (sizeof(T) == 8 && !((M & OP_A) && (M & OP_BT))) ? 2 : 1;
+        if (shape == 0) launch_one<T, M, 1, true, W0>(L, args, s);
+        else launch_one<T, M, 4, true, W0>(L, args, s);
+    };
+    switch (mode) {
+        case OP_A: go(std::integral_constant<int, OP_A>{}); break;
+        case OP_B: go(std::integral_constant<int, OP_B>{}); break;
+        case OP_BT: go(std::integral_constant<int, OP_BT>{}); break;
+        case OP_A | OP_BT: go(std::integral_constant<int, OP_A | OP_BT>{}); break;
+        default: go(std::integral_constant<int, OP_A | OP_BT | OP_B>{}); break;
+    }
+}
+
 template <typename T>
 void launch_cell_cheb(const Level& L, int variant, int phase, const T* K, const T* cv, T* x, T* d, const T* r,
                       const T* dinv, T* v, double c1, double c2, bool first, bool store_d, hipStream_t s) {
@@ -1225,6 +1276,10 @@ void launch_cell_res_all(const Level& L, int variant, const T* K, const T* cv, c
     for (int ph = 0; ph < L.nphases(); ++ph) launch_cell_res<T>(L, variant, ph, K, cv, u, p, f_u, f_p, r_u, r_p, s);
 }
 
+template void launch_cell_atomic<double>(const Level&, int, int, const double*, const double*, const double*,
+                                         const double*, double*, double*, hipStream_t);
+template void launch_cell_atomic<float>(const Level&, int, int, const float*, const float*, const float*,
+                                        const double*, float*, double*, hipStream_t);
 template void launch_cell<double>(const Level&, int, int, int, const double*, const double*, const double*,
                                   const double*, double*, double*, hipStream_t);
 template void launch_cell<float>(const Level&, int, int, int, const float*, const float*, const float*,

@@ -26,6 +26,10 @@ FSI_ERR_BREAKDOWN = -6
 FSI_ERR_NONFINITE = -7
 PREC_FP64 = 0
 PREC_MIXED = 1
+# cell-kernel launch variants that fsi_set_tuning accepts (0 .. N_LAUNCH_VARIANTS - 1)
+N_LAUNCH_VARIANTS = 16
+# fsi_set_tuning values of the single atomic launch over all phases (3D levels)
+ATOMIC_VARIANTS = (16, 17)
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_STATE", -3: "ERR_HIP", -4: "ERR_OOM",
                 -5: "ERR_INVERTED_CELL", -6: "ERR_BREAKDOWN", -7: "ERR_NONFINITE"}
@@ -238,7 +242,8 @@ class Context:
 
 
     def set_tuning(self, level: int, precision: int, variant: int):
-        """Pin the launch variant of every operator class on a level (overrides autotune)."""
+        """Pin the launch variant (0 .. N_LAUNCH_VARIANTS - 1) of every operator class on a
+        level (overrides autotune)."""
         self._check(self.lib.fsi_set_tuning(self.h, level, precision, variant))
     def time_operator(self, level: int, precision: int = 0, mode: int = 1, reps: int = 10):
         """(cell-kernel us, operator us, launches) of one application: medians over `reps`

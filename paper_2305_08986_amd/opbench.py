@@ -22,7 +22,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--mode", default="A", choices=sorted(MODES))
     ap.add_argument("--prec", default="fp64", help="fp64, fp32 or a comma-separated list")
-    ap.add_argument("--variant", default="", help="launch variant(s) 0..11 to pin, comma-separated")
+    ap.add_argument("--variant", default="", help="launch variant(s) 0..15 to pin, comma-separated")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--level", type=int, default=-1)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch variant")

@@ -171,9 +171,10 @@ def test_full_size_operators_in_the_tuned_launch_shapes(name):
 
 @pytest.mark.parametrize("name", ["T3_R", "T3_16", "T3_4"])
 def test_every_launch_variant_gives_the_same_operator(name):
-    """Each of the 12 launch variants (one or four wavefronts per row, streaming or
+    """Each of the 16 launch variants (one to four wavefronts per row, streaming or
     cached geometry loads, register caps) computes the same FP64 and FP32 applies;
     FP64 also against the oracle."""
+    from paper_2305_08986_amd import fsi
     wl, ctx, ops = _ctx_and_ops(name)
     ctx.set_mg_params(tuned=1)
     rng = np.random.default_rng(17)
@@ -184,7 +185,7 @@ def test_every_launch_variant_gives_the_same_operator(name):
     ref_v, ref_q = op.apply_stokes(u, p)
     ref_a = op.apply_A(u)
     base = None
-    for var in range(12):
+    for var in range(fsi.N_LAUNCH_VARIANTS):
         for prec in (0, 1):
             ctx.set_tuning(j, prec, var)
         ut, pt = torch.from_numpy(u).cuda(), torch.from_numpy(p).cuda()
@@ -199,6 +200,44 @@ def test_every_launch_variant_gives_the_same_operator(name):
             base = (got, got32)
         for g, b in zip(got + got32, base[0] + base[1]):
             assert np.array_equal(g, b), (name, var)
+
+
+@pytest.mark.parametrize("name", ["T3_R", "T3_16", "T3_4"])
+def test_atomic_single_launch_matches_oracle(name):
+    """The single launch over all phases with atomic adds (pinned on every level, both
+    shapes) gives the oracle's operators: FP64 to 1e-12, FP32 to 1e-5, wall rows exact."""
+    from paper_2305_08986_amd import fsi
+    wl, ctx, ops = _ctx_and_ops(name)
+    ctx.set_mg_params(tuned=1)
+    rng = np.random.default_rng([23, len(name)])
+    try:
+        for var in fsi.ATOMIC_VARIANTS:
+            for j in range(ctx.n_levels):
+                for prec in (0, 1):
+                    ctx.set_tuning(j, prec, var)
+            for j in sorted({0, ctx.n_levels - 1, ctx.n_levels // 2}):
+                op = ops[j]
+                u = rng.uniform(-1, 1, op.box.n_vel)
+                p = rng.uniform(-1, 1, op.box.n_p)
+                ut, pt = torch.from_numpy(u).cuda(), torch.from_numpy(p).cuda()
+                ra, rb, rbt = op.apply_A(u), op.apply_B(u), op.apply_BT(p)
+                rv, rq = op.apply_stokes(u, p)
+                a = ctx.apply_A(j, ut)
+                assert np.array_equal(a.cpu().numpy()[op.dir_mask], u[op.dir_mask])
+                _cmp(a, ra, 1e-12, f"{name} var{var} L{j} A")
+                _cmp(ctx.apply_B(j, ut), rb, 1e-12, f"{name} var{var} L{j} B")
+                _cmp(ctx.apply_BT(j, pt), rbt, 1e-12, f"{name} var{var} L{j} BT")
+                v, q = ctx.apply_stokes(j, ut, pt)
+                _cmp(v, rv, 1e-12, f"{name} var{var} L{j} stokes-v")
+                _cmp(q, rq, 1e-12, f"{name} var{var} L{j} stokes-q")
+                _cmp(ctx.apply_A(j, ut.float()), ra, 1e-5, f"{name} var{var} L{j} fp32 A")
+                v32, q32 = ctx.apply_stokes(j, ut.float(), pt.float())
+                _cmp(v32, rv, 1e-5, f"{name} var{var} L{j} fp32 stokes-v")
+                _cmp(q32, rq, 1e-5, f"{name} var{var} L{j} fp32 stokes-q")
+    finally:
+        for j in range(ctx.n_levels):
+            for prec in (0, 1):
+                ctx.set_tuning(j, prec, 0)
 
 
 def test_jacobian_input_path_matches_oracle_and_keeps_stored_fp32_geometry():

@@ -70,6 +70,7 @@ def test_corrector_apply_matches_oracle(name):
 
 
 def test_corrector_every_launch_variant_same_result():
+    from paper_2305_08986_amd import fsi
     wl, ctx, conv = _setup("T3_R")
     ctx.set_mg_params(tuned=1)
     j = ctx.n_levels - 1
@@ -78,7 +79,7 @@ def test_corrector_every_launch_variant_same_result():
     u = torch.from_numpy(rng.uniform(-1, 1, box.n_vel)).cuda()
     p = torch.from_numpy(rng.uniform(-1, 1, box.n_p)).cuda()
     base = None
-    for var in range(12):
+    for var in range(fsi.N_LAUNCH_VARIANTS):
         for prec in (0, 1):
             ctx.set_tuning(j, prec, var)
         got = [t.cpu().numpy() for t in ctx.apply_corrector(j, u, p)]

@@ -59,7 +59,7 @@ def test_argument_errors():
     s = fsi.Sizes()
     assert ctx.lib.fsi_get_sizes(ctx.h, ctx.n_levels, ctypes.byref(s)) == fsi.FSI_ERR_ARG
     # launch variants and solve options out of range
-    for lev, prec, var in ((ctx.n_levels, 0, 0), (0, 2, 0), (0, 0, 12), (0, 1, -1)):
+    for lev, prec, var in ((ctx.n_levels, 0, 0), (0, 2, 0), (0, 0, fsi.N_LAUNCH_VARIANTS + len(fsi.ATOMIC_VARIANTS)), (0, 1, -1)):
         assert ctx.lib.fsi_set_tuning(ctx.h, lev, prec, var) == fsi.FSI_ERR_ARG
     fsi.setup_workload(ctx, wl)
     ctx.setup()
