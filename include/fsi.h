@@ -260,8 +260,11 @@ fsi_status fsi_solve_extension(fsi_ctx* ctx, const double* g, double* u, const f
 /* Autotuner: times the cell-kernel launch variants (wavefronts per workgroup,
  * register cap, cached or streaming geometry loads) for every operator class
  * (A, A with the fused Chebyshev step, Stokes, Stokes with the fused residual,
- * B, B^T), level and precision, and keeps the fastest of each.  Synchronises;
- * fsi_get_tuning reports the choice for A. */
+ * B, B^T), level and precision, and keeps the fastest of each; then, per 3D level,
+ * the phased launches of the unfused applies against their single atomic launch
+ * (variants 16, 17 below), and the fused epilogues against the separate vector
+ * kernels.  Synchronises; fsi_get_tuning reports the choice for A (16 or 17 where the
+ * atomic launch was chosen). */
 fsi_status fsi_autotune(fsi_ctx* ctx);
 fsi_status fsi_get_tuning(const fsi_ctx* ctx, int level, int precision, int* variant, double* best_us);
 /* Pin the launch variant (0 .. 15) of every operator class on one level and
@@ -286,9 +289,11 @@ fsi_status fsi_set_tuning(fsi_ctx* ctx, int level, int precision, int variant);
  * internal work vectors, timing every launch of the cell kernel with HIP events
  * on the context's stream, after three untimed warm-up applications.
  * kernel_us = cell-kernel time of one application (sum over its n_launches
- * launches, one per processing phase), op_us = duration of the whole
- * application (including the wall rows); both are medians over the `reps`
- * timed applications.  Synchronises.  Errors: FSI_ERR_ARG, FSI_ERR_STATE. */
+ * launches, one per processing phase; with tuned = 1 on a level where the
+ * autotuner chose the single atomic launch, that one launch with the zeroing of
+ * its outputs, n_launches = 1), op_us = duration of the whole application
+ * (including the wall rows); both are medians over the `reps` timed
+ * applications.  Synchronises.  Errors: FSI_ERR_ARG, FSI_ERR_STATE. */
 fsi_status fsi_time_operator(fsi_ctx* ctx, int level, int precision, int mode, int reps,
                              double* kernel_us, double* op_us, int* n_launches);
 

@@ -297,7 +297,7 @@ static void op_apply(Context* ctx, int j, int mode, const T* u, const double* p,
     // every output entry is written by its first touching cell (no clearing pass);
     // wall rows: identity for A, zero for B^T alone
     const Level& L = ctx->lv[j];
-    const int am = ctx->prm.tuned ? ctx->atom[prec_index<T>()][j] : -1;
+    const int am = ctx->prm.tuned ? ctx->atom_of(prec_index<T>(), j, mode & ~OP_CONV) : -1;
     if (am >= 0 && L.dim == 3 && !(mode & OP_CONV))
         launch_cell_atomic<T>(L, mode, am, Kmode<T>(L, mode), CVp<T>(L), u, p, v, q, s);
     else
@@ -865,7 +865,7 @@ fsi_status fsi_create(fsi_ctx** out, const fsi_mesh_desc* m, void* hip_stream) {
         ctx->tune_us[pi].assign((size_t)ctx->nlev * kTuneClasses, 0.0);
         ctx->fuse_cheb[pi].assign(ctx->nlev, 1);
         ctx->fuse_res[pi].assign(ctx->nlev, 1);
-        ctx->atom[pi].assign(ctx->nlev, -1);
+        ctx->atom[pi].assign((size_t)ctx->nlev * kTuneClasses, -1);
     }
     if (st != FSI_OK) {
         fsi_destroy(h);
@@ -1559,19 +1559,17 @@ fsi_status fsi_autotune(fsi_ctx* h) {
                 ctx->tune_variant[pi][(size_t)j * kTuneClasses + cls] = bestv;
                 ctx->tune_us[pi][(size_t)j * kTuneClasses + cls] = best;
             }
-    // phased launches (tuned) against the single atomic launch, over the unfused
-    // classes A, Stokes, B, B^T together
+    // per unfused class (A, Stokes, B, B^T): phased launches (tuned variant) against
+    // the single atomic launch in either shape
     const int unfused[4] = {OP_A, OP_A | OP_BT | OP_B, OP_B, OP_BT};
     for (int pi = 0; pi < 2; ++pi)
-        for (int j = 0; j < ctx->nlev; ++j) {
-            ctx->atom[pi][j] = -1;
-            if (ctx->lv[j].dim != 3) continue;
-            double phased = 0;
-            for (int m : unfused) phased += ctx->tune_us[pi][(size_t)j * kTuneClasses + tune_class(m)];
-            double best = phased;
-            for (int shape = 0; shape < 2; ++shape) {
-                double tot = 0;
-                for (int m : unfused) {
+        for (int j = 0; j < ctx->nlev; ++j)
+            for (int m : unfused) {
+                const size_t k = (size_t)j * kTuneClasses + tune_class(m);
+                ctx->atom[pi][k] = -1;
+                if (ctx->lv[j].dim != 3) continue;
+                double best = ctx->tune_us[pi][k];
+                for (int shape = 0; shape < 2; ++shape) {
                     const int reps = 3;
                     for (int r = 0; r <= reps; ++r) {
                         if (r == 1) FSI_HIP_TRY(hipEventRecord(e0, s));
@@ -1581,17 +1579,16 @@ fsi_status fsi_autotune(fsi_ctx* h) {
                     FSI_HIP_TRY(hipEventSynchronize(e1));
                     float ms = 0;
                     FSI_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                    tot += 1000.0 * ms / reps;
-                }
-                if (getenv("FSI_TUNE_VERBOSE"))
-                    fprintf(stderr, "[fsi autotune] precision %d level %d unfused applies %.1f us phased / %.1f us atomic "
-                            "(shape %d)\n", pi, j, phased, tot, shape);
-                if (tot < best) {
-                    best = tot;
-                    ctx->atom[pi][j] = (int8_t)shape;
+                    const double us = 1000.0 * ms / reps;
+                    if (getenv("FSI_TUNE_VERBOSE"))
+                        fprintf(stderr, "[fsi autotune] precision %d level %d mode %d: %.1f us phased / %.1f us atomic "
+                                "(shape %d)\n", pi, j, m, ctx->tune_us[pi][k], us, shape);
+                    if (us < best) {
+                        best = us;
+                        ctx->atom[pi][k] = (int8_t)shape;
+                    }
                 }
             }
-        }
     // fused epilogues against operator + separate vector kernel, each with its tuned variant
     auto timed = [&](auto&& body, double* us) -> fsi_status {
         body();
@@ -1610,8 +1607,8 @@ fsi_status fsi_autotune(fsi_ctx* h) {
             auto var = [&](int mode) { return ctx->tune_variant[pi][(size_t)j * kTuneClasses + tune_class(mode)]; };
             auto all = [&](int mode) {
                 const bool epilogue = (mode & (OP_CHEB | OP_RES)) != 0;
-                if (!epilogue && ctx->atom[pi][j] >= 0) {
-                    launch_atomic_on_work(ctx, pi, j, mode, ctx->atom[pi][j], s);
+                if (!epilogue && ctx->atom_of(pi, j, mode) >= 0) {
+                    launch_atomic_on_work(ctx, pi, j, mode, ctx->atom_of(pi, j, mode), s);
                     return;
                 }
                 for (int ph = 0; ph < L.nphases(); ++ph) launch_phase_on_work(ctx, pi, j, mode, var(mode), ph, s);
@@ -1659,10 +1656,15 @@ fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int
     TRY(alloc_work<float>(ctx));
     const Level& L = ctx->lv[level];
     hipStream_t s = ctx->stream;
-    const int nph = L.nphases();
+    // tuned levels where the autotuner chose the single atomic launch time that launch
+    // (with the zeroing of its outputs) as one unit
+    const int am = (ctx->prm.tuned && !fused_mode && !conv_mode) ? ctx->atom_of(precision, level, mode) : -1;
+    const bool atomic = am >= 0 && L.dim == 3;
+    const int nph = atomic ? 1 : L.nphases();
     std::vector<hipEvent_t> ev((size_t)2 * nph + 2);
     for (auto& e : ev) FSI_HIP_TRY(hipEventCreate(&e));
     const int var = variant_of(ctx, precision, level, mode);
+    auto nonempty = [&](int ph) { return atomic || L.phase_off[ph + 1] > L.phase_off[ph]; };
     constexpr int kWarmup = 3;
     std::vector<double> kt, ot;
     int launched = 0;
@@ -1671,8 +1673,9 @@ fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int
         launched = 0;
         for (int ph = 0; ph < nph; ++ph) {
             FSI_HIP_TRY(hipEventRecord(ev[1 + 2 * ph], s));
-            if (L.phase_off[ph + 1] > L.phase_off[ph]) ++launched;
-            launch_phase_on_work(ctx, precision, level, mode, var, ph, s);
+            if (nonempty(ph)) ++launched;
+            if (atomic) launch_atomic_on_work(ctx, precision, level, mode, am, s);
+            else launch_phase_on_work(ctx, precision, level, mode, var, ph, s);
             FSI_HIP_TRY(hipEventRecord(ev[2 + 2 * ph], s));
         }
         if (precision == 0) {
@@ -1690,7 +1693,7 @@ fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int
         float ms;
         double ksum = 0.0;
         for (int ph = 0; ph < nph; ++ph) {
-            if (L.phase_off[ph + 1] == L.phase_off[ph]) continue;
+            if (!nonempty(ph)) continue;
             FSI_HIP_TRY(hipEventElapsedTime(&ms, ev[1 + 2 * ph], ev[2 + 2 * ph]));
             ksum += ms;
         }
@@ -1721,7 +1724,8 @@ fsi_status fsi_set_tuning(fsi_ctx* h, int level, int precision, int variant) {
         return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: the single atomic launch is 3D only");
     for (int c = 0; c < kTuneClasses; ++c)
         ctx->tune_variant[precision][(size_t)level * kTuneClasses + c] = atomic ? 0 : variant;
-    ctx->atom[precision][level] = atomic ? (int8_t)(variant - kNumVariants) : (int8_t)-1;
+    for (int c = 0; c < kTuneClasses; ++c)
+        ctx->atom[precision][(size_t)level * kTuneClasses + c] = atomic ? (int8_t)(variant - kNumVariants) : (int8_t)-1;
     if (ctx->setup_done) TRY(capture_graphs(ctx));   // captured graphs hold the old launch shapes
     return FSI_OK;
 }
@@ -1730,7 +1734,8 @@ fsi_status fsi_get_tuning(const fsi_ctx* h, int level, int precision, int* varia
     if (!h || !variant || !best_us) return FSI_ERR_ARG;
     const Context* ctx = &h->c;
     if (level < 0 || level >= ctx->nlev || (precision != 0 && precision != 1)) return FSI_ERR_ARG;
-    *variant = ctx->tune_variant[precision][(size_t)level * kTuneClasses];       // class A
+    const int am = ctx->atom[precision][(size_t)level * kTuneClasses];   // class A
+    *variant = am >= 0 ? kNumVariants + am : ctx->tune_variant[precision][(size_t)level * kTuneClasses];   // class A
     *best_us = ctx->tune_us[precision][(size_t)level * kTuneClasses];
     return FSI_OK;
 }

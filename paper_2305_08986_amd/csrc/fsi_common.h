@@ -195,6 +195,19 @@ struct Krylov {
     double* h_host = nullptr;      // pinned host mirror
 };
 
+// cell-operator launch variants (wavefronts per workgroup, load kind, register cap)
+constexpr int kNumVariants = 16;
+// launch variants are tuned per operator class: A, A with the Chebyshev epilogue,
+// Stokes, Stokes with the residual epilogue, B, B^T
+constexpr int kTuneClasses = 6;
+constexpr int kTuneModes[kTuneClasses] = {OP_A, OP_A | OP_CHEB, OP_A | OP_BT | OP_B, OP_A | OP_BT | OP_B | OP_RES,
+                                          OP_B, OP_BT};
+inline int tune_class(int mode) {
+    for (int c = 0; c < kTuneClasses; ++c)
+        if (kTuneModes[c] == mode) return c;
+    return 2;   // A + B^T is timed as the Stokes class
+}
+
 struct Context {
     fsi_mesh_desc mesh{};
     int nlev = 0;
@@ -237,27 +250,20 @@ struct Context {
     // per level and precision: use the fused Chebyshev / residual epilogue (when the
     // fused path is enabled); the autotuner keeps whichever it measured faster
     std::vector<uint8_t> fuse_cheb[2], fuse_res[2];
-    // per level and precision: -1 phased launches; 0 or 1 the single atomic launch
-    // (one or four wavefronts per row) for the unfused applies, where the autotuner
-    // measured it faster (results then vary in the last bits from run to run)
+    // per level, operator class (as tune_variant) and precision: -1 phased launches;
+    // 0 or 1 the single atomic launch (one or four wavefronts per row) of an unfused
+    // class, where the autotuner measured it faster (results then vary in the last
+    // bits from run to run)
     std::vector<int8_t> atom[2];
+    int atom_of(int prec, int level, int mode) const {
+        return atom[prec][(size_t)level * kTuneClasses + tune_class(mode)];
+    }
     std::vector<void*> allocations;
 };
 
 // ---------------------------------------------------------------- launchers (kernels_*.hip)
 // cell operator on one colour range; mode = OP_* bits; variant selects the
 // workgroup size (wavefronts per workgroup) and block->tile mapping.
-constexpr int kNumVariants = 16;
-// launch variants are tuned per operator class: A, A with the Chebyshev epilogue,
-// Stokes, Stokes with the residual epilogue, B, B^T
-constexpr int kTuneClasses = 6;
-constexpr int kTuneModes[kTuneClasses] = {OP_A, OP_A | OP_CHEB, OP_A | OP_BT | OP_B, OP_A | OP_BT | OP_B | OP_RES,
-                                          OP_B, OP_BT};
-inline int tune_class(int mode) {
-    for (int c = 0; c < kTuneClasses; ++c)
-        if (kTuneModes[c] == mode) return c;
-    return 2;   // A + B^T is timed as the Stokes class
-}
 template <typename T>
 void launch_cell(const Level& L, int mode, int variant, int phase, const T* K, const T* cv,
                  const T* u, const double* p, T* v, double* q, hipStream_t s);
