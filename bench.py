@@ -123,7 +123,8 @@ def corrector_measure(name, ctx, W, np, torch, fsi, solve_workload: str = "C2", 
     """Corrector mode (convection and streamline terms, Sec. 3.1.1 and 3.2): the Stokes
     apply with the terms on the bench workload's finest level (FP64 and FP32, median of
     timed applications), and the corrector solve (k_A = 6, BiCGStab Schur step) on the
-    64^3 box to rtol 1e-8: plain FP64 path, optimised FP64 and mixed precision."""
+    64^3 box to rtol 1e-8: plain FP64 path, optimised FP64 and mixed precision (the last
+    two: the median of three solves)."""
     J = ctx.n_levels - 1
     sz = ctx.sizes(J)
     wl = W.make_workload(name, levels=[J])
@@ -156,13 +157,22 @@ def corrector_measure(name, ctx, W, np, torch, fsi, solve_workload: str = "C2", 
     gp = torch.from_numpy(wl.g_p).cuda()
     res = {}
     sol = {}
-    for label, prm in (("plain_fp64", dict(precision=0, use_graph=0, fused=0, tuned=0)),
-                       ("fp64", dict(precision=0)), ("mixed", dict(precision=1))):
+    # the tuned paths may add with atomics on some levels, and the mixed corrector
+    # preconditioner's iteration count moves with rounding: median of three solves
+    for label, prm, runs in (("plain_fp64", dict(precision=0, use_graph=0, fused=0, tuned=0), 1),
+                             ("fp64", dict(precision=0), 3), ("mixed", dict(precision=1), 3)):
         cctx.set_mg_params(corrector=1, k_A=6, **prm)
-        u, p, info = cctx.solve(gu, gp, rtol=rtol, max_iter=300)
+        got = []
+        for _ in range(runs):
+            u, p, info = cctx.solve(gu, gp, rtol=rtol, max_iter=300)
+            got.append((info["time_ms"], info, u))
+        got.sort(key=lambda g: g[0])
+        ms, info, u = got[len(got) // 2]
         sol[label] = u
-        res[label] = dict(ms=round(info["time_ms"], 1), iters=info["iters"], rel_res=info["rel_res"],
-                          status=info["status"])
+        res[label] = dict(ms=round(ms, 1), iters=info["iters"], rel_res=info["rel_res"], status=info["status"])
+        if runs > 1:
+            res[label]["runs_ms"] = [round(g[0], 1) for g in got]
+            res[label]["runs_iters"] = [g[1]["iters"] for g in got]
     du = float(torch.linalg.vector_norm(sol["mixed"] - sol["fp64"]) / torch.linalg.vector_norm(sol["fp64"]))
     out["solve"] = {"workload": solve_workload, "rtol": rtol, "k_A": 6, "setup_ms": round(setup_ms, 1), **res,
                     "speedup_mixed_vs_plain_fp64": round(res["plain_fp64"]["ms"] / res["mixed"]["ms"], 3),
