@@ -105,6 +105,12 @@ typedef struct {
                                 epilogues are not used; set k_A = 6 for Table 4's corrector
                                 column.  0: predictor mode (default).  Changing it needs a new
                                 setup. */
+    int atomics;             /* 1 (default): with tuned = 1, the operator classes for which
+                                fsi_autotune chose the single atomic launch over all processing
+                                phases use it (faster on latency-bound levels; the order of the
+                                atomic adds varies, so results differ in the last bits from run
+                                to run); 0: phased launches only, bitwise reproducible.
+                                Switching needs no new setup. */
 } fsi_mg_params;
 
 typedef struct {

@@ -286,6 +286,12 @@ static int variant_of(const Context* ctx, int prec, int level, int mode) {
     return k < v.size() ? v[k] : 0;
 }
 
+// the parameters that change what a captured graph launches
+static int path_key(const Context* ctx) {
+    return (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0) |
+           (ctx->prm.corrector ? 8 : 0) | (ctx->prm.atomics ? 16 : 0);
+}
+
 // the solver's velocity block: A, or in the corrector mode A + N + S
 static int solver_mode(const Context* ctx, int mode) {
     return (ctx->prm.corrector && (mode & OP_A)) ? (mode | OP_CONV) : mode;
@@ -297,7 +303,7 @@ static void op_apply(Context* ctx, int j, int mode, const T* u, const double* p,
     // every output entry is written by its first touching cell (no clearing pass);
     // wall rows: identity for A, zero for B^T alone
     const Level& L = ctx->lv[j];
-    const int am = ctx->prm.tuned ? ctx->atom_of(prec_index<T>(), j, mode & ~OP_CONV) : -1;
+    const int am = (ctx->prm.tuned && ctx->prm.atomics) ? ctx->atom_of(prec_index<T>(), j, mode & ~OP_CONV) : -1;
     if (am >= 0 && L.dim == 3 && !(mode & OP_CONV))
         launch_cell_atomic<T>(L, mode, am, Kmode<T>(L, mode), CVp<T>(L), u, p, v, q, s);
     else
@@ -442,7 +448,7 @@ static fsi_status capture_graphs(Context* ctx);
 
 static fsi_status run_vcycle(Context* ctx, hipStream_t s) {
     const int pi = ctx->prm.precision == FSI_PREC_MIXED ? 1 : 0;
-    const int key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0) | (ctx->prm.corrector ? 8 : 0);
+    const int key = path_key(ctx);
     if (ctx->prm.use_graph && ctx->graph_valid[pi] && ctx->graph_key != key) TRY(capture_graphs(ctx));
     if (ctx->prm.use_graph && ctx->graph_valid[pi]) {
         FSI_HIP_TRY(hipGraphLaunch(ctx->graph[pi], s));
@@ -480,7 +486,7 @@ static fsi_status capture_graphs(Context* ctx) {
         ctx->graph_valid[pi] = true;
     }
     hipStreamDestroy(cs);
-    ctx->graph_key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0) | (ctx->prm.corrector ? 8 : 0);
+    ctx->graph_key = path_key(ctx);
     return FSI_OK;
 }
 
@@ -772,7 +778,7 @@ static fsi_status ext_run_precond(Context* ctx, const double* r, double* z, hipS
         else ext_precondition<double>(ctx, r, z, s);
         return FSI_OK;
     }
-    const int key = (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0) | (ctx->prm.corrector ? 8 : 0);
+    const int key = path_key(ctx);
     if (!ctx->ext_graph_valid[pi] || ctx->ext_graph_key[pi] != key) {
         if (ctx->ext_graph_valid[pi]) {
             hipGraphExecDestroy(ctx->ext_graph[pi]);
@@ -818,6 +824,7 @@ void fsi_default_mg_params(fsi_mg_params* p) {
     p->tuned = 1;
     p->vertex_geometry = 0;   // measured slower than the stored values on MI355X
     p->corrector = 0;
+    p->atomics = 1;
 }
 
 fsi_status fsi_create(fsi_ctx** out, const fsi_mesh_desc* m, void* hip_stream) {
@@ -982,7 +989,7 @@ fsi_status fsi_set_mg_params(fsi_ctx* h, const fsi_mg_params* p) {
     Context* ctx = &h->c;
     if (p->k_A < 1 || p->m < 0 || p->n_cycles < 1 || p->k_S != 1 || p->n_S != 1 || !(p->cheb_upper > 0) ||
         !(p->cheb_ratio > 1) || p->n_eig < 1 || (p->precision != FSI_PREC_FP64 && p->precision != FSI_PREC_MIXED) ||
-        (p->corrector != 0 && p->corrector != 1))
+        (p->corrector != 0 && p->corrector != 1) || (p->atomics != 0 && p->atomics != 1))
         return fail(ctx, FSI_ERR_ARG, "invalid multigrid parameters (only k_S = n_S = 1 are implemented)");
     const fsi_mg_params& o = ctx->prm;
     // precision and graph use select among already prepared paths; the rest changes the setup
@@ -1658,7 +1665,7 @@ fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int
     hipStream_t s = ctx->stream;
     // tuned levels where the autotuner chose the single atomic launch time that launch
     // (with the zeroing of its outputs) as one unit
-    const int am = (ctx->prm.tuned && !fused_mode && !conv_mode) ? ctx->atom_of(precision, level, mode) : -1;
+    const int am = (ctx->prm.tuned && ctx->prm.atomics && !fused_mode && !conv_mode) ? ctx->atom_of(precision, level, mode) : -1;
     const bool atomic = am >= 0 && L.dim == 3;
     const int nph = atomic ? 1 : L.nphases();
     std::vector<hipEvent_t> ev((size_t)2 * nph + 2);

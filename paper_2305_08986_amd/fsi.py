@@ -50,7 +50,8 @@ class MGParams(C.Structure):
     _fields_ = [("k_A", C.c_int), ("m", C.c_int), ("n_cycles", C.c_int), ("k_S", C.c_int), ("n_S", C.c_int),
                 ("cheb_upper", C.c_double), ("cheb_ratio", C.c_double), ("n_eig", C.c_int),
                 ("precision", C.c_int), ("use_graph", C.c_int),
-                ("fused", C.c_int), ("tuned", C.c_int), ("vertex_geometry", C.c_int), ("corrector", C.c_int)]
+                ("fused", C.c_int), ("tuned", C.c_int), ("vertex_geometry", C.c_int), ("corrector", C.c_int),
+                ("atomics", C.c_int)]
 
 
 class LevelInfo(C.Structure):

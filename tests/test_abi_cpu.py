@@ -72,7 +72,7 @@ def test_default_parameters_are_the_predictor_column():
     p = fsi.MGParams()
     lib.fsi_default_mg_params(ctypes.byref(p))
     assert (p.k_A, p.m, p.n_cycles, p.k_S, p.n_S) == (4, 2, 1, 1, 1)
-    assert (p.use_graph, p.fused, p.tuned, p.vertex_geometry) == (1, 1, 1, 0)
+    assert (p.use_graph, p.fused, p.tuned, p.vertex_geometry, p.corrector, p.atomics) == (1, 1, 1, 0, 0, 1)
 
 
 def test_invalid_mesh_is_rejected_without_gpu_work():

@@ -126,6 +126,30 @@ def test_vcycle_with_atomic_levels_matches_phased(name):
                 ctx.set_tuning(j, prec, 0)
 
 
+def test_atomics_switch_gives_reproducible_tuned_vcycles():
+    """With the atomic launch pinned on every level, atomics = 0 falls back to the phased
+    launches: repeated tuned V-cycles are then bitwise equal (eager and graph), and
+    atomics = 1 agrees with them to rounding."""
+    from paper_2305_08986_amd import fsi
+    wl, ctx, ops = _setup("T3_8")
+    rng = np.random.default_rng(31)
+    op = ops[-1]
+    ru = torch.from_numpy(rng.uniform(-1, 1, op.box.n_vel) * ~op.dir_mask).cuda()
+    rp = torch.from_numpy(rng.uniform(-1, 1, op.box.n_p)).cuda()
+    for prec, tol in ((0, 1e-12), (1, 1e-5)):
+        for j in range(ctx.n_levels):
+            ctx.set_tuning(j, prec, fsi.ATOMIC_VARIANTS[1])
+        ref_u, ref_p = _vc(ctx, ru, rp, precision=prec, fused=0, tuned=1, use_graph=0, atomics=0)
+        for graph in (0, 1, 1):
+            zu, zp = _vc(ctx, ru, rp, precision=prec, fused=0, tuned=1, use_graph=graph, atomics=0)
+            assert np.array_equal(zu, ref_u) and np.array_equal(zp, ref_p), (prec, graph)
+        zu, zp = _vc(ctx, ru, rp, precision=prec, fused=0, tuned=1, use_graph=1, atomics=1)
+        assert np.linalg.norm(zu - ref_u) <= tol * np.linalg.norm(ref_u), prec
+        assert np.linalg.norm(zp - ref_p) <= tol * np.linalg.norm(ref_p), prec
+        for j in range(ctx.n_levels):
+            ctx.set_tuning(j, prec, 0)
+
+
 def test_graph_replays_match_eager():
     """Replays of the captured V-cycle, with eager work and synchronisations in
     between, all reproduce the eager result."""
