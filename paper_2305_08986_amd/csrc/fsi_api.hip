@@ -304,11 +304,12 @@ static void op_apply(Context* ctx, int j, int mode, const T* u, const double* p,
     // wall rows: identity for A, zero for B^T alone
     const Level& L = ctx->lv[j];
     const int am = (ctx->prm.tuned && ctx->prm.atomics) ? ctx->atom_of(prec_index<T>(), j, mode & ~OP_CONV) : -1;
-    if (am >= 0 && L.dim == 3 && !(mode & OP_CONV))
-        launch_cell_atomic<T>(L, mode, am, Kmode<T>(L, mode), CVp<T>(L), u, p, v, q, s);
-    else
-        launch_cell_all<T>(L, mode, variant_of(ctx, prec_index<T>(), j, mode), Kmode<T>(L, mode), CVp<T>(L), u, p,
-                           v, q, s);
+    if (am >= 0 && L.dim == 3 && !(mode & OP_CONV)) {
+        launch_cell_atomic<T>(L, mode, am, Kmode<T>(L, mode), CVp<T>(L), u, p, v, q, s);   // wall rows included
+        return;
+    }
+    launch_cell_all<T>(L, mode, variant_of(ctx, prec_index<T>(), j, mode), Kmode<T>(L, mode), CVp<T>(L), u, p, v, q,
+                       s);
     if (mode & OP_A) launch_dirichlet_copy<T>(L, u, v, s);
     else if (mode & OP_BT) launch_dirichlet_zero<T>(L, v, s);
 }
@@ -1685,7 +1686,9 @@ fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int
             else launch_phase_on_work(ctx, precision, level, mode, var, ph, s);
             FSI_HIP_TRY(hipEventRecord(ev[2 + 2 * ph], s));
         }
-        if (precision == 0) {
+        if (atomic) {
+            // the atomic launch's initialisation has set the wall rows
+        } else if (precision == 0) {
             LevelWork<double>& W = ctx->w64[level];
             if (mode & OP_A) launch_dirichlet_copy<double>(L, W.x_u, W.r_u, s);
             else if (mode & OP_BT) launch_dirichlet_zero<double>(L, W.r_u, s);

@@ -270,8 +270,8 @@ void launch_cell(const Level& L, int mode, int variant, int phase, const T* K, c
 template <typename T>
 void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T* cv,
                      const T* u, const double* p, T* v, double* q, hipStream_t s);
-// the same apply in one launch over all phases with atomic adds (3D; modes A, B, B^T
-// and A + B^T + B; shape 0 or 1: one or four wavefronts per row)
+// the same apply in one launch over all phases with atomic adds, wall rows included
+// (3D; modes A, B, B^T and A + B^T + B; shape 0 or 1: one or four wavefronts per row)
 template <typename T>
 void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T* cv,
                         const T* u, const double* p, T* v, double* q, hipStream_t s);
@@ -313,6 +313,9 @@ inline const uint8_t* level_wall_mask(const Level& L) { return L.d_wall; }
 
 template <typename T>
 void launch_fill(T* x, T val, int64_t n, hipStream_t s);
+// v = 0 except v[wall] = u[wall] (u may be null: zero there too), q = 0; v or q may be null
+template <typename T>
+void launch_atomic_init(const Level& L, const T* u, T* v, double* q, hipStream_t s);
 template <typename T>
 void launch_dirichlet_copy(const Level& L, const T* u, T* v, hipStream_t s);   // v[wall] = u[wall]
 template <typename T>

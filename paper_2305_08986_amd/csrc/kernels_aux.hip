@@ -550,6 +550,27 @@ void launch_dirichlet_copy(const Level& L, const T* u, T* v, hipStream_t s) {
 template void launch_dirichlet_copy<double>(const Level&, const double*, double*, hipStream_t);
 template void launch_dirichlet_copy<float>(const Level&, const float*, float*, hipStream_t);
 
+// outputs of the single atomic cell launch: v = 0 except on wall nodes, where v = u
+// (u null: 0 there too), and q = 0; either output may be null
+template <typename T>
+__global__ void k_atomic_init(const uint8_t* __restrict__ wall, int dim, int64_t nvn, const T* __restrict__ u,
+                              T* __restrict__ v, double* __restrict__ q, int64_t np) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v && i < nvn) {
+        const bool w = u && wall[i];
+        for (int c = 0; c < dim; ++c) v[c * nvn + i] = w ? u[c * nvn + i] : T(0);
+    }
+    if (q && i < np) q[i] = 0.0;
+}
+template <typename T>
+void launch_atomic_init(const Level& L, const T* u, T* v, double* q, hipStream_t s) {
+    const int64_t n = std::max(v ? L.nvn : 0, q ? L.np : 0);
+    if (n > 0)
+        hipLaunchKernelGGL(k_atomic_init<T>, dim3(nblocks(n)), dim3(TPB), 0, s, L.d_wall, L.dim, L.nvn, u, v, q, L.np);
+}
+template void launch_atomic_init<double>(const Level&, const double*, double*, double*, hipStream_t);
+template void launch_atomic_init<float>(const Level&, const float*, float*, double*, hipStream_t);
+
 template <typename T>
 __global__ void k_dir_zero(const int* __restrict__ nodes, int64_t nd, int dim, int64_t nvn, T* __restrict__ v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -1203,10 +1203,11 @@ void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T*
     for (int ph = 0; ph < L.nphases(); ++ph) launch_cell<T>(L, mode, variant, ph, K, cv, u, p, v, q, s);
 }
 
-// every phase in one launch (3D, modes A, B, B^T, A + B^T + B): the outputs are
-// zeroed, then each cell adds its contributions atomically.  shape 0: one wavefront
-// per row; 1: four wavefronts share a row.  Wall rows are left at zero (the callers'
-// Dirichlet kernels follow as for the phased launches).
+// every phase in one launch (3D, modes A, B, B^T, A + B^T + B): one kernel sets the
+// outputs (zero, and on wall rows v = u when A is applied, else zero: the rows the
+// phased launches leave to the Dirichlet kernels), then each cell adds its
+// contributions atomically.  shape 0: one wavefront per row; 1: four wavefronts
+// share a row.
 template <typename T>
 void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T* cv, const T* u, const double* p,
                         T* v, double* q, hipStream_t s) {
@@ -1217,8 +1218,8 @@ void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T
     args.p = p;
     args.v = v;
     args.q = q;
-    if (mode & (OP_A | OP_BT)) launch_fill<T>(v, T(0), L.nv, s);
-    if (mode & OP_B) launch_fill<double>(q, 0.0, L.np, s);
+    launch_atomic_init<T>(L, (mode & OP_A) ? u : nullptr, (mode & (OP_A | OP_BT)) ? v : nullptr,
+                          (mode & OP_B) ? q : nullptr, s);
     auto go = [&](auto mc) {
         constexpr int M = decltype(mc)::value | OP_ATOM;
         constexpr int W0 = (sizeof(T) == 8 && !((M & OP_A) && (M & OP_BT))) ? 2 : 1;
