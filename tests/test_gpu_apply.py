@@ -205,7 +205,8 @@ def test_every_launch_variant_gives_the_same_operator(name):
 @pytest.mark.parametrize("name", ["T3_R", "T3_16", "T3_4"])
 def test_atomic_single_launch_matches_oracle(name):
     """The single launch over all phases with atomic adds (pinned on every level, both
-    shapes) gives the oracle's operators: FP64 to 1e-12, FP32 to 1e-5, wall rows exact."""
+    shapes) gives the oracle's operators: FP64 to 1e-12, FP32 to 1e-5 (stored geometry and
+    geometry formed from the vertices), wall rows exact."""
     from paper_2305_08986_amd import fsi
     wl, ctx, ops = _ctx_and_ops(name)
     ctx.set_mg_params(tuned=1)
@@ -230,10 +231,19 @@ def test_atomic_single_launch_matches_oracle(name):
                 v, q = ctx.apply_stokes(j, ut, pt)
                 _cmp(v, rv, 1e-12, f"{name} var{var} L{j} stokes-v")
                 _cmp(q, rq, 1e-12, f"{name} var{var} L{j} stokes-q")
-                _cmp(ctx.apply_A(j, ut.float()), ra, 1e-5, f"{name} var{var} L{j} fp32 A")
-                v32, q32 = ctx.apply_stokes(j, ut.float(), pt.float())
-                _cmp(v32, rv, 1e-5, f"{name} var{var} L{j} fp32 stokes-v")
-                _cmp(q32, rq, 1e-5, f"{name} var{var} L{j} fp32 stokes-q")
+                # FP32 with stored geometry and with the geometry formed from the vertices
+                for vg in (0, 1):
+                    ctx.set_mg_params(tuned=1, vertex_geometry=vg)
+                    uf, pf = ut.float(), pt.float()
+                    ru32, rp32 = uf.double().cpu().numpy(), pf.double().cpu().numpy()
+                    _cmp(ctx.apply_A(j, uf), op.apply_A(ru32), 1e-5, f"{name} var{var} L{j} vg{vg} fp32 A")
+                    _cmp(ctx.apply_B(j, uf), op.apply_B(ru32), 1e-5, f"{name} var{var} L{j} vg{vg} fp32 B")
+                    _cmp(ctx.apply_BT(j, pf), op.apply_BT(rp32), 1e-5, f"{name} var{var} L{j} vg{vg} fp32 BT")
+                    v32, q32 = ctx.apply_stokes(j, uf, pf)
+                    rv32, rq32 = op.apply_stokes(ru32, rp32)
+                    _cmp(v32, rv32, 1e-5, f"{name} var{var} L{j} vg{vg} fp32 stokes-v")
+                    _cmp(q32, rq32, 1e-5, f"{name} var{var} L{j} vg{vg} fp32 stokes-q")
+                ctx.set_mg_params(tuned=1)
     finally:
         for j in range(ctx.n_levels):
             for prec in (0, 1):
