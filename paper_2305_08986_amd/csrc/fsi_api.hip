@@ -132,6 +132,22 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
             }
     }
     L.phase_off[nph] = k;
+    // dispatch order of the single atomic launch: natural row g (iy fastest) to its
+    // phase-major row, with XCD-aware slots: slot b < 8q takes g = (b mod 8) q + b / 8
+    // (q = rows / 8), the remaining slots the remaining rows in order
+    const int64_t nrow = L.nc / nx;
+    std::vector<int> atom_rows((size_t)nrow);
+    {
+        std::vector<int64_t> stor((size_t)nrow);   // natural row -> phase-major row
+        int64_t sr = 0;
+        for (int p = 0; p < nph; ++p)
+            for (int64_t r : rows[p]) stor[(size_t)(r / nx)] = sr++;
+        const int64_t q = nrow / 8;
+        for (int64_t b = 0; b < nrow; ++b) {
+            const int64_t g = b < 8 * q ? (b % 8) * q + b / 8 : b;
+            atom_rows[(size_t)b] = (int)stor[(size_t)g];
+        }
+    }
     L.geo.nx = nx;
     L.geo.nchunks = nchunk;
     L.geo.cpw = cpw;
@@ -198,6 +214,7 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
     TRY(dalloc(ctx, &L.d_col2lex, L.nc));
     TRY(dalloc(ctx, &L.d_lex2col, L.nc));
     TRY(dalloc(ctx, &L.d_vmap, L.nc * NLOC));
+    TRY(dalloc(ctx, &L.d_atom_rows, nrow));
     TRY(dalloc(ctx, &L.d_pmap, L.nc * NPL));
     TRY(dalloc(ctx, &L.d_info, L.nc));
     TRY(dalloc(ctx, &L.d_wall, L.nvn));
@@ -205,6 +222,7 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
     FSI_HIP_TRY(hipMemcpy(L.d_col2lex, col2lex.data(), sizeof(int) * L.nc, hipMemcpyHostToDevice));
     FSI_HIP_TRY(hipMemcpy(L.d_lex2col, lex2col.data(), sizeof(int) * L.nc, hipMemcpyHostToDevice));
     FSI_HIP_TRY(hipMemcpy(L.d_vmap, vmap.data(), sizeof(int) * vmap.size(), hipMemcpyHostToDevice));
+    FSI_HIP_TRY(hipMemcpy(L.d_atom_rows, atom_rows.data(), sizeof(int) * atom_rows.size(), hipMemcpyHostToDevice));
     FSI_HIP_TRY(hipMemcpy(L.d_pmap, pmap.data(), sizeof(int) * pmap.size(), hipMemcpyHostToDevice));
     FSI_HIP_TRY(hipMemcpy(L.d_info, info.data(), sizeof(uint4) * info.size(), hipMemcpyHostToDevice));
     FSI_HIP_TRY(hipMemcpy(L.d_wall, L.h_dir_node.data(), (size_t)L.nvn, hipMemcpyHostToDevice));

@@ -73,6 +73,7 @@ struct CellArgs {
     int64_t nchk;       // geometry chunks on the level (stride of the qx blocks)
     const int* __restrict__ vmap;
     const uint4* __restrict__ info;
+    const int* __restrict__ rowmap;   // OP_ATOM: phase-major row of each dispatch slot
     const int* __restrict__ pmap;
     const T* __restrict__ K;
     const T* __restrict__ cv;
@@ -148,8 +149,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane / NT, t = lane - slot * NT;
     const bool inwave = slot < CPW;
-    const int64_t row = RS ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * WPB + wave;
-    const bool rowact = row < a.nrows;
+    const int64_t slot_row = RS ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * WPB + wave;
+    const bool rowact = slot_row < a.nrows;
+    // the atomic form has no order to keep: its dispatch slots follow the row map
+    const int64_t row = (ATOM && rowact) ? (int64_t)a.rowmap[slot_row] : slot_row;
     const int nsteps = RS ? (a.nchunks + WPB - 1) / WPB : a.nchunks;
     const int cw = RS ? 0 : wave;                  // owner of the chunk-to-chunk carry
     const bool carry_out = !RS || wave == WPB - 1; // this wavefront's last cell feeds the next step
@@ -1214,6 +1217,7 @@ void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T
     CellArgs<T> args = phase_args<T>(L, 0, K, cv);
     args.cend = L.phase_off[L.nphases()];
     args.nrows = (args.cend - args.cbeg) / L.cells[0];
+    args.rowmap = L.d_atom_rows;
     args.u = u;
     args.p = p;
     args.v = v;
