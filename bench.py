@@ -72,9 +72,12 @@ def kernel_bytes_per_cell(dim: int, elem: int) -> int:
     return (dim * dim + 1) * q * elem + 2 * (2 ** dim) * dim * elem + 4 * q
 
 
-def load_counter_profile(workload: str):
-    """HBM traffic per colour launch from the committed rocprofv3 counter summary."""
-    path = os.path.join(ROOT, "profiles", f"counters_cell3d_A_fp64_{workload}.json")
+def load_counter_profile(workload: str, form: str = "phased"):
+    """HBM traffic of the FP64 A apply from the committed rocprofv3 counter summary:
+    per processing-phase launch of the default phased form, or per apply (the single
+    launch and its initialisation kernel) of the atomic form."""
+    tag = "" if form == "phased" else "atomic_"
+    path = os.path.join(ROOT, "profiles", f"counters_cell3d_A_fp64_{tag}{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -266,10 +269,12 @@ def main():
     def one_step(record):
         t0 = time.perf_counter()
         # the FP64 A apply in its default launch shape (one wavefront per row, streaming
-        # geometry loads): the kernel the committed counter summary covers
+        # geometry loads, four phase launches) and in the form the autotuner chose (on
+        # the large 3D levels usually the single atomic launch)
         ctx.set_mg_params(tuned=0)
-        k_us, op_us, nl = ctx.time_operator(J, precision=0, mode=1, reps=args.apply_reps)
+        k0_us, op0_us, nl0 = ctx.time_operator(J, precision=0, mode=1, reps=args.apply_reps)
         ctx.set_mg_params(tuned=1)
+        k_us, op_us, nl = ctx.time_operator(J, precision=0, mode=1, reps=args.apply_reps)
         k32_us, op32_us, _ = ctx.time_operator(J, precision=1, mode=1, reps=max(4, args.apply_reps // 2))
         ks_us, ops_us, _ = ctx.time_operator(J, precision=0, mode=7, reps=max(4, args.apply_reps // 2))
         # FP32 A with the geometry formed from the vertex displacements in the kernel
@@ -292,7 +297,7 @@ def main():
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         du = float(torch.linalg.vector_norm(umx - u64) / torch.linalg.vector_norm(u64))
-        rec = dict(k_us=k_us, op_us=op_us, n_launch=nl, k32_us=k32_us, op32_us=op32_us, ks_us=ks_us, ops_us=ops_us,
+        rec = dict(k_us=k_us, op_us=op_us, n_launch=nl, k0_us=k0_us, op0_us=op0_us, n_launch0=nl0, k32_us=k32_us, op32_us=op32_us, ks_us=ks_us, ops_us=ops_us,
                    opv_us=opv_us,
                    apply_s=t1 - t0, setup_s=t2 - t1, solve_s=t3 - t2, fp64=i64, fp64_opt=ift, mixed=imx, du=du,
                    step_s=t3 - t0)
@@ -322,11 +327,17 @@ def main():
     k_us = mean("k_us")
     gdofs = nv / (op_us * 1e-6) / 1e9
     n_launch = recs[-1]["n_launch"]
+    tuned_var = tuning[f"L{J}"][0]
+    atomic = tuned_var >= fsi.N_LAUNCH_VARIANTS
+    op0_us, k0_us, n_launch0 = mean("op0_us"), mean("k0_us"), recs[-1]["n_launch0"]
     bpc = algorithmic_bytes_per_cell(mesh.dim, 8)
-    # algorithmic bytes per launch / mean launch duration (k_us = all launches of one apply)
+    # algorithmic bytes per launch / mean launch duration (k_us = all launches of one
+    # apply; the atomic form: its one launch and the initialisation kernel)
     achieved = bpc * nc / (k_us * 1e-6) / 1e9
     kbpc = kernel_bytes_per_cell(mesh.dim, 8)
-    prof = load_counter_profile(name)
+    # the counter summary must cover the measured form: the atomic one, or the default
+    # phased variant
+    prof = load_counter_profile(name, "atomic") if atomic else (load_counter_profile(name) if tuned_var == 0 else None)
     traffic = None
     flops = None
     if prof is not None:
@@ -362,6 +373,12 @@ def main():
             "fp64_A_kernel_us": round(k_us, 2),
             "fp64_A_launches": n_launch,
             "fp64_A_mean_launch_us": round(k_us / n_launch, 2),
+            "fp64_A_form": (f"single atomic launch over all phases (variant {tuned_var}) + output initialisation"
+                            if atomic else f"phased, variant {tuned_var}"),
+            "fp64_A_phased_default_gdofs": round(nv / (op0_us * 1e-6) / 1e9, 4),
+            "fp64_A_phased_default_us": round(op0_us, 1),
+            "fp64_A_phased_default_mean_launch_us": round(k0_us / n_launch0, 2),
+            "fp64_A_phased_default_roofline_frac": round(bpc * nc / (k0_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
             "fp32_A_gdofs": round(nv / (mean("op32_us") * 1e-6) / 1e9, 4),
             "fp64_stokes_gdofs": round((nv + npr) / (mean("ops_us") * 1e-6) / 1e9, 4),
             "fp32_A_vertex_geometry_gdofs": round(nv / (mean("opv_us") * 1e-6) / 1e9, 4),
@@ -384,9 +401,12 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "achieved_kernel_bytes": round(kbpc * nc / (k_us * 1e-6) / 1e9, 1),
-            "kernel": ("cell3d<double, A>" if mesh.dim == 3 else "cell2d<double, A>")
-                      + f" default launch variant, {n_launch} launches (processing phases) per apply, "
-                      + f"median apply {k_us / n_launch:.1f} us per launch",
+            "kernel": (("cell3d<double, A> as one atomic launch over all phases plus its output "
+                        f"initialisation, autotuned; median apply {k_us:.1f} us (both kernels); traffic per apply")
+                       if atomic else
+                       (("cell3d<double, A>" if mesh.dim == 3 else "cell2d<double, A>")
+                        + f" launch variant {tuned_var}, {n_launch} launches (processing phases) per apply, "
+                        + f"median apply {k_us / n_launch:.1f} us per launch; traffic per launch")),
         },
         "flops": flops,
     }
