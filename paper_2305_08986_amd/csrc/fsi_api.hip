@@ -132,21 +132,14 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
             }
     }
     L.phase_off[nph] = k;
-    // dispatch order of the single atomic launch: natural row g (iy fastest) to its
-    // phase-major row, with XCD-aware slots: slot b < 8q takes g = (b mod 8) q + b / 8
-    // (q = rows / 8), the remaining slots the remaining rows in order
+    // dispatch order of the single atomic launch: slot g takes natural row g (iy
+    // fastest), stored at its phase-major row
     const int64_t nrow = L.nc / nx;
     std::vector<int> atom_rows((size_t)nrow);
     {
-        std::vector<int64_t> stor((size_t)nrow);   // natural row -> phase-major row
         int64_t sr = 0;
         for (int p = 0; p < nph; ++p)
-            for (int64_t r : rows[p]) stor[(size_t)(r / nx)] = sr++;
-        const int64_t q = nrow / 8;
-        for (int64_t b = 0; b < nrow; ++b) {
-            const int64_t g = b < 8 * q ? (b % 8) * q + b / 8 : b;
-            atom_rows[(size_t)b] = (int)stor[(size_t)g];
-        }
+            for (int64_t r : rows[p]) atom_rows[(size_t)(r / nx)] = (int)sr++;
     }
     L.geo.nx = nx;
     L.geo.nchunks = nchunk;

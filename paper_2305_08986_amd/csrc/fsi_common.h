@@ -102,9 +102,9 @@ struct Level {
     int* d_col2lex = nullptr;      // [nc]
     int* d_lex2col = nullptr;      // [nc]
     int* d_vmap = nullptr;         // [nc][NLOC] Q2 node of local node
-    // single atomic launch (3D): phase-major row of each dispatch slot, so that rows
-    // that share node lines run at the same time on the same XCD (slot b goes to XCD
-    // b mod 8; each XCD takes a contiguous range of rows in natural (iy, iz) order)
+    // single atomic launch (3D): phase-major row of each dispatch slot, in natural
+    // (iy, iz) order, so that rows sharing node lines run at the same time and their
+    // repeated touches of a line meet in the caches
     int* d_atom_rows = nullptr;    // [nc / nx]
     int* d_pmap = nullptr;         // [nc][NPL]  Q1 node / vertex of local vertex
     // per cell: x = wall bits of the local Q2 nodes, y = first-touch bits of the
