@@ -1607,6 +1607,7 @@ fsi_status fsi_autotune(fsi_ctx* h) {
                         ctx->atom[pi][k] = (int8_t)shape;
                     }
                 }
+                ctx->tune_us[pi][k] = best;   // the time of the chosen form
             }
     // fused epilogues against operator + separate vector kernel, each with its tuned variant
     auto timed = [&](auto&& body, double* us) -> fsi_status {
