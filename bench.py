@@ -26,7 +26,7 @@ to 1e-6), FP64 and FP32 V-cycle, reported under "extension"; the corrector
 mode (convection and streamline terms): its Stokes apply on the same mesh and
 its solve on the 64^3 box, reported under "corrector".
 
-Prints one JSON line (rank 0, N = 1 only: this build targets one GPU).
+Prints one JSON line (N = 1 only: the library runs the hot path on one GPU).
 """
 from __future__ import annotations
 
@@ -227,7 +227,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs the hot path on one GPU only (no multi-GPU path); "
+        print("bench.py: the library runs the hot path on one GPU only (no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
