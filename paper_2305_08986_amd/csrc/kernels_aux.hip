@@ -562,8 +562,39 @@ __global__ void k_atomic_init(const uint8_t* __restrict__ wall, int dim, int64_t
     }
     if (q && i < np) q[i] = 0.0;
 }
+// zero n elements: 16-byte stores over the body (x 16-byte aligned), element stores
+// for the tail
+template <typename T>
+__global__ void k_zero16(T* __restrict__ x, int64_t n) {
+    constexpr int E = 16 / sizeof(T);
+    const int64_t nb = n / E;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) reinterpret_cast<uint4*>(x)[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (i < n - nb * E) x[nb * E + i] = T(0);
+}
+template <typename T>
+static void launch_zero(T* x, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    if (reinterpret_cast<uintptr_t>(x) % 16 != 0) {
+        launch_fill<T>(x, T(0), n, s);
+        return;
+    }
+    constexpr int E = 16 / sizeof(T);
+    const int64_t nb = n / E;
+    hipLaunchKernelGGL(k_zero16<T>, dim3(nblocks(std::max<int64_t>(nb, n - nb * E))), dim3(TPB), 0, s, x, n);
+}
 template <typename T>
 void launch_atomic_init(const Level& L, const T* u, T* v, double* q, hipStream_t s) {
+    // large levels: streaming zero fills at full store width, then the wall rows; small
+    // levels: one kernel (launch latency dominates there)
+    if (L.nvn >= (int64_t(1) << 20)) {
+        if (v) {
+            launch_zero<T>(v, L.nv, s);
+            if (u) launch_dirichlet_copy<T>(L, u, v, s);
+        }
+        if (q) launch_zero<double>(q, L.np, s);
+        return;
+    }
     const int64_t n = std::max(v ? L.nvn : 0, q ? L.np : 0);
     if (n > 0)
         hipLaunchKernelGGL(k_atomic_init<T>, dim3(nblocks(n)), dim3(TPB), 0, s, L.d_wall, L.dim, L.nvn, u, v, q, L.np);
