@@ -78,6 +78,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not found: build it with `python -m paper_2305_08986_amd.build`")
+    # torch first: it brings its own HIP runtime, and the library must bind to that same
+    # runtime (one per process) so that torch's device pointers and streams are valid in
+    # it; loaded the other way round, context creation fails with FSI_ERR_HIP
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, i, d = C.c_void_p, C.c_int, C.c_double
     sig = {

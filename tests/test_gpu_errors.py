@@ -1,6 +1,9 @@
 """Failure handling through the C ABI, forced from host-side inputs (every
 kernel still runs to completion)."""
 import ctypes
+import os
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -115,3 +118,18 @@ def test_zero_rhs_gives_zero_solution():
     u, p, info = ctx.solve(gu, gp, u=torch.ones_like(gu), p=torch.ones_like(gp))
     assert info["status"] == "OK" and info["iters"] == 0
     assert float(u.abs().max()) == 0.0 and float(p.abs().max()) == 0.0
+
+
+def test_library_loaded_before_any_gpu_work_gives_a_working_context():
+    """A fresh process that loads the library before torch has touched the GPU: the
+    binding imports torch first, so both bind to torch's HIP runtime and the context
+    is created (loaded the other way round, creation failed with FSI_ERR_HIP)."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_2305_08986_amd import fsi, workloads as W\n"
+            "fsi.load_library()\n"
+            "ctx = fsi.Context.from_mesh(W.make_workload('T3_4').mesh)\n"
+            "print('create ok', ctx.n_levels, flush=True)\n")
+    env = dict(os.environ, PYTHONPATH=root + os.pathsep + os.environ.get("PYTHONPATH", ""))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0 and "create ok" in r.stdout, (r.returncode, r.stdout[-1000:], r.stderr[-2000:])
