@@ -757,8 +757,15 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                                 }
                             }
                         } else if (ATOM) {
+                            // the node in the middle of the cell's y-z cross-section belongs
+                            // to this row alone, and the row writes it once: a plain store
+                            if (jc == 1 && k == 1) {
 #pragma unroll
-                            for (int c = 0; c < 3; ++c) unsafeAtomicAdd(&a.v[c * a.nvn + node[k]], out[c][k]);
+                                for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node[k]] = out[c][k];
+                            } else {
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) unsafeAtomicAdd(&a.v[c * a.nvn + node[k]], out[c][k]);
+                            }
                         } else if (first) {
 #pragma unroll
                             for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node[k]] = out[c][k];
