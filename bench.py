@@ -4,37 +4,41 @@ Workload (default): the 128^3 warped box with log-uniform viscosity per 8^3
 block (contrast up to 1e6), Q2-Q1, 6 levels down to 4^3, 50.9M velocity +
 2.1M pressure dofs.
 
-One timed step = one pass of the whole hot path on that workload:
-  * R applications of the FP64 matrix-free operator A (the dominant kernel;
-    every colour launch timed with HIP events on the library stream);
-  * geometry + coefficient upload and preconditioner setup (ALE Jacobians,
-    coefficient packing, diag(A), diag(B diag(A)^-1 B^T), Lanczos bounds,
-    dense coarse inverse, V-cycle graphs);
+Timed region: K steps, each one application of the FP64 matrix-free operator
+v = A u on the finest level (the hot-path kernel of every Krylov iteration and
+smoothing step), in the launch form the autotuner chose for that level, with
+u and v resident in HBM.  Every step is bracketed by HIP events on the library
+stream (the context is created on torch's current stream), and the whole loop
+by device synchronisations.  `value` = N_vel * K / wall time, in GDoF/s.
+
+After the timed loop (reported, not timed as steps), each once and in a fixed
+budget:
+  * the same apply in its default phased launch form, FP32 A, the FP64 Stokes
+    apply and the FP32 apply with geometry formed from the vertices;
+  * geometry + coefficient upload and preconditioner setup;
   * three solves from a zero guess to relative residual 1e-8: the plain FP64
     path (FP64 V-cycle launched kernel by kernel, separate Chebyshev/residual
     vector kernels, default launch shapes), the same FP64 solve with every
-    optimisation (captured graph, fused last-touch epilogues, tuned launches),
-    and the mixed-precision solve (FP32 V-cycle, FP64 FGMRES / residuals /
-    Schur block) with the same optimisations.
-Inputs are resident in HBM before the timed region.  `value` is the FP64
-vmult throughput N_vel / t_apply in GDoF/s; the solve times, their ratio
-and the mixed-vs-FP64 velocity difference are reported beside it.
+    optimisation (captured graph, fused epilogues where faster, tuned launch
+    shapes), and the mixed-precision solve (FP32 V-cycle, FP64 FGMRES /
+    residuals / Schur block; median of three, its iteration count moves with
+    the order of the atomic adds);
+  * the pseudo-elastic extension solve on the same mesh;
+  * the corrector mode: its Stokes apply on the same mesh and its solve on the
+    64^3 box;
+  * the CPU oracle's element-by-element apply on a bounded sample of the same
+    workload's cells, on every host core the box gives this job (run first, in
+    a child process, before the GPU is touched).
 
-After the timed steps (not part of them): the pseudo-elastic extension solve
-on the same mesh (flexible CG + multigrid on A with c_m = 0, eta = mu_A / 2,
-to 1e-6), FP64 and FP32 V-cycle, reported under "extension"; the corrector
-mode (convection and streamline terms): its Stokes apply on the same mesh and
-its solve on the 64^3 box, reported under "corrector".
-
-Prints one JSON line (N = 1 only: the library runs the hot path on one GPU).
+Prints one JSON line (one GPU only: the library runs the hot path on one GPU).
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import math
 import os
+import subprocess
 import sys
 import time
 
@@ -43,6 +47,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+# worker processes of the CPU leg: the host cores a one-GPU job gets on the box
+CPU_WORKERS_MAX = 16
 
 
 def _log(msg):
@@ -87,10 +93,99 @@ def load_counter_profile(workload: str, form: str = "phased"):
     return d
 
 
-def extension_measure(name, mesh, d_disp, fsi, W, np, torch, rtol: float = 1e-6, reps: int = 3):
+def _median(xs):
+    s = sorted(xs)
+    m = len(s) // 2
+    return s[m] if len(s) % 2 else 0.5 * (s[m - 1] + s[m])
+
+
+# ---------------------------------------------------------------- CPU leg (oracle)
+_CPU = {}
+
+
+def _cpu_block(c0: int, c1: int):
+    """One block of the oracle's element-by-element apply (a worker of the CPU leg)."""
+    import numpy as np
+    from oracle import fem
+    g = _CPU
+    d, v = fem.apply_ebe(g["box"], g["disp"], g["cm"], g["eta"], g["ref"], g["u"], np.arange(c0, c1))
+    return c1 - c0, float(v @ g["u"][d])
+
+
+def cpu_leg(name: str, seconds: float, block: int) -> dict:
+    """The CPU oracle's A apply (fem.apply_ebe: element matrices by quadrature, local
+    products, scatter) over consecutive blocks of the workload's finest-level cells,
+    on a pool of worker processes, until the time budget is spent.  Runs in a process
+    that never touches the GPU."""
+    import multiprocessing as mp
+
+    import numpy as np
+    from oracle import fem
+    from paper_2305_08986_amd import workloads as W
+
+    mesh = W.make_mesh(name)
+    J = mesh.n_levels - 1
+    wl = W.make_workload(name, levels=[J])
+    box = fem.level_box(wl.mesh, J)
+    _CPU.update(box=box, disp=wl.disp, cm=wl.c_mass[J], eta=wl.eta[J], ref=fem.Reference(mesh.dim),
+                u=np.random.default_rng(7).uniform(-1.0, 1.0, box.n_vel))
+    ncell = box.n_cells
+    workers = max(1, min(CPU_WORKERS_MAX, os.cpu_count() or 1))
+    done = 0
+    chk = 0.0
+    with mp.get_context("fork").Pool(workers) as pool:
+        t0 = time.perf_counter()
+        pending = []
+        nxt = 0
+        while True:
+            while nxt < ncell and len(pending) < 2 * workers and time.perf_counter() - t0 < seconds:
+                pending.append(pool.apply_async(_cpu_block, (nxt, min(ncell, nxt + block))))
+                nxt += block
+            if not pending:
+                break
+            n, c = pending.pop(0).get()
+            done += n
+            chk += c
+        dt = time.perf_counter() - t0
+    dof_per_cell = box.n_vel / ncell
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {
+        "value": done * dof_per_cell / dt / 1e9, "unit": "GDoF/s", "cores": workers, "kind": "oracle",
+        "sample": (f"oracle element-by-element FP64 A apply (fem.apply_ebe: Gauss-quadrature element matrices, "
+                   f"local products, scatter) on the first {done} of the {ncell} finest-level cells of the {name} "
+                   f"workload, blocks of {block} cells over {workers} worker processes, {dt:.1f} s; GDoF/s = "
+                   f"cells/s x N_vel/N_cells ({dof_per_cell:.2f})"),
+        "nproc": os.cpu_count(), "cpu_model": model, "cells": done, "seconds": round(dt, 2),
+        "checksum": chk,
+    }
+
+
+def run_cpu_leg_child(name: str, seconds: float) -> dict:
+    """The CPU leg in a child process (single-threaded numpy per worker)."""
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = "1"
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", "--workload", name,
+                        "--cpu-seconds", str(seconds)], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=seconds + 240)
+    if r.returncode != 0:
+        raise RuntimeError(f"CPU leg failed: {r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+# ---------------------------------------------------------------- GPU legs
+def extension_measure(name, mesh, d_disp, fsi, W, np, torch, rtol: float = 1e-6):
     """The pseudo-elastic extension on the same warped mesh (mu_A law, seeded wall data):
     flexible CG + multigrid to rtol 1e-6 (the paper's extension criterion), FP64 and FP32
-    V-cycle, each after one untimed solve; median of ``reps`` timed solves."""
+    V-cycle; the first solve of each builds the graphs, the second is timed."""
     ext = W.make_extension_inputs(name, mesh)
     ectx = fsi.Context.from_mesh(mesh)
     ectx.set_displacement(d_disp)
@@ -108,26 +203,23 @@ def extension_measure(name, mesh, d_disp, fsi, W, np, torch, rtol: float = 1e-6,
     for label, prec in (("fp64", 0), ("mixed", 1)):
         ectx.set_mg_params(precision=prec)
         ectx.solve_extension(g, rtol=rtol, max_iter=200)
-        times = []
-        for _ in range(reps):
-            u, info = ectx.solve_extension(g, rtol=rtol, max_iter=200)
-            times.append(info["time_ms"])
+        u, info = ectx.solve_extension(g, rtol=rtol, max_iter=200)
         sol[label] = u
-        res[label] = dict(ms=round(float(np.median(times)), 2), iters=info["iters"], rel_res=info["rel_res"],
+        res[label] = dict(ms=round(info["time_ms"], 2), iters=info["iters"], rel_res=info["rel_res"],
                           status=info["status"])
     diff = float(torch.linalg.vector_norm(sol["mixed"] - sol["fp64"]) / torch.linalg.vector_norm(sol["fp64"]))
+    ectx.close()
     return {"rtol": rtol, "setup_ms": round(setup_ms, 1), "fp64": res["fp64"], "mixed": res["mixed"],
             "speedup_mixed_vs_fp64": round(res["fp64"]["ms"] / res["mixed"]["ms"], 3),
-            "rel_diff_mixed_vs_fp64": diff,
-            "first_solve_builds_coarse_inverse": True}
+            "rel_diff_mixed_vs_fp64": diff}
 
 
 def corrector_measure(name, ctx, W, np, torch, fsi, solve_workload: str = "C2", rtol: float = 1e-8):
     """Corrector mode (convection and streamline terms, Sec. 3.1.1 and 3.2): the Stokes
     apply with the terms on the bench workload's finest level (FP64 and FP32, median of
     timed applications), and the corrector solve (k_A = 6, BiCGStab Schur step) on the
-    64^3 box to rtol 1e-8: plain FP64 path, optimised FP64 and mixed precision (the last
-    two: the median of three solves)."""
+    64^3 box to rtol 1e-8: plain FP64 path, optimised FP64 and mixed precision (the
+    mixed one: median of three)."""
     J = ctx.n_levels - 1
     sz = ctx.sizes(J)
     wl = W.make_workload(name, levels=[J])
@@ -160,10 +252,8 @@ def corrector_measure(name, ctx, W, np, torch, fsi, solve_workload: str = "C2", 
     gp = torch.from_numpy(wl.g_p).cuda()
     res = {}
     sol = {}
-    # the tuned paths may add with atomics on some levels, and the mixed corrector
-    # preconditioner's iteration count moves with rounding: median of three solves
     for label, prm, runs in (("plain_fp64", dict(precision=0, use_graph=0, fused=0, tuned=0), 1),
-                             ("fp64", dict(precision=0), 3), ("mixed", dict(precision=1), 3)):
+                             ("fp64", dict(precision=0), 1), ("mixed", dict(precision=1), 3)):
         cctx.set_mg_params(corrector=1, k_A=6, **prm)
         got = []
         for _ in range(runs):
@@ -176,60 +266,46 @@ def corrector_measure(name, ctx, W, np, torch, fsi, solve_workload: str = "C2", 
         if runs > 1:
             res[label]["runs_ms"] = [round(g[0], 1) for g in got]
             res[label]["runs_iters"] = [g[1]["iters"] for g in got]
-    du = float(torch.linalg.vector_norm(sol["mixed"] - sol["fp64"]) / torch.linalg.vector_norm(sol["fp64"]))
+    du = float(torch.linalg.vector_norm(sol["mixed"] - sol["plain_fp64"]) /
+               torch.linalg.vector_norm(sol["plain_fp64"]))
+    cctx.close()
     out["solve"] = {"workload": solve_workload, "rtol": rtol, "k_A": 6, "setup_ms": round(setup_ms, 1), **res,
                     "speedup_mixed_vs_plain_fp64": round(res["plain_fp64"]["ms"] / res["mixed"]["ms"], 3),
                     "velocity_rel_diff_mixed_vs_fp64": du}
     return out
 
 
-def cpu_baseline(seconds: float = 12.0):
-    """The CPU oracle's A-apply (CSR SpMV, scipy) timed on a bounded sample."""
-    import numpy as np
-    from oracle import fem
-    from paper_2305_08986_amd import workloads as W
-
-    wl = W.make_workload("T3_16", levels=[2])
-    box = fem.level_box(wl.mesh, 2)
-    ref = fem.Reference(3)
-    t0 = time.perf_counter()
-    J = fem.jacobians_q1(box, wl.disp, ref)
-    op = fem.assemble(box, J, wl.c_mass[2], wl.eta[2], ref)
-    t_asm = time.perf_counter() - t0
-    u = np.random.default_rng(0).uniform(-1, 1, box.n_vel)
-    reps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        op.A @ u
-        reps += 1
-    dt = time.perf_counter() - t0
-    gdofs = box.n_vel * reps / dt / 1e9
-    return {
-        "value": gdofs, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-        "sample": (f"FP64 CSR SpMV y = A u (scipy, single thread) of the oracle-assembled Q2 velocity block on a "
-                   f"16^3 warped box with the same viscosity law (n_vel={box.n_vel}, nnz={op.A.nnz}); "
-                   f"{reps} products in {dt:.1f} s; assembly {t_asm:.1f} s not included"),
-    }
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="C3")
-    ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--mixed-runs", type=int, default=3, help="mixed solves (the median is reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solves", action="store_true", help="skip the three solves")
     ap.add_argument("--no-extension", action="store_true", help="skip the extension-solve measurement")
     ap.add_argument("--no-corrector", action="store_true", help="skip the corrector-mode measurement")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-block", type=int, default=512)
+    ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+
+    if args.cpu_leg:
+        print(json.dumps(cpu_leg(args.workload, args.cpu_seconds, args.cpu_block)), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: the library runs the hot path on one GPU only (no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        _log(f"[bench] CPU oracle baseline ({args.cpu_seconds:.0f} s budget, before any GPU work)")
+        cpu = run_cpu_leg_child(args.workload, args.cpu_seconds)
+        _log(f"[bench] CPU oracle: {cpu['value']:.5f} GDoF/s on {cpu['cores']} processes, {cpu['cells']} cells")
 
     import numpy as np
     import torch
@@ -262,93 +338,66 @@ def main():
         ctx.setup()
 
     _log("[bench] setup + autotune")
+    t0 = time.perf_counter()
     do_setup()
     ctx.autotune()
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
     tuning = {f"L{j}": [ctx.tuning(j, 0)[0], ctx.tuning(j, 1)[0]] for j in range(ctx.n_levels)}
-
-    def one_step(record):
-        t0 = time.perf_counter()
-        # the FP64 A apply in its default launch shape (one wavefront per row, streaming
-        # geometry loads, four phase launches) and in the form the autotuner chose (on
-        # the large 3D levels usually the single atomic launch)
-        ctx.set_mg_params(tuned=0)
-        k0_us, op0_us, nl0 = ctx.time_operator(J, precision=0, mode=1, reps=args.apply_reps)
-        ctx.set_mg_params(tuned=1)
-        k_us, op_us, nl = ctx.time_operator(J, precision=0, mode=1, reps=args.apply_reps)
-        k32_us, op32_us, _ = ctx.time_operator(J, precision=1, mode=1, reps=max(4, args.apply_reps // 2))
-        ks_us, ops_us, _ = ctx.time_operator(J, precision=0, mode=7, reps=max(4, args.apply_reps // 2))
-        # FP32 A with the geometry formed from the vertex displacements in the kernel
-        ctx.set_mg_params(vertex_geometry=1)
-        kv_us, opv_us, _ = ctx.time_operator(J, precision=1, mode=1, reps=max(4, args.apply_reps // 2))
-        ctx.set_mg_params(vertex_geometry=0)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        do_setup()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        # plain FP64: per-launch V-cycle, separate vector kernels, default launch shapes
-        ctx.set_mg_params(precision=0, use_graph=0, fused=0, tuned=0)
-        u64, p64, i64 = ctx.solve(gu, gp, rtol=args.rtol, max_iter=300, restart=100)
-        # FP64 with every optimisation of the mixed path (graph, fused epilogues, tuned launches)
-        ctx.set_mg_params(precision=0, use_graph=1, fused=1, tuned=1)
-        uft, pft, ift = ctx.solve(gu, gp, rtol=args.rtol, max_iter=300, restart=100)
-        ctx.set_mg_params(precision=1, use_graph=1, fused=1, tuned=1)
-        umx, pmx, imx = ctx.solve(gu, gp, rtol=args.rtol, max_iter=300, restart=100)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        du = float(torch.linalg.vector_norm(umx - u64) / torch.linalg.vector_norm(u64))
-        rec = dict(k_us=k_us, op_us=op_us, n_launch=nl, k0_us=k0_us, op0_us=op0_us, n_launch0=nl0, k32_us=k32_us, op32_us=op32_us, ks_us=ks_us, ops_us=ops_us,
-                   opv_us=opv_us,
-                   apply_s=t1 - t0, setup_s=t2 - t1, solve_s=t3 - t2, fp64=i64, fp64_opt=ift, mixed=imx, du=du,
-                   step_s=t3 - t0)
-        record.append(rec)
-        _log(f"[bench] step: A-apply {op_us:.0f} us (cell kernel {k_us:.1f} us in {nl} launches), "
-             f"setup {1e3*(t2-t1):.0f} ms, "
-             f"plain fp64 solve {i64['time_ms']:.0f} ms/{i64['iters']} it ({i64['status']}), "
-             f"optimised fp64 {ift['time_ms']:.0f} ms/{ift['iters']} it ({ift['status']}), "
-             f"mixed {imx['time_ms']:.0f} ms/{imx['iters']} it ({imx['status']}), du {du:.2e}")
-
-    warm = []
-    for _ in range(args.warmup):
-        one_step(warm)
-    torch.cuda.synchronize()
-    recs = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        one_step(recs)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    def mean(key, sub=None):
-        vals = [r[key][sub] if sub else r[key] for r in recs]
-        return float(np.mean(vals))
-
-    op_us = mean("op_us")
-    k_us = mean("k_us")
-    gdofs = nv / (op_us * 1e-6) / 1e9
-    n_launch = recs[-1]["n_launch"]
     tuned_var = tuning[f"L{J}"][0]
     atomic = tuned_var >= fsi.N_LAUNCH_VARIANTS
-    op0_us, k0_us, n_launch0 = mean("op0_us"), mean("k0_us"), recs[-1]["n_launch0"]
+
+    # ---------------- timed loop: K applications of v = A u (FP64, autotuned form)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    u = torch.rand(nv, dtype=torch.float64, device="cuda", generator=gen) * 2.0 - 1.0
+    v = torch.empty_like(u)
+    stream = torch.cuda.current_stream()
+    assert stream.cuda_stream == ctx.stream.cuda_stream
+    _log(f"[bench] timed loop: {args.warmup} warm-up + {args.steps} FP64 A applies on {nc} cells")
+    for _ in range(args.warmup):
+        ctx.apply_A(J, u, out=v)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        ctx.apply_A(J, u, out=v)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_us = [1e3 * a.elapsed_time(b) for a, b in evs]
+    apply_us = sum(step_us) / len(step_us)
+    gdofs = nv * args.steps / wall / 1e9
+    _log(f"[bench] FP64 A apply: {apply_us:.1f} us mean (events), {1e3 * wall / args.steps:.3f} ms per step (wall), "
+         f"{gdofs:.3f} GDoF/s")
+
+    # ---------------- the other forms and operators (fsi_time_operator: medians)
+    ctx.set_mg_params(tuned=0)
+    k0_us, op0_us, nl0 = ctx.time_operator(J, precision=0, mode=1, reps=10)
+    ctx.set_mg_params(tuned=1)
+    k_us, op_us, nl = ctx.time_operator(J, precision=0, mode=1, reps=10)
+    _, op32_us, _ = ctx.time_operator(J, precision=1, mode=1, reps=10)
+    _, ops_us, _ = ctx.time_operator(J, precision=0, mode=7, reps=10)
+    ctx.set_mg_params(vertex_geometry=1)
+    _, opv_us, _ = ctx.time_operator(J, precision=1, mode=1, reps=10)
+    ctx.set_mg_params(vertex_geometry=0)
+
     bpc = algorithmic_bytes_per_cell(mesh.dim, 8)
-    # algorithmic bytes per launch / mean launch duration (k_us = all launches of one
-    # apply; the atomic form: its one launch and the initialisation kernel)
-    achieved = bpc * nc / (k_us * 1e-6) / 1e9
     kbpc = kernel_bytes_per_cell(mesh.dim, 8)
-    # the counter summary must cover the measured form: the atomic one, or the default
-    # phased variant
+    # algorithmic bytes of one apply / its mean duration over the timed steps (HIP events on
+    # the library stream; the atomic form is its output initialisation plus one cell launch)
+    achieved = bpc * nc / (apply_us * 1e-6) / 1e9
     prof = load_counter_profile(name, "atomic") if atomic else (load_counter_profile(name) if tuned_var == 0 else None)
     traffic = None
     flops = None
     if prof is not None:
         traffic = prof["hbm_bytes_per_launch"]
         if prof.get("fp64_flops_per_launch"):
-            tf = prof["fp64_flops_per_launch"] / (k_us / n_launch * 1e-6) / 1e12
+            per = apply_us if atomic else apply_us / max(1, nl)
+            tf = prof["fp64_flops_per_launch"] / (per * 1e-6) / 1e12
             flops = {"fp64_tflops": round(tf, 2), "peak": FP64_PEAK_TFLOPS, "frac": round(tf / FP64_PEAK_TFLOPS, 4),
                      "source": "rocprofv3 SQ_INSTS_VALU_FMA/ADD/MUL_F64 per launch (profiles/)"}
-    fp64_ms = mean("fp64", "time_ms")
-    ft_ms = mean("fp64_opt", "time_ms")
-    mx_ms = mean("mixed", "time_ms")
     out = {
         "metric": "Q2 matrix-free vmult GDoF/s; Stokes solve time to rel.res 1e-8, FP64 vs mixed",
         "value": round(gdofs, 4),
@@ -356,7 +405,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * wall / args.steps, 2),
+        "ms_per_step": round(1e3 * wall / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -364,61 +413,99 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{name}: {W.CONFIGS[name]['desc']}, Q2-Q1, {ctx.n_levels} levels",
+            "step": "one FP64 matrix-free apply v = A u on the finest level (autotuned launch form)",
             "cells": nc, "n_vel": nv, "n_p": npr, "rtol": args.rtol,
             "mg": "FGMRES(100) + 1 V-cycle, k_A=4, m=2, k_S=n_S=1",
         },
         "apply": {
             "fp64_A_gdofs": round(gdofs, 4),
-            "fp64_A_us": round(op_us, 1),
-            "fp64_A_kernel_us": round(k_us, 2),
-            "fp64_A_launches": n_launch,
-            "fp64_A_mean_launch_us": round(k_us / n_launch, 2),
-            "fp64_A_form": (f"single atomic launch over all phases (variant {tuned_var}) + output initialisation"
-                            if atomic else f"phased, variant {tuned_var}"),
+            "fp64_A_event_us_mean": round(apply_us, 2),
+            "fp64_A_event_us_min": round(min(step_us), 2),
+            "fp64_A_event_us_max": round(max(step_us), 2),
+            "fp64_A_form": (f"output initialisation + one atomic cell launch over all phases (variant {tuned_var})"
+                            if atomic else f"phased, variant {tuned_var}, {nl} launches"),
+            "fp64_A_timeop_kernel_us": round(k_us, 2),
+            "fp64_A_timeop_us": round(op_us, 2),
             "fp64_A_phased_default_gdofs": round(nv / (op0_us * 1e-6) / 1e9, 4),
             "fp64_A_phased_default_us": round(op0_us, 1),
-            "fp64_A_phased_default_mean_launch_us": round(k0_us / n_launch0, 2),
+            "fp64_A_phased_default_mean_launch_us": round(k0_us / max(1, nl0), 2),
             "fp64_A_phased_default_roofline_frac": round(bpc * nc / (k0_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-            "fp32_A_gdofs": round(nv / (mean("op32_us") * 1e-6) / 1e9, 4),
-            "fp64_stokes_gdofs": round((nv + npr) / (mean("ops_us") * 1e-6) / 1e9, 4),
-            "fp32_A_vertex_geometry_gdofs": round(nv / (mean("opv_us") * 1e-6) / 1e9, 4),
+            "fp32_A_gdofs": round(nv / (op32_us * 1e-6) / 1e9, 4),
+            "fp64_stokes_gdofs": round((nv + npr) / (ops_us * 1e-6) / 1e9, 4),
+            "fp32_A_vertex_geometry_gdofs": round(nv / (opv_us * 1e-6) / 1e9, 4),
             "algorithmic_bytes_per_cell": bpc,
             "kernel_bytes_per_cell": kbpc,
         },
-        "solve": {
-            "fp64_plain_ms": round(fp64_ms, 1), "fp64_plain_iters": recs[-1]["fp64"]["iters"],
-            "fp64_plain_rel_res": recs[-1]["fp64"]["rel_res"], "fp64_plain_status": recs[-1]["fp64"]["status"],
-            "fp64_optimised_ms": round(ft_ms, 1), "fp64_optimised_iters": recs[-1]["fp64_opt"]["iters"],
-            "mixed_graph_ms": round(mx_ms, 1), "mixed_iters": recs[-1]["mixed"]["iters"],
-            "mixed_rel_res": recs[-1]["mixed"]["rel_res"], "mixed_status": recs[-1]["mixed"]["status"],
-            "speedup_mixed_vs_plain_fp64": round(fp64_ms / mx_ms, 3),
-            "speedup_mixed_vs_optimised_fp64": round(ft_ms / mx_ms, 3),
-            "velocity_rel_diff_mixed_vs_fp64": recs[-1]["du"],
-            "setup_ms": round(1e3 * mean("setup_s"), 1),
-        },
         "tuning_variant": tuning,
+        "setup_autotune_s": round(tune_s, 2),
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "achieved_kernel_bytes": round(kbpc * nc / (k_us * 1e-6) / 1e9, 1),
-            "kernel": (("cell3d<double, A> as one atomic launch over all phases plus its output "
-                        f"initialisation, autotuned; median apply {k_us:.1f} us (both kernels); traffic per apply")
+            "achieved_kernel_bytes": round(kbpc * nc / (apply_us * 1e-6) / 1e9, 1),
+            "frac_kernel_bytes": round(kbpc * nc / (apply_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernel": (("cell3d<double, A> as one atomic launch over all phases, with its output initialisation, "
+                        f"autotuned; mean apply {apply_us:.1f} us over the timed steps; traffic per apply")
                        if atomic else
                        (("cell3d<double, A>" if mesh.dim == 3 else "cell2d<double, A>")
-                        + f" launch variant {tuned_var}, {n_launch} launches (processing phases) per apply, "
-                        + f"median apply {k_us / n_launch:.1f} us per launch; traffic per launch")),
+                        + f" launch variant {tuned_var}, {nl} launches per apply, mean apply {apply_us:.1f} us")),
         },
         "flops": flops,
     }
+    print(json.dumps({"partial": "timed loop done", "value": out["value"], "roofline_frac": out["roofline"]["frac"]}),
+          file=sys.stderr, flush=True)
+
+    if not args.no_solves:
+        _log("[bench] setup (timed once)")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        do_setup()
+        torch.cuda.synchronize()
+        setup_ms = 1e3 * (time.perf_counter() - t1)
+        solves = {}
+        _log("[bench] plain FP64 solve")
+        ctx.set_mg_params(precision=0, use_graph=0, fused=0, tuned=0)
+        u64, p64, i64 = ctx.solve(gu, gp, rtol=args.rtol, max_iter=300, restart=100)
+        _log(f"[bench]   {i64['time_ms']:.0f} ms, {i64['iters']} it, {i64['status']}")
+        _log("[bench] optimised FP64 solve")
+        ctx.set_mg_params(precision=0, use_graph=1, fused=1, tuned=1)
+        uft, pft, ift = ctx.solve(gu, gp, rtol=args.rtol, max_iter=300, restart=100)
+        _log(f"[bench]   {ift['time_ms']:.0f} ms, {ift['iters']} it, {ift['status']}")
+        ctx.set_mg_params(precision=1, use_graph=1, fused=1, tuned=1)
+        mixed = []
+        for r in range(max(1, args.mixed_runs)):
+            _log(f"[bench] mixed solve {r + 1}/{args.mixed_runs}")
+            umx, pmx, imx = ctx.solve(gu, gp, rtol=args.rtol, max_iter=300, restart=100)
+            du = float(torch.linalg.vector_norm(umx - u64) / torch.linalg.vector_norm(u64))
+            dp = float(torch.linalg.vector_norm(pmx - p64) / torch.linalg.vector_norm(p64))
+            mixed.append((imx["time_ms"], imx, du, dp))
+            _log(f"[bench]   {imx['time_ms']:.0f} ms, {imx['iters']} it, {imx['status']}, du {du:.2e}")
+        mixed.sort(key=lambda m: m[0])
+        mx_ms, imx, du, dp = mixed[len(mixed) // 2]
+        solves = {
+            "fp64_plain_ms": round(i64["time_ms"], 1), "fp64_plain_iters": i64["iters"],
+            "fp64_plain_rel_res": i64["rel_res"], "fp64_plain_status": i64["status"],
+            "fp64_optimised_ms": round(ift["time_ms"], 1), "fp64_optimised_iters": ift["iters"],
+            "fp64_optimised_rel_res": ift["rel_res"],
+            "mixed_graph_ms": round(mx_ms, 1), "mixed_iters": imx["iters"],
+            "mixed_rel_res": imx["rel_res"], "mixed_status": imx["status"],
+            "mixed_runs_ms": [round(m[0], 1) for m in mixed], "mixed_runs_iters": [m[1]["iters"] for m in mixed],
+            "speedup_mixed_vs_plain_fp64": round(i64["time_ms"] / mx_ms, 3),
+            "speedup_mixed_vs_optimised_fp64": round(ift["time_ms"] / mx_ms, 3),
+            "velocity_rel_diff_mixed_vs_fp64": du,
+            "velocity_rel_diff_mixed_vs_fp64_max": max(m[2] for m in mixed),
+            "pressure_rel_diff_mixed_vs_fp64": dp,
+            "setup_ms": round(setup_ms, 1),
+        }
+        out["solve"] = solves
+        del u64, p64, uft, pft, umx, pmx
     if not args.no_extension:
         _log("[bench] extension solve")
         out["extension"] = extension_measure(name, mesh, d_disp, fsi, W, np, torch)
     if not args.no_corrector:
         _log("[bench] corrector mode")
         out["corrector"] = corrector_measure(name, ctx, W, np, torch, fsi)
-    if not args.no_cpu_baseline:
-        _log("[bench] CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

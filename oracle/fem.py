@@ -476,6 +476,30 @@ def apply_rows(box: Box, disp: np.ndarray, c_mass: np.ndarray, eta: np.ndarray,
     return ov, op
 
 
+def apply_ebe(box: Box, disp: np.ndarray, c_mass: np.ndarray, eta: np.ndarray, ref: Reference,
+              u: np.ndarray, cells: np.ndarray):
+    """Contributions of ``cells`` to A u, element by element (no global matrix).
+
+    The operator on a mesh too large to assemble: for each cell the element matrix
+    A_K of ``element_matrices`` times the cell's gathered velocity values (Dirichlet
+    columns zero, as in ``assemble``), summed into the global dofs the cell touches.
+    Returns (dofs, vals), the touched free velocity dofs in increasing order and their
+    summed contributions; summed over all cells of the mesh this is A u on the free
+    rows (the identity rows of the Dirichlet dofs are not cell contributions).
+    """
+    dm = box.dirichlet_vel_dofs()
+    cells = np.asarray(cells, dtype=np.int64)
+    J = jacobians_q1(box, disp, ref, cells)
+    AK, _ = element_matrices(J, c_mass[cells], eta[cells], ref)
+    gd = _global_vel_dofs(box, box.cell_vel_nodes(cells))
+    uK = np.where(dm[gd], 0.0, u[gd])
+    yK = np.einsum("cij,cj->ci", AK, uK)
+    dofs, inv = np.unique(gd, return_inverse=True)
+    vals = np.bincount(inv.ravel(), weights=yK.ravel(), minlength=len(dofs))
+    keep = ~dm[dofs]
+    return dofs[keep], vals[keep]
+
+
 def level_box(mesh, level: int) -> Box:
     """Box of ``level`` from a mesh description (dim, n_coarse, extent, dirichlet_faces)."""
     cells = tuple(mesh.n_coarse[i] << level for i in range(mesh.dim))

@@ -165,6 +165,50 @@ def test_rigid_motions_in_null_space(dim):
     assert np.linalg.norm(op.A @ s.ravel()) > 1e-3 * np.linalg.norm(s)
 
 
+def test_element_by_element_apply_invariants():
+    """The element-by-element apply (used where no global matrix fits): the mass of a
+    constant field is the mapped volume, rigid motions give zero viscous response on a
+    warped mesh with random eta, the result does not depend on how the cells are
+    split into blocks, and on a box with walls it is A u on the free rows."""
+    box = fem.Box(3, (3, 2, 2), (1.0, 0.8, 0.9), 0)
+    ref = fem.Reference(3)
+    disp = bubble_disp(box, 0.05, seed=4)
+    rng = np.random.default_rng(6)
+    cells = np.arange(box.n_cells)
+    one = np.ones((box.n_cells, 27))
+    vol = float(np.prod(box.extent))
+    for a in range(3):
+        e = np.zeros(box.n_vel)
+        e[a * box.n_vel_nodes:(a + 1) * box.n_vel_nodes] = 1.0
+        d, v = fem.apply_ebe(box, disp, one, 0 * one, ref, e, cells)
+        assert abs(v @ e[d] - vol) < 1e-13 * vol
+    eta = 10 ** rng.uniform(-3, 3, size=(box.n_cells, 27))
+    x = box.vel_node_ref_coords() + _q1_interp_at_nodes(box, disp)
+    r = np.zeros_like(x)
+    r[0], r[1] = -x[1], x[0]
+    d, v = fem.apply_ebe(box, disp, 0 * one, eta, ref, r.ravel(), cells)
+    trans = np.repeat([1.0, 0.0, 0.0], box.n_vel_nodes)
+    d1, v1 = fem.apply_ebe(box, disp, 0 * one, eta, ref, trans, cells)
+    assert np.abs(v).max() <= 1e-12 * eta.max() and np.abs(v1).max() <= 1e-12 * eta.max()
+    s = np.zeros_like(x)
+    s[0] = x[0]
+    _, vs = fem.apply_ebe(box, disp, 0 * one, eta, ref, s.ravel(), cells)
+    assert np.abs(vs).max() > 1e-3
+    # walls, random data: blocks of cells summed = A u on the free rows
+    wbox = fem.Box(3, (3, 2, 2), (1.0, 0.8, 0.9), W.default_dirichlet_faces(3))
+    cm = rng.uniform(0, 5, size=(box.n_cells, 27))
+    u = rng.normal(size=box.n_vel)
+    op = fem.assemble(wbox, fem.jacobians_q1(wbox, disp, ref), cm, eta, ref)
+    acc = np.zeros(box.n_vel)
+    for blk in (cells[:5], cells[5:7], cells[7:]):
+        d, v = fem.apply_ebe(wbox, disp, cm, eta, ref, u, blk)
+        np.add.at(acc, d, v)
+    free = ~wbox.dirichlet_vel_dofs()
+    ref_v = op.A @ u
+    assert np.allclose(acc[free], ref_v[free], rtol=0, atol=1e-13 * np.abs(ref_v).max())
+    assert not acc[~free].any()
+
+
 def _q1_interp_at_nodes(box, disp):
     """Displacement interpolated (multilinear) at every Q2 node."""
     nn = box.vel_nodes
