@@ -206,6 +206,21 @@ fsi_status fsi_apply_BT_f32(fsi_ctx* ctx, int level, const float* p, float* v);
 fsi_status fsi_apply_stokes_f32(fsi_ctx* ctx, int level, const float* u, const float* p,
                                 float* v, float* q);
 
+/* Allocation-free FP32 Stokes apply, for callers that cannot allocate device memory
+ * during the call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same operator, layouts, outputs and errors as
+ * fsi_apply_stokes_f32, but the FP64 pressure staging (the copy of p and the sums of
+ * q) lives in a file-scope device array of the library instead of the context's work
+ * vectors, and the call allocates nothing (fsi_apply_stokes_f32 allocates every
+ * level's work vectors at its first use before fsi_setup).  Limit: levels with at most
+ * 4194304 (2^22) pressure nodes; larger levels return FSI_ERR_ARG.  The array (64 MiB)
+ * is one per device, shared by every context and call on that device and kept until
+ * the process ends; calls that overlap on one device (several streams or threads)
+ * race on it.  FSI_ERR_HIP if its device address could not be resolved at
+ * fsi_create. */
+fsi_status fsi_apply_stokes_f32_noalloc(fsi_ctx* ctx, int level, const float* u, const float* p,
+                                        float* v, float* q);
+
 /* Corrector-mode terms (3D): with the semi-implicit advection of the corrector
  * mode (Sec. 3.1.1: the form a_j with v* the unknown and v° known) and the
  * streamline term of Sec. 3.2, the velocity block becomes

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -813,6 +814,32 @@ static fsi_status ext_run_precond(Context* ctx, const double* r, double* z, hipS
     return FSI_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free FP32 Stokes apply
+// Pressure staging of fsi_apply_stokes_f32_noalloc: the FP64 copy of p (first half)
+// and the FP64 sums of q (second half), for levels of up to kNoAllocMaxP pressure
+// nodes.  One copy per device, held until the process ends.  In host code the name
+// `scratch` is only a host-side stand-in: kernels receive the device address that
+// hipGetSymbolAddress returned for the current device.
+constexpr int64_t kNoAllocMaxP = int64_t(1) << 22;
+static __device__ __align__(256) double scratch[2 * kNoAllocMaxP];
+
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_addr;   // per device id; null until resolved
+
+// the device address of `scratch` on the current device, resolved once per device
+static double* scratch_address() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_addr.size() <= dev) g_scratch_addr.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch_addr[(size_t)dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_addr[(size_t)dev] = static_cast<double*>(ptr);
+    }
+    return g_scratch_addr[(size_t)dev];
+}
+
 }  // namespace fsi
 
 using namespace fsi;
@@ -876,6 +903,8 @@ fsi_status fsi_create(fsi_ctx** out, const fsi_mesh_desc* m, void* hip_stream) {
         st = build_level(ctx, ctx->lv[j], m->dim, cells, *m);
     }
     if (st == FSI_OK) st = dalloc(ctx, &ctx->d_scratch, 4 * kReduceBlocks + 64);
+    // the allocation-free FP32 Stokes apply's staging array on this device
+    if (st == FSI_OK) ctx->noalloc_scratch = scratch_address();
     if (st == FSI_OK) st = dalloc(ctx, &ctx->d_flag, 4);
     if (st == FSI_OK && hipHostMalloc((void**)&ctx->h_flag, sizeof(int) * 4) != hipSuccess) st = FSI_ERR_HIP;
     if (st == FSI_OK && hipHostMalloc((void**)&ctx->h_dbl, sizeof(double) * 64) != hipSuccess) st = FSI_ERR_HIP;
@@ -1150,6 +1179,29 @@ fsi_status fsi_apply_stokes_f32(fsi_ctx* h, int level, const float* u, const flo
     launch_cast<double, float>(a, p, ctx->lv[level].np, ctx->stream);
     op_apply<float>(ctx, level, OP_A | OP_BT | OP_B, u, a, v, b, ctx->stream);
     launch_cast<float, double>(q, b, ctx->lv[level].np, ctx->stream);
+    return FSI_OK;
+}
+
+fsi_status fsi_apply_stokes_f32_noalloc(fsi_ctx* h, int level, const float* u, const float* p, float* v,
+                                        float* q) {
+    if (!h || !u || !p || !v || !q) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    TRY(check_level(ctx, level));
+    const Level& L = ctx->lv[level];
+    if (L.np > kNoAllocMaxP)
+        return fail(ctx, FSI_ERR_ARG, "fsi_apply_stokes_f32_noalloc: the level has " + std::to_string(L.np) +
+                                          " pressure nodes, more than the staging limit of " +
+                                          std::to_string(kNoAllocMaxP));
+    if (!ctx->noalloc_scratch)
+        return fail(ctx, FSI_ERR_HIP, "fsi_apply_stokes_f32_noalloc: no device address for the staging array");
+    TRY(apply_check(ctx, level, true));
+    // the same kernels as fsi_apply_stokes_f32; the outputs of the pressure sums are
+    // written in full by the apply (first-touch stores, or the atomic form's zeroing)
+    double* a = ctx->noalloc_scratch;
+    double* b = ctx->noalloc_scratch + kNoAllocMaxP;
+    launch_cast<double, float>(a, p, L.np, ctx->stream);
+    op_apply<float>(ctx, level, OP_A | OP_BT | OP_B, u, a, v, b, ctx->stream);
+    launch_cast<float, double>(q, b, L.np, ctx->stream);
     return FSI_OK;
 }
 

@@ -263,6 +263,9 @@ struct Context {
         return atom[prec][(size_t)level * kTuneClasses + tune_class(mode)];
     }
     std::vector<void*> allocations;
+    // device address of the file-scope pressure staging array of the allocation-free
+    // FP32 Stokes apply on this context's device (resolved at create; null if that failed)
+    double* noalloc_scratch = nullptr;
 };
 
 // ---------------------------------------------------------------- launchers (kernels_*.hip)

@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fsi_apply_B_f32": (i, [vp, i, vp, vp]),
         "fsi_apply_BT_f32": (i, [vp, i, vp, vp]),
         "fsi_apply_stokes_f32": (i, [vp, i, vp, vp, vp, vp]),
+        "fsi_apply_stokes_f32_noalloc": (i, [vp, i, vp, vp, vp, vp]),
         "fsi_set_convection": (i, [vp, i, vp, vp, C.c_double]),
         "fsi_apply_corrector": (i, [vp, i, vp, vp, vp, vp]),
         "fsi_apply_corrector_f32": (i, [vp, i, vp, vp, vp, vp]),
@@ -297,6 +298,13 @@ class Context:
         self._check(fn(self.h, level, C.c_void_p(_ptr(u)), C.c_void_p(_ptr(p)), C.c_void_p(_ptr(v)),
                        C.c_void_p(_ptr(q))))
         return v, q
+
+    def apply_stokes_f32_noalloc(self, level, u, p, out_v, out_q):
+        """FP32 Stokes apply that allocates nothing (fsi_apply_stokes_f32_noalloc); the
+        caller provides the outputs."""
+        self._check(self.lib.fsi_apply_stokes_f32_noalloc(self.h, level, C.c_void_p(_ptr(u)), C.c_void_p(_ptr(p)),
+                                                          C.c_void_p(_ptr(out_v)), C.c_void_p(_ptr(out_q))))
+        return out_v, out_q
 
     def apply_corrector(self, level, u, p, out_v=None, out_q=None):
         """Stokes apply with the corrector-mode terms (fsi_apply_corrector[_f32])."""
