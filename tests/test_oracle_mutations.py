@@ -133,3 +133,87 @@ def test_planted_convection_mistake_is_caught(fn, monkeypatch):
         except AssertionError:
             caught += 1
     assert caught >= 1, fn.__doc__
+
+
+# ---------------------------------------------------------------- V-cycle composition
+from oracle import solvers  # noqa: E402
+
+_orig_vcycle = solvers.Hierarchy.vcycle
+
+
+def _vcycle_no_post(self, j, f_u, f_p):
+    """the post-smoothing steps left out"""
+    if j == 0:
+        return self.coarse_solve(f_u, f_p)
+    op = self.levels[j].op
+    x_u, x_p = np.zeros_like(f_u), np.zeros_like(f_p)
+    for s in range(self.params.m):
+        a_u, a_p = op.apply_stokes(x_u, x_p)
+        y_u, y_p = self.smoother(j, f_u - a_u, f_p - a_p)
+        x_u, x_p = x_u + y_u, x_p + y_p
+    a_u, a_p = op.apply_stokes(x_u, x_p)
+    c_u, c_p = self.restrict(j, f_u - a_u, f_p - a_p)
+    e_u, e_p = _vcycle_no_post(self, j - 1, c_u, c_p)
+    p_u, p_p = self.prolongate(j, e_u, e_p)
+    return x_u + p_u, x_p + p_p
+
+
+def _vcycle_one_step(self, j, f_u, f_p):
+    """one pre- and one post-smoothing step where m = 2 are asked for"""
+    m = self.params.m
+    self.params.m = 1
+    try:
+        return _orig_vcycle(self, j, f_u, f_p)
+    finally:
+        self.params.m = m
+
+
+def _vcycle_stale_residual(self, j, f_u, f_p):
+    """the second pre-smoothing step applied to the first step's residual"""
+    if j == 0:
+        return self.coarse_solve(f_u, f_p)
+    op = self.levels[j].op
+    y_u, y_p = self.smoother(j, f_u, f_p)
+    x_u, x_p = 2 * y_u, 2 * y_p
+    a_u, a_p = op.apply_stokes(x_u, x_p)
+    c_u, c_p = self.restrict(j, f_u - a_u, f_p - a_p)
+    e_u, e_p = _vcycle_stale_residual(self, j - 1, c_u, c_p)
+    p_u, p_p = self.prolongate(j, e_u, e_p)
+    x_u, x_p = x_u + p_u, x_p + p_p
+    for s in range(self.params.m):
+        a_u, a_p = op.apply_stokes(x_u, x_p)
+        y_u, y_p = self.smoother(j, f_u - a_u, f_p - a_p)
+        x_u, x_p = x_u + y_u, x_p + y_p
+    return x_u, x_p
+
+
+_orig_smoother = solvers.Hierarchy.smoother
+
+
+def _smoother_schur_sign(self, j, r_u, r_p):
+    """the Schur right-hand side taken as r_p - B w instead of B w - r_p"""
+    lv = self.levels[j]
+    B = lv.op.B
+    ainv = lambda r: self.cheb(j, r)
+    sinv = lambda t: solvers.minres1(lambda z: B @ ainv(B.T @ z), lv.dS_inv, t)[0]
+    w = ainv(r_u)
+    y_p = sinv(r_p - B @ w)
+    return w - ainv(B.T @ y_p), y_p
+
+
+@pytest.mark.parametrize("attr,fn", [("vcycle", _vcycle_no_post), ("vcycle", _vcycle_one_step),
+                                     ("vcycle", _vcycle_stale_residual), ("smoother", _smoother_schur_sign)])
+def test_planted_vcycle_mistake_is_caught(attr, fn, monkeypatch):
+    """The two-grid identity pin catches schedule mistakes in the V-cycle; the smoother's
+    own mistake is caught by the V-cycle-preconditioned FGMRES pin (the identity takes the
+    smoother as given)."""
+    monkeypatch.setattr(solvers.Hierarchy, attr, fn)
+    caught = 0
+    for pin in (lambda: pins.test_two_grid_vcycle_is_the_error_propagation_identity("C0", (1, 2), 1e-8),
+                lambda: pins.test_two_grid_vcycle_is_the_error_propagation_identity("T3_4", (0, 1), 1e-10),
+                pins.test_vcycle_preconditioned_fgmres_reaches_direct_solution_c0):
+        try:
+            pin()
+        except AssertionError:
+            caught += 1
+    assert caught >= 1, fn.__doc__
