@@ -254,12 +254,19 @@ def jacobians_q1(box: Box, disp: np.ndarray, ref: Reference, cells: Optional[np.
 
     The ALE map (Sec. 2.2 and the mapped spaces of Sec. 3.2) is the Q1
     interpolant of the vertex positions X_v + d_v of each cell; xi in [0,1]^dim.
+    The box cell's own map X(xi) is affine with Jacobian diag(h), so
+    J = diag(h) + sum_v d_v (grad psi_v)^T: the displacement part is formed from the
+    displacements themselves, not from differences of positions (whose rounding grows
+    with |X| / h).
     """
-    X = box.vertex_coords() + disp
     vn = box.cell_p_nodes(cells)                          # [nc][2^d] vertices
-    xv = X[:, vn]                                         # [dim][nc][2^d]
-    # J[c,q,a,b] = sum_v dpsi[q,v,b] * xv[a,c,v]
-    return np.einsum("qvb,acv->cqab", ref.dpsi, xv)
+    dv = disp[:, vn]                                      # [dim][nc][2^d]
+    # J[c,q,a,b] = h_a delta_ab + sum_v dpsi[q,v,b] * dv[a,c,v]
+    J = np.einsum("qvb,acv->cqab", ref.dpsi, dv)
+    h = box.h()
+    for a in range(box.dim):
+        J[:, :, a, a] += h[a]
+    return J
 
 
 def geometry_factors(J: np.ndarray, ref: Reference):
@@ -300,6 +307,54 @@ def element_matrices(J: np.ndarray, c_mass: np.ndarray, eta: np.ndarray, ref: Re
     return A, B
 
 
+def element_matrices_abs(J: np.ndarray, c_mass: np.ndarray, eta: np.ndarray, ref: Reference):
+    """Magnitude scales of ``element_matrices``: the same quadrature with every factor of
+    the integrand replaced by its absolute value, and the physical gradients by
+    |G|_{j,x} = sum_b |J^{-1}_{b,x}| |d_b phi_j|,
+
+      |A_K|_{(a,i),(b,j)} = sum_q |w_q det J_q| [ |c_m| d_ab |phi_i phi_j|
+                                               + |eta| ( d_ab sum_x |G|_ix |G|_jx + |G|_ib |G|_ja ) ]
+      |B_K|_{k,(a,j)}     = sum_q |w_q det J_q| |psi_k| |G|_ja.
+
+    Applied to |x| they bound the sum of magnitudes of every term that an evaluation by
+    this quadrature adds, which is the scale of its rounding error (an entry of A_K can
+    vanish by cancellation of its quadrature terms, e.g. the 1D integral of N_1' N_1,
+    while the terms themselves do not)."""
+    dim = ref.dim
+    Jinv, wdet = geometry_factors(J, ref)
+    Ga = np.einsum("cqbx,qib->cqix", np.abs(Jinv), np.abs(ref.dphi))
+    wd = np.abs(wdet)
+    nl = ref.phi.shape[1]
+    aphi = np.abs(ref.phi)
+    mass = np.einsum("cq,qi,qj->cij", wd * np.abs(c_mass), aphi, aphi)
+    lap = np.einsum("cq,cqix,cqjx->cij", wd * np.abs(eta), Ga, Ga)
+    cross = np.einsum("cq,cqib,cqja->caibj", wd * np.abs(eta), Ga, Ga)
+    nc = J.shape[0]
+    A = cross.copy()
+    for a in range(dim):
+        A[:, a, :, a, :] += mass + lap
+    A = A.reshape(nc, dim * nl, dim * nl)
+    B = np.einsum("cq,qk,cqja->ckaj", wd, np.abs(ref.psi), Ga).reshape(nc, ref.psi.shape[1], dim * nl)
+    return A, B
+
+
+def convection_matrices_abs(J: np.ndarray, vconv: np.ndarray, rho: float, r: np.ndarray, ref: Reference):
+    """Magnitude scales of ``convection_matrices`` (absolute integrand factors, |G| as in
+    ``element_matrices_abs``)."""
+    dim = ref.dim
+    Jinv, wdet = geometry_factors(J, ref)
+    Ga = np.einsum("cqbx,qib->cqix", np.abs(Jinv), np.abs(ref.dphi))
+    vg = np.einsum("cqx,cqix->cqi", np.abs(vconv), Ga)
+    wd = np.abs(wdet)
+    conv = abs(rho) * np.einsum("cq,qi,cqj->cij", wd, np.abs(ref.phi), vg)
+    stab = np.einsum("cq,cqi,cqj->cij", wd * np.abs(r), vg, vg)
+    nc, nl = J.shape[0], ref.phi.shape[1]
+    C = np.zeros((nc, dim, nl, dim, nl))
+    for a in range(dim):
+        C[:, a, :, a, :] = conv + stab
+    return C.reshape(nc, dim * nl, dim * nl)
+
+
 def convection_matrices(J: np.ndarray, vconv: np.ndarray, rho: float, r: np.ndarray, ref: Reference):
     """Element matrices of the corrector-mode terms on every cell of the batch.
 
@@ -328,14 +383,15 @@ def convection_matrices(J: np.ndarray, vconv: np.ndarray, rho: float, r: np.ndar
 
 
 def assemble_convection(box: "Box", J: np.ndarray, vconv: np.ndarray, rho: float, r: np.ndarray,
-                        ref: "Reference", chunk: int = 2048) -> sp.csr_matrix:
+                        ref: "Reference", chunk: int = 2048, absolute: bool = False) -> sp.csr_matrix:
     """Global velocity-block matrix of the corrector-mode terms; Dirichlet rows and
-    columns are zero, so A + C keeps the identity rows of ``assemble``."""
+    columns are zero, so A + C keeps the identity rows of ``assemble``.  absolute=True
+    assembles the magnitude scales of ``convection_matrices_abs`` (as ``assemble``)."""
     rows, cols, vals = [], [], []
     nc = box.n_cells
     for s0 in range(0, nc, chunk):
         cs = np.arange(s0, min(nc, s0 + chunk))
-        CK = convection_matrices(J[cs], vconv[cs], rho, r[cs], ref)
+        CK = (convection_matrices_abs if absolute else convection_matrices)(J[cs], vconv[cs], rho, r[cs], ref)
         gd = _global_vel_dofs(box, box.cell_vel_nodes(cs))
         n = gd.shape[1]
         rows.append(np.repeat(gd, n, axis=1).ravel())
@@ -380,14 +436,19 @@ def _global_vel_dofs(box: Box, vn: np.ndarray):
 
 
 def assemble(box: Box, J: np.ndarray, c_mass: np.ndarray, eta: np.ndarray, ref: Reference,
-             chunk: int = 2048) -> Operator:
-    """Global CSR matrices; Dirichlet rows/columns of A become identity, B columns zero."""
+             chunk: int = 2048, absolute: bool = False) -> Operator:
+    """Global CSR matrices; Dirichlet rows/columns of A become identity, B columns zero.
+
+    absolute=True assembles the magnitude scales of ``element_matrices_abs`` instead:
+    applied to |x| they give, per row, the sum of magnitudes of every quadrature term
+    of every cell, the scale of the rounding error of any evaluation of the operator by
+    this quadrature (componentwise error bounds of the parity tests)."""
     rows, cols, vals = [], [], []
     brow, bcol, bval = [], [], []
     nc = box.n_cells
     for s in range(0, nc, chunk):
         cs = np.arange(s, min(nc, s + chunk))
-        AK, BK = element_matrices(J[cs], c_mass[cs], eta[cs], ref)
+        AK, BK = (element_matrices_abs if absolute else element_matrices)(J[cs], c_mass[cs], eta[cs], ref)
         gd = _global_vel_dofs(box, box.cell_vel_nodes(cs))
         gp = box.cell_p_nodes(cs)
         n = gd.shape[1]
@@ -421,14 +482,19 @@ def assemble_unconstrained(box: Box, J, c_mass, eta, ref: Reference) -> Operator
 # ---------------------------------------------------------------- sampled rows (large meshes)
 def apply_rows(box: Box, disp: np.ndarray, c_mass: np.ndarray, eta: np.ndarray,
                ref: Reference, u: np.ndarray, p: Optional[np.ndarray],
-               vel_dofs: Sequence[int], p_dofs: Sequence[int], conv=None):
+               vel_dofs: Sequence[int], p_dofs: Sequence[int], conv=None, absolute: bool = False):
     """Selected entries of (A u + B^T p, B u) evaluated cell by cell.
 
     Only the cells touching the requested rows are integrated, so this works at
     any mesh size.  Dirichlet handling matches ``assemble``.  ``conv`` =
     (vconv, rho, r) adds the corrector-mode terms of ``convection_matrices`` to A.
+    absolute=True evaluates the magnitude scales (|A| |u| + |B|^T |p|, |B| |u|) with the
+    matrices of ``element_matrices_abs``, as ``assemble(absolute=True)``.
     """
     dm = box.dirichlet_vel_dofs()
+    if absolute:
+        u = np.abs(u)
+        p = None if p is None else np.abs(p)
     uf = np.where(dm, 0.0, u)
     nn = box.n_vel_nodes
     needed = set()
@@ -445,10 +511,10 @@ def apply_rows(box: Box, disp: np.ndarray, c_mass: np.ndarray, eta: np.ndarray,
     cells = np.array(sorted(needed), dtype=np.int64)
     pos = {c: i for i, c in enumerate(cells)}
     J = jacobians_q1(box, disp, ref, cells)
-    AK, BK = element_matrices(J, c_mass[cells], eta[cells], ref)
+    AK, BK = (element_matrices_abs if absolute else element_matrices)(J, c_mass[cells], eta[cells], ref)
     if conv is not None:
         vconv, rho, r = conv
-        AK = AK + convection_matrices(J, vconv[cells], rho, r[cells], ref)
+        AK = AK + (convection_matrices_abs if absolute else convection_matrices)(J, vconv[cells], rho, r[cells], ref)
     gd = _global_vel_dofs(box, box.cell_vel_nodes(cells))
     gp = box.cell_p_nodes(cells)
     ov = np.zeros(len(vel_dofs))

@@ -993,7 +993,7 @@ fsi_status fsi_set_displacement(fsi_ctx* h, const double* disp) {
         Level& L = ctx->lv[j];
         double hh[3];
         for (int d = 0; d < L.dim; ++d) hh[d] = ctx->mesh.extent[d] / L.cells[d];
-        launch_geometry_from_disp_h(L, disp, 1 << (J - j), F.pnodes, hh, L.d_K64, L.d_cw64, L.d_K32, ctx->d_flag,
+        launch_geometry_from_disp(L, disp, 1 << (J - j), F.pnodes, hh, L.d_K64, L.d_cw64, L.d_K32, ctx->d_flag,
                                     ctx->stream);
         launch_vertex_disp32(L, disp, 1 << (J - j), F.pnodes, L.d_vd32, ctx->stream);
         L.geo_set = false;

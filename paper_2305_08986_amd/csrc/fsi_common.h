@@ -303,7 +303,7 @@ void launch_cell_res_all(const Level& L, int variant, const T* K, const T* cv, c
 
 void launch_geometry(const Level& L, const double* J, double* K, double* cw, float* K32, int* flag,
                      hipStream_t s);
-void launch_geometry_from_disp_h(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
+void launch_geometry_from_disp(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
                                  const double* h, double* K, double* cw, float* K32, int* flag, hipStream_t s);
 void launch_coefficients(const Level& L, const double* cm, const double* eta, const double* cw,
                          double* cv64, float* cv32, float* cq32, const double* K64, double* Ks64, float* Ks32,

@@ -132,48 +132,31 @@ __global__ void k_geometry_disp(GeoOut g, DispIn in) {
         qi[d] = rq % 3;
         rq /= 3;
     }
+    // x = X + d: the box cell's own map X has Jacobian diag(h) exactly, so only the
+    // displacement is differentiated (differences of positions X + d would lose
+    // digits in proportion to |X| / h)
     double J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int nv = 1 << dim;
     for (int v = 0; v < nv; ++v) {
         int vi[3] = {v & 1, (v >> 1) & 1, (v >> 2) & 1};
         int64_t fidx = 0, st = 1;
-        double X[3];
         for (int d = 0; d < dim; ++d) {
             const int lv = ci[d] + vi[d];
-            X[d] = lv * in.h[d];
             fidx += (int64_t)lv * in.stride * st;
             st *= in.fp[d];
         }
         for (int b = 0; b < dim; ++b) {
             double dl = 1.0;
             for (int d = 0; d < dim; ++d) dl *= (d == b) ? dLd(vi[d]) : dL(qi[d], vi[d]);
-            for (int a = 0; a < dim; ++a) {
-                const double xa = X[a] + in.disp[(int64_t)a * in.nvert_fine + fidx];
-                J[a * dim + b] += dl * xa;
-            }
+            for (int a = 0; a < dim; ++a) J[a * dim + b] += dl * in.disp[(int64_t)a * in.nvert_fine + fidx];
         }
     }
+    for (int a = 0; a < dim; ++a) J[a * dim + a] += in.h[a];
     store_geometry(g, cell, q, J);
 }
 
+// h: the level's reference cell sizes (extent / cells)
 void launch_geometry_from_disp(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
-                               double* K, double* cw, float* K32, int* flag, hipStream_t s) {
-    GeoOut g{L.dim, L.dim == 3 ? 9 : 3, L.Q, L.nc, L.plane(), L.geo, L.d_lex2col, K, cw, K32, flag};
-    DispIn in;
-    in.disp = disp_fine;
-    in.stride = stride;
-    in.nvert_fine = 1;
-    for (int d = 0; d < 3; ++d) {
-        in.fp[d] = d < L.dim ? fine_pnodes[d] : 1;
-        in.cells[d] = L.cells[d];
-        in.h[d] = 0;
-    }
-    for (int d = 0; d < L.dim; ++d) in.nvert_fine *= in.fp[d];
-    hipLaunchKernelGGL(k_geometry_disp, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, g, in);
-}
-
-// h must be set by the caller through a second entry (extent known on the host)
-void launch_geometry_from_disp_h(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
                                  const double* h, double* K, double* cw, float* K32, int* flag, hipStream_t s) {
     GeoOut g{L.dim, L.dim == 3 ? 9 : 3, L.Q, L.nc, L.plane(), L.geo, L.d_lex2col, K, cw, K32, flag};
     DispIn in;

@@ -68,7 +68,33 @@ def test_fgmres_solution_matches_direct(name, prec):
     uo, po = solvers.direct_solve(op, wl.g_u, wl.g_p)
     eu = np.linalg.norm(u - uo) / np.linalg.norm(uo)
     print("velocity error vs direct", eu)
-    assert eu <= 1e3 * rtol
+    # the benchmark spec: velocity within 1e-7 of the FP64 solution at residual 1e-8 (C0 is solved
+    # to 1e-10, so 1e-9 there)
+    assert eu <= 10 * rtol, eu
+
+
+@pytest.mark.parametrize("name", ["T3_16", "T3_8"])
+def test_mixed_and_fp64_solutions_agree_to_1e7(name):
+    """Mixed precision (FP32 V-cycle, FP64 FGMRES) and plain FP64 solves to the same true
+    residual 1e-8: the velocities differ by at most 1e-7 relative (the benchmark spec), and each is
+    within 1e-7 of the oracle's direct solution."""
+    wl, ctx, ops = _setup(name)
+    ctx.autotune()
+    op = ops[-1]
+    gu = torch.from_numpy(wl.g_u).cuda()
+    gp = torch.from_numpy(wl.g_p).cuda()
+    sol = {}
+    for label, prm in (("fp64", dict(precision=0, use_graph=0, fused=0, tuned=0)), ("mixed", dict(precision=1))):
+        ctx.set_mg_params(**prm)
+        u, p, info = ctx.solve(gu, gp, rtol=1e-8, max_iter=400)
+        assert info["status"] == "OK" and info["rel_res"] <= 1e-8, (label, info["rel_res"])
+        sol[label] = (u.cpu().numpy(), p.cpu().numpy(), info["iters"])
+    uo, po = solvers.direct_solve(op, wl.g_u, wl.g_p)
+    du = np.linalg.norm(sol["mixed"][0] - sol["fp64"][0]) / np.linalg.norm(sol["fp64"][0])
+    e64 = np.linalg.norm(sol["fp64"][0] - uo) / np.linalg.norm(uo)
+    emx = np.linalg.norm(sol["mixed"][0] - uo) / np.linalg.norm(uo)
+    print(name, "iterations", sol["fp64"][2], sol["mixed"][2], "du", du, "vs direct", e64, emx)
+    assert du <= 1e-7 and e64 <= 1e-7 and emx <= 1e-7, (du, e64, emx)
 
 
 def _vc(ctx, ru, rp, **prm):

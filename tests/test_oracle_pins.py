@@ -833,3 +833,25 @@ def test_corrector_hierarchy_solves_the_nonsymmetric_system():
     nv = ops[-1].box.n_vel
     assert res.converged and res.iters < 40
     assert np.linalg.norm(res.x[:nv] - u) / np.linalg.norm(u) <= 1e-8
+
+
+def test_absolute_scales_dominate_and_match_signed_diagonals():
+    """The magnitude scales of the parity bounds (fem.element_matrices_abs) dominate the
+    element matrices entry by entry (triangle inequality) and equal them where every
+    integrand term is non-negative: the diagonal of A_K on an axis-aligned cell."""
+    ref = fem.Reference(3)
+    rng = np.random.default_rng(8)
+    box = fem.Box(3, (2, 2, 2), (1.0, 0.9, 0.8), 0)
+    J = fem.jacobians_q1(box, bubble_disp(box, 0.06, seed=9), ref)
+    cm = rng.uniform(0, 3, (box.n_cells, 27))
+    eta = 10 ** rng.uniform(-2, 2, (box.n_cells, 27))
+    A, B = fem.element_matrices(J, cm, eta, ref)
+    Aa, Ba = fem.element_matrices_abs(J, cm, eta, ref)
+    assert (np.abs(A) <= Aa * (1 + 1e-14)).all() and (np.abs(B) <= Ba * (1 + 1e-14)).all()
+    # strictly larger somewhere (cancelling quadrature terms), e.g. the divergence block
+    assert (Ba > np.abs(B) * 1.5 + 1e-12).any()
+    A1, _ = _single_cell(3, (0.5, 0.3, 0.7), 2.0, 0.9)
+    box1 = fem.Box(3, (1, 1, 1), (0.5, 0.3, 0.7), 0)
+    J1 = fem.jacobians_q1(box1, np.zeros((3, box1.n_p)), ref)
+    Aa1, _ = fem.element_matrices_abs(J1, np.full((1, 27), 2.0), np.full((1, 27), 0.9), ref)
+    assert np.allclose(np.diag(Aa1[0]), np.diag(A1), rtol=1e-14, atol=0)
