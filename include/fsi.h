@@ -283,8 +283,8 @@ fsi_status fsi_solve_extension(fsi_ctx* ctx, const double* g, double* u, const f
  * (A, A with the fused Chebyshev step, Stokes, Stokes with the fused residual,
  * B, B^T), level and precision, and keeps the fastest of each; then, per 3D level,
  * the phased launches of the unfused applies against their single atomic launch
- * (variants 16, 17 below), and the fused epilogues against the separate vector
- * kernels.  Synchronises; fsi_get_tuning reports the choice for A (16 or 17 where the
+ * (variants 16 .. 20 below), and the fused epilogues against the separate vector
+ * kernels.  Synchronises; fsi_get_tuning reports the choice for A (16 .. 20 where the
  * atomic launch was chosen) and its measured time per application in best_us. */
 fsi_status fsi_autotune(fsi_ctx* ctx);
 fsi_status fsi_get_tuning(const fsi_ctx* ctx, int level, int precision, int* variant, double* best_us);
@@ -294,12 +294,14 @@ fsi_status fsi_get_tuning(const fsi_ctx* ctx, int level, int precision, int* var
  * per wavefront, at most two); (v / 3) % 2 cached instead of streaming geometry
  * loads; v / 6 a register cap of one more wavefront per SIMD.  v = 12 .. 15: three
  * wavefronts share a row (2D: two rows), (v - 12) % 2 cached loads, (v - 12) / 2 the
- * register cap.  v = 16, 17 (3D levels): the unfused applies (A, B, B^T, Stokes) run
+ * register cap.  v = 16 .. 20 (3D levels): the unfused applies (A, B, B^T, Stokes) run
  * as one launch over all processing phases that adds into zeroed outputs with
- * atomics, one (16) or four (17) wavefronts per row; results then vary in the last
- * bits from run to run; the fused epilogues keep variant 0.  fsi_autotune picks this
- * form for a level where it measures it faster (latency-bound small levels).
- * Errors: FSI_ERR_ARG. */
+ * atomics and writes the wall rows itself: one (16) or four (17) wavefronts per row,
+ * one wavefront over two (18) or four (19) rows along z, four wavefronts over two rows
+ * along z (20), where the node plane two rows of a group share is summed in registers
+ * and stored once; results then vary in the last bits from run to run; the fused
+ * epilogues keep variant 0.  fsi_autotune picks this form for a level where it
+ * measures it faster.  Errors: FSI_ERR_ARG. */
 fsi_status fsi_set_tuning(fsi_ctx* ctx, int level, int precision, int variant);
 
 /* Measurement support: runs `reps` applications of the level operator

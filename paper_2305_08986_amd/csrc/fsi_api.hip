@@ -75,6 +75,7 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
     }
     L.nv = dim * L.nvn;
     L.nvert = L.np;
+    L.dfaces = m.dirichlet_faces;
     const int NLOC = dim == 3 ? 27 : 9, NPL = dim == 3 ? 8 : 4;
     // wall mask of the velocity nodes
     L.h_dir_node.assign((size_t)L.nvn, 0);
@@ -1640,7 +1641,7 @@ fsi_status fsi_autotune(fsi_ctx* h) {
                 ctx->atom[pi][k] = -1;
                 if (ctx->lv[j].dim != 3) continue;
                 double best = ctx->tune_us[pi][k];
-                for (int shape = 0; shape < 2; ++shape) {
+                for (int shape = 0; shape < kAtomShapes; ++shape) {
                     const int reps = 3;
                     for (int r = 0; r <= reps; ++r) {
                         if (r == 1) FSI_HIP_TRY(hipEventRecord(e0, s));
@@ -1791,7 +1792,7 @@ fsi_status fsi_set_tuning(fsi_ctx* h, int level, int precision, int variant) {
     if (!h) return FSI_ERR_ARG;
     Context* ctx = &h->c;
     if (level < 0 || level >= ctx->nlev || (precision != 0 && precision != 1) || variant < 0 ||
-        variant >= kNumVariants + 2)
+        variant >= kNumVariants + kAtomShapes)
         return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: level, precision or variant out of range");
     const bool atomic = variant >= kNumVariants;
     if (atomic && ctx->lv[level].dim != 3)

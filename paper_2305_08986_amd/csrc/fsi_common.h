@@ -90,6 +90,7 @@ struct Level {
     int vnodes[3] = {1, 1, 1};
     int pnodes[3] = {1, 1, 1};
     int64_t nc = 0, nvn = 0, nv = 0, np = 0, nvert = 0;
+    uint32_t dfaces = 0;           // Dirichlet face bits of the mesh (fsi_mesh_desc)
     int Q = 0;
     int ncolors = 0;
     // processing phases: the parity colours of the row index (iy[, iz]); cells
@@ -278,7 +279,9 @@ template <typename T>
 void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T* cv,
                      const T* u, const double* p, T* v, double* q, hipStream_t s);
 // the same apply in one launch over all phases with atomic adds, wall rows included
-// (3D; modes A, B, B^T and A + B^T + B; shape 0 or 1: one or four wavefronts per row)
+// (3D; modes A, B, B^T and A + B^T + B; shape 0 .. kAtomShapes - 1: one or four
+// wavefronts per row, rows grouped along z by one, two or four)
+constexpr int kAtomShapes = 5;
 template <typename T>
 void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T* cv,
                         const T* u, const double* p, T* v, double* q, hipStream_t s);
@@ -320,9 +323,9 @@ inline const uint8_t* level_wall_mask(const Level& L) { return L.d_wall; }
 
 template <typename T>
 void launch_fill(T* x, T val, int64_t n, hipStream_t s);
-// v = 0 except v[wall] = u[wall] (u may be null: zero there too), q = 0; v or q may be null
+// outputs of the single atomic launch: v = 0 (all rows) and q = 0; v or q may be null
 template <typename T>
-void launch_atomic_init(const Level& L, const T* u, T* v, double* q, hipStream_t s);
+void launch_atomic_init(const Level& L, T* v, double* q, hipStream_t s);
 template <typename T>
 void launch_dirichlet_copy(const Level& L, const T* u, T* v, hipStream_t s);   // v[wall] = u[wall]
 template <typename T>

@@ -533,18 +533,6 @@ void launch_dirichlet_copy(const Level& L, const T* u, T* v, hipStream_t s) {
 template void launch_dirichlet_copy<double>(const Level&, const double*, double*, hipStream_t);
 template void launch_dirichlet_copy<float>(const Level&, const float*, float*, hipStream_t);
 
-// outputs of the single atomic cell launch: v = 0 except on wall nodes, where v = u
-// (u null: 0 there too), and q = 0; either output may be null
-template <typename T>
-__global__ void k_atomic_init(const uint8_t* __restrict__ wall, int dim, int64_t nvn, const T* __restrict__ u,
-                              T* __restrict__ v, double* __restrict__ q, int64_t np) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v && i < nvn) {
-        const bool w = u && wall[i];
-        for (int c = 0; c < dim; ++c) v[c * nvn + i] = w ? u[c * nvn + i] : T(0);
-    }
-    if (q && i < np) q[i] = 0.0;
-}
 // zero n elements: 16-byte stores over the body (x 16-byte aligned), element stores
 // for the tail
 template <typename T>
@@ -566,24 +554,26 @@ static void launch_zero(T* x, int64_t n, hipStream_t s) {
     const int64_t nb = n / E;
     hipLaunchKernelGGL(k_zero16<T>, dim3(nblocks(std::max<int64_t>(nb, n - nb * E))), dim3(TPB), 0, s, x, n);
 }
+// v = 0 and q = 0 in one launch (small levels, where launch latency dominates)
 template <typename T>
-void launch_atomic_init(const Level& L, const T* u, T* v, double* q, hipStream_t s) {
-    // large levels: streaming zero fills at full store width, then the wall rows; small
-    // levels: one kernel (launch latency dominates there)
+__global__ void k_zero2(T* __restrict__ v, int64_t nv, double* __restrict__ q, int64_t np) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v && i < nv) v[i] = T(0);
+    if (q && i < np) q[i] = 0.0;
+}
+template <typename T>
+void launch_atomic_init(const Level& L, T* v, double* q, hipStream_t s) {
+    // large levels: streaming zero fills at full store width; small levels: one kernel
     if (L.nvn >= (int64_t(1) << 20)) {
-        if (v) {
-            launch_zero<T>(v, L.nv, s);
-            if (u) launch_dirichlet_copy<T>(L, u, v, s);
-        }
+        if (v) launch_zero<T>(v, L.nv, s);
         if (q) launch_zero<double>(q, L.np, s);
         return;
     }
-    const int64_t n = std::max(v ? L.nvn : 0, q ? L.np : 0);
-    if (n > 0)
-        hipLaunchKernelGGL(k_atomic_init<T>, dim3(nblocks(n)), dim3(TPB), 0, s, L.d_wall, L.dim, L.nvn, u, v, q, L.np);
+    const int64_t n = std::max(v ? L.nv : 0, q ? L.np : 0);
+    if (n > 0) hipLaunchKernelGGL(k_zero2<T>, dim3(nblocks(n)), dim3(TPB), 0, s, v, L.nv, q, L.np);
 }
-template void launch_atomic_init<double>(const Level&, const double*, double*, double*, hipStream_t);
-template void launch_atomic_init<float>(const Level&, const float*, float*, double*, hipStream_t);
+template void launch_atomic_init<double>(const Level&, double*, double*, hipStream_t);
+template void launch_atomic_init<float>(const Level&, float*, double*, hipStream_t);
 
 template <typename T>
 __global__ void k_dir_zero(const int* __restrict__ nodes, int64_t nd, int dim, int64_t nvn, T* __restrict__ v) {

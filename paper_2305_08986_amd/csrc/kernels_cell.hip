@@ -102,6 +102,13 @@ struct CellArgs {
     const T* __restrict__ cb;
     const T* __restrict__ cs;
     T rho;
+    // OP_ATOM: cell->node and cell->vertex indices and wall bits follow from the cell's
+    // coordinates on the structured box (no map or cell-info reads): cells per direction
+    // (y, z), Q2 node counts, Q1 vertex counts (x, y), Dirichlet face bits
+    int cny, cnz;
+    int vnx, vny, vnz;
+    int pnx, pny;
+    unsigned dfaces;
 };
 
 // ============================================================== 3D
@@ -113,7 +120,11 @@ struct CellArgs {
 // times more wavefronts in flight; the x-face hand-over then crosses wavefronts.
 // Only the two hand-overs (x-face values and pressure partial sums) synchronise the
 // workgroup; the LDS transposes between sweep directions are wavefront-private.
-template <typename T, int MODE, int WPB, bool RS, bool NTL, int WPE, bool VG>
+// ZG > 1 (the atomic form): a workgroup takes ZG consecutive rows along z at the same y
+// and walks them chunk by chunk, z innermost; the node plane two neighbouring rows of the
+// group share is summed in registers and stored once, so only the group's outer z-planes
+// and the y-faces take atomics.
+template <typename T, int MODE, int WPB, bool RS, bool NTL, int WPE, bool VG, int ZG>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE))) void cell3d(CellArgs<T> a) {
     constexpr int NT = 9, CPW = 7, NLOC = 27, BUF = 243;
     constexpr bool FWD = (MODE & (OP_A | OP_B)) != 0;
@@ -133,6 +144,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     static_assert(!CONV || !VG, "the corrector terms use the stored geometry");
     static_assert(!RES || MODE == (OP_A | OP_BT | OP_B | OP_RES), "the residual epilogue goes with the Stokes apply");
     static_assert(!VG || sizeof(T) == 4, "geometry from vertices is the FP32 path");
+    static_assert(ZG == 1 || ATOM, "row groups along z belong to the atomic form");
     // A alone reads K' = sqrt(cvisc) K (no cvisc plane): sym(grad-hat u K') K'^T = cvisc sym(H) K^T
     constexpr bool SCALED = !VG && ((MODE & ~OP_ATOM) == OP_A || MODE == (OP_A | OP_CHEB));
     __shared__ T sbuf[WPB][CPW][BUF];
@@ -142,17 +154,36 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     // (double-buffered by step parity, so that a wavefront may start the next step
     // while its right neighbour still reads the previous step's values)
     __shared__ T xb[2][WPB][CPW][27];
-    __shared__ T xcarry[WPB][2][27];
+    __shared__ T xcarry[WPB][ZG][2][27];
     __shared__ double pxb[2][HAS_B ? WPB : 1][CPW][4];
-    __shared__ double pcarry[HAS_B ? WPB : 1][2][4];
+    __shared__ double pcarry[HAS_B ? WPB : 1][ZG][2][4];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane / NT, t = lane - slot * NT;
     const bool inwave = slot < CPW;
     const int64_t slot_row = RS ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * WPB + wave;
-    const bool rowact = slot_row < a.nrows;
-    // the atomic form has no order to keep: its dispatch slots follow the row map
-    const int64_t row = (ATOM && rowact) ? (int64_t)a.rowmap[slot_row] : slot_row;
+    const bool slotact = slot_row < a.nrows;
+    // the atomic form has no order to keep: dispatch slot g takes the natural rows
+    // (iy, iz) = (g mod ny, ZG (g div ny) + z), whose geometry sits at the phase-major
+    // row that the row map gives
+    int siy = 0, siz0 = 0;
+    if constexpr (ATOM) {
+        siy = (int)(slot_row % a.cny);
+        siz0 = (int)(slot_row / a.cny) * ZG;
+    }
+    // row z of the slot's group active; its geometry row (loaded once, before the walk,
+    // so that no step's geometry loads wait for a row-map load)
+    auto zact = [&](int z) { return ATOM ? (slotact && siz0 + z < a.cnz) : slotact; };
+    int zr[4] = {0, 0, 0, 0};
+    if constexpr (ATOM) {
+#pragma unroll
+        for (int z = 0; z < ZG; ++z)
+            zr[z] = zact(z) ? __builtin_amdgcn_readfirstlane(a.rowmap[siy + (int64_t)a.cny * (siz0 + z)]) : 0;
+    }
+    auto zrow = [&](int z) -> int64_t {
+        if constexpr (ATOM) return z == 0 ? zr[0] : (z == 1 ? zr[1] : (z == 2 ? zr[2] : zr[3]));
+        else return slot_row;
+    };
     const int nsteps = RS ? (a.nchunks + WPB - 1) / WPB : a.nchunks;
     const int cw = RS ? 0 : wave;                  // owner of the chunk-to-chunk carry
     const bool carry_out = !RS || wave == WPB - 1; // this wavefront's last cell feeds the next step
@@ -169,21 +200,29 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     // dependent round trip out of the step; the other modes fetch them in the step
     // itself (measured faster there: 7 more live registers cost them more than the
     // round trip)
-    constexpr bool PREF = HAS_A && HAS_BT;
-    uint4 inf_nx;
-    int node_nx[3];
+    constexpr bool PREF = HAS_A && HAS_BT && !ATOM;
+    uint4 inf_nx = make_uint4(0u, 0u, 0u, 0u);
+    int node_nx[3] = {0, 0, 0};
     auto fetch_idx = [&](int stp) {
         const int chp = RS ? stp * WPB + wave : stp;
         const int ixp = chp * CPW + slot;
-        const bool actp = rowact && inwave && stp < nsteps && ixp < a.nx;
-        const int64_t cellp = a.cbeg + row * a.nx + ixp;
+        const bool actp = slotact && inwave && stp < nsteps && ixp < a.nx;
+        const int64_t cellp = a.cbeg + slot_row * a.nx + ixp;
         inf_nx = actp ? a.info[cellp] : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
         for (int k = 0; k < 3; ++k) node_nx[k] = actp ? a.vmap[cellp * NLOC + t + 9 * k] : 0;
     };
     if constexpr (PREF) fetch_idx(0);
-    for (int st = 0; st < nsteps; ++st) {
-        if constexpr (!PREF) fetch_idx(st);
+    // the node plane a row of a z-group shares with the next row: this thread's sums
+    // there (the writer threads' complete x-face values), added at the next z
+    T zc[3] = {T(0), T(0), T(0)};
+    for (int st = 0; st < nsteps; ++st)
+#pragma unroll 1
+    for (int z = 0; z < ZG; ++z) {
+        const int ls = st * ZG + z;                        // linear step: hand-over buffer parity
+        const bool rowact = zact(z);
+        const int64_t row = __builtin_amdgcn_readfirstlane((int)zrow(z));
+        if constexpr (!PREF && !ATOM) fetch_idx(st);
         const int ch = RS ? st * WPB + wave : st;
         const int ix = ch * CPW + slot;
         const bool act = rowact && inwave && ix < a.nx;
@@ -195,14 +234,39 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         // does this thread write its column (x-face columns go to the right neighbour)?
         const bool vwriter = act && (ic != 2 || ix == a.nx - 1);
         const bool pwriter = act && t < 8 && (pax == 0 || ix == a.nx - 1);
+        // the atomic form: node indices, wall bits of this thread's column and the cell's
+        // vertices from the cell coordinates (ix, iy, iz)
+        const int iz = siz0 + z;
+        int node[3] = {node_nx[0], node_nx[1], node_nx[2]};
+        unsigned wbits = 0;   // bit k: node (ic, jc, k) lies on a Dirichlet face
+        if constexpr (ATOM) {
+            const int gx = 2 * ix + ic, gy = 2 * siy + jc;
+            const bool wxy = ((a.dfaces & 1u) && gx == 0) || ((a.dfaces & 2u) && gx == a.vnx - 1) ||
+                             ((a.dfaces & 4u) && gy == 0) || ((a.dfaces & 8u) && gy == a.vny - 1);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int gz = 2 * iz + k;
+                node[k] = gx + a.vnx * (gy + a.vny * gz);
+                const bool w = wxy || ((a.dfaces & 16u) && gz == 0) || ((a.dfaces & 32u) && gz == a.vnz - 1);
+                wbits |= (w ? 1u : 0u) << k;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) wbits |= ((inf.x >> (t + 9 * k)) & 1u) << k;
+        }
+        // Q1 vertex n = (n & 1, (n >> 1) & 1, n >> 2) of the cell
+        auto vert = [&](int n) -> int {
+            if constexpr (ATOM)
+                return (ix + (n & 1)) + a.pnx * ((siy + ((n >> 1) & 1)) + a.pny * (iz + (n >> 2)));
+            else
+                return a.pmap[cell * 8 + n];
+        };
 
         // ---------------- loads
-        const int node[3] = {node_nx[0], node_nx[1], node_nx[2]};
         T uu[3][3];     // [comp][k] velocity of the column nodes
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const int ln = t + 9 * k;
-            const bool wall = (inf.x >> ln) & 1u;
+            const bool wall = (wbits >> k) & 1u;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 uu[c][k] = (FWD && act && !wall) ? (CHEB ? a.x : a.u)[c * a.nvn + node[k]] : T(0);
@@ -222,14 +286,14 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         }
         int pnode = 0;
         if constexpr (HAS_B) {
-            if (pwriter) pnode = a.pmap[cell * 8 + t];
+            if (pwriter) pnode = vert(t);
         }
         T pv[8];
         if constexpr (HAS_BT) {
             // threads t < 8 of a cell fetch one vertex value each; the cell's other
             // threads read them across lanes (one memory round trip instead of
             // eight index + eight value loads per thread)
-            const T mine = (act && t < 8) ? T(a.p[a.pmap[cell * 8 + t]]) : T(0);
+            const T mine = (act && t < 8) ? T(a.p[vert(t)]) : T(0);
             const int base = lane - t;   // lane of the cell's first thread
 #pragma unroll
             for (int n = 0; n < 8; ++n) pv[n] = __shfl(mine, base + n, 64);
@@ -242,7 +306,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         if constexpr (VG) {
             float4 dv[8];
 #pragma unroll
-            for (int n = 0; n < 8; ++n) dv[n] = act ? a.vd[a.pmap[cell * 8 + n]] : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int n = 0; n < 8; ++n) dv[n] = act ? a.vd[vert(n)] : make_float4(0.f, 0.f, 0.f, 0.f);
             const T ly0 = rL<T>(qy, 0), ly1 = rL<T>(qy, 1), lz0 = rL<T>(qz, 0), lz1 = rL<T>(qz, 1);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -600,19 +664,19 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             if (inwave && t < 8) {
 #pragma unroll
                 for (int tt = 0; tt < NT; ++tt) sq += pbuf[wave][slot][tt][t];
-                if (pax == 1) pxb[st & 1][wave][slot][pyz] = sq;
+                if (pax == 1) pxb[ls & 1][wave][slot][pyz] = sq;
             }
             __syncthreads();   // pxb crosses wavefronts (row sharing)
             if (act && t < 8) {
                 if (pax == 0 && ix > 0)
-                    sq += slot > 0 ? pxb[st & 1][wave][slot - 1][pyz]
-                                   : ((RS && wave > 0) ? pxb[st & 1][wave - 1][CPW - 1][pyz]
-                                                       : pcarry[cw][(st + 1) & 1][pyz]);
+                    sq += slot > 0 ? pxb[ls & 1][wave][slot - 1][pyz]
+                                   : ((RS && wave > 0) ? pxb[ls & 1][wave - 1][CPW - 1][pyz]
+                                                       : pcarry[cw][z][(st + 1) & 1][pyz]);
                 if (pwriter) {
                     if constexpr (ATOM) unsafeAtomicAdd(&a.q[pnode], sq);
                     else a.q[pnode] = plast ? qold - sq : qold + sq;
                 } else if (slot == CPW - 1 && carry_out) {
-                    pcarry[cw][st & 1][pyz] = sq;
+                    pcarry[cw][z][st & 1][pyz] = sq;
                 }
             }
         }
@@ -641,9 +705,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const int ln = t + 9 * k;
-                    const bool last = vwriter && !((inf.x >> ln) & 1u) && ((inf.w >> ln) & 1u);
+                    const bool last = vwriter && !((wbits >> k) & 1u) && ((inf.w >> ln) & 1u);
                     // every node this step adds to: earlier phases' partial sum
-                    const bool part = vwriter && !((inf.x >> ln) & 1u) && !((inf.y >> ln) & 1u);
+                    const bool part = vwriter && !((wbits >> k) & 1u) && !((inf.y >> ln) & 1u);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         const int64_t i = c * a.nvn + node[k];
@@ -662,7 +726,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const int ln = t + 9 * k;
-                    const bool part = !ATOM && vwriter && !((inf.x >> ln) & 1u) && !((inf.y >> ln) & 1u);
+                    const bool part = !ATOM && vwriter && !((wbits >> k) & 1u) && !((inf.y >> ln) & 1u);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) ep[c][k] = part ? a.v[c * a.nvn + node[k]] : T(0);
                 }
@@ -722,7 +786,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) xb[st & 1][wave][slot][jc * 9 + c * 3 + k] = out[c][k];
+                    for (int k = 0; k < 3; ++k) xb[ls & 1][wave][slot][jc * 9 + c * 3 + k] = out[c][k];
             }
             __syncthreads();   // xb crosses wavefronts (row sharing)
             if (act) {
@@ -731,15 +795,56 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                     for (int c = 0; c < 3; ++c)
 #pragma unroll
                         for (int k = 0; k < 3; ++k)
-                            out[c][k] += slot > 0 ? xb[st & 1][wave][slot - 1][jc * 9 + c * 3 + k]
-                                                  : ((RS && wave > 0) ? xb[st & 1][wave - 1][CPW - 1][jc * 9 + c * 3 + k]
-                                                                      : xcarry[cw][(st + 1) & 1][jc * 9 + c * 3 + k]);
+                            out[c][k] += slot > 0 ? xb[ls & 1][wave][slot - 1][jc * 9 + c * 3 + k]
+                                                  : ((RS && wave > 0) ? xb[ls & 1][wave - 1][CPW - 1][jc * 9 + c * 3 + k]
+                                                                      : xcarry[cw][z][(st + 1) & 1][jc * 9 + c * 3 + k]);
                 }
-                if (vwriter) {
+                if (ATOM && vwriter) {
+                    // z-group: the plane shared with the previous row of the group is complete
+                    // once that row's sums are added; the plane shared with the next row is
+                    // carried; the group's outer planes and the y-faces (jc 0 and 2, shared
+                    // with the neighbouring y rows) take atomics.  Wall rows: v = u (A and
+                    // the Stokes apply; B^T leaves the zeroed output), written by one owner
+                    // per node: the x writer, at jc > 0 or iy = 0, at k > 0 or iz = 0.
+                    const bool carry_next = ZG > 1 && z + 1 < ZG && zact(z + 1);
+                    if (ZG > 1 && z > 0) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) out[c][0] += zc[c];
+                    }
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const int64_t nd = node[k];
+                        if ((wbits >> k) & 1u) {
+                            if (HAS_A && (jc > 0 || siy == 0) && (k > 0 || iz == 0)) {
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) a.v[c * a.nvn + nd] = a.u[c * a.nvn + nd];
+                            }
+                            continue;
+                        }
+                        if (k == 0 && ZG > 1 && z > 0 && jc != 1) {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) unsafeAtomicAdd(&a.v[c * a.nvn + nd], out[c][0]);
+                            continue;
+                        }
+                        if (k == 2 && carry_next) continue;   // added at the next z
+                        const bool plain = jc == 1 && (k == 1 || (k == 0 && ZG > 1 && z > 0));
+                        if (plain) {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) a.v[c * a.nvn + nd] = out[c][k];
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) unsafeAtomicAdd(&a.v[c * a.nvn + nd], out[c][k]);
+                        }
+                    }
+                    if (ZG > 1) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) zc[c] = out[c][2];
+                    }
+                } else if (vwriter) {
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
                         const int ln = t + 9 * k;
-                        if ((inf.x >> ln) & 1u) continue;
+                        if ((wbits >> k) & 1u) continue;
                         const bool first = (inf.y >> ln) & 1u;   // first touch of the node in phase order
                         if ((CHEB || RES) && ((inf.w >> ln) & 1u)) {
                             // last touch: the row of A x (M u) is complete here
@@ -756,16 +861,6 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                                     a.v[i] = er[c][k] - tot;
                                 }
                             }
-                        } else if (ATOM) {
-                            // the node in the middle of the cell's y-z cross-section belongs
-                            // to this row alone, and the row writes it once: a plain store
-                            if (jc == 1 && k == 1) {
-#pragma unroll
-                                for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node[k]] = out[c][k];
-                            } else {
-#pragma unroll
-                                for (int c = 0; c < 3; ++c) unsafeAtomicAdd(&a.v[c * a.nvn + node[k]], out[c][k]);
-                            }
                         } else if (first) {
 #pragma unroll
                             for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node[k]] = out[c][k];
@@ -774,16 +869,17 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                             for (int c = 0; c < 3; ++c) a.v[c * a.nvn + node[k]] = ep[c][k] + out[c][k];
                         }
                     }
-                } else if (slot == CPW - 1 && carry_out) {
+                }
+                if (!vwriter && slot == CPW - 1 && carry_out) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) xcarry[cw][st & 1][jc * 9 + c * 3 + k] = out[c][k];
+                        for (int k = 0; k < 3; ++k) xcarry[cw][z][st & 1][jc * 9 + c * 3 + k] = out[c][k];
                 }
             }
         }
         wave_sync();
-    }   // chunk loop
+    }   // chunk and z loops
 }
 
 // ============================================================== 2D
@@ -1085,22 +1181,24 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
 // Phase p holds whole rows of cells (cells[0] each); one wavefront walks a row.
 // WPB > 1: in 3D the wavefronts of a workgroup share a row (one row per workgroup);
 // in 2D each wavefront keeps its own row (two per workgroup)
-template <typename T, int MODE, int WPB, bool NTL, int WPE>
+template <typename T, int MODE, int WPB, bool NTL, int WPE, int ZG = 1>
 static void launch_one(const Level& L, const CellArgs<T>& args, hipStream_t s) {
     if (args.nrows <= 0) return;
     if (L.dim == 3) {
         constexpr bool RS = WPB > 1;
-        const int64_t grid = args.nrows;   // one workgroup per row
+        const int64_t grid = args.nrows;   // one workgroup per row (per z-group of rows)
         // the corrector terms use the stored geometry, also where the FP32 applies form it
         // from the vertices
         if constexpr (sizeof(T) == 4 && (MODE & OP_CONV) == 0) {
             if (args.vd) {
-                hipLaunchKernelGGL((cell3d<T, MODE, WPB, RS, NTL, WPE, true>), dim3((unsigned)grid), dim3(64 * WPB), 0,
-                                   s, args);
+                // forming the geometry takes more registers: at most three wavefronts per SIMD
+                constexpr int WV = WPE > 3 ? 3 : WPE;
+                hipLaunchKernelGGL((cell3d<T, MODE, WPB, RS, NTL, WV, true, ZG>), dim3((unsigned)grid), dim3(64 * WPB),
+                                   0, s, args);
                 return;
             }
         }
-        hipLaunchKernelGGL((cell3d<T, MODE, WPB, RS, NTL, WPE, false>), dim3((unsigned)grid), dim3(64 * WPB), 0, s,
+        hipLaunchKernelGGL((cell3d<T, MODE, WPB, RS, NTL, WPE, false, ZG>), dim3((unsigned)grid), dim3(64 * WPB), 0, s,
                            args);
     } else if constexpr ((MODE & (OP_CONV | OP_ATOM)) == 0) {   // the corrector terms and the atomic form are 3D only
         constexpr int W2 = WPB > 1 ? 2 : 1;   // 2D: one row per wavefront, at most two
@@ -1213,29 +1311,49 @@ void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T*
     for (int ph = 0; ph < L.nphases(); ++ph) launch_cell<T>(L, mode, variant, ph, K, cv, u, p, v, q, s);
 }
 
-// every phase in one launch (3D, modes A, B, B^T, A + B^T + B): one kernel sets the
-// outputs (zero, and on wall rows v = u when A is applied, else zero: the rows the
-// phased launches leave to the Dirichlet kernels), then each cell adds its
-// contributions atomically.  shape 0: one wavefront per row; 1: four wavefronts
-// share a row.
+// every phase in one launch (3D, modes A, B, B^T, A + B^T + B): one kernel zeroes the
+// outputs, then each cell adds its contributions atomically and the cell kernel writes
+// the wall rows itself (v = u when A is applied; B^T alone leaves them zero).  Shapes
+// (kAtomShapes): 0 one wavefront per row; 1 four wavefronts share a row; 2, 3 one
+// wavefront takes two or four rows along z (the plane they share summed in registers);
+// 4 four wavefronts share a pair of rows along z.
+template <int ZG>
+static int64_t atom_slots(const Level& L) {
+    return (int64_t)L.cells[1] * ((L.cells[2] + ZG - 1) / ZG);
+}
+
 template <typename T>
 void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T* cv, const T* u, const double* p,
                         T* v, double* q, hipStream_t s) {
     CellArgs<T> args = phase_args<T>(L, 0, K, cv);
     args.cend = L.phase_off[L.nphases()];
-    args.nrows = (args.cend - args.cbeg) / L.cells[0];
     args.rowmap = L.d_atom_rows;
+    args.cny = L.cells[1];
+    args.cnz = L.cells[2];
+    args.vnx = L.vnodes[0];
+    args.vny = L.vnodes[1];
+    args.vnz = L.vnodes[2];
+    args.pnx = L.pnodes[0];
+    args.pny = L.pnodes[1];
+    args.dfaces = L.dfaces;
     args.u = u;
     args.p = p;
     args.v = v;
     args.q = q;
-    launch_atomic_init<T>(L, (mode & OP_A) ? u : nullptr, (mode & (OP_A | OP_BT)) ? v : nullptr,
-                          (mode & OP_B) ? q : nullptr, s);
+    launch_atomic_init<T>(L, (mode & (OP_A | OP_BT)) ? v : nullptr, (mode & OP_B) ? q : nullptr, s);
     auto go = [&](auto mc) {
         constexpr int M = decltype(mc)::value | OP_ATOM;
-        constexpr int W0 = (sizeof(T) == 8 && !((M & OP_A) && (M & OP_BT))) ? 2 : 1;
-        if (shape == 0) launch_one<T, M, 1, true, W0>(L, args, s);
-        else launch_one<T, M, 4, true, W0>(L, args, s);
+        // waves per SIMD the unfused classes reach: FP64 two (A, B, B^T), FP32 four; the
+        // Stokes classes are left unconstrained
+        constexpr bool STOKES = (M & OP_A) && (M & OP_BT);
+        constexpr int W0 = STOKES ? 1 : (sizeof(T) == 8 ? 2 : 4);
+        switch (shape) {
+            case 0: args.nrows = atom_slots<1>(L); launch_one<T, M, 1, true, W0, 1>(L, args, s); break;
+            case 1: args.nrows = atom_slots<1>(L); launch_one<T, M, 4, true, W0, 1>(L, args, s); break;
+            case 2: args.nrows = atom_slots<2>(L); launch_one<T, M, 1, true, W0, 2>(L, args, s); break;
+            case 3: args.nrows = atom_slots<4>(L); launch_one<T, M, 1, true, W0, 4>(L, args, s); break;
+            default: args.nrows = atom_slots<2>(L); launch_one<T, M, 4, true, W0, 2>(L, args, s); break;
+        }
     };
     switch (mode) {
         case OP_A: go(std::integral_constant<int, OP_A>{}); break;

@@ -28,8 +28,10 @@ PREC_FP64 = 0
 PREC_MIXED = 1
 # cell-kernel launch variants that fsi_set_tuning accepts (0 .. N_LAUNCH_VARIANTS - 1)
 N_LAUNCH_VARIANTS = 16
-# fsi_set_tuning values of the single atomic launch over all phases (3D levels)
-ATOMIC_VARIANTS = (16, 17)
+# fsi_set_tuning values of the single atomic launch over all phases (3D levels): one or
+# four wavefronts per row, one wavefront over two or four rows along z, four wavefronts
+# over two rows along z
+ATOMIC_VARIANTS = (16, 17, 18, 19, 20)
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_STATE", -3: "ERR_HIP", -4: "ERR_OOM",
                 -5: "ERR_INVERTED_CELL", -6: "ERR_BREAKDOWN", -7: "ERR_NONFINITE"}
