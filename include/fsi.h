@@ -92,12 +92,13 @@ typedef struct {
     int tuned;               /* 1: autotuned launch variant per level and, with fused = 1, the
                                 fused or separate form per level, whichever fsi_autotune
                                 measured faster; 0: the default variant, fused everywhere */
-    int vertex_geometry;     /* 1: FP32 cell kernels on 3D levels form det(J) w J^{-1} at each
-                                quadrature point from the vertex displacements given to
-                                fsi_set_displacement (multilinear map, Sec. 3.2) instead of
-                                reading the stored values; 0: stored values (default).  FP64
-                                kernels always read the stored values.  Switching needs no new
-                                setup. */
+    int vertex_geometry;     /* bit 0: FP32 cell kernels, bit 1: FP64 cell kernels on 3D levels
+                                form det(J) w J^{-1} = w adj(J) at each quadrature point from the
+                                vertex displacements given to fsi_set_displacement (multilinear
+                                map, Sec. 3.2) and read only (2 eta, c_m) per point, instead of
+                                reading the stored values; 0: stored values (default).  Levels
+                                whose geometry came from fsi_set_jacobians always read the
+                                stored values.  Switching needs no new setup. */
     int corrector;           /* 1: corrector mode (Sec. 3.1.1, Sec. 4; 3D): every level's velocity
                                 block is A + N + S with the terms of fsi_set_convection (needed on
                                 every level before fsi_setup), the Schur step is one BiCGStab

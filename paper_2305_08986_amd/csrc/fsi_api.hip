@@ -234,6 +234,8 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
     TRY(dalloc(ctx, &L.d_Ks64, (int64_t)dim * dim * P));
     TRY(dalloc(ctx, &L.d_Ks32, (int64_t)dim * dim * P));
     TRY(dalloc(ctx, &L.d_vd32, L.np));
+    TRY(dalloc(ctx, &L.d_cq64, 2 * P));
+    TRY(dalloc(ctx, &L.d_vd64, L.np));
     for (int d = 0; d < dim; ++d) L.h[d] = m.extent[d] / L.cells[d];
     TRY(dalloc(ctx, &L.d_dAinv64, L.nv));
     TRY(dalloc(ctx, &L.d_dAinv32, L.nv));
@@ -301,8 +303,8 @@ static int variant_of(const Context* ctx, int prec, int level, int mode) {
 
 // the parameters that change what a captured graph launches
 static int path_key(const Context* ctx) {
-    return (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry ? 4 : 0) |
-           (ctx->prm.corrector ? 8 : 0) | (ctx->prm.atomics ? 16 : 0);
+    return (ctx->prm.fused ? 1 : 0) | (ctx->prm.tuned ? 2 : 0) | (ctx->prm.vertex_geometry << 2) |
+           (ctx->prm.corrector ? 16 : 0) | (ctx->prm.atomics ? 32 : 0);
 }
 
 // the solver's velocity block: A, or in the corrector mode A + N + S
@@ -976,7 +978,7 @@ fsi_status fsi_set_jacobians(fsi_ctx* h, int level, const double* J) {
     launch_geometry(L, J, L.d_K64, L.d_cw64, L.d_K32, ctx->d_flag, ctx->stream);
     L.geo_set = false;
     L.coef_set = false;
-    L.vgeo_avail = L.vgeo = false;   // arbitrary per-point Jacobians: stored geometry only
+    L.vgeo_avail = L.vgeo = L.vgeo64 = false;   // arbitrary per-point Jacobians: stored geometry only
     TRY(sync_flag(ctx, FSI_ERR_INVERTED_CELL, "det J <= 0 (or not finite) at a quadrature point"));
     L.geo_set = true;
     L.conv_set = false;   // beta = K v° follows the geometry
@@ -996,11 +998,12 @@ fsi_status fsi_set_displacement(fsi_ctx* h, const double* disp) {
         for (int d = 0; d < L.dim; ++d) hh[d] = ctx->mesh.extent[d] / L.cells[d];
         launch_geometry_from_disp(L, disp, 1 << (J - j), F.pnodes, hh, L.d_K64, L.d_cw64, L.d_K32, ctx->d_flag,
                                     ctx->stream);
-        launch_vertex_disp32(L, disp, 1 << (J - j), F.pnodes, L.d_vd32, ctx->stream);
+        launch_vertex_disp(L, disp, 1 << (J - j), F.pnodes, L.d_vd32, L.d_vd64, ctx->stream);
         L.geo_set = false;
         L.coef_set = false;
         L.vgeo_avail = L.dim == 3;
-        L.vgeo = L.vgeo_avail && ctx->prm.vertex_geometry;
+        L.vgeo = L.vgeo_avail && (ctx->prm.vertex_geometry & 1);
+        L.vgeo64 = L.vgeo_avail && (ctx->prm.vertex_geometry & 2);
     }
     TRY(sync_flag(ctx, FSI_ERR_INVERTED_CELL, "det J <= 0 (or not finite) at a quadrature point"));
     for (int j = 0; j <= J; ++j) {
@@ -1018,7 +1021,7 @@ fsi_status fsi_set_coefficients(fsi_ctx* h, int level, const double* c_mass, con
     if (!L.geo_set) return fail(ctx, FSI_ERR_STATE, "set_coefficients before the level's geometry");
     invalidate(ctx);
     launch_fill<int>(ctx->d_flag, 0, 1, ctx->stream);
-    launch_coefficients(L, c_mass, eta, L.d_cw64, L.d_cv64, L.d_cv32, L.d_cq32, L.d_K64, L.d_Ks64, L.d_Ks32,
+    launch_coefficients(L, c_mass, eta, L.d_cw64, L.d_cv64, L.d_cv32, L.d_cq32, L.d_cq64, L.d_K64, L.d_Ks64, L.d_Ks32,
                         ctx->d_flag, ctx->stream);
     L.coef_set = false;
     TRY(sync_flag(ctx, FSI_ERR_NONFINITE, "coefficient not finite (or negative viscosity)"));
@@ -1031,14 +1034,18 @@ fsi_status fsi_set_mg_params(fsi_ctx* h, const fsi_mg_params* p) {
     Context* ctx = &h->c;
     if (p->k_A < 1 || p->m < 0 || p->n_cycles < 1 || p->k_S != 1 || p->n_S != 1 || !(p->cheb_upper > 0) ||
         !(p->cheb_ratio > 1) || p->n_eig < 1 || (p->precision != FSI_PREC_FP64 && p->precision != FSI_PREC_MIXED) ||
-        (p->corrector != 0 && p->corrector != 1) || (p->atomics != 0 && p->atomics != 1))
+        (p->corrector != 0 && p->corrector != 1) || (p->atomics != 0 && p->atomics != 1) ||
+        p->vertex_geometry < 0 || p->vertex_geometry > 3)
         return fail(ctx, FSI_ERR_ARG, "invalid multigrid parameters (only k_S = n_S = 1 are implemented)");
     const fsi_mg_params& o = ctx->prm;
     // precision and graph use select among already prepared paths; the rest changes the setup
     const bool same = o.k_A == p->k_A && o.m == p->m && o.n_cycles == p->n_cycles && o.cheb_upper == p->cheb_upper &&
                       o.cheb_ratio == p->cheb_ratio && o.n_eig == p->n_eig && o.corrector == p->corrector;
     ctx->prm = *p;
-    for (Level& L : ctx->lv) L.vgeo = L.vgeo_avail && p->vertex_geometry;
+    for (Level& L : ctx->lv) {
+        L.vgeo = L.vgeo_avail && (p->vertex_geometry & 1);
+        L.vgeo64 = L.vgeo_avail && (p->vertex_geometry & 2);
+    }
     if (!same) invalidate(ctx);
     return FSI_OK;
 }

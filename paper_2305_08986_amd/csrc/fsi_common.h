@@ -132,6 +132,9 @@ struct Level {
     // point (2 eta, c_m) in the geometry layout; valid after fsi_set_displacement
     float4* d_vd32 = nullptr;
     float* d_cq32 = nullptr;
+    // the same for the FP64 kernels: vertex displacement (x, y, z, 0) and (2 eta, c_m)
+    double4* d_vd64 = nullptr;
+    double* d_cq64 = nullptr;
     // corrector-mode terms per point in the geometry layout: beta = K v° (3 planes,
     // K = det(J) w J^{-1}) and sigma = r / (det J w) (1 plane); rho is the density
     double* d_cb64 = nullptr;
@@ -142,6 +145,7 @@ struct Level {
     double rho = 0.0;
     bool vgeo_avail = false;          // geometry came from vertex displacements (3D)
     bool vgeo = false;                // ... and the FP32 kernels use it
+    bool vgeo64 = false;              // ... and the FP64 kernels use it
     double h[3] = {1.0, 1.0, 1.0};    // reference cell sizes
     bool geo_set = false, coef_set = false;
 
@@ -309,11 +313,12 @@ void launch_geometry(const Level& L, const double* J, double* K, double* cw, flo
 void launch_geometry_from_disp(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
                                  const double* h, double* K, double* cw, float* K32, int* flag, hipStream_t s);
 void launch_coefficients(const Level& L, const double* cm, const double* eta, const double* cw,
-                         double* cv64, float* cv32, float* cq32, const double* K64, double* Ks64, float* Ks32,
-                         int* flag, hipStream_t s);
-// level vertex displacement (FP32 float4) from the fine-level displacement by injection
-void launch_vertex_disp32(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
-                          float4* out, hipStream_t s);
+                         double* cv64, float* cv32, float* cq32, double* cq64, const double* K64, double* Ks64,
+                         float* Ks32, int* flag, hipStream_t s);
+// level vertex displacement (FP32 float4 and FP64 double4) from the fine-level
+// displacement by injection
+void launch_vertex_disp(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes,
+                        float4* out32, double4* out64, hipStream_t s);
 // conv: add the corrector-mode terms of the level (fsi_set_convection)
 void launch_diagA(const Level& L, const double* K, const double* cv, double* diag, hipStream_t s, bool conv = false);
 void launch_diagA_finish(const Level& L, double* diag, double* dinv64, float* dinv32, hipStream_t s);

@@ -177,6 +177,7 @@ __global__ void k_coefficients(int dim, int64_t nc, int Q, GeoLayout geo, int64_
                                const int* __restrict__ lex2col, const double* __restrict__ cm,
                                const double* __restrict__ eta, const double* __restrict__ cw,
                                double* __restrict__ cv64, float* __restrict__ cv32, float* __restrict__ cq32,
+                               double* __restrict__ cq64,
                                const double* __restrict__ K64, double* __restrict__ Ks64, float* __restrict__ Ks32,
                                int* flag) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -195,6 +196,10 @@ __global__ void k_coefficients(int dim, int64_t nc, int Q, GeoLayout geo, int64_
     if (cq32) {
         cq32[off] = (float)(2.0 * e);
         cq32[plane + off] = (float)m;
+    }
+    if (cq64) {
+        cq64[off] = 2.0 * e;
+        cq64[plane + off] = m;
     }
     const double sv = sqrt(cvisc);
     for (int pl = 0; pl < dim * dim; ++pl) {
@@ -235,30 +240,33 @@ void launch_convection(const Level& L, const double* vconv, const double* r, dou
 }
 
 void launch_coefficients(const Level& L, const double* cm, const double* eta, const double* cw, double* cv64,
-                         float* cv32, float* cq32, const double* K64, double* Ks64, float* Ks32, int* flag,
-                         hipStream_t s) {
+                         float* cv32, float* cq32, double* cq64, const double* K64, double* Ks64, float* Ks32,
+                         int* flag, hipStream_t s) {
     hipLaunchKernelGGL(k_coefficients, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, L.dim, L.nc, L.Q, L.geo,
-                       L.plane(), L.d_lex2col, cm, eta, cw, cv64, cv32, cq32, K64, Ks64, Ks32, flag);
+                       L.plane(), L.d_lex2col, cm, eta, cw, cv64, cv32, cq32, cq64, K64, Ks64, Ks32, flag);
 }
 
 // level vertex v (lexicographic) takes the fine displacement at fine vertex stride * v
-__global__ void k_vertex_disp32(int dim, int pn0, int pn1, int pn2, int stride, int fp0, int fp1, int64_t nvert_fine,
-                                const double* __restrict__ disp, float4* __restrict__ out) {
+__global__ void k_vertex_disp(int dim, int pn0, int pn1, int pn2, int stride, int fp0, int fp1, int64_t nvert_fine,
+                              const double* __restrict__ disp, float4* __restrict__ out32,
+                              double4* __restrict__ out64) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nv = (int64_t)pn0 * pn1 * pn2;
     if (v >= nv) return;
     const int i = (int)(v % pn0), j = (int)((v / pn0) % pn1), k = (int)(v / ((int64_t)pn0 * pn1));
     const int64_t f = (int64_t)i * stride + (int64_t)fp0 * ((int64_t)j * stride + (int64_t)fp1 * ((int64_t)k * stride));
-    float c[3] = {0.f, 0.f, 0.f};
-    for (int d = 0; d < dim; ++d) c[d] = (float)disp[(int64_t)d * nvert_fine + f];
-    out[v] = make_float4(c[0], c[1], c[2], 0.f);
+    double c[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < dim; ++d) c[d] = disp[(int64_t)d * nvert_fine + f];
+    out32[v] = make_float4((float)c[0], (float)c[1], (float)c[2], 0.f);
+    out64[v] = make_double4(c[0], c[1], c[2], 0.0);
 }
-void launch_vertex_disp32(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes, float4* out,
-                          hipStream_t s) {
+void launch_vertex_disp(const Level& L, const double* disp_fine, int stride, const int* fine_pnodes, float4* out32,
+                        double4* out64, hipStream_t s) {
     int64_t nvf = 1;
     for (int d = 0; d < L.dim; ++d) nvf *= fine_pnodes[d];
-    hipLaunchKernelGGL(k_vertex_disp32, dim3(nblocks(L.np)), dim3(TPB), 0, s, L.dim, L.pnodes[0], L.pnodes[1],
-                       L.pnodes[2], stride, fine_pnodes[0], L.dim > 1 ? fine_pnodes[1] : 1, nvf, disp_fine, out);
+    hipLaunchKernelGGL(k_vertex_disp, dim3(nblocks(L.np)), dim3(TPB), 0, s, L.dim, L.pnodes[0], L.pnodes[1],
+                       L.pnodes[2], stride, fine_pnodes[0], L.dim > 1 ? fine_pnodes[1] : 1, nvf, disp_fine, out32,
+                       out64);
 }
 
 // ---------------------------------------------------------------- diag(A)

@@ -95,6 +95,7 @@ struct CellArgs {
     // multilinear ALE map, reference cell sizes, and per point (2 eta, c_m) in the
     // geometry layout (2 planes)
     const float4* __restrict__ vd;
+    const double4* __restrict__ vd64;
     const T* __restrict__ cq;
     T hx, hy, hz;
     // corrector-mode terms (OP_CONV): beta = K v° (3 planes) and sigma = r / (det J w)
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                   "the corrector terms go with A or the Stokes apply");
     static_assert(!CONV || !VG, "the corrector terms use the stored geometry");
     static_assert(!RES || MODE == (OP_A | OP_BT | OP_B | OP_RES), "the residual epilogue goes with the Stokes apply");
-    static_assert(!VG || sizeof(T) == 4, "geometry from vertices is the FP32 path");
+
     static_assert(ZG == 1 || ATOM, "row groups along z belong to the atomic form");
     // A alone reads K' = sqrt(cvisc) K (no cvisc plane): sym(grad-hat u K') K'^T = cvisc sym(H) K^T
     constexpr bool SCALED = !VG && ((MODE & ~OP_ATOM) == OP_A || MODE == (OP_A | OP_CHEB));
@@ -274,7 +275,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         if constexpr (PREF) fetch_idx(st + 1);
         // the first point's geometry (per-point path): issued before the forward sweeps,
         // whose work hides its latency
-        constexpr bool PERQX0 = sizeof(T) == 8 || (HAS_A && HAS_BT && !VG) || CONV;
+        constexpr bool PERQX0 = !VG && (sizeof(T) == 8 || (HAS_A && HAS_BT) || CONV);
+        // FP64 geometry from the vertices: the backward x-sweep accumulates in the
+        // transpose buffer (the registers go to the Jacobian data)
+        constexpr bool LACC = VG && sizeof(T) == 8 && BWD;
         T g0[11];
         if constexpr (PERQX0) {
             const int64_t off0 = chunk * kGeoSlots + (slot * NT + t);
@@ -304,9 +308,13 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         // reference cell sizes are folded in (L0 + L1 = 1); vertex v = i + 2j + 4k
         T vg0[3], vb0[3], vb1[3], vf0[3], vf1[3];
         if constexpr (VG) {
-            float4 dv[8];
+            using V4 = std::conditional_t<sizeof(T) == 8, double4, float4>;
+            const V4* vdp;
+            if constexpr (sizeof(T) == 8) vdp = a.vd64;
+            else vdp = a.vd;
+            V4 dv[8];
 #pragma unroll
-            for (int n = 0; n < 8; ++n) dv[n] = act ? a.vd[vert(n)] : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int n = 0; n < 8; ++n) dv[n] = act ? vdp[vert(n)] : V4{};
             const T ly0 = rL<T>(qy, 0), ly1 = rL<T>(qy, 1), lz0 = rL<T>(qz, 0), lz1 = rL<T>(qz, 1);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -417,7 +425,35 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             T Kq[9];
             const int64_t off = ((int64_t)qx * a.nchk + chunk) * kGeoSlots + (slot * NT + t);
             T cvq, cmq;
-            if (qx == 0) {
+            if constexpr (VG) {
+                // det(J) w J^{-1} = w adj(J) from the multilinear map (no division for K);
+                // J[r][a] = dx_r/dxi_a
+                const T lx0 = rL<T>(qx, 0), lx1 = rL<T>(qx, 1);
+                T Jm[9];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    Jm[r * 3 + 0] = vg0[r];
+                    Jm[r * 3 + 1] = lx0 * vb0[r] + lx1 * vb1[r];
+                    Jm[r * 3 + 2] = lx0 * vf0[r] + lx1 * vf1[r];
+                }
+                const T wq = rW<T>(qx) * rW<T>(qy) * rW<T>(qz);
+                const T c00 = Jm[4] * Jm[8] - Jm[5] * Jm[7];
+                const T c01 = Jm[5] * Jm[6] - Jm[3] * Jm[8];
+                const T c02 = Jm[3] * Jm[7] - Jm[4] * Jm[6];
+                const T det = Jm[0] * c00 + Jm[1] * c01 + Jm[2] * c02;
+                Kq[0] = wq * c00;
+                Kq[1] = wq * (Jm[2] * Jm[7] - Jm[1] * Jm[8]);
+                Kq[2] = wq * (Jm[1] * Jm[5] - Jm[2] * Jm[4]);
+                Kq[3] = wq * c01;
+                Kq[4] = wq * (Jm[0] * Jm[8] - Jm[2] * Jm[6]);
+                Kq[5] = wq * (Jm[2] * Jm[3] - Jm[0] * Jm[5]);
+                Kq[6] = wq * c02;
+                Kq[7] = wq * (Jm[1] * Jm[6] - Jm[0] * Jm[7]);
+                Kq[8] = wq * (Jm[0] * Jm[4] - Jm[1] * Jm[3]);
+                const T cw = det * wq;
+                cvq = (HAS_A && act) ? gload<NTL>(a.cq + off) / cw : T(0);       // 2 eta / (det J w)
+                cmq = (HAS_A && act) ? gload<NTL>(a.cq + a.plane + off) * cw : T(0);   // c_m det J w
+            } else if (qx == 0) {
 #pragma unroll
                 for (int e = 0; e < 9; ++e) Kq[e] = g0[e];
                 cvq = SCALED ? T(1) : ((HAS_A && act) ? g0[9] : T(0));
@@ -501,9 +537,26 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                     }
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        wa[c][i] += cS<T>(qx, i) * Fv[c] + cD<T>(qx, i) * F0;
-                        wb[c][i] += cS<T>(qx, i) * F1;
-                        wc[c][i] += cS<T>(qx, i) * F2;
+                        const T da = cS<T>(qx, i) * Fv[c] + cD<T>(qx, i) * F0;
+                        const T db = cS<T>(qx, i) * F1;
+                        const T dc = cS<T>(qx, i) * F2;
+                        if constexpr (LACC) {
+                            // the thread's own slots of the transpose buffer, which hold
+                            // the backward sweep's input in this layout afterwards (its
+                            // forward values were already read into registers)
+                            if (inwave) {
+                                T* pa = &B[((c * 3 + 0) * 9 + t) * 3 + i];
+                                T* pb = &B[((c * 3 + 1) * 9 + t) * 3 + i];
+                                T* pc = &B[((c * 3 + 2) * 9 + t) * 3 + i];
+                                *pa = (qx == 0 ? T(0) : *pa) + da;
+                                *pb = (qx == 0 ? T(0) : *pb) + db;
+                                *pc = (qx == 0 ? T(0) : *pc) + dc;
+                            }
+                        } else {
+                            wa[c][i] += da;
+                            wb[c][i] += db;
+                            wc[c][i] += dc;
+                        }
                     }
                 }
             }
@@ -687,7 +740,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         T ep[3][3], er[3][3], ex[3][3], ed[3][3], eg[3][3];
         if constexpr (BWD) {
             wave_sync();
-            if (inwave) {
+            if (inwave && !LACC) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -1189,8 +1242,8 @@ static void launch_one(const Level& L, const CellArgs<T>& args, hipStream_t s) {
         const int64_t grid = args.nrows;   // one workgroup per row (per z-group of rows)
         // the corrector terms use the stored geometry, also where the FP32 applies form it
         // from the vertices
-        if constexpr (sizeof(T) == 4 && (MODE & OP_CONV) == 0) {
-            if (args.vd) {
+        if constexpr ((MODE & OP_CONV) == 0) {
+            if (args.vd || args.vd64) {
                 // forming the geometry takes more registers: at most three wavefronts per SIMD
                 constexpr int WV = WPE > 3 ? 3 : WPE;
                 hipLaunchKernelGGL((cell3d<T, MODE, WPB, RS, NTL, WV, true, ZG>), dim3((unsigned)grid), dim3(64 * WPB),
@@ -1281,6 +1334,14 @@ static CellArgs<T> phase_args(const Level& L, int phase, const T* K, const T* cv
             args.hx = (T)L.h[0];
             args.hy = (T)L.h[1];
             args.hz = (T)L.h[2];
+        }
+    } else {
+        if (L.vgeo64 && L.dim == 3) {
+            args.vd64 = L.d_vd64;
+            args.cq = L.d_cq64;
+            args.hx = L.h[0];
+            args.hy = L.h[1];
+            args.hz = L.h[2];
         }
     }
     return args;

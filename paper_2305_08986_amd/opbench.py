@@ -27,6 +27,8 @@ def main(argv=None):
     ap.add_argument("--level", type=int, default=-1)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch variant")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--vertex-geometry", type=int, default=0,
+                    help="fsi_mg_params.vertex_geometry: bit 0 FP32 kernels, bit 1 FP64 kernels")
     a = ap.parse_args(argv)
 
     import torch
@@ -58,6 +60,8 @@ def main(argv=None):
     if MODES[a.mode] & 32:
         c = W.make_convection_inputs(a.workload, wl.mesh, lev, wl.eta[lev])
         ctx.set_convection(lev, c.vconv, c.r, c.rho)
+    if a.vertex_geometry:
+        ctx.set_mg_params(vertex_geometry=a.vertex_geometry)
     precs = [{"fp64": 0, "fp32": 1}[x] for x in a.prec.split(",")]
     variants = [int(v) for v in a.variant.split(",")] if a.variant else [None]
     if not a.no_autotune and variants == [None]:
@@ -69,6 +73,7 @@ def main(argv=None):
                 ctx.set_tuning(lev, p, var)
             k_us, op_us, nl = ctx.time_operator(lev, precision=p, mode=MODES[a.mode], reps=a.reps)
             out.update(dict(workload=a.workload, level=lev, mode=a.mode, prec=["fp64", "fp32"][p], reps=a.reps,
+                            vertex_geometry=a.vertex_geometry,
                             variant=ctx.tuning(lev, p)[0], n_cells=s["n_cells"], n_vel=s["n_vel"],
                             kernel_us=k_us, launches=nl, mean_launch_us=k_us / nl, operator_us=op_us,
                             gdofs=s["n_vel"] / (op_us * 1e-6) / 1e9))

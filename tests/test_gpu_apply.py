@@ -78,9 +78,15 @@ def _cmp(got, ref, tol, what, bound=None, unit=U64):
     assert err <= tol, (what, err)
 
 
+@pytest.mark.parametrize("vertex_geometry", [0, 2])
 @pytest.mark.parametrize("name", ["C0", "T2_R", "T3_4", "T3_R", "T3_8", "C1", "T3_16"])
-def test_fp64_operators_match_oracle(name):
+def test_fp64_operators_match_oracle(name, vertex_geometry):
+    """FP64 applies with stored geometry and (3D, vertex_geometry = 2) with det(J) w J^-1
+    formed at every point from the vertex displacements inside the kernel."""
     wl, ctx, ops, aops = _ctx_and_ops(name)
+    if vertex_geometry and wl.mesh.dim == 2:
+        pytest.skip("geometry from the vertices is built for 3D levels")
+    ctx.set_mg_params(vertex_geometry=vertex_geometry)
     rng = np.random.default_rng([7, len(name)])
     for j in sorted({0, ctx.n_levels - 1, ctx.n_levels // 2}):
         op = ops[j]
@@ -96,6 +102,7 @@ def test_fp64_operators_match_oracle(name):
         rv, rq = op.apply_stokes(u, p)
         _cmp(v, rv, 1e-12, f"{name} L{j} stokes-v", bd["v"])
         _cmp(q, rq, 1e-12, f"{name} L{j} stokes-q", bd["q"])
+    ctx.set_mg_params(vertex_geometry=0)
 
 
 @pytest.mark.parametrize("vertex_geometry", [0, 1])
@@ -268,14 +275,18 @@ def test_atomic_single_launch_matches_oracle(name):
                 ra, rb, rbt = op.apply_A(u), op.apply_B(u), op.apply_BT(p)
                 rv, rq = op.apply_stokes(u, p)
                 bd = bounds(aops[j], u, p)
-                a = ctx.apply_A(j, ut)
-                assert np.array_equal(a.cpu().numpy()[op.dir_mask], u[op.dir_mask])
-                _cmp(a, ra, 1e-12, f"{name} var{var} L{j} A", bd["A"])
-                _cmp(ctx.apply_B(j, ut), rb, 1e-12, f"{name} var{var} L{j} B", bd["B"])
-                _cmp(ctx.apply_BT(j, pt), rbt, 1e-12, f"{name} var{var} L{j} BT", bd["BT"])
-                v, q = ctx.apply_stokes(j, ut, pt)
-                _cmp(v, rv, 1e-12, f"{name} var{var} L{j} stokes-v", bd["v"])
-                _cmp(q, rq, 1e-12, f"{name} var{var} L{j} stokes-q", bd["q"])
+                # FP64 with stored geometry and with the geometry formed from the vertices
+                for vg in (0, 2):
+                    ctx.set_mg_params(tuned=1, vertex_geometry=vg)
+                    tag = f"{name} var{var} L{j} vg{vg}"
+                    a = ctx.apply_A(j, ut)
+                    assert np.array_equal(a.cpu().numpy()[op.dir_mask], u[op.dir_mask])
+                    _cmp(a, ra, 1e-12, f"{tag} A", bd["A"])
+                    _cmp(ctx.apply_B(j, ut), rb, 1e-12, f"{tag} B", bd["B"])
+                    _cmp(ctx.apply_BT(j, pt), rbt, 1e-12, f"{tag} BT", bd["BT"])
+                    v, q = ctx.apply_stokes(j, ut, pt)
+                    _cmp(v, rv, 1e-12, f"{tag} stokes-v", bd["v"])
+                    _cmp(q, rq, 1e-12, f"{tag} stokes-q", bd["q"])
                 # FP32 with stored geometry and with the geometry formed from the vertices
                 for vg in (0, 1):
                     ctx.set_mg_params(tuned=1, vertex_geometry=vg)
