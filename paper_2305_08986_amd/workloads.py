@@ -128,10 +128,19 @@ CONFIGS = {
                  eta="loguniform", block=3, desc="2D 22x14 warped, odd coarse counts"),
     "T4_S": dict(dim=3, n=(16, 16, 16), extent=(1.0, 1.0, 1.0), n_coarse=(4, 4, 4), amp=0.0025,
                  eta="loguniform", block=4, steps=3, desc="3D 16^3 step sequence (C4 law, small)"),
+    # the C0 law refined (the inclusion stays aligned with the 4x4 coarse grid): robustness
+    # of the iteration count with the number of levels
+    "C0_32": dict(dim=2, n=(32, 32), extent=(1.0, 1.0), n_coarse=(4, 4), amp=0.0,
+                  eta="inclusion", desc="2D unit square 32x32 affine, inclusion contrast 1e4"),
+    "C0_64": dict(dim=2, n=(64, 64), extent=(1.0, 1.0), n_coarse=(4, 4), amp=0.0,
+                  eta="inclusion", desc="2D unit square 64x64 affine, inclusion contrast 1e4"),
+    "C0_128": dict(dim=2, n=(128, 128), extent=(1.0, 1.0), n_coarse=(4, 4), amp=0.0,
+                   eta="inclusion", desc="2D unit square 128x128 affine, inclusion contrast 1e4"),
 }
 
 CONFIG_INDEX = {"C0": 0, "C1": 1, "C2": 2, "C3": 3, "C4": 4,
-                "T3_4": 100, "T3_8": 101, "T3_16": 102, "T3_R": 103, "T2_R": 104, "T4_S": 105}
+                "T3_4": 100, "T3_8": 101, "T3_16": 102, "T3_R": 103, "T2_R": 104, "T4_S": 105,
+                "C0_32": 10, "C0_64": 11, "C0_128": 12}
 
 
 # ---------------------------------------------------------------- geometry of the grids
@@ -203,19 +212,21 @@ def _sine_displacement(X: np.ndarray, extent, amp: float, modes) -> np.ndarray:
     return amp * b[None, :] * 0.25 * out
 
 
-def _eta_law(cfg: dict, mesh: MeshDesc, rng: np.random.Generator, level_coords):
+def _eta_law(cfg: dict, mesh: MeshDesc, rng: np.random.Generator, level_coords, contrast: Optional[float] = None):
     kind = cfg["eta"]
     if kind == "inclusion":
+        c = 1e4 if contrast is None else contrast
         out = []
         for X in level_coords:
             inside = np.all((X >= 0.25) & (X <= 0.5), axis=-1)
-            out.append(np.where(inside, 1e4, 1.0))
+            out.append(np.where(inside, c, 1.0))
         return out, None
     if kind == "strip":
+        c = 1e6 if contrast is None else contrast
         out = []
         for X in level_coords:
             inside = (X[..., 0] >= 0.6) & (X[..., 0] <= 1.0) & (X[..., 1] >= 0.19) & (X[..., 1] <= 0.21)
-            out.append(np.where(inside, 1e3, 1e-3))
+            out.append(np.where(inside, 1e-3 * c, 1e-3))
         return out, None
     if kind == "loguniform":
         blk = cfg.get("block", 8)
@@ -243,7 +254,8 @@ def make_mesh(name: str, dirichlet_faces: Optional[int] = None) -> MeshDesc:
 def make_workload(name: str, step: Optional[int] = None, seed: int = BASE_SEED,
                   dirichlet_faces: Optional[int] = None,
                   prev_disp: Optional[np.ndarray] = None,
-                  levels: Optional[Sequence[int]] = None) -> Workload:
+                  levels: Optional[Sequence[int]] = None,
+                  contrast: Optional[float] = None) -> Workload:
     """Draw the inputs of workload ``name``.
 
     Draw order (numpy PCG64 seeded with ``[seed, config]`` or
@@ -252,6 +264,8 @@ def make_workload(name: str, step: Optional[int] = None, seed: int = BASE_SEED,
     then zeroed.  For the time-step sequence the displacement of ``step`` is
     ``prev_disp`` plus a fresh increment.
     ``levels`` restricts which levels get coefficient arrays (all by default).
+    ``contrast`` replaces the viscosity ratio of the inclusion (default 1e4) or the
+    strip (default 1e6) laws.
     """
     cfg = CONFIGS[name]
     mesh = make_mesh(name, dirichlet_faces)
@@ -269,7 +283,7 @@ def make_workload(name: str, step: Optional[int] = None, seed: int = BASE_SEED,
         disp = disp + prev_disp
     lvls = list(range(J + 1)) if levels is None else list(levels)
     coords = [qpoint_ref_coords(mesh, l) for l in lvls]
-    eta_l, logeta = _eta_law(cfg, mesh, rng, coords)
+    eta_l, logeta = _eta_law(cfg, mesh, rng, coords, contrast)
     eta = [None] * (J + 1)
     cm = [None] * (J + 1)
     for l, e in zip(lvls, eta_l):

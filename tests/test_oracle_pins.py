@@ -855,3 +855,26 @@ def test_absolute_scales_dominate_and_match_signed_diagonals():
     J1 = fem.jacobians_q1(box1, np.zeros((3, box1.n_p)), ref)
     Aa1, _ = fem.element_matrices_abs(J1, np.full((1, 27), 2.0), np.full((1, 27), 0.9), ref)
     assert np.allclose(np.diag(Aa1[0]), np.diag(A1), rtol=1e-14, atol=0)
+
+
+@pytest.mark.slow
+def test_oracle_iterations_bounded_with_levels_and_contrast():
+    """The preconditioner of Sec. 4 with the interface aligned to the coarse grid: the
+    oracle's FGMRES iteration count stays bounded as levels are added (C0 law, 16^2 to
+    64^2) and as the inclusion contrast grows from 1 to 1e4."""
+    its = []
+    for name in ("C0", "C0_32", "C0_64"):
+        wl = W.make_workload(name)
+        h = solvers.Hierarchy(solvers.build_levels(wl.mesh, wl.disp, wl.c_mass, wl.eta))
+        res = solvers.solve_stokes(h, wl.g_u, wl.g_p, rtol=1e-8, max_iter=100)
+        assert res.converged
+        its.append(res.iters)
+    assert max(its) <= 1.5 * min(its), its
+    byc = []
+    for c in (1.0, 1e2, 1e4):
+        wl = W.make_workload("C0_32", contrast=c)
+        h = solvers.Hierarchy(solvers.build_levels(wl.mesh, wl.disp, wl.c_mass, wl.eta))
+        res = solvers.solve_stokes(h, wl.g_u, wl.g_p, rtol=1e-8, max_iter=100)
+        assert res.converged
+        byc.append(res.iters)
+    assert max(byc) <= 3 * byc[0], byc
