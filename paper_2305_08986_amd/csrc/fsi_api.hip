@@ -46,6 +46,17 @@ static fsi_status dalloc(Context* ctx, T** p, int64_t n) {
     return FSI_OK;
 }
 
+// release a buffer from dalloc (null is ignored); the caller makes sure no queued work
+// still uses it
+template <typename T>
+static void dfree(Context* ctx, T** p) {
+    if (!*p) return;
+    auto& a = ctx->allocations;
+    a.erase(std::remove(a.begin(), a.end(), (void*)*p), a.end());
+    hipFree((void*)*p);
+    *p = nullptr;
+}
+
 #define TRY(expr)                          \
     do {                                   \
         fsi_status st_ = (expr);           \
@@ -395,12 +406,17 @@ static void smoother(Context* ctx, int j, const T* r_u, const double* r_p, T* x_
     launch_smoother_update<T>(W.w_u, W.v_u, W.z_p, W.dots, x_u, x_p, L.nv, L.np, first, s);
 }
 
+// the residual of level j in precision pi is formed in the cell kernel's last-touch epilogue
+static bool res_epilogue(const Context* ctx, int pi, int j) {
+    return ctx->prm.fused && !ctx->prm.corrector && (!ctx->prm.tuned || ctx->fuse_res[pi][j]);
+}
+
 // r = f - M x on level j (into W.r_u, W.r_p)
 template <typename T>
 static void residual(Context* ctx, int j, hipStream_t s) {
     const Level& L = ctx->lv[j];
     LevelWork<T>& W = works<T>(ctx)[j];
-    if (ctx->prm.fused && !ctx->prm.corrector && (!ctx->prm.tuned || ctx->fuse_res[prec_index<T>()][j])) {
+    if (res_epilogue(ctx, prec_index<T>(), j)) {
         launch_cell_res_all<T>(L, variant_of(ctx, prec_index<T>(), j, OP_A | OP_BT | OP_B | OP_RES), Kp<T>(L),
                                CVp<T>(L), W.x_u, W.x_p, W.f_u,
                                W.f_p, W.r_u, W.r_p, s);
@@ -433,12 +449,18 @@ static void vcycle_level(Context* ctx, int j, hipStream_t s) {
         launch_fill<T>(W.x_u, T(0), ctx->lv[j].nv, s);
         launch_fill<double>(W.x_p, 0.0, ctx->lv[j].np, s);
     }
-    residual<T>(ctx, j, s);
     LevelWork<T>& C = works<T>(ctx)[j - 1];
     // FP64 transfer scratch: the level's FP64 smoother work vectors, free here in
     // either precision (one V-cycle runs at a time on the context's stream)
     LevelWork<double>& S = ctx->w64[j];
-    launch_restrict<T>(ctx->lv[j], ctx->lv[j - 1], W.r_u, W.r_p, C.f_u, C.f_p, S.w_u, S.v_u, s);
+    if (ctx->prm.fused && !res_epilogue(ctx, prec_index<T>(), j)) {
+        // residual fused into the restriction: M x into W.r, the first pass restricts f - M x
+        op_apply<T>(ctx, j, solver_mode(ctx, OP_A | OP_BT | OP_B), W.x_u, W.x_p, W.r_u, W.r_p, s);
+        launch_restrict<T>(ctx->lv[j], ctx->lv[j - 1], W.f_u, W.f_p, C.f_u, C.f_p, S.w_u, S.v_u, s, W.r_u, W.r_p);
+    } else {
+        residual<T>(ctx, j, s);
+        launch_restrict<T>(ctx->lv[j], ctx->lv[j - 1], W.r_u, W.r_p, C.f_u, C.f_p, S.w_u, S.v_u, s);
+    }
     vcycle_level<T>(ctx, j - 1, s);
     launch_prolongate_add<T>(ctx->lv[j], ctx->lv[j - 1], C.x_u, C.x_p, W.x_u, W.x_p, S.w_u, S.v_u, s);
     for (int st = 0; st < m; ++st) {
@@ -661,9 +683,18 @@ static fsi_status ensure_krylov(Context* ctx, int restart) {
     const Level& L = ctx->lv[ctx->nlev - 1];
     const int64_t n = L.nv + L.np;
     if (K.restart >= restart && K.n == n) return FSI_OK;
-    // previous buffers stay in ctx->allocations until destroy
-    K.restart = restart;
-    K.n = n;
+    // superseded buffers are released (no queued work uses them: every solve synchronises)
+    FSI_HIP_TRY(hipStreamSynchronize(ctx->stream));
+    dfree(ctx, &K.V);
+    dfree(ctx, &K.Z);
+    dfree(ctx, &K.w);
+    dfree(ctx, &K.r);
+    dfree(ctx, &K.x);
+    dfree(ctx, &K.g);
+    dfree(ctx, &K.h);
+    dfree(ctx, &K.partials);
+    K.restart = 0;
+    K.n = 0;
     TRY(dalloc(ctx, &K.V, (int64_t)(restart + 1) * n));
     TRY(dalloc(ctx, &K.Z, (int64_t)restart * n));
     TRY(dalloc(ctx, &K.w, n));
@@ -674,7 +705,10 @@ static fsi_status ensure_krylov(Context* ctx, int restart) {
     TRY(dalloc(ctx, &K.partials, std::max<int64_t>(std::max<int64_t>(1024 * (int64_t)(restart + 2), 4096),
                                                    2 * kReduceBlocks)));
     if (K.h_host) hipHostFree(K.h_host);
+    K.h_host = nullptr;
     FSI_HIP_TRY(hipHostMalloc((void**)&K.h_host, sizeof(double) * 3 * (restart + 2)));
+    K.restart = restart;
+    K.n = n;
     return FSI_OK;
 }
 
@@ -763,10 +797,16 @@ static void ext_vcycle_level(Context* ctx, int j, hipStream_t s) {
         return;
     }
     cheb<T>(ctx, j, W.f_u, W.x_u, s);          // pre-smoothing from zero
-    ext_residual<T>(ctx, j, s);
     LevelWork<T>& C = works<T>(ctx)[j - 1];
     LevelWork<double>& S = ctx->w64[j];         // FP64 transfer scratch, free here
-    launch_restrict<T>(L, ctx->lv[j - 1], W.r_u, nullptr, C.f_u, nullptr, S.w_u, S.v_u, s);
+    if (ctx->prm.fused) {
+        // residual fused into the restriction: A x into W.tu, the first pass restricts f - A x
+        op_apply<T>(ctx, j, OP_A, W.x_u, nullptr, W.tu, nullptr, s);
+        launch_restrict<T>(L, ctx->lv[j - 1], W.f_u, nullptr, C.f_u, nullptr, S.w_u, S.v_u, s, W.tu, nullptr);
+    } else {
+        ext_residual<T>(ctx, j, s);
+        launch_restrict<T>(L, ctx->lv[j - 1], W.r_u, nullptr, C.f_u, nullptr, S.w_u, S.v_u, s);
+    }
     ext_vcycle_level<T>(ctx, j - 1, s);
     launch_prolongate_add<T>(L, ctx->lv[j - 1], C.x_u, nullptr, W.x_u, nullptr, S.w_u, S.v_u, s);
     ext_residual<T>(ctx, j, s);                 // post-smoothing

@@ -377,9 +377,12 @@ void launch_bicg_mid(const double* dsinv, const double* dots, const double* v, d
 template <typename T>
 void launch_bicg_update(const T* w, const T* t1, const T* t2, const double* p, const double* q, const double* dots,
                         T* x_u, double* x_p, int64_t nu, int64_t np, bool first, hipStream_t s);
+// rb_u, rb_p (may be null): restrict rf - rb instead of rf (the residual f - M x from f
+// and M x, no separate subtraction)
 template <typename T>
 void launch_restrict(const Level& fine, const Level& coarse, const T* rf_u, const double* rf_p,
-                     T* rc_u, double* rc_p, double* s1, double* s2, hipStream_t s);
+                     T* rc_u, double* rc_p, double* s1, double* s2, hipStream_t s, const T* rb_u = nullptr,
+                     const double* rb_p = nullptr);
 template <typename T>
 void launch_prolongate_add(const Level& fine, const Level& coarse, const T* ec_u, const double* ec_p,
                            T* xf_u, double* xf_p, double* s1, double* s2, hipStream_t s);

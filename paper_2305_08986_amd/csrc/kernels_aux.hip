@@ -926,7 +926,9 @@ struct XferDims {
     int64_t fnv, cnv, fnp, cnp;
 };
 
-__global__ void k_restrict_p(XferDims x, const double* __restrict__ rf, double* __restrict__ rc) {
+// rb (may be null): restrict rf - rb (the residual f - M x from f and M x)
+__global__ void k_restrict_p(XferDims x, const double* __restrict__ rf, const double* __restrict__ rb,
+                             double* __restrict__ rc) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= x.cnp) return;
     int c[3] = {0, 0, 0};
@@ -943,7 +945,7 @@ __global__ void k_restrict_p(XferDims x, const double* __restrict__ rf, double* 
         for (int j = 0; j < m[1]; ++j)
             for (int i = 0; i < m[0]; ++i) {
                 const int64_t fn = fi[0][i] + (int64_t)x.fp[0] * (fi[1][j] + (int64_t)x.fp[1] * fi[2][k]);
-                acc += wi[0][i] * wi[1][j] * wi[2][k] * rf[fn];
+                acc += wi[0][i] * wi[1][j] * wi[2][k] * (rb ? rf[fn] - rb[fn] : rf[fn]);
             }
     rc[id] = acc;
 }
@@ -955,28 +957,34 @@ __global__ void k_restrict_p(XferDims x, const double* __restrict__ rf, double* 
 // the coarse wall rows); prolongation expands z, then y, then x (the last pass adds
 // into the fine vector, skipping its wall rows).  Sums are formed in FP64 and the
 // intermediate tensors are FP64, so an FP32 transfer rounds once, at its output.
-template <typename Tin, typename Tout>
-__global__ void k_restrict_axis(const Tin* __restrict__ in, Tout* __restrict__ out, int64_t outer, int nf, int nc,
-                                int64_t inner, const uint8_t* __restrict__ cwall, int64_t cnv) {
+// SUB: the pass restricts in - inb (the first pass of the residual restriction, which
+// then needs no separate subtraction kernel); the difference is formed in FP64
+template <typename Tin, typename Tout, bool SUB>
+__global__ void k_restrict_axis(const Tin* __restrict__ in, const Tin* __restrict__ inb, Tout* __restrict__ out,
+                                int64_t outer, int nf, int nc, int64_t inner, const uint8_t* __restrict__ cwall,
+                                int64_t cnv) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= outer * nc * inner) return;
     const int64_t b = id % inner, r = id / inner;
     const int c = (int)(r % nc);
     const int64_t a = r / nc;
     const Tin* src = in + a * nf * inner + b;
+    const Tin* srb = SUB ? inb + a * nf * inner + b : nullptr;
+    auto val = [&](int f) {
+        return SUB ? double(src[(int64_t)f * inner]) - double(srb[(int64_t)f * inner]) : double(src[(int64_t)f * inner]);
+    };
     const int e = c >> 1;
     double acc;
     if ((c & 1) == 0) {
         const int f0 = 4 * e;
-        acc = double(src[(int64_t)f0 * inner]);
-        if (f0 - 1 >= 0) acc += 0.375 * double(src[(int64_t)(f0 - 1) * inner]);
-        if (f0 + 1 < nf) acc += 0.375 * double(src[(int64_t)(f0 + 1) * inner]);
-        if (f0 - 3 >= 0) acc -= 0.125 * double(src[(int64_t)(f0 - 3) * inner]);
-        if (f0 + 3 < nf) acc -= 0.125 * double(src[(int64_t)(f0 + 3) * inner]);
+        acc = val(f0);
+        if (f0 - 1 >= 0) acc += 0.375 * val(f0 - 1);
+        if (f0 + 1 < nf) acc += 0.375 * val(f0 + 1);
+        if (f0 - 3 >= 0) acc -= 0.125 * val(f0 - 3);
+        if (f0 + 3 < nf) acc -= 0.125 * val(f0 + 3);
     } else {
         const int f1 = 4 * e + 1;
-        acc = 0.75 * (double(src[(int64_t)f1 * inner]) + double(src[(int64_t)(f1 + 2) * inner])) +
-              double(src[(int64_t)(f1 + 1) * inner]);
+        acc = 0.75 * (val(f1) + val(f1 + 2)) + val(f1 + 1);
     }
     if (cwall && cwall[id % cnv]) acc = 0.0;
     out[id] = Tout(acc);
@@ -1061,10 +1069,15 @@ AxisPass axis_pass(const int64_t ext[3], int d, int D, int nout) {
     return p;
 }
 template <typename Tin, typename Tout>
-void restrict_pass(const Tin* in, Tout* out, const AxisPass& p, const uint8_t* cwall, int64_t cnv, hipStream_t s) {
+void restrict_pass(const Tin* in, Tout* out, const AxisPass& p, const uint8_t* cwall, int64_t cnv, hipStream_t s,
+                   const Tin* inb = nullptr) {
     const int64_t n = p.outer * p.nout * p.inner;
-    hipLaunchKernelGGL((k_restrict_axis<Tin, Tout>), dim3(nblocks(n)), dim3(TPB), 0, s, in, out, p.outer, p.nin, p.nout,
-                       p.inner, cwall, cnv);
+    if (inb)
+        hipLaunchKernelGGL((k_restrict_axis<Tin, Tout, true>), dim3(nblocks(n)), dim3(TPB), 0, s, in, inb, out,
+                           p.outer, p.nin, p.nout, p.inner, cwall, cnv);
+    else
+        hipLaunchKernelGGL((k_restrict_axis<Tin, Tout, false>), dim3(nblocks(n)), dim3(TPB), 0, s, in, inb, out,
+                           p.outer, p.nin, p.nout, p.inner, cwall, cnv);
 }
 template <typename Tin, typename Tout>
 void prolong_pass(const Tin* in, Tout* out, const AxisPass& p, int ncells, const uint8_t* fwall, int64_t fnv,
@@ -1077,14 +1090,14 @@ void prolong_pass(const Tin* in, Tout* out, const AxisPass& p, int ncells, const
 
 template <typename T>
 void launch_restrict(const Level& fine, const Level& coarse, const T* rf_u, const double* rf_p, T* rc_u, double* rc_p,
-                     double* s1, double* s2, hipStream_t s) {
+                     double* s1, double* s2, hipStream_t s, const T* rb_u, const double* rb_p) {
     const XferDims x = xdims(fine, coarse);
     const int D = x.dim;
     // extents of the tensor [comp][z][y][x] as the passes shrink it
     int64_t ext[3] = {x.fv[0], x.fv[1], D == 3 ? x.fv[2] : 1};
     const uint8_t* cw = level_wall_mask(coarse);
     AxisPass p = axis_pass(ext, 0, D, x.cv[0]);
-    restrict_pass<T, double>(rf_u, s1, p, nullptr, x.cnv, s);
+    restrict_pass<T, double>(rf_u, s1, p, nullptr, x.cnv, s, rb_u);
     ext[0] = x.cv[0];
     p = axis_pass(ext, 1, D, x.cv[1]);
     if (D == 2) {
@@ -1095,7 +1108,7 @@ void launch_restrict(const Level& fine, const Level& coarse, const T* rf_u, cons
         p = axis_pass(ext, 2, D, x.cv[2]);
         restrict_pass<double, T>(s2, rc_u, p, cw, x.cnv, s);
     }
-    if (rf_p) hipLaunchKernelGGL(k_restrict_p, dim3(nblocks(x.cnp)), dim3(TPB), 0, s, x, rf_p, rc_p);
+    if (rf_p) hipLaunchKernelGGL(k_restrict_p, dim3(nblocks(x.cnp)), dim3(TPB), 0, s, x, rf_p, rb_p, rc_p);
 }
 template <typename T>
 void launch_prolongate_add(const Level& fine, const Level& coarse, const T* ec_u, const double* ec_p, T* xf_u,
@@ -1123,9 +1136,9 @@ void launch_prolongate_add(const Level& fine, const Level& coarse, const T* ec_u
     if (ec_p) hipLaunchKernelGGL(k_prolong_p, dim3(nblocks(x.fnp)), dim3(TPB), 0, s, x, ec_p, xf_p);
 }
 template void launch_restrict<double>(const Level&, const Level&, const double*, const double*, double*, double*,
-                                      double*, double*, hipStream_t);
+                                      double*, double*, hipStream_t, const double*, const double*);
 template void launch_restrict<float>(const Level&, const Level&, const float*, const double*, float*, double*,
-                                     double*, double*, hipStream_t);
+                                     double*, double*, hipStream_t, const float*, const double*);
 template void launch_prolongate_add<double>(const Level&, const Level&, const double*, const double*, double*,
                                             double*, double*, double*, hipStream_t);
 template void launch_prolongate_add<float>(const Level&, const Level&, const float*, const double*, float*, double*,
