@@ -401,19 +401,23 @@ def fgmres(apply_M: Callable, precond: Callable, g: np.ndarray, x0: Optional[np.
 
 
 # ---------------------------------------------------------------- extension (Sec. 2)
-def extension_solve(box: fem.Box, J: np.ndarray, mu: np.ndarray, ref: fem.Reference, g: np.ndarray):
+def extension_solve(box: fem.Box, J: np.ndarray, mu: np.ndarray, ref: fem.Reference, g: np.ndarray,
+                    fixed: Optional[np.ndarray] = None):
     """Ext of Sec. 2: the displacement u with u = g on the Dirichlet dofs of ``box`` and
     (mu eps(u), eps(v)) = 0 for every v that vanishes there.
 
     The bilinear form is the operator's a(u, v) = (c_m u, v) + (2 eta eps(u), eps(v)) with
     c_m = 0 and eta = mu / 2.  Interior dofs I, Dirichlet dofs W of the unconstrained
     matrix: A_II u_I = -A_IW g_W, solved by SuperLU.  Reading: the Dirichlet set is the box
-    walls (the paper's fixed outer boundary, with data allowed to be nonzero); the
-    interface with the solid would be a further Dirichlet set of the same kind.
+    walls (the paper's fixed outer boundary, with data allowed to be nonzero) and, where
+    ``fixed`` (a mask over the velocity vector) is given, those dofs too: the nodes of
+    the solid, where the extension takes the solid's values.
     """
     zero = np.zeros_like(mu)
     A = fem.assemble_unconstrained(box, J, zero, 0.5 * mu, ref).A.tocsr()
     dm = box.dirichlet_vel_dofs()
+    if fixed is not None:
+        dm = dm | fixed
     I = np.nonzero(~dm)[0]
     W = np.nonzero(dm)[0]
     u = np.where(dm, g, 0.0)

@@ -419,3 +419,97 @@ def inject_displacement(mesh: MeshDesc, disp_fine: np.ndarray, level: int) -> np
 def random_vector(n: int, seed_key) -> np.ndarray:
     """A seeded U[-1,1] test vector (for parity tests)."""
     return np.random.default_rng(seed_key).uniform(-1.0, 1.0, size=n)
+
+
+# ---------------------------------------------------------------- time-step (GCSI) inputs
+# One step of the GCSI_2(P, C) scheme (Algorithm 1) on a channel with an elastic strip:
+# the box [0, 2] x [0, 0.5] x [0, 0.5] (no-slip walls, x+ a do-nothing outflow) with a
+# solid strip [0.5, 1.25] x [0.125, 0.25] spanning the channel depth (clamped by the
+# z walls), cell-aligned on every level.  Material constants follow the FSI2-type
+# setting of Sec. 5 (rho_f = 1e3, eta_f = 1, rho_s = 1e4, mu_s = 5e5, gravity 2 in -y,
+# tau = 0.005, the volume-correction parameter 0.1); the extension coefficient is the law
+# of Sec. 5 centred at the strip's tip.  The history (u, v, w at the two previous steps,
+# the last pressure) is a set of smooth seeded fields vanishing on every face: four
+# sine modes per field (as the displacement law), amplitude 0.005 for displacements and
+# 0.5 for velocities; w takes the values of v on every node of a solid cell (the mesh
+# moves with the solid).
+GCSI_STREAM = 11
+GCSI_CONFIGS = {
+    "G1": dict(n=(16, 4, 4), n_coarse=(4, 1, 1)),
+    "G2": dict(n=(128, 32, 32), n_coarse=(4, 1, 1)),
+    "G3": dict(n=(256, 64, 64), n_coarse=(4, 1, 1)),
+}
+GCSI_EXTENT = (2.0, 0.5, 0.5)
+GCSI_STRIP = ((0.5, 1.25), (0.125, 0.25), (0.0, 0.5))
+GCSI_CONFIG_INDEX = {"G1": 20, "G2": 21, "G3": 22}
+GCSI_MATERIAL = dict(k=2, tau=0.005, rho_f=1e3, rho_s=1e4, eta_f=1.0, mu_s=5e5, eta_V=0.1,
+                     body=(0.0, -2.0, 0.0))
+
+
+@dataclasses.dataclass
+class GcsiInputs:
+    mesh: MeshDesc               # channel (walls, x+ outflow)
+    ext_mesh: MeshDesc           # the same box with every face fixed (extension)
+    solid_q: list                # per level [n_cells][Q] uint8: point inside the strip
+    solid_cells: np.ndarray      # finest level [n_cells] uint8: cell inside the strip
+    mu_A: list                   # per level [n_cells][Q]
+    material: dict
+    u: list                      # [u^{n-1}, u^{n-2}], each [n_vel] component-major
+    v: list
+    w: list
+    p: np.ndarray                # [n_p]
+
+
+def _inside_strip(X: np.ndarray) -> np.ndarray:
+    m = np.ones(X.shape[:-1], dtype=bool)
+    for d, (lo, hi) in enumerate(GCSI_STRIP):
+        m &= (X[..., d] >= lo) & (X[..., d] <= hi)
+    return m
+
+
+def make_gcsi_inputs(name: str = "G1", seed: int = BASE_SEED) -> GcsiInputs:
+    """Draw the inputs of one GCSI step on the channel-with-strip ``name``.
+
+    Draw order (PCG64 ``[seed, config, GCSI_STREAM]``): sine modes of u^{n-1}, u^{n-2},
+    v^{n-1}, v^{n-2}, w^{n-1}, w^{n-2}, then p (U[-1, 1]) at the pressure nodes."""
+    cfg = GCSI_CONFIGS[name]
+    mesh = MeshDesc(dim=3, n_fine=tuple(cfg["n"]), extent=GCSI_EXTENT, n_coarse=tuple(cfg["n_coarse"]),
+                    dirichlet_faces=default_dirichlet_faces(3))
+    ext_mesh = dataclasses.replace(mesh, dirichlet_faces=63)
+    J = mesh.n_levels - 1
+    rng = np.random.default_rng([seed, GCSI_CONFIG_INDEX[name], GCSI_STREAM])
+    X = velocity_node_coords(mesh, J)
+
+    def field(amp):
+        return np.ascontiguousarray(_sine_displacement(X, mesh.extent, amp, _sine_modes(rng, 3)).ravel())
+
+    u = [field(0.005), field(0.005)]
+    v = [field(0.5), field(0.5)]
+    w = [field(0.5), field(0.5)]
+    p = rng.uniform(-1.0, 1.0, size=mesh.n_p(J))
+    solid_q, mu_A = [], []
+    tip = (GCSI_STRIP[0][1], 0.5 * (GCSI_STRIP[1][0] + GCSI_STRIP[1][1]))
+    for l in range(J + 1):
+        Xq = qpoint_ref_coords(mesh, l)
+        solid_q.append(np.ascontiguousarray(_inside_strip(Xq).astype(np.uint8)))
+        r2 = (Xq[..., 0] - tip[0]) ** 2 + (Xq[..., 1] - tip[1]) ** 2
+        mu_A.append(np.ascontiguousarray(1.0 + 50.0 * np.exp(-800.0 * r2)))
+    cells = mesh.cells(J)
+    h = [mesh.extent[d] / cells[d] for d in range(3)]
+    ci = np.meshgrid(*[np.arange(c) for c in cells], indexing="ij")
+    centres = np.stack([(g.ravel(order="F") + 0.5) * h[d] for d, g in enumerate(ci)], axis=-1)
+    solid_cells = np.ascontiguousarray(_inside_strip(centres).astype(np.uint8))
+    # w = v on every node of a solid cell: mark those nodes
+    nn = mesh.vel_nodes(J)
+    node = np.zeros(int(np.prod(nn)), dtype=bool)
+    sc = np.nonzero(solid_cells)[0]
+    cx, cy, cz = sc % cells[0], (sc // cells[0]) % cells[1], sc // (cells[0] * cells[1])
+    for lz in range(3):
+        for ly in range(3):
+            for lx in range(3):
+                node[(2 * cx + lx) + nn[0] * ((2 * cy + ly) + nn[1] * (2 * cz + lz))] = True
+    for i in range(2):
+        wi = w[i].reshape(3, -1)
+        wi[:, node] = v[i].reshape(3, -1)[:, node]
+    return GcsiInputs(mesh=mesh, ext_mesh=ext_mesh, solid_q=solid_q, solid_cells=solid_cells, mu_A=mu_A,
+                      material=dict(GCSI_MATERIAL), u=u, v=v, w=w, p=p)

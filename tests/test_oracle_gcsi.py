@@ -1,0 +1,279 @@
+"""Pins of the time-step oracle (oracle/gcsi.py) against what the paper and the
+mathematics fix, independent of its own code:
+
+* the BDF stencil of Sec. 3.1 is exact on polynomials in time of degree k;
+* every right-hand-side term of eq. form_g_j / eq. form_g_p, on affine geometry
+  (where the integrals have closed forms: volumes, centroids, constant gradients);
+* the Q2 interpolation of the corrector's convective velocity and the Peclet law;
+* the extension with fixed solid nodes reproduces affine fields and minimises the energy;
+* whole steps: a free solid translating or uniformly accelerated by a body force is
+  reproduced exactly, and a fluid at rest under a body force keeps v = 0 with the
+  hydrostatic pressure.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fem, gcsi, solvers
+
+pytestmark = pytest.mark.filterwarnings("ignore::scipy.sparse.SparseEfficiencyWarning")
+
+REF = fem.Reference(3)
+EXT = (1.0, 0.5, 0.5)
+CELLS = (4, 2, 2)
+
+
+def _box(faces=0):
+    return fem.Box(3, CELLS, EXT, faces)
+
+
+def _solid_cells(box, xr=(1, 3)):
+    ci = box.cell_index_grid()
+    return (ci[0] >= xr[0]) & (ci[0] < xr[1])
+
+
+def _nodal(box, f):
+    """Nodal values (component-major) of f(X) at the Q2 nodes; f maps [3][n] -> [3][n]."""
+    return np.ascontiguousarray(f(box.vel_node_ref_coords()).ravel())
+
+
+def _prm(**kw):
+    base = dict(k=2, tau=0.01, rho_f=2.0, rho_s=5.0, eta_f=0.3, mu_s=7.0, eta_V=0.1, body=(0.0, 0.0, 0.0))
+    base.update(kw)
+    return gcsi.Params(**base)
+
+
+def _zero_state(box, k=2):
+    z = np.zeros(box.n_vel)
+    return gcsi.State(u=[z] * k, v=[z] * k, w=[z] * k)
+
+
+def _affine(box, D):
+    return D @ box.vertex_coords()
+
+
+def test_bdf_constants_exact_on_time_polynomials():
+    rng = np.random.default_rng(1)
+    n, tau, tn = 7, 0.013, 0.4
+    for k in (1, 2):
+        c = rng.normal(size=(k + 1, n))                       # u(t) = sum_j c_j t^j
+        u = lambda t: sum(c[j] * t ** j for j in range(k + 1))
+        du = lambda t: sum(j * c[j] * t ** (j - 1) for j in range(1, k + 1))
+        prm = _prm(k=k, tau=tau)
+        hist = [u(tn - (i + 1) * tau) for i in range(k)]
+        got = gcsi.explicit_displacement(prm, du(tn), hist)
+        assert np.allclose(got, u(tn), rtol=0, atol=1e-13), k
+        # the stencil sums to zero and reproduces the derivative (alpha_0 = 1)
+        assert abs(1.0 + sum(prm.alpha)) < 1e-15
+
+
+def _cells_volume_moment(box, cells, D):
+    """Volume and first moment of the image (I + D) of the given cells."""
+    h = box.h()
+    ci = box.cell_index_grid()
+    vol = np.prod(h) * np.count_nonzero(cells) * np.linalg.det(np.eye(3) + D)
+    cen = np.stack([(ci[d][cells] + 0.5) * h[d] for d in range(3)])    # reference centroids
+    mom = (np.eye(3) + D) @ cen.sum(axis=1) * np.prod(h) * np.linalg.det(np.eye(3) + D)
+    return vol, mom
+
+
+def test_rhs_body_and_mass_history_closed_form():
+    box = _box()
+    D = np.array([[0.05, 0.02, -0.01], [0.0, -0.03, 0.04], [0.01, 0.0, 0.02]])
+    prm = _prm(body=(0.3, -1.1, 0.7))
+    sc = _solid_cells(box)
+    sq = np.repeat(sc[:, None], 27, 1)
+    c1, c2 = np.array([0.4, -0.2, 0.9]), np.array([-0.6, 0.5, 0.1])
+    st = _zero_state(box)
+    st.v = [_nodal(box, lambda X: np.tile(c1[:, None], X.shape[1])), _nodal(box, lambda X: np.tile(c2[:, None], X.shape[1]))]
+    g_u, g_p = gcsi.rhs(box, REF, prm, "C", sq, _affine(box, D), np.zeros(box.n_vel), st)
+    F = np.asarray(prm.body) - (prm.alpha[0] * c1 + prm.alpha[1] * c2) / (prm.gamma * prm.tau)
+    vs, ms = _cells_volume_moment(box, sc, D)
+    vf, mf = _cells_volume_moment(box, ~sc, D)
+    G = g_u.reshape(3, -1)
+    # partition of unity: sum_i g[a, i] = int rho F_a
+    assert np.allclose(G.sum(axis=1), (prm.rho_s * vs + prm.rho_f * vf) * F, rtol=1e-12)
+    # linear test fields x_b (physical coordinates of the nodes): int rho F_a x_b
+    x = (np.eye(3) + D) @ box.vel_node_ref_coords()
+    got = G @ x.T
+    want = np.outer(F, prm.rho_s * ms + prm.rho_f * mf)
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-14)
+    assert not np.any(g_p)
+
+
+def test_rhs_predictor_convection_closed_form():
+    box = _box()
+    D = np.array([[0.04, -0.02, 0.0], [0.01, 0.02, 0.03], [-0.02, 0.0, -0.01]])
+    prm = _prm()
+    Gv = np.array([[0.3, -0.2, 0.5], [0.1, 0.4, -0.3], [-0.6, 0.2, 0.1]])
+    b0 = np.array([0.2, -0.1, 0.3])
+    cc = np.array([0.7, -0.4, 0.25])
+    L = lambda X: Gv @ ((np.eye(3) + D) @ X) + b0[:, None]              # linear in x
+    st = _zero_state(box)
+    Ln = _nodal(box, L)
+    cn = _nodal(box, lambda X: np.tile(cc[:, None], X.shape[1]))
+    st.v = [Ln, Ln]
+    st.w = [0.5 * (Ln - cn), np.zeros(box.n_vel)]                       # v° = c, v* = L (G2)
+    sq = np.zeros((box.n_cells, 27), dtype=bool)
+    g_u, _ = gcsi.rhs(box, REF, prm, "P", sq, _affine(box, D), np.zeros(box.n_vel), st)
+    vol, mom = _cells_volume_moment(box, np.ones(box.n_cells, dtype=bool), D)
+    intL = Gv @ mom + b0 * vol                                          # int_O# L
+    # mass history: -(rho / (gamma tau)) (alpha_1 + alpha_2) int L = (rho/(gamma tau)) int L
+    want = prm.rho_f / (prm.gamma * prm.tau) * intL - prm.rho_f * (Gv @ cc) * vol
+    assert np.allclose(g_u.reshape(3, -1).sum(axis=1), want, rtol=1e-12)
+
+
+def test_rhs_solid_stress_closed_form():
+    box = _box()
+    D = np.array([[0.03, 0.05, -0.02], [-0.01, 0.02, 0.04], [0.02, -0.03, 0.01]])
+    prm = _prm()
+    rng = np.random.default_rng(5)
+    U1, U2, Uh = (0.05 * rng.normal(size=(3, 3)) for _ in range(3))
+    st = _zero_state(box)
+    st.u = [_nodal(box, lambda X: U1 @ X), _nodal(box, lambda X: U2 @ X)]
+    uh = _nodal(box, lambda X: Uh @ X)
+    sc = _solid_cells(box)
+    sq = np.repeat(sc[:, None], 27, 1)
+    g_u, _ = gcsi.rhs(box, REF, prm, "C", sq, _affine(box, D), uh, st)
+    Fi = np.linalg.inv(np.eye(3) + D)
+    Ub = prm.alpha[0] * U1 + prm.alpha[1] * U2
+    Gs, Gh = Ub @ Fi, Uh @ Fi                                           # physical gradients
+    T = prm.mu_s * (Gs + Gs.T + Gh.T @ Gh)                              # reading G1
+    vs, _ = _cells_volume_moment(box, sc, D)
+    G = g_u.reshape(3, -1)
+    assert np.allclose(G.sum(axis=1), 0.0, atol=1e-12 * prm.mu_s)       # eps(constant) = 0
+    Bm = np.array([[0.3, -0.7, 0.2], [0.5, 0.1, -0.4], [-0.2, 0.6, 0.9]])
+    phi = Bm @ ((np.eye(3) + D) @ box.vel_node_ref_coords())            # phi(x) = B x
+    assert np.isclose(np.sum(G * phi), vs * np.sum(T * Bm), rtol=1e-12)
+
+
+def test_volume_correction_closed_forms():
+    box = _box()
+    prm = _prm()
+    sc = _solid_cells(box)
+    sq = np.repeat(sc[:, None], 27, 1)
+    h = box.h()
+    x0, x1 = 1 * h[0], 3 * h[0]
+    area = EXT[1] * EXT[2]
+    # affine u#: J# constant
+    U = np.array([[0.1, 0.02, 0.0], [-0.03, 0.05, 0.01], [0.0, 0.04, -0.02]])
+    gp = gcsi.volume_correction(box, REF, prm, sq, _nodal(box, lambda X: U @ X))
+    assert np.isclose(gp.sum(), -(np.linalg.det(np.eye(3) + U) - 1.0) / prm.eta_V * (x1 - x0) * area, rtol=1e-12)
+    # u# = (a X^2, 0, 0): J# = 1 + 2 a X; tested with q = 1 and q = X
+    a = 0.2
+    uq = _nodal(box, lambda X: np.stack([a * X[0] ** 2, 0 * X[0], 0 * X[0]]))
+    gp = gcsi.volume_correction(box, REF, prm, sq, uq)
+    Xp = box.vertex_coords()[0]
+    assert np.isclose(gp.sum(), -(a / prm.eta_V) * (x1 ** 2 - x0 ** 2) * area, rtol=1e-12)
+    assert np.isclose(gp @ Xp, -(2 * a / prm.eta_V) * (x1 ** 3 - x0 ** 3) / 3 * area, rtol=1e-12)
+    # a simple shear keeps the volume: no correction
+    us = _nodal(box, lambda X: np.stack([0.3 * X[1], 0 * X[0], 0 * X[0]]))
+    assert np.abs(gcsi.volume_correction(box, REF, prm, sq, us)).max() < 1e-15
+    # eta_V = infinity switches it off
+    assert not np.any(gcsi.volume_correction(box, REF, _prm(eta_V=math.inf), sq, uq))
+
+
+def test_convection_inputs_interpolate_and_follow_the_peclet_law():
+    box = _box()
+    f = lambda X: np.stack([X[0] ** 2 - X[1] * X[2], 0.5 * X[1] + X[0] * X[2], X[2] ** 2 - 0.2])
+    vh = _nodal(box, f)
+    wh = np.zeros(box.n_vel)
+    eta = np.full((box.n_cells, 27), 1e-3)
+    vq, r = gcsi.convection_inputs(box, REF, vh, wh, eta)
+    # the Gauss points of every cell, from the rule itself
+    pts = fem.gauss_rule(3)[0]
+    ci = box.cell_index_grid()
+    h = box.h()
+    q = np.array([(a, b, c) for c in range(3) for b in range(3) for a in range(3)])
+    Xq = np.stack([(ci[d][:, None] + pts[q[:, d]][None, :]) * h[d] for d in range(3)])   # [3][nc][Q]
+    want = np.moveaxis(f(Xq.reshape(3, -1)).reshape(3, box.n_cells, 27), 0, -1)
+    assert np.allclose(vq, want, rtol=0, atol=1e-14)
+    # constant speed c: r from coth, computed with cosh / sinh
+    c = np.array([0.6, 0.0, -0.8])
+    vh = _nodal(box, lambda X: np.tile(c[:, None], X.shape[1]))
+    hK = math.sqrt(float(np.sum(h ** 2)))
+    for mu, on in ((1e-3, True), (10.0, False)):
+        _, r = gcsi.convection_inputs(box, REF, vh, wh, np.full((box.n_cells, 27), mu))
+        pe = 1.0 * hK / (2 * mu * 2.0)
+        want = hK / (2 * 1.0 * 2.0) * (math.cosh(pe) / math.sinh(pe) - 1.0 / pe) if on else 0.0
+        assert pe >= 1.0 if on else pe < 1.0
+        assert np.allclose(r, want, rtol=1e-12, atol=0)
+
+
+def test_extension_with_fixed_nodes_reproduces_affine_fields():
+    box = _box(faces=63)
+    disp0 = np.zeros((3, box.n_p))
+    J = fem.jacobians_q1(box, disp0, REF)
+    mu = np.full((box.n_cells, 27), 2.5)
+    Mx = np.array([[0.1, -0.2, 0.05], [0.3, 0.0, -0.1], [0.02, 0.07, -0.04]])
+    g = _nodal(box, lambda X: Mx @ X + np.array([[0.1], [0.2], [-0.3]]))
+    fixed = np.tile(gcsi.fixed_nodes(box, _solid_cells(box)), 3)
+    u = solvers.extension_solve(box, J, mu, REF, g, fixed=fixed)
+    assert np.allclose(u, g, rtol=0, atol=1e-12)
+
+
+def test_extension_fixes_the_solid_and_minimises_the_energy():
+    box = _box(faces=63)
+    rng = np.random.default_rng(3)
+    mu = 1.0 + 50.0 * rng.uniform(size=(box.n_cells, 27))
+    v = rng.uniform(-1, 1, size=box.n_vel)
+    fn = gcsi.fixed_nodes(box, _solid_cells(box))
+    w = gcsi.extension(box, REF, mu, v, fn)
+    f3 = np.tile(fn, 3)
+    walls = box.dirichlet_vel_dofs()
+    assert np.array_equal(w[f3], v[f3])
+    assert not np.any(w[walls & ~f3])
+    J = fem.jacobians_q1(box, np.zeros((3, box.n_p)), REF)
+    E = lambda x: solvers.extension_energy(box, J, mu, REF, x)
+    free = ~(walls | f3)
+    e0 = E(w)
+    for s in range(5):
+        z = np.where(free, rng.normal(size=box.n_vel), 0.0)
+        assert E(w + 1e-3 * z) > e0 and E(w - 1e-3 * z) > e0
+
+
+def _all_solid_problem(prm):
+    box = _box()
+    return gcsi.Problem(box=box, ext_box=_box(faces=63), solid_q=np.ones((box.n_cells, 27), dtype=bool),
+                        solid_cells=np.ones(box.n_cells, dtype=bool),
+                        mu_A=np.ones((box.n_cells, 27)), prm=prm)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_step_reproduces_a_uniformly_accelerated_free_solid(k):
+    """u(t) = V0 t + b t^2 / 2, v = w = V0 + b t: both stages and the displacement
+    recovery are exact (BDF_k is exact on these polynomials in time)."""
+    b = np.array([0.4, -2.0, 0.3]) if k == 2 else np.zeros(3)     # BDF1: linear only
+    prm = _prm(k=k, body=tuple(b), tau=0.02)
+    pb = _all_solid_problem(prm)
+    box = pb.box
+    V0 = np.array([0.5, 0.25, -0.75])
+    tn = 0.3
+    vel = lambda t: V0 + b * t
+    disp = lambda t: V0 * t + 0.5 * b * t * t
+    const = lambda c: _nodal(box, lambda X: np.tile(c[:, None], X.shape[1]))
+    ts = [tn - (i + 1) * prm.tau for i in range(k)]
+    st = gcsi.State(u=[const(disp(t)) for t in ts], v=[const(vel(t)) for t in ts],
+                    w=[const(vel(t)) for t in ts])
+    out = gcsi.step(pb, st, ("P", "C"), REF)
+    for key, want in (("v", vel(tn)), ("w", vel(tn)), ("u", disp(tn))):
+        assert np.allclose(out[key], const(want), rtol=0, atol=1e-11), key
+    assert np.abs(out["p"]).max() < 1e-9
+
+
+def test_step_keeps_a_fluid_at_rest_with_the_hydrostatic_pressure():
+    """Walls everywhere but the outflow x = L, body force b along x, no history: v = 0
+    and p = rho b (L - x) (so that p = 0 where the outflow's natural condition holds)."""
+    box = fem.Box(3, CELLS, EXT, 0b111101)
+    bx = 3.0
+    prm = _prm(body=(bx, 0.0, 0.0))
+    sq = np.zeros((box.n_cells, 27), dtype=bool)
+    pb = gcsi.Problem(box=box, ext_box=_box(faces=63), solid_q=sq, solid_cells=np.zeros(box.n_cells, dtype=bool),
+                      mu_A=np.ones((box.n_cells, 27)), prm=prm)
+    out = gcsi.step(pb, _zero_state(box), ("P", "C"), REF)
+    X = box.vertex_coords()[0]
+    p_want = prm.rho_f * bx * (EXT[0] - X)
+    assert np.abs(out["v"]).max() < 1e-10 * np.abs(p_want).max()
+    assert np.allclose(out["p"], p_want, rtol=1e-10, atol=1e-10)
+    assert not np.any(out["w"]) and not np.any(out["u"])

@@ -217,3 +217,65 @@ def test_planted_vcycle_mistake_is_caught(attr, fn, monkeypatch):
         except AssertionError:
             caught += 1
     assert caught >= 1, fn.__doc__
+
+
+# ---------------------------------------------------------------- time step (Algorithm 1)
+from oracle import gcsi  # noqa: E402
+import tests.test_oracle_gcsi as gpins  # noqa: E402
+
+_orig_rhs = gcsi.rhs
+_orig_explicit = gcsi.explicit_displacement
+
+
+def _with_state(fn):
+    def rhs(box, ref, prm, mode, solid_q, disp, u_hash, state, absolute=False):
+        return _orig_rhs(box, ref, prm, mode, solid_q, disp, u_hash, fn(state), absolute)
+    return rhs
+
+
+def _printed_stress_sign(st):
+    """+2 eps(sum alpha u) in the explicit stress, as printed"""
+    return gcsi.State(u=[-x for x in st.u], v=st.v, w=st.w, p=st.p)
+
+
+def _printed_vcirc(st):
+    """w^{n,1} in the second term of the predictor's extrapolation, as printed"""
+    return gcsi.State(u=st.u, v=st.v, w=[st.w[0], st.w[0]], p=st.p)
+
+
+def _mass_history_sign(st):
+    """the BDF history of the velocity added instead of subtracted"""
+    return gcsi.State(u=st.u, v=[-x for x in st.v], w=st.w, p=st.p)
+
+
+def _explicit_last_only(prm, w, u_hist):
+    """u^{n-k} in every term of the explicit step (the misprint of Algorithm 1)"""
+    return _orig_explicit(prm, w, [u_hist[-1]] * len(u_hist))
+
+
+GCSI_CASES = {
+    "printed stress sign": ("rhs", _with_state(_printed_stress_sign)),
+    "printed extrapolation": ("rhs", _with_state(_printed_vcirc)),
+    "mass history sign": ("rhs", _with_state(_mass_history_sign)),
+    "u^{n-k} in the explicit step": ("explicit_displacement", _explicit_last_only),
+    "alpha_1 and alpha_2 swapped": ("BDF", {1: gcsi.BDF[1], 2: (2.0 / 3.0, (1.0 / 3.0, -4.0 / 3.0))}),
+}
+
+GCSI_PINS = [gpins.test_bdf_constants_exact_on_time_polynomials,
+             gpins.test_rhs_body_and_mass_history_closed_form,
+             gpins.test_rhs_predictor_convection_closed_form,
+             gpins.test_rhs_solid_stress_closed_form,
+             lambda: gpins.test_step_reproduces_a_uniformly_accelerated_free_solid(2)]
+
+
+@pytest.mark.parametrize("case", sorted(GCSI_CASES))
+def test_planted_time_step_mistake_is_caught(case, monkeypatch):
+    attr, fn = GCSI_CASES[case]
+    monkeypatch.setattr(gcsi, attr, fn)
+    caught = 0
+    for pin in GCSI_PINS:
+        try:
+            pin()
+        except AssertionError:
+            caught += 1
+    assert caught >= 1, case
