@@ -279,6 +279,90 @@ fsi_status fsi_solve(fsi_ctx* ctx, const double* g_u, const double* g_p, double*
 fsi_status fsi_solve_extension(fsi_ctx* ctx, const double* g, double* u, const fsi_solve_opts* opts,
                                fsi_solve_info* info);
 
+/* Interior Dirichlet nodes for the extension Ext of Sec. 2, which is solved on the
+ * fluid part only, with the solid's values on the solid: marks every velocity node of
+ * the flagged finest-level cells as constrained, exactly like a wall node (identity
+ * row, zero column; fsi_solve_extension then keeps u = g there).  Coarser levels
+ * constrain the node at the same position (the flagged region should be a union of
+ * coarse cells for the best multigrid; otherwise it stays a valid symmetric
+ * preconditioner).  fixed: HOST array of n_cells (finest level), nonzero = fixed.
+ * Call once, before fsi_setup; the single atomic launch (variants 16 .. 20) is not used
+ * on such a context.  Errors: FSI_ERR_ARG, FSI_ERR_STATE after fsi_setup or a second
+ * call. */
+fsi_status fsi_set_fixed_cells(fsi_ctx* ctx, const uint8_t* fixed);
+/* Boundary data of the extension: g = v on the nodes of the fixed cells, 0 elsewhere
+ * (finest level, device [n_vel] both).  Errors: FSI_ERR_ARG, FSI_ERR_STATE without
+ * fsi_set_fixed_cells. */
+fsi_status fsi_fixed_values(fsi_ctx* ctx, const double* v, double* g);
+
+/* One step of the GCSI_k(M_1, .., M_S) scheme (Algorithm 1, Sec. 3.1.1) is composed by
+ * the caller from: fsi_gcsi_displacement (explicit step, new geometry through
+ * fsi_set_displacement), fsi_gcsi_set_coefficients, fsi_gcsi_set_convection (corrector
+ * stage), fsi_setup, fsi_gcsi_rhs, fsi_solve, then fsi_fixed_values and
+ * fsi_solve_extension on a second context (every face fixed, the solid's cells fixed,
+ * reference geometry, c_m = 0, eta = mu_A / 2), and fsi_gcsi_displacement once more for
+ * the displacement recovery.  Fields are finest-level nodal arrays of the reference
+ * mesh (the pull-backs u^{n,i} of Sec. 3.1 have the stored nodal values), device FP64,
+ * component-major [3][n_vel_nodes].  3D contexts only.
+ * Physical data: BDF order k (Sec. 3.1: k = 1 gamma = 1, alpha_1 = -1; k = 2
+ * gamma = 2/3, alpha_1 = -4/3, alpha_2 = 1/3), time step tau, densities, fluid
+ * viscosity eta_f, solid shear modulus mu_s (solid viscosity gamma tau mu_s, Sec. 3.1.1),
+ * volume-correction parameter eta_V (Sec. 3.1.2; <= 0 or infinite: none) and the body
+ * acceleration (force density rho * body). */
+typedef struct {
+    int k;
+    double tau;
+    double rho_f, rho_s;
+    double eta_f, mu_s;
+    double eta_V;
+    double body[3];
+} fsi_gcsi_params;
+
+#define FSI_GCSI_PREDICTOR 0
+#define FSI_GCSI_CORRECTOR 1
+
+/* Velocity splitting (Sec. 3.1.1): u_out = gamma tau w - sum_i alpha_i u_i (the
+ * explicit displacement u# from w#, and the displacement recovery from w^n), and, if
+ * disp_out is not NULL, its vertex values [3][n_vert] for fsi_set_displacement (the
+ * multilinear map through the vertex values of the Q2 field).  u2 is read for k = 2
+ * only.  Either output may be NULL.  Errors: FSI_ERR_ARG. */
+fsi_status fsi_gcsi_displacement(fsi_ctx* ctx, const fsi_gcsi_params* prm, const double* w, const double* u1,
+                                 const double* u2, double* u_out, double* disp_out);
+/* Coefficients of the stress splitting on every level, c_m = rho / (gamma tau) and
+ * eta = eta_f (fluid) or gamma tau mu_s (solid), then as fsi_set_coefficients.
+ * solid_q: HOST array of n_levels DEVICE pointers, each [n_cells][27] uint8 of that
+ * level (nonzero: the point lies in the solid).  Call after every geometry change.
+ * Errors: as fsi_set_coefficients. */
+fsi_status fsi_gcsi_set_coefficients(fsi_ctx* ctx, const fsi_gcsi_params* prm, const uint8_t* const* solid_q);
+/* Right-hand side of the M-mode system on the finest level (eq. form_g_j, eq. form_g_p),
+ * on the explicit geometry given by its vertex displacement disp ([3][n_vert]):
+ *   g_u(v) = (rho (body - (1/(gamma tau)) sum_i alpha_i v_i), v)
+ *            - [predictor] (rho (grad v*) v°, v)        v* = 2 v1 - v2,
+ *                                                       v° = 2 (v1 - w1) - (v2 - w2)
+ *                                                       (k = 1: v1 and v1 - w1)
+ *            + (mu_s [2 eps(sum_i alpha_i u_i) + (grad u#)^T grad u#], eps(v))_solid
+ *   g_p(q) = -(1/eta_V) (det(I + grad-hat u#) - 1, q-hat)_{reference solid}
+ * (readings: the explicit solid stress as the velocity splitting substituted into the
+ * solid stress of Sec. 2.3, sign -2 eps(..) where the paper prints +; v° extrapolates
+ * the relative velocity, with w2 in its second term where the paper prints w1; the
+ * predictor's convective term explicit as a whole).  solid_q: DEVICE [n_cells][27]
+ * uint8 of the finest level.  Dirichlet rows of g_u are zero.  Sums with atomics (the
+ * last bits vary from run to run).  u2, v2, w2 are read for k = 2, w1 and w2 in the
+ * predictor mode only.  Errors: FSI_ERR_ARG. */
+fsi_status fsi_gcsi_rhs(fsi_ctx* ctx, const fsi_gcsi_params* prm, int mode, const uint8_t* solid_q,
+                        const double* disp, const double* u_hash, const double* u1, const double* u2,
+                        const double* v1, const double* v2, const double* w1, const double* w2, double* g_u,
+                        double* g_p);
+/* Corrector-mode terms on every level (as fsi_set_convection, rho = rho_f): v° = v# - w#
+ * at the Gauss points (the fine fields read at each level's nodes) and the streamline
+ * parameter of Sec. 3.2 per cell (p1 = 2, h_K the reference cell diagonal, |v°| the
+ * largest point value, eta the cell mean of the last fsi_gcsi_set_coefficients):
+ * Pe = |v°| h_K / (2 eta p1), r = h_K / (2 |v°| p1) (coth Pe - 1/Pe) for Pe >= 1, else 0.
+ * rho_f suffices: v° vanishes on every node of a solid cell (w# = v# there).  Errors:
+ * FSI_ERR_ARG, FSI_ERR_STATE without fsi_gcsi_set_coefficients or geometry. */
+fsi_status fsi_gcsi_set_convection(fsi_ctx* ctx, const fsi_gcsi_params* prm, const double* v_hash,
+                                   const double* w_hash);
+
 /* Autotuner: times the cell-kernel launch variants (wavefronts per workgroup,
  * register cap, cached or streaming geometry loads) for every operator class
  * (A, A with the fused Chebyshev step, Stokes, Stokes with the fused residual,

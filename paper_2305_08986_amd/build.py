@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfsi.so")
-SOURCES = ["kernels_cell.hip", "kernels_aux.hip", "fsi_api.hip"]
+SOURCES = ["kernels_cell.hip", "kernels_aux.hip", "kernels_gcsi.hip", "fsi_api.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 # -packed-fp32-ops: never emit packed FP32 VALU instructions

@@ -653,6 +653,16 @@ static fsi_status setup_coarse(Context* ctx) {
     launch_gj(C.d_inv64, n, C.d_piv, C.d_piv + n, C.d_col, C.d_tmp, ctx->d_flag, s);
     launch_cast<float, double>(C.d_inv32, C.d_inv64, n * n, s);
     // synchronises the stream, so the host vectors above outlive their copies
+    ctx->coarse_block_ok = true;
+    if (ctx->has_fixed) {
+        // fixed cells can leave pressure nodes with no free velocity dof around them: the
+        // block matrix is then singular, and only the extension (velocity-only coarse
+        // solve) is available on the context
+        FSI_HIP_TRY(hipMemcpyAsync(ctx->h_flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        FSI_HIP_TRY(hipStreamSynchronize(s));
+        ctx->coarse_block_ok = *ctx->h_flag == 0;
+        return FSI_OK;
+    }
     return sync_flag(ctx, FSI_ERR_BREAKDOWN, "singular coarse-level matrix");
 }
 
@@ -1307,6 +1317,8 @@ fsi_status fsi_vcycle(fsi_ctx* h, const double* r_u, const double* r_p, double* 
     if (!h || !r_u || !r_p || !z_u || !z_p) return FSI_ERR_ARG;
     Context* ctx = &h->c;
     if (!ctx->setup_done) return fail(ctx, FSI_ERR_STATE, "vcycle before setup");
+    if (!ctx->coarse_block_ok)
+        return fail(ctx, FSI_ERR_STATE, "singular coarse block matrix (fixed cells): extension solves only");
     const Level& L = ctx->lv[ctx->nlev - 1];
     hipStream_t s = ctx->stream;
     // combined staging through the Krylov-independent IO buffers
@@ -1334,6 +1346,8 @@ fsi_status fsi_solve(fsi_ctx* h, const double* g_u, const double* g_p, double* u
     if (!h || !g_u || !g_p || !u || !p || !o) return FSI_ERR_ARG;
     Context* ctx = &h->c;
     if (!ctx->setup_done) return fail(ctx, FSI_ERR_STATE, "solve before setup");
+    if (!ctx->coarse_block_ok)
+        return fail(ctx, FSI_ERR_STATE, "singular coarse block matrix (fixed cells): extension solves only");
     if (o->restart < 1 || o->max_iter < 0 || !(o->rtol >= 0) || o->reorth < 0 || o->reorth > 2)
         return fail(ctx, FSI_ERR_ARG, "invalid solve options");
     const auto t0 = std::chrono::steady_clock::now();
@@ -1637,6 +1651,206 @@ fsi_status fsi_solve_extension(fsi_ctx* h, const double* g, double* u, const fsi
     return finish(it, rel, rel <= o->rtol ? FSI_OK : FSI_NOT_CONVERGED);
 }
 
+// ---------------------------------------------------------------- fixed nodes (extension on the fluid part)
+fsi_status fsi_set_fixed_cells(fsi_ctx* h, const uint8_t* fixed) {
+    if (!h || !fixed) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    if (ctx->setup_done) return fail(ctx, FSI_ERR_STATE, "fsi_set_fixed_cells after fsi_setup");
+    if (ctx->has_fixed) return fail(ctx, FSI_ERR_STATE, "fsi_set_fixed_cells called twice");
+    const int J = ctx->nlev - 1;
+    Level& F = ctx->lv[J];
+    const int dim = F.dim, NLOC = dim == 3 ? 27 : 9;
+    // nodes of the fixed cells on the finest level
+    std::vector<uint8_t> fm((size_t)F.nvn, 0);
+    for (int64_t c = 0; c < F.nc; ++c) {
+        if (!fixed[c]) continue;
+        const int64_t cx = c % F.cells[0], cy = (c / F.cells[0]) % F.cells[1], cz = c / ((int64_t)F.cells[0] * F.cells[1]);
+        for (int n = 0; n < NLOC; ++n) {
+            const int lx = n % 3, ly = (n / 3) % 3, lz = n / 9;
+            fm[(size_t)((2 * cx + lx) + F.vnodes[0] * ((2 * cy + ly) + (int64_t)F.vnodes[1] * (2 * cz + lz)))] = 1;
+        }
+    }
+    hipStream_t s = ctx->stream;
+    FSI_HIP_TRY(hipStreamSynchronize(s));
+    for (int j = 0; j <= J; ++j) {
+        Level& L = ctx->lv[j];
+        const int64_t st = int64_t(1) << (J - j);
+        bool changed = false;
+        for (int64_t n = 0; n < L.nvn; ++n) {
+            const int64_t ix = n % L.vnodes[0], iy = (n / L.vnodes[0]) % L.vnodes[1],
+                          iz = n / ((int64_t)L.vnodes[0] * L.vnodes[1]);
+            const int64_t fn = st * ix + F.vnodes[0] * (st * iy + (int64_t)F.vnodes[1] * st * iz);
+            if (fm[(size_t)fn] && !L.h_dir_node[(size_t)n]) {
+                L.h_dir_node[(size_t)n] = 1;
+                changed = true;
+            }
+        }
+        if (!changed) continue;
+        std::vector<int> dirn;
+        for (int64_t n = 0; n < L.nvn; ++n)
+            if (L.h_dir_node[(size_t)n]) dirn.push_back((int)n);
+        dfree(ctx, &L.d_dir_nodes);
+        TRY(dalloc(ctx, &L.d_dir_nodes, (int64_t)dirn.size()));
+        L.n_dir = (int64_t)dirn.size();
+        FSI_HIP_TRY(hipMemcpy(L.d_dir_nodes, dirn.data(), sizeof(int) * dirn.size(), hipMemcpyHostToDevice));
+        FSI_HIP_TRY(hipMemcpy(L.d_wall, L.h_dir_node.data(), (size_t)L.nvn, hipMemcpyHostToDevice));
+        // wall bits of the cell info (processing order; vmap gives each local node's node)
+        std::vector<int> vmap((size_t)L.nc * NLOC);
+        std::vector<uint4> info((size_t)L.nc);
+        FSI_HIP_TRY(hipMemcpy(vmap.data(), L.d_vmap, sizeof(int) * vmap.size(), hipMemcpyDeviceToHost));
+        FSI_HIP_TRY(hipMemcpy(info.data(), L.d_info, sizeof(uint4) * info.size(), hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < L.nc; ++k)
+            for (int n = 0; n < NLOC; ++n)
+                if (L.h_dir_node[(size_t)vmap[(size_t)(k * NLOC + n)]]) info[(size_t)k].x |= 1u << n;
+        FSI_HIP_TRY(hipMemcpy(L.d_info, info.data(), sizeof(uint4) * info.size(), hipMemcpyHostToDevice));
+    }
+    TRY(dalloc(ctx, &F.d_fixed, F.nvn));
+    FSI_HIP_TRY(hipMemcpy(F.d_fixed, fm.data(), (size_t)F.nvn, hipMemcpyHostToDevice));
+    for (int pi = 0; pi < 2; ++pi) std::fill(ctx->atom[pi].begin(), ctx->atom[pi].end(), (int8_t)-1);
+    ctx->has_fixed = true;
+    return FSI_OK;
+}
+
+fsi_status fsi_fixed_values(fsi_ctx* h, const double* v, double* g) {
+    if (!h || !v || !g) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    if (!ctx->has_fixed) return fail(ctx, FSI_ERR_STATE, "fsi_fixed_values without fsi_set_fixed_cells");
+    const Level& F = ctx->lv[ctx->nlev - 1];
+    launch_fixed_values(F, F.d_fixed, v, g, ctx->stream);
+    return FSI_OK;
+}
+
+// ---------------------------------------------------------------- time step (Algorithm 1)
+struct Bdf {
+    double gamma, a1, a2;
+};
+static fsi_status gcsi_check(Context* ctx, const fsi_gcsi_params* p, Bdf* b) {
+    if (!p) return FSI_ERR_ARG;
+    if (ctx->lv[0].dim != 3) return fail(ctx, FSI_ERR_ARG, "the time-step kernels are 3D only");
+    if (p->k != 1 && p->k != 2) return fail(ctx, FSI_ERR_ARG, "BDF order k must be 1 or 2");
+    auto fin = [](double x) { return std::isfinite(x); };
+    if (!(p->tau > 0) || !fin(p->tau) || !(p->rho_f >= 0) || !fin(p->rho_f) || !(p->rho_s >= 0) || !fin(p->rho_s) ||
+        !(p->eta_f > 0) || !fin(p->eta_f) || !(p->mu_s >= 0) || !fin(p->mu_s) || std::isnan(p->eta_V) ||
+        !fin(p->body[0]) || !fin(p->body[1]) || !fin(p->body[2]))
+        return fail(ctx, FSI_ERR_ARG, "invalid time-step parameters");
+    // BDF stencil of Sec. 3.1 (alpha_0 = 1)
+    if (p->k == 1) *b = {1.0, -1.0, 0.0};
+    else *b = {2.0 / 3.0, -4.0 / 3.0, 1.0 / 3.0};
+    return FSI_OK;
+}
+
+fsi_status fsi_gcsi_displacement(fsi_ctx* h, const fsi_gcsi_params* prm, const double* w, const double* u1,
+                                 const double* u2, double* u_out, double* disp_out) {
+    if (!h || !w || !u1 || (!u_out && !disp_out)) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    Bdf b;
+    TRY(gcsi_check(ctx, prm, &b));
+    if (prm->k == 2 && !u2) return fail(ctx, FSI_ERR_ARG, "k = 2 needs u^{n-2}");
+    const Level& F = ctx->lv[ctx->nlev - 1];
+    launch_gcsi_displacement(F, w, u1, prm->k == 2 ? u2 : nullptr, b.gamma * prm->tau, b.a1, b.a2, u_out, disp_out,
+                             ctx->stream);
+    return FSI_OK;
+}
+
+static fsi_status gcsi_scratch(Context* ctx) {
+    if (!ctx->gcsi_tmp) TRY(dalloc(ctx, &ctx->gcsi_tmp, 4 * ctx->lv[ctx->nlev - 1].nc * 27));
+    return FSI_OK;
+}
+
+fsi_status fsi_gcsi_set_coefficients(fsi_ctx* h, const fsi_gcsi_params* prm, const uint8_t* const* solid_q) {
+    if (!h || !solid_q) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    Bdf b;
+    TRY(gcsi_check(ctx, prm, &b));
+    for (int j = 0; j < ctx->nlev; ++j)
+        if (!solid_q[j]) return fail(ctx, FSI_ERR_ARG, "fsi_gcsi_set_coefficients: null solid indicator");
+    TRY(gcsi_scratch(ctx));
+    const double gt = b.gamma * prm->tau;
+    for (int j = 0; j < ctx->nlev; ++j) {
+        Level& L = ctx->lv[j];
+        const int64_t n = L.nc * 27;
+        if (!L.d_gcsi_eta) TRY(dalloc(ctx, &L.d_gcsi_eta, n));
+        launch_gcsi_coefficients(solid_q[j], prm->rho_f / gt, prm->rho_s / gt, prm->eta_f, gt * prm->mu_s,
+                                 ctx->gcsi_tmp, L.d_gcsi_eta, n, ctx->stream);
+        TRY(fsi_set_coefficients(h, j, ctx->gcsi_tmp, L.d_gcsi_eta));
+    }
+    ctx->gcsi_rho_f = prm->rho_f;
+    return FSI_OK;
+}
+
+fsi_status fsi_gcsi_rhs(fsi_ctx* h, const fsi_gcsi_params* prm, int mode, const uint8_t* solid_q,
+                        const double* disp, const double* u_hash, const double* u1, const double* u2,
+                        const double* v1, const double* v2, const double* w1, const double* w2, double* g_u,
+                        double* g_p) {
+    if (!h || !solid_q || !disp || !u_hash || !u1 || !v1 || !g_u || !g_p) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    Bdf b;
+    TRY(gcsi_check(ctx, prm, &b));
+    if (mode != FSI_GCSI_PREDICTOR && mode != FSI_GCSI_CORRECTOR) return fail(ctx, FSI_ERR_ARG, "mode must be P or C");
+    const bool k2 = prm->k == 2, pred = mode == FSI_GCSI_PREDICTOR;
+    if (k2 && (!u2 || !v2)) return fail(ctx, FSI_ERR_ARG, "k = 2 needs the fields at n-2");
+    if (pred && (!w1 || (k2 && !w2))) return fail(ctx, FSI_ERR_ARG, "the predictor needs the mesh velocities");
+    const Level& F = ctx->lv[ctx->nlev - 1];
+    GcsiRhsArgs a{};
+    a.nx = F.cells[0];
+    a.ny = F.cells[1];
+    a.nz = F.cells[2];
+    a.vnx = F.vnodes[0];
+    a.vny = F.vnodes[1];
+    a.pnx = F.pnodes[0];
+    a.pny = F.pnodes[1];
+    a.nvn = F.nvn;
+    a.nvert = F.nvert;
+    for (int d = 0; d < 3; ++d) a.h[d] = F.h[d];
+    a.disp = disp;
+    a.solid = solid_q;
+    a.wall = F.d_wall;
+    a.uh = u_hash;
+    a.u1 = u1;
+    a.u2 = k2 ? u2 : nullptr;
+    a.v1 = v1;
+    a.v2 = k2 ? v2 : nullptr;
+    a.w1 = pred ? w1 : nullptr;
+    a.w2 = (pred && k2) ? w2 : nullptr;
+    a.a1 = b.a1;
+    a.a2 = b.a2;
+    a.gt = b.gamma * prm->tau;
+    a.rho_f = prm->rho_f;
+    a.rho_s = prm->rho_s;
+    a.mu_s = prm->mu_s;
+    a.inv_etaV = (prm->eta_V > 0 && std::isfinite(prm->eta_V)) ? 1.0 / prm->eta_V : 0.0;
+    for (int d = 0; d < 3; ++d) a.body[d] = prm->body[d];
+    a.predictor = pred ? 1 : 0;
+    a.g_u = g_u;
+    a.g_p = g_p;
+    launch_fill<double>(g_u, 0.0, F.nv, ctx->stream);
+    launch_fill<double>(g_p, 0.0, F.np, ctx->stream);
+    launch_gcsi_rhs(a, F.nc, ctx->stream);
+    return FSI_OK;
+}
+
+fsi_status fsi_gcsi_set_convection(fsi_ctx* h, const fsi_gcsi_params* prm, const double* v_hash,
+                                   const double* w_hash) {
+    if (!h || !v_hash || !w_hash) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    Bdf b;
+    TRY(gcsi_check(ctx, prm, &b));
+    const int J = ctx->nlev - 1;
+    for (int j = 0; j <= J; ++j)
+        if (!ctx->lv[j].d_gcsi_eta || !ctx->lv[j].coef_set)
+            return fail(ctx, FSI_ERR_STATE, "fsi_gcsi_set_convection before fsi_gcsi_set_coefficients");
+    TRY(gcsi_scratch(ctx));
+    const Level& F = ctx->lv[J];
+    for (int j = 0; j <= J; ++j) {
+        const Level& L = ctx->lv[j];
+        double* vconv = ctx->gcsi_tmp;
+        double* r = vconv + 3 * L.nc * 27;
+        launch_gcsi_convection(L, F, v_hash, w_hash, L.d_gcsi_eta, 1 << (J - j), vconv, r, ctx->stream);
+        TRY(fsi_set_convection(h, j, vconv, r, prm->rho_f));
+    }
+    return FSI_OK;
+}
+
 fsi_status fsi_autotune(fsi_ctx* h) {
     if (!h) return FSI_ERR_ARG;
     Context* ctx = &h->c;
@@ -1686,7 +1900,7 @@ fsi_status fsi_autotune(fsi_ctx* h) {
             for (int m : unfused) {
                 const size_t k = (size_t)j * kTuneClasses + tune_class(m);
                 ctx->atom[pi][k] = -1;
-                if (ctx->lv[j].dim != 3) continue;
+                if (ctx->lv[j].dim != 3 || ctx->has_fixed) continue;
                 double best = ctx->tune_us[pi][k];
                 for (int shape = 0; shape < kAtomShapes; ++shape) {
                     const int reps = 3;
@@ -1844,6 +2058,8 @@ fsi_status fsi_set_tuning(fsi_ctx* h, int level, int precision, int variant) {
     const bool atomic = variant >= kNumVariants;
     if (atomic && ctx->lv[level].dim != 3)
         return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: the single atomic launch is 3D only");
+    if (atomic && ctx->has_fixed)
+        return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: no single atomic launch with fixed cells");
     for (int c = 0; c < kTuneClasses; ++c)
         ctx->tune_variant[precision][(size_t)level * kTuneClasses + c] = atomic ? 0 : variant;
     for (int c = 0; c < kTuneClasses; ++c)

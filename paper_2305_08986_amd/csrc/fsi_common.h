@@ -117,6 +117,10 @@ struct Level {
     int* d_dir_nodes = nullptr;    // wall nodes
     int64_t n_dir = 0;
     std::vector<uint8_t> h_dir_node;   // [nvn] host copy of the wall mask
+    // fsi_set_fixed_cells: nodes of fixed cells (finest level; also in the wall mask)
+    uint8_t* d_fixed = nullptr;
+    // fsi_gcsi_set_coefficients: the viscosity per point ([nc][Q]) for the streamline law
+    double* d_gcsi_eta = nullptr;
 
     // geometry and coefficients, internal layout [plane][qx][chunk][slot] (GeoLayout)
     double* d_K64 = nullptr;       // 9 (or 4) planes: det(J) w_q J^{-1}, entry (b,a) in plane b*dim+a
@@ -271,6 +275,14 @@ struct Context {
     // device address of the file-scope pressure staging array of the allocation-free
     // FP32 Stokes apply on this context's device (resolved at create; null if that failed)
     double* noalloc_scratch = nullptr;
+    // fsi_set_fixed_cells was called: interior Dirichlet nodes, so no single atomic launch
+    // (it derives the wall rows from the faces)
+    bool has_fixed = false;
+    // the block coarse matrix could be inverted (false only with fixed cells)
+    bool coarse_block_ok = true;
+    // time-step scratch: [n_cells][27] x 4 doubles of the finest level
+    double* gcsi_tmp = nullptr;
+    double gcsi_rho_f = -1.0;   // fluid density of the last fsi_gcsi_set_coefficients
 };
 
 // ---------------------------------------------------------------- launchers (kernels_*.hip)
@@ -424,5 +436,36 @@ void launch_sub_into(const double* g, const double* mx, double* r, int64_t n, hi
 void launch_recip(const double* a, double* b, int64_t n, hipStream_t s);
 
 constexpr int kReduceBlocks = 1024;
+
+// ---------------------------------------------------------------- time step (kernels_gcsi.hip)
+// u_out = gt w - a1 u1 - a2 u2 (velocity dofs; u2 may be null) and its values at the
+// vertices, [dim][n_vert] (either output may be null)
+void launch_gcsi_displacement(const Level& L, const double* w, const double* u1, const double* u2, double gt, double a1,
+                              double a2, double* u_out, double* disp_out, hipStream_t s);
+// c_m and eta per point from the solid indicator
+void launch_gcsi_coefficients(const uint8_t* solid, double cm_f, double cm_s, double eta_f, double eta_s, double* cm,
+                              double* eta, int64_t n, hipStream_t s);
+// g = v on the fixed nodes, 0 elsewhere
+void launch_fixed_values(const Level& L, const uint8_t* fixed, const double* v, double* g, hipStream_t s);
+struct GcsiRhsArgs {
+    int nx, ny, nz, vnx, vny, pnx, pny;
+    int64_t nvn, nvert;
+    double h[3];
+    const double* disp;                   // [3][n_vert] vertex displacement of the explicit geometry
+    const uint8_t* solid;                 // [n_cells][27]
+    const uint8_t* wall;                  // [n_vel_nodes] Dirichlet rows (left zero)
+    const double *uh, *u1, *u2, *v1, *v2, *w1, *w2;
+    double a1, a2, gt;                    // BDF alpha_1, alpha_2 and gamma tau
+    double rho_f, rho_s, mu_s, inv_etaV;  // inv_etaV = 0: no volume correction
+    double body[3];
+    int predictor;
+    double* g_u;                          // zeroed, accumulated with atomics
+    double* g_p;
+};
+void launch_gcsi_rhs(const GcsiRhsArgs& a, int64_t nc, hipStream_t s);
+// v° = v# - w# at the Gauss points of level L ([n_cells][27][3]) and the streamline
+// parameter ([n_cells][27]); the fine-level fields are read at L's nodes (stride)
+void launch_gcsi_convection(const Level& L, const Level& F, const double* vh, const double* wh, const double* eta,
+                            int stride, double* vconv, double* r, hipStream_t s);
 
 }  // namespace fsi

@@ -61,6 +61,20 @@ class LevelInfo(C.Structure):
                 ("diagA_norm2", C.c_double), ("diagS_norm2", C.c_double), ("coarse_n", C.c_int64)]
 
 
+class GcsiParams(C.Structure):
+    _fields_ = [("k", C.c_int), ("tau", C.c_double), ("rho_f", C.c_double), ("rho_s", C.c_double),
+                ("eta_f", C.c_double), ("mu_s", C.c_double), ("eta_V", C.c_double), ("body", C.c_double * 3)]
+
+    @classmethod
+    def of(cls, k=2, tau=0.005, rho_f=1e3, rho_s=1e4, eta_f=1.0, mu_s=5e5, eta_V=0.1, body=(0.0, 0.0, 0.0)):
+        return cls(k=k, tau=tau, rho_f=rho_f, rho_s=rho_s, eta_f=eta_f, mu_s=mu_s, eta_V=eta_V,
+                   body=(C.c_double * 3)(*body))
+
+
+GCSI_PREDICTOR = 0
+GCSI_CORRECTOR = 1
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int), ("reorth", C.c_int)]
 
@@ -118,6 +132,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fsi_get_tuning": (i, [vp, i, i, C.POINTER(i), C.POINTER(d)]),
         "fsi_set_tuning": (i, [vp, i, i, i]),
         "fsi_time_operator": (i, [vp, i, i, i, i, C.POINTER(d), C.POINTER(d), C.POINTER(i)]),
+        "fsi_set_fixed_cells": (i, [vp, vp]),
+        "fsi_fixed_values": (i, [vp, vp, vp]),
+        "fsi_gcsi_displacement": (i, [vp, C.POINTER(GcsiParams), vp, vp, vp, vp, vp]),
+        "fsi_gcsi_set_coefficients": (i, [vp, C.POINTER(GcsiParams), C.POINTER(vp)]),
+        "fsi_gcsi_rhs": (i, [vp, C.POINTER(GcsiParams), i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "fsi_gcsi_set_convection": (i, [vp, C.POINTER(GcsiParams), vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -131,6 +151,11 @@ class FSIError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
         self.status = status
+
+
+def _vp(t):
+    """c_void_p of a tensor's data, or NULL for None."""
+    return C.c_void_p(None if t is None else _ptr(t))
 
 
 def _ptr(t) -> int:
@@ -359,6 +384,38 @@ class Context:
         out = dict(status=STATUS_NAMES[st], iters=info.iters, rel_res=info.final_rel_res, time_ms=info.time_ms,
                    history=[hist[k] for k in range(info.n_hist)])
         return u, out
+
+    # ---------------------------------------------------------------- time step (Algorithm 1)
+    def set_fixed_cells(self, fixed):
+        """Fix every node of the flagged finest-level cells (fsi_set_fixed_cells; host uint8)."""
+        import numpy as np
+        f = np.ascontiguousarray(np.asarray(fixed, dtype=np.uint8))
+        self._check(self.lib.fsi_set_fixed_cells(self.h, f.ctypes.data_as(C.c_void_p)))
+
+    def fixed_values(self, v, out):
+        self._check(self.lib.fsi_fixed_values(self.h, C.c_void_p(_ptr(v)), C.c_void_p(_ptr(out))))
+        return out
+
+    def gcsi_displacement(self, prm: GcsiParams, w, u1, u2=None, out=None, disp=None):
+        self._check(self.lib.fsi_gcsi_displacement(self.h, C.byref(prm), C.c_void_p(_ptr(w)), C.c_void_p(_ptr(u1)),
+                                                   _vp(u2), _vp(out), _vp(disp)))
+        return out, disp
+
+    def gcsi_set_coefficients(self, prm: GcsiParams, solid_q):
+        """solid_q: per level, a device uint8 tensor [n_cells][27]."""
+        arr = (C.c_void_p * len(solid_q))(*[_ptr(x) for x in solid_q])
+        self._check(self.lib.fsi_gcsi_set_coefficients(self.h, C.byref(prm), arr))
+
+    def gcsi_rhs(self, prm: GcsiParams, mode: int, solid_q, disp, u_hash, u1, u2, v1, v2, w1, w2, g_u, g_p):
+        self._check(self.lib.fsi_gcsi_rhs(self.h, C.byref(prm), mode, C.c_void_p(_ptr(solid_q)),
+                                          C.c_void_p(_ptr(disp)), C.c_void_p(_ptr(u_hash)), _vp(u1), _vp(u2),
+                                          _vp(v1), _vp(v2), _vp(w1), _vp(w2), C.c_void_p(_ptr(g_u)),
+                                          C.c_void_p(_ptr(g_p))))
+        return g_u, g_p
+
+    def gcsi_set_convection(self, prm: GcsiParams, v_hash, w_hash):
+        self._check(self.lib.fsi_gcsi_set_convection(self.h, C.byref(prm), C.c_void_p(_ptr(v_hash)),
+                                                     C.c_void_p(_ptr(w_hash))))
 
     def raw_status(self, name: str, *args) -> int:
         """Call a C entry point and return its status without raising (error-path tests)."""

@@ -435,9 +435,9 @@ def random_vector(n: int, seed_key) -> np.ndarray:
 # moves with the solid).
 GCSI_STREAM = 11
 GCSI_CONFIGS = {
-    "G1": dict(n=(16, 4, 4), n_coarse=(4, 1, 1)),
-    "G2": dict(n=(128, 32, 32), n_coarse=(4, 1, 1)),
-    "G3": dict(n=(256, 64, 64), n_coarse=(4, 1, 1)),
+    "G1": dict(n=(16, 4, 4), n_coarse=(8, 2, 2)),
+    "G2": dict(n=(128, 32, 32), n_coarse=(8, 2, 2)),
+    "G3": dict(n=(256, 64, 64), n_coarse=(8, 2, 2)),
 }
 GCSI_EXTENT = (2.0, 0.5, 0.5)
 GCSI_STRIP = ((0.5, 1.25), (0.125, 0.25), (0.0, 0.5))

@@ -1,0 +1,203 @@
+"""GPU parity of one GCSI_k(M_1, .., M_S) time step (Algorithm 1, Sec. 3.1.1) on the
+channel-with-strip case G1 (16 x 4 x 4 cells, two levels) against the oracle's step
+(oracle/gcsi.py: assembled operators, direct solves).
+
+* the explicit displacement and its vertex values (rounding of one BDF combination);
+* the right-hand sides g_vM and g_p of both modes, componentwise against the sum of
+  magnitudes of every quadrature term: |g - g*|_i <= 64 u (|terms|)_i;
+* the corrector-mode operator built from v# and w# (convective velocity at the Gauss
+  points and the Peclet law on the finest and the next level), componentwise;
+* the extension with the solid's cells fixed, against the direct solve;
+* whole GCSI_2(P, C) and GCSI_1(P) steps, FP64 and mixed-precision V-cycles, against
+  the oracle's step: every stage's velocity, mesh velocity and pressure and the
+  recovered displacement.
+"""
+import numpy as np
+import pytest
+
+from oracle import fem
+from oracle import gcsi as og
+from paper_2305_08986_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+C_BOUND = 64
+
+
+def _dev(x, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(x), device="cuda", dtype=dtype or torch.float64).contiguous()
+
+
+@pytest.fixture(scope="module")
+def case():
+    g = W.make_gcsi_inputs("G1")
+    J = g.mesh.n_levels - 1
+    ref = fem.Reference(3)
+    pb = og.Problem(box=fem.level_box(g.mesh, J), ext_box=fem.level_box(g.ext_mesh, J),
+                    solid_q=g.solid_q[J].astype(bool), solid_cells=g.solid_cells.astype(bool), mu_A=g.mu_A[J],
+                    prm=og.Params(**g.material))
+    st = og.State(u=g.u, v=g.v, w=g.w, p=g.p)
+    out = og.step(pb, st, ("P", "C"), ref)
+    return g, pb, st, ref, out
+
+
+def _within(got, want, scale, what):
+    err = np.abs(got - want)
+    bound = C_BOUND * U64 * scale
+    bad = err > bound
+    worst = float(np.max(err / np.maximum(scale * U64, 1e-300)))
+    print(f"{what}: worst |err| / (u scale) = {worst:.1f}")
+    assert not np.any(bad), (what, int(bad.sum()), worst)
+
+
+def _ctx(mesh):
+    from paper_2305_08986_amd import fsi
+    return fsi, fsi.Context.from_mesh(mesh)
+
+
+def test_explicit_displacement_and_vertex_values(case):
+    g, pb, st, ref, out = case
+    fsi, ctx = _ctx(g.mesh)
+    prm = fsi.GcsiParams.of(**g.material)
+    J = g.mesh.n_levels - 1
+    nvert = ctx.sizes(J)["n_vert"]
+    u_out = torch.empty(pb.box.n_vel, device="cuda", dtype=torch.float64)
+    disp = torch.empty(3 * nvert, device="cuda", dtype=torch.float64)
+    ctx.gcsi_displacement(prm, _dev(g.w[0]), _dev(g.u[0]), _dev(g.u[1]), out=u_out, disp=disp)
+    torch.cuda.synchronize()
+    want = og.explicit_displacement(pb.prm, g.w[0], g.u)
+    scale = pb.prm.gamma * pb.prm.tau * np.abs(g.w[0]) + sum(abs(a) * np.abs(x) for a, x in zip(pb.prm.alpha, g.u))
+    _within(u_out.cpu().numpy(), want, scale, "u#")
+    assert np.array_equal(disp.cpu().numpy().reshape(3, -1), og.vertex_values(pb.box, u_out.cpu().numpy()))
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", ["P", "C"])
+def test_right_hand_side_matches_oracle(case, mode):
+    g, pb, st, ref, out = case
+    fsi, ctx = _ctx(g.mesh)
+    prm = fsi.GcsiParams.of(**g.material)
+    J = g.mesh.n_levels - 1
+    uh = out["stages"][0 if mode == "P" else 1]["u_hash"]
+    disp = og.vertex_values(pb.box, uh)
+    want_u, want_p = og.rhs(pb.box, ref, pb.prm, mode, pb.solid_q, disp, uh, st)
+    abs_u, abs_p = og.rhs(pb.box, ref, pb.prm, mode, pb.solid_q, disp, uh, st, absolute=True)
+    g_u = torch.full((pb.box.n_vel,), np.nan, device="cuda", dtype=torch.float64)
+    g_p = torch.full((pb.box.n_p,), np.nan, device="cuda", dtype=torch.float64)
+    f = [_dev(x) for x in (g.u[0], g.u[1], g.v[0], g.v[1], g.w[0], g.w[1])]
+    ctx.gcsi_rhs(prm, fsi.GCSI_PREDICTOR if mode == "P" else fsi.GCSI_CORRECTOR,
+                 _dev(g.solid_q[J], torch.uint8), _dev(disp.ravel()), _dev(uh), *f, g_u, g_p)
+    torch.cuda.synchronize()
+    assert np.abs(want_p).max() > 0 and np.abs(want_u).max() > 0
+    _within(g_u.cpu().numpy(), want_u, abs_u, f"g_u ({mode})")
+    _within(g_p.cpu().numpy(), want_p, abs_p, f"g_p ({mode})")
+    ctx.close()
+
+
+def _inject(mesh, f, level):
+    """Nodal values of a fine Q2 field at the nodes of ``level`` (same positions)."""
+    J = mesh.n_levels - 1
+    s = 1 << (J - level)
+    nn = mesh.vel_nodes(J)
+    return np.ascontiguousarray(f.reshape(3, nn[2], nn[1], nn[0])[:, ::s, ::s, ::s].reshape(-1))
+
+
+def test_corrector_operator_from_the_step_fields_matches_oracle(case):
+    g, pb, st, ref, out = case
+    fsi, ctx = _ctx(g.mesh)
+    prm = fsi.GcsiParams.of(**g.material)
+    J = g.mesh.n_levels - 1
+    uh = out["stages"][1]["u_hash"]
+    vh, wh = out["stages"][0]["v"], out["stages"][0]["w"]
+    disp = og.vertex_values(pb.box, uh)
+    ctx.set_displacement(disp.ravel())
+    ctx.gcsi_set_coefficients(prm, [_dev(x, torch.uint8) for x in g.solid_q])
+    ctx.gcsi_set_convection(prm, _dev(vh), _dev(wh))
+    rng = np.random.default_rng(17)
+    for j in (J, J - 1):
+        box = fem.level_box(g.mesh, j)
+        dj = W.inject_displacement(g.mesh, disp, j)
+        Jq = fem.jacobians_q1(box, dj, ref)
+        cm, eta = og.coefficients(pb.prm, g.solid_q[j].astype(bool))
+        vq, r = og.convection_inputs(box, ref, _inject(g.mesh, vh, j), _inject(g.mesh, wh, j), eta)
+        op = fem.assemble(box, Jq, cm, eta, ref)
+        A = op.A + fem.assemble_convection(box, Jq, vq, pb.prm.rho_f, r, ref)
+        opa = fem.assemble(box, Jq, cm, eta, ref, absolute=True)
+        Aa = opa.A + fem.assemble_convection(box, Jq, vq, pb.prm.rho_f, r, ref, absolute=True)
+        x = rng.uniform(-1, 1, box.n_vel)
+        x[op.dir_mask] = rng.uniform(-1, 1, int(op.dir_mask.sum()))
+        y = rng.uniform(-1, 1, box.n_p)
+        v, q = ctx.apply_corrector(j, _dev(x), _dev(y))
+        torch.cuda.synchronize()
+        _within(v.cpu().numpy(), A @ x + op.B.T @ y, Aa @ np.abs(x) + np.abs(opa.B.T) @ np.abs(y), f"(A+N+S) x level {j}")
+        _within(q.cpu().numpy(), op.B @ x, np.abs(opa.B) @ np.abs(x), f"B x level {j}")
+    ctx.close()
+
+
+def test_extension_with_fixed_solid_cells_matches_direct_solve(case):
+    g, pb, st, ref, out = case
+    fsi, ctx = _ctx(g.ext_mesh)
+    J = g.mesh.n_levels - 1
+    ctx.set_fixed_cells(g.solid_cells)
+    ctx.set_displacement(np.zeros(3 * ctx.sizes(J)["n_vert"]))
+    for j in range(ctx.n_levels):
+        ctx.set_coefficients(j, np.zeros_like(g.mu_A[j]), 0.5 * g.mu_A[j])
+    ctx.setup()
+    v = np.random.default_rng(5).uniform(-1, 1, pb.box.n_vel)
+    gv = torch.empty(pb.box.n_vel, device="cuda", dtype=torch.float64)
+    ctx.fixed_values(_dev(v), gv)
+    w, info = ctx.solve_extension(gv, rtol=1e-12, max_iter=300)
+    torch.cuda.synchronize()
+    want = og.extension(pb.ext_box, ref, pb.mu_A, v, og.fixed_nodes(pb.ext_box, pb.solid_cells))
+    got = w.cpu().numpy()
+    print("extension", info["iters"], info["rel_res"])
+    assert info["status"] == "OK"
+    fixed = np.tile(og.fixed_nodes(pb.ext_box, pb.solid_cells), 3)
+    assert np.array_equal(got[fixed], v[fixed])
+    assert np.linalg.norm(got - want) <= 1e-9 * np.linalg.norm(want)
+    ctx.close()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_gcsi2_pc_step_matches_oracle_step(case, precision):
+    g, pb, st, ref, out = case
+    from paper_2305_08986_amd import gcsi
+    S = gcsi.Stepper(g, precision=precision)
+    res = S.step([_dev(x) for x in g.u], [_dev(x) for x in g.v], [_dev(x) for x in g.w], _dev(g.p),
+                 ("P", "C"), rtol=1e-12, ext_rtol=1e-12)
+    for k, rec in enumerate(res["stages"]):
+        print({a: b for a, b in rec.items() if a != "u_hash"})
+        assert rec["status"] == "OK" and rec["ext_status"] == "OK"
+    # per stage: the predictor's fields set the corrector's geometry and convection
+    for k, (mode, want) in enumerate(zip(("P", "C"), out["stages"])):
+        rec = res["stages"][k]
+        assert _rel(rec["u_hash"].cpu().numpy(), want["u_hash"]) <= 1e-9, mode
+    errs = {key: _rel(res[key].cpu().numpy(), out[key]) for key in ("u", "v", "w", "p")}
+    print("relative max-norm differences", errs)
+    for key, e in errs.items():
+        assert e <= 1e-8, (key, e)
+    S.close()
+
+
+def test_gcsi1_predictor_step_matches_oracle_step(case):
+    g, pb, st, ref, _ = case
+    from paper_2305_08986_amd import gcsi
+    mat = dict(g.material, k=1)
+    pb1 = og.Problem(box=pb.box, ext_box=pb.ext_box, solid_q=pb.solid_q, solid_cells=pb.solid_cells, mu_A=pb.mu_A,
+                     prm=og.Params(**mat))
+    st1 = og.State(u=g.u[:1], v=g.v[:1], w=g.w[:1], p=g.p)
+    want = og.step(pb1, st1, ("P",), ref)
+    g1 = W.GcsiInputs(**{**g.__dict__, "material": mat})
+    S = gcsi.Stepper(g1)
+    res = S.step([_dev(g.u[0])], [_dev(g.v[0])], [_dev(g.w[0])], _dev(g.p), ("P",), rtol=1e-12, ext_rtol=1e-12)
+    errs = {key: _rel(res[key].cpu().numpy(), want[key]) for key in ("u", "v", "w", "p")}
+    print("GCSI_1(P)", errs)
+    for key, e in errs.items():
+        assert e <= 1e-8, (key, e)
+    S.close()
