@@ -201,3 +201,39 @@ def test_gcsi1_predictor_step_matches_oracle_step(case):
     for key, e in errs.items():
         assert e <= 1e-8, (key, e)
     S.close()
+
+
+def test_gcsi2_step_at_128x32x32_converges_and_keeps_its_invariants():
+    """At the measured size (the oracle's direct solves do not reach it): every stage
+    converges, the mesh velocity equals the velocity on the solid's nodes and vanishes on
+    the other walls, no-slip rows stay zero, the displacement is the recovery formula of
+    the final mesh velocity, and the mixed-precision step agrees with the FP64 one."""
+    from paper_2305_08986_amd import gcsi
+    g = W.make_gcsi_inputs("G2")
+    J = g.mesh.n_levels - 1
+    args = ([_dev(x) for x in g.u], [_dev(x) for x in g.v], [_dev(x) for x in g.w], _dev(g.p))
+    res = {}
+    for label, prec in (("fp64", 0), ("mixed", 1)):
+        S = gcsi.Stepper(g, precision=prec, autotune=True)
+        res[label] = S.step(*args, rtol=1e-10, ext_rtol=1e-10)
+        S.close()
+        for rec in res[label]["stages"]:
+            print(label, {a: b for a, b in rec.items() if a != "u_hash"})
+            assert rec["status"] == "OK" and rec["ext_status"] == "OK", rec
+            assert rec["rel_res"] <= 1e-10 and rec["ext_rel_res"] <= 1e-10
+    box, ebox = fem.level_box(g.mesh, J), fem.level_box(g.ext_mesh, J)
+    fixed = np.tile(og.fixed_nodes(ebox, g.solid_cells.astype(bool)), 3)
+    prm = og.Params(**g.material)
+    for label, r in res.items():
+        v, w, u = (r[k].cpu().numpy() for k in ("v", "w", "u"))
+        assert np.array_equal(w[fixed], v[fixed]), label
+        assert not np.any(w[ebox.dirichlet_vel_dofs() & ~fixed]), label
+        assert not np.any(v[box.dirichlet_vel_dofs()]), label
+        want = og.explicit_displacement(prm, w, g.u)
+        scale = prm.gamma * prm.tau * np.abs(w) + sum(abs(a) * np.abs(x) for a, x in zip(prm.alpha, g.u))
+        _within(u, want, scale, f"u^n ({label})")
+    for key in ("v", "w", "u", "p"):
+        a, b = res["mixed"][key].cpu().numpy(), res["fp64"][key].cpu().numpy()
+        e = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        print("mixed vs fp64", key, e)
+        assert e <= 1e-7, (key, e)
