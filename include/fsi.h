@@ -368,8 +368,9 @@ fsi_status fsi_gcsi_set_convection(fsi_ctx* ctx, const fsi_gcsi_params* prm, con
  * (A, A with the fused Chebyshev step, Stokes, Stokes with the fused residual,
  * B, B^T), level and precision, and keeps the fastest of each; then, per 3D level,
  * the phased launches of the unfused applies against their single atomic launch
- * (variants 16 .. 20 below), and the fused epilogues against the separate vector
- * kernels.  Synchronises; fsi_get_tuning reports the choice for A (16 .. 20 where the
+ * (variants 16 .. 20 below), on levels where the corrector terms are set
+ * (fsi_set_convection) the same choice for the corrector classes (A + N + S alone and in
+ * the Stokes apply), and the fused epilogues against the separate vector kernels.  Synchronises; fsi_get_tuning reports the choice for A (16 .. 20 where the
  * atomic launch was chosen) and its measured time per application in best_us. */
 fsi_status fsi_autotune(fsi_ctx* ctx);
 fsi_status fsi_get_tuning(const fsi_ctx* ctx, int level, int precision, int* variant, double* best_us);
@@ -384,7 +385,7 @@ fsi_status fsi_get_tuning(const fsi_ctx* ctx, int level, int precision, int* var
  * atomics and writes the wall rows itself: one (16) or four (17) wavefronts per row,
  * one wavefront over two (18) or four (19) rows along z, four wavefronts over two rows
  * along z (20), where the node plane two rows of a group share is summed in registers
- * and stored once; results then vary in the last bits from run to run; the fused
+ * and stored once (also for the corrector classes); results then vary in the last bits from run to run; the fused
  * epilogues keep variant 0.  fsi_autotune picks this form for a level where it
  * measures it faster.  Errors: FSI_ERR_ARG. */
 fsi_status fsi_set_tuning(fsi_ctx* ctx, int level, int precision, int variant);

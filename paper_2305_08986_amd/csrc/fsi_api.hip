@@ -329,8 +329,10 @@ static void op_apply(Context* ctx, int j, int mode, const T* u, const double* p,
     // every output entry is written by its first touching cell (no clearing pass);
     // wall rows: identity for A, zero for B^T alone
     const Level& L = ctx->lv[j];
-    const int am = (ctx->prm.tuned && ctx->prm.atomics) ? ctx->atom_of(prec_index<T>(), j, mode & ~OP_CONV) : -1;
-    if (am >= 0 && L.dim == 3 && !(mode & OP_CONV)) {
+    const int am = !(ctx->prm.tuned && ctx->prm.atomics) ? -1
+                   : (mode & OP_CONV) ? ctx->atom_conv[prec_index<T>()][(size_t)j]
+                                      : ctx->atom_of(prec_index<T>(), j, mode);
+    if (am >= 0 && L.dim == 3) {
         launch_cell_atomic<T>(L, mode, am, Kmode<T>(L, mode), CVp<T>(L), u, p, v, q, s);   // wall rows included
         return;
     }
@@ -967,6 +969,7 @@ fsi_status fsi_create(fsi_ctx** out, const fsi_mesh_desc* m, void* hip_stream) {
         ctx->fuse_cheb[pi].assign(ctx->nlev, 1);
         ctx->fuse_res[pi].assign(ctx->nlev, 1);
         ctx->atom[pi].assign((size_t)ctx->nlev * kTuneClasses, -1);
+        ctx->atom_conv[pi].assign((size_t)ctx->nlev, -1);
     }
     if (st != FSI_OK) {
         fsi_destroy(h);
@@ -1706,7 +1709,10 @@ fsi_status fsi_set_fixed_cells(fsi_ctx* h, const uint8_t* fixed) {
     }
     TRY(dalloc(ctx, &F.d_fixed, F.nvn));
     FSI_HIP_TRY(hipMemcpy(F.d_fixed, fm.data(), (size_t)F.nvn, hipMemcpyHostToDevice));
-    for (int pi = 0; pi < 2; ++pi) std::fill(ctx->atom[pi].begin(), ctx->atom[pi].end(), (int8_t)-1);
+    for (int pi = 0; pi < 2; ++pi) {
+        std::fill(ctx->atom[pi].begin(), ctx->atom[pi].end(), (int8_t)-1);
+        std::fill(ctx->atom_conv[pi].begin(), ctx->atom_conv[pi].end(), (int8_t)-1);
+    }
     ctx->has_fixed = true;
     return FSI_OK;
 }
@@ -1923,6 +1929,40 @@ fsi_status fsi_autotune(fsi_ctx* h) {
                 }
                 ctx->tune_us[pi][k] = best;   // the time of the chosen form
             }
+    // the corrector terms (A + N + S, alone and in the Stokes apply) on levels where they are
+    // set: phased launches of the tuned variant against the single atomic launch
+    for (int pi = 0; pi < 2; ++pi)
+        for (int j = 0; j < ctx->nlev; ++j) {
+            ctx->atom_conv[pi][(size_t)j] = -1;
+            const Level& L = ctx->lv[j];
+            if (L.dim != 3 || ctx->has_fixed || !L.conv_set) continue;
+            const int m = OP_A | OP_CONV;
+            double best = 1e300;
+            for (int shape = -1; shape < kAtomShapes; ++shape) {
+                const int reps = 3;
+                for (int r = 0; r <= reps; ++r) {
+                    if (r == 1) FSI_HIP_TRY(hipEventRecord(e0, s));
+                    if (shape < 0) {
+                        for (int ph = 0; ph < L.nphases(); ++ph)
+                            launch_phase_on_work(ctx, pi, j, m, variant_of(ctx, pi, j, m), ph, s);
+                    } else {
+                        launch_atomic_on_work(ctx, pi, j, m, shape, s);
+                    }
+                }
+                FSI_HIP_TRY(hipEventRecord(e1, s));
+                FSI_HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0;
+                FSI_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                const double us = 1000.0 * ms / reps;
+                if (getenv("FSI_TUNE_VERBOSE"))
+                    fprintf(stderr, "[fsi autotune] precision %d level %d corrector A: %.1f us (%s %d)\n", pi, j, us,
+                            shape < 0 ? "phased" : "atomic shape", shape);
+                if (us < best) {
+                    best = us;
+                    ctx->atom_conv[pi][(size_t)j] = (int8_t)shape;
+                }
+            }
+        }
     // fused epilogues against operator + separate vector kernel, each with its tuned variant
     auto timed = [&](auto&& body, double* us) -> fsi_status {
         body();
@@ -2064,6 +2104,7 @@ fsi_status fsi_set_tuning(fsi_ctx* h, int level, int precision, int variant) {
         ctx->tune_variant[precision][(size_t)level * kTuneClasses + c] = atomic ? 0 : variant;
     for (int c = 0; c < kTuneClasses; ++c)
         ctx->atom[precision][(size_t)level * kTuneClasses + c] = atomic ? (int8_t)(variant - kNumVariants) : (int8_t)-1;
+    ctx->atom_conv[precision][(size_t)level] = atomic ? (int8_t)(variant - kNumVariants) : (int8_t)-1;
     if (ctx->setup_done) TRY(capture_graphs(ctx));   // captured graphs hold the old launch shapes
     return FSI_OK;
 }

@@ -268,6 +268,9 @@ struct Context {
     // class, where the autotuner measured it faster (results then vary in the last
     // bits from run to run)
     std::vector<int8_t> atom[2];
+    // per level and precision: the same choice for the corrector classes (A + N + S, alone
+    // and in the Stokes apply), measured by fsi_autotune where the terms are set
+    std::vector<int8_t> atom_conv[2];
     int atom_of(int prec, int level, int mode) const {
         return atom[prec][(size_t)level * kTuneClasses + tune_class(mode)];
     }

@@ -138,9 +138,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     constexpr bool CONV = (MODE & OP_CONV) != 0;
     // every phase in one launch: each touch adds atomically (outputs zeroed beforehand)
     constexpr bool ATOM = (MODE & OP_ATOM) != 0;
-    static_assert(!ATOM || !(CHEB || RES || CONV), "the atomic form has no epilogue and no corrector terms");
+    static_assert(!ATOM || !(CHEB || RES), "the atomic form has no epilogue");
     static_assert(!CHEB || MODE == (OP_A | OP_CHEB), "the Chebyshev epilogue goes with A alone");
-    static_assert(!CONV || (MODE == (OP_A | OP_CONV) || MODE == (OP_A | OP_BT | OP_B | OP_CONV)),
+    static_assert(!CONV || ((MODE & ~OP_ATOM) == (OP_A | OP_CONV) || (MODE & ~OP_ATOM) == (OP_A | OP_BT | OP_B | OP_CONV)),
                   "the corrector terms go with A or the Stokes apply");
     static_assert(!CONV || !VG, "the corrector terms use the stored geometry");
     static_assert(!RES || MODE == (OP_A | OP_BT | OP_B | OP_RES), "the residual epilogue goes with the Stokes apply");
@@ -1372,7 +1372,8 @@ void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T*
     for (int ph = 0; ph < L.nphases(); ++ph) launch_cell<T>(L, mode, variant, ph, K, cv, u, p, v, q, s);
 }
 
-// every phase in one launch (3D, modes A, B, B^T, A + B^T + B): one kernel zeroes the
+// every phase in one launch (3D, modes A, B, B^T, A + B^T + B, and A or the Stokes apply
+// with the corrector terms): one kernel zeroes the
 // outputs, then each cell adds its contributions atomically and the cell kernel writes
 // the wall rows itself (v = u when A is applied; B^T alone leaves them zero).  Shapes
 // (kAtomShapes): 0 one wavefront per row; 1 four wavefronts share a row; 2, 3 one
@@ -1407,7 +1408,7 @@ void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T
         // waves per SIMD the unfused classes reach: FP64 two (A, B, B^T), FP32 four; the
         // Stokes classes are left unconstrained
         constexpr bool STOKES = (M & OP_A) && (M & OP_BT);
-        constexpr int W0 = STOKES ? 1 : (sizeof(T) == 8 ? 2 : 4);
+        constexpr int W0 = (STOKES || (M & OP_CONV)) ? 1 : (sizeof(T) == 8 ? 2 : 4);
         switch (shape) {
             case 0: args.nrows = atom_slots<1>(L); launch_one<T, M, 1, true, W0, 1>(L, args, s); break;
             case 1: args.nrows = atom_slots<1>(L); launch_one<T, M, 4, true, W0, 1>(L, args, s); break;
@@ -1421,6 +1422,8 @@ void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T
         case OP_B: go(std::integral_constant<int, OP_B>{}); break;
         case OP_BT: go(std::integral_constant<int, OP_BT>{}); break;
         case OP_A | OP_BT: go(std::integral_constant<int, OP_A | OP_BT>{}); break;
+        case OP_A | OP_CONV: go(std::integral_constant<int, OP_A | OP_CONV>{}); break;
+        case OP_A | OP_BT | OP_B | OP_CONV: go(std::integral_constant<int, OP_A | OP_BT | OP_B | OP_CONV>{}); break;
         default: go(std::integral_constant<int, OP_A | OP_BT | OP_B>{}); break;
     }
 }

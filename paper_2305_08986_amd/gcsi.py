@@ -54,7 +54,7 @@ class Stepper:
         self.g_p = torch.empty(self.np, **dev)
         self.g_ext = torch.empty(self.nv, **dev)
         self.autotune = autotune
-        self._tuned = False
+        self._tuned = set()
 
     def close(self):
         self.stokes.close()
@@ -71,9 +71,9 @@ class Stepper:
         if corr:
             S.gcsi_set_convection(prm, v_hash, w_hash)
         S.setup()
-        if self.autotune and not self._tuned:
+        if self.autotune and mode not in self._tuned:   # the corrector classes are tuned once their terms are set
             S.autotune()
-            self._tuned = True
+            self._tuned.add(mode)
         S.gcsi_rhs(prm, fsi.GCSI_CORRECTOR if corr else fsi.GCSI_PREDICTOR, self.solid_q[self.J], self.disp,
                    self.u_hash, u1, u2, v1, v2, w1, w2, self.g_u, self.g_p)
         v, p = v0.clone(), p0.clone()

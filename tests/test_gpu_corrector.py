@@ -4,8 +4,8 @@ Sec. 3.1.1 and 3.2) against the assembled oracle, through the C ABI.
 FP64 within 1e-12 normwise and, entry by entry, within 64 u (sum_K |A_K + N_K + S_K|
 |x_K|)_i (u = 2^-53; the oracle's assembly of the absolute element matrices of the
 operator and of the corrector terms, applied to |x|); FP32 within 1e-5 normwise and
-the same componentwise bound with u = 2^-24; every launch variant gives bitwise the
-same result; 128^3 sampled rows in the autotuned launch shapes; error cases.
+the same componentwise bound with u = 2^-24; every phased launch variant gives bitwise
+the same result, the single atomic launch (every shape) the same within the bounds; 128^3 sampled rows in the autotuned launch shapes; error cases.
 """
 import ctypes as C
 
@@ -105,6 +105,31 @@ def test_corrector_every_launch_variant_same_result():
             base = got
         for g, b in zip(got, base):
             assert np.array_equal(g, b), var
+
+
+@pytest.mark.parametrize("name", ["T3_R", "T3_8"])
+def test_corrector_atomic_launch_matches_oracle(name):
+    """The single atomic launch over all phases with the corrector terms (every shape,
+    FP64 and FP32), alone and in the Stokes apply, within the componentwise bound."""
+    from paper_2305_08986_amd import fsi
+    wl, ctx, conv = _setup(name)
+    ctx.set_mg_params(tuned=1, atomics=1)
+    rng = np.random.default_rng(71)
+    for j in range(ctx.n_levels):
+        box = fem.level_box(wl.mesh, j)
+        u = rng.uniform(-1, 1, box.n_vel)
+        p = rng.uniform(-1, 1, box.n_p)
+        rv, rq, op, bv, bq = _oracle(wl, j, conv[j], u, p)
+        ud, pd = torch.from_numpy(u).cuda(), torch.from_numpy(p).cuda()
+        for var in fsi.ATOMIC_VARIANTS:
+            for prec in (0, 1):
+                ctx.set_tuning(j, prec, var)
+            v, q = ctx.apply_corrector(j, ud, pd)
+            _cmp(v, rv, 1e-12, f"{name} L{j} v atomic {var}", bv)
+            _cmp(q, rq, 1e-12, f"{name} L{j} q atomic {var}", bq)
+            v, q = ctx.apply_corrector(j, ud.float(), pd.float())
+            _cmp(v, rv, 1e-5, f"{name} L{j} v f32 atomic {var}", bv, U32)
+            _cmp(q, rq, 1e-5, f"{name} L{j} q f32 atomic {var}", bq, U32)
 
 
 def test_corrector_full_size_sampled_rows():
