@@ -45,7 +45,8 @@ def test_binding_covers_every_declared_symbol():
 def test_struct_layouts_match_c_header():
     from paper_2305_08986_amd import fsi
     structs = {"fsi_mesh_desc": fsi.MeshDesc, "fsi_sizes": fsi.Sizes, "fsi_mg_params": fsi.MGParams,
-               "fsi_level_info": fsi.LevelInfo, "fsi_solve_opts": fsi.SolveOpts, "fsi_solve_info": fsi.SolveInfo}
+               "fsi_level_info": fsi.LevelInfo, "fsi_solve_opts": fsi.SolveOpts, "fsi_solve_info": fsi.SolveInfo,
+               "fsi_gcsi_params": fsi.GcsiParams}
     src = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for cname, py in structs.items():
         src.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

@@ -237,3 +237,54 @@ def test_gcsi2_step_at_128x32x32_converges_and_keeps_its_invariants():
         e = float(np.linalg.norm(a - b) / np.linalg.norm(b))
         print("mixed vs fp64", key, e)
         assert e <= 1e-7, (key, e)
+
+
+def test_time_step_entry_points_reject_bad_input(case):
+    """Argument and state errors of the time-step and fixed-cell entry points (host-side
+    checks; no kernel sees a bad input)."""
+    import ctypes as C
+    g, pb, st, ref, out = case
+    fsi, ctx = _ctx(g.mesh)
+    prm = fsi.GcsiParams.of(**g.material)
+    z = torch.zeros(pb.box.n_vel, device="cuda", dtype=torch.float64)
+    zp = torch.zeros(pb.box.n_p, device="cuda", dtype=torch.float64)
+    sq = _dev(g.solid_q[-1], torch.uint8)
+    vp = lambda t: C.c_void_p(None if t is None else t.data_ptr())
+    for bad in (dict(k=3), dict(tau=0.0), dict(eta_f=0.0), dict(rho_s=-1.0), dict(mu_s=float("nan"))):
+        b = fsi.GcsiParams.of(**{**g.material, **bad})
+        assert ctx.raw_status("fsi_gcsi_displacement", C.byref(b), vp(z), vp(z), vp(z), vp(z), None) == fsi.FSI_ERR_ARG
+    # k = 2 needs u^{n-2}; at least one output
+    assert ctx.raw_status("fsi_gcsi_displacement", C.byref(prm), vp(z), vp(z), None, vp(z), None) == fsi.FSI_ERR_ARG
+    assert ctx.raw_status("fsi_gcsi_displacement", C.byref(prm), vp(z), vp(z), vp(z), None, None) == fsi.FSI_ERR_ARG
+    args = [vp(sq), vp(z), vp(z), vp(z), vp(z), vp(z), vp(z), vp(z), vp(z), vp(z), vp(zp)]
+    assert ctx.raw_status("fsi_gcsi_rhs", C.byref(prm), 7, *args) == fsi.FSI_ERR_ARG           # mode
+    bad = list(args)
+    bad[7] = C.c_void_p(None)                                                                    # w1
+    assert ctx.raw_status("fsi_gcsi_rhs", C.byref(prm), fsi.GCSI_PREDICTOR, *bad) == fsi.FSI_ERR_ARG
+    assert ctx.raw_status("fsi_gcsi_rhs", C.byref(prm), fsi.GCSI_CORRECTOR, *bad) == fsi.FSI_OK   # w unused
+    # the convection needs the time-step coefficients; fixed values need fixed cells
+    assert ctx.raw_status("fsi_gcsi_set_convection", C.byref(prm), vp(z), vp(z)) == fsi.FSI_ERR_STATE
+    assert ctx.raw_status("fsi_fixed_values", vp(z), vp(z)) == fsi.FSI_ERR_STATE
+    torch.cuda.synchronize()
+    ctx.close()
+    # fixed cells: once, before the set-up; the block solve is refused when its coarse
+    # matrix is singular
+    fsi, ext = _ctx(g.ext_mesh)
+    ext.set_fixed_cells(g.solid_cells)
+    with pytest.raises(fsi.FSIError) as e:
+        ext.set_fixed_cells(g.solid_cells)
+    assert e.value.status == fsi.FSI_ERR_STATE
+    ext.set_displacement(np.zeros(3 * ext.sizes(ext.n_levels - 1)["n_vert"]))
+    for j in range(ext.n_levels):
+        ext.set_coefficients(j, np.zeros_like(g.mu_A[j]), 0.5 * g.mu_A[j])
+    ext.setup()
+    with pytest.raises(fsi.FSIError) as e:
+        ext.solve(z, zp)
+    assert e.value.status == fsi.FSI_ERR_STATE
+    assert ext.raw_status("fsi_set_tuning", ext.n_levels - 1, 0, 16) == fsi.FSI_ERR_ARG
+    ext.close()
+    # 2D contexts have no time-step kernels
+    wl = W.make_workload("T2_R")
+    c2 = fsi.Context.from_mesh(wl.mesh)
+    assert c2.raw_status("fsi_gcsi_displacement", C.byref(prm), vp(z), vp(z), vp(z), vp(z), None) == fsi.FSI_ERR_ARG
+    c2.close()
