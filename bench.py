@@ -238,6 +238,13 @@ def corrector_measure(name, ctx, W, np, torch, fsi, solve_workload: str = "C2", 
         cctx.set_convection(j, cj.vconv, cj.r, cj.rho)
     cctx.setup()
     cctx.autotune()
+    # the 64^3 level's FP64 A apply in its autotuned form (the 64^3 row of the measurement plan)
+    Jc = cctx.n_levels - 1
+    _, a64_us, _ = cctx.time_operator(Jc, precision=0, mode=1, reps=20)
+    nvc, ncc = cctx.sizes(Jc)["n_vel"], cctx.sizes(Jc)["n_cells"]
+    out["apply_64cube"] = {"workload": solve_workload, "fp64_A_us": round(a64_us, 1),
+                           "fp64_A_gdofs": round(nvc / (a64_us * 1e-6) / 1e9, 3),
+                           "roofline_frac": round(algorithmic_bytes_per_cell(3, 8) * ncc / (a64_us * 1e-6) / 8e12, 4)}
     cctx.set_mg_params(corrector=1, k_A=6)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -526,6 +533,7 @@ def main():
     if not args.no_corrector:
         _log("[bench] corrector mode")
         out["corrector"] = corrector_measure(name, ctx, W, np, torch, fsi)
+        out["apply_64cube"] = out["corrector"].pop("apply_64cube")
     if not args.no_gcsi:
         _log("[bench] GCSI_2(P,C) time step")
         out["gcsi_step"] = gcsi_measure(W, torch, fsi)

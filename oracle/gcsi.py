@@ -14,7 +14,8 @@ Plain FP64 CPU version of one time step of the GCSI_k(M_1, .., M_S) scheme
 * the predictor and corrector convective velocities (the extrapolation of Sec. 3.1.1
   and v° = v# - w#) with the streamline parameter of Sec. 3.2;
 * the stage loop: explicit step, new geometry, M-mode solve (direct), extension
-  Ext(v) (Sec. 2, solved directly with the solid nodes fixed), w# := w.
+  Ext(v) (Sec. 2, solved directly with the solid nodes fixed), w# := w;
+* nonzero Dirichlet data (an inflow profile, Sec. 5 test problems) by lifting.
 
 All fields are nodal arrays in the reference numbering of ``fem.Box``: the pull-back
 u^{n,i} = u^{n-i} o A^{n-i} o (A^n)^{-1} of Sec. 3.1 has the same nodal values as
@@ -256,6 +257,25 @@ def convection_inputs(box: fem.Box, ref: fem.Reference, v_hash: np.ndarray, w_ha
     return vq, np.repeat(r[:, None], vq.shape[1], 1)
 
 
+# ---------------------------------------------------------------- nonzero Dirichlet data
+def lift_dirichlet(box: fem.Box, ref: fem.Reference, J: np.ndarray, c_mass: np.ndarray, eta: np.ndarray,
+                   d: np.ndarray, g_u: np.ndarray, g_p: np.ndarray, conv=None):
+    """Right-hand side of the constrained system for velocity data d on the Dirichlet dofs
+    (an inflow profile): the unknown is split u = d_W + u_I, so the free rows lose the
+    constrained columns applied to d, g_I - (A d_W)_I and g_p - B d_W, and the Dirichlet rows
+    (identity) take d.  A and B are the unconstrained operators (with the corrector terms
+    (vconv, rho, r) when conv is given).  Returns new arrays."""
+    dm = box.dirichlet_vel_dofs()
+    dw = np.where(dm, d, 0.0)
+    op = fem.assemble_unconstrained(box, J, c_mass, eta, ref)
+    A = op.A
+    if conv is not None:
+        b0 = fem.Box(box.dim, box.cells, box.extent, 0)
+        A = A + fem.assemble_convection(b0, J, conv[0], conv[1], conv[2], ref)
+    gu = np.where(dm, d, g_u - A @ dw)
+    return gu, g_p - op.B @ dw
+
+
 # ---------------------------------------------------------------- extension with fixed nodes
 def fixed_nodes(box: fem.Box, solid_cells: np.ndarray) -> np.ndarray:
     """[n_vel_nodes] bool: nodes of solid cells (G7)."""
@@ -283,6 +303,7 @@ class Problem:
     solid_cells: np.ndarray       # [nc] bool
     mu_A: np.ndarray              # [nc][Q] extension coefficient
     prm: Params = field(default_factory=Params)
+    dirichlet: Optional[np.ndarray] = None   # velocity data on the Dirichlet dofs (inflow), else 0
 
 
 def stage_system(pb: Problem, ref: fem.Reference, mode: str, u_hash: np.ndarray, state: State,
@@ -293,10 +314,14 @@ def stage_system(pb: Problem, ref: fem.Reference, mode: str, u_hash: np.ndarray,
     J = fem.jacobians_q1(box, disp, ref)
     cm, eta = coefficients(prm, pb.solid_q)
     op = fem.assemble(box, J, cm, eta, ref)
+    conv = None
     if mode == "C":
         vq, r = convection_inputs(box, ref, v_hash, w_hash, eta)
         op.A = (op.A + fem.assemble_convection(box, J, vq, prm.rho_f, r, ref)).tocsr()
+        conv = (vq, prm.rho_f, r)
     g_u, g_p = rhs(box, ref, prm, mode, pb.solid_q, disp, u_hash, state)
+    if pb.dirichlet is not None:
+        g_u, g_p = lift_dirichlet(box, ref, J, cm, eta, pb.dirichlet, g_u, g_p, conv)
     return op, g_u, g_p
 
 

@@ -8,7 +8,9 @@ mathematics fix, independent of its own code:
 * the extension with fixed solid nodes reproduces affine fields and minimises the energy;
 * whole steps: a free solid translating or uniformly accelerated by a body force is
   reproduced exactly, and a fluid at rest under a body force keeps v = 0 with the
-  hydrostatic pressure.
+  hydrostatic pressure;
+* the lifting of nonzero Dirichlet data: a uniform flow (with mass and with the corrector
+  terms) and a linear strain field with zero outflow traction are reproduced exactly.
 """
 import math
 
@@ -277,3 +279,49 @@ def test_step_keeps_a_fluid_at_rest_with_the_hydrostatic_pressure():
     assert np.abs(out["v"]).max() < 1e-10 * np.abs(p_want).max()
     assert np.allclose(out["p"], p_want, rtol=1e-10, atol=1e-10)
     assert not np.any(out["w"]) and not np.any(out["u"])
+
+
+def _lift_case(faces=0b111101):
+    box = fem.Box(3, CELLS, EXT, faces)
+    # D[0, 1] = D[0, 2] = 0 keeps the outflow face's normal along x
+    D = np.array([[0.03, 0.0, 0.0], [0.02, 0.04, -0.01], [-0.01, 0.02, 0.03]])
+    J = fem.jacobians_q1(box, _affine(box, D), REF)
+    return box, D, J
+
+
+def test_lifting_reproduces_uniform_flow_with_mass_and_convection():
+    """Data u = U on every Dirichlet face, right-hand side (c_m U, v), outflow at x = L: the
+    discrete solution is u = U, p = 0 exactly (eps(U) = 0, div U = 0, zero outflow
+    traction); with the corrector terms for v° = U too ((grad U) v° = 0)."""
+    box, D, J = _lift_case()
+    U = np.array([0.7, -0.3, 0.2])
+    Un = _nodal(box, lambda X: np.tile(U[:, None], X.shape[1]))
+    cm = np.full((box.n_cells, 27), 4.0)
+    eta = np.full((box.n_cells, 27), 0.3)
+    opu = fem.assemble_unconstrained(box, J, cm, np.zeros_like(eta), REF)
+    g = opu.A @ Un                                   # (c_m U, v)
+    for conv in (None, (np.tile(U, (box.n_cells, 27, 1)), 2.0, np.full((box.n_cells, 27), 0.05))):
+        op = fem.assemble(box, J, cm, eta, REF)
+        if conv is not None:
+            op.A = (op.A + fem.assemble_convection(box, J, conv[0], conv[1], conv[2], REF)).tocsr()
+        gu, gp = gcsi.lift_dirichlet(box, REF, J, cm, eta, Un, g, np.zeros(box.n_p), conv)
+        u, p = solvers.direct_solve(op, gu, gp)
+        assert np.allclose(u, Un, rtol=0, atol=1e-11), conv is None
+        assert np.abs(p).max() < 1e-10
+
+
+def test_lifting_reproduces_a_linear_strain_field():
+    """u = G x with tr G = 0 and sym(G) e_x = 0, constant viscosity, no mass: u on the
+    Dirichlet faces and zero right-hand side give u = G x, p = 0 (the outflow traction
+    (2 eta sym G + p I) e_x vanishes)."""
+    box, D, J = _lift_case()
+    a = 0.4
+    G = np.diag([0.0, a, -a])
+    Gn = _nodal(box, lambda X: G @ ((np.eye(3) + D) @ X))
+    cm = np.zeros((box.n_cells, 27))
+    eta = np.full((box.n_cells, 27), 0.8)
+    op = fem.assemble(box, J, cm, eta, REF)
+    gu, gp = gcsi.lift_dirichlet(box, REF, J, cm, eta, Gn, np.zeros(box.n_vel), np.zeros(box.n_p))
+    u, p = solvers.direct_solve(op, gu, gp)
+    assert np.allclose(u, Gn, rtol=0, atol=1e-11)
+    assert np.abs(p).max() < 1e-10

@@ -279,3 +279,33 @@ def test_planted_time_step_mistake_is_caught(case, monkeypatch):
         except AssertionError:
             caught += 1
     assert caught >= 1, case
+
+
+_orig_lift = gcsi.lift_dirichlet
+
+
+def _lift_no_pressure(box, ref, J, c_mass, eta, d, g_u, g_p, conv=None):
+    """the constrained columns of B left out of the pressure right-hand side"""
+    gu, _ = _orig_lift(box, ref, J, c_mass, eta, d, g_u, g_p, conv)
+    return gu, g_p
+
+
+def _lift_added(box, ref, J, c_mass, eta, d, g_u, g_p, conv=None):
+    """the constrained columns added instead of subtracted"""
+    gu, gp = _orig_lift(box, ref, J, c_mass, eta, -d, g_u, g_p, conv)
+    dm = box.dirichlet_vel_dofs()
+    gu[dm] = d[dm]
+    return gu, gp
+
+
+@pytest.mark.parametrize("fn", [_lift_no_pressure, _lift_added])
+def test_planted_lifting_mistake_is_caught(fn, monkeypatch):
+    monkeypatch.setattr(gcsi, "lift_dirichlet", fn)
+    caught = 0
+    for pin in (gpins.test_lifting_reproduces_uniform_flow_with_mass_and_convection,
+                gpins.test_lifting_reproduces_a_linear_strain_field):
+        try:
+            pin()
+        except AssertionError:
+            caught += 1
+    assert caught >= 1, fn.__doc__
