@@ -363,6 +363,19 @@ fsi_status fsi_gcsi_rhs(fsi_ctx* ctx, const fsi_gcsi_params* prm, int mode, cons
 fsi_status fsi_gcsi_set_convection(fsi_ctx* ctx, const fsi_gcsi_params* prm, const double* v_hash,
                                    const double* w_hash);
 
+/* Nonzero Dirichlet velocity data (an inflow profile, Sec. 5 test problems) for fsi_solve:
+ * with d the data on the Dirichlet nodes of the finest level (other entries are not read),
+ * the free rows of g_u lose the constrained columns applied to d, the Dirichlet rows of g_u
+ * take d, and g_p loses B's constrained columns applied to d:
+ *   g_u <- g_u - (M_u d_W) on free rows, g_u <- d on Dirichlet rows, g_p <- g_p - B d_W,
+ * with M_u the velocity block in the configured mode (A, or A + N + S with corrector = 1).
+ * Then the solve's Dirichlet rows (identity) take the data and its free rows are the
+ * unconstrained equations.  d, g_u: device [n_vel]; g_p: device [n_p]; updated in place.
+ * Requires the finest level's geometry and coefficients (and fsi_set_convection in the
+ * corrector mode).  Errors: FSI_ERR_ARG, FSI_ERR_STATE, FSI_ERR_NONFINITE (d not finite on
+ * the Dirichlet nodes; synchronises). */
+fsi_status fsi_lift_dirichlet(fsi_ctx* ctx, const double* d, double* g_u, double* g_p);
+
 /* Autotuner: times the cell-kernel launch variants (wavefronts per workgroup,
  * register cap, cached or streaming geometry loads) for every operator class
  * (A, A with the fused Chebyshev step, Stokes, Stokes with the fused residual,

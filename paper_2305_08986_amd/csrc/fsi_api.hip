@@ -753,6 +753,22 @@ static fsi_status precond_combined(Context* ctx, const double* r, double* z, hip
 }
 
 
+// ---------------------------------------------------------------- unconstrained operator (boundary liftings)
+// The finest level's operator with the Dirichlet rows and columns kept (the cell info with its
+// wall bits cleared stands in for the level's own), in the phased launches: the single atomic
+// launch derives its wall rows from the box faces, so it cannot serve here.
+static fsi_status apply_unconstrained(Context* ctx, int mode, const double* u, const double* p, double* v,
+                                      double* q, hipStream_t s) {
+    Level& L = ctx->lv[ctx->nlev - 1];
+    if (!ctx->d_info_free) TRY(dalloc(ctx, &ctx->d_info_free, L.nc));
+    launch_clear_wall_bits(L.d_info, ctx->d_info_free, L.nc, s);
+    uint4* own = L.d_info;
+    L.d_info = ctx->d_info_free;
+    launch_cell_all<double>(L, mode, 0, Kmode<double>(L, mode), L.d_cv64, u, p, v, q, s);
+    L.d_info = own;
+    return FSI_OK;
+}
+
 // ---------------------------------------------------------------- extension solve
 // The pseudo-elastic extension of Sec. 2: u = g on the Dirichlet nodes and a(u, v) = 0
 // for every v vanishing there, with a the context's A form (c_m = 0 and eta = mu_A / 2
@@ -1544,8 +1560,6 @@ fsi_status fsi_solve_extension(fsi_ctx* h, const double* g, double* u, const fsi
     hipStream_t s = ctx->stream;
     if (!ctx->ext_ready) {
         TRY(setup_coarse_u(ctx));
-        if (!ctx->d_info_free) TRY(dalloc(ctx, &ctx->d_info_free, L.nc));
-        launch_clear_wall_bits(L.d_info, ctx->d_info_free, L.nc, s);
         if (!ctx->ext_buf) TRY(dalloc(ctx, &ctx->ext_buf, 8 * nv));
         ctx->ext_ready = true;
     }
@@ -1568,13 +1582,8 @@ fsi_status fsi_solve_extension(fsi_ctx* h, const double* g, double* u, const fsi
     launch_nonfinite(x, nv, ctx->d_flag, s);
     TRY(sync_flag(ctx, FSI_ERR_NONFINITE, "boundary data or initial guess not finite"));
     // lifting: b = -(A gw) on the interior rows, with the unconstrained operator (wall
-    // columns kept); the cell info without wall bits stands in for the level's own
-    {
-        uint4* own = L.d_info;
-        L.d_info = ctx->d_info_free;
-        op_apply<double>(ctx, J, OP_A, gw, nullptr, q, nullptr, s);
-        L.d_info = own;
-    }
+    // columns kept)
+    TRY(apply_unconstrained(ctx, OP_A, gw, nullptr, q, nullptr, s));
     launch_scale_host(-1.0, q, b, nv, s);
     launch_dirichlet_zero<double>(L, b, s);
     double bn2;
@@ -1854,6 +1863,34 @@ fsi_status fsi_gcsi_set_convection(fsi_ctx* h, const fsi_gcsi_params* prm, const
         launch_gcsi_convection(L, F, v_hash, w_hash, L.d_gcsi_eta, 1 << (J - j), vconv, r, ctx->stream);
         TRY(fsi_set_convection(h, j, vconv, r, prm->rho_f));
     }
+    return FSI_OK;
+}
+
+fsi_status fsi_lift_dirichlet(fsi_ctx* h, const double* d, double* g_u, double* g_p) {
+    if (!h || !d || !g_u || !g_p) return FSI_ERR_ARG;
+    Context* ctx = &h->c;
+    const int J = ctx->nlev - 1;
+    TRY(apply_check(ctx, J, true));
+    Level& L = ctx->lv[J];
+    const bool conv = ctx->prm.corrector != 0;
+    if (conv && !L.conv_set) return fail(ctx, FSI_ERR_STATE, "corrector lifting before fsi_set_convection");
+    hipStream_t s = ctx->stream;
+    if (!ctx->lift_buf) TRY(dalloc(ctx, &ctx->lift_buf, 2 * L.nv + 2 * L.np));
+    double* gw = ctx->lift_buf;
+    double* qu = gw + L.nv;
+    double* zp = qu + L.nv;
+    double* qp = zp + L.np;
+    launch_fill<double>(gw, 0.0, L.nv, s);
+    launch_dirichlet_copy<double>(L, d, gw, s);
+    launch_fill<int>(ctx->d_flag, 0, 1, s);
+    launch_nonfinite(gw, L.nv, ctx->d_flag, s);
+    TRY(sync_flag(ctx, FSI_ERR_NONFINITE, "Dirichlet data not finite"));
+    launch_fill<double>(zp, 0.0, L.np, s);
+    // [q_u; q_p] = [A (+ N + S); B] gw with the constrained columns kept
+    TRY(apply_unconstrained(ctx, conv ? (OP_A | OP_BT | OP_B | OP_CONV) : (OP_A | OP_BT | OP_B), gw, zp, qu, qp, s));
+    launch_axpy_host(-1.0, qu, g_u, L.nv, s);
+    launch_dirichlet_copy<double>(L, d, g_u, s);
+    launch_axpy_host(-1.0, qp, g_p, L.np, s);
     return FSI_OK;
 }
 

@@ -285,6 +285,7 @@ struct Context {
     bool coarse_block_ok = true;
     // time-step scratch: [n_cells][27] x 4 doubles of the finest level
     double* gcsi_tmp = nullptr;
+    double* lift_buf = nullptr;    // fsi_lift_dirichlet: 2 velocity + 2 pressure vectors
     double gcsi_rho_f = -1.0;   // fluid density of the last fsi_gcsi_set_coefficients
 };
 

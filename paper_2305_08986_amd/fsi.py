@@ -133,6 +133,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "fsi_set_tuning": (i, [vp, i, i, i]),
         "fsi_time_operator": (i, [vp, i, i, i, i, C.POINTER(d), C.POINTER(d), C.POINTER(i)]),
         "fsi_set_fixed_cells": (i, [vp, vp]),
+        "fsi_lift_dirichlet": (i, [vp, vp, vp, vp]),
         "fsi_fixed_values": (i, [vp, vp, vp]),
         "fsi_gcsi_displacement": (i, [vp, C.POINTER(GcsiParams), vp, vp, vp, vp, vp]),
         "fsi_gcsi_set_coefficients": (i, [vp, C.POINTER(GcsiParams), C.POINTER(vp)]),
@@ -391,6 +392,12 @@ class Context:
         import numpy as np
         f = np.ascontiguousarray(np.asarray(fixed, dtype=np.uint8))
         self._check(self.lib.fsi_set_fixed_cells(self.h, f.ctypes.data_as(C.c_void_p)))
+
+    def lift_dirichlet(self, d, g_u, g_p):
+        """Nonzero Dirichlet data d into the right-hand side (fsi_lift_dirichlet; in place)."""
+        self._check(self.lib.fsi_lift_dirichlet(self.h, C.c_void_p(_ptr(d)), C.c_void_p(_ptr(g_u)),
+                                                C.c_void_p(_ptr(g_p))))
+        return g_u, g_p
 
     def fixed_values(self, v, out):
         self._check(self.lib.fsi_fixed_values(self.h, C.c_void_p(_ptr(v)), C.c_void_p(_ptr(out))))

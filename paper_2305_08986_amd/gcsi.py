@@ -48,6 +48,9 @@ class Stepper:
         self.ext.set_mg_params(precision=precision if ext_precision is None else ext_precision)
         self.ext.setup()
         self.solid_q = [torch.as_tensor(x, device="cuda", dtype=torch.uint8).contiguous() for x in inputs.solid_q]
+        # velocity data on the Dirichlet nodes of the Stokes system (an inflow profile), or none
+        d = getattr(inputs, "dirichlet", None)
+        self.dirichlet = None if d is None else torch.as_tensor(d, **dev).contiguous()
         self.u_hash = torch.empty(self.nv, **dev)
         self.disp = torch.empty(3 * self.nvert, **dev)
         self.g_u = torch.empty(self.nv, **dev)
@@ -76,6 +79,8 @@ class Stepper:
             self._tuned.add(mode)
         S.gcsi_rhs(prm, fsi.GCSI_CORRECTOR if corr else fsi.GCSI_PREDICTOR, self.solid_q[self.J], self.disp,
                    self.u_hash, u1, u2, v1, v2, w1, w2, self.g_u, self.g_p)
+        if self.dirichlet is not None:
+            S.lift_dirichlet(self.dirichlet, self.g_u, self.g_p)
         v, p = v0.clone(), p0.clone()
         _, _, info = S.solve(self.g_u, self.g_p, v, p, rtol=rtol, max_iter=max_iter)
         self.ext.fixed_values(v, self.g_ext)

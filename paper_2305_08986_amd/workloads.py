@@ -458,6 +458,7 @@ class GcsiInputs:
     v: list
     w: list
     p: np.ndarray                # [n_p]
+    dirichlet: Optional[np.ndarray] = None   # [n_vel] velocity data on the Dirichlet nodes, or None
 
 
 def _inside_strip(X: np.ndarray) -> np.ndarray:
@@ -467,11 +468,15 @@ def _inside_strip(X: np.ndarray) -> np.ndarray:
     return m
 
 
-def make_gcsi_inputs(name: str = "G1", seed: int = BASE_SEED) -> GcsiInputs:
+def make_gcsi_inputs(name: str = "G1", seed: int = BASE_SEED, inflow: float = 0.0) -> GcsiInputs:
     """Draw the inputs of one GCSI step on the channel-with-strip ``name``.
 
     Draw order (PCG64 ``[seed, config, GCSI_STREAM]``): sine modes of u^{n-1}, u^{n-2},
-    v^{n-1}, v^{n-2}, w^{n-1}, w^{n-2}, then p (U[-1, 1]) at the pressure nodes."""
+    v^{n-1}, v^{n-2}, w^{n-1}, w^{n-2}, then p (U[-1, 1]) at the pressure nodes.
+    ``inflow`` > 0 adds Dirichlet data on the inflow face x = 0: the x-velocity
+    16 inflow y (H - y) z (W - z) / (H^2 W^2) (peak ``inflow`` at the centre, zero on the
+    edges), zero on the other walls; the velocity history then carries the same profile,
+    scaled by (1 - x / L), so that it matches the data on the inflow face."""
     cfg = GCSI_CONFIGS[name]
     mesh = MeshDesc(dim=3, n_fine=tuple(cfg["n"]), extent=GCSI_EXTENT, n_coarse=tuple(cfg["n_coarse"]),
                     dirichlet_faces=default_dirichlet_faces(3))
@@ -511,5 +516,18 @@ def make_gcsi_inputs(name: str = "G1", seed: int = BASE_SEED) -> GcsiInputs:
     for i in range(2):
         wi = w[i].reshape(3, -1)
         wi[:, node] = v[i].reshape(3, -1)[:, node]
+    dirichlet = None
+    if inflow > 0:
+        L, H, Wd = mesh.extent
+        prof = 16.0 * inflow * X[1] * (H - X[1]) * X[2] * (Wd - X[2]) / (H * H * Wd * Wd)
+        dirichlet = np.zeros_like(X)
+        dirichlet[0] = np.where(X[0] == 0.0, prof, 0.0)
+        dirichlet = np.ascontiguousarray(dirichlet.ravel())
+        for i in range(2):
+            v[i].reshape(3, -1)[0] += prof * (1.0 - X[0] / L)
+        # the mesh velocity follows the velocity on the solid's nodes
+        for i in range(2):
+            wi = w[i].reshape(3, -1)
+            wi[:, node] = v[i].reshape(3, -1)[:, node]
     return GcsiInputs(mesh=mesh, ext_mesh=ext_mesh, solid_q=solid_q, solid_cells=solid_cells, mu_A=mu_A,
-                      material=dict(GCSI_MATERIAL), u=u, v=v, w=w, p=p)
+                      material=dict(GCSI_MATERIAL), u=u, v=v, w=w, p=p, dirichlet=dirichlet)
