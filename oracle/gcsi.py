@@ -343,3 +343,18 @@ def step(pb: Problem, state: State, modes: Sequence[str] = ("P", "C"),
         v_hash, w_hash = v, w
     u_new = explicit_displacement(prm, w_hash, state.u)
     return dict(u=u_new, v=v_hash, w=w_hash, p=stages[-1]["p"], stages=stages)
+
+
+def run(pb: Problem, state: State, n_steps: int, modes: Sequence[str] = ("P", "C"),
+        ref: Optional[fem.Reference] = None):
+    """n_steps steps of Algorithm 1; after each the history moves back by one step
+    (u^{n-2} := u^{n-1}, u^{n-1} := u^n, likewise v and w).  Returns the final state and the
+    steps' outputs."""
+    outs = []
+    k = pb.prm.k
+    for _ in range(n_steps):
+        out = step(pb, state, modes, ref)
+        state = State(u=[out["u"]] + state.u[:k - 1], v=[out["v"]] + state.v[:k - 1],
+                      w=[out["w"]] + state.w[:k - 1], p=out["p"])
+        outs.append(out)
+    return state, outs

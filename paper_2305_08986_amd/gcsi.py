@@ -27,7 +27,7 @@ class Stepper:
     reference geometry, c_m = 0 and eta = mu_A / 2, set up once)."""
 
     def __init__(self, inputs, precision: int = fsi.PREC_FP64, autotune: bool = False, ext_precision=None,
-                 **mg):
+                 reorth: int = 0, **mg):
         import torch
         self.torch = torch
         self.inputs = inputs
@@ -58,6 +58,7 @@ class Stepper:
         self.g_ext = torch.empty(self.nv, **dev)
         self.autotune = autotune
         self._tuned = set()
+        self.reorth = reorth     # FGMRES Gram-Schmidt passes (fsi_solve_opts.reorth)
 
     def close(self):
         self.stokes.close()
@@ -82,7 +83,7 @@ class Stepper:
         if self.dirichlet is not None:
             S.lift_dirichlet(self.dirichlet, self.g_u, self.g_p)
         v, p = v0.clone(), p0.clone()
-        _, _, info = S.solve(self.g_u, self.g_p, v, p, rtol=rtol, max_iter=max_iter)
+        _, _, info = S.solve(self.g_u, self.g_p, v, p, rtol=rtol, max_iter=max_iter, reorth=self.reorth)
         self.ext.fixed_values(v, self.g_ext)
         w = w_hash.clone()
         _, einfo = self.ext.solve_extension(self.g_ext, w, rtol=ext_rtol, max_iter=max_iter)
@@ -111,3 +112,20 @@ class Stepper:
         self.torch.cuda.synchronize()
         return dict(u=u_new, v=v_cur, w=w_hash, p=p_cur, stages=stages,
                     step_ms=1e3 * (time.perf_counter() - t0))
+
+    def run(self, u, v, w, p, n_steps: int, modes: Sequence[str] = ("P", "C"), rtol: float = 1e-8,
+            ext_rtol: float = 1e-6, max_iter: int = 300):
+        """n_steps steps; after each the history moves back by one step (u^{n-2} := u^{n-1},
+        u^{n-1} := u^n, likewise v and w).  Returns the final (u, v, w, p) lists/tensor and the
+        per-step records."""
+        k = self.prm.k
+        u, v, w = list(u)[:k], list(v)[:k], list(w)[:k]
+        recs = []
+        for _ in range(n_steps):
+            r = self.step(u, v, w, p, modes, rtol, ext_rtol, max_iter)
+            u = [r["u"]] + u[:k - 1]
+            v = [r["v"]] + v[:k - 1]
+            w = [r["w"]] + w[:k - 1]
+            p = r["p"]
+            recs.append(dict(step_ms=r["step_ms"], stages=r["stages"]))
+        return u, v, w, p, recs

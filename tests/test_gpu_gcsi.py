@@ -358,3 +358,26 @@ def test_gcsi2_step_with_inflow_matches_oracle_step(case):
     print("GCSI_2(P,C) with inflow", errs, [r["iters"] for r in res["stages"]])
     for key, e in errs.items():
         assert e <= 1e-8, (key, e)
+
+
+def test_three_steps_with_inflow_match_the_oracle_run(case):
+    """Three GCSI_2(P,C) steps with the history moved back after each (Algorithm 1's data),
+    inflow and gravity, against the oracle's run."""
+    g0, pb0, _, ref, _ = case
+    from paper_2305_08986_amd import gcsi
+    g = W.make_gcsi_inputs("G1", inflow=1.0)
+    pb = og.Problem(box=pb0.box, ext_box=pb0.ext_box, solid_q=pb0.solid_q, solid_cells=pb0.solid_cells,
+                    mu_A=pb0.mu_A, prm=og.Params(**g.material), dirichlet=g.dirichlet)
+    st, _ = og.run(pb, og.State(u=g.u, v=g.v, w=g.w, p=g.p), 3, ("P", "C"), ref)
+    S = gcsi.Stepper(g, precision=1)
+    u, v, w, p, recs = S.run([_dev(x) for x in g.u], [_dev(x) for x in g.v], [_dev(x) for x in g.w], _dev(g.p),
+                             3, rtol=1e-12, ext_rtol=1e-12)
+    S.close()
+    for i in range(2):
+        errs = {key: _rel(got.cpu().numpy(), want) for key, got, want in
+                (("u", u[i], st.u[i]), ("v", v[i], st.v[i]), ("w", w[i], st.w[i]))}
+        print("history", i, errs)
+        for key, e in errs.items():
+            assert e <= 1e-8, (i, key, e)
+    assert _rel(p.cpu().numpy(), st.p) <= 1e-8
+    print("iterations", [[s["iters"] for s in r["stages"]] for r in recs])

@@ -325,3 +325,26 @@ def test_lifting_reproduces_a_linear_strain_field():
     u, p = solvers.direct_solve(op, gu, gp)
     assert np.allclose(u, Gn, rtol=0, atol=1e-11)
     assert np.abs(p).max() < 1e-10
+
+
+def test_run_shifts_the_history():
+    """Three steps of the accelerated free solid: after each step the history holds the
+    exact u, v, w at the last two times (the shift of Algorithm 1's data)."""
+    b = np.array([0.4, -2.0, 0.3])
+    prm = _prm(k=2, body=tuple(b), tau=0.02)
+    pb = _all_solid_problem(prm)
+    box = pb.box
+    V0 = np.array([0.5, 0.25, -0.75])
+    vel = lambda t: V0 + b * t
+    disp = lambda t: V0 * t + 0.5 * b * t * t
+    const = lambda c: _nodal(box, lambda X: np.tile(c[:, None], X.shape[1]))
+    t0 = 0.3
+    ts = [t0 - (i + 1) * prm.tau for i in range(2)]
+    st = gcsi.State(u=[const(disp(t)) for t in ts], v=[const(vel(t)) for t in ts], w=[const(vel(t)) for t in ts])
+    st, outs = gcsi.run(pb, st, 3, ("P", "C"), REF)
+    tn = t0 + 2 * prm.tau
+    for i, t in enumerate((tn, tn - prm.tau)):
+        assert np.allclose(st.u[i], const(disp(t)), rtol=0, atol=1e-11)
+        assert np.allclose(st.v[i], const(vel(t)), rtol=0, atol=1e-11)
+        assert np.allclose(st.w[i], const(vel(t)), rtol=0, atol=1e-11)
+    assert len(outs) == 3

@@ -309,3 +309,20 @@ def test_planted_lifting_mistake_is_caught(fn, monkeypatch):
         except AssertionError:
             caught += 1
     assert caught >= 1, fn.__doc__
+
+
+def _run_no_shift(pb, state, n_steps, modes=("P", "C"), ref=None):
+    """the oldest history entry kept instead of moved back"""
+    outs = []
+    for _ in range(n_steps):
+        out = gcsi.step(pb, state, modes, ref)
+        state = gcsi.State(u=[out["u"]] + state.u[1:], v=[out["v"]] + state.v[1:], w=[out["w"]] + state.w[1:],
+                           p=out["p"])
+        outs.append(out)
+    return state, outs
+
+
+def test_planted_history_shift_mistake_is_caught(monkeypatch):
+    monkeypatch.setattr(gcsi, "run", _run_no_shift)
+    with pytest.raises(AssertionError):
+        gpins.test_run_shifts_the_history()
