@@ -1,7 +1,7 @@
 """Solver runs for kernel traces: one FGMRES solve per configuration, or one GCSI time step.
 
     python -m paper_2305_08986_amd.solvebench --workload C3 --configs mixed,fp64,plain
-    python -m paper_2305_08986_amd.solvebench --gcsi G2
+    python -m paper_2305_08986_amd.solvebench --gcsi G2 [--inflow 1.0]
 
 Before each timed solve (or the timed second step) a float32 torch fill of 2^23
 elements runs alone on the device: in a kernel trace, the dispatches between two such
@@ -32,6 +32,7 @@ def main(argv=None):
     ap.add_argument("--configs", default="mixed,fp64,plain")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--gcsi", default="", help="time one GCSI_2(P,C) step of this channel case instead")
+    ap.add_argument("--inflow", type=float, default=1.0, help="inflow peak of the channel case")
     a = ap.parse_args(argv)
 
     import torch
@@ -42,7 +43,7 @@ def main(argv=None):
     torch.cuda.set_device(0)
     if a.gcsi:
         from . import gcsi
-        g = W.make_gcsi_inputs(a.gcsi)
+        g = W.make_gcsi_inputs(a.gcsi, inflow=a.inflow)
         S = gcsi.Stepper(g, precision=fsi.PREC_MIXED, autotune=True)
         dev = lambda x: torch.from_numpy(x).cuda()
         args = ([dev(x) for x in g.u], [dev(x) for x in g.v], [dev(x) for x in g.w], dev(g.p))
