@@ -6,8 +6,9 @@ algorithm: the explicit displacement u# = gamma tau w# - sum_i alpha_i u^{n-i}
 the new geometry (fsi_set_displacement) and the coefficients of the stress splitting
 (fsi_gcsi_set_coefficients), in the corrector stage the convective velocity
 v° = v# - w# with the streamline parameter (fsi_gcsi_set_convection), the set-up of the
-block V-cycle (fsi_setup), the right-hand side g_vM, g_p (fsi_gcsi_rhs), the FGMRES
-solve from the last velocity and pressure (fsi_solve), and the extension w = Ext(v) on
+block V-cycle (fsi_setup), the right-hand side g_vM, g_p (fsi_gcsi_rhs, with nonzero
+Dirichlet data such as an inflow profile lifted by fsi_lift_dirichlet), the FGMRES solve
+from the last velocity and pressure (fsi_solve), and the extension w = Ext(v) on
 a second context that fixes the solid's nodes (fsi_fixed_values, fsi_solve_extension);
 then w# := w.  After the stages the displacement is recovered with the same splitting
 from w^n.  This module orders the calls and holds the device buffers; every arithmetic
