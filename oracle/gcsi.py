@@ -132,9 +132,9 @@ def coefficients(prm: Params, solid_q: np.ndarray):
     return rho / gt, eta
 
 
-def _cell_values(box: fem.Box, f: np.ndarray):
-    """[nc][dim][n_loc] local nodal values of a component-major Q2 field."""
-    vn = box.cell_vel_nodes()
+def _cell_values(box: fem.Box, f: np.ndarray, cells: Optional[np.ndarray] = None):
+    """[nc][dim][n_loc] local nodal values of a component-major Q2 field (of the given cells)."""
+    vn = box.cell_vel_nodes(cells)
     F = f.reshape(box.dim, -1)
     return np.stack([F[a][vn] for a in range(box.dim)], axis=1)
 
@@ -145,7 +145,8 @@ def _phys_grad(fe: np.ndarray, G: np.ndarray):
 
 
 def rhs(box: fem.Box, ref: fem.Reference, prm: Params, mode: str, solid_q: np.ndarray,
-        disp: np.ndarray, u_hash: np.ndarray, state: State, absolute: bool = False):
+        disp: np.ndarray, u_hash: np.ndarray, state: State, absolute: bool = False,
+        cells: Optional[np.ndarray] = None):
     """(g_u, g_p) of the M-mode system (eq. form_g_j with readings G1-G5, eq. form_g_p).
 
       g_u(v) = (rho (body - (1/(gamma tau)) sum_i alpha_i v^{n,i}), v)_{O#}
@@ -155,22 +156,26 @@ def rhs(box: fem.Box, ref: fem.Reference, prm: Params, mode: str, solid_q: np.nd
 
     disp: vertex displacement of the explicit geometry O# = (Id + u#)(O-hat).  Rows of
     Dirichlet velocity dofs are zero.  absolute=True sums the magnitudes of every
-    quadrature term instead (the rounding scale of any evaluation by this rule)."""
+    quadrature term instead (the rounding scale of any evaluation by this rule).  cells
+    (lexicographic indices) restricts the sums to those cells: the rows of nodes whose cells
+    are all among them are complete (sampled rows of large meshes)."""
     dim = box.dim
-    J = fem.jacobians_q1(box, disp, ref)
+    if cells is not None:
+        solid_q = solid_q[cells]
+    J = fem.jacobians_q1(box, disp, ref, cells)
     Jinv, wdet = fem.geometry_factors(J, ref)
     G = np.einsum("cqbx,qib->cqix", Jinv, ref.dphi)               # physical basis gradients
     gt = prm.gamma * prm.tau
     rho = np.where(solid_q, prm.rho_s, prm.rho_f)                  # [nc][Q]
     al = prm.alpha
-    V = [_cell_values(box, x) for x in state.v]
+    V = [_cell_values(box, x, cells) for x in state.v]
     vsum = sum(a * x for a, x in zip(al, V))                        # sum_i alpha_i v^{n,i}
     body = np.asarray(prm.body, dtype=float)[None, None, :dim]
-    U = [_cell_values(box, x) for x in state.u]
+    U = [_cell_values(box, x, cells) for x in state.u]
     usum = sum(a * x for a, x in zip(al, U))
-    uh = _cell_values(box, u_hash)
+    uh = _cell_values(box, u_hash, cells)
     if mode == "P":
-        W = [_cell_values(box, x) for x in state.w]
+        W = [_cell_values(box, x, cells) for x in state.w]
         if prm.k == 1:
             vstar, vcirc = V[0], V[0] - W[0]
         else:
@@ -204,24 +209,24 @@ def rhs(box: fem.Box, ref: fem.Reference, prm: Params, mode: str, solid_q: np.nd
     T = prm.mu_s * (T2 + Tq) * solid_q[..., None, None]
     ge = np.einsum("cq,cqa,qi->cai", wdet, Fv, phi) + np.einsum("cq,cqax,cqix->cai", wdet, T, G)
     g_u = np.zeros(box.n_vel)
-    vnodes = box.cell_vel_nodes()
+    vnodes = box.cell_vel_nodes(cells)
     nn = box.n_vel_nodes
     for a in range(dim):
         np.add.at(g_u, vnodes + a * nn, ge[:, a, :])
     g_u[box.dirichlet_vel_dofs()] = 0.0
-    g_p = volume_correction(box, ref, prm, solid_q, u_hash, absolute)
+    g_p = volume_correction(box, ref, prm, solid_q, u_hash, absolute, cells)
     return g_u, g_p
 
 
 def volume_correction(box: fem.Box, ref: fem.Reference, prm: Params, solid_q: np.ndarray,
-                      u_hash: np.ndarray, absolute: bool = False) -> np.ndarray:
+                      u_hash: np.ndarray, absolute: bool = False, cells: Optional[np.ndarray] = None) -> np.ndarray:
     """g_p(q) = (-(1/eta_V) (J# - 1), q-hat) over the reference solid (eq. form_g_p):
     J# = det(I + grad-hat u#) of the Q2 field at the Gauss points, dx-hat = prod(h) w_q."""
     g_p = np.zeros(box.n_p)
     if not (prm.eta_V > 0 and math.isfinite(prm.eta_V)):
         return g_p
     h = box.h()
-    gref = np.einsum("cai,qib->cqab", _cell_values(box, u_hash), ref.dphi) / h[None, None, None, :]
+    gref = np.einsum("cai,qib->cqab", _cell_values(box, u_hash, cells), ref.dphi) / h[None, None, None, :]
     F = gref + np.eye(box.dim)[None, None]
     Jh = np.linalg.det(F)
     vol = np.prod(h) * ref.w                                          # [Q]
@@ -229,7 +234,7 @@ def volume_correction(box: fem.Box, ref: fem.Reference, prm: Params, solid_q: np
     if absolute:
         s = (1.0 / prm.eta_V) * (np.abs(Jh) + 1.0) * solid_q
     ge = np.einsum("q,cq,qk->ck", vol, s, np.abs(ref.psi) if absolute else ref.psi)
-    np.add.at(g_p, box.cell_p_nodes(), ge)
+    np.add.at(g_p, box.cell_p_nodes(cells), ge)
     return g_p
 
 

@@ -381,3 +381,45 @@ def test_three_steps_with_inflow_match_the_oracle_run(case):
             assert e <= 1e-8, (i, key, e)
     assert _rel(p.cpu().numpy(), st.p) <= 1e-8
     print("iterations", [[s["iters"] for s in r["stages"]] for r in recs])
+
+
+@pytest.mark.parametrize("mode", ["P", "C"])
+def test_right_hand_side_at_128x32x32_sampled_rows(mode):
+    """The measured size: sampled rows of g_vM and g_p (nodes in the solid, on its boundary,
+    next to the walls and the inflow face, and random ones) against the oracle summed over
+    the cells around them, componentwise."""
+    g = W.make_gcsi_inputs("G2", inflow=1.0)
+    J = g.mesh.n_levels - 1
+    box = fem.level_box(g.mesh, J)
+    ref = fem.Reference(3)
+    prm = og.Params(**g.material)
+    st = og.State(u=g.u, v=g.v, w=g.w, p=g.p)
+    uh = og.explicit_displacement(prm, g.w[0], g.u)
+    disp = og.vertex_values(box, uh)
+    sq = g.solid_q[J].astype(bool)
+    rng = np.random.default_rng(23)
+    vn = box.vel_nodes
+    lex = lambda i, j, k: i + vn[0] * (j + vn[1] * k)
+    solid_nodes = np.nonzero(og.fixed_nodes(box, g.solid_cells.astype(bool)))[0]
+    nodes = np.unique(np.concatenate([
+        rng.choice(box.n_vel_nodes, 24, replace=False), rng.choice(solid_nodes, 12, replace=False),
+        [lex(1, 1, 1), lex(1, vn[1] // 2, vn[2] // 2), lex(vn[0] - 1, vn[1] // 2, vn[2] // 2),
+         lex(vn[0] // 2, 1, vn[2] - 2), lex(vn[0] // 2, vn[1] - 2, 1)]]))
+    pn = rng.choice(box.n_p, 16, replace=False)
+    cells = np.unique(np.concatenate([box.cells_of_vel_node(int(n)) for n in nodes] +
+                                     [box.cells_of_p_node(int(k)) for k in pn]))
+    want_u, want_p = og.rhs(box, ref, prm, mode, sq, disp, uh, st, cells=cells)
+    abs_u, abs_p = og.rhs(box, ref, prm, mode, sq, disp, uh, st, absolute=True, cells=cells)
+    fsi, ctx = _ctx(g.mesh)
+    gp_ = fsi.GcsiParams.of(**g.material)
+    g_u = torch.empty(box.n_vel, device="cuda", dtype=torch.float64)
+    g_p = torch.empty(box.n_p, device="cuda", dtype=torch.float64)
+    f = [_dev(x) for x in (g.u[0], g.u[1], g.v[0], g.v[1], g.w[0], g.w[1])]
+    ctx.gcsi_rhs(gp_, fsi.GCSI_PREDICTOR if mode == "P" else fsi.GCSI_CORRECTOR, _dev(g.solid_q[J], torch.uint8),
+                 _dev(disp.ravel()), _dev(uh), *f, g_u, g_p)
+    torch.cuda.synchronize()
+    rows = np.concatenate([nodes + a * box.n_vel_nodes for a in range(3)])
+    assert np.abs(want_u[rows]).max() > 0 and np.abs(want_p[pn]).max() > 0
+    _within(g_u.cpu().numpy()[rows], want_u[rows], abs_u[rows], f"g_u rows ({mode}, 128x32x32)")
+    _within(g_p.cpu().numpy()[pn], want_p[pn], abs_p[pn], f"g_p rows ({mode}, 128x32x32)")
+    ctx.close()

@@ -348,3 +348,28 @@ def test_run_shifts_the_history():
         assert np.allclose(st.v[i], const(vel(t)), rtol=0, atol=1e-11)
         assert np.allclose(st.w[i], const(vel(t)), rtol=0, atol=1e-11)
     assert len(outs) == 3
+
+
+def test_rhs_on_a_cell_subset_gives_complete_rows():
+    """The right-hand side summed over the cells around a set of nodes equals the full one
+    on those nodes' rows (the sampled-row form used on meshes too large for the oracle)."""
+    from paper_2305_08986_amd import workloads as W
+    g = W.make_gcsi_inputs("G1", inflow=1.0)
+    J = g.mesh.n_levels - 1
+    box = fem.level_box(g.mesh, J)
+    prm = gcsi.Params(**g.material)
+    st = gcsi.State(u=g.u, v=g.v, w=g.w, p=g.p)
+    uh = gcsi.explicit_displacement(prm, g.w[0], g.u)
+    disp = gcsi.vertex_values(box, uh)
+    sq = g.solid_q[J].astype(bool)
+    rng = np.random.default_rng(4)
+    nodes = rng.choice(box.n_vel_nodes, 12, replace=False)
+    pn = rng.choice(box.n_p, 6, replace=False)
+    cells = np.unique(np.concatenate([box.cells_of_vel_node(int(n)) for n in nodes] +
+                                     [box.cells_of_p_node(int(k)) for k in pn]))
+    for mode in ("P", "C"):
+        fu, fp = gcsi.rhs(box, REF, prm, mode, sq, disp, uh, st)
+        su, sp = gcsi.rhs(box, REF, prm, mode, sq, disp, uh, st, cells=cells)
+        rows = np.concatenate([nodes + a * box.n_vel_nodes for a in range(3)])
+        assert np.allclose(su[rows], fu[rows], rtol=1e-13, atol=1e-13 * np.abs(fu).max())
+        assert np.allclose(sp[pn], fp[pn], rtol=1e-13, atol=1e-13 * np.abs(fp).max())
