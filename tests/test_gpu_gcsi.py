@@ -265,6 +265,18 @@ def test_time_step_entry_points_reject_bad_input(case):
     # the convection needs the time-step coefficients; fixed values need fixed cells
     assert ctx.raw_status("fsi_gcsi_set_convection", C.byref(prm), vp(z), vp(z)) == fsi.FSI_ERR_STATE
     assert ctx.raw_status("fsi_fixed_values", vp(z), vp(z)) == fsi.FSI_ERR_STATE
+    # the lifting needs geometry and coefficients, the corrector terms in the corrector mode,
+    # and finite data on the Dirichlet nodes
+    assert ctx.raw_status("fsi_lift_dirichlet", vp(z), vp(z), vp(zp)) == fsi.FSI_ERR_STATE
+    J = g.mesh.n_levels - 1
+    ctx.set_displacement(np.zeros(3 * ctx.sizes(J)["n_vert"]))
+    ctx.gcsi_set_coefficients(prm, [_dev(x, torch.uint8) for x in g.solid_q])
+    bad_d = torch.zeros_like(z)
+    bad_d[0] = float("nan")                      # node 0 is a wall node (corner)
+    assert ctx.raw_status("fsi_lift_dirichlet", vp(bad_d), vp(z), vp(zp)) == fsi.FSI_ERR_NONFINITE
+    assert ctx.raw_status("fsi_lift_dirichlet", vp(z), vp(z), vp(zp)) == fsi.FSI_OK
+    ctx.set_mg_params(corrector=1, k_A=6)
+    assert ctx.raw_status("fsi_lift_dirichlet", vp(z), vp(z), vp(zp)) == fsi.FSI_ERR_STATE
     torch.cuda.synchronize()
     ctx.close()
     # fixed cells: once, before the set-up; the block solve is refused when its coarse
