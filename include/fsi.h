@@ -99,7 +99,7 @@ typedef struct {
                                 reading the stored values; 0: stored values (default).  Levels
                                 whose geometry came from fsi_set_jacobians always read the
                                 stored values.  Switching needs no new setup. */
-    int corrector;           /* 1: corrector mode (Sec. 3.1.1, Sec. 4; 3D): every level's velocity
+    int corrector;           /* 1: corrector mode (Sec. 3.1.1, Sec. 4): every level's velocity
                                 block is A + N + S with the terms of fsi_set_convection (needed on
                                 every level before fsi_setup), the Schur step is one BiCGStab
                                 iteration (ChebBiCGStab(1, 1)) instead of MINRES, the fused
@@ -222,16 +222,16 @@ fsi_status fsi_apply_stokes_f32(fsi_ctx* ctx, int level, const float* u, const f
 fsi_status fsi_apply_stokes_f32_noalloc(fsi_ctx* ctx, int level, const float* u, const float* p,
                                         float* v, float* q);
 
-/* Corrector-mode terms (3D): with the semi-implicit advection of the corrector
+/* Corrector-mode terms (2D and 3D): with the semi-implicit advection of the corrector
  * mode (Sec. 3.1.1: the form a_j with v* the unknown and v° known) and the
  * streamline term of Sec. 3.2, the velocity block becomes
  *   a(u, w) + (rho (grad u) v°, w) + sum_K (r (v° . grad u), (v° . grad w))_K.
- * vconv: device [N_c][Q][3] FP64, v° at the quadrature points (physical
+ * vconv: device [N_c][Q][dim] FP64, v° at the quadrature points (physical
  * components); r: device [N_c][Q] FP64, the streamline parameter (>= 0, e.g. the
  * Peclet law of Sec. 3.2, constant per cell); rho >= 0 the density.  Cells and
  * points as for fsi_set_coefficients.  Needs the level's geometry; a later
  * geometry change clears the terms (set them again).  Copies on the stream and
- * synchronises.  Errors: FSI_ERR_ARG (2D mesh, bad level or rho), FSI_ERR_STATE
+ * synchronises.  Errors: FSI_ERR_ARG (bad level or rho), FSI_ERR_STATE
  * (no geometry), FSI_ERR_NONFINITE (non-finite input or r < 0). */
 fsi_status fsi_set_convection(fsi_ctx* ctx, int level, const double* vconv, const double* r, double rho);
 /* Corrector-mode Stokes apply on one level: v = (A + N + S) u + B^T p, q = B u,

@@ -1287,12 +1287,11 @@ fsi_status fsi_set_convection(fsi_ctx* h, int level, const double* vconv, const 
     Context* ctx = &h->c;
     TRY(check_level(ctx, level));
     Level& L = ctx->lv[level];
-    if (L.dim != 3) return fail(ctx, FSI_ERR_ARG, "fsi_set_convection: the corrector terms are 3D only");
     if (!(rho >= 0.0) || !std::isfinite(rho)) return fail(ctx, FSI_ERR_ARG, "fsi_set_convection: rho must be >= 0");
     if (!L.geo_set) return fail(ctx, FSI_ERR_STATE, "fsi_set_convection before the level's geometry");
     const int64_t P = L.plane();
     if (!L.d_cb64) {
-        TRY(dalloc(ctx, &L.d_cb64, 3 * P));
+        TRY(dalloc(ctx, &L.d_cb64, 3 * P));   // dim planes used
         TRY(dalloc(ctx, &L.d_cs64, P));
         TRY(dalloc(ctx, &L.d_cb32, 3 * P));
         TRY(dalloc(ctx, &L.d_cs32, P));

@@ -210,8 +210,9 @@ __global__ void k_coefficients(int dim, int64_t nc, int Q, GeoLayout geo, int64_
 }
 
 // corrector-mode terms: per point (lexicographic cell, point) beta_b = sum_e K[b][e] v°_e
-// and sigma = r / (det J w), written into the geometry layout in FP64 and FP32
-__global__ void k_convection(int64_t nc, int Q, GeoLayout geo, int64_t plane, const int* __restrict__ lex2col,
+// and sigma = r / (det J w), written into the geometry layout in FP64 and FP32 (2D and 3D;
+// vconv holds dim components per point)
+__global__ void k_convection(int dim, int64_t nc, int Q, GeoLayout geo, int64_t plane, const int* __restrict__ lex2col,
                              const double* __restrict__ vconv, const double* __restrict__ r,
                              const double* __restrict__ K64, const double* __restrict__ cw,
                              double* __restrict__ cb64, double* __restrict__ cs64, float* __restrict__ cb32,
@@ -221,11 +222,17 @@ __global__ void k_convection(int64_t nc, int Q, GeoLayout geo, int64_t plane, co
     const int64_t cell = id / Q;
     const int q = (int)(id - cell * Q);
     const int64_t off = geo_off(geo, q % 3, lex2col[cell], q / 3);
-    const double v0 = vconv[3 * id], v1 = vconv[3 * id + 1], v2 = vconv[3 * id + 2], rr = r[id];
-    if (!isfinite(v0) || !isfinite(v1) || !isfinite(v2) || !isfinite(rr) || !(rr >= 0.0)) flag[0] = 1;
-    for (int b = 0; b < 3; ++b) {
-        const double be = K64[(3 * b) * plane + off] * v0 + K64[(3 * b + 1) * plane + off] * v1 +
-                          K64[(3 * b + 2) * plane + off] * v2;
+    double v[3] = {0.0, 0.0, 0.0};
+    bool bad = false;
+    for (int e = 0; e < dim; ++e) {
+        v[e] = vconv[dim * id + e];
+        bad |= !isfinite(v[e]);
+    }
+    const double rr = r[id];
+    if (bad || !isfinite(rr) || !(rr >= 0.0)) flag[0] = 1;
+    for (int b = 0; b < dim; ++b) {
+        double be = 0.0;
+        for (int e = 0; e < dim; ++e) be += K64[(dim * b + e) * plane + off] * v[e];
         cb64[b * plane + off] = be;
         cb32[b * plane + off] = (float)be;
     }
@@ -235,7 +242,7 @@ __global__ void k_convection(int64_t nc, int Q, GeoLayout geo, int64_t plane, co
 }
 void launch_convection(const Level& L, const double* vconv, const double* r, double* cb64, double* cs64, float* cb32,
                        float* cs32, int* flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_convection, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, L.nc, L.Q, L.geo, L.plane(),
+    hipLaunchKernelGGL(k_convection, dim3(nblocks(L.nc * L.Q)), dim3(TPB), 0, s, L.dim, L.nc, L.Q, L.geo, L.plane(),
                        L.d_lex2col, vconv, r, L.d_K64, L.d_cw64, cb64, cs64, cb32, cs32, flag);
 }
 

@@ -943,8 +943,11 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
     constexpr bool BWD = (MODE & (OP_A | OP_BT)) != 0;
     constexpr bool CHEB = (MODE & OP_CHEB) != 0;
     constexpr bool RES = (MODE & OP_RES) != 0;
+    constexpr bool CONV = (MODE & OP_CONV) != 0;
     static_assert(!CHEB || MODE == (OP_A | OP_CHEB), "the Chebyshev epilogue goes with A alone");
     static_assert(!RES || MODE == (OP_A | OP_BT | OP_B | OP_RES), "the residual epilogue goes with the Stokes apply");
+    static_assert(!CONV || MODE == (OP_A | OP_CONV) || MODE == (OP_A | OP_BT | OP_B | OP_CONV),
+                  "the corrector terms go with A or the Stokes apply");
     constexpr bool SCALED = MODE == OP_A || MODE == (OP_A | OP_CHEB);   // K' = sqrt(cvisc) K, no cvisc plane
     __shared__ T sbuf[WPB][CPW][BUF];
     __shared__ double pbuf[(MODE & OP_B) ? WPB : 1][CPW][NT][4];
@@ -1055,6 +1058,13 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
             for (int aa = 0; aa < 2; ++aa) Km[b][aa] = act ? gload<NTL>(a.K + (b * 2 + aa) * P + off) : T(0);
         T Tm[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
         divq[qx] = T(0);
+        // corrector terms: with beta = K v°, (grad-hat u_c) . beta = det(J) w (v° . grad u_c)
+        T be[2] = {T(0), T(0)}, sg = T(0), cvc[2] = {T(0), T(0)};
+        if constexpr (CONV) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b) be[b] = act ? gload<NTL>(a.cb + b * P + off) : T(0);
+            sg = act ? gload<NTL>(a.cs + off) : T(0);
+        }
         if constexpr (FWD) {
             T H[2][2];
 #pragma unroll
@@ -1072,6 +1082,13 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
                 Tm[1][0] = e01;
 #pragma unroll
                 for (int c = 0; c < 2; ++c) Fv[c][qx] = cmass * val[c][qx];
+                if constexpr (CONV) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        cvc[c] = g0[c][qx] * be[0] + g1[c][qx] * be[1];
+                        Fv[c][qx] += a.rho * cvc[c];   // rho (v° . grad u_c) det(J) w, tested with phi
+                    }
+                }
             }
         }
         if constexpr ((MODE & OP_A) == 0) {
@@ -1087,6 +1104,10 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
             for (int c = 0; c < 2; ++c) {
                 F0[c][qx] = Tm[c][0] * Km[0][0] + Tm[c][1] * Km[0][1];
                 F1[c][qx] = Tm[c][0] * Km[1][0] + Tm[c][1] * Km[1][1];
+                if constexpr (CONV) {   // streamline term, tested with (grad-hat w_c) . beta / (det J w)
+                    F0[c][qx] += sg * cvc[c] * be[0];
+                    F1[c][qx] += sg * cvc[c] * be[1];
+                }
             }
         }
     }
@@ -1253,7 +1274,7 @@ static void launch_one(const Level& L, const CellArgs<T>& args, hipStream_t s) {
         }
         hipLaunchKernelGGL((cell3d<T, MODE, WPB, RS, NTL, WPE, false, ZG>), dim3((unsigned)grid), dim3(64 * WPB), 0, s,
                            args);
-    } else if constexpr ((MODE & (OP_CONV | OP_ATOM)) == 0) {   // the corrector terms and the atomic form are 3D only
+    } else if constexpr ((MODE & OP_ATOM) == 0) {   // the atomic form is 3D only
         constexpr int W2 = WPB > 1 ? 2 : 1;   // 2D: one row per wavefront, at most two
         const int64_t grid = (args.nrows + W2 - 1) / W2;   // one wavefront per row of cells
         hipLaunchKernelGGL((cell2d<T, MODE, W2, false, NTL>), dim3((unsigned)grid), dim3(64 * W2), 0, s, args);
