@@ -303,7 +303,7 @@ fsi_status fsi_fixed_values(fsi_ctx* ctx, const double* v, double* g);
  * reference geometry, c_m = 0, eta = mu_A / 2), and fsi_gcsi_displacement once more for
  * the displacement recovery.  Fields are finest-level nodal arrays of the reference
  * mesh (the pull-backs u^{n,i} of Sec. 3.1 have the stored nodal values), device FP64,
- * component-major [3][n_vel_nodes].  3D contexts only.
+ * component-major [dim][n_vel_nodes]; 2D and 3D contexts.
  * Physical data: BDF order k (Sec. 3.1: k = 1 gamma = 1, alpha_1 = -1; k = 2
  * gamma = 2/3, alpha_1 = -4/3, alpha_2 = 1/3), time step tau, densities, fluid
  * viscosity eta_f, solid shear modulus mu_s (solid viscosity gamma tau mu_s, Sec. 3.1.1),
@@ -323,19 +323,19 @@ typedef struct {
 
 /* Velocity splitting (Sec. 3.1.1): u_out = gamma tau w - sum_i alpha_i u_i (the
  * explicit displacement u# from w#, and the displacement recovery from w^n), and, if
- * disp_out is not NULL, its vertex values [3][n_vert] for fsi_set_displacement (the
+ * disp_out is not NULL, its vertex values [dim][n_vert] for fsi_set_displacement (the
  * multilinear map through the vertex values of the Q2 field).  u2 is read for k = 2
  * only.  Either output may be NULL.  Errors: FSI_ERR_ARG. */
 fsi_status fsi_gcsi_displacement(fsi_ctx* ctx, const fsi_gcsi_params* prm, const double* w, const double* u1,
                                  const double* u2, double* u_out, double* disp_out);
 /* Coefficients of the stress splitting on every level, c_m = rho / (gamma tau) and
  * eta = eta_f (fluid) or gamma tau mu_s (solid), then as fsi_set_coefficients.
- * solid_q: HOST array of n_levels DEVICE pointers, each [n_cells][27] uint8 of that
+ * solid_q: HOST array of n_levels DEVICE pointers, each [n_cells][3^dim] uint8 of that
  * level (nonzero: the point lies in the solid).  Call after every geometry change.
  * Errors: as fsi_set_coefficients. */
 fsi_status fsi_gcsi_set_coefficients(fsi_ctx* ctx, const fsi_gcsi_params* prm, const uint8_t* const* solid_q);
 /* Right-hand side of the M-mode system on the finest level (eq. form_g_j, eq. form_g_p),
- * on the explicit geometry given by its vertex displacement disp ([3][n_vert]):
+ * on the explicit geometry given by its vertex displacement disp ([dim][n_vert]):
  *   g_u(v) = (rho (body - (1/(gamma tau)) sum_i alpha_i v_i), v)
  *            - [predictor] (rho (grad v*) v°, v)        v* = 2 v1 - v2,
  *                                                       v° = 2 (v1 - w1) - (v2 - w2)
@@ -345,8 +345,8 @@ fsi_status fsi_gcsi_set_coefficients(fsi_ctx* ctx, const fsi_gcsi_params* prm, c
  * (readings: the explicit solid stress as the velocity splitting substituted into the
  * solid stress of Sec. 2.3, sign -2 eps(..) where the paper prints +; v° extrapolates
  * the relative velocity, with w2 in its second term where the paper prints w1; the
- * predictor's convective term explicit as a whole).  solid_q: DEVICE [n_cells][27]
- * uint8 of the finest level.  Dirichlet rows of g_u are zero.  Sums with atomics (the
+ * predictor's convective term explicit as a whole).  solid_q: DEVICE [n_cells][3^dim]
+ * uint8 of the finest level; body[2] is not read in 2D.  Dirichlet rows of g_u are zero.  Sums with atomics (the
  * last bits vary from run to run).  u2, v2, w2 are read for k = 2, w1 and w2 in the
  * predictor mode only.  Errors: FSI_ERR_ARG. */
 fsi_status fsi_gcsi_rhs(fsi_ctx* ctx, const fsi_gcsi_params* prm, int mode, const uint8_t* solid_q,

@@ -1740,12 +1740,11 @@ struct Bdf {
 };
 static fsi_status gcsi_check(Context* ctx, const fsi_gcsi_params* p, Bdf* b) {
     if (!p) return FSI_ERR_ARG;
-    if (ctx->lv[0].dim != 3) return fail(ctx, FSI_ERR_ARG, "the time-step kernels are 3D only");
     if (p->k != 1 && p->k != 2) return fail(ctx, FSI_ERR_ARG, "BDF order k must be 1 or 2");
     auto fin = [](double x) { return std::isfinite(x); };
     if (!(p->tau > 0) || !fin(p->tau) || !(p->rho_f >= 0) || !fin(p->rho_f) || !(p->rho_s >= 0) || !fin(p->rho_s) ||
         !(p->eta_f > 0) || !fin(p->eta_f) || !(p->mu_s >= 0) || !fin(p->mu_s) || std::isnan(p->eta_V) ||
-        !fin(p->body[0]) || !fin(p->body[1]) || !fin(p->body[2]))
+        !fin(p->body[0]) || !fin(p->body[1]) || (ctx->lv[0].dim == 3 && !fin(p->body[2])))
         return fail(ctx, FSI_ERR_ARG, "invalid time-step parameters");
     // BDF stencil of Sec. 3.1 (alpha_0 = 1)
     if (p->k == 1) *b = {1.0, -1.0, 0.0};
@@ -1767,7 +1766,8 @@ fsi_status fsi_gcsi_displacement(fsi_ctx* h, const fsi_gcsi_params* prm, const d
 }
 
 static fsi_status gcsi_scratch(Context* ctx) {
-    if (!ctx->gcsi_tmp) TRY(dalloc(ctx, &ctx->gcsi_tmp, 4 * ctx->lv[ctx->nlev - 1].nc * 27));
+    const Level& F = ctx->lv[ctx->nlev - 1];
+    if (!ctx->gcsi_tmp) TRY(dalloc(ctx, &ctx->gcsi_tmp, (F.dim + 1) * F.nc * F.Q));
     return FSI_OK;
 }
 
@@ -1782,7 +1782,7 @@ fsi_status fsi_gcsi_set_coefficients(fsi_ctx* h, const fsi_gcsi_params* prm, con
     const double gt = b.gamma * prm->tau;
     for (int j = 0; j < ctx->nlev; ++j) {
         Level& L = ctx->lv[j];
-        const int64_t n = L.nc * 27;
+        const int64_t n = L.nc * L.Q;
         if (!L.d_gcsi_eta) TRY(dalloc(ctx, &L.d_gcsi_eta, n));
         launch_gcsi_coefficients(solid_q[j], prm->rho_f / gt, prm->rho_s / gt, prm->eta_f, gt * prm->mu_s,
                                  ctx->gcsi_tmp, L.d_gcsi_eta, n, ctx->stream);
@@ -1839,7 +1839,7 @@ fsi_status fsi_gcsi_rhs(fsi_ctx* h, const fsi_gcsi_params* prm, int mode, const 
     a.g_p = g_p;
     launch_fill<double>(g_u, 0.0, F.nv, ctx->stream);
     launch_fill<double>(g_p, 0.0, F.np, ctx->stream);
-    launch_gcsi_rhs(a, F.nc, ctx->stream);
+    launch_gcsi_rhs(a, F.dim, F.nc, ctx->stream);
     return FSI_OK;
 }
 
@@ -1858,7 +1858,7 @@ fsi_status fsi_gcsi_set_convection(fsi_ctx* h, const fsi_gcsi_params* prm, const
     for (int j = 0; j <= J; ++j) {
         const Level& L = ctx->lv[j];
         double* vconv = ctx->gcsi_tmp;
-        double* r = vconv + 3 * L.nc * 27;
+        double* r = vconv + (int64_t)L.dim * L.nc * L.Q;
         launch_gcsi_convection(L, F, v_hash, w_hash, L.d_gcsi_eta, 1 << (J - j), vconv, r, ctx->stream);
         TRY(fsi_set_convection(h, j, vconv, r, prm->rho_f));
     }

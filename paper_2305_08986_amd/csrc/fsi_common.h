@@ -456,7 +456,7 @@ struct GcsiRhsArgs {
     int64_t nvn, nvert;
     double h[3];
     const double* disp;                   // [3][n_vert] vertex displacement of the explicit geometry
-    const uint8_t* solid;                 // [n_cells][27]
+    const uint8_t* solid;                 // [n_cells][3^dim]
     const uint8_t* wall;                  // [n_vel_nodes] Dirichlet rows (left zero)
     const double *uh, *u1, *u2, *v1, *v2, *w1, *w2;
     double a1, a2, gt;                    // BDF alpha_1, alpha_2 and gamma tau
@@ -466,7 +466,7 @@ struct GcsiRhsArgs {
     double* g_u;                          // zeroed, accumulated with atomics
     double* g_p;
 };
-void launch_gcsi_rhs(const GcsiRhsArgs& a, int64_t nc, hipStream_t s);
+void launch_gcsi_rhs(const GcsiRhsArgs& a, int dim, int64_t nc, hipStream_t s);
 // v° = v# - w# at the Gauss points of level L ([n_cells][27][3]) and the streamline
 // parameter ([n_cells][27]); the fine-level fields are read at L's nodes (stride)
 void launch_gcsi_convection(const Level& L, const Level& F, const double* vh, const double* wh, const double* eta,

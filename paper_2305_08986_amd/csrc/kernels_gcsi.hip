@@ -67,22 +67,38 @@ __global__ void k_fixed_values(const uint8_t* __restrict__ fixed, const double* 
     g[i] = fixed[i % nvn] ? v[i] : 0.0;
 }
 
-// right-hand side: one 64-thread workgroup per cell (3D).  Threads 0..26 load the
-// cell's nodal combinations and then own one Gauss point each (Jacobian of the
-// multilinear map through the vertex displacement, physical gradients, the integrands
-// scaled by det(J) w), then one test node each (sum over the points, atomic add into
-// g_u, wall rows left zero); threads 27..34 own the cell's vertices (g_p).
+// right-hand side: one 64-thread workgroup per cell.  Threads 0..NL-1 (NL = 3^dim local
+// nodes and as many Gauss points) load the cell's nodal combinations and then own one Gauss
+// point each (Jacobian of the multilinear map through the vertex displacement, physical
+// gradients, the integrands scaled by det(J) w), then one test node each (sum over the
+// points, atomic add into g_u, wall rows left zero); threads NL..NL+2^dim-1 own the cell's
+// vertices (g_p).
+template <int DIM>
 __global__ __launch_bounds__(64) void k_gcsi_rhs(GcsiRhsArgs a) {
+    constexpr int NL = DIM == 3 ? 27 : 9, NV = DIM == 3 ? 8 : 4;
     const int64_t c = blockIdx.x;
     const int t = threadIdx.x;
-    const int64_t cx = c % a.nx, cy = (c / a.nx) % a.ny, cz = c / ((int64_t)a.nx * a.ny);
+    const int64_t cx = c % a.nx, cy = (c / a.nx) % a.ny, cz = DIM == 3 ? c / ((int64_t)a.nx * a.ny) : 0;
     __shared__ double s_uh[3][27], s_us[3][27], s_vs[3][27], s_vt[3][27], s_vc[3][27];
     __shared__ double s_d[3][8];
     __shared__ double s_F[27][3], s_T[27][9], s_Ji[27][9], s_gp[27];
-    if (t < 27) {
-        const int lx = t % 3, ly = (t / 3) % 3, lz = t / 9;
-        const int64_t node = (2 * cx + lx) + (int64_t)a.vnx * ((2 * cy + ly) + (int64_t)a.vny * (2 * cz + lz));
-        for (int k = 0; k < 3; ++k) {
+    auto loc = [](int i, int& ix, int& iy, int& iz) {
+        ix = i % 3;
+        iy = (i / 3) % 3;
+        iz = DIM == 3 ? i / 9 : 0;
+    };
+    auto node_of = [&](int i) -> int64_t {
+        int ix, iy, iz;
+        loc(i, ix, iy, iz);
+        return (2 * cx + ix) + (int64_t)a.vnx * ((2 * cy + iy) + (int64_t)a.vny * (2 * cz + iz));
+    };
+    auto vertex_of = [&](int v) -> int64_t {
+        const int vx = v & 1, vy = (v >> 1) & 1, vz = DIM == 3 ? v >> 2 : 0;
+        return (cx + vx) + (int64_t)a.pnx * ((cy + vy) + (int64_t)a.pny * (cz + vz));
+    };
+    if (t < NL) {
+        const int64_t node = node_of(t);
+        for (int k = 0; k < DIM; ++k) {
             const int64_t n = k * a.nvn + node;
             s_uh[k][t] = a.uh[n];
             s_us[k][t] = a.a1 * a.u1[n] + (a.u2 ? a.a2 * a.u2[n] : 0.0);
@@ -99,85 +115,105 @@ __global__ __launch_bounds__(64) void k_gcsi_rhs(GcsiRhsArgs a) {
                 }
             }
         }
-    } else if (t < 35) {
-        const int v = t - 27;
-        const int64_t vtx = (cx + (v & 1)) + (int64_t)a.pnx * ((cy + ((v >> 1) & 1)) + (int64_t)a.pny * (cz + (v >> 2)));
-        for (int k = 0; k < 3; ++k) s_d[k][v] = a.disp[k * a.nvert + vtx];
+    } else if (t < NL + NV) {
+        const int v = t - NL;
+        const int64_t vtx = vertex_of(v);
+        for (int k = 0; k < DIM; ++k) s_d[k][v] = a.disp[k * a.nvert + vtx];
     }
     __syncthreads();
-    if (t < 27) {
-        const int q = t, qx = q % 3, qy = (q / 3) % 3, qz = q / 9;
+    if (t < NL) {
+        const int q = t;
+        int qx, qy, qz;
+        loc(q, qx, qy, qz);
         // J[r][b] = h_r d_rb + sum_v d_v[r] d psi_v / d xi_b
-        double J[3][3] = {{a.h[0], 0, 0}, {0, a.h[1], 0}, {0, 0, a.h[2]}};
-        for (int v = 0; v < 8; ++v) {
-            const int vx = v & 1, vy = (v >> 1) & 1, vz = v >> 2;
-            const double Lx = Tab::L[qx][vx], Ly = Tab::L[qy][vy], Lz = Tab::L[qz][vz];
+        double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int r = 0; r < DIM; ++r) J[r][r] = a.h[r];
+        for (int v = 0; v < NV; ++v) {
+            const int vx = v & 1, vy = (v >> 1) & 1, vz = DIM == 3 ? v >> 2 : 0;
+            const double Lx = Tab::L[qx][vx], Ly = Tab::L[qy][vy], Lz = DIM == 3 ? Tab::L[qz][vz] : 1.0;
             const double dp[3] = {(vx ? 1.0 : -1.0) * Ly * Lz, Lx * (vy ? 1.0 : -1.0) * Lz, Lx * Ly * (vz ? 1.0 : -1.0)};
-            for (int r = 0; r < 3; ++r)
-                for (int b = 0; b < 3; ++b) J[r][b] += s_d[r][v] * dp[b];
+            for (int r = 0; r < DIM; ++r)
+                for (int b = 0; b < DIM; ++b) J[r][b] += s_d[r][v] * dp[b];
         }
-        double adj[3][3];
-        adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-        adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-        adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-        adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-        adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-        adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-        adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-        adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-        adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
-        const double idet = 1.0 / det;
-        double Ji[3][3];                            // Ji[b][x] = d xi_b / d x_x
-        for (int b = 0; b < 3; ++b)
-            for (int x = 0; x < 3; ++x) Ji[b][x] = adj[b][x] * idet;
-        const double wq = Tab::W[qx] * Tab::W[qy] * Tab::W[qz];
+        double Ji[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // Ji[b][x] = d xi_b / d x_x
+        double det;
+        if constexpr (DIM == 3) {
+            double adj[3][3];
+            adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+            adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+            adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+            adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+            adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+            adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+            adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+            adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+            adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+            const double idet = 1.0 / det;
+            for (int b = 0; b < 3; ++b)
+                for (int x = 0; x < 3; ++x) Ji[b][x] = adj[b][x] * idet;
+        } else {
+            det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            const double idet = 1.0 / det;
+            Ji[0][0] = J[1][1] * idet;
+            Ji[0][1] = -J[0][1] * idet;
+            Ji[1][0] = -J[1][0] * idet;
+            Ji[1][1] = J[0][0] * idet;
+        }
+        const double wq = Tab::W[qx] * Tab::W[qy] * (DIM == 3 ? Tab::W[qz] : 1.0);
         const double wd = wq * det;
         // reference gradients (d / d xi_b) and point values
         double guh[3][3] = {}, gus[3][3] = {}, gvt[3][3] = {}, vs[3] = {}, vc[3] = {};
-        for (int i = 0; i < 27; ++i) {
-            const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
-            const double sx = Tab::S[qx][ix], sy = Tab::S[qy][iy], sz = Tab::S[qz][iz];
-            const double dphi[3] = {Tab::D[qx][ix] * sy * sz, sx * Tab::D[qy][iy] * sz, sx * sy * Tab::D[qz][iz]};
+        for (int i = 0; i < NL; ++i) {
+            int ix, iy, iz;
+            loc(i, ix, iy, iz);
+            const double sx = Tab::S[qx][ix], sy = Tab::S[qy][iy], sz = DIM == 3 ? Tab::S[qz][iz] : 1.0;
+            const double dphi[3] = {Tab::D[qx][ix] * sy * sz, sx * Tab::D[qy][iy] * sz,
+                                    DIM == 3 ? sx * sy * Tab::D[qz][iz] : 0.0};
             const double phi = sx * sy * sz;
-            for (int k = 0; k < 3; ++k) {
+            for (int k = 0; k < DIM; ++k) {
                 vs[k] += phi * s_vs[k][i];
-                for (int b = 0; b < 3; ++b) {
+                for (int b = 0; b < DIM; ++b) {
                     guh[k][b] += s_uh[k][i] * dphi[b];
                     gus[k][b] += s_us[k][i] * dphi[b];
                 }
                 if (a.predictor) {
                     vc[k] += phi * s_vc[k][i];
-                    for (int b = 0; b < 3; ++b) gvt[k][b] += s_vt[k][i] * dphi[b];
+                    for (int b = 0; b < DIM; ++b) gvt[k][b] += s_vt[k][i] * dphi[b];
                 }
             }
         }
         // physical gradients: P[k][x] = sum_b R[k][b] Ji[b][x]
-        double gh[3][3], gs[3][3];
-        for (int k = 0; k < 3; ++k)
-            for (int x = 0; x < 3; ++x) {
-                gh[k][x] = guh[k][0] * Ji[0][x] + guh[k][1] * Ji[1][x] + guh[k][2] * Ji[2][x];
-                gs[k][x] = gus[k][0] * Ji[0][x] + gus[k][1] * Ji[1][x] + gus[k][2] * Ji[2][x];
-            }
-        const bool solid = a.solid[c * 27 + q] != 0;
+        double gh[3][3] = {}, gs[3][3] = {};
+        for (int k = 0; k < DIM; ++k)
+            for (int x = 0; x < DIM; ++x)
+                for (int b = 0; b < DIM; ++b) {
+                    gh[k][x] += guh[k][b] * Ji[b][x];
+                    gs[k][x] += gus[k][b] * Ji[b][x];
+                }
+        const bool solid = a.solid[c * NL + q] != 0;
         const double rho = solid ? a.rho_s : a.rho_f;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < DIM; ++k) {
             double f = rho * (a.body[k] - vs[k] / a.gt);
             if (a.predictor) {
                 double cv = 0.0;
-                for (int x = 0; x < 3; ++x) {
-                    const double gv = gvt[k][0] * Ji[0][x] + gvt[k][1] * Ji[1][x] + gvt[k][2] * Ji[2][x];
+                for (int x = 0; x < DIM; ++x) {
+                    double gv = 0.0;
+                    for (int b = 0; b < DIM; ++b) gv += gvt[k][b] * Ji[b][x];
                     cv += gv * vc[x];
                 }
                 f -= rho * cv;
             }
             s_F[q][k] = wd * f;
         }
-        for (int k = 0; k < 3; ++k)
-            for (int x = 0; x < 3; ++x) {
+        for (int k = 0; k < DIM; ++k)
+            for (int x = 0; x < DIM; ++x) {
                 double T = 0.0;
-                if (solid)
-                    T = a.mu_s * (gs[k][x] + gs[x][k] + gh[0][k] * gh[0][x] + gh[1][k] * gh[1][x] + gh[2][k] * gh[2][x]);
+                if (solid) {
+                    double tq = 0.0;
+                    for (int b = 0; b < DIM; ++b) tq += gh[b][k] * gh[b][x];
+                    T = a.mu_s * (gs[k][x] + gs[x][k] + tq);
+                }
                 s_T[q][k * 3 + x] = wd * T;
                 s_Ji[q][k * 3 + x] = Ji[k][x];
             }
@@ -185,42 +221,55 @@ __global__ __launch_bounds__(64) void k_gcsi_rhs(GcsiRhsArgs a) {
         double gp = 0.0;
         if (solid && a.inv_etaV > 0.0) {
             double F[3][3];
-            for (int k = 0; k < 3; ++k)
-                for (int b = 0; b < 3; ++b) F[k][b] = (k == b ? 1.0 : 0.0) + guh[k][b] / a.h[b];
-            const double Jh = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) -
-                              F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
-                              F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
-            gp = -a.inv_etaV * (Jh - 1.0) * wq * a.h[0] * a.h[1] * a.h[2];
+            for (int k = 0; k < DIM; ++k)
+                for (int b = 0; b < DIM; ++b) F[k][b] = (k == b ? 1.0 : 0.0) + guh[k][b] / a.h[b];
+            double Jh, hv;
+            if constexpr (DIM == 3) {
+                Jh = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+                     F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+                hv = a.h[0] * a.h[1] * a.h[2];
+            } else {
+                Jh = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+                hv = a.h[0] * a.h[1];
+            }
+            gp = -a.inv_etaV * (Jh - 1.0) * wq * hv;
         }
         s_gp[q] = gp;
     }
     __syncthreads();
-    if (t < 27) {
-        const int i = t, ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
+    if (t < NL) {
+        const int i = t;
+        int ix, iy, iz;
+        loc(i, ix, iy, iz);
         double acc[3] = {0.0, 0.0, 0.0};
-        for (int q = 0; q < 27; ++q) {
-            const int qx = q % 3, qy = (q / 3) % 3, qz = q / 9;
-            const double sx = Tab::S[qx][ix], sy = Tab::S[qy][iy], sz = Tab::S[qz][iz];
-            const double dphi[3] = {Tab::D[qx][ix] * sy * sz, sx * Tab::D[qy][iy] * sz, sx * sy * Tab::D[qz][iz]};
+        for (int q = 0; q < NL; ++q) {
+            int qx, qy, qz;
+            loc(q, qx, qy, qz);
+            const double sx = Tab::S[qx][ix], sy = Tab::S[qy][iy], sz = DIM == 3 ? Tab::S[qz][iz] : 1.0;
+            const double dphi[3] = {Tab::D[qx][ix] * sy * sz, sx * Tab::D[qy][iy] * sz,
+                                    DIM == 3 ? sx * sy * Tab::D[qz][iz] : 0.0};
             const double phi = sx * sy * sz;
-            double gx[3];
-            for (int x = 0; x < 3; ++x)
-                gx[x] = dphi[0] * s_Ji[q][x] + dphi[1] * s_Ji[q][3 + x] + dphi[2] * s_Ji[q][6 + x];
-            for (int k = 0; k < 3; ++k)
-                acc[k] += s_F[q][k] * phi + s_T[q][k * 3] * gx[0] + s_T[q][k * 3 + 1] * gx[1] + s_T[q][k * 3 + 2] * gx[2];
+            double gx[3] = {0.0, 0.0, 0.0};
+            for (int x = 0; x < DIM; ++x)
+                for (int b = 0; b < DIM; ++b) gx[x] += dphi[b] * s_Ji[q][b * 3 + x];
+            for (int k = 0; k < DIM; ++k) {
+                double sacc = s_F[q][k] * phi;
+                for (int x = 0; x < DIM; ++x) sacc += s_T[q][k * 3 + x] * gx[x];
+                acc[k] += sacc;
+            }
         }
-        const int64_t node = (2 * cx + ix) + (int64_t)a.vnx * ((2 * cy + iy) + (int64_t)a.vny * (2 * cz + iz));
+        const int64_t node = node_of(i);
         if (!a.wall[node])
-            for (int k = 0; k < 3; ++k) atomicAdd(&a.g_u[k * a.nvn + node], acc[k]);
-    } else if (t < 35 && a.inv_etaV > 0.0) {
-        const int v = t - 27, vx = v & 1, vy = (v >> 1) & 1, vz = v >> 2;
+            for (int k = 0; k < DIM; ++k) atomicAdd(&a.g_u[k * a.nvn + node], acc[k]);
+    } else if (t < NL + NV && a.inv_etaV > 0.0) {
+        const int v = t - NL, vx = v & 1, vy = (v >> 1) & 1, vz = DIM == 3 ? v >> 2 : 0;
         double acc = 0.0;
-        for (int q = 0; q < 27; ++q) {
-            const int qx = q % 3, qy = (q / 3) % 3, qz = q / 9;
-            acc += s_gp[q] * Tab::L[qx][vx] * Tab::L[qy][vy] * Tab::L[qz][vz];
+        for (int q = 0; q < NL; ++q) {
+            int qx, qy, qz;
+            loc(q, qx, qy, qz);
+            acc += s_gp[q] * Tab::L[qx][vx] * Tab::L[qy][vy] * (DIM == 3 ? Tab::L[qz][vz] : 1.0);
         }
-        const int64_t vtx = (cx + vx) + (int64_t)a.pnx * ((cy + vy) + (int64_t)a.pny * (cz + vz));
-        atomicAdd(&a.g_p[vtx], acc);
+        atomicAdd(&a.g_p[vertex_of(v)], acc);
     }
 }
 
@@ -228,47 +277,53 @@ __global__ __launch_bounds__(64) void k_gcsi_rhs(GcsiRhsArgs a) {
 // level's nodes, stride s) at the Gauss points, and the Peclet-law streamline parameter
 // per cell (Sec. 3.2, p1 = 2): Pe = |v°|_max h_K / (2 eta_mean p1),
 // r = h_K / (2 |v°|_max p1) (coth Pe - 1/Pe) for Pe >= 1, else 0.  Two cells per
-// 64-thread workgroup, one Gauss point per thread.
+// 64-thread workgroup, one Gauss point per thread; vconv is [n_cells][3^dim][dim].
+template <int DIM>
 __global__ __launch_bounds__(64) void k_gcsi_conv(const double* __restrict__ vh, const double* __restrict__ wh,
                                                   const double* __restrict__ eta, int nx, int ny, int64_t nc,
                                                   int stride, int vnx_f, int vny_f, int64_t nvn_f, double hK,
                                                   double* __restrict__ vconv, double* __restrict__ r) {
+    constexpr int NL = DIM == 3 ? 27 : 9;
     const int half = threadIdx.x >> 5, t = threadIdx.x & 31;
     const int64_t c = (int64_t)blockIdx.x * 2 + half;
     __shared__ double s_v[2][3][27];
     __shared__ double s_m[2][27], s_e[2][27];
     const bool on = c < nc;
-    const int64_t cx = on ? c % nx : 0, cy = on ? (c / nx) % ny : 0, cz = on ? c / ((int64_t)nx * ny) : 0;
-    if (on && t < 27) {
-        const int lx = t % 3, ly = (t / 3) % 3, lz = t / 9;
+    const int64_t cx = on ? c % nx : 0, cy = on ? (c / nx) % ny : 0, cz = (on && DIM == 3) ? c / ((int64_t)nx * ny) : 0;
+    if (on && t < NL) {
+        const int lx = t % 3, ly = (t / 3) % 3, lz = DIM == 3 ? t / 9 : 0;
         const int64_t node = (int64_t)stride * (2 * cx + lx) +
                              (int64_t)vnx_f * ((int64_t)stride * (2 * cy + ly) + (int64_t)vny_f * stride * (2 * cz + lz));
-        for (int k = 0; k < 3; ++k) s_v[half][k][t] = vh[k * nvn_f + node] - wh[k * nvn_f + node];
+        for (int k = 0; k < DIM; ++k) s_v[half][k][t] = vh[k * nvn_f + node] - wh[k * nvn_f + node];
     }
     __syncthreads();
-    if (on && t < 27) {
-        const int q = t, qx = q % 3, qy = (q / 3) % 3, qz = q / 9;
+    if (on && t < NL) {
+        const int q = t, qx = q % 3, qy = (q / 3) % 3, qz = DIM == 3 ? q / 9 : 0;
         double v[3] = {0.0, 0.0, 0.0};
-        for (int i = 0; i < 27; ++i) {
-            const double phi = Tab::S[qx][i % 3] * Tab::S[qy][(i / 3) % 3] * Tab::S[qz][i / 9];
-            for (int k = 0; k < 3; ++k) v[k] += phi * s_v[half][k][i];
+        for (int i = 0; i < NL; ++i) {
+            const double phi = Tab::S[qx][i % 3] * Tab::S[qy][(i / 3) % 3] * (DIM == 3 ? Tab::S[qz][i / 9] : 1.0);
+            for (int k = 0; k < DIM; ++k) v[k] += phi * s_v[half][k][i];
         }
-        for (int k = 0; k < 3; ++k) vconv[(c * 27 + q) * 3 + k] = v[k];
-        s_m[half][q] = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        s_e[half][q] = eta[c * 27 + q];
+        double m2 = 0.0;
+        for (int k = 0; k < DIM; ++k) {
+            vconv[(c * NL + q) * DIM + k] = v[k];
+            m2 += v[k] * v[k];
+        }
+        s_m[half][q] = sqrt(m2);
+        s_e[half][q] = eta[c * NL + q];
     }
     __syncthreads();
-    if (on && t < 27) {
+    if (on && t < NL) {
         double vmax = 0.0, es = 0.0;
-        for (int q = 0; q < 27; ++q) {
+        for (int q = 0; q < NL; ++q) {
             vmax = fmax(vmax, s_m[half][q]);
             es += s_e[half][q];
         }
-        const double mu = es / 27.0, p1 = 2.0;
+        const double mu = es / NL, p1 = 2.0;
         const double pe = vmax * hK / (2.0 * mu * p1);
         double rr = 0.0;
         if (pe >= 1.0) rr = hK / (2.0 * vmax * p1) * (1.0 / tanh(pe) - 1.0 / pe);
-        r[c * 27 + t] = rr;
+        r[c * NL + t] = rr;
     }
 }
 
@@ -291,15 +346,22 @@ void launch_fixed_values(const Level& L, const uint8_t* fixed, const double* v, 
     hipLaunchKernelGGL(k_fixed_values, dim3(nblk(L.nv)), dim3(TPB_G), 0, s, fixed, v, g, L.nvn, L.nv);
 }
 
-void launch_gcsi_rhs(const GcsiRhsArgs& a, int64_t nc, hipStream_t s) {
-    hipLaunchKernelGGL(k_gcsi_rhs, dim3((unsigned)nc), dim3(64), 0, s, a);
+void launch_gcsi_rhs(const GcsiRhsArgs& a, int dim, int64_t nc, hipStream_t s) {
+    if (dim == 3) hipLaunchKernelGGL(k_gcsi_rhs<3>, dim3((unsigned)nc), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL(k_gcsi_rhs<2>, dim3((unsigned)nc), dim3(64), 0, s, a);
 }
 
 void launch_gcsi_convection(const Level& L, const Level& F, const double* vh, const double* wh, const double* eta,
                             int stride, double* vconv, double* r, hipStream_t s) {
-    const double hK = sqrt(L.h[0] * L.h[0] + L.h[1] * L.h[1] + L.h[2] * L.h[2]);
-    hipLaunchKernelGGL(k_gcsi_conv, dim3((unsigned)((L.nc + 1) / 2)), dim3(64), 0, s, vh, wh, eta, L.cells[0],
-                       L.cells[1], L.nc, stride, F.vnodes[0], F.vnodes[1], F.nvn, hK, vconv, r);
+    double h2 = 0.0;
+    for (int d = 0; d < L.dim; ++d) h2 += L.h[d] * L.h[d];
+    const double hK = sqrt(h2);
+    if (L.dim == 3)
+        hipLaunchKernelGGL(k_gcsi_conv<3>, dim3((unsigned)((L.nc + 1) / 2)), dim3(64), 0, s, vh, wh, eta, L.cells[0],
+                           L.cells[1], L.nc, stride, F.vnodes[0], F.vnodes[1], F.nvn, hK, vconv, r);
+    else
+        hipLaunchKernelGGL(k_gcsi_conv<2>, dim3((unsigned)((L.nc + 1) / 2)), dim3(64), 0, s, vh, wh, eta, L.cells[0],
+                           L.cells[1], L.nc, stride, F.vnodes[0], F.vnodes[1], F.nvn, hK, vconv, r);
 }
 
 }  // namespace fsi

@@ -409,7 +409,7 @@ class Context:
         return out, disp
 
     def gcsi_set_coefficients(self, prm: GcsiParams, solid_q):
-        """solid_q: per level, a device uint8 tensor [n_cells][27]."""
+        """solid_q: per level, a device uint8 tensor [n_cells][3^dim]."""
         arr = (C.c_void_p * len(solid_q))(*[_ptr(x) for x in solid_q])
         self._check(self.lib.fsi_gcsi_set_coefficients(self.h, C.byref(prm), arr))
 

@@ -46,8 +46,9 @@ class Stepper:
         self.J = J
         sz = self.stokes.sizes(J)
         self.nv, self.np, self.nvert = sz["n_vel"], sz["n_p"], sz["n_vert"]
+        self.dim = inputs.mesh.dim
         dev = dict(device="cuda", dtype=torch.float64)
-        self.ext.set_displacement(torch.zeros(3 * self.nvert, **dev))
+        self.ext.set_displacement(torch.zeros(self.dim * self.nvert, **dev))
         for j in range(self.ext.n_levels):
             mu = torch.as_tensor(inputs.mu_A[j], **dev)
             self.ext.set_coefficients(j, torch.zeros_like(mu), 0.5 * mu)
@@ -58,7 +59,7 @@ class Stepper:
         d = getattr(inputs, "dirichlet", None)
         self.dirichlet = None if d is None else torch.as_tensor(d, **dev).contiguous()
         self.u_hash = torch.empty(self.nv, **dev)
-        self.disp = torch.empty(3 * self.nvert, **dev)
+        self.disp = torch.empty(self.dim * self.nvert, **dev)
         self.g_u = torch.empty(self.nv, **dev)
         self.g_p = torch.empty(self.np, **dev)
         self.g_ext = torch.empty(self.nv, **dev)

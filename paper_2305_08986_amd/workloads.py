@@ -425,23 +425,30 @@ def random_vector(n: int, seed_key) -> np.ndarray:
 # One step of the GCSI_2(P, C) scheme (Algorithm 1) on a channel with an elastic strip:
 # the box [0, 2] x [0, 0.5] x [0, 0.5] (no-slip walls, x+ a do-nothing outflow) with a
 # solid strip [0.5, 1.25] x [0.125, 0.25] spanning the channel depth (clamped by the
-# z walls), cell-aligned on every level.  Material constants follow the FSI2-type
+# z walls), cell-aligned on every level; the 2D cases are the x-y section of the same
+# channel (the strip a rectangle attached to nothing, as the FSI2/FSI3-type flag is a
+# rectangle in a 2D channel).  Material constants follow the FSI2-type
 # setting of Sec. 5 (rho_f = 1e3, eta_f = 1, rho_s = 1e4, mu_s = 5e5, gravity 2 in -y,
 # tau = 0.005, the volume-correction parameter 0.1); the extension coefficient is the law
 # of Sec. 5 centred at the strip's tip.  The history (u, v, w at the two previous steps,
 # the last pressure) is a set of smooth seeded fields vanishing on every face: four
 # sine modes per field (as the displacement law), amplitude 0.005 for displacements and
-# 0.5 for velocities; w takes the values of v on every node of a solid cell (the mesh
-# moves with the solid).
+# 0.5 for velocities; the mesh velocity w blends from v on the strip (the mesh moves with
+# the solid) to its own sine field over the distance GCSI_BLEND from the strip, with the
+# weight 1 - 3t^2 + 2t^3 of t = distance / GCSI_BLEND (continuous, so that the explicit
+# geometry gamma tau w stays unfolded on fine meshes).
 GCSI_STREAM = 11
 GCSI_CONFIGS = {
     "G1": dict(n=(16, 4, 4), n_coarse=(8, 2, 2)),
     "G2": dict(n=(128, 32, 32), n_coarse=(8, 2, 2)),
     "G3": dict(n=(256, 64, 64), n_coarse=(8, 2, 2)),
+    "G1_2D": dict(n=(32, 8), n_coarse=(8, 2)),
+    "G2_2D": dict(n=(1024, 256), n_coarse=(8, 2)),
 }
 GCSI_EXTENT = (2.0, 0.5, 0.5)
+GCSI_BLEND = 0.1
 GCSI_STRIP = ((0.5, 1.25), (0.125, 0.25), (0.0, 0.5))
-GCSI_CONFIG_INDEX = {"G1": 20, "G2": 21, "G3": 22}
+GCSI_CONFIG_INDEX = {"G1": 20, "G2": 21, "G3": 22, "G1_2D": 23, "G2_2D": 24}
 GCSI_MATERIAL = dict(k=2, tau=0.005, rho_f=1e3, rho_s=1e4, eta_f=1.0, mu_s=5e5, eta_V=0.1,
                      body=(0.0, -2.0, 0.0))
 
@@ -463,9 +470,20 @@ class GcsiInputs:
 
 def _inside_strip(X: np.ndarray) -> np.ndarray:
     m = np.ones(X.shape[:-1], dtype=bool)
-    for d, (lo, hi) in enumerate(GCSI_STRIP):
+    for d in range(X.shape[-1]):
+        lo, hi = GCSI_STRIP[d]
         m &= (X[..., d] >= lo) & (X[..., d] <= hi)
     return m
+
+
+def _strip_weight(X: np.ndarray) -> np.ndarray:
+    """1 on the strip, 0 beyond GCSI_BLEND from it, C^1 in between; X is [dim][n]."""
+    d2 = np.zeros(X.shape[1])
+    for d in range(X.shape[0]):
+        lo, hi = GCSI_STRIP[d]
+        d2 += np.maximum(np.maximum(lo - X[d], X[d] - hi), 0.0) ** 2
+    t = np.minimum(np.sqrt(d2) / GCSI_BLEND, 1.0)
+    return 1.0 - t * t * (3.0 - 2.0 * t)
 
 
 def make_gcsi_inputs(name: str = "G1", seed: int = BASE_SEED, inflow: float = 0.0) -> GcsiInputs:
@@ -474,19 +492,21 @@ def make_gcsi_inputs(name: str = "G1", seed: int = BASE_SEED, inflow: float = 0.
     Draw order (PCG64 ``[seed, config, GCSI_STREAM]``): sine modes of u^{n-1}, u^{n-2},
     v^{n-1}, v^{n-2}, w^{n-1}, w^{n-2}, then p (U[-1, 1]) at the pressure nodes.
     ``inflow`` > 0 adds Dirichlet data on the inflow face x = 0: the x-velocity
-    16 inflow y (H - y) z (W - z) / (H^2 W^2) (peak ``inflow`` at the centre, zero on the
-    edges), zero on the other walls; the velocity history then carries the same profile,
-    scaled by (1 - x / L), so that it matches the data on the inflow face."""
+    16 inflow y (H - y) z (W - z) / (H^2 W^2) in 3D, 4 inflow y (H - y) / H^2 in 2D (peak
+    ``inflow`` at the centre, zero on the edges), zero on the other walls; the velocity
+    history then carries the same profile, scaled by (1 - x / L), so that it matches the
+    data on the inflow face."""
     cfg = GCSI_CONFIGS[name]
-    mesh = MeshDesc(dim=3, n_fine=tuple(cfg["n"]), extent=GCSI_EXTENT, n_coarse=tuple(cfg["n_coarse"]),
-                    dirichlet_faces=default_dirichlet_faces(3))
-    ext_mesh = dataclasses.replace(mesh, dirichlet_faces=63)
+    dim = len(cfg["n"])
+    mesh = MeshDesc(dim=dim, n_fine=tuple(cfg["n"]), extent=GCSI_EXTENT[:dim], n_coarse=tuple(cfg["n_coarse"]),
+                    dirichlet_faces=default_dirichlet_faces(dim))
+    ext_mesh = dataclasses.replace(mesh, dirichlet_faces=(1 << (2 * dim)) - 1)
     J = mesh.n_levels - 1
     rng = np.random.default_rng([seed, GCSI_CONFIG_INDEX[name], GCSI_STREAM])
     X = velocity_node_coords(mesh, J)
 
     def field(amp):
-        return np.ascontiguousarray(_sine_displacement(X, mesh.extent, amp, _sine_modes(rng, 3)).ravel())
+        return np.ascontiguousarray(_sine_displacement(X, mesh.extent, amp, _sine_modes(rng, dim)).ravel())
 
     u = [field(0.005), field(0.005)]
     v = [field(0.5), field(0.5)]
@@ -500,34 +520,27 @@ def make_gcsi_inputs(name: str = "G1", seed: int = BASE_SEED, inflow: float = 0.
         r2 = (Xq[..., 0] - tip[0]) ** 2 + (Xq[..., 1] - tip[1]) ** 2
         mu_A.append(np.ascontiguousarray(1.0 + 50.0 * np.exp(-800.0 * r2)))
     cells = mesh.cells(J)
-    h = [mesh.extent[d] / cells[d] for d in range(3)]
+    h = [mesh.extent[d] / cells[d] for d in range(dim)]
     ci = np.meshgrid(*[np.arange(c) for c in cells], indexing="ij")
     centres = np.stack([(g.ravel(order="F") + 0.5) * h[d] for d, g in enumerate(ci)], axis=-1)
     solid_cells = np.ascontiguousarray(_inside_strip(centres).astype(np.uint8))
-    # w = v on every node of a solid cell: mark those nodes
-    nn = mesh.vel_nodes(J)
-    node = np.zeros(int(np.prod(nn)), dtype=bool)
-    sc = np.nonzero(solid_cells)[0]
-    cx, cy, cz = sc % cells[0], (sc // cells[0]) % cells[1], sc // (cells[0] * cells[1])
-    for lz in range(3):
-        for ly in range(3):
-            for lx in range(3):
-                node[(2 * cx + lx) + nn[0] * ((2 * cy + ly) + nn[1] * (2 * cz + lz))] = True
-    for i in range(2):
-        wi = w[i].reshape(3, -1)
-        wi[:, node] = v[i].reshape(3, -1)[:, node]
     dirichlet = None
     if inflow > 0:
-        L, H, Wd = mesh.extent
-        prof = 16.0 * inflow * X[1] * (H - X[1]) * X[2] * (Wd - X[2]) / (H * H * Wd * Wd)
+        L, H = mesh.extent[0], mesh.extent[1]
+        if dim == 3:
+            Wd = mesh.extent[2]
+            prof = 16.0 * inflow * X[1] * (H - X[1]) * X[2] * (Wd - X[2]) / (H * H * Wd * Wd)
+        else:
+            prof = 4.0 * inflow * X[1] * (H - X[1]) / (H * H)
         dirichlet = np.zeros_like(X)
         dirichlet[0] = np.where(X[0] == 0.0, prof, 0.0)
         dirichlet = np.ascontiguousarray(dirichlet.ravel())
         for i in range(2):
-            v[i].reshape(3, -1)[0] += prof * (1.0 - X[0] / L)
-        # the mesh velocity follows the velocity on the solid's nodes
-        for i in range(2):
-            wi = w[i].reshape(3, -1)
-            wi[:, node] = v[i].reshape(3, -1)[:, node]
+            v[i].reshape(dim, -1)[0] += prof * (1.0 - X[0] / L)
+    # the mesh velocity follows the velocity on (and near) the solid
+    phi = _strip_weight(X)
+    for i in range(2):
+        wi, vi = w[i].reshape(dim, -1), v[i].reshape(dim, -1)
+        wi[:] = phi * vi + (1.0 - phi) * wi
     return GcsiInputs(mesh=mesh, ext_mesh=ext_mesh, solid_q=solid_q, solid_cells=solid_cells, mu_A=mu_A,
                       material=dict(GCSI_MATERIAL), u=u, v=v, w=w, p=p, dirichlet=dirichlet)

@@ -295,11 +295,6 @@ def test_time_step_entry_points_reject_bad_input(case):
     assert e.value.status == fsi.FSI_ERR_STATE
     assert ext.raw_status("fsi_set_tuning", ext.n_levels - 1, 0, 16) == fsi.FSI_ERR_ARG
     ext.close()
-    # 2D contexts have no time-step kernels
-    wl = W.make_workload("T2_R")
-    c2 = fsi.Context.from_mesh(wl.mesh)
-    assert c2.raw_status("fsi_gcsi_displacement", C.byref(prm), vp(z), vp(z), vp(z), vp(z), None) == fsi.FSI_ERR_ARG
-    c2.close()
 
 
 @pytest.mark.parametrize("mode", ["P", "C"])

@@ -1,0 +1,291 @@
+"""GPU parity of the GCSI_k(M_1, .., M_S) time step (Algorithm 1, Sec. 3.1.1) in 2D: the
+x-y section of the channel with an elastic strip (32 x 8 cells, three levels, an inflow
+profile on x = 0 and gravity) against the oracle's step (oracle/gcsi.py: assembled
+operators, direct solves), and the 1024 x 256 channel at size through its invariants.
+
+* the explicit displacement and its vertex values;
+* the right-hand sides g_vM and g_p of both modes, before and after the lifting of the
+  inflow data, componentwise: |g - g*|_i <= 64 u (|terms|)_i;
+* the corrector-mode operator built from the predictor's fields on two levels;
+* the extension with the solid's cells fixed, against the direct solve;
+* whole GCSI_2(P, C) steps (FP64 and mixed V-cycles) and three steps with the history
+  moved back, against the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import fem
+from oracle import gcsi as og
+from paper_2305_08986_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+C_BOUND = 64
+
+
+def _dev(x, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(x), device="cuda", dtype=dtype or torch.float64).contiguous()
+
+
+@pytest.fixture(scope="module")
+def case():
+    g = W.make_gcsi_inputs("G1_2D", inflow=1.0)
+    J = g.mesh.n_levels - 1
+    ref = fem.Reference(2)
+    pb = og.Problem(box=fem.level_box(g.mesh, J), ext_box=fem.level_box(g.ext_mesh, J),
+                    solid_q=g.solid_q[J].astype(bool), solid_cells=g.solid_cells.astype(bool), mu_A=g.mu_A[J],
+                    prm=og.Params(**g.material), dirichlet=g.dirichlet)
+    st = og.State(u=g.u, v=g.v, w=g.w, p=g.p)
+    out = og.step(pb, st, ("P", "C"), ref)
+    return g, pb, st, ref, out
+
+
+def _within(got, want, scale, what):
+    err = np.abs(got - want)
+    bad = err > C_BOUND * U64 * scale
+    worst = float(np.max(err / np.maximum(scale * U64, 1e-300)))
+    print(f"{what}: worst |err| / (u scale) = {worst:.1f}")
+    assert not np.any(bad), (what, int(bad.sum()), worst)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _ctx(mesh):
+    from paper_2305_08986_amd import fsi
+    return fsi, fsi.Context.from_mesh(mesh)
+
+
+def _fields(g):
+    return [_dev(x) for x in (g.u[0], g.u[1], g.v[0], g.v[1], g.w[0], g.w[1])]
+
+
+def test_explicit_displacement_and_vertex_values_2d(case):
+    g, pb, st, ref, out = case
+    fsi, ctx = _ctx(g.mesh)
+    prm = fsi.GcsiParams.of(**g.material)
+    nvert = ctx.sizes(g.mesh.n_levels - 1)["n_vert"]
+    u_out = torch.empty(pb.box.n_vel, device="cuda", dtype=torch.float64)
+    disp = torch.empty(2 * nvert, device="cuda", dtype=torch.float64)
+    ctx.gcsi_displacement(prm, _dev(g.w[0]), _dev(g.u[0]), _dev(g.u[1]), out=u_out, disp=disp)
+    torch.cuda.synchronize()
+    want = og.explicit_displacement(pb.prm, g.w[0], g.u)
+    scale = pb.prm.gamma * pb.prm.tau * np.abs(g.w[0]) + sum(abs(a) * np.abs(x) for a, x in zip(pb.prm.alpha, g.u))
+    _within(u_out.cpu().numpy(), want, scale, "u#")
+    assert np.array_equal(disp.cpu().numpy().reshape(2, -1), og.vertex_values(pb.box, u_out.cpu().numpy()))
+    ctx.close()
+
+
+def _rhs_case(ctx, fsi, g, pb, ref, out, mode):
+    """Geometry, coefficients (and corrector terms) of the stage on ctx; the oracle's
+    right-hand side, its magnitudes, and the stage's operator pieces for the lifting."""
+    prm = fsi.GcsiParams.of(**g.material)
+    st = og.State(u=g.u, v=g.v, w=g.w, p=g.p)
+    uh = out["stages"][0 if mode == "P" else 1]["u_hash"]
+    disp = og.vertex_values(pb.box, uh)
+    ctx.set_displacement(disp.ravel())
+    ctx.gcsi_set_coefficients(prm, [_dev(x, torch.uint8) for x in g.solid_q])
+    conv = None
+    cm, eta = og.coefficients(pb.prm, pb.solid_q)
+    if mode == "C":
+        vh, wh = out["stages"][0]["v"], out["stages"][0]["w"]
+        ctx.gcsi_set_convection(prm, _dev(vh), _dev(wh))
+        ctx.set_mg_params(corrector=1, k_A=6)
+        vq, r = og.convection_inputs(pb.box, ref, vh, wh, eta)
+        conv = (vq, pb.prm.rho_f, r)
+    want = og.rhs(pb.box, ref, pb.prm, mode, pb.solid_q, disp, uh, st)
+    absv = og.rhs(pb.box, ref, pb.prm, mode, pb.solid_q, disp, uh, st, absolute=True)
+    return prm, uh, disp, cm, eta, conv, want, absv
+
+
+@pytest.mark.parametrize("mode", ["P", "C"])
+def test_right_hand_side_and_lifting_match_oracle_2d(case, mode):
+    g, pb, st, ref, out = case
+    fsi, ctx = _ctx(g.mesh)
+    J = g.mesh.n_levels - 1
+    prm, uh, disp, cm, eta, conv, (want_u, want_p), (abs_u, abs_p) = _rhs_case(ctx, fsi, g, pb, ref, out, mode)
+    g_u = torch.full((pb.box.n_vel,), np.nan, device="cuda", dtype=torch.float64)
+    g_p = torch.full((pb.box.n_p,), np.nan, device="cuda", dtype=torch.float64)
+    m = fsi.GCSI_PREDICTOR if mode == "P" else fsi.GCSI_CORRECTOR
+    args = (prm, m, _dev(g.solid_q[J], torch.uint8), _dev(disp.ravel()), _dev(uh), *_fields(g))
+    ctx.gcsi_rhs(*args, g_u, g_p)
+    torch.cuda.synchronize()
+    assert np.abs(want_p).max() > 0 and np.abs(want_u).max() > 0
+    _within(g_u.cpu().numpy(), want_u, abs_u, f"g_u ({mode})")
+    _within(g_p.cpu().numpy(), want_p, abs_p, f"g_p ({mode})")
+    # then the inflow data lifted into it
+    Jq = fem.jacobians_q1(pb.box, disp, ref)
+    lu, lp = og.lift_dirichlet(pb.box, ref, Jq, cm, eta, g.dirichlet, want_u, want_p, conv)
+    dm = pb.box.dirichlet_vel_dofs()
+    dw = np.abs(np.where(dm, g.dirichlet, 0.0))
+    box0 = fem.Box(2, pb.box.cells, pb.box.extent, 0)
+    opa = fem.assemble(box0, Jq, cm, eta, ref, absolute=True)
+    Aa = opa.A if conv is None else opa.A + fem.assemble_convection(box0, Jq, conv[0], conv[1], conv[2], ref,
+                                                                      absolute=True)
+    ctx.lift_dirichlet(_dev(g.dirichlet), g_u, g_p)
+    torch.cuda.synchronize()
+    gu = g_u.cpu().numpy()
+    assert np.array_equal(gu[dm], g.dirichlet[dm])
+    _within(gu, lu, abs_u + Aa @ dw + np.abs(lu), f"lifted g_u ({mode})")
+    _within(g_p.cpu().numpy(), lp, abs_p + opa.B @ dw + np.abs(lp), f"lifted g_p ({mode})")
+    ctx.close()
+
+
+def _inject(mesh, f, level):
+    J = mesh.n_levels - 1
+    s = 1 << (J - level)
+    nn = mesh.vel_nodes(J)
+    return np.ascontiguousarray(f.reshape(2, nn[1], nn[0])[:, ::s, ::s].reshape(-1))
+
+
+def test_corrector_operator_from_the_step_fields_matches_oracle_2d(case):
+    g, pb, st, ref, out = case
+    fsi, ctx = _ctx(g.mesh)
+    prm = fsi.GcsiParams.of(**g.material)
+    J = g.mesh.n_levels - 1
+    uh = out["stages"][1]["u_hash"]
+    vh, wh = out["stages"][0]["v"], out["stages"][0]["w"]
+    disp = og.vertex_values(pb.box, uh)
+    ctx.set_displacement(disp.ravel())
+    ctx.gcsi_set_coefficients(prm, [_dev(x, torch.uint8) for x in g.solid_q])
+    ctx.gcsi_set_convection(prm, _dev(vh), _dev(wh))
+    rng = np.random.default_rng(17)
+    n_conv = 0
+    for j in (J, J - 1):
+        box = fem.level_box(g.mesh, j)
+        Jq = fem.jacobians_q1(box, W.inject_displacement(g.mesh, disp, j), ref)
+        cm, eta = og.coefficients(pb.prm, g.solid_q[j].astype(bool))
+        vq, r = og.convection_inputs(box, ref, _inject(g.mesh, vh, j), _inject(g.mesh, wh, j), eta)
+        n_conv += int(np.count_nonzero(r))
+        op = fem.assemble(box, Jq, cm, eta, ref)
+        A = op.A + fem.assemble_convection(box, Jq, vq, pb.prm.rho_f, r, ref)
+        opa = fem.assemble(box, Jq, cm, eta, ref, absolute=True)
+        Aa = opa.A + fem.assemble_convection(box, Jq, vq, pb.prm.rho_f, r, ref, absolute=True)
+        x = rng.uniform(-1, 1, box.n_vel)
+        y = rng.uniform(-1, 1, box.n_p)
+        v, q = ctx.apply_corrector(j, _dev(x), _dev(y))
+        torch.cuda.synchronize()
+        _within(v.cpu().numpy(), A @ x + op.B.T @ y, Aa @ np.abs(x) + np.abs(opa.B.T) @ np.abs(y),
+                f"(A+N+S) x level {j}")
+        _within(q.cpu().numpy(), op.B @ x, np.abs(opa.B) @ np.abs(x), f"B x level {j}")
+    print("cells with a streamline term", n_conv)
+    ctx.close()
+
+
+def test_extension_with_fixed_solid_cells_matches_direct_solve_2d(case):
+    g, pb, st, ref, out = case
+    fsi, ctx = _ctx(g.ext_mesh)
+    J = g.mesh.n_levels - 1
+    ctx.set_fixed_cells(g.solid_cells)
+    ctx.set_displacement(np.zeros(2 * ctx.sizes(J)["n_vert"]))
+    for j in range(ctx.n_levels):
+        ctx.set_coefficients(j, np.zeros_like(g.mu_A[j]), 0.5 * g.mu_A[j])
+    ctx.setup()
+    v = np.random.default_rng(5).uniform(-1, 1, pb.box.n_vel)
+    gv = torch.empty(pb.box.n_vel, device="cuda", dtype=torch.float64)
+    ctx.fixed_values(_dev(v), gv)
+    w, info = ctx.solve_extension(gv, rtol=1e-12, max_iter=300)
+    torch.cuda.synchronize()
+    fixed = og.fixed_nodes(pb.ext_box, pb.solid_cells)
+    want = og.extension(pb.ext_box, ref, pb.mu_A, v, fixed)
+    got = w.cpu().numpy()
+    print("extension", info["iters"], info["rel_res"])
+    assert info["status"] == "OK"
+    assert np.array_equal(got[np.tile(fixed, 2)], v[np.tile(fixed, 2)])
+    assert np.linalg.norm(got - want) <= 1e-9 * np.linalg.norm(want)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_gcsi2_pc_step_with_inflow_matches_oracle_step_2d(case, precision):
+    g, pb, st, ref, out = case
+    from paper_2305_08986_amd import gcsi
+    S = gcsi.Stepper(g, precision=precision)
+    res = S.step([_dev(x) for x in g.u], [_dev(x) for x in g.v], [_dev(x) for x in g.w], _dev(g.p),
+                 ("P", "C"), rtol=1e-12, ext_rtol=1e-12)
+    S.close()
+    for k, rec in enumerate(res["stages"]):
+        print({a: b for a, b in rec.items() if a != "u_hash"})
+        assert rec["status"] == "OK" and rec["ext_status"] == "OK"
+        assert _rel(rec["u_hash"].cpu().numpy(), out["stages"][k]["u_hash"]) <= 1e-9
+    v = res["v"].cpu().numpy()
+    dm = pb.box.dirichlet_vel_dofs()
+    assert np.allclose(v[dm], g.dirichlet[dm], rtol=0, atol=1e-9)
+    errs = {key: _rel(res[key].cpu().numpy(), out[key]) for key in ("u", "v", "w", "p")}
+    print("relative max-norm differences", errs)
+    for key, e in errs.items():
+        assert e <= 1e-8, (key, e)
+
+
+def test_three_steps_with_inflow_match_the_oracle_run_2d(case):
+    g, pb, _, ref, _ = case
+    from paper_2305_08986_amd import gcsi
+    st, _ = og.run(pb, og.State(u=g.u, v=g.v, w=g.w, p=g.p), 3, ("P", "C"), ref)
+    S = gcsi.Stepper(g, precision=1)
+    u, v, w, p, recs = S.run([_dev(x) for x in g.u], [_dev(x) for x in g.v], [_dev(x) for x in g.w], _dev(g.p),
+                             3, rtol=1e-12, ext_rtol=1e-12)
+    S.close()
+    for i in range(2):
+        errs = {key: _rel(got.cpu().numpy(), want) for key, got, want in
+                (("u", u[i], st.u[i]), ("v", v[i], st.v[i]), ("w", w[i], st.w[i]))}
+        print("history", i, errs)
+        for key, e in errs.items():
+            assert e <= 1e-8, (i, key, e)
+    assert _rel(p.cpu().numpy(), st.p) <= 1e-8
+    print("iterations", [[s["iters"] for s in r["stages"]] for r in recs])
+
+
+def test_body_third_component_is_not_read_in_2d(case):
+    """In 2D the body acceleration has two components: a non-finite third one is ignored,
+    a non-finite second one is rejected."""
+    import ctypes as C
+    g, pb, st, ref, out = case
+    fsi, ctx = _ctx(g.mesh)
+    z = torch.zeros(pb.box.n_vel, device="cuda", dtype=torch.float64)
+    vp = lambda t: C.c_void_p(None if t is None else t.data_ptr())
+    ok = fsi.GcsiParams.of(**{**g.material, "body": (0.0, -2.0, float("nan"))})
+    bad = fsi.GcsiParams.of(**{**g.material, "body": (0.0, float("nan"), 0.0)})
+    assert ctx.raw_status("fsi_gcsi_displacement", C.byref(ok), vp(z), vp(z), vp(z), vp(z), None) == fsi.FSI_OK
+    assert ctx.raw_status("fsi_gcsi_displacement", C.byref(bad), vp(z), vp(z), vp(z), vp(z), None) == fsi.FSI_ERR_ARG
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def test_gcsi2_step_at_1024x256_converges_and_keeps_its_invariants():
+    """The 2D channel at 1024 x 256 cells (the oracle's direct solves do not reach it):
+    every stage converges, the mesh velocity equals the velocity on the solid's nodes and
+    vanishes on the other walls, the inflow rows carry the data, the displacement is the
+    recovery formula of the final mesh velocity, and mixed and FP64 steps agree."""
+    from paper_2305_08986_amd import gcsi
+    g = W.make_gcsi_inputs("G2_2D", inflow=1.0)
+    J = g.mesh.n_levels - 1
+    args = ([_dev(x) for x in g.u], [_dev(x) for x in g.v], [_dev(x) for x in g.w], _dev(g.p))
+    res = {}
+    for label, prec in (("fp64", 0), ("mixed", 1)):
+        S = gcsi.Stepper(g, precision=prec, autotune=True)
+        res[label] = S.step(*args, rtol=1e-10, ext_rtol=1e-10)
+        S.close()
+        for rec in res[label]["stages"]:
+            print(label, {a: b for a, b in rec.items() if a != "u_hash"})
+            assert rec["status"] == "OK" and rec["ext_status"] == "OK", rec
+            assert rec["rel_res"] <= 1e-10 and rec["ext_rel_res"] <= 1e-10
+    box, ebox = fem.level_box(g.mesh, J), fem.level_box(g.ext_mesh, J)
+    fixed = np.tile(og.fixed_nodes(ebox, g.solid_cells.astype(bool)), 2)
+    dm = box.dirichlet_vel_dofs()
+    prm = og.Params(**g.material)
+    for label, r in res.items():
+        v, w, u = (r[k].cpu().numpy() for k in ("v", "w", "u"))
+        assert np.array_equal(w[fixed], v[fixed]), label
+        assert not np.any(w[ebox.dirichlet_vel_dofs() & ~fixed]), label
+        assert np.allclose(v[dm], g.dirichlet[dm], rtol=0, atol=1e-9), label
+        want = og.explicit_displacement(prm, w, g.u)
+        scale = prm.gamma * prm.tau * np.abs(w) + sum(abs(a) * np.abs(x) for a, x in zip(prm.alpha, g.u))
+        _within(u, want, scale, f"u^n ({label})")
+    for key in ("v", "w", "u", "p"):
+        a, b = res["mixed"][key].cpu().numpy(), res["fp64"][key].cpu().numpy()
+        e = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        print("mixed vs fp64", key, e)
+        assert e <= 1e-7, (key, e)
