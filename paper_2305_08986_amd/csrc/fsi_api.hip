@@ -105,8 +105,21 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
     }
     L.n_dir = (int64_t)dirn.size();
     // processing order: phases are the parity colours of (iy, iz); a phase holds
-    // whole rows of cells along x (lexicographic), so one wavefront can own a row
-    L.ncolors = 1 << (dim - 1);
+    // whole rows of cells along x (lexicographic), so one wavefront can own a row.
+    // In 2D a row of cells is cut into segments of seg cells (seg = nx / 2^m, the
+    // shortest such length of at least kSeg2D cells) and the segment's parity joins
+    // the colour: four phases, and a wavefront owns one segment.  The 2D kernel walks
+    // its row chunk by chunk with a dependent load chain per chunk, so short rows
+    // (many wavefronts, one or two chunks each) hide the latency that one long row
+    // per wavefront (nx / 21 chunks in sequence) cannot.
+    const int nx = L.cells[0];
+    int seg = nx;
+    if (dim == 2) {
+        constexpr int kSeg2D = 16;
+        while (seg % 2 == 0 && seg / 2 >= kSeg2D) seg /= 2;
+    }
+    const bool split = seg < nx;
+    L.ncolors = (1 << (dim - 1)) * (split ? 2 : 1);
     auto cell_coords = [&](int64_t c, int ci[3]) {
         int64_t r = c;
         ci[0] = ci[1] = ci[2] = 0;
@@ -118,16 +131,16 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
     auto phase_of = [&](const int ci[3]) {
         int col = 0;
         for (int d = 1; d < dim; ++d) col |= (ci[d] & 1) << (d - 1);
+        if (split) col |= ((ci[0] / seg) & 1) << (dim - 1);
         return col;
     };
     const int nph = L.nphases();
     const int cpw = dim == 3 ? Shape<3>::CPW : Shape<2>::CPW;
-    const int nx = L.cells[0];
-    const int nchunk = (nx + cpw - 1) / cpw;
+    const int nchunk = (seg + cpw - 1) / cpw;
     std::vector<int> col2lex((size_t)L.nc), lex2col((size_t)L.nc);
-    // rows of each phase (lexicographic in the row index)
+    // rows (segments) of each phase (lexicographic in the row index)
     std::vector<std::vector<int64_t>> rows((size_t)nph);
-    for (int64_t c = 0; c < L.nc; c += nx) {
+    for (int64_t c = 0; c < L.nc; c += seg) {
         int ci[3];
         cell_coords(c, ci);
         rows[phase_of(ci)].push_back(c);      // lex index of the row's first cell
@@ -138,34 +151,39 @@ static fsi_status build_level(Context* ctx, Level& L, int dim, const int cells[3
     for (int p = 0; p < nph; ++p) {
         L.phase_off[p] = k;
         for (int64_t r : rows[p])
-            for (int ix = 0; ix < nx; ++ix) {
+            for (int ix = 0; ix < seg; ++ix) {
                 col2lex[k] = (int)(r + ix);
                 lex2col[r + ix] = (int)k;
                 ++k;
             }
     }
     L.phase_off[nph] = k;
-    // dispatch order of the single atomic launch: slot g takes natural row g (iy
+    // dispatch order of the single atomic launch (3D): slot g takes natural row g (iy
     // fastest), stored at its phase-major row
-    const int64_t nrow = L.nc / nx;
+    const int64_t nrow = L.nc / seg;
     std::vector<int> atom_rows((size_t)nrow);
     {
         int64_t sr = 0;
         for (int p = 0; p < nph; ++p)
-            for (int64_t r : rows[p]) atom_rows[(size_t)(r / nx)] = (int)sr++;
+            for (int64_t r : rows[p]) atom_rows[(size_t)(r / seg)] = (int)sr++;
     }
-    L.geo.nx = nx;
+    L.geo.nx = seg;
     L.geo.nchunks = nchunk;
     L.geo.cpw = cpw;
     L.geo.nt = dim == 3 ? Shape<3>::NT : Shape<2>::NT;
-    L.geo.nchk = (L.nc / nx) * nchunk;
+    L.geo.nchk = nrow * nchunk;
     std::vector<int> vmap((size_t)L.nc * NLOC), pmap((size_t)L.nc * NPL);
     std::vector<uint4> info((size_t)L.nc);
     // first/last touch of a shared node: compare the phase of every other cell containing it
-    // x-neighbours belong to the same row: their contributions are summed in the
-    // wavefront before the write, so only y/z neighbours decide first/last touch
+    // x-neighbours in the same row (segment) are summed in the wavefront before the
+    // write, so only y/z neighbours and the x-neighbours across a segment boundary
+    // decide first/last touch
     auto touch_bits = [&](const int ci[3], const int li[3], int hi_index, bool& first, bool& last) {
         int dirs[3], nd = 0;
+        if (split) {
+            if (li[0] == 0 && ci[0] > 0 && ci[0] % seg == 0) dirs[nd++] = -1;
+            else if (li[0] == hi_index && ci[0] < nx - 1 && (ci[0] + 1) % seg == 0) dirs[nd++] = 1;
+        }
         for (int d = 1; d < dim; ++d) {
             if (li[d] == 0 && ci[d] > 0) dirs[nd++] = -(d + 1);
             else if (li[d] == hi_index && ci[d] < L.cells[d] - 1) dirs[nd++] = d + 1;

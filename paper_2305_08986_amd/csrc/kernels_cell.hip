@@ -1325,12 +1325,11 @@ static CellArgs<T> phase_args(const Level& L, int phase, const T* K, const T* cv
     CellArgs<T> args{};
     args.cbeg = L.phase_off[phase];
     args.cend = L.phase_off[phase + 1];
-    args.nx = L.cells[0];
-    args.nrows = (args.cend - args.cbeg) / L.cells[0];
-    const int cpw = L.dim == 3 ? Shape<3>::CPW : Shape<2>::CPW;
-    args.nchunks = (L.cells[0] + cpw - 1) / cpw;
-    args.wlast = L.cells[0] - (args.nchunks - 1) * cpw;
-    args.chunk0 = (args.cbeg / L.cells[0]) * args.nchunks;
+    args.nx = L.geo.nx;   // cells per row: a whole x-line in 3D, a segment of one in 2D
+    args.nrows = (args.cend - args.cbeg) / L.geo.nx;
+    args.nchunks = L.geo.nchunks;
+    args.wlast = L.geo.nx - (args.nchunks - 1) * L.geo.cpw;
+    args.chunk0 = (args.cbeg / L.geo.nx) * args.nchunks;
     args.nchk = L.geo.nchk;
     args.nc = L.nc;
     args.nvn = L.nvn;
