@@ -350,7 +350,7 @@ static void op_apply(Context* ctx, int j, int mode, const T* u, const double* p,
     const int am = !(ctx->prm.tuned && ctx->prm.atomics) ? -1
                    : (mode & OP_CONV) ? ctx->atom_conv[prec_index<T>()][(size_t)j]
                                       : ctx->atom_of(prec_index<T>(), j, mode);
-    if (am >= 0 && L.dim == 3) {
+    if (am >= 0) {
         launch_cell_atomic<T>(L, mode, am, Kmode<T>(L, mode), CVp<T>(L), u, p, v, q, s);   // wall rows included
         return;
     }
@@ -1960,9 +1960,10 @@ fsi_status fsi_autotune(fsi_ctx* h) {
             for (int m : unfused) {
                 const size_t k = (size_t)j * kTuneClasses + tune_class(m);
                 ctx->atom[pi][k] = -1;
-                if (ctx->lv[j].dim != 3 || ctx->has_fixed) continue;
+                // the 3D atomic form takes its wall bits from the box faces: not with fixed cells
+                if (ctx->lv[j].dim == 3 && ctx->has_fixed) continue;
                 double best = ctx->tune_us[pi][k];
-                for (int shape = 0; shape < kAtomShapes; ++shape) {
+                for (int shape = 0; shape < atom_shapes(ctx->lv[j].dim); ++shape) {
                     const int reps = 3;
                     for (int r = 0; r <= reps; ++r) {
                         if (r == 1) FSI_HIP_TRY(hipEventRecord(e0, s));
@@ -1989,10 +1990,10 @@ fsi_status fsi_autotune(fsi_ctx* h) {
         for (int j = 0; j < ctx->nlev; ++j) {
             ctx->atom_conv[pi][(size_t)j] = -1;
             const Level& L = ctx->lv[j];
-            if (L.dim != 3 || ctx->has_fixed || !L.conv_set) continue;
+            if ((L.dim == 3 && ctx->has_fixed) || !L.conv_set) continue;
             const int m = OP_A | OP_CONV;
             double best = 1e300;
-            for (int shape = -1; shape < kAtomShapes; ++shape) {
+            for (int shape = -1; shape < atom_shapes(L.dim); ++shape) {
                 const int reps = 3;
                 for (int r = 0; r <= reps; ++r) {
                     if (r == 1) FSI_HIP_TRY(hipEventRecord(e0, s));
@@ -2087,7 +2088,7 @@ fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int
     // tuned levels where the autotuner chose the single atomic launch time that launch
     // (with the zeroing of its outputs) as one unit
     const int am = (ctx->prm.tuned && ctx->prm.atomics && !fused_mode && !conv_mode) ? ctx->atom_of(precision, level, mode) : -1;
-    const bool atomic = am >= 0 && L.dim == 3;
+    const bool atomic = am >= 0;
     const int nph = atomic ? 1 : L.nphases();
     std::vector<hipEvent_t> ev((size_t)2 * nph + 2);
     for (auto& e : ev) FSI_HIP_TRY(hipEventCreate(&e));
@@ -2150,10 +2151,10 @@ fsi_status fsi_set_tuning(fsi_ctx* h, int level, int precision, int variant) {
         variant >= kNumVariants + kAtomShapes)
         return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: level, precision or variant out of range");
     const bool atomic = variant >= kNumVariants;
-    if (atomic && ctx->lv[level].dim != 3)
-        return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: the single atomic launch is 3D only");
-    if (atomic && ctx->has_fixed)
-        return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: no single atomic launch with fixed cells");
+    if (atomic && variant >= kNumVariants + atom_shapes(ctx->lv[level].dim))
+        return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: 2D levels have two atomic shapes (variants 16, 17)");
+    if (atomic && ctx->has_fixed && ctx->lv[level].dim == 3)
+        return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: no 3D single atomic launch with fixed cells");
     for (int c = 0; c < kTuneClasses; ++c)
         ctx->tune_variant[precision][(size_t)level * kTuneClasses + c] = atomic ? 0 : variant;
     for (int c = 0; c < kTuneClasses; ++c)

@@ -299,9 +299,12 @@ template <typename T>
 void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T* cv,
                      const T* u, const double* p, T* v, double* q, hipStream_t s);
 // the same apply in one launch over all phases with atomic adds, wall rows included
-// (3D; modes A, B, B^T and A + B^T + B; shape 0 .. kAtomShapes - 1: one or four
-// wavefronts per row, rows grouped along z by one, two or four)
+// (modes A, B, B^T and A + B^T + B, and the corrector classes; 3D shapes 0 ..
+// kAtomShapes - 1: one or four wavefronts per row, rows grouped along z by one, two or
+// four; 2D shapes 0 .. kAtomShapes2D - 1: one or two wavefronts per workgroup)
 constexpr int kAtomShapes = 5;
+constexpr int kAtomShapes2D = 2;
+inline int atom_shapes(int dim) { return dim == 3 ? kAtomShapes : kAtomShapes2D; }
 template <typename T>
 void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T* cv,
                         const T* u, const double* p, T* v, double* q, hipStream_t s);

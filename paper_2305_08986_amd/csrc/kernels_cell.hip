@@ -944,11 +944,16 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
     constexpr bool CHEB = (MODE & OP_CHEB) != 0;
     constexpr bool RES = (MODE & OP_RES) != 0;
     constexpr bool CONV = (MODE & OP_CONV) != 0;
+    // OP_ATOM: every row of every phase in one launch; shared nodes take hardware atomic
+    // adds into the zeroed output, and wall rows take v = u (plain stores of one value)
+    constexpr bool ATOM = (MODE & OP_ATOM) != 0;
+    constexpr int MB = MODE & ~OP_ATOM;
+    static_assert(!ATOM || !(CHEB || RES), "the atomic form has no epilogue");
     static_assert(!CHEB || MODE == (OP_A | OP_CHEB), "the Chebyshev epilogue goes with A alone");
     static_assert(!RES || MODE == (OP_A | OP_BT | OP_B | OP_RES), "the residual epilogue goes with the Stokes apply");
-    static_assert(!CONV || MODE == (OP_A | OP_CONV) || MODE == (OP_A | OP_BT | OP_B | OP_CONV),
+    static_assert(!CONV || MB == (OP_A | OP_CONV) || MB == (OP_A | OP_BT | OP_B | OP_CONV),
                   "the corrector terms go with A or the Stokes apply");
-    constexpr bool SCALED = MODE == OP_A || MODE == (OP_A | OP_CHEB);   // K' = sqrt(cvisc) K, no cvisc plane
+    constexpr bool SCALED = MB == OP_A || MODE == (OP_A | OP_CHEB);   // K' = sqrt(cvisc) K, no cvisc plane
     __shared__ T sbuf[WPB][CPW][BUF];
     __shared__ double pbuf[(MODE & OP_B) ? WPB : 1][CPW][NT][4];
 
@@ -1138,15 +1143,21 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
             if (ix > 0) s0 += slot > 0 ? pxb[wave][slot - 1][t] : pcarry[wave][(ch + 1) & 1][t];
             const uint32_t pf = a.info[cell].z;
             const int n0 = a.pmap[cell * 4 + 2 * t], n1 = a.pmap[cell * 4 + 2 * t + 1];
-            {
-                const double tot = ((pf >> (2 * t)) & 1u) ? s0 : a.q[n0] + s0;
-                a.q[n0] = (RES && ((pf >> (16 + 2 * t)) & 1u)) ? a.fp[n0] - tot : tot;
-            }
-            if (ix == a.nx - 1) {
-                const double tot = ((pf >> (2 * t + 1)) & 1u) ? s1 : a.q[n1] + s1;
-                a.q[n1] = (RES && ((pf >> (16 + 2 * t + 1)) & 1u)) ? a.fp[n1] - tot : tot;
-            } else if (slot == CPW - 1) {
-                pcarry[wave][ch & 1][t] = s1;
+            if constexpr (ATOM) {
+                unsafeAtomicAdd(&a.q[n0], s0);
+                if (ix == a.nx - 1) unsafeAtomicAdd(&a.q[n1], s1);
+                else if (slot == CPW - 1) pcarry[wave][ch & 1][t] = s1;
+            } else {
+                {
+                    const double tot = ((pf >> (2 * t)) & 1u) ? s0 : a.q[n0] + s0;
+                    a.q[n0] = (RES && ((pf >> (16 + 2 * t)) & 1u)) ? a.fp[n0] - tot : tot;
+                }
+                if (ix == a.nx - 1) {
+                    const double tot = ((pf >> (2 * t + 1)) & 1u) ? s1 : a.q[n1] + s1;
+                    a.q[n1] = (RES && ((pf >> (16 + 2 * t + 1)) & 1u)) ? a.fp[n1] - tot : tot;
+                } else if (slot == CPW - 1) {
+                    pcarry[wave][ch & 1][t] = s1;
+                }
             }
         }
     }
@@ -1214,6 +1225,19 @@ __global__ __launch_bounds__(64 * WPB) void cell2d(CellArgs<T> a) {
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
                     const int ln = t + 3 * j;
+                    if constexpr (ATOM) {
+                        const int node = a.vmap[cell * NLOC + ln];
+                        if ((inf.x >> ln) & 1u) {
+                            if constexpr ((MODE & OP_A) != 0) {
+#pragma unroll
+                                for (int c = 0; c < 2; ++c) a.v[c * a.nvn + node] = a.u[c * a.nvn + node];
+                            }
+                            continue;
+                        }
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) unsafeAtomicAdd(&a.v[c * a.nvn + node], out[c][j]);
+                        continue;
+                    }
                     if ((inf.x >> ln) & 1u) continue;
                     const int node = a.vmap[cell * NLOC + ln];
                     const bool first = (inf.y >> ln) & 1u;
@@ -1274,7 +1298,7 @@ static void launch_one(const Level& L, const CellArgs<T>& args, hipStream_t s) {
         }
         hipLaunchKernelGGL((cell3d<T, MODE, WPB, RS, NTL, WPE, false, ZG>), dim3((unsigned)grid), dim3(64 * WPB), 0, s,
                            args);
-    } else if constexpr ((MODE & OP_ATOM) == 0) {   // the atomic form is 3D only
+    } else {
         constexpr int W2 = WPB > 1 ? 2 : 1;   // 2D: one row per wavefront, at most two
         const int64_t grid = (args.nrows + W2 - 1) / W2;   // one wavefront per row of cells
         hipLaunchKernelGGL((cell2d<T, MODE, W2, false, NTL>), dim3((unsigned)grid), dim3(64 * W2), 0, s, args);
@@ -1392,13 +1416,15 @@ void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T*
     for (int ph = 0; ph < L.nphases(); ++ph) launch_cell<T>(L, mode, variant, ph, K, cv, u, p, v, q, s);
 }
 
-// every phase in one launch (3D, modes A, B, B^T, A + B^T + B, and A or the Stokes apply
+// every phase in one launch (modes A, B, B^T, A + B^T + B, and A or the Stokes apply
 // with the corrector terms): one kernel zeroes the
 // outputs, then each cell adds its contributions atomically and the cell kernel writes
 // the wall rows itself (v = u when A is applied; B^T alone leaves them zero).  Shapes
-// (kAtomShapes): 0 one wavefront per row; 1 four wavefronts share a row; 2, 3 one
+// in 3D (kAtomShapes): 0 one wavefront per row; 1 four wavefronts share a row; 2, 3 one
 // wavefront takes two or four rows along z (the plane they share summed in registers);
-// 4 four wavefronts share a pair of rows along z.
+// 4 four wavefronts share a pair of rows along z.  In 2D (kAtomShapes2D): one wavefront
+// per row segment, one (0) or two (1) wavefronts per workgroup; the cell info and the
+// node map supply the wall bits, so fixed cells are honoured.
 template <int ZG>
 static int64_t atom_slots(const Level& L) {
     return (int64_t)L.cells[1] * ((L.cells[2] + ZG - 1) / ZG);
@@ -1425,6 +1451,13 @@ void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T
     launch_atomic_init<T>(L, (mode & (OP_A | OP_BT)) ? v : nullptr, (mode & OP_B) ? q : nullptr, s);
     auto go = [&](auto mc) {
         constexpr int M = decltype(mc)::value | OP_ATOM;
+        if (L.dim == 2) {
+            // every row segment of every phase; shape 0 one wavefront per workgroup, else two
+            args.nrows = (args.cend - args.cbeg) / L.geo.nx;
+            if (shape == 0) launch_one<T, M, 1, true, 1, 1>(L, args, s);
+            else launch_one<T, M, 2, true, 1, 1>(L, args, s);
+            return;
+        }
         // waves per SIMD the unfused classes reach: FP64 two (A, B, B^T), FP32 four; the
         // Stokes classes are left unconstrained
         constexpr bool STOKES = (M & OP_A) && (M & OP_BT);

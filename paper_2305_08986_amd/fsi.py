@@ -32,6 +32,7 @@ N_LAUNCH_VARIANTS = 16
 # four wavefronts per row, one wavefront over two or four rows along z, four wavefronts
 # over two rows along z
 ATOMIC_VARIANTS = (16, 17, 18, 19, 20)
+ATOMIC_VARIANTS_2D = (16, 17)   # the same form on 2D levels: one or two wavefronts per workgroup
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_STATE", -3: "ERR_HIP", -4: "ERR_OOM",
                 -5: "ERR_INVERTED_CELL", -6: "ERR_BREAKDOWN", -7: "ERR_NONFINITE"}

@@ -308,6 +308,54 @@ def test_atomic_single_launch_matches_oracle(name):
                 ctx.set_tuning(j, prec, 0)
 
 
+@pytest.mark.parametrize("name", ["T2_R", "C0", "C1"])
+def test_atomic_single_launch_matches_oracle_2d(name):
+    """2D levels: the single launch over every row segment of every phase with atomic adds
+    (both shapes, pinned on every level) gives the oracle's operators: FP64 to 1e-12, FP32
+    to 1e-5, within the componentwise bounds, wall rows exact."""
+    from paper_2305_08986_amd import fsi
+    wl, ctx, ops, aops = _ctx_and_ops(name)
+    ctx.set_mg_params(tuned=1)
+    rng = np.random.default_rng([29, len(name)])
+    try:
+        for var in fsi.ATOMIC_VARIANTS_2D:
+            for j in range(ctx.n_levels):
+                for prec in (0, 1):
+                    ctx.set_tuning(j, prec, var)
+            for j in sorted({0, ctx.n_levels - 1, ctx.n_levels // 2}):
+                op = ops[j]
+                u = rng.uniform(-1, 1, op.box.n_vel)
+                p = rng.uniform(-1, 1, op.box.n_p)
+                ut, pt = torch.from_numpy(u).cuda(), torch.from_numpy(p).cuda()
+                bd = bounds(aops[j], u, p)
+                tag = f"{name} var{var} L{j}"
+                a = ctx.apply_A(j, ut)
+                assert np.array_equal(a.cpu().numpy()[op.dir_mask], u[op.dir_mask])
+                _cmp(a, op.apply_A(u), 1e-12, f"{tag} A", bd["A"])
+                _cmp(ctx.apply_B(j, ut), op.apply_B(u), 1e-12, f"{tag} B", bd["B"])
+                bt = ctx.apply_BT(j, pt)
+                assert not np.any(bt.cpu().numpy()[op.dir_mask])
+                _cmp(bt, op.apply_BT(p), 1e-12, f"{tag} BT", bd["BT"])
+                rv, rq = op.apply_stokes(u, p)
+                v, q = ctx.apply_stokes(j, ut, pt)
+                _cmp(v, rv, 1e-12, f"{tag} stokes-v", bd["v"])
+                _cmp(q, rq, 1e-12, f"{tag} stokes-q", bd["q"])
+                uf, pf = ut.float(), pt.float()
+                ru32, rp32 = uf.double().cpu().numpy(), pf.double().cpu().numpy()
+                b32 = bounds(aops[j], ru32, rp32)
+                _cmp(ctx.apply_A(j, uf), op.apply_A(ru32), 1e-5, f"{tag} fp32 A", b32["A"], U32)
+                _cmp(ctx.apply_B(j, uf), op.apply_B(ru32), 1e-5, f"{tag} fp32 B", b32["B"], U32)
+                _cmp(ctx.apply_BT(j, pf), op.apply_BT(rp32), 1e-5, f"{tag} fp32 BT", b32["BT"], U32)
+                v32, q32 = ctx.apply_stokes(j, uf, pf)
+                rv32, rq32 = op.apply_stokes(ru32, rp32)
+                _cmp(v32, rv32, 1e-5, f"{tag} fp32 stokes-v", b32["v"], U32)
+                _cmp(q32, rq32, 1e-5, f"{tag} fp32 stokes-q", b32["q"], U32)
+    finally:
+        for j in range(ctx.n_levels):
+            for prec in (0, 1):
+                ctx.set_tuning(j, prec, 0)
+
+
 def test_jacobian_input_path_matches_oracle_and_keeps_stored_fp32_geometry():
     """Per-point Jacobians through fsi_set_jacobians (the general ALE input) give the
     oracle's operator in FP64; FP32 applies use the stored geometry even when the

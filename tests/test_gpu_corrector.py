@@ -108,10 +108,11 @@ def test_corrector_every_launch_variant_same_result(name):
             assert np.array_equal(g, b), var
 
 
-@pytest.mark.parametrize("name", ["T3_R", "T3_8"])
+@pytest.mark.parametrize("name", ["T3_R", "T3_8", "T2_R"])
 def test_corrector_atomic_launch_matches_oracle(name):
     """The single atomic launch over all phases with the corrector terms (every shape,
-    FP64 and FP32), alone and in the Stokes apply, within the componentwise bound."""
+    FP64 and FP32, 3D and 2D), alone and in the Stokes apply, within the componentwise
+    bound."""
     from paper_2305_08986_amd import fsi
     wl, ctx, conv = _setup(name)
     ctx.set_mg_params(tuned=1, atomics=1)
@@ -122,7 +123,7 @@ def test_corrector_atomic_launch_matches_oracle(name):
         p = rng.uniform(-1, 1, box.n_p)
         rv, rq, op, bv, bq = _oracle(wl, j, conv[j], u, p)
         ud, pd = torch.from_numpy(u).cuda(), torch.from_numpy(p).cuda()
-        for var in fsi.ATOMIC_VARIANTS:
+        for var in (fsi.ATOMIC_VARIANTS if wl.mesh.dim == 3 else fsi.ATOMIC_VARIANTS_2D):
             for prec in (0, 1):
                 ctx.set_tuning(j, prec, var)
             v, q = ctx.apply_corrector(j, ud, pd)

@@ -64,6 +64,11 @@ def test_argument_errors():
     # launch variants and solve options out of range
     for lev, prec, var in ((ctx.n_levels, 0, 0), (0, 2, 0), (0, 0, fsi.N_LAUNCH_VARIANTS + len(fsi.ATOMIC_VARIANTS)), (0, 1, -1)):
         assert ctx.lib.fsi_set_tuning(ctx.h, lev, prec, var) == fsi.FSI_ERR_ARG
+    # 2D levels have two atomic shapes
+    c2 = fsi.Context.from_mesh(W.make_workload("T2_R").mesh)
+    assert c2.lib.fsi_set_tuning(c2.h, 0, 0, fsi.N_LAUNCH_VARIANTS + len(fsi.ATOMIC_VARIANTS_2D)) == fsi.FSI_ERR_ARG
+    assert c2.lib.fsi_set_tuning(c2.h, 0, 0, fsi.ATOMIC_VARIANTS_2D[-1]) == fsi.FSI_OK
+    c2.close()
     fsi.setup_workload(ctx, wl)
     ctx.setup()
     gu = torch.from_numpy(wl.g_u).cuda()

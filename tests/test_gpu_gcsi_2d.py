@@ -175,7 +175,10 @@ def test_corrector_operator_from_the_step_fields_matches_oracle_2d(case):
     ctx.close()
 
 
-def test_extension_with_fixed_solid_cells_matches_direct_solve_2d(case):
+@pytest.mark.parametrize("launch", ["phased", 16, 17])
+def test_extension_with_fixed_solid_cells_matches_direct_solve_2d(case, launch):
+    """Also with the single atomic launch pinned on every level: in 2D it takes the wall
+    bits from the cell info, so the fixed nodes stay constrained."""
     g, pb, st, ref, out = case
     fsi, ctx = _ctx(g.ext_mesh)
     J = g.mesh.n_levels - 1
@@ -184,6 +187,11 @@ def test_extension_with_fixed_solid_cells_matches_direct_solve_2d(case):
     for j in range(ctx.n_levels):
         ctx.set_coefficients(j, np.zeros_like(g.mu_A[j]), 0.5 * g.mu_A[j])
     ctx.setup()
+    if launch != "phased":
+        ctx.set_mg_params(tuned=1, atomics=1)
+        for j in range(ctx.n_levels):
+            for prec in (0, 1):
+                ctx.set_tuning(j, prec, launch)
     v = np.random.default_rng(5).uniform(-1, 1, pb.box.n_vel)
     gv = torch.empty(pb.box.n_vel, device="cuda", dtype=torch.float64)
     ctx.fixed_values(_dev(v), gv)
