@@ -286,9 +286,10 @@ fsi_status fsi_solve_extension(fsi_ctx* ctx, const double* g, double* u, const f
  * constrain the node at the same position (the flagged region should be a union of
  * coarse cells for the best multigrid; otherwise it stays a valid symmetric
  * preconditioner).  fixed: HOST array of n_cells (finest level), nonzero = fixed.
- * Call once, before fsi_setup; on 3D levels the single atomic launch (variants 16 .. 20,
- * whose wall bits follow from the box faces) is not used on such a context; the 2D atomic
- * launch reads the cell's wall bits and keeps the fixed nodes.  Errors: FSI_ERR_ARG, FSI_ERR_STATE after fsi_setup or a second
+ * Call once, before fsi_setup.  The single atomic launch (variants 16 ..) keeps the fixed
+ * nodes as well: in 3D the A apply then reads a per-node wall mask instead of deriving the
+ * wall bits from the box faces (the other 3D classes keep the phased launches on such a
+ * context), in 2D every class reads the cell's wall bits.  Errors: FSI_ERR_ARG, FSI_ERR_STATE after fsi_setup or a second
  * call. */
 fsi_status fsi_set_fixed_cells(fsi_ctx* ctx, const uint8_t* fixed);
 /* Boundary data of the extension: g = v on the nodes of the fixed cells, 0 elsewhere

@@ -336,6 +336,10 @@ static int path_key(const Context* ctx) {
            (ctx->prm.corrector ? 16 : 0) | (ctx->prm.atomics ? 32 : 0);
 }
 
+// the single atomic launch serves a class on this level: on 3D levels with fixed cells only A
+// has the kernel that reads the fixed nodes' wall mask (the other classes keep the phases)
+static bool atomic_ok(const Level& L, int mode) { return !(L.dim == 3 && L.fixed_nodes) || mode == OP_A; }
+
 // the solver's velocity block: A, or in the corrector mode A + N + S
 static int solver_mode(const Context* ctx, int mode) {
     return (ctx->prm.corrector && (mode & OP_A)) ? (mode | OP_CONV) : mode;
@@ -350,7 +354,7 @@ static void op_apply(Context* ctx, int j, int mode, const T* u, const double* p,
     const int am = !(ctx->prm.tuned && ctx->prm.atomics) ? -1
                    : (mode & OP_CONV) ? ctx->atom_conv[prec_index<T>()][(size_t)j]
                                       : ctx->atom_of(prec_index<T>(), j, mode);
-    if (am >= 0) {
+    if (am >= 0 && atomic_ok(L, mode)) {
         launch_cell_atomic<T>(L, mode, am, Kmode<T>(L, mode), CVp<T>(L), u, p, v, q, s);   // wall rows included
         return;
     }
@@ -1723,6 +1727,7 @@ fsi_status fsi_set_fixed_cells(fsi_ctx* h, const uint8_t* fixed) {
         L.n_dir = (int64_t)dirn.size();
         FSI_HIP_TRY(hipMemcpy(L.d_dir_nodes, dirn.data(), sizeof(int) * dirn.size(), hipMemcpyHostToDevice));
         FSI_HIP_TRY(hipMemcpy(L.d_wall, L.h_dir_node.data(), (size_t)L.nvn, hipMemcpyHostToDevice));
+        L.fixed_nodes = true;
         // wall bits of the cell info (processing order; vmap gives each local node's node)
         std::vector<int> vmap((size_t)L.nc * NLOC);
         std::vector<uint4> info((size_t)L.nc);
@@ -1960,8 +1965,7 @@ fsi_status fsi_autotune(fsi_ctx* h) {
             for (int m : unfused) {
                 const size_t k = (size_t)j * kTuneClasses + tune_class(m);
                 ctx->atom[pi][k] = -1;
-                // the 3D atomic form takes its wall bits from the box faces: not with fixed cells
-                if (ctx->lv[j].dim == 3 && ctx->has_fixed) continue;
+                if (!atomic_ok(ctx->lv[j], m)) continue;
                 double best = ctx->tune_us[pi][k];
                 for (int shape = 0; shape < atom_shapes(ctx->lv[j].dim); ++shape) {
                     const int reps = 3;
@@ -1990,7 +1994,7 @@ fsi_status fsi_autotune(fsi_ctx* h) {
         for (int j = 0; j < ctx->nlev; ++j) {
             ctx->atom_conv[pi][(size_t)j] = -1;
             const Level& L = ctx->lv[j];
-            if ((L.dim == 3 && ctx->has_fixed) || !L.conv_set) continue;
+            if (!L.conv_set || !atomic_ok(L, OP_A | OP_CONV)) continue;
             const int m = OP_A | OP_CONV;
             double best = 1e300;
             for (int shape = -1; shape < atom_shapes(L.dim); ++shape) {
@@ -2088,7 +2092,7 @@ fsi_status fsi_time_operator(fsi_ctx* h, int level, int precision, int mode, int
     // tuned levels where the autotuner chose the single atomic launch time that launch
     // (with the zeroing of its outputs) as one unit
     const int am = (ctx->prm.tuned && ctx->prm.atomics && !fused_mode && !conv_mode) ? ctx->atom_of(precision, level, mode) : -1;
-    const bool atomic = am >= 0;
+    const bool atomic = am >= 0 && atomic_ok(L, mode);
     const int nph = atomic ? 1 : L.nphases();
     std::vector<hipEvent_t> ev((size_t)2 * nph + 2);
     for (auto& e : ev) FSI_HIP_TRY(hipEventCreate(&e));
@@ -2153,8 +2157,6 @@ fsi_status fsi_set_tuning(fsi_ctx* h, int level, int precision, int variant) {
     const bool atomic = variant >= kNumVariants;
     if (atomic && variant >= kNumVariants + atom_shapes(ctx->lv[level].dim))
         return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: 2D levels have two atomic shapes (variants 16, 17)");
-    if (atomic && ctx->has_fixed && ctx->lv[level].dim == 3)
-        return fail(ctx, FSI_ERR_ARG, "fsi_set_tuning: no 3D single atomic launch with fixed cells");
     for (int c = 0; c < kTuneClasses; ++c)
         ctx->tune_variant[precision][(size_t)level * kTuneClasses + c] = atomic ? 0 : variant;
     for (int c = 0; c < kTuneClasses; ++c)

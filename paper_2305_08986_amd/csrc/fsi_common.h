@@ -61,7 +61,10 @@ __host__ __device__ inline int64_t geo_off(const GeoLayout& g, int qx, int64_t c
 // the streamline term r (v° . grad u)(v° . grad w)
 // OP_ATOM: one launch over every phase, adding into zeroed outputs with atomics
 // (small levels, where the four phase launches are latency-bound)
-enum : int { OP_A = 1, OP_BT = 2, OP_B = 4, OP_CHEB = 8, OP_RES = 16, OP_CONV = 32, OP_ATOM = 64 };
+enum : int { OP_A = 1, OP_BT = 2, OP_B = 4, OP_CHEB = 8, OP_RES = 16, OP_CONV = 32, OP_ATOM = 64, OP_FIXW = 128 };
+// OP_FIXW (3D, with OP_ATOM | OP_A only): the level has interior constrained nodes (fixed cells), whose
+// wall bits come from the per-node mask instead of the box faces; a template bit, so that the
+// other atomic kernels carry no test for it
 
 // ---------------------------------------------------------------- error helpers
 #define FSI_HIP_TRY(expr)                                                          \
@@ -146,6 +149,7 @@ struct Level {
     float* d_cb32 = nullptr;
     float* d_cs32 = nullptr;
     bool conv_set = false;
+    bool fixed_nodes = false;   // interior constrained nodes (fsi_set_fixed_cells) in d_wall
     double rho = 0.0;
     bool vgeo_avail = false;          // geometry came from vertex displacements (3D)
     bool vgeo = false;                // ... and the FP32 kernels use it

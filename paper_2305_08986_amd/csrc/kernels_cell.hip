@@ -74,6 +74,9 @@ struct CellArgs {
     const int* __restrict__ vmap;
     const uint4* __restrict__ info;
     const int* __restrict__ rowmap;   // OP_ATOM: phase-major row of each dispatch slot
+    // OP_FIXW (the 3D atomic A on a level with fixed cells): the per-node wall mask, which
+    // replaces the wall bits derived from the box faces
+    const uint8_t* __restrict__ wallmask;
     const int* __restrict__ pmap;
     const T* __restrict__ K;
     const T* __restrict__ cv;
@@ -138,6 +141,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     constexpr bool CONV = (MODE & OP_CONV) != 0;
     // every phase in one launch: each touch adds atomically (outputs zeroed beforehand)
     constexpr bool ATOM = (MODE & OP_ATOM) != 0;
+    constexpr bool FIXW = (MODE & OP_FIXW) != 0;
+    static_assert(!FIXW || MODE == (OP_A | OP_ATOM | OP_FIXW), "the fixed-node wall mask goes with the atomic A");
     static_assert(!ATOM || !(CHEB || RES), "the atomic form has no epilogue");
     static_assert(!CHEB || MODE == (OP_A | OP_CHEB), "the Chebyshev epilogue goes with A alone");
     static_assert(!CONV || ((MODE & ~OP_ATOM) == (OP_A | OP_CONV) || (MODE & ~OP_ATOM) == (OP_A | OP_BT | OP_B | OP_CONV)),
@@ -147,7 +152,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
 
     static_assert(ZG == 1 || ATOM, "row groups along z belong to the atomic form");
     // A alone reads K' = sqrt(cvisc) K (no cvisc plane): sym(grad-hat u K') K'^T = cvisc sym(H) K^T
-    constexpr bool SCALED = !VG && ((MODE & ~OP_ATOM) == OP_A || MODE == (OP_A | OP_CHEB));
+    constexpr bool SCALED = !VG && ((MODE & ~(OP_ATOM | OP_FIXW)) == OP_A || MODE == (OP_A | OP_CHEB));
     __shared__ T sbuf[WPB][CPW][BUF];
     __shared__ double pbuf[HAS_B ? WPB : 1][CPW][NT][8];
     // x-face hand-over between neighbouring cells of the row: [slot][j][comp][k],
@@ -250,6 +255,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                 node[k] = gx + a.vnx * (gy + a.vny * gz);
                 const bool w = wxy || ((a.dfaces & 16u) && gz == 0) || ((a.dfaces & 32u) && gz == a.vnz - 1);
                 wbits |= (w ? 1u : 0u) << k;
+            }
+            if constexpr (FIXW) {   // fixed nodes inside the box
+                wbits = 0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) wbits |= ((act && a.wallmask[node[k]]) ? 1u : 0u) << k;
             }
         } else {
 #pragma unroll
@@ -1422,9 +1432,10 @@ void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T*
 // the wall rows itself (v = u when A is applied; B^T alone leaves them zero).  Shapes
 // in 3D (kAtomShapes): 0 one wavefront per row; 1 four wavefronts share a row; 2, 3 one
 // wavefront takes two or four rows along z (the plane they share summed in registers);
-// 4 four wavefronts share a pair of rows along z.  In 2D (kAtomShapes2D): one wavefront
-// per row segment, one (0) or two (1) wavefronts per workgroup; the cell info and the
-// node map supply the wall bits, so fixed cells are honoured.
+// 4 four wavefronts share a pair of rows along z; the wall bits follow from the box faces,
+// or on a level with fixed cells from the per-node wall mask.  In 2D (kAtomShapes2D): one
+// wavefront per row segment, one (0) or two (1) wavefronts per workgroup; the cell info
+// and the node map supply the wall bits, so fixed cells are honoured.
 template <int ZG>
 static int64_t atom_slots(const Level& L) {
     return (int64_t)L.cells[1] * ((L.cells[2] + ZG - 1) / ZG);
@@ -1436,6 +1447,7 @@ void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T
     CellArgs<T> args = phase_args<T>(L, 0, K, cv);
     args.cend = L.phase_off[L.nphases()];
     args.rowmap = L.d_atom_rows;
+    args.wallmask = L.d_wall;
     args.cny = L.cells[1];
     args.cnz = L.cells[2];
     args.vnx = L.vnodes[0];
@@ -1451,12 +1463,14 @@ void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T
     launch_atomic_init<T>(L, (mode & (OP_A | OP_BT)) ? v : nullptr, (mode & OP_B) ? q : nullptr, s);
     auto go = [&](auto mc) {
         constexpr int M = decltype(mc)::value | OP_ATOM;
-        if (L.dim == 2) {
-            // every row segment of every phase; shape 0 one wavefront per workgroup, else two
-            args.nrows = (args.cend - args.cbeg) / L.geo.nx;
-            if (shape == 0) launch_one<T, M, 1, true, 1, 1>(L, args, s);
-            else launch_one<T, M, 2, true, 1, 1>(L, args, s);
-            return;
+        if constexpr ((M & OP_FIXW) == 0) {
+            if (L.dim == 2) {
+                // every row segment of every phase; shape 0 one wavefront per workgroup, else two
+                args.nrows = (args.cend - args.cbeg) / L.geo.nx;
+                if (shape == 0) launch_one<T, M, 1, true, 1, 1>(L, args, s);
+                else launch_one<T, M, 2, true, 1, 1>(L, args, s);
+                return;
+            }
         }
         // waves per SIMD the unfused classes reach: FP64 two (A, B, B^T), FP32 four; the
         // Stokes classes are left unconstrained
@@ -1471,7 +1485,10 @@ void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T
         }
     };
     switch (mode) {
-        case OP_A: go(std::integral_constant<int, OP_A>{}); break;
+        case OP_A:
+            if (L.fixed_nodes && L.dim == 3) go(std::integral_constant<int, OP_A | OP_FIXW>{});
+            else go(std::integral_constant<int, OP_A>{});
+            break;
         case OP_B: go(std::integral_constant<int, OP_B>{}); break;
         case OP_BT: go(std::integral_constant<int, OP_BT>{}); break;
         case OP_A | OP_BT: go(std::integral_constant<int, OP_A | OP_BT>{}); break;

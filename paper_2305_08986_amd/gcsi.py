@@ -54,6 +54,8 @@ class Stepper:
             self.ext.set_coefficients(j, torch.zeros_like(mu), 0.5 * mu)
         self.ext.set_mg_params(precision=precision if ext_precision is None else ext_precision)
         self.ext.setup()
+        if autotune:   # the extension's reference geometry never changes: tune its launches once
+            self.ext.autotune()
         self.solid_q = [torch.as_tensor(x, device="cuda", dtype=torch.uint8).contiguous() for x in inputs.solid_q]
         # velocity data on the Dirichlet nodes of the Stokes system (an inflow profile), or none
         d = getattr(inputs, "dirichlet", None)

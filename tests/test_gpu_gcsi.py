@@ -136,7 +136,10 @@ def test_corrector_operator_from_the_step_fields_matches_oracle(case):
     ctx.close()
 
 
-def test_extension_with_fixed_solid_cells_matches_direct_solve(case):
+@pytest.mark.parametrize("launch", ["phased", 16, 17, 18, 19, 20])
+def test_extension_with_fixed_solid_cells_matches_direct_solve(case, launch):
+    """Also with the single atomic launch (every shape) pinned on every level: with fixed
+    cells it reads the per-node wall mask, so the fixed nodes stay constrained."""
     g, pb, st, ref, out = case
     fsi, ctx = _ctx(g.ext_mesh)
     J = g.mesh.n_levels - 1
@@ -145,6 +148,11 @@ def test_extension_with_fixed_solid_cells_matches_direct_solve(case):
     for j in range(ctx.n_levels):
         ctx.set_coefficients(j, np.zeros_like(g.mu_A[j]), 0.5 * g.mu_A[j])
     ctx.setup()
+    if launch != "phased":
+        ctx.set_mg_params(tuned=1, atomics=1)
+        for j in range(ctx.n_levels):
+            for prec in (0, 1):
+                ctx.set_tuning(j, prec, launch)
     v = np.random.default_rng(5).uniform(-1, 1, pb.box.n_vel)
     gv = torch.empty(pb.box.n_vel, device="cuda", dtype=torch.float64)
     ctx.fixed_values(_dev(v), gv)
@@ -293,7 +301,8 @@ def test_time_step_entry_points_reject_bad_input(case):
     with pytest.raises(fsi.FSIError) as e:
         ext.solve(z, zp)
     assert e.value.status == fsi.FSI_ERR_STATE
-    assert ext.raw_status("fsi_set_tuning", ext.n_levels - 1, 0, 16) == fsi.FSI_ERR_ARG
+    # the single atomic launch reads the fixed nodes' wall bits: allowed with fixed cells
+    assert ext.raw_status("fsi_set_tuning", ext.n_levels - 1, 0, 16) == fsi.FSI_OK
     ext.close()
 
 
