@@ -23,7 +23,7 @@ budget:
     vector kernels, default launch shapes), the same FP64 solve with every
     optimisation (captured graph, fused epilogues where faster, tuned launch
     shapes), and the mixed-precision solve (FP32 V-cycle, FP64 FGMRES /
-    residuals / Schur block; median of three, its iteration count moves with
+    residuals / Schur block; median of five, its iteration count moves with
     the order of the atomic adds);
   * the pseudo-elastic extension solve on the same mesh;
   * the corrector mode: its Stokes apply on the same mesh and its solve on the
@@ -312,7 +312,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--mixed-runs", type=int, default=3, help="mixed solves (the median is reported)")
+    ap.add_argument("--mixed-runs", type=int, default=5, help="mixed solves (the median is reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true", help="skip the three solves")
     ap.add_argument("--no-extension", action="store_true", help="skip the extension-solve measurement")

@@ -275,16 +275,21 @@ def test_atomic_single_launch_matches_oracle(name):
                 ra, rb, rbt = op.apply_A(u), op.apply_B(u), op.apply_BT(p)
                 rv, rq = op.apply_stokes(u, p)
                 bd = bounds(aops[j], u, p)
+                # outputs start as NaN: every entry must be written (the initialisation
+                # leaves out the node lines that one row writes by plain stores)
+                def nan_like(x, dt):
+                    return torch.full((x.numel(),), float("nan"), dtype=dt, device="cuda")
                 # FP64 with stored geometry and with the geometry formed from the vertices
                 for vg in (0, 2):
                     ctx.set_mg_params(tuned=1, vertex_geometry=vg)
                     tag = f"{name} var{var} L{j} vg{vg}"
-                    a = ctx.apply_A(j, ut)
+                    a = ctx.apply_A(j, ut, out=nan_like(ut, torch.float64))
                     assert np.array_equal(a.cpu().numpy()[op.dir_mask], u[op.dir_mask])
                     _cmp(a, ra, 1e-12, f"{tag} A", bd["A"])
                     _cmp(ctx.apply_B(j, ut), rb, 1e-12, f"{tag} B", bd["B"])
-                    _cmp(ctx.apply_BT(j, pt), rbt, 1e-12, f"{tag} BT", bd["BT"])
-                    v, q = ctx.apply_stokes(j, ut, pt)
+                    _cmp(ctx.apply_BT(j, pt, out=nan_like(ut, torch.float64)), rbt, 1e-12, f"{tag} BT", bd["BT"])
+                    v, q = ctx.apply_stokes(j, ut, pt, out_v=nan_like(ut, torch.float64),
+                                            out_q=nan_like(pt, torch.float64))
                     _cmp(v, rv, 1e-12, f"{tag} stokes-v", bd["v"])
                     _cmp(q, rq, 1e-12, f"{tag} stokes-q", bd["q"])
                 # FP32 with stored geometry and with the geometry formed from the vertices
@@ -294,10 +299,12 @@ def test_atomic_single_launch_matches_oracle(name):
                     ru32, rp32 = uf.double().cpu().numpy(), pf.double().cpu().numpy()
                     b32 = bounds(aops[j], ru32, rp32)
                     tag = f"{name} var{var} L{j} vg{vg} fp32"
-                    _cmp(ctx.apply_A(j, uf), op.apply_A(ru32), 1e-5, f"{tag} A", b32["A"], U32)
+                    _cmp(ctx.apply_A(j, uf, out=nan_like(uf, torch.float32)), op.apply_A(ru32), 1e-5, f"{tag} A",
+                         b32["A"], U32)
                     _cmp(ctx.apply_B(j, uf), op.apply_B(ru32), 1e-5, f"{tag} B", b32["B"], U32)
                     _cmp(ctx.apply_BT(j, pf), op.apply_BT(rp32), 1e-5, f"{tag} BT", b32["BT"], U32)
-                    v32, q32 = ctx.apply_stokes(j, uf, pf)
+                    v32, q32 = ctx.apply_stokes(j, uf, pf, out_v=nan_like(uf, torch.float32),
+                                                out_q=nan_like(pf, torch.float32))
                     rv32, rq32 = op.apply_stokes(ru32, rp32)
                     _cmp(v32, rv32, 1e-5, f"{tag} stokes-v", b32["v"], U32)
                     _cmp(q32, rq32, 1e-5, f"{tag} stokes-q", b32["q"], U32)

@@ -126,10 +126,13 @@ def test_corrector_atomic_launch_matches_oracle(name):
         for var in (fsi.ATOMIC_VARIANTS if wl.mesh.dim == 3 else fsi.ATOMIC_VARIANTS_2D):
             for prec in (0, 1):
                 ctx.set_tuning(j, prec, var)
-            v, q = ctx.apply_corrector(j, ud, pd)
+            # outputs start as NaN: every entry must be written
+            nan = lambda n, dt: torch.full((n,), float("nan"), dtype=dt, device="cuda")
+            v, q = ctx.apply_corrector(j, ud, pd, out_v=nan(box.n_vel, torch.float64), out_q=nan(box.n_p, torch.float64))
             _cmp(v, rv, 1e-12, f"{name} L{j} v atomic {var}", bv)
             _cmp(q, rq, 1e-12, f"{name} L{j} q atomic {var}", bq)
-            v, q = ctx.apply_corrector(j, ud.float(), pd.float())
+            v, q = ctx.apply_corrector(j, ud.float(), pd.float(), out_v=nan(box.n_vel, torch.float32),
+                                       out_q=nan(box.n_p, torch.float32))
             _cmp(v, rv, 1e-5, f"{name} L{j} v f32 atomic {var}", bv, U32)
             _cmp(q, rq, 1e-5, f"{name} L{j} q f32 atomic {var}", bq, U32)
 
