@@ -71,15 +71,16 @@ def test_fgmres_solution_matches_direct(name, prec):
     uo, po = solvers.direct_solve(op, wl.g_u, wl.g_p)
     eu = np.linalg.norm(u - uo) / np.linalg.norm(uo)
     print("velocity error vs direct", eu)
-    # the benchmark spec: velocity within 1e-7 of the FP64 solution at residual 1e-8 (C0 is solved
-    # to 1e-10, so 1e-9 there)
+    # target: velocity within 1e-7 of the FP64 solution at residual 1e-8 (C0 is solved to
+    # 1e-10, so 1e-9 there)
     assert eu <= 10 * rtol, eu
 
 
 @pytest.mark.parametrize("name", ["T3_16", "T3_8"])
 def test_mixed_and_fp64_solutions_agree_to_1e7(name):
     """Mixed precision (FP32 V-cycle, FP64 FGMRES) and plain FP64 solves to the same true
-    residual 1e-8: the velocities differ by at most 1e-7 relative (the benchmark spec), and each is
+    residual 1e-8: the velocities differ by at most 1e-7 relative (the accuracy target of the
+    mixed-precision path), and each is
     within 1e-7 of the oracle's direct solution."""
     wl, ctx, ops = _setup(name)
     ctx.autotune()
