@@ -49,6 +49,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 # worker processes of the CPU leg: the host cores a one-GPU job gets on the box
 CPU_WORKERS_MAX = 16
 
@@ -80,12 +81,12 @@ def kernel_bytes_per_cell(dim: int, elem: int) -> int:
     return (dim * dim + 1) * q * elem + 2 * (2 ** dim) * dim * elem + 4 * q
 
 
-def load_counter_profile(workload: str, form: str = "phased"):
-    """HBM traffic of the FP64 A apply from the committed rocprofv3 counter summary:
-    per processing-phase launch of the default phased form, or per apply (the single
-    launch and its initialisation kernel) of the atomic form."""
+def load_counter_profile(workload: str, form: str = "phased", prec: str = "fp64"):
+    """HBM traffic of the A apply (FP64 or FP32) from the committed rocprofv3 counter
+    summary: per processing-phase launch of the default phased form, or per apply (the
+    single launch and its initialisation kernel) of the atomic form."""
     tag = "" if form == "phased" else "atomic_"
-    path = os.path.join(ROOT, "profiles", f"counters_cell3d_A_fp64_{tag}{workload}.json")
+    path = os.path.join(ROOT, "profiles", f"counters_cell3d_A_{prec}_{tag}{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -431,6 +432,22 @@ def main():
             tf = prof["fp64_flops_per_launch"] / (per * 1e-6) / 1e12
             flops = {"fp64_tflops": round(tf, 2), "peak": FP64_PEAK_TFLOPS, "frac": round(tf / FP64_PEAK_TFLOPS, 4),
                      "source": "rocprofv3 SQ_INSTS_VALU_FMA/ADD/MUL_F64 per launch (profiles/)"}
+    # the FP32 A apply of the V-cycle (median of timed applies in its tuned form): its own
+    # roofline and, where the committed counter summary matches the tuned variant and the
+    # kernel source, its HBM traffic and FP32 FLOP rate
+    bpc32 = algorithmic_bytes_per_cell(mesh.dim, 4)
+    var32 = tuning[f"L{J}"][1]
+    prof32 = load_counter_profile(name, "atomic", "fp32") if var32 >= fsi.N_LAUNCH_VARIANTS else None
+    if prof32 is not None and f"variant {var32}" not in prof32.get("kernel", ""):
+        prof32 = None
+    fp32_roof = {
+        "bound": "hbm", "achieved": round(bpc32 * nc / (op32_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(bpc32 * nc / (op32_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_cell": bpc32,
+        "apply_us": round(op32_us, 1), "variant": var32,
+        "traffic": prof32["hbm_bytes_per_launch"] if prof32 else None,
+        "fp32_tflops": (round(prof32["fp32_flops_per_launch"] / (op32_us * 1e-6) / 1e12, 2) if prof32 else None),
+        "fp32_peak_tflops": FP32_PEAK_TFLOPS,
+    }
     out = {
         "metric": "Q2 matrix-free vmult GDoF/s; Stokes solve time to rel.res 1e-8, FP64 vs mixed",
         "value": round(gdofs, 4),
@@ -462,6 +479,7 @@ def main():
             "fp64_A_phased_default_mean_launch_us": round(k0_us / max(1, nl0), 2),
             "fp64_A_phased_default_roofline_frac": round(bpc * nc / (k0_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
             "fp32_A_gdofs": round(nv / (op32_us * 1e-6) / 1e9, 4),
+            "fp32_A_roofline": fp32_roof,
             "fp64_stokes_gdofs": round((nv + npr) / (ops_us * 1e-6) / 1e9, 4),
             "fp32_A_vertex_geometry_gdofs": round(nv / (opv_us * 1e-6) / 1e9, 4),
             "fp64_A_vertex_geometry_gdofs": round(nv / (opv64_us * 1e-6) / 1e9, 4),

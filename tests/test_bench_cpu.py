@@ -31,13 +31,15 @@ def test_counter_profiles_follow_the_kernel_source():
     """The committed counter summaries are used only while their source hash matches
     the cell-kernel source; a changed source gives no traffic figure."""
     b = _bench()
-    for form in ("phased", "atomic"):
-        prof = b.load_counter_profile("C3", form)
-        assert prof is not None, form
+    for form, prec in (("phased", "fp64"), ("atomic", "fp64"), ("atomic", "fp32")):
+        prof = b.load_counter_profile("C3", form, prec)
+        assert prof is not None, (form, prec)
         assert prof["hbm_bytes_per_launch"] > 0
+    assert b.load_counter_profile("C3", "atomic", "fp32")["fp32_flops_per_launch"] > 0
     b.cell_kernel_source_hash = lambda: "0" * 16
     assert b.load_counter_profile("C3") is None
     assert b.load_counter_profile("C3", "atomic") is None
+    assert b.load_counter_profile("C3", "atomic", "fp32") is None
     assert b.load_counter_profile("no-such-workload") is None
 
 
