@@ -383,9 +383,9 @@ fsi_status fsi_lift_dirichlet(fsi_ctx* ctx, const double* d, double* g_u, double
  * (A, A with the fused Chebyshev step, Stokes, Stokes with the fused residual,
  * B, B^T), level and precision, and keeps the fastest of each; then, per level,
  * the phased launches of the unfused applies against their single atomic launch
- * (variants 16 .. 20 below on 3D levels, 16 and 17 on 2D levels), on levels where the corrector terms are set
+ * (variants 16 .. 22 below on 3D levels, 16 and 17 on 2D levels), on levels where the corrector terms are set
  * (fsi_set_convection) the same choice for the corrector classes (A + N + S alone and in
- * the Stokes apply), and the fused epilogues against the separate vector kernels.  Synchronises; fsi_get_tuning reports the choice for A (16 .. 20 where the
+ * the Stokes apply), and the fused epilogues against the separate vector kernels.  Synchronises; fsi_get_tuning reports the choice for A (16 .. 22 where the
  * atomic launch was chosen) and its measured time per application in best_us. */
 fsi_status fsi_autotune(fsi_ctx* ctx);
 fsi_status fsi_get_tuning(const fsi_ctx* ctx, int level, int precision, int* variant, double* best_us);
@@ -395,12 +395,13 @@ fsi_status fsi_get_tuning(const fsi_ctx* ctx, int level, int precision, int* var
  * per wavefront, at most two); (v / 3) % 2 cached instead of streaming geometry
  * loads; v / 6 a register cap of one more wavefront per SIMD.  v = 12 .. 15: three
  * wavefronts share a row (2D: two rows), (v - 12) % 2 cached loads, (v - 12) / 2 the
- * register cap.  v = 16 .. 20 on 3D levels, 16 and 17 on 2D levels: the unfused applies
+ * register cap.  v = 16 .. 22 on 3D levels, 16 and 17 on 2D levels: the unfused applies
  * (A, B, B^T, Stokes, and the corrector classes) run as one launch over all processing
  * phases that adds into zeroed outputs with atomics and writes the wall rows itself.
  * 3D: one (16) or four (17) wavefronts per row, one wavefront over two (18) or four (19)
  * rows along z, four wavefronts over two rows along z (20), where the node plane two rows
- * of a group share is summed in registers and stored once.  2D: one wavefront per row
+ * of a group share is summed in registers and stored once, one wavefront per half (21) or
+ * quarter (22) row, where the x-face node two segments share takes atomics from both.  2D: one wavefront per row
  * segment, one (16) or two (17) per workgroup.  Results then vary in the last bits from
  * run to run; the fused epilogues keep variant 0.  fsi_autotune picks this form for a level where it
  * measures it faster.  Errors: FSI_ERR_ARG. */

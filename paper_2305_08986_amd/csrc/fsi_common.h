@@ -305,8 +305,9 @@ void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T*
 // the same apply in one launch over all phases with atomic adds, wall rows included
 // (modes A, B, B^T and A + B^T + B, and the corrector classes; 3D shapes 0 ..
 // kAtomShapes - 1: one or four wavefronts per row, rows grouped along z by one, two or
-// four; 2D shapes 0 .. kAtomShapes2D - 1: one or two wavefronts per workgroup)
-constexpr int kAtomShapes = 5;
+// four, or one wavefront per half or quarter row; 2D shapes 0 .. kAtomShapes2D - 1: one or
+// two wavefronts per workgroup)
+constexpr int kAtomShapes = 7;
 constexpr int kAtomShapes2D = 2;
 inline int atom_shapes(int dim) { return dim == 3 ? kAtomShapes : kAtomShapes2D; }
 template <typename T>

@@ -113,6 +113,11 @@ struct CellArgs {
     int vnx, vny, vnz;
     int pnx, pny;
     unsigned dfaces;
+    // OP_ATOM, one wavefront per row (no row sharing): each row is cut into nseg segments
+    // of segch chunks, one dispatch slot per segment (shorter work units, a shorter tail
+    // at the end of the launch); the x-face node two segments share takes atomics from
+    // both.  nseg = 1: whole rows
+    int nseg, segch;
 };
 
 // ============================================================== 3D
@@ -169,14 +174,23 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     const bool inwave = slot < CPW;
     const int64_t slot_row = RS ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * WPB + wave;
     const bool slotact = slot_row < a.nrows;
-    // the atomic form has no order to keep: dispatch slot g takes the natural rows
-    // (iy, iz) = (g mod ny, ZG (g div ny) + z), whose geometry sits at the phase-major
-    // row that the row map gives
+    // the atomic form has no order to keep: dispatch slot g takes segment g mod nseg of
+    // the natural rows (iy, iz) = (r mod ny, ZG (r div ny) + z), r = g div nseg, whose
+    // geometry sits at the phase-major row that the row map gives
     int siy = 0, siz0 = 0;
+    int chb = 0, che = a.nchunks;   // the slot's chunks [chb, che) of its rows
     if constexpr (ATOM) {
-        siy = (int)(slot_row % a.cny);
-        siz0 = (int)(slot_row / a.cny) * ZG;
+        const int64_t rslot = slot_row / a.nseg;
+        siy = (int)(rslot % a.cny);
+        siz0 = (int)(rslot / a.cny) * ZG;
+        if constexpr (!RS) {
+            chb = (int)(slot_row - rslot * a.nseg) * a.segch;
+            che = min(a.nchunks, chb + a.segch);
+        }
     }
+    // cells [xbeg, xend) of the row; the x-face columns at a segment seam are shared with
+    // the neighbouring segment
+    const int xbeg = chb * CPW, xend = min(a.nx, che * CPW);
     // row z of the slot's group active; its geometry row (loaded once, before the walk,
     // so that no step's geometry loads wait for a row-map load)
     auto zact = [&](int z) { return ATOM ? (slotact && siz0 + z < a.cnz) : slotact; };
@@ -190,7 +204,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         if constexpr (ATOM) return z == 0 ? zr[0] : (z == 1 ? zr[1] : (z == 2 ? zr[2] : zr[3]));
         else return slot_row;
     };
-    const int nsteps = RS ? (a.nchunks + WPB - 1) / WPB : a.nchunks;
+    const int nsteps = RS ? (a.nchunks + WPB - 1) / WPB : max(0, che - chb);
     const int cw = RS ? 0 : wave;                  // owner of the chunk-to-chunk carry
     const bool carry_out = !RS || wave == WPB - 1; // this wavefront's last cell feeds the next step
     T* B = sbuf[wave][inwave ? slot : 0];
@@ -229,17 +243,19 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
         const bool rowact = zact(z);
         const int64_t row = __builtin_amdgcn_readfirstlane((int)zrow(z));
         if constexpr (!PREF && !ATOM) fetch_idx(st);
-        const int ch = RS ? st * WPB + wave : st;
+        const int ch = RS ? st * WPB + wave : chb + st;
         const int ix = ch * CPW + slot;
-        const bool act = rowact && inwave && ix < a.nx;
+        const bool act = rowact && inwave && ix < xend;
         const int64_t cell = a.cbeg + row * a.nx + ix;   // phase cells are stored row by row
         // the chunk is wavefront-uniform: keep it scalar so that every geometry load is
         // a scalar base plus the lane's fixed offset (no per-plane vector addresses)
         const int64_t chunk = __builtin_amdgcn_readfirstlane((int)(a.chunk0 + row * a.nchunks + ch));
         const uint4 inf = inf_nx;
         // does this thread write its column (x-face columns go to the right neighbour)?
-        const bool vwriter = act && (ic != 2 || ix == a.nx - 1);
-        const bool pwriter = act && t < 8 && (pax == 0 || ix == a.nx - 1);
+        const bool vwriter = act && (ic != 2 || ix == xend - 1);
+        const bool pwriter = act && t < 8 && (pax == 0 || ix == xend - 1);
+        // a column on a seam between two segments of the row: its sums are partial
+        const bool xseam = ATOM && ((ic == 0 && ix == xbeg && ix > 0) || (ic == 2 && xend < a.nx));
         // the atomic form: node indices, wall bits of this thread's column and the cell's
         // vertices from the cell coordinates (ix, iy, iz)
         const int iz = siz0 + z;
@@ -731,7 +747,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             }
             __syncthreads();   // pxb crosses wavefronts (row sharing)
             if (act && t < 8) {
-                if (pax == 0 && ix > 0)
+                if (pax == 0 && ix > xbeg)
                     sq += slot > 0 ? pxb[ls & 1][wave][slot - 1][pyz]
                                    : ((RS && wave > 0) ? pxb[ls & 1][wave - 1][CPW - 1][pyz]
                                                        : pcarry[cw][z][(st + 1) & 1][pyz]);
@@ -853,7 +869,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             }
             __syncthreads();   // xb crosses wavefronts (row sharing)
             if (act) {
-                if (ic == 0 && ix > 0) {
+                if (ic == 0 && ix > xbeg) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -890,7 +906,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                             continue;
                         }
                         if (k == 2 && carry_next) continue;   // added at the next z
-                        const bool plain = jc == 1 && (k == 1 || (k == 0 && ZG > 1 && z > 0));
+                        const bool plain = !xseam && jc == 1 && (k == 1 || (k == 0 && ZG > 1 && z > 0));
                         if (plain) {
 #pragma unroll
                             for (int c = 0; c < 3; ++c) a.v[c * a.nvn + nd] = out[c][k];
@@ -1432,7 +1448,8 @@ void launch_cell_all(const Level& L, int mode, int variant, const T* K, const T*
 // the wall rows itself (v = u when A is applied; B^T alone leaves them zero).  Shapes
 // in 3D (kAtomShapes): 0 one wavefront per row; 1 four wavefronts share a row; 2, 3 one
 // wavefront takes two or four rows along z (the plane they share summed in registers);
-// 4 four wavefronts share a pair of rows along z; the wall bits follow from the box faces,
+// 4 four wavefronts share a pair of rows along z; 5, 6 one wavefront per half or quarter
+// row; the wall bits follow from the box faces,
 // or on a level with fixed cells from the per-node wall mask.  In 2D (kAtomShapes2D): one
 // wavefront per row segment, one (0) or two (1) wavefronts per workgroup; the cell info
 // and the node map supply the wall bits, so fixed cells are honoured.
@@ -1476,11 +1493,16 @@ void launch_cell_atomic(const Level& L, int mode, int shape, const T* K, const T
         // Stokes classes are left unconstrained
         constexpr bool STOKES = (M & OP_A) && (M & OP_BT);
         constexpr int W0 = (STOKES || (M & OP_CONV)) ? 1 : (sizeof(T) == 8 ? 2 : 4);
+        // shapes 5 and 6: shape 0 with every row cut into two or four segments
+        args.nseg = shape == 5 ? 2 : (shape == 6 ? 4 : 1);
+        args.segch = (args.nchunks + args.nseg - 1) / args.nseg;
         switch (shape) {
             case 0: args.nrows = atom_slots<1>(L); launch_one<T, M, 1, true, W0, 1>(L, args, s); break;
             case 1: args.nrows = atom_slots<1>(L); launch_one<T, M, 4, true, W0, 1>(L, args, s); break;
             case 2: args.nrows = atom_slots<2>(L); launch_one<T, M, 1, true, W0, 2>(L, args, s); break;
             case 3: args.nrows = atom_slots<4>(L); launch_one<T, M, 1, true, W0, 4>(L, args, s); break;
+            case 5:
+            case 6: args.nrows = atom_slots<1>(L) * args.nseg; launch_one<T, M, 1, true, W0, 1>(L, args, s); break;
             default: args.nrows = atom_slots<2>(L); launch_one<T, M, 4, true, W0, 2>(L, args, s); break;
         }
     };

@@ -30,8 +30,8 @@ PREC_MIXED = 1
 N_LAUNCH_VARIANTS = 16
 # fsi_set_tuning values of the single atomic launch over all phases (3D levels): one or
 # four wavefronts per row, one wavefront over two or four rows along z, four wavefronts
-# over two rows along z
-ATOMIC_VARIANTS = (16, 17, 18, 19, 20)
+# over two rows along z, one wavefront per half or quarter row
+ATOMIC_VARIANTS = (16, 17, 18, 19, 20, 21, 22)
 ATOMIC_VARIANTS_2D = (16, 17)   # the same form on 2D levels: one or two wavefronts per workgroup
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_STATE", -3: "ERR_HIP", -4: "ERR_OOM",
