@@ -81,19 +81,28 @@ def kernel_bytes_per_cell(dim: int, elem: int) -> int:
     return (dim * dim + 1) * q * elem + 2 * (2 ** dim) * dim * elem + 4 * q
 
 
-def load_counter_profile(workload: str, form: str = "phased", prec: str = "fp64"):
+def load_counter_profile(workload: str, form: str = "phased", prec: str = "fp64", variant=None):
     """HBM traffic of the A apply (FP64 or FP32) from the committed rocprofv3 counter
     summary: per processing-phase launch of the default phased form, or per apply (the
-    single launch and its initialisation kernel) of the atomic form."""
+    single launch and its initialisation kernel) of the atomic form.  With `variant`,
+    only a summary taken in that launch variant (the file of the form, or the one named
+    for the variant)."""
     tag = "" if form == "phased" else "atomic_"
-    path = os.path.join(ROOT, "profiles", f"counters_cell3d_A_{prec}_{tag}{workload}.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        d = json.load(f)
-    if d.get("kernel_source_sha256_16") != cell_kernel_source_hash():
-        return None
-    return d
+    names = [f"counters_cell3d_A_{prec}_{tag}{workload}.json"]
+    if variant is not None:
+        names.insert(0, f"counters_cell3d_A_{prec}_{tag}v{variant}_{workload}.json")
+    for name in names:
+        path = os.path.join(ROOT, "profiles", name)
+        if not os.path.exists(path):
+            continue
+        with open(path) as f:
+            d = json.load(f)
+        if d.get("kernel_source_sha256_16") != cell_kernel_source_hash():
+            continue
+        if variant is not None and d.get("variant") != variant:
+            continue
+        return d
+    return None
 
 
 # ---------------------------------------------------------------- CPU leg (oracle)
@@ -422,7 +431,7 @@ def main():
     # algorithmic bytes of one apply / its mean duration over the timed steps (HIP events on
     # the library stream; the atomic form is its output zero fill plus one cell launch)
     achieved = bpc * nc / (apply_us * 1e-6) / 1e9
-    prof = load_counter_profile(name, "atomic") if atomic else (load_counter_profile(name) if tuned_var == 0 else None)
+    prof = load_counter_profile(name, "atomic", "fp64", tuned_var) if atomic else load_counter_profile(name, "phased", "fp64", tuned_var)
     traffic = None
     flops = None
     if prof is not None:
@@ -437,9 +446,7 @@ def main():
     # kernel source, its HBM traffic and FP32 FLOP rate
     bpc32 = algorithmic_bytes_per_cell(mesh.dim, 4)
     var32 = tuning[f"L{J}"][1]
-    prof32 = load_counter_profile(name, "atomic", "fp32") if var32 >= fsi.N_LAUNCH_VARIANTS else None
-    if prof32 is not None and f"variant {var32}" not in prof32.get("kernel", ""):
-        prof32 = None
+    prof32 = load_counter_profile(name, "atomic", "fp32", var32) if var32 >= fsi.N_LAUNCH_VARIANTS else None
     fp32_roof = {
         "bound": "hbm", "achieved": round(bpc32 * nc / (op32_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(bpc32 * nc / (op32_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_cell": bpc32,

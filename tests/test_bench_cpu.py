@@ -31,11 +31,14 @@ def test_counter_profiles_follow_the_kernel_source():
     """The committed counter summaries are used only while their source hash matches
     the cell-kernel source; a changed source gives no traffic figure."""
     b = _bench()
-    for form, prec in (("phased", "fp64"), ("atomic", "fp64"), ("atomic", "fp32")):
-        prof = b.load_counter_profile("C3", form, prec)
-        assert prof is not None, (form, prec)
-        assert prof["hbm_bytes_per_launch"] > 0
+    for form, prec, var in (("phased", "fp64", 0), ("atomic", "fp64", 16), ("atomic", "fp64", 21),
+                            ("atomic", "fp32", 20), ("atomic", "fp32", 17)):
+        prof = b.load_counter_profile("C3", form, prec, var)
+        assert prof is not None, (form, prec, var)
+        assert prof["variant"] == var and prof["hbm_bytes_per_launch"] > 0
     assert b.load_counter_profile("C3", "atomic", "fp32")["fp32_flops_per_launch"] > 0
+    # a variant with no summary of its own gives no traffic figure
+    assert b.load_counter_profile("C3", "atomic", "fp64", 18) is None
     b.cell_kernel_source_hash = lambda: "0" * 16
     assert b.load_counter_profile("C3") is None
     assert b.load_counter_profile("C3", "atomic") is None
