@@ -1968,7 +1968,8 @@ fsi_status fsi_autotune(fsi_ctx* h) {
                 if (!atomic_ok(ctx->lv[j], m)) continue;
                 double best = ctx->tune_us[pi][k];
                 for (int shape = 0; shape < atom_shapes(ctx->lv[j].dim); ++shape) {
-                    const int reps = 3;
+                    // large levels: more repetitions (the atomic shapes there differ by about 1%)
+                    const int reps = ctx->lv[j].nc >= (int64_t(1) << 18) ? 10 : 3;
                     for (int r = 0; r <= reps; ++r) {
                         if (r == 1) FSI_HIP_TRY(hipEventRecord(e0, s));
                         launch_atomic_on_work(ctx, pi, j, m, shape, s);
@@ -1998,7 +1999,7 @@ fsi_status fsi_autotune(fsi_ctx* h) {
             const int m = OP_A | OP_CONV;
             double best = 1e300;
             for (int shape = -1; shape < atom_shapes(L.dim); ++shape) {
-                const int reps = 3;
+                const int reps = L.nc >= (int64_t(1) << 18) ? 10 : 3;
                 for (int r = 0; r <= reps; ++r) {
                     if (r == 1) FSI_HIP_TRY(hipEventRecord(e0, s));
                     if (shape < 0) {
