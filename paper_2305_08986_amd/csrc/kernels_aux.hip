@@ -576,11 +576,42 @@ __global__ void k_zero2(T* __restrict__ v, int64_t nv, double* __restrict__ q, i
     if (v && i < nv) v[i] = T(0);
     if (q && i < np) q[i] = 0.0;
 }
+// zero fill of a velocity vector (component-major, x fastest), node plane by node plane
+// (kZeroPlaneParts blocks per plane), top planes first: the planes the atomic cell launch reaches first (low z; it walks the
+// rows in natural order) are written last and are the likeliest to still sit in the
+// memory-side cache when its adds arrive.  16-byte stores; a store unit that straddles
+// two planes is written by both blocks (zeros either way); the array's last unit may run
+// past the end and is written element by element.
+constexpr int kZeroPlaneParts = 4;   // blocks per node plane and component
+template <typename T>
+__global__ void k_zero_planes_desc(T* __restrict__ x, int64_t nvn, int64_t plane, int nz, int ncomp, int64_t n) {
+    constexpr int E = 16 / sizeof(T);
+    const int part = (int)(blockIdx.x % kZeroPlaneParts), pc = (int)(blockIdx.x / kZeroPlaneParts);
+    const int zz = pc / ncomp, c = pc % ncomp;
+    const int64_t p0 = c * nvn + (int64_t)(nz - 1 - zz) * plane;
+    const int64_t s0 = p0 + plane * part / kZeroPlaneParts, s1 = p0 + plane * (part + 1) / kZeroPlaneParts;
+    const int64_t u0 = s0 / E, u1 = (s1 + E - 1) / E;
+    for (int64_t u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
+        if ((u + 1) * E <= n) {
+            reinterpret_cast<uint4*>(x)[u] = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            for (int64_t i = u * E; i < n; ++i) x[i] = T(0);
+        }
+    }
+}
+
 template <typename T>
 void launch_atomic_init(const Level& L, T* v, double* q, hipStream_t s) {
-    // large levels: streaming zero fills at full store width; small levels: one kernel
+    // large levels: streaming zero fills at full store width (3D velocity: plane by plane,
+    // top planes first); small levels: one kernel
     if (L.nvn >= (int64_t(1) << 20)) {
-        if (v) launch_zero<T>(v, L.nv, s);
+        if (v && L.dim == 3 && reinterpret_cast<uintptr_t>(v) % 16 == 0) {
+            const int64_t plane = (int64_t)L.vnodes[0] * L.vnodes[1];
+            hipLaunchKernelGGL(k_zero_planes_desc<T>, dim3((unsigned)(L.vnodes[2] * L.dim * kZeroPlaneParts)), dim3(256), 0, s, v,
+                               L.nvn, plane, L.vnodes[2], L.dim, L.nv);
+        } else if (v) {
+            launch_zero<T>(v, L.nv, s);
+        }
         if (q) launch_zero<double>(q, L.np, s);
         return;
     }
