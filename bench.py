@@ -65,8 +65,13 @@ def _log(msg):
 
 
 def cell_kernel_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_2305_08986_amd", "csrc", "kernels_cell.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources of the kernels the counter summaries measure: the cell kernels
+    and the initialisation (zero fill) of the atomic form."""
+    h = hashlib.sha256()
+    for name in ("kernels_cell.hip", "kernels_aux.hip"):
+        with open(os.path.join(ROOT, "paper_2305_08986_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes_per_cell(dim: int, elem: int) -> int:
